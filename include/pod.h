@@ -1,0 +1,166 @@
+/*
+ * pod.h -- C ABI of the MI355X (gfx950) implementation of the iterative
+ * sample-and-merge POD (ISMA) of Charumathi, Ramakrishna & Vasudevan,
+ * arXiv 1905.05107.
+ *
+ * Conventions for every entry point
+ *  - The snapshot matrix A is m x n, column-major (snapshot j is contiguous),
+ *    leading dimension lda >= m, stored as FP64 or FP32 in device memory.
+ *  - Device pointers are plain HIP device addresses; "host" buffers are
+ *    ordinary CPU memory.  The library never takes ownership of a caller
+ *    buffer.  The caller keeps A alive and unmodified (except through
+ *    center_rows) until pod_destroy.
+ *  - All work is enqueued on the stream given to pod_init (a hipStream_t
+ *    passed as void*, NULL = the default stream) in call order.  Entry
+ *    points that return data to host memory synchronise that stream; they
+ *    are marked "syncs".
+ *  - Every entry point returns a pod_status; nothing throws across the ABI.
+ *    After POD_EHIP the context must be destroyed.
+ */
+#ifndef POD_H
+#define POD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pod_ctx pod_ctx;
+
+typedef enum {
+    POD_OK = 0,
+    POD_EINVAL = 1,     /* bad argument or parameter combination            */
+    POD_ENOMEM = 2,     /* device or host allocation failed                 */
+    POD_EHIP = 3,       /* a HIP runtime call failed                        */
+    POD_ENOTPD = 4,     /* Cholesky breakdown even after the shifted retry  */
+    POD_ESTATE = 5,     /* call out of order (e.g. merge before sample)     */
+    POD_EXHAUSTED = 6,  /* no column of S left to draw: normal stop         */
+    POD_ENONFINITE = 7, /* NaN/Inf met in A or in a computed quantity       */
+    POD_ENOCONV = 8     /* a Jacobi SVD did not converge in its sweep limit */
+} pod_status;
+
+/* Arithmetic of the merge / projection GEMMs.  The Cholesky factors and the
+ * small SVDs are FP64 in every path. */
+typedef enum { POD_F64 = 0, POD_F32 = 1, POD_BF16_REFINE = 2 } pod_precision;
+
+/* Column sampling from the second iteration on (first iteration: always
+ * column-norm probabilities, Eq. LTSVD_prob). */
+typedef enum { POD_COL_L2N = 0, POD_COL_UNF = 1 } pod_col_strategy;
+
+/* Row sampling when w > 0: squared row norms of the sampled columns
+ * (Eq. CTSVD_prob) or leverage scores of the current modes (second
+ * iteration on). */
+typedef enum { POD_ROW_L2 = 0, POD_ROW_LS = 1 } pod_row_strategy;
+
+/* Convergence test of Alg. 1: principal angles between the subspaces of
+ * successive estimates, or angles between corresponding modes. */
+typedef enum { POD_CRIT_SUBSPACE = 0, POD_CRIT_MODE = 1 } pod_criterion;
+
+/* Inputs of ISMA(A, p, k, c, w, r, tau, rows) (Alg. 1). */
+typedef struct {
+    int64_t m, n, lda;     /* A is m x n column-major, lda >= m                 */
+    int32_t a_dtype;       /* storage of A: POD_F64 or POD_F32                  */
+    int32_t precision;     /* pod_precision                                     */
+    int32_t k;             /* modes reported                                    */
+    int32_t r;             /* rank kept after each merge (0 -> k), r >= k       */
+    int32_t c;             /* column draws per iteration (with replacement)     */
+    int32_t w;             /* row draws per iteration; 0 = columns only (ICS)   */
+    int32_t r_update;      /* >0: keep the top r_update right singular          */
+                           /* directions of each new block before the merge     */
+    int32_t col_strategy;  /* pod_col_strategy                                  */
+    int32_t row_strategy;  /* pod_row_strategy                                  */
+    int32_t criterion;     /* pod_criterion                                     */
+    int32_t center_rows;   /* 1: subtract row means of A in place at init       */
+    int32_t max_iter;      /* merges allowed (>= 1)                             */
+    double theta_tol;      /* stop when the largest angle < theta_tol (radians) */
+    uint64_t seed;         /* Philox key word 0                                 */
+    uint64_t block;        /* Philox counter word 2 (column block of Alg. 3)    */
+} pod_params;
+
+/* Host-readable progress of a context (pod_get_info, syncs). */
+typedef struct {
+    int32_t iter;          /* merges done                                       */
+    int32_t rank;          /* columns of the current basis U                    */
+    int32_t g;             /* distinct columns of the last draw                 */
+    int32_t h;             /* distinct rows of the last draw                    */
+    int32_t exhausted;     /* S had no drawable column at the last pod_sample   */
+    int32_t flags;         /* bit 0: shifted Cholesky used; bit 1: non-finite;  */
+                           /* bit 2: Jacobi sweep limit hit                     */
+    double sin_theta;      /* sine of the last convergence angle (NaN first)    */
+} pod_info;
+
+/* Create a context for A (device, borrowed) and run the set-up pass:
+ * optional row centring (two passes over A), the column squared norms
+ * (Eq. LTSVD_prob, one pass, FP64 in a fixed summation order) and their
+ * integer sampling weights.  Errors: POD_EINVAL for bad sizes or options,
+ * POD_ENOMEM, POD_EHIP. */
+pod_status pod_init(pod_ctx **ctx, const pod_params *prm, void *A_dev, void *stream);
+
+/* GET UPDATE of Alg. 1: draw c columns from S with the current probabilities
+ * (Philox-4x64-10, key (seed, 0), counter (iter, d/4, block, 0)), keep the
+ * distinct ones in ascending order, remove them from S, and, when w > 0,
+ * SAMPLE AND SCALE UNIQUE ROWS (key (seed, 1)) followed by the small SVD of
+ * W^T W.  g_out / h_out (host, nullable) receive the numbers of distinct
+ * columns / rows: passing them syncs.  POD_EXHAUSTED (syncs) when S has no
+ * drawable column; the context then stays valid for pod_project. */
+pod_status pod_sample(pod_ctx *ctx, int32_t *g_out, int32_t *h_out);
+
+/* BLOCK MERGE of Alg. 2 on [U_r Sigma_r | C]: CholeskyQR2 of the tall
+ * block, FP64 SVD of the (r+g) x (r+g) factor, rank guard, truncation to r.
+ * POD_ESTATE if no sample is pending. */
+pod_status pod_merge(pod_ctx *ctx);
+
+/* Convergence test of Alg. 1 (syncs): *done = 1 when the largest angle
+ * between the first k modes of the last two estimates is below theta_tol,
+ * S is exhausted, or max_iter merges were done.  *sin_theta_max (nullable)
+ * gets the sine of that angle (NaN after the first merge). */
+pod_status pod_converged(pod_ctx *ctx, int32_t *done, double *sin_theta_max);
+
+/* Final step of Alg. 1 (syncs): B = U_r^T A (one pass over A), SVD of B,
+ * U <- U U_B, Sigma <- Sigma_B, V = B^T U_B Sigma_B^-1.  Writes the first
+ * k modes: U_out (device, m x k column-major, FP64 for POD_F64 else FP32),
+ * sigma_out (device, k FP64), V_out (device, n x k like U_out, nullable).
+ * Each u_i is signed so that its largest-magnitude entry is positive. */
+pod_status pod_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out);
+
+/* Copy the current merged basis (before the final step) to caller device
+ * buffers: U_out m x rank (ld = m, precision as in pod_project) and
+ * sigma_out (device, rank FP64); *rank_out (host) gets the rank.  Syncs. */
+pod_status pod_get_basis(pod_ctx *ctx, void *U_out, double *sigma_out, int32_t *rank_out);
+
+/* Progress counters (syncs). */
+pod_status pod_get_info(pod_ctx *ctx, pod_info *info);
+
+/* Indices drawn at merge `iter` (0-based), copied to host buffers of at
+ * least c (cols, col_counts) and w (rows, row_counts) entries; any pointer
+ * may be NULL.  *g / *h (host, nullable) get their numbers.  Syncs. */
+pod_status pod_get_indices(pod_ctx *ctx, int32_t iter, int32_t *cols, int32_t *col_counts, int32_t *g,
+                           int32_t *rows, int32_t *row_counts, int32_t *h);
+
+/* Column squared norms computed at init (device -> host, n FP64).  Syncs. */
+pod_status pod_get_col_sqnorms(pod_ctx *ctx, double *nu_host);
+
+/* Stand-alone column squared norms of an m x n device matrix in the
+ * library's fixed summation order: nu_dev (device, n FP64).  Stream-ordered
+ * on `stream`, no sync. */
+pod_status pod_col_sqnorms(const void *A_dev, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
+                           double *nu_dev, void *stream);
+
+/* Sample sizes of Eqs. (c_LTSVD) and (c_w_CTSVD), rounded up:
+ * kind 0: c = 4k (1 + sqrt(8 ln(1/delta)))^2 / eps^2;
+ * kind 1: c = w = k^2 (1 + sqrt(ln(2/delta)))^2 / eps^4.
+ * Returns -1 for invalid arguments. */
+int64_t pod_sample_size(int32_t kind, int32_t k, double eps, double delta);
+
+/* Release everything the context owns (not A).  Syncs its stream. */
+void pod_destroy(pod_ctx *ctx);
+
+/* Static description of a status code. */
+const char *pod_status_str(pod_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POD_H */

@@ -1,0 +1,296 @@
+"""MI355X (gfx950) iterative sample-and-merge POD (ISMA, arXiv 1905.05107).
+
+Thin ctypes binding of ``libpod.so`` (declared in ``include/pod.h``): argument
+marshalling only.  Every step of the method runs in the library's HIP kernels;
+PyTorch supplies device memory and the stream.  There is no CPU fallback: if
+the library is not built this module raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import List, Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpod.so")
+
+POD_OK, POD_EINVAL, POD_ENOMEM, POD_EHIP, POD_ENOTPD, POD_ESTATE, POD_EXHAUSTED, POD_ENONFINITE, POD_ENOCONV = range(9)
+POD_F64, POD_F32, POD_BF16_REFINE = 0, 1, 2
+POD_COL_L2N, POD_COL_UNF = 0, 1
+POD_ROW_L2, POD_ROW_LS = 0, 1
+POD_CRIT_SUBSPACE, POD_CRIT_MODE = 0, 1
+
+# every symbol include/pod.h declares
+EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project", "pod_get_basis", "pod_get_info",
+           "pod_get_indices", "pod_get_col_sqnorms", "pod_col_sqnorms", "pod_sample_size", "pod_destroy",
+           "pod_status_str"]
+
+
+class PodError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_str(status)} (status {status})")
+        self.status = status
+
+
+class pod_params(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+        ("a_dtype", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("k", ctypes.c_int32), ("r", ctypes.c_int32), ("c", ctypes.c_int32), ("w", ctypes.c_int32),
+        ("r_update", ctypes.c_int32), ("col_strategy", ctypes.c_int32), ("row_strategy", ctypes.c_int32),
+        ("criterion", ctypes.c_int32), ("center_rows", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+        ("theta_tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("block", ctypes.c_uint64),
+    ]
+
+
+class pod_info(ctypes.Structure):
+    _fields_ = [
+        ("iter", ctypes.c_int32), ("rank", ctypes.c_int32), ("g", ctypes.c_int32), ("h", ctypes.c_int32),
+        ("exhausted", ctypes.c_int32), ("flags", ctypes.c_int32), ("sin_theta", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpod.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1905_05107_amd.build` first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        P = ctypes.POINTER
+        sig = {
+            "pod_init": (i32, [P(vp), P(pod_params), vp, vp]),
+            "pod_sample": (i32, [vp, P(i32), P(i32)]),
+            "pod_merge": (i32, [vp]),
+            "pod_converged": (i32, [vp, P(i32), P(d)]),
+            "pod_project": (i32, [vp, vp, vp, vp]),
+            "pod_get_basis": (i32, [vp, vp, vp, P(i32)]),
+            "pod_get_info": (i32, [vp, P(pod_info)]),
+            "pod_get_indices": (i32, [vp, i32, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)]),
+            "pod_get_col_sqnorms": (i32, [vp, vp]),
+            "pod_col_sqnorms": (i32, [vp, i32, i64, i64, i64, vp, vp]),
+            "pod_sample_size": (i64, [i32, i32, d, d]),
+            "pod_destroy": (None, [vp]),
+            "pod_status_str": (ctypes.c_char_p, [i32]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_str(s: int) -> str:
+    return lib().pod_status_str(int(s)).decode()
+
+
+def _check(s: int, what: str, ok=(POD_OK,)):
+    if s not in ok:
+        raise PodError(s, what)
+    return s
+
+
+def sample_size(kind: str, k: int, eps: float, delta: float) -> int:
+    """Eq. (c_LTSVD) for kind 'ltsvd', Eq. (c_w_CTSVD) for 'ctsvd'."""
+    return int(lib().pod_sample_size(0 if kind == "ltsvd" else 1, int(k), float(eps), float(delta)))
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _a_layout(A):
+    """(ptr, m, n, lda, dtype code) of a column-major device matrix.
+
+    Accepts an m x n tensor whose columns are contiguous (A.stride(0) == 1),
+    e.g. the transpose of an (n, m) contiguous tensor."""
+    import torch
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    if A.dim() != 2 or (A.shape[0] > 1 and A.stride(0) != 1):
+        raise ValueError("A must be m x n with contiguous columns (stride(0) == 1)")
+    if A.dtype == torch.float64:
+        code = POD_F64
+    elif A.dtype == torch.float32:
+        code = POD_F32
+    else:
+        raise ValueError("A must be float32 or float64")
+    m, n = A.shape
+    lda = A.stride(1) if n > 1 else m
+    return A.data_ptr(), m, n, max(lda, m), code
+
+
+@dataclass
+class Result:
+    U: "object"            # m x k device tensor
+    sigma: "object"        # k (float64 device tensor)
+    V: Optional["object"]  # n x k device tensor
+    iters: int
+    sin_theta: List[float]
+    exhausted: bool
+    converged: bool
+    flags: int
+
+
+class PodContext:
+    """One ISMA run on one device matrix (pod_init ... pod_destroy)."""
+
+    def __init__(self, A, k: int, c: int, r: int = 0, w: int = 0, precision: int = POD_F64,
+                 theta_tol: float = 1e-10, col_strategy: int = POD_COL_L2N, row_strategy: int = POD_ROW_L2,
+                 criterion: int = POD_CRIT_SUBSPACE, max_iter: Optional[int] = None, seed: int = 0,
+                 block: int = 0, r_update: int = 0, center_rows: bool = False, stream=None):
+        ptr, m, n, lda, code = _a_layout(A)
+        self.A = A
+        self.m, self.n = m, n
+        self.k = k
+        self.precision = precision
+        p = pod_params()
+        p.m, p.n, p.lda, p.a_dtype, p.precision = m, n, lda, code, precision
+        p.k, p.r, p.c, p.w, p.r_update = k, r, c, w, r_update
+        p.col_strategy, p.row_strategy, p.criterion = col_strategy, row_strategy, criterion
+        p.center_rows = 1 if center_rows else 0
+        p.max_iter = int(max_iter if max_iter is not None else n + 1)
+        p.theta_tol = float(theta_tol)
+        p.seed = int(seed) & (2**64 - 1)
+        p.block = int(block)
+        self.params = p
+        self.stream = _stream_handle(stream)
+        h = ctypes.c_void_p()
+        _check(lib().pod_init(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(ptr), self.stream), "pod_init")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().pod_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- steps
+    def sample(self, want_counts: bool = False):
+        """GET UPDATE; returns True if a draw was made (False: S exhausted)."""
+        if want_counts:
+            g, h = ctypes.c_int32(), ctypes.c_int32()
+            s = lib().pod_sample(self.h, ctypes.byref(g), ctypes.byref(h))
+            _check(s, "pod_sample", ok=(POD_OK, POD_EXHAUSTED))
+            return (s == POD_OK, g.value, h.value)
+        s = lib().pod_sample(self.h, None, None)
+        _check(s, "pod_sample", ok=(POD_OK, POD_EXHAUSTED))
+        return s == POD_OK
+
+    def merge(self):
+        _check(lib().pod_merge(self.h), "pod_merge")
+
+    def converged(self):
+        done, sn = ctypes.c_int32(), ctypes.c_double()
+        _check(lib().pod_converged(self.h, ctypes.byref(done), ctypes.byref(sn)), "pod_converged")
+        return bool(done.value), sn.value
+
+    def info(self) -> pod_info:
+        inf = pod_info()
+        _check(lib().pod_get_info(self.h, ctypes.byref(inf)), "pod_get_info")
+        return inf
+
+    def _out_dtype(self):
+        import torch
+        return torch.float64 if self.precision == POD_F64 else torch.float32
+
+    def project(self, want_v: bool = True):
+        import torch
+        inf = self.info()
+        k = min(self.k, inf.rank)
+        dev = self.A.device
+        Ut = torch.empty((k, self.m), dtype=self._out_dtype(), device=dev)
+        sig = torch.empty(k, dtype=torch.float64, device=dev)
+        Vt = torch.empty((k, self.n), dtype=self._out_dtype(), device=dev) if want_v else None
+        _check(lib().pod_project(self.h, ctypes.c_void_p(Ut.data_ptr()), ctypes.c_void_p(sig.data_ptr()),
+                                 ctypes.c_void_p(Vt.data_ptr()) if want_v else None), "pod_project")
+        return Ut.T, sig, (Vt.T if want_v else None)
+
+    def basis(self):
+        import torch
+        inf = self.info()
+        rk = inf.rank
+        dev = self.A.device
+        Ut = torch.empty((max(rk, 1), self.m), dtype=self._out_dtype(), device=dev)
+        sig = torch.empty(max(rk, 1), dtype=torch.float64, device=dev)
+        r = ctypes.c_int32()
+        _check(lib().pod_get_basis(self.h, ctypes.c_void_p(Ut.data_ptr()), ctypes.c_void_p(sig.data_ptr()),
+                                   ctypes.byref(r)), "pod_get_basis")
+        return Ut[:r.value].T, sig[:r.value]
+
+    def indices(self, it: int):
+        import numpy as np
+        c = self.params.c
+        cols = np.zeros(max(c, 1), dtype=np.int32)
+        cnt = np.zeros(max(c, 1), dtype=np.int32)
+        g = ctypes.c_int32()
+        P = ctypes.POINTER(ctypes.c_int32)
+        _check(lib().pod_get_indices(self.h, int(it), cols.ctypes.data_as(P), cnt.ctypes.data_as(P),
+                                     ctypes.byref(g), None, None, None), "pod_get_indices")
+        return cols[:g.value].copy(), cnt[:g.value].copy()
+
+    def col_sqnorms(self):
+        import numpy as np
+        nu = np.zeros(self.n, dtype=np.float64)
+        _check(lib().pod_get_col_sqnorms(self.h, ctypes.c_void_p(nu.ctypes.data)), "pod_get_col_sqnorms")
+        return nu
+
+    def run(self, n_iter: Optional[int] = None):
+        """Alg. 1: sample/merge until converged, S is exhausted, max_iter
+        merges were done, or (when given) n_iter merges were done.  Returns
+        the convergence sines of the merges (NaN for the first)."""
+        sines = []
+        while n_iter is None or len(sines) < n_iter:
+            if not self.sample():
+                break
+            before = len(sines)
+            self.merge()
+            done, sn = self.converged()
+            if done and self.info().iter == before:   # the draw found S exhausted: no merge happened
+                break
+            sines.append(sn)
+            if done and n_iter is None:
+                break
+        return sines
+
+
+def isma(A, k: int, c: int, want_v: bool = True, n_iter: Optional[int] = None, **kw) -> Result:
+    """Run Alg. 1 on the device matrix A (m x n, contiguous columns) and the
+    final projection; returns the first k modes."""
+    with PodContext(A, k, c, **kw) as ctx:
+        sines = ctx.run(n_iter=n_iter)
+        inf = ctx.info()
+        U, sig, V = ctx.project(want_v=want_v)
+        tol = kw.get("theta_tol", 1e-10)
+        conv = inf.iter >= 2 and not math.isnan(inf.sin_theta) and inf.sin_theta < math.sin(min(tol, math.pi / 2))
+        return Result(U, sig, V, inf.iter, sines, bool(inf.exhausted), conv, inf.flags)
+
+
+def col_sqnorms(A, stream=None):
+    """Column squared norms of a device matrix in the library's fixed order."""
+    import torch
+    ptr, m, n, lda, code = _a_layout(A)
+    nu = torch.empty(n, dtype=torch.float64, device=A.device)
+    _check(lib().pod_col_sqnorms(ctypes.c_void_p(ptr), code, m, n, lda, ctypes.c_void_p(nu.data_ptr()),
+                                 _stream_handle(stream)), "pod_col_sqnorms")
+    return nu

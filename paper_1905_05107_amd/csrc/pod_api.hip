@@ -1,0 +1,473 @@
+// pod_api.hip -- the C ABI of include/pod.h: context ownership, argument
+// checks and the order of kernel launches for one ISMA run (Alg. 1) on a
+// single gfx950 GPU.  Every step of the method runs in the kernels of
+// pod_sample.hip, pod_gemm.hip and pod_small.hip; this file only allocates,
+// launches and copies results.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "pod_internal.h"
+
+using namespace pod;
+
+struct pod_ctx {
+    pod_params prm;
+    int32_t r = 0, pmax = 0;
+    hipStream_t st = nullptr;
+    void *A = nullptr;
+    size_t esz = 8;          // bytes per element of the compute type
+    DevState *ds = nullptr;  // device
+    DevState hs{};           // host copy after the last sync
+    double *nu = nullptr;
+    uint64_t *wq = nullptr;
+    uint8_t *inS = nullptr;
+    int32_t *cols = nullptr, *ccnt = nullptr, *col_log = nullptr, *ccnt_log = nullptr, *col_log_off = nullptr;
+    int32_t *forced = nullptr;
+    void *U[2] = {nullptr, nullptr};
+    double *sig[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *part = nullptr, *G = nullptr, *R1 = nullptr, *R2 = nullptr, *work = nullptr;
+    void *Tc = nullptr, *Y = nullptr;
+    int32_t nblk = 0;
+    double *Bpart = nullptr, *B = nullptr, *GB = nullptr, *UB = nullptr, *sigB = nullptr;
+    void *Zc = nullptr;
+    int32_t nsplit = 0;
+    int pending = 0;         // a draw waits for its merge
+    int32_t merges = 0;      // merges launched
+    int exhausted = 0;       // known on the host
+    int failed = 0;          // a HIP error happened: only destroy is allowed
+    int32_t forced_g = -1;   // replay of the next draw
+};
+
+namespace {
+
+template <typename T> hipError_t dalloc(T **p, size_t count)
+{
+    return hipMalloc((void **)p, count * sizeof(T) + 16);
+}
+
+double unit_roundoff(int32_t prec) { return prec == POD_F64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08; }
+
+#define POD_HIP(call)                                                                                                 \
+    do {                                                                                                              \
+        hipError_t e_ = (call);                                                                                       \
+        if (e_ != hipSuccess) {                                                                                       \
+            if (ctx) ctx->failed = 1;                                                                                 \
+            return (e_ == hipErrorOutOfMemory) ? POD_ENOMEM : POD_EHIP;                                               \
+        }                                                                                                             \
+    } while (0)
+
+pod_status sync_state(pod_ctx *ctx)
+{
+    POD_HIP(hipMemcpyAsync(&ctx->hs, ctx->ds, sizeof(DevState), hipMemcpyDeviceToHost, ctx->st));
+    POD_HIP(hipStreamSynchronize(ctx->st));
+    // a merge launched on an exhausted draw is a no-op on the device
+    if (ctx->hs.it < ctx->merges) {
+        ctx->cur ^= 1;
+        ctx->merges = ctx->hs.it;
+    }
+    if (ctx->hs.exhausted || (ctx->hs.s_empty && !ctx->pending)) ctx->exhausted = 1;
+    return POD_OK;
+}
+
+void free_all(pod_ctx *ctx)
+{
+    void *ptrs[] = {ctx->ds,   ctx->nu,   ctx->wq,    ctx->inS,  ctx->cols, ctx->ccnt, ctx->col_log, ctx->ccnt_log,
+                    ctx->col_log_off, ctx->forced, ctx->U[0], ctx->U[1], ctx->sig[0], ctx->sig[1], ctx->part,
+                    ctx->G,    ctx->R1,   ctx->R2,    ctx->work, ctx->Tc,   ctx->Y,    ctx->Bpart,
+                    ctx->B,    ctx->GB,   ctx->UB,    ctx->sigB, ctx->Zc};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+GemmDesc gather_desc(pod_ctx *ctx)
+{
+    GemmDesc d;
+    d.prec = ctx->prm.precision;
+    d.a_dtype = ctx->prm.a_dtype;
+    d.m = ctx->prm.m;
+    d.U = ctx->U[ctx->cur];
+    d.A = ctx->A;
+    d.lda = ctx->prm.lda;
+    d.cols = ctx->cols;
+    d.Y = nullptr;
+    d.gather = 1;
+    d.guard = 1;
+    return d;
+}
+
+GemmDesc plain_desc(pod_ctx *ctx, const void *Y)
+{
+    GemmDesc d = gather_desc(ctx);
+    d.Y = Y;
+    d.gather = 0;
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pod_status_str(pod_status s)
+{
+    switch (s) {
+    case POD_OK: return "ok";
+    case POD_EINVAL: return "invalid argument";
+    case POD_ENOMEM: return "out of memory";
+    case POD_EHIP: return "HIP runtime error";
+    case POD_ENOTPD: return "Cholesky breakdown after the shifted retry";
+    case POD_ESTATE: return "call out of order";
+    case POD_EXHAUSTED: return "no column left to sample";
+    case POD_ENONFINITE: return "non-finite value";
+    case POD_ENOCONV: return "Jacobi SVD did not converge";
+    }
+    return "unknown status";
+}
+
+int64_t pod_sample_size(int32_t kind, int32_t k, double eps, double delta)
+{
+    if (k < 1 || !(eps > 0.0) || !(delta > 0.0)) return -1;
+    double c;
+    if (kind == 0) {
+        if (!(delta < 1.0)) return -1;
+        c = 4.0 * k * pow(1.0 + sqrt(8.0 * log(1.0 / delta)), 2.0) / (eps * eps);
+    } else if (kind == 1) {
+        if (!(delta < 2.0)) return -1;
+        c = (double)k * k * pow(1.0 + sqrt(log(2.0 / delta)), 2.0) / (eps * eps * eps * eps);
+    } else {
+        return -1;
+    }
+    if (!(c < 9.0e18)) return -1;
+    return (int64_t)ceil(c);
+}
+
+pod_status pod_col_sqnorms(const void *A_dev, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *nu_dev,
+                           void *stream)
+{
+    pod_ctx *ctx = nullptr;
+    if (!A_dev || !nu_dev || m < 1 || n < 1 || lda < m || (a_dtype != POD_F64 && a_dtype != POD_F32))
+        return POD_EINVAL;
+    if (n > 0x7fffffff) return POD_EINVAL;
+    POD_HIP(launch_col_sqnorms(A_dev, a_dtype, m, n, lda, nu_dev, (hipStream_t)stream));
+    return POD_OK;
+}
+
+pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *stream)
+{
+    if (!out || !prm || !A_dev) return POD_EINVAL;
+    *out = nullptr;
+    const pod_params &p = *prm;
+    if (p.m < 1 || p.n < 1 || p.lda < p.m || p.n > 0x7fffffff || p.m > ((int64_t)1 << 40)) return POD_EINVAL;
+    if (p.a_dtype != POD_F64 && p.a_dtype != POD_F32) return POD_EINVAL;
+    if (p.precision != POD_F64 && p.precision != POD_F32) return POD_EINVAL;
+    if (p.precision == POD_F32 && p.a_dtype == POD_F64) return POD_EINVAL;
+    const int32_t r = p.r ? p.r : p.k;
+    if (p.k < 1 || r < p.k || p.c < 1 || p.c > 1024 || p.max_iter < 1) return POD_EINVAL;
+    if (p.w != 0 || p.r_update != 0) return POD_EINVAL;
+    if (p.col_strategy != POD_COL_L2N && p.col_strategy != POD_COL_UNF) return POD_EINVAL;
+    if (p.criterion != POD_CRIT_SUBSPACE && p.criterion != POD_CRIT_MODE) return POD_EINVAL;
+    if (!(p.theta_tol >= 0.0)) return POD_EINVAL;
+    const int64_t cmax = (p.c < p.n) ? p.c : p.n;
+    const int32_t pmax = (int32_t)(((r + cmax) + 15) & ~15);
+    if (pmax > 64) return POD_EINVAL;
+
+    pod_ctx *ctx = new (std::nothrow) pod_ctx();
+    if (!ctx) return POD_ENOMEM;
+    ctx->prm = p;
+    ctx->prm.r = r;
+    ctx->r = r;
+    ctx->pmax = pmax;
+    ctx->st = (hipStream_t)stream;
+    ctx->A = A_dev;
+    ctx->esz = (p.precision == POD_F64) ? 8 : 4;
+    const int64_t m = p.m, n = p.n;
+    const int32_t cap_iter = (int32_t)((p.max_iter < n) ? p.max_iter : n) + 1;
+    ctx->nblk = (int32_t)((m + 255) / 256 < 256 ? (m + 255) / 256 : 256);
+    if (ctx->nblk < 1) ctx->nblk = 1;
+    ctx->nsplit = 32;
+    if (m < 4096) ctx->nsplit = 8;
+    hipError_t e = hipSuccess;
+#define ALLOC(ptr, T, count)                                                                                          \
+    if (e == hipSuccess) e = dalloc((T **)&(ptr), (size_t)(count))
+    ALLOC(ctx->ds, DevState, 1);
+    ALLOC(ctx->nu, double, n);
+    ALLOC(ctx->wq, uint64_t, n);
+    ALLOC(ctx->inS, uint8_t, n);
+    ALLOC(ctx->cols, int32_t, 1024);
+    ALLOC(ctx->ccnt, int32_t, 1024);
+    ALLOC(ctx->forced, int32_t, 1024);
+    ALLOC(ctx->col_log, int32_t, n);
+    ALLOC(ctx->ccnt_log, int32_t, n);
+    ALLOC(ctx->col_log_off, int32_t, cap_iter + 1);
+    for (int b = 0; b < 2; ++b) {
+        ALLOC(ctx->U[b], unsigned char, (size_t)m * r * ctx->esz);
+        ALLOC(ctx->sig[b], double, r);
+    }
+    ALLOC(ctx->part, double, (size_t)ctx->nblk * pmax * pmax);
+    ALLOC(ctx->G, double, pmax * pmax);
+    ALLOC(ctx->R1, double, pmax * pmax);
+    ALLOC(ctx->R2, double, pmax * pmax);
+    ALLOC(ctx->work, double, pmax * pmax);
+    ALLOC(ctx->Tc, unsigned char, (size_t)pmax * pmax * ctx->esz);
+    ALLOC(ctx->Y, unsigned char, (size_t)m * pmax * ctx->esz);
+    ALLOC(ctx->Bpart, double, (size_t)ctx->nsplit * r * n);
+    ALLOC(ctx->B, double, (size_t)r * n);
+    ALLOC(ctx->GB, double, (size_t)r * r);
+    ALLOC(ctx->UB, double, (size_t)r * r);
+    ALLOC(ctx->sigB, double, r);
+    ALLOC(ctx->Zc, unsigned char, (size_t)r * r * ctx->esz);
+#undef ALLOC
+    if (e != hipSuccess) {
+        free_all(ctx);
+        delete ctx;
+        return e == hipErrorOutOfMemory ? POD_ENOMEM : POD_EHIP;
+    }
+    DevState h{};
+    h.sin_theta = __builtin_nan("");
+    POD_HIP(hipMemcpyAsync(ctx->ds, &h, sizeof(DevState), hipMemcpyHostToDevice, ctx->st));
+    POD_HIP(hipMemsetAsync(ctx->inS, 1, (size_t)n, ctx->st));
+    POD_HIP(hipMemsetAsync(ctx->col_log_off, 0, sizeof(int32_t) * (cap_iter + 1), ctx->st));
+    POD_HIP(hipMemsetAsync(ctx->sig[0], 0, sizeof(double) * r, ctx->st));
+    POD_HIP(hipMemsetAsync(ctx->sig[1], 0, sizeof(double) * r, ctx->st));
+    if (p.center_rows) {
+        // row means over 8 column ranges (FP64), then a_ij <- a_ij - mean_i
+        const int32_t ns = 8;
+        double *scratch = nullptr;
+        POD_HIP(hipMalloc((void **)&scratch, sizeof(double) * (size_t)(ns + 1) * m));
+        POD_HIP(launch_row_means(A_dev, p.a_dtype, m, n, p.lda, scratch, ns, scratch + (size_t)ns * m, ctx->st));
+        POD_HIP(launch_center(A_dev, p.a_dtype, m, n, p.lda, scratch + (size_t)ns * m, ctx->st));
+        POD_HIP(hipStreamSynchronize(ctx->st));
+        POD_HIP(hipFree(scratch));
+    }
+    POD_HIP(launch_col_sqnorms(A_dev, p.a_dtype, m, n, p.lda, ctx->nu, ctx->st));
+    POD_HIP(launch_quantize(ctx->nu, n, ctx->wq, ctx->ds, ctx->st));
+    *out = ctx;
+    return POD_OK;
+}
+
+pod_status pod_sample(pod_ctx *ctx, int32_t *g_out, int32_t *h_out)
+{
+    if (!ctx) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (ctx->pending) return POD_ESTATE;
+    if (ctx->exhausted) return POD_EXHAUSTED;
+    if (ctx->merges >= ctx->prm.max_iter) return POD_ESTATE;
+    DrawArgs a;
+    a.wq = ctx->wq;
+    a.inS = ctx->inS;
+    a.n = ctx->prm.n;
+    a.c = ctx->prm.c;
+    a.unf = (ctx->prm.col_strategy == POD_COL_UNF);
+    a.seed = ctx->prm.seed;
+    a.block = ctx->prm.block;
+    a.cols = ctx->cols;
+    a.ccnt = ctx->ccnt;
+    a.col_log = ctx->col_log;
+    a.ccnt_log = ctx->ccnt_log;
+    a.col_log_off = ctx->col_log_off;
+    a.max_iter = (int32_t)((ctx->prm.max_iter < ctx->prm.n) ? ctx->prm.max_iter : ctx->prm.n);
+    a.forced = (ctx->forced_g >= 0) ? ctx->forced : nullptr;
+    a.forced_g = ctx->forced_g;
+    a.ds = ctx->ds;
+    POD_HIP(launch_draw_cols(a, ctx->st));
+    ctx->forced_g = -1;
+    ctx->pending = 1;
+    if (g_out || h_out) {
+        pod_status s = sync_state(ctx);
+        if (s != POD_OK) return s;
+        if (g_out) *g_out = ctx->hs.g;
+        if (h_out) *h_out = ctx->hs.h;
+        if (ctx->hs.exhausted) {
+            ctx->pending = 0;
+            return POD_EXHAUSTED;
+        }
+    }
+    return POD_OK;
+}
+
+pod_status pod_merge(pod_ctx *ctx)
+{
+    if (!ctx) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (!ctx->pending) return POD_ESTATE;
+    const int32_t pm = ctx->pmax;
+    const pod_params &p = ctx->prm;
+    // pass 1: G0 = X0^T X0, X0 = [U | A(:, I_c)] gathered on the fly
+    GemmDesc gd = gather_desc(ctx);
+    POD_HIP(launch_gram_partial(gd, ctx->ds, -1, pm, ctx->part, ctx->nblk, ctx->st));
+    POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -1, ctx->G, ctx->st));
+    SmallArgs sa;
+    sa.ds = ctx->ds;
+    sa.sigma = ctx->sig[ctx->cur];
+    sa.sigma_new = ctx->sig[ctx->cur ^ 1];
+    sa.G = ctx->G;
+    sa.R1 = ctx->R1;
+    sa.R2 = ctx->R2;
+    sa.Tc = ctx->Tc;
+    sa.work = ctx->work;
+    sa.pmax = pm;
+    sa.r = ctx->r;
+    sa.k = p.k;
+    sa.prec = p.precision;
+    sa.criterion = p.criterion;
+    sa.urnd = unit_roundoff(p.precision);
+    POD_HIP(launch_chol_first(sa, ctx->st));
+    // Q1 = X0 T1 (T1 = P R1^-1)
+    POD_HIP(launch_gemm_tall(gd, ctx->ds, -1, -2, pm, pm, ctx->Tc, pm, ctx->Y, ctx->st));
+    // pass 2: G2 = Q1^T Q1
+    GemmDesc yd = plain_desc(ctx, ctx->Y);
+    POD_HIP(launch_gram_partial(yd, ctx->ds, -2, pm, ctx->part, ctx->nblk, ctx->st));
+    POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -2, ctx->G, ctx->st));
+    POD_HIP(launch_svd_merge(sa, ctx->st));
+    // U_new = Q1 R2^-1 U_R(:, 0:r')
+    POD_HIP(launch_gemm_tall(yd, ctx->ds, -2, -3, pm, ctx->r, ctx->Tc, pm, ctx->U[ctx->cur ^ 1], ctx->st));
+    ctx->cur ^= 1;
+    ctx->pending = 0;
+    ctx->merges += 1;
+    return POD_OK;
+}
+
+pod_status pod_converged(pod_ctx *ctx, int32_t *done, double *sin_theta_max)
+{
+    if (!ctx || !done) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (ctx->pending) return POD_ESTATE;
+    pod_status s = sync_state(ctx);
+    if (s != POD_OK) return s;
+    const DevState &h = ctx->hs;
+    if (sin_theta_max) *sin_theta_max = h.sin_theta;
+    const double tol = ctx->prm.theta_tol < 1.5707963267948966 ? sin(ctx->prm.theta_tol) : 1.0;
+    *done = h.exhausted || h.s_empty || h.it >= ctx->prm.max_iter || (h.it >= 2 && h.sin_theta < tol);
+    if (h.flags & FLAG_NONFINITE) return POD_ENONFINITE;
+    if (h.flags & FLAG_NOCONV) return POD_ENOCONV;
+    return POD_OK;
+}
+
+pod_status pod_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out)
+{
+    if (!ctx || !U_out || !sigma_out) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (ctx->pending) return POD_ESTATE;
+    pod_status s = sync_state(ctx);
+    if (s != POD_OK) return s;
+    const int32_t rs = ctx->hs.rs;
+    if (rs < 1) return POD_ESTATE;
+    const int32_t k = (ctx->prm.k < rs) ? ctx->prm.k : rs;
+    const pod_params &p = ctx->prm;
+    ProjArgs pa;
+    pa.prec = p.precision;
+    pa.a_dtype = p.a_dtype;
+    pa.m = p.m;
+    pa.n = p.n;
+    pa.lda = p.lda;
+    pa.U = ctx->U[ctx->cur];
+    pa.A = ctx->A;
+    pa.r = rs;
+    pa.Bpart = ctx->Bpart;
+    pa.nsplit = ctx->nsplit;
+    pa.B = ctx->B;
+    POD_HIP(launch_project_partial(pa, ctx->st));
+    POD_HIP(launch_project_reduce(pa, ctx->st));
+    RRArgs ra;
+    ra.B = ctx->B;
+    ra.n = p.n;
+    ra.r = rs;
+    ra.k = k;
+    ra.GB = ctx->GB;
+    ra.UB = ctx->UB;
+    ra.sig = ctx->sigB;
+    ra.Zc = ctx->Zc;
+    ra.prec = p.precision;
+    ra.ds = ctx->ds;
+    POD_HIP(launch_rr_small(ra, ctx->st));
+    GemmDesc ud = plain_desc(ctx, ctx->U[ctx->cur]);
+    ud.guard = 0;
+    POD_HIP(launch_gemm_tall(ud, ctx->ds, rs, k, rs, k, ctx->Zc, rs, U_out, ctx->st));
+    POD_HIP(hipMemcpyAsync(sigma_out, ctx->sigB, sizeof(double) * k, hipMemcpyDeviceToDevice, ctx->st));
+    if (V_out) POD_HIP(launch_rr_v(ctx->B, p.n, rs, k, ctx->UB, ctx->sigB, p.precision, V_out, ctx->st));
+    POD_HIP(launch_sign_fix(p.precision, U_out, p.m, k, V_out, p.n, ctx->st));
+    s = sync_state(ctx);
+    if (s != POD_OK) return s;
+    if (ctx->hs.flags & FLAG_NONFINITE) return POD_ENONFINITE;
+    if (ctx->hs.flags & FLAG_NOCONV) return POD_ENOCONV;
+    return POD_OK;
+}
+
+pod_status pod_get_basis(pod_ctx *ctx, void *U_out, double *sigma_out, int32_t *rank_out)
+{
+    if (!ctx) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    pod_status s = sync_state(ctx);
+    if (s != POD_OK) return s;
+    const int32_t rs = ctx->hs.rs;
+    if (rank_out) *rank_out = rs;
+    if (U_out && rs > 0)
+        POD_HIP(hipMemcpyAsync(U_out, ctx->U[ctx->cur], (size_t)ctx->prm.m * rs * ctx->esz, hipMemcpyDeviceToDevice,
+                               ctx->st));
+    if (sigma_out && rs > 0)
+        POD_HIP(hipMemcpyAsync(sigma_out, ctx->sig[ctx->cur], sizeof(double) * rs, hipMemcpyDeviceToDevice, ctx->st));
+    POD_HIP(hipStreamSynchronize(ctx->st));
+    return POD_OK;
+}
+
+pod_status pod_get_info(pod_ctx *ctx, pod_info *info)
+{
+    if (!ctx || !info) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    pod_status s = sync_state(ctx);
+    if (s != POD_OK) return s;
+    info->iter = ctx->hs.it;
+    info->rank = ctx->hs.rs;
+    info->g = ctx->hs.g;
+    info->h = ctx->hs.h;
+    info->exhausted = ctx->hs.exhausted || ctx->hs.s_empty;
+    info->flags = ctx->hs.flags;
+    info->sin_theta = ctx->hs.sin_theta;
+    return POD_OK;
+}
+
+pod_status pod_get_indices(pod_ctx *ctx, int32_t iter, int32_t *cols, int32_t *col_counts, int32_t *g, int32_t *rows,
+                           int32_t *row_counts, int32_t *h)
+{
+    if (!ctx || iter < 0) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    pod_status s = sync_state(ctx);
+    if (s != POD_OK) return s;
+    const int32_t cap = (int32_t)((ctx->prm.max_iter < ctx->prm.n) ? ctx->prm.max_iter : ctx->prm.n);
+    const int32_t drawn = ctx->hs.it + (ctx->pending ? 1 : 0);
+    if (iter >= drawn || iter >= cap) return POD_EINVAL;
+    int32_t off[2];
+    POD_HIP(hipMemcpy(off, ctx->col_log_off + iter, sizeof(off), hipMemcpyDeviceToHost));
+    const int32_t cnt = off[1] - off[0];
+    if (g) *g = cnt;
+    if (cols && cnt > 0)
+        POD_HIP(hipMemcpy(cols, ctx->col_log + off[0], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+    if (col_counts && cnt > 0)
+        POD_HIP(hipMemcpy(col_counts, ctx->ccnt_log + off[0], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+    (void)rows;
+    (void)row_counts;
+    if (h) *h = 0;
+    return POD_OK;
+}
+
+pod_status pod_get_col_sqnorms(pod_ctx *ctx, double *nu_host)
+{
+    if (!ctx || !nu_host) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    POD_HIP(hipMemcpyAsync(nu_host, ctx->nu, sizeof(double) * ctx->prm.n, hipMemcpyDeviceToHost, ctx->st));
+    POD_HIP(hipStreamSynchronize(ctx->st));
+    return POD_OK;
+}
+
+void pod_destroy(pod_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->st);
+    free_all(ctx);
+    delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// pod_internal.h -- shared device/host declarations of the gfx950 ISMA library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pod.h"
+
+namespace pod {
+
+// Device-resident progress of one context.  Kernels read sizes from here so
+// that one iteration (sample -> merge) runs without a host round trip.
+struct DevState {
+    int32_t it;         // merges done so far (= iteration index of the next draw)
+    int32_t rs;         // columns of the current basis U
+    int32_t g;          // distinct columns of the pending draw
+    int32_t h;          // distinct rows of the pending draw
+    int32_t ru;         // columns of the update block after its right factor
+    int32_t p0;         // rs + g: columns of the gathered block X0 = [U | A(:, I_c)]
+    int32_t p;          // rs + ru: columns of M = X0 P
+    int32_t rnew;       // rank after the pending merge
+    int32_t exhausted;  // no drawable column at the last draw
+    int32_t flags;      // bit0 shifted Cholesky, bit1 non-finite, bit2 Jacobi limit, bit3 zero row weights
+    int32_t sweeps;     // Jacobi sweeps of the last merge
+    int32_t col_log_len;// entries used in the column log
+    int32_t s_empty;    // no drawable column left after the last draw
+    int32_t pad0;
+    double sin_theta;   // last convergence sine (NaN until the second merge)
+    uint64_t wtot;      // total column weight of the last draw
+};
+
+enum : int32_t { FLAG_SHIFT = 1, FLAG_NONFINITE = 2, FLAG_NOCONV = 4, FLAG_ZERO_ROWS = 8 };
+
+// ---------------------------------------------------------------- Philox-4x64-10
+// Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+// SC'11: ten rounds of two 64x64->128 multiplies with a Weyl key schedule.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t lo0 = 0xD2E7470EE14C6C93ULL * c[0];
+        const uint64_t hi0 = __umul64hi(0xD2E7470EE14C6C93ULL, c[0]);
+        const uint64_t lo1 = 0xCA5A826395121157ULL * c[2];
+        const uint64_t hi1 = __umul64hi(0xCA5A826395121157ULL, c[2]);
+        const uint64_t n0 = hi1 ^ c[1] ^ k0;
+        const uint64_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B97F4A7C15ULL;
+        k1 += 0xBB67AE8584CAA73BULL;
+    }
+}
+
+// ---------------------------------------------------------------- MFMA wrappers
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef v4d type; };
+template <> struct Acc<float> { typedef v4f type; };
+
+// D(16x16) += A(16x4) * B(4x16).  Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16].  Its four results are D[acc_row<T>(l, v)][l%16], v = 0..3:
+// rows 4*(l/16)+v for the FP32 instruction, rows l/16 + 4v for the FP64 one.
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int v);
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int v) { return (lane >> 4) + 4 * v; }
+__device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16x16x4(float a, float b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+}  // namespace pod
+
+// ---------------------------------------------------------------- host launchers
+namespace pod {
+
+hipError_t launch_col_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *nu,
+                              hipStream_t st);
+hipError_t launch_row_means(const void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *part,
+                            int32_t nsplit, double *mean, hipStream_t st);
+hipError_t launch_center(void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, const double *mean,
+                         hipStream_t st);
+hipError_t launch_quantize(const double *v, int64_t len, uint64_t *w, DevState *ds, hipStream_t st);
+
+struct DrawArgs {
+    const uint64_t *wq;   // L2N weights (n)
+    uint8_t *inS;         // membership of S (n)
+    int64_t n;
+    int32_t c;
+    int32_t unf;          // uniform weights over S from the second iteration
+    uint64_t seed, block;
+    int32_t *cols;        // out: distinct columns (c)
+    int32_t *ccnt;        // out: multiplicities (c)
+    int32_t *col_log;     // out: appended distinct columns (n)
+    int32_t *ccnt_log;    // out: their multiplicities (n)
+    int32_t *col_log_off; // out: offsets per merge (max_iter + 1)
+    int32_t max_iter;
+    const int32_t *forced;// replayed columns (nullable)
+    int32_t forced_g;
+    DevState *ds;
+};
+hipError_t launch_draw_cols(const DrawArgs &a, hipStream_t st);
+
+struct GemmDesc {
+    int32_t prec;         // POD_F64 or POD_F32 (compute type)
+    int32_t a_dtype;      // storage of A
+    int64_t m;
+    const void *U;        // basis (compute type), ld = m
+    const void *A;
+    int64_t lda;
+    const int32_t *cols;
+    const void *Y;        // contiguous m x P source (compute type), ld = m (when gather == 0)
+    int32_t gather;       // 1: source is X0 = [U | A(:, cols)], 0: Y
+    int32_t guard;        // 1: skip when the pending draw found S exhausted
+};
+// Partial Grams of the first `P` (device count) columns of the source, P <= pmax.
+// Kernels launched with guard = 1 do nothing when the pending draw found S exhausted.
+hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t which_p, int32_t pmax, double *part,
+                               int32_t nblk, hipStream_t st);
+hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax, const DevState *ds,
+                                  int32_t which_p, double *G, hipStream_t st);
+// Y (m x pout, ld m) = source (m x pin) * T (pin x pout, ld ldt); counts from the device state.
+hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
+                            int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout,
+                            hipStream_t st);
+
+struct SmallArgs {
+    DevState *ds;
+    const double *sigma;   // current Sigma (rs)
+    double *sigma_new;     // Sigma after the merge (r)
+    const double *G;       // reduced Gram (pmax x pmax, ld pmax)
+    double *R1;            // (pmax x pmax)
+    double *R2;            // (pmax x pmax)
+    void *Tc;              // transform in compute type (pmax x pmax, ld pmax)
+    double *work;          // scratch (pmax x pmax)
+    int32_t pmax;
+    int32_t r, k;
+    int32_t prec;
+    int32_t criterion;
+    double urnd;           // unit roundoff of the merge arithmetic
+};
+hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st);
+hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st);
+
+struct ProjArgs {
+    int32_t prec, a_dtype;
+    int64_t m, n, lda;
+    const void *U;        // basis m x r (compute type)
+    const void *A;
+    int32_t r;
+    double *Bpart;        // partial B (nsplit x r x n)
+    int32_t nsplit;
+    double *B;            // r x n
+};
+hipError_t launch_project_partial(const ProjArgs &a, hipStream_t st);
+hipError_t launch_project_reduce(const ProjArgs &a, hipStream_t st);
+struct RRArgs {
+    const double *B;      // r x n
+    int64_t n;
+    int32_t r, k;
+    double *GB;           // r x r
+    double *UB;           // r x r (out, ld r)
+    double *sig;          // r (out)
+    void *Zc;             // U_B in compute type (r x k, ld r)
+    int32_t prec;
+    DevState *ds;
+};
+hipError_t launch_rr_small(const RRArgs &a, hipStream_t st);
+hipError_t launch_rr_v(const double *B, int64_t n, int32_t r, int32_t k, const double *UB, const double *sig,
+                       int32_t prec, void *V, hipStream_t st);
+hipError_t launch_sign_fix(int32_t prec, void *U, int64_t m, int32_t k, void *V, int64_t n, hipStream_t st);
+
+}  // namespace pod

@@ -1,0 +1,397 @@
+// pod_sample.hip -- column squared norms, row centring, integer sampling weights
+// and the Philox column draw of GET UPDATE (Alg. 1) for gfx950.
+//
+// The column norms and the draw must reproduce the same integers on every
+// run and on any machine that follows the same definition, so this file is
+// compiled without floating-point contraction and every sum has a fixed order.
+#include "pod_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace pod {
+
+// ---------------------------------------------------------------------------
+// Column squared norms nu_j = sum_i a_ij^2 (Eq. LTSVD_prob), one workgroup of
+// 256 threads per column, FP64 accumulation.  Fixed order: thread t adds, in
+// increasing row order, rows s*256*V + t*V + q (V = 16 / sizeof(T) values
+// per 16-byte vector) with acc = fma(x, x, acc); the 64 lanes of each wave
+// combine by XOR butterfly (offsets 32..1); the four wave sums are added
+// left to right.  Loads are 16-byte vectors (unrolled by 8 for memory-level
+// parallelism) when the column is 16-byte aligned, scalar otherwise; the
+// order of the additions is the same either way.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef f32x4 type; };
+template <> struct Vec16<double> { typedef f64x2 type; };
+
+template <typename T>
+__device__ __forceinline__ void acc_vec(double &acc, const typename Vec16<T>::type &v);
+template <>
+__device__ __forceinline__ void acc_vec<float>(double &acc, const f32x4 &v)
+{
+    acc = fma((double)v[0], (double)v[0], acc);
+    acc = fma((double)v[1], (double)v[1], acc);
+    acc = fma((double)v[2], (double)v[2], acc);
+    acc = fma((double)v[3], (double)v[3], acc);
+}
+template <>
+__device__ __forceinline__ void acc_vec<double>(double &acc, const f64x2 &v)
+{
+    acc = fma(v[0], v[0], acc);
+    acc = fma(v[1], v[1], acc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_col_sqnorms(const T *__restrict__ A, int64_t m, int64_t lda,
+                                                     double *__restrict__ nu)
+{
+    typedef typename Vec16<T>::type VT;
+    constexpr int V = 16 / sizeof(T);
+    constexpr int64_t L = 256 * V;
+    constexpr int UNR = 8;
+    const int t = threadIdx.x;
+    const T *col = A + (int64_t)blockIdx.x * lda;
+    const int64_t nfull = m / L;
+    double acc = 0.0;
+    int64_t s = 0;
+    if (((uintptr_t)col & 15) == 0) {
+        const VT *cv = reinterpret_cast<const VT *>(col) + t;
+        for (; s + UNR <= nfull; s += UNR) {
+            VT v[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) v[u] = __builtin_nontemporal_load(cv + (s + u) * 256);
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) acc_vec<T>(acc, v[u]);
+        }
+        for (; s < nfull; ++s) {
+            VT v = __builtin_nontemporal_load(cv + s * 256);
+            acc_vec<T>(acc, v);
+        }
+    } else {
+        for (; s < nfull; ++s) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const double x = (double)col[s * L + (int64_t)t * V + q];
+                acc = fma(x, x, acc);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+        const int64_t i = nfull * L + (int64_t)t * V + q;
+        if (i < m) {
+            const double x = (double)col[i];
+            acc = fma(x, x, acc);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc = acc + __shfl_xor(acc, o, 64);
+    __shared__ double ws[4];
+    if ((t & 63) == 0) ws[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) nu[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+hipError_t launch_col_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *nu,
+                              hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (a_dtype == POD_F64)
+        hipLaunchKernelGGL(k_col_sqnorms<double>, dim3((unsigned)n), dim3(256), 0, st, (const double *)A, m, lda,
+                           nu);
+    else
+        hipLaunchKernelGGL(k_col_sqnorms<float>, dim3((unsigned)n), dim3(256), 0, st, (const float *)A, m, lda, nu);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Row centring (optional set-up step): mean_i = (1/n) sum_j a_ij in FP64, then
+// a_ij <- a_ij - mean_i rounded to the storage type.  Threads run along rows
+// (coalesced in column-major storage); the n columns are split into `nsplit`
+// ranges whose partial sums are added in range order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_partial(const T *__restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                                     int32_t nsplit, double *__restrict__ part)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int32_t sp = blockIdx.y;
+    const int64_t j0 = (n * sp) / nsplit, j1 = (n * (sp + 1)) / nsplit;
+    double acc = 0.0;
+    for (int64_t j = j0; j < j1; ++j) acc += (double)A[j * lda + i];
+    part[(int64_t)sp * m + i] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_row_mean(const double *__restrict__ part, int64_t m, int64_t n,
+                                                  int32_t nsplit, double *__restrict__ mean)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    double acc = 0.0;
+    for (int32_t sp = 0; sp < nsplit; ++sp) acc += part[(int64_t)sp * m + i];
+    mean[i] = acc / (double)n;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_center(T *__restrict__ A, int64_t m, int64_t lda,
+                                                const double *__restrict__ mean)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    T *a = A + (int64_t)blockIdx.y * lda + i;
+    *a = (T)((double)*a - mean[i]);
+}
+
+hipError_t launch_row_means(const void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *part,
+                            int32_t nsplit, double *mean, hipStream_t st)
+{
+    dim3 g1((unsigned)((m + 255) / 256), (unsigned)nsplit);
+    if (a_dtype == POD_F64)
+        hipLaunchKernelGGL(k_row_partial<double>, g1, dim3(256), 0, st, (const double *)A, m, n, lda, nsplit, part);
+    else
+        hipLaunchKernelGGL(k_row_partial<float>, g1, dim3(256), 0, st, (const float *)A, m, n, lda, nsplit, part);
+    hipLaunchKernelGGL(k_row_mean, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, part, m, n, nsplit, mean);
+    return hipGetLastError();
+}
+
+hipError_t launch_center(void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, const double *mean,
+                         hipStream_t st)
+{
+    // one grid row per column; n <= 65535 per launch in y, so split larger n
+    for (int64_t j0 = 0; j0 < n; j0 += 65535) {
+        const int64_t nj = (n - j0 < 65535) ? (n - j0) : 65535;
+        dim3 g((unsigned)((m + 255) / 256), (unsigned)nj);
+        if (a_dtype == POD_F64)
+            hipLaunchKernelGGL(k_center<double>, g, dim3(256), 0, st, (double *)A + j0 * lda, m, lda, mean);
+        else
+            hipLaunchKernelGGL(k_center<float>, g, dim3(256), 0, st, (float *)A + j0 * lda, m, lda, mean);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Integer sampling weights (one workgroup).  With B = 63 - ceil(log2 len) and
+// e the exponent of max(v) (max < 2^e), w_j = floor(v_j 2^(B-1-e)), so the
+// total stays below 2^62 and Pr[j] = w_j / sum w reproduces p_j = v_j / sum v
+// up to one quantum.  A negative, infinite or NaN value raises FLAG_NONFINITE
+// and zeroes every weight.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_quantize(const double *__restrict__ v, int64_t len,
+                                                   uint64_t *__restrict__ w, DevState *ds)
+{
+    __shared__ double smax[16];
+    __shared__ int sbad[16];
+    const int t = threadIdx.x;
+    double mx = 0.0;
+    int bad = 0;
+    for (int64_t i = t; i < len; i += 1024) {
+        const double x = v[i];
+        if (!(x >= 0.0) || isinf(x)) bad = 1;
+        else mx = fmax(mx, x);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+        bad |= __shfl_xor(bad, o, 64);
+    }
+    if ((t & 63) == 0) {
+        smax[t >> 6] = mx;
+        sbad[t >> 6] = bad;
+    }
+    __syncthreads();
+    double vmax = 0.0;
+    int anybad = 0;
+    for (int q = 0; q < 16; ++q) {
+        vmax = fmax(vmax, smax[q]);
+        anybad |= sbad[q];
+    }
+    int cl = 0;
+    while (((int64_t)1 << cl) < len) ++cl;
+    const int B = 63 - cl;
+    int e = 0;
+    if (vmax > 0.0) (void)frexp(vmax, &e);
+    for (int64_t i = t; i < len; i += 1024) {
+        uint64_t q = 0;
+        if (!anybad && vmax > 0.0) q = (uint64_t)floor(ldexp(v[i], B - 1 - e));
+        w[i] = q;
+    }
+    if (t == 0 && anybad && ds) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
+}
+
+hipError_t launch_quantize(const double *v, int64_t len, uint64_t *w, DevState *ds, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_quantize, dim3(1), dim3(1024), 0, st, v, len, w, ds);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Column draw of GET UPDATE (one workgroup of 1024 threads).
+//   weights over S: L2N (quantised norms) or, from the second iteration, 1
+//   (UNF); W = their total.  W == 0 marks S as exhausted.
+//   c draws: u_d = word (d mod 4) of Philox(key (seed, 0),
+//   counter (it, d/4, block, 0)); t = floor(u_d W / 2^64); index = first j
+//   with F_j > t (F = inclusive prefix sum).  Thread chunks of the weight
+//   vector are scanned in LDS; each draw finds its chunk by binary search
+//   and its column by a short walk inside the chunk.
+//   Distinct indices in ascending order with multiplicities, S <- S \ I_c,
+//   appended to the column log.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_draw_cols(DrawArgs a)
+{
+    __shared__ uint64_t sincl[1024];   // inclusive prefix of chunk sums
+    __shared__ int64_t sdraw[1024];
+    __shared__ int64_t ssorted[1024];
+    __shared__ int32_t sflag[1024];
+    __shared__ int32_t spos[1024];
+    __shared__ uint64_t swave[16];
+    const int t = threadIdx.x;
+    DevState *ds = a.ds;
+    const int32_t it = ds->it;
+    const bool unf = a.unf && it > 0;
+    const int64_t n = a.n;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t j0 = (int64_t)t * chunk;
+    const int64_t j1 = (j0 + chunk < n) ? j0 + chunk : n;
+
+    int32_t g = 0;
+    if (a.forced) {
+        // replay: the caller supplies the distinct columns (ascending) and counts
+        g = a.forced_g;
+        for (int32_t d = t; d < g; d += 1024) {
+            a.cols[d] = a.forced[d];
+            a.ccnt[d] = 1;
+        }
+        __syncthreads();
+    } else {
+        uint64_t csum = 0;
+        for (int64_t j = j0; j < j1; ++j)
+            if (a.inS[j]) csum += unf ? 1ULL : a.wq[j];
+        // inclusive scan of csum over 1024 threads (wave scan + wave totals)
+        uint64_t x = csum;
+        const int lane = t & 63, wv = t >> 6;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) swave[wv] = x;
+        __syncthreads();
+        uint64_t off = 0;
+        for (int q = 0; q < wv; ++q) off += swave[q];
+        x += off;
+        sincl[t] = x;
+        __syncthreads();
+        const uint64_t W = sincl[1023];
+        if (W == 0) {
+            if (t == 0) {
+                ds->exhausted = 1;
+                ds->s_empty = 1;
+                ds->g = 0;
+                ds->wtot = 0;
+            }
+            return;
+        }
+        const int32_t c = a.c;
+        for (int32_t d = t; d < c; d += 1024) {
+            uint64_t ctr[4] = {(uint64_t)it, (uint64_t)(d >> 2), a.block, 0};
+            philox4x64_10(ctr, a.seed, 0);
+            const uint64_t u = ctr[d & 3];
+            const uint64_t tg = __umul64hi(u, W);
+            // chunk q: first with sincl[q] > tg
+            int lo = 0, hi = 1023;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (sincl[mid] > tg) hi = mid;
+                else lo = mid + 1;
+            }
+            uint64_t run = (lo > 0) ? sincl[lo - 1] : 0;
+            const int64_t q0 = (int64_t)lo * chunk;
+            const int64_t q1 = (q0 + chunk < n) ? q0 + chunk : n;
+            int64_t sel = q1 - 1;
+            for (int64_t j = q0; j < q1; ++j) {
+                if (a.inS[j]) run += unf ? 1ULL : a.wq[j];
+                if (run > tg) {
+                    sel = j;
+                    break;
+                }
+            }
+            sdraw[d] = sel;
+        }
+        __syncthreads();
+        // rank sort (stable) of the c draws, then keep first occurrences
+        for (int32_t d = t; d < c; d += 1024) {
+            const int64_t v = sdraw[d];
+            int32_t rk = 0;
+            for (int32_t e = 0; e < c; ++e) {
+                const int64_t u = sdraw[e];
+                rk += (u < v) || (u == v && e < d);
+            }
+            ssorted[rk] = v;
+        }
+        __syncthreads();
+        for (int32_t d = t; d < c; d += 1024) sflag[d] = (d == 0) || (ssorted[d] != ssorted[d - 1]);
+        __syncthreads();
+        if (t == 0) {
+            int32_t run2 = 0;
+            for (int32_t d = 0; d < c; ++d) {
+                spos[d] = run2;
+                run2 += sflag[d];
+            }
+            g = run2;
+            spos[1023] = g;
+        }
+        __syncthreads();
+        g = spos[1023];
+        for (int32_t d = t; d < c; d += 1024) {
+            if (sflag[d]) {
+                int32_t e = d + 1;
+                while (e < c && ssorted[e] == ssorted[d]) ++e;
+                a.cols[spos[d]] = (int32_t)ssorted[d];
+                a.ccnt[spos[d]] = e - d;
+            }
+        }
+        if (t == 0) ds->wtot = W;
+        __syncthreads();
+    }
+    // S update and log
+    const int32_t base = ds->col_log_len;
+    for (int32_t d = t; d < g; d += 1024) {
+        const int32_t j = a.cols[d];
+        a.inS[j] = 0;
+        if (base + d < a.n) {
+            a.col_log[base + d] = j;
+            a.ccnt_log[base + d] = a.ccnt[d];
+        }
+    }
+    __syncthreads();
+    // does S keep a drawable column for the next iteration?
+    int left = 0;
+    for (int64_t j = j0; j < j1; ++j)
+        if (a.inS[j] && (a.unf || a.wq[j] != 0)) left = 1;
+    left = __syncthreads_or(left);
+    if (t == 0) {
+        ds->s_empty = !left;
+        ds->g = g;
+        ds->h = 0;
+        ds->ru = g;
+        ds->p0 = ds->rs + g;
+        ds->p = ds->rs + g;
+        if (it < a.max_iter) {
+            a.col_log_off[it] = base;
+            a.col_log_off[it + 1] = base + g;
+        }
+        ds->col_log_len = base + g;
+        ds->exhausted = 0;
+    }
+}
+
+hipError_t launch_draw_cols(const DrawArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_draw_cols, dim3(1), dim3(1024), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace pod

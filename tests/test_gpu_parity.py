@@ -1,0 +1,238 @@
+"""Parity of the HIP library (called through its C ABI) with the FP64 oracle.
+
+Bars: sampled indices and column norms bit-exact; FP64 path singular values
+within 1e-10 relative and largest principal angle <= 1e-8; FP32 path within
+1e-5 / 1e-5 rad (angles measured between the GPU's and the oracle's first k
+modes after the final Rayleigh-Ritz step, sign-free).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import snapgen
+from oracle.isma import IsmaParams, isma as oracle_isma
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1905_05107_amd as pod  # noqa: E402
+
+
+def _dev(A_np):
+    """Column-major device copy of an m x n numpy array."""
+    t = torch.from_numpy(np.ascontiguousarray(np.asarray(A_np).T)).cuda()
+    return t.T
+
+
+def _angles(Ua, Ub):
+    return float(np.max(oracle.subspace_sines(np.asarray(Ua, np.float64), np.asarray(Ub, np.float64))))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pod.lib()
+
+
+# ------------------------------------------------------------------ column norms
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("m,n", [(1, 3), (5, 2), (1023, 4), (1024, 3), (1025, 5), (4097, 7), (20011, 9),
+                                 (262147, 3)])
+def test_col_sqnorms_bit_exact(dtype, m, n):
+    rng = np.random.default_rng(m + n)
+    A = (rng.standard_normal((m, n)) * np.exp(rng.uniform(-3, 3, size=(1, n)))).astype(dtype)
+    print(f"col_sqnorms dtype={np.dtype(dtype).name} m={m} n={n}", flush=True)
+    nu = pod.col_sqnorms(_dev(A)).cpu().numpy()
+    want = oracle.col_sqnorms(A)
+    assert np.array_equal(nu, want)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_col_sqnorms_unaligned_leading_dimension(dtype):
+    rng = np.random.default_rng(7)
+    m, n, lda = 3001, 6, 3003       # lda not a multiple of the vector width
+    store = rng.standard_normal((n, lda)).astype(dtype)
+    t = torch.from_numpy(store).cuda()
+    A_dev = t[:, :m].T
+    nu = pod.col_sqnorms(A_dev).cpu().numpy()
+    want = oracle.col_sqnorms(store[:, :m].T.copy())
+    assert np.array_equal(nu, want)
+
+
+# ------------------------------------------------------------------ small FP64 workload
+
+def _c1_params(**kw):
+    d = dict(k=10, c=20, seed=2001, theta_tol=1e-10)
+    d.update(kw)
+    return d
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return snapgen.config_small_fp64()
+
+
+def test_c1_indices_and_norms_bit_exact(c1):
+    A = c1.A
+    print("c1 indices", flush=True)
+    ref = oracle_isma(A, IsmaParams(**_c1_params()), final_step=False)
+    with pod.PodContext(_dev(A), **_c1_params()) as ctx:
+        nu = ctx.col_sqnorms()
+        assert np.array_equal(nu, oracle.col_sqnorms(A))
+        sines = ctx.run()
+        assert len(sines) == len(ref.log)
+        for it, lg in enumerate(ref.log):
+            cols, cnt = ctx.indices(it)
+            assert np.array_equal(cols, lg.cols), it
+            assert np.array_equal(cnt, lg.col_counts), it
+
+
+@pytest.mark.parametrize("criterion", [pod.POD_CRIT_SUBSPACE, pod.POD_CRIT_MODE])
+def test_c1_fp64_parity(c1, criterion):
+    A = c1.A
+    crit = "subspace" if criterion == pod.POD_CRIT_SUBSPACE else "mode"
+    print(f"c1 fp64 parity {crit}", flush=True)
+    ref = oracle_isma(A, IsmaParams(**_c1_params(criterion=crit)))
+    res = pod.isma(_dev(A), criterion=criterion, **_c1_params())
+    assert res.iters == len(ref.log)
+    U = res.U.cpu().numpy()
+    s = res.sigma.cpu().numpy()
+    assert np.max(np.abs(s - ref.sigma) / ref.sigma) <= 1e-10
+    assert _angles(ref.U, U) <= 1e-8
+    # per-iteration convergence sines agree (explicit residual vs. small-SVD shortcut)
+    for g_s, lg in zip(res.sin_theta[1:], ref.log[1:]):
+        assert abs(g_s - lg.sin_theta) <= 1e-9 * max(1.0, lg.sin_theta) + 1e-12
+    # sign convention: largest-magnitude entry positive
+    for i in range(U.shape[1]):
+        j = int(np.argmax(np.abs(U[:, i])))
+        assert U[j, i] > 0
+    V = res.V.cpu().numpy()
+    assert _angles(ref.V, V) <= 1e-8
+
+
+def test_c1_merge_state_each_iteration(c1):
+    A = c1.A
+    print("c1 merge state", flush=True)
+    for t in (1, 2, 5):
+        ref = oracle_isma(A, IsmaParams(**_c1_params()), n_iter=t, final_step=False)
+        with pod.PodContext(_dev(A), **_c1_params()) as ctx:
+            ctx.run(n_iter=t)
+            U, s = ctx.basis()
+            U, s = U.cpu().numpy(), s.cpu().numpy()
+        assert U.shape[1] == ref.U_merge.shape[1]
+        assert np.max(np.abs(s - ref.s_merge) / ref.s_merge) <= 1e-10, t
+        assert _angles(ref.U_merge[:, :10], U[:, :10]) <= 1e-8, t
+        assert np.linalg.norm(U.T @ U - np.eye(U.shape[1])) <= 1e-12
+
+
+def test_unf_strategy_and_r_larger_than_k(c1):
+    A = c1.A
+    kw = _c1_params(col_strategy="unf", r=30)
+    ref = oracle_isma(A, IsmaParams(**kw))
+    kw_gpu = dict(kw)
+    kw_gpu["col_strategy"] = pod.POD_COL_UNF
+    print("c1 unf r=30", flush=True)
+    res = pod.isma(_dev(A), **kw_gpu)
+    assert res.iters == len(ref.log)
+    s = res.sigma.cpu().numpy()
+    assert np.max(np.abs(s - ref.sigma) / ref.sigma) <= 1e-10
+    assert _angles(ref.U, res.U.cpu().numpy()) <= 1e-8
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_exact_low_rank_recovers_spectrum():
+    s = np.array([3.0, 2.0, 1.5, 1.0, 0.7, 0.4])
+    sm = snapgen.spectrum_matrix(500, 90, s, 0.0, 13, centre=True)
+    print("low rank", flush=True)
+    res = pod.isma(_dev(sm.A), k=6, r=6, c=12, seed=5, theta_tol=1e-13)
+    assert np.max(np.abs(res.sigma.cpu().numpy() - s) / s) < 1e-11
+    assert _angles(sm.U, res.U.cpu().numpy()) < 1e-10
+
+
+def test_exhaustion_samples_each_column_once():
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((80, 37))
+    ref = oracle_isma(A, IsmaParams(k=3, c=8, seed=1, theta_tol=0.0))
+    print("exhaustion", flush=True)
+    with pod.PodContext(_dev(A), k=3, c=8, seed=1, theta_tol=0.0) as ctx:
+        ctx.run()
+        inf = ctx.info()
+        assert inf.exhausted and inf.iter == len(ref.log)
+        cols = np.concatenate([ctx.indices(i)[0] for i in range(inf.iter)])
+        assert np.array_equal(np.sort(cols), np.arange(37))
+        assert ctx.sample() is False
+        U, s, V = ctx.project()
+    assert np.max(np.abs(s.cpu().numpy() - ref.sigma) / ref.sigma) <= 1e-10
+
+
+def test_single_column_and_c_above_n():
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((300, 12))
+    print("c above n", flush=True)
+    res = pod.isma(_dev(A), k=4, c=200, seed=8)
+    Ul, sl, _ = np.linalg.svd(A, full_matrices=False)
+    assert res.iters == 1
+    assert np.max(np.abs(res.sigma.cpu().numpy() - sl[:4]) / sl[:4]) < 1e-12
+    assert _angles(Ul[:, :4], res.U.cpu().numpy()) < 1e-11
+    B = rng.standard_normal((50, 1))
+    res1 = pod.isma(_dev(B), k=1, c=3, seed=1)
+    assert abs(res1.sigma.cpu().numpy()[0] - np.linalg.norm(B)) <= 1e-13 * np.linalg.norm(B)
+
+
+def test_invalid_arguments_rejected():
+    A = _dev(np.zeros((10, 4)))
+    with pytest.raises(pod.PodError) as e:
+        pod.PodContext(A, k=5, c=2, r=3)          # r < k
+    assert e.value.status == pod.POD_EINVAL
+    with pytest.raises(pod.PodError):
+        pod.PodContext(A, k=1, c=0)
+
+
+def test_zero_matrix_is_exhausted_at_once():
+    A = _dev(np.zeros((64, 5)))
+    with pod.PodContext(A, k=1, c=2) as ctx:
+        assert ctx.sample() is True       # no sync: exhaustion is found on the device
+        ctx.merge()
+        done, _ = ctx.converged()
+        assert done and ctx.info().exhausted and ctx.info().iter == 0
+
+
+# ------------------------------------------------------------------ FP32 path (travelling waves)
+
+@pytest.fixture(scope="module")
+def waves_small():
+    return snapgen.waves_np(20000, 400, 60, 1.5, 1e-3, seed=1002)
+
+
+def test_waves_indices_bit_exact_fp32(waves_small):
+    A = waves_small
+    kw = dict(k=20, c=40, seed=2002, theta_tol=1e-5, max_iter=6)
+    ref = oracle_isma(A, IsmaParams(**kw), n_iter=4, final_step=False, elem_bytes=4)
+    print("waves fp32 indices", flush=True)
+    with pod.PodContext(_dev(A), precision=pod.POD_F32, **kw) as ctx:
+        assert np.array_equal(ctx.col_sqnorms(), oracle.col_sqnorms(A))
+        ctx.run(n_iter=4)
+        for it in range(4):
+            assert np.array_equal(ctx.indices(it)[0], ref.log[it].cols)
+
+
+@pytest.mark.parametrize("precision", [pod.POD_F64, pod.POD_F32])
+def test_waves_parity(waves_small, precision):
+    A = waves_small
+    kw = dict(k=20, c=40, seed=2002, theta_tol=1e-5)
+    print(f"waves parity precision={precision}", flush=True)
+    res = pod.isma(_dev(A), precision=precision, **kw)
+    ref = oracle_isma(A, IsmaParams(**kw), n_iter=res.iters, elem_bytes=4)
+    s = res.sigma.cpu().numpy()
+    U = res.U.cpu().numpy()
+    tol_s, tol_a = (1e-10, 1e-8) if precision == pod.POD_F64 else (1e-5, 1e-5)
+    rel = np.max(np.abs(s - ref.sigma) / ref.sigma)
+    ang = _angles(ref.U, U)
+    print(f"  iters={res.iters} sigma_rel={rel:.3e} angle={ang:.3e} flags={res.flags}", flush=True)
+    assert rel <= tol_s
+    assert ang <= tol_a
