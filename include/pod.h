@@ -87,6 +87,8 @@ typedef struct {
     int32_t exhausted;     /* S had no drawable column at the last pod_sample   */
     int32_t flags;         /* bit 0: shifted Cholesky used; bit 1: non-finite;  */
                            /* bit 2: Jacobi sweep limit hit                     */
+    int32_t max_sweeps;    /* most Jacobi sweeps of any merge so far            */
+    int32_t reserved;
     double sin_theta;      /* sine of the last convergence angle (NaN first)    */
 } pod_info;
 
@@ -152,6 +154,29 @@ pod_status pod_col_sqnorms(const void *A_dev, int32_t a_dtype, int64_t m, int64_
  * kind 1: c = w = k^2 (1 + sqrt(ln(2/delta)))^2 / eps^4.
  * Returns -1 for invalid arguments. */
 int64_t pod_sample_size(int32_t kind, int32_t k, double eps, double delta);
+
+/* Kernel classes for measurement (pod_profile_enable). */
+typedef enum {
+    POD_K_COLNORMS = 0,   /* column squared norms (one pass over A)          */
+    POD_K_DRAW = 1,       /* weights + Philox draw + dedupe                  */
+    POD_K_GRAM = 2,       /* partial Grams of the tall block (CholeskyQR)    */
+    POD_K_GRAM_REDUCE = 3,/* fixed-order sum of the Gram partials            */
+    POD_K_CHOL = 4,       /* FP64 Cholesky + triangular inverse (pass 1)     */
+    POD_K_TALL = 5,       /* tall transform Y = X T                          */
+    POD_K_SVD = 6,        /* pass-2 Cholesky + FP64 Jacobi SVD of the merge  */
+    POD_K_PROJECT = 7,    /* B = U^T A (one pass over A)                     */
+    POD_K_RR = 8,         /* Rayleigh-Ritz small kernels                     */
+    POD_K_SIGN = 9,       /* sign convention of the outputs                  */
+    POD_K_COUNT = 10
+} pod_kernel_class;
+
+/* Measurement hook for benchmarks (process-wide, not thread-safe): while a
+ * class is enabled, every launch of that class is bracketed by HIP events on
+ * its launch stream.  pod_profile_read (syncs those events) returns the
+ * number of launches and their summed event time in ms, then clears the
+ * record.  kclass = -1 disables.  POD_EINVAL for an unknown class. */
+pod_status pod_profile_enable(int32_t kclass);
+pod_status pod_profile_read(int64_t *launches, double *total_ms);
 
 /* Release everything the context owns (not A).  Syncs its stream. */
 void pod_destroy(pod_ctx *ctx);

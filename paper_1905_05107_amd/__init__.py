@@ -25,7 +25,7 @@ POD_CRIT_SUBSPACE, POD_CRIT_MODE = 0, 1
 # every symbol include/pod.h declares
 EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project", "pod_get_basis", "pod_get_info",
            "pod_get_indices", "pod_get_col_sqnorms", "pod_col_sqnorms", "pod_sample_size", "pod_destroy",
-           "pod_status_str"]
+           "pod_status_str", "pod_profile_enable", "pod_profile_read"]
 
 
 class PodError(RuntimeError):
@@ -48,7 +48,8 @@ class pod_params(ctypes.Structure):
 class pod_info(ctypes.Structure):
     _fields_ = [
         ("iter", ctypes.c_int32), ("rank", ctypes.c_int32), ("g", ctypes.c_int32), ("h", ctypes.c_int32),
-        ("exhausted", ctypes.c_int32), ("flags", ctypes.c_int32), ("sin_theta", ctypes.c_double),
+        ("exhausted", ctypes.c_int32), ("flags", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("sin_theta", ctypes.c_double),
     ]
 
 
@@ -78,6 +79,8 @@ def lib():
             "pod_sample_size": (i64, [i32, i32, d, d]),
             "pod_destroy": (None, [vp]),
             "pod_status_str": (ctypes.c_char_p, [i32]),
+            "pod_profile_enable": (i32, [i32]),
+            "pod_profile_read": (i32, [P(i64), P(d)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -284,6 +287,22 @@ def isma(A, k: int, c: int, want_v: bool = True, n_iter: Optional[int] = None, *
         tol = kw.get("theta_tol", 1e-10)
         conv = inf.iter >= 2 and not math.isnan(inf.sin_theta) and inf.sin_theta < math.sin(min(tol, math.pi / 2))
         return Result(U, sig, V, inf.iter, sines, bool(inf.exhausted), conv, inf.flags)
+
+
+POD_K = dict(colnorms=0, draw=1, gram=2, gram_reduce=3, chol=4, tall=5, svd=6, project=7, rr=8, sign=9)
+
+
+def profile_enable(kclass):
+    """Time every launch of one kernel class with HIP events (None disables)."""
+    code = -1 if kclass is None else (POD_K[kclass] if isinstance(kclass, str) else int(kclass))
+    _check(lib().pod_profile_enable(code), "pod_profile_enable")
+
+
+def profile_read():
+    """(launches, total ms) of the enabled class since the last read."""
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(lib().pod_profile_read(ctypes.byref(n), ctypes.byref(ms)), "pod_profile_read")
+    return n.value, ms.value
 
 
 def col_sqnorms(A, stream=None):

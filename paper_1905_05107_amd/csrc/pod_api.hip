@@ -34,6 +34,8 @@ struct pod_ctx {
     int32_t nblk = 0;
     double *Bpart = nullptr, *B = nullptr, *GB = nullptr, *UB = nullptr, *sigB = nullptr;
     void *Zc = nullptr;
+    double *signv = nullptr;
+    int64_t *signi = nullptr;
     int32_t nsplit = 0;
     int pending = 0;         // a draw waits for its merge
     int32_t merges = 0;      // merges launched
@@ -78,7 +80,7 @@ void free_all(pod_ctx *ctx)
     void *ptrs[] = {ctx->ds,   ctx->nu,   ctx->wq,    ctx->inS,  ctx->cols, ctx->ccnt, ctx->col_log, ctx->ccnt_log,
                     ctx->col_log_off, ctx->forced, ctx->U[0], ctx->U[1], ctx->sig[0], ctx->sig[1], ctx->part,
                     ctx->G,    ctx->R1,   ctx->R2,    ctx->work, ctx->Tc,   ctx->Y,    ctx->Bpart,
-                    ctx->B,    ctx->GB,   ctx->UB,    ctx->sigB, ctx->Zc};
+                    ctx->B,    ctx->GB,   ctx->UB,    ctx->sigB, ctx->Zc, ctx->signv, ctx->signi};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -219,6 +221,8 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
     ALLOC(ctx->UB, double, (size_t)r * r);
     ALLOC(ctx->sigB, double, r);
     ALLOC(ctx->Zc, unsigned char, (size_t)r * r * ctx->esz);
+    ALLOC(ctx->signv, double, (size_t)64 * r);
+    ALLOC(ctx->signi, int64_t, (size_t)64 * r);
 #undef ALLOC
     if (e != hipSuccess) {
         free_all(ctx);
@@ -388,7 +392,7 @@ pod_status pod_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out
     POD_HIP(launch_gemm_tall(ud, ctx->ds, rs, k, rs, k, ctx->Zc, rs, U_out, ctx->st));
     POD_HIP(hipMemcpyAsync(sigma_out, ctx->sigB, sizeof(double) * k, hipMemcpyDeviceToDevice, ctx->st));
     if (V_out) POD_HIP(launch_rr_v(ctx->B, p.n, rs, k, ctx->UB, ctx->sigB, p.precision, V_out, ctx->st));
-    POD_HIP(launch_sign_fix(p.precision, U_out, p.m, k, V_out, p.n, ctx->st));
+    POD_HIP(launch_sign_fix(p.precision, U_out, p.m, k, V_out, p.n, ctx->signv, ctx->signi, ctx->st));
     s = sync_state(ctx);
     if (s != POD_OK) return s;
     if (ctx->hs.flags & FLAG_NONFINITE) return POD_ENONFINITE;
@@ -425,6 +429,8 @@ pod_status pod_get_info(pod_ctx *ctx, pod_info *info)
     info->h = ctx->hs.h;
     info->exhausted = ctx->hs.exhausted || ctx->hs.s_empty;
     info->flags = ctx->hs.flags;
+    info->max_sweeps = ctx->hs.sweeps;
+    info->reserved = 0;
     info->sin_theta = ctx->hs.sin_theta;
     return POD_OK;
 }

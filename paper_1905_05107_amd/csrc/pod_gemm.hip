@@ -7,16 +7,21 @@
 //
 // X is either the gathered block X0 = [U | A(:, I_c)] -- the sampled columns
 // are streamed straight from A into LDS, never materialised -- or a
-// contiguous m x p workspace.  Row blocks are staged through LDS in
-// column-major order (rows contiguous) with an odd padded stride, so the
-// 16 lanes that read one MFMA operand row hit distinct banks.  Partial sums
-// are FP64 and reduced in a fixed order (deterministic results).
+// contiguous m x p workspace.  Rows are staged through LDS in 32-row stages,
+// column-major with an odd padded stride (the 16 lanes that read one MFMA
+// operand row hit distinct banks).  Stages are loaded as 16-byte vectors
+// into registers one stage ahead of the MFMA work on the current stage.
+// Partial sums are FP64 and reduced in a fixed order (deterministic results).
 #include "pod_internal.h"
 
 namespace pod {
 
 constexpr int RB = 32;       // rows per LDS stage
 constexpr int LDSR = RB + 1; // padded stride (elements) of one staged column
+constexpr int GRP = RB / 4;  // 4-row groups per staged column
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <typename TC> struct SrcT {
     const TC *U;          // basis, ld = m
@@ -30,16 +35,6 @@ template <typename TC> struct SrcT {
     int32_t guard;        // skip when the pending draw found S exhausted
 };
 
-template <typename TC>
-__device__ __forceinline__ TC src_load(const SrcT<TC> &s, int64_t m, int c, int64_t row)
-{
-    if (!s.gather) return s.Y[(int64_t)c * m + row];
-    if (c < s.rs) return s.U[(int64_t)c * m + row];
-    const int64_t j = s.cols[c - s.rs];
-    if (s.a_f64) return (TC)(reinterpret_cast<const double *>(s.A)[j * s.lda + row]);
-    return (TC)(reinterpret_cast<const float *>(s.A)[j * s.lda + row]);
-}
-
 __device__ __forceinline__ int sel_count(const DevState *ds, int sel)
 {
     if (sel >= 0) return sel;
@@ -51,32 +46,127 @@ __device__ __forceinline__ int sel_count(const DevState *ds, int sel)
     }
 }
 
-// Stage rows [r0, r0 + RB) x columns [0, P) of the source into Xs (column c at
-// Xs + c * LDSR); rows past m and columns past P are zero.
-template <typename TC>
-__device__ __forceinline__ void stage_rows(const SrcT<TC> &s, int64_t m, int64_t r0, int P, int PP, TC *Xs)
+// Address and storage type of one source column.
+struct ColPtr {
+    const void *p;
+    int f64;   // element is double
+};
+template <typename TC> __device__ __forceinline__ ColPtr col_ptr(const SrcT<TC> &s, int64_t m, int c)
 {
-    for (int idx = threadIdx.x; idx < PP * RB; idx += 256) {
-        const int c = idx / RB, rr = idx % RB;
-        const int64_t row = r0 + rr;
-        TC v = (TC)0;
-        if (c < P && row < m) v = src_load<TC>(s, m, c, row);
-        Xs[c * LDSR + rr] = v;
+    ColPtr r;
+    if (!s.gather) {
+        r.p = s.Y + (int64_t)c * m;
+        r.f64 = sizeof(TC) == 8;
+    } else if (c < s.rs) {
+        r.p = s.U + (int64_t)c * m;
+        r.f64 = sizeof(TC) == 8;
+    } else {
+        const int64_t j = s.cols[c - s.rs];
+        if (s.a_f64) {
+            r.p = reinterpret_cast<const double *>(s.A) + j * s.lda;
+            r.f64 = 1;
+        } else {
+            r.p = reinterpret_cast<const float *>(s.A) + j * s.lda;
+            r.f64 = 0;
+        }
+    }
+    return r;
+}
+
+// Four consecutive rows [row, row + 4) of a column, converted to TC; vector
+// loads when the group is in range and the column is 16-byte aligned.
+template <typename TC>
+__device__ __forceinline__ void load4(const ColPtr &cp, int64_t row, int64_t lim, bool vec, TC out[4])
+{
+    if (cp.f64) {
+        const double *p = reinterpret_cast<const double *>(cp.p) + row;
+        if (vec && row + 4 <= lim) {
+            const f64x2 a = *reinterpret_cast<const f64x2 *>(p);
+            const f64x2 b = *reinterpret_cast<const f64x2 *>(p + 2);
+            out[0] = (TC)a[0];
+            out[1] = (TC)a[1];
+            out[2] = (TC)b[0];
+            out[3] = (TC)b[1];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out[q] = (row + q < lim) ? (TC)p[q] : (TC)0;
+        }
+    } else {
+        const float *p = reinterpret_cast<const float *>(cp.p) + row;
+        if (vec && row + 4 <= lim) {
+            const f32x4 a = *reinterpret_cast<const f32x4 *>(p);
+            out[0] = (TC)a[0];
+            out[1] = (TC)a[1];
+            out[2] = (TC)a[2];
+            out[3] = (TC)a[3];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out[q] = (row + q < lim) ? (TC)p[q] : (TC)0;
+        }
     }
 }
 
+// A register-held stage: item `it` of thread t is (column, 4-row group)
+// = ((t + 256 it) / GRP, (t + 256 it) % GRP).
+template <typename TC, int ITEMS> struct Stage {
+    TC v[ITEMS][4];
+
+    __device__ __forceinline__ void load(const SrcT<TC> &s, int64_t m, int64_t rb, int P, bool vec)
+    {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int idx = threadIdx.x + 256 * it;
+            const int c = idx / GRP, g = idx % GRP;
+            if (c < P) {
+                const ColPtr cp = col_ptr<TC>(s, m, c);
+                load4<TC>(cp, rb + 4 * g, m, vec, v[it]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[it][q] = (TC)0;
+            }
+        }
+    }
+    __device__ __forceinline__ void store(TC *Xs, int PP) const
+    {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int idx = threadIdx.x + 256 * it;
+            const int c = idx / GRP, g = idx % GRP;
+            if (c < PP) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Xs[c * LDSR + 4 * g + q] = v[it][q];
+            }
+        }
+    }
+};
+
+// 16-byte loads are legal for every column of the source.
+template <typename TC> static bool vec_ok(const SrcT<TC> &s, int64_t m)
+{
+    const size_t esz = sizeof(TC);
+    bool ok = ((m * esz) % 16 == 0);
+    if (s.gather) {
+        ok = ok && ((uintptr_t)s.U % 16 == 0);
+        const size_t ae = s.a_f64 ? 8 : 4;
+        ok = ok && ((uintptr_t)s.A % 16 == 0) && ((s.lda * ae) % 16 == 0);
+    } else {
+        ok = ok && ((uintptr_t)s.Y % 16 == 0);
+    }
+    return ok;
+}
+
 // ---------------------------------------------------------------------------
-// Partial Grams.  Workgroup b owns rows [m b / nblk, m (b+1) / nblk); each of
-// its 4 waves accumulates a fixed set of the upper-triangular 16x16 tiles
-// (I <= J) over the staged rows.  The tile is written (and mirrored) to
-// part[b] (pmax x pmax, FP64); tiles outside P x P stay untouched and are
-// ignored by the reduction.
+// Partial Grams.  Workgroup b owns stages [ns b / nblk, ns (b+1) / nblk) of
+// the ns = ceil(m / 32) row stages; each of its 4 waves accumulates a fixed
+// set of the upper-triangular 16x16 tiles (I <= J).  The tile is written (and
+// mirrored) to part[b] (pmax x pmax, FP64); the reduction reads only P x P.
 // ---------------------------------------------------------------------------
-constexpr int MAXPW = 3;  // tiles per wave for pmax <= 64 (10 tiles / 4 waves)
+constexpr int MAXPW = 3;     // tiles per wave for pmax <= 64 (10 tiles / 4 waves)
+constexpr int ITEMS64 = 2;   // 64 columns x 8 groups / 256 threads
 
 template <typename TC>
 __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, const DevState *ds, int which_p,
-                                                      int pmax, double *__restrict__ part, int nblk)
+                                                      int pmax, double *__restrict__ part, int nblk, int vec)
 {
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
@@ -88,8 +178,8 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
     const int NT16 = PP / 16;
     const int npairs = NT16 * (NT16 + 1) / 2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t b = blockIdx.x;
-    const int64_t r0 = (m * b) / nblk, r1 = (m * (b + 1)) / nblk;
+    const int64_t nst = (m + RB - 1) / RB;
+    const int64_t s0 = (nst * blockIdx.x) / nblk, s1 = (nst * (blockIdx.x + 1)) / nblk;
     int tI[MAXPW], tJ[MAXPW];
 #pragma unroll
     for (int q = 0; q < MAXPW; ++q) {
@@ -108,18 +198,13 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
     AccT acc[MAXPW];
 #pragma unroll
     for (int q = 0; q < MAXPW; ++q) acc[q] = AccT{0, 0, 0, 0};
-    for (int64_t rb = r0; rb < r1; rb += RB) {
+    Stage<TC, ITEMS64> st;
+    if (s0 < s1) st.load(s, m, s0 * RB, P, vec);
+    for (int64_t sg = s0; sg < s1; ++sg) {
         __syncthreads();
-        // rows past r1 belong to the next workgroup: mask them
-        const int64_t lim = (rb + RB < r1) ? rb + RB : r1;
-        for (int idx = threadIdx.x; idx < PP * RB; idx += 256) {
-            const int c = idx / RB, rr = idx % RB;
-            const int64_t row = rb + rr;
-            TC v = (TC)0;
-            if (c < P && row < lim) v = src_load<TC>(s, m, c, row);
-            Xs[c * LDSR + rr] = v;
-        }
+        st.store(Xs, PP);
         __syncthreads();
+        if (sg + 1 < s1) st.load(s, m, (sg + 1) * RB, P, vec);
 #pragma unroll
         for (int q = 0; q < MAXPW; ++q) {
             if (tI[q] >= 0) {
@@ -130,7 +215,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
             }
         }
     }
-    double *pb = part + b * (int64_t)pmax * pmax;
+    double *pb = part + (int64_t)blockIdx.x * pmax * pmax;
 #pragma unroll
     for (int q = 0; q < MAXPW; ++q) {
         if (tI[q] < 0) continue;
@@ -139,12 +224,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
         for (int v = 0; v < 4; ++v) {
             const int i = tI[q] * 16 + acc_row<TC>(lane, v);
             const double x = (double)acc[q][v];
-            if (tI[q] == tJ[q]) {
-                if (i <= j) {
-                    pb[i + (int64_t)j * pmax] = x;
-                    pb[j + (int64_t)i * pmax] = x;
-                }
-            } else {
+            if (tI[q] < tJ[q] || i <= j) {
                 pb[i + (int64_t)j * pmax] = x;
                 pb[j + (int64_t)i * pmax] = x;
             }
@@ -152,17 +232,26 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
     }
 }
 
+// Fixed-order reduction of the partial Grams: workgroup w owns 64 entries;
+// its 4 waves each add a contiguous quarter of the partials in order, and the
+// four quarter sums are added in order.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ part, int nblk, int pmax,
                                                      const DevState *ds, int which_p, double *__restrict__ G)
 {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= pmax * pmax || ds->exhausted) return;
+    __shared__ double sq[4][64];
+    if (ds->exhausted) return;
     const int P = sel_count(ds, which_p);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int idx = blockIdx.x * 64 + lane;
     const int i = idx % pmax, j = idx / pmax;
+    const bool live = idx < pmax * pmax && i < P && j < P;
+    const int b0 = (nblk * wv) / 4, b1 = (nblk * (wv + 1)) / 4;
     double s = 0.0;
-    if (i < P && j < P)
-        for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * pmax * pmax + idx];
-    G[idx] = s;
+    if (live)
+        for (int b = b0; b < b1; ++b) s += part[(int64_t)b * pmax * pmax + idx];
+    sq[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && idx < pmax * pmax) G[idx] = live ? ((sq[0][lane] + sq[1][lane]) + sq[2][lane]) + sq[3][lane] : 0.0;
 }
 
 template <typename TC> static SrcT<TC> make_src(const GemmDesc &d)
@@ -184,14 +273,17 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
                                int32_t nblk, hipStream_t st)
 {
     if (pmax > 64) return hipErrorInvalidValue;
+    ProfScope ps(POD_K_GRAM, st);
     if (d.prec == POD_F64) {
+        const SrcT<double> s = make_src<double>(d);
         const size_t lds = (size_t)pmax * LDSR * sizeof(double);
-        hipLaunchKernelGGL(k_gram_partial<double>, dim3(nblk), dim3(256), lds, st, make_src<double>(d), d.m, ds,
-                           which_p, pmax, part, nblk);
+        hipLaunchKernelGGL(k_gram_partial<double>, dim3(nblk), dim3(256), lds, st, s, d.m, ds, which_p, pmax, part,
+                           nblk, (int)vec_ok(s, d.m));
     } else {
+        const SrcT<float> s = make_src<float>(d);
         const size_t lds = (size_t)pmax * LDSR * sizeof(float);
-        hipLaunchKernelGGL(k_gram_partial<float>, dim3(nblk), dim3(256), lds, st, make_src<float>(d), d.m, ds,
-                           which_p, pmax, part, nblk);
+        hipLaunchKernelGGL(k_gram_partial<float>, dim3(nblk), dim3(256), lds, st, s, d.m, ds, which_p, pmax, part,
+                           nblk, (int)vec_ok(s, d.m));
     }
     return hipGetLastError();
 }
@@ -199,21 +291,24 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
 hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax, const DevState *ds,
                                   int32_t which_p, double *G, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gram_reduce, dim3((pmax * pmax + 255) / 256), dim3(256), 0, st, part, nblk, pmax, ds,
-                       which_p, G);
+    ProfScope ps(POD_K_GRAM_REDUCE, st);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((pmax * pmax + 63) / 64), dim3(256), 0, st, part, nblk, pmax, ds, which_p,
+                       G);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Tall transform Y = X T (m x pout) with T pin x pout (ld ldt, compute type).
-// Each workgroup stages RB rows of X and all of T in LDS and produces the
-// RB x pout block of Y as Y^T tiles = T^T X^T, so that each lane's four
-// results are consecutive-row entries of one output column.
+// Each workgroup stages T once and TALL_ST stages of RB rows of X, producing
+// the output as Y^T tiles = T^T X^T so that each lane's four results are
+// consecutive rows of one output column.
 // ---------------------------------------------------------------------------
+constexpr int TALL_ST = 4;   // row stages per workgroup
+
 template <typename TC>
 __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
                                                    int sel_out, int pmax_in, int pmax_out, const TC *__restrict__ T,
-                                                   int ldt, TC *__restrict__ Yout)
+                                                   int ldt, TC *__restrict__ Yout, int vec)
 {
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
@@ -221,30 +316,38 @@ __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const 
     const int pin = sel_count(ds, sel_in), pout = sel_count(ds, sel_out);
     s.rs = ds->rs;
     const int PI = (pin + 15) & ~15, PO = (pout + 15) & ~15;
-    TC *Xs = reinterpret_cast<TC *>(lds_raw);        // PI x LDSR
+    TC *Xs = reinterpret_cast<TC *>(lds_raw);        // pmax_in x LDSR
     TC *Ts = Xs + pmax_in * LDSR;                    // PI x PO, row k at Ts + k * PO
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    const int64_t nst = (m + RB - 1) / RB;
+    const int64_t s0 = (int64_t)blockIdx.x * TALL_ST;
+    const int64_t s1 = (s0 + TALL_ST < nst) ? s0 + TALL_ST : nst;
     for (int idx = threadIdx.x; idx < PI * PO; idx += 256) {
         const int k = idx / PO, j = idx % PO;
         Ts[idx] = (k < pin && j < pout) ? T[k + (int64_t)j * ldt] : (TC)0;
     }
-    stage_rows<TC>(s, m, r0, pin, PI, Xs);
-    __syncthreads();
-    // tiles: (row block rbk in 0..RB/16) x (col block jc in 0..PO/16)
+    (void)pmax_out;
+    Stage<TC, ITEMS64> st;
+    st.load(s, m, s0 * RB, pin, vec);
     const int ntile = (RB / 16) * (PO / 16);
-    for (int tile = wv; tile < ntile; tile += 4) {
-        const int rbk = tile % (RB / 16), jc = tile / (RB / 16);
-        AccT acc = AccT{0, 0, 0, 0};
-        const TC *ta = Ts + (lane >> 4) * PO + jc * 16 + (lane & 15);
-        const TC *xb = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
-        for (int k4 = 0; k4 < PI; k4 += 4) acc = mfma16x16x4(ta[k4 * PO], xb[k4 * LDSR], acc);
-        const int64_t row = r0 + rbk * 16 + (lane & 15);
-        if (row < m) {
+    for (int64_t sg = s0; sg < s1; ++sg) {
+        __syncthreads();
+        st.store(Xs, PI);
+        __syncthreads();
+        if (sg + 1 < s1) st.load(s, m, (sg + 1) * RB, pin, vec);
+        for (int tile = wv; tile < ntile; tile += 4) {
+            const int rbk = tile % (RB / 16), jc = tile / (RB / 16);
+            AccT acc = AccT{0, 0, 0, 0};
+            const TC *ta = Ts + (lane >> 4) * PO + jc * 16 + (lane & 15);
+            const TC *xb = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
+            for (int k4 = 0; k4 < PI; k4 += 4) acc = mfma16x16x4(ta[k4 * PO], xb[k4 * LDSR], acc);
+            const int64_t row = sg * RB + rbk * 16 + (lane & 15);
+            if (row < m) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int col = jc * 16 + acc_row<TC>(lane, v);
-                if (col < pout) Yout[(int64_t)col * m + row] = acc[v];
+                for (int v = 0; v < 4; ++v) {
+                    const int col = jc * 16 + acc_row<TC>(lane, v);
+                    if (col < pout) Yout[(int64_t)col * m + row] = acc[v];
+                }
             }
         }
     }
@@ -255,47 +358,50 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
                             hipStream_t st)
 {
     if (pin_max > 64 || pout_max > 64) return hipErrorInvalidValue;
-    const unsigned nb = (unsigned)((d.m + RB - 1) / RB);
+    ProfScope ps(POD_K_TALL, st);
+    const int64_t nst = (d.m + RB - 1) / RB;
+    const unsigned nb = (unsigned)((nst + TALL_ST - 1) / TALL_ST);
     const int PI = (pin_max + 15) & ~15, PO = (pout_max + 15) & ~15;
     if (d.prec == POD_F64) {
+        const SrcT<double> s = make_src<double>(d);
         const size_t lds = (size_t)(PI * LDSR + PI * PO) * sizeof(double);
-        hipLaunchKernelGGL(k_gemm_tall<double>, dim3(nb), dim3(256), lds, st, make_src<double>(d), d.m, ds,
-                           which_in, which_out, PI, PO, (const double *)T, ldt, (double *)Yout);
+        hipLaunchKernelGGL(k_gemm_tall<double>, dim3(nb), dim3(256), lds, st, s, d.m, ds, which_in, which_out, PI,
+                           PO, (const double *)T, ldt, (double *)Yout, (int)vec_ok(s, d.m));
     } else {
+        const SrcT<float> s = make_src<float>(d);
         const size_t lds = (size_t)(PI * LDSR + PI * PO) * sizeof(float);
-        hipLaunchKernelGGL(k_gemm_tall<float>, dim3(nb), dim3(256), lds, st, make_src<float>(d), d.m, ds,
-                           which_in, which_out, PI, PO, (const float *)T, ldt, (float *)Yout);
+        hipLaunchKernelGGL(k_gemm_tall<float>, dim3(nb), dim3(256), lds, st, s, d.m, ds, which_in, which_out, PI, PO,
+                           (const float *)T, ldt, (float *)Yout, (int)vec_ok(s, d.m));
     }
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Projection B = U^T A (r x n), one pass over A.  Workgroup (split, column
-// block of 64) covers rows [m s / nsplit, m (s+1) / nsplit) of 64 columns of
-// A; wave w owns 16 of those columns and all ceil(r/16) mode tiles.  The
-// linear block index is remapped so that all column blocks of one row split
-// run on the same XCD (workgroups are dealt round-robin to the 8 XCDs), where
-// they share that split's rows of U in L2.
+// block of 64) covers row stages [ns s / nsplit, ns (s+1) / nsplit) of 64
+// columns of A; wave w owns 16 of those columns and all ceil(r/16) mode
+// tiles.  The linear block index is remapped so that all column blocks of
+// one row split run on the same XCD (workgroups are dealt round-robin to the
+// 8 XCDs), where they share that split's rows of U in L2.
 // ---------------------------------------------------------------------------
 constexpr int PCB = 64;  // columns of A per workgroup
 
 template <typename TC, typename TA>
 __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ U, const TA *__restrict__ A,
                                                          int64_t m, int64_t n, int64_t lda, int r, int nsplit,
-                                                         int ncb, double *__restrict__ Bpart)
+                                                         int ncb, double *__restrict__ Bpart, int vec)
 {
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
     const int RP = (r + 15) & ~15;
     TC *As = reinterpret_cast<TC *>(lds_raw);   // PCB x LDSR
     TC *Us = As + PCB * LDSR;                   // RP x LDSR
-    // XCD-aware remap of the linear workgroup id
     const int total = nsplit * ncb;
     const int id = blockIdx.x;
     int sidx, cb;
     if (total % 8 == 0 && nsplit % 8 == 0) {
-        const int xcd = id % 8, local = id / 8;   // local in [0, total/8)
-        const int spx = nsplit / 8;               // splits per XCD
+        const int xcd = id % 8, local = id / 8;
+        const int spx = nsplit / 8;
         sidx = xcd * spx + local / ncb;
         cb = local % ncb;
     } else {
@@ -303,26 +409,56 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
         cb = id % ncb;
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t r0 = (m * sidx) / nsplit, r1 = (m * (sidx + 1)) / nsplit;
+    const int64_t nst = (m + RB - 1) / RB;
+    const int64_t s0 = (nst * sidx) / nsplit, s1 = (nst * (sidx + 1)) / nsplit;
     const int64_t c0 = (int64_t)cb * PCB;
+    const int ncol = (n - c0 < PCB) ? (int)(n - c0) : PCB;
+    SrcT<TC> su;
+    su.U = nullptr;
+    su.A = nullptr;
+    su.lda = 0;
+    su.cols = nullptr;
+    su.Y = U;
+    su.gather = 0;
+    su.a_f64 = 0;
+    su.rs = 0;
+    su.guard = 0;
     constexpr int MT = 4;  // r <= 64
     AccT acc[MT];
 #pragma unroll
     for (int q = 0; q < MT; ++q) acc[q] = AccT{0, 0, 0, 0};
-    for (int64_t rb = r0; rb < r1; rb += RB) {
-        __syncthreads();
-        const int64_t lim = (rb + RB < r1) ? rb + RB : r1;
-        for (int idx = threadIdx.x; idx < PCB * RB; idx += 256) {
-            const int c = idx / RB, rr = idx % RB;
-            const int64_t row = rb + rr, col = c0 + c;
-            As[c * LDSR + rr] = (row < lim && col < n) ? (TC)A[col * lda + row] : (TC)0;
+    // A stage: 64 columns x 8 groups = 512 items; U stage: RP columns x 8 groups <= 512 items
+    Stage<TC, 2> sta, stu;
+    const TA *Ab = A + c0 * lda;
+    auto loadA = [&](int64_t sg) {
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int idx = threadIdx.x + 256 * it;
+            const int c = idx / GRP, g = idx % GRP;
+            if (c < ncol) {
+                ColPtr cp;
+                cp.p = Ab + (int64_t)c * lda;
+                cp.f64 = sizeof(TA) == 8;
+                load4<TC>(cp, sg * RB + 4 * g, m, vec, sta.v[it]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sta.v[it][q] = (TC)0;
+            }
         }
-        for (int idx = threadIdx.x; idx < RP * RB; idx += 256) {
-            const int c = idx / RB, rr = idx % RB;
-            const int64_t row = rb + rr;
-            Us[c * LDSR + rr] = (row < lim && c < r) ? U[(int64_t)c * m + row] : (TC)0;
-        }
+    };
+    if (s0 < s1) {
+        loadA(s0);
+        stu.load(su, m, s0 * RB, r, vec);
+    }
+    for (int64_t sg = s0; sg < s1; ++sg) {
         __syncthreads();
+        sta.store(As, PCB);
+        stu.store(Us, RP);
+        __syncthreads();
+        if (sg + 1 < s1) {
+            loadA(sg + 1);
+            stu.load(su, m, (sg + 1) * RB, r, vec);
+        }
         const TC *xb = As + (wv * 16 + (lane & 15)) * LDSR + (lane >> 4);
 #pragma unroll
         for (int q = 0; q < MT; ++q) {
@@ -362,21 +498,26 @@ hipError_t launch_project_partial(const ProjArgs &a, hipStream_t st)
     const int ncb = (int)((a.n + PCB - 1) / PCB);
     const int RP = (a.r + 15) & ~15;
     const unsigned total = (unsigned)(a.nsplit * ncb);
+    ProfScope ps(POD_K_PROJECT, st);
+    const size_t ae = (a.a_dtype == POD_F64) ? 8 : 4;
+    const size_t ce = (a.prec == POD_F64) ? 8 : 4;
+    const int vec = ((uintptr_t)a.A % 16 == 0) && ((a.lda * ae) % 16 == 0) && ((uintptr_t)a.U % 16 == 0) &&
+                    ((a.m * ce) % 16 == 0);
     if (a.prec == POD_F64) {
         const size_t lds = (size_t)(PCB + RP) * LDSR * sizeof(double);
         if (a.a_dtype == POD_F64)
             hipLaunchKernelGGL((k_project_partial<double, double>), dim3(total), dim3(256), lds, st,
                                (const double *)a.U, (const double *)a.A, a.m, a.n, a.lda, a.r, a.nsplit, ncb,
-                               a.Bpart);
+                               a.Bpart, vec);
         else
             hipLaunchKernelGGL((k_project_partial<double, float>), dim3(total), dim3(256), lds, st,
                                (const double *)a.U, (const float *)a.A, a.m, a.n, a.lda, a.r, a.nsplit, ncb,
-                               a.Bpart);
+                               a.Bpart, vec);
     } else {
         const size_t lds = (size_t)(PCB + RP) * LDSR * sizeof(float);
         if (a.a_dtype == POD_F64) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_project_partial<float, float>), dim3(total), dim3(256), lds, st, (const float *)a.U,
-                           (const float *)a.A, a.m, a.n, a.lda, a.r, a.nsplit, ncb, a.Bpart);
+                           (const float *)a.A, a.m, a.n, a.lda, a.r, a.nsplit, ncb, a.Bpart, vec);
     }
     return hipGetLastError();
 }
@@ -384,6 +525,7 @@ hipError_t launch_project_partial(const ProjArgs &a, hipStream_t st)
 hipError_t launch_project_reduce(const ProjArgs &a, hipStream_t st)
 {
     const int64_t rn = (int64_t)a.r * a.n;
+    ProfScope ps(POD_K_PROJECT, st);
     hipLaunchKernelGGL(k_project_reduce, dim3((unsigned)((rn + 255) / 256)), dim3(256), 0, st, a.Bpart, rn,
                        a.nsplit, a.B);
     return hipGetLastError();

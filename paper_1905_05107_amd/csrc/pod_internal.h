@@ -81,6 +81,14 @@ __device__ __forceinline__ v4f mfma16x16x4(float a, float b, v4f c)
 // ---------------------------------------------------------------- host launchers
 namespace pod {
 
+// Brackets one launch with HIP events when its kernel class is being profiled.
+struct ProfScope {
+    ProfScope(int kclass, hipStream_t st);
+    ~ProfScope();
+    bool on;
+    hipStream_t st;
+};
+
 hipError_t launch_col_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *nu,
                               hipStream_t st);
 hipError_t launch_row_means(const void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *part,
@@ -175,6 +183,7 @@ struct RRArgs {
 hipError_t launch_rr_small(const RRArgs &a, hipStream_t st);
 hipError_t launch_rr_v(const double *B, int64_t n, int32_t r, int32_t k, const double *UB, const double *sig,
                        int32_t prec, void *V, hipStream_t st);
-hipError_t launch_sign_fix(int32_t prec, void *U, int64_t m, int32_t k, void *V, int64_t n, hipStream_t st);
+hipError_t launch_sign_fix(int32_t prec, void *U, int64_t m, int32_t k, void *V, int64_t n, double *cv, int64_t *ci,
+                           hipStream_t st);
 
 }  // namespace pod

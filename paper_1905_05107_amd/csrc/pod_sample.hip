@@ -98,6 +98,7 @@ hipError_t launch_col_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t
                               hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
+    ProfScope ps(POD_K_COLNORMS, st);
     if (a_dtype == POD_F64)
         hipLaunchKernelGGL(k_col_sqnorms<double>, dim3((unsigned)n), dim3(256), 0, st, (const double *)A, m, lda,
                            nu);
@@ -223,6 +224,7 @@ __global__ __launch_bounds__(1024) void k_quantize(const double *__restrict__ v,
 
 hipError_t launch_quantize(const double *v, int64_t len, uint64_t *w, DevState *ds, hipStream_t st)
 {
+    ProfScope ps(POD_K_DRAW, st);
     hipLaunchKernelGGL(k_quantize, dim3(1), dim3(1024), 0, st, v, len, w, ds);
     return hipGetLastError();
 }
@@ -390,6 +392,7 @@ __global__ __launch_bounds__(1024) void k_draw_cols(DrawArgs a)
 
 hipError_t launch_draw_cols(const DrawArgs &a, hipStream_t st)
 {
+    ProfScope ps(POD_K_DRAW, st);
     hipLaunchKernelGGL(k_draw_cols, dim3(1), dim3(1024), 0, st, a);
     return hipGetLastError();
 }

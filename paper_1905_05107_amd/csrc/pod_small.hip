@@ -10,7 +10,7 @@
 
 namespace pod {
 
-constexpr int NT = 1024;
+constexpr int NT = 512;
 
 // ---------------------------------------------------------------------------
 // In-place Cholesky S = R^T R of the symmetric p x p matrix S (LDS,
@@ -74,72 +74,121 @@ __device__ void trinv_upper(double *R, int p, double *tmp)
 }
 
 // ---------------------------------------------------------------------------
-// One-sided (Hestenes) Jacobi on the columns of X (rows x cols, column-major,
-// ld = rows, LDS), parallel round-robin ordering: each step rotates cols/2
-// disjoint pairs, G threads per pair.  A pair (a, b) is rotated when
-// |x_a^T x_b| > tol |x_a| |x_b|; the sweep loop stops after a sweep without
-// rotation.  Returns the number of sweeps or -1.
+// Wave-local helpers: sums over aligned groups of G lanes by DPP moves
+// (mirror / half-mirror / quad permutations: no LDS traffic), and an FP64
+// reciprocal square root from the FP32 estimate refined by two Newton steps
+// (relative error below 1e-15).
 // ---------------------------------------------------------------------------
-__device__ int jacobi_cols(double *X, int rows, int cols, double tol, int max_sweeps, int *sflag)
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
 {
-    if (cols < 2) return 1;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int G> __device__ __forceinline__ double group_sum(double v)
+{
+    if (G >= 16) v += dpp_f64<0x140>(v);   // row_mirror
+    if (G >= 8) v += dpp_f64<0x141>(v);    // row_half_mirror
+    if (G >= 4) v += dpp_f64<0x4E>(v);     // quad_perm [2,3,0,1]
+    if (G >= 2) v += dpp_f64<0xB1>(v);     // quad_perm [1,0,3,2]
+    return v;
+}
+__device__ __forceinline__ double rsqrt_f64(double x)
+{
+    // x = f 2^e with f in [0.5, 2) and e even keeps the FP32 estimate in range
+    int e;
+    double f = frexp(x, &e);
+    if (e & 1) {
+        f *= 2.0;
+        e -= 1;
+    }
+    double y = (double)__frsqrt_rn((float)f);
+    y = y * fma(-0.5 * f * y, y, 1.5);
+    y = y * fma(-0.5 * f * y, y, 1.5);
+    return ldexp(y, -e / 2);
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi on the columns of X (rows x cols, column-major,
+// ld = rows, LDS, rows <= 64), parallel round-robin ordering: each step
+// rotates cols/2 disjoint pairs, G threads per pair (a pair's two columns
+// are held in registers for the step).  A pair is rotated when
+// (x_a^T x_b)^2 > tol^2 |x_a|^2 |x_b|^2, with
+//   tau = |x_b|^2 - |x_a|^2, rho = 2 x_a^T x_b, h = sqrt(tau^2 + rho^2),
+//   d = |tau| + h, c = d / sqrt(d^2 + rho^2), s = sign(tau) rho / sqrt(d^2 + rho^2),
+// the closed form of the classical angle t = sign(zeta)/(|zeta| + sqrt(1+zeta^2)),
+// zeta = tau/rho, written without divisions by rho.  The sweep loop stops
+// after a sweep without rotation.  `sched` holds (cols|1)*(cols+1)/2 short2.
+// Returns the number of sweeps or -1.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ int jacobi_cols_g(double *X, int rows, int cols, double tol, int max_sweeps, short2 *sched)
+{
+    constexpr int MAXR = 64 / G;
     const int np = (cols + 1) & ~1;
     const int npair = np / 2;
-    int G = 64;
-    while (G > 1 && npair * G > NT) G >>= 1;
+    for (int i = threadIdx.x; i < (np - 1) * npair; i += NT) {
+        const int s = i / npair, q = i % npair;
+        const int a = (q == 0) ? 0 : ((q - 1 + s) % (np - 1)) + 1;
+        const int b = ((np - 2 - q + s) % (np - 1)) + 1;
+        sched[i] = make_short2((short)a, (short)b);
+    }
+    __syncthreads();
     const int q = threadIdx.x / G, gl = threadIdx.x % G;
     const bool active = q < npair;
+    const double tol2 = tol * tol;
     for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
-        if (threadIdx.x == 0) *sflag = 0;
-        __syncthreads();
+        int rotated = 0;
         for (int s = 0; s < np - 1; ++s) {
-            int a = 0, b = 0;
-            if (active) {
-                a = (q == 0) ? 0 : ((q - 1 + s) % (np - 1)) + 1;
-                const int qb = np - 1 - q;
-                b = ((qb - 1 + s) % (np - 1)) + 1;
-            }
+            const short2 ab = active ? sched[s * npair + q] : make_short2(0, 0);
+            const int a = ab.x, b = ab.y;
             const bool real = active && a < cols && b < cols;
+            double xa[MAXR], xb[MAXR];
             double al = 0.0, be = 0.0, ga = 0.0;
-            if (real) {
-                const double *xa = X + (int64_t)a * rows, *xb = X + (int64_t)b * rows;
-                for (int r = gl; r < rows; r += G) {
-                    const double u = xa[r], v = xb[r];
-                    al += u * u;
-                    be += v * v;
-                    ga += u * v;
-                }
-            }
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                if (o < G) {
-                    al += __shfl_xor(al, o, 64);
-                    be += __shfl_xor(be, o, 64);
-                    ga += __shfl_xor(ga, o, 64);
-                }
+            for (int i = 0; i < MAXR; ++i) {
+                const int r = gl + i * G;
+                const bool ok = real && r < rows;
+                xa[i] = ok ? X[a * rows + r] : 0.0;
+                xb[i] = ok ? X[b * rows + r] : 0.0;
+                al = fma(xa[i], xa[i], al);
+                be = fma(xb[i], xb[i], be);
+                ga = fma(xa[i], xb[i], ga);
             }
-            if (real && ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-                const double zeta = (be - al) / (2.0 * ga);
-                double t;
-                if (fabs(zeta) > 1e150) t = 0.5 / zeta;
-                else t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + t * t);
-                const double sn = c * t;
-                double *xa = X + (int64_t)a * rows, *xb = X + (int64_t)b * rows;
-                for (int r = gl; r < rows; r += G) {
-                    const double u = xa[r], v = xb[r];
-                    xa[r] = c * u - sn * v;
-                    xb[r] = sn * u + c * v;
+            al = group_sum<G>(al);
+            be = group_sum<G>(be);
+            ga = group_sum<G>(ga);
+            if (real && ga * ga > tol2 * al * be) {
+                const double tau = be - al, rho = 2.0 * ga;
+                const double x1 = fma(tau, tau, rho * rho);
+                const double h = x1 * rsqrt_f64(x1);
+                const double d = fabs(tau) + h;
+                const double iw = rsqrt_f64(fma(d, d, rho * rho));
+                const double c = d * iw;
+                const double sn = (tau >= 0.0 ? rho : -rho) * iw;
+#pragma unroll
+                for (int i = 0; i < MAXR; ++i) {
+                    const int r = gl + i * G;
+                    if (r < rows) {
+                        X[a * rows + r] = c * xa[i] - sn * xb[i];
+                        X[b * rows + r] = sn * xa[i] + c * xb[i];
+                    }
                 }
-                if (gl == 0) *sflag = 1;
+                rotated = 1;
             }
             __syncthreads();
         }
-        const int f = *sflag;
-        __syncthreads();
-        if (!f) return sweep;
+        if (__syncthreads_or(rotated) == 0) return sweep;
     }
     return -1;
+}
+
+__device__ int jacobi_cols(double *X, int rows, int cols, double tol, int max_sweeps, short2 *sched)
+{
+    if (cols < 2) return 1;
+    const int npair = ((cols + 1) & ~1) / 2;
+    if (npair * 16 <= NT) return jacobi_cols_g<16>(X, rows, cols, tol, max_sweeps, sched);
+    return jacobi_cols_g<8>(X, rows, cols, tol, max_sweeps, sched);
 }
 
 // After jacobi_cols: sigma_i = |x_i|, sorted descending (ties by index);
@@ -189,7 +238,7 @@ __device__ __forceinline__ void store_c(void *base, int prec, int64_t idx, doubl
 // R1 = chol(G1) (shifted by s = p u tr(G1) if a pivot breaks down),
 // T1 = P R1^-1 written in the compute type for the tall GEMM Y = X0 T1.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_chol_first(SmallArgs a)
+__global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
 {
     extern __shared__ double lds[];
     __shared__ double sP[64];
@@ -220,7 +269,7 @@ __global__ __launch_bounds__(1024) void k_chol_first(SmallArgs a)
     if (bad) sbad = 1;
     __syncthreads();
     double trace = 0.0;
-    for (int q = 0; q < 16; ++q) trace += sred[q];
+    for (int q = 0; q < NT / 64; ++q) trace += sred[q];
     if (sbad) {
         if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
         for (int idx = threadIdx.x; idx < p * p; idx += NT) S[idx] = (idx % p == idx / p) ? 1.0 : 0.0;
@@ -259,6 +308,7 @@ __global__ __launch_bounds__(1024) void k_chol_first(SmallArgs a)
 hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 {
     const size_t lds = (size_t)(a.pmax * a.pmax + a.pmax) * sizeof(double);
+    ProfScope ps(POD_K_CHOL, st);
     hipLaunchKernelGGL(k_chol_first, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
@@ -276,13 +326,13 @@ hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 // the principal angles are the singular values of U_R(k:p, 0:k); the mode
 // criterion compares R(:, i)/|R(:, i)| with U_R(:, i) one by one.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_svd_merge(SmallArgs a)
+__global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
 {
     extern __shared__ double lds[];
     __shared__ double ssig[64];
     __shared__ double snorm[64];
     __shared__ int sperm[64];
-    __shared__ int sflag;
+    __shared__ short2 ssched[64 * 32];
     __shared__ double sred[16];
     DevState *ds = a.ds;
     if (ds->exhausted) return;
@@ -306,7 +356,7 @@ __global__ __launch_bounds__(1024) void k_svd_merge(SmallArgs a)
     if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = tr;
     __syncthreads();
     double trace = 0.0;
-    for (int q = 0; q < 16; ++q) trace += sred[q];
+    for (int q = 0; q < NT / 64; ++q) trace += sred[q];
     int fail = isfinite(trace) ? chol_upper(S1, p, a.urnd * trace * 1e-3) : 1;
     if (fail) {
         const double shift = (double)p * a.urnd * (isfinite(trace) ? trace : 1.0);
@@ -339,9 +389,9 @@ __global__ __launch_bounds__(1024) void k_svd_merge(SmallArgs a)
     __syncthreads();
     // ---- one-sided Jacobi SVD of R
     const double tol = (double)p * 1.1102230246251565e-16;
-    const int sw = jacobi_cols(S3, p, p, tol, 60, &sflag);
+    const int sw = jacobi_cols(S3, p, p, tol, 60, ssched);
     if (threadIdx.x == 0) {
-        ds->sweeps = sw;
+        ds->sweeps = (sw < 0 || ds->sweeps < 0) ? -1 : (sw > ds->sweeps ? sw : ds->sweeps);
         if (sw < 0) atomicOr(&ds->flags, (int32_t)FLAG_NOCONV);
     }
     jacobi_finish(S3, p, p, ssig, S2, p, snorm, sperm);   // S2 <- U_R (sorted), ssig <- Sigma_R
@@ -394,7 +444,7 @@ __global__ __launch_bounds__(1024) void k_svd_merge(SmallArgs a)
                     S3[idx] = S2[(kk + r) + c * p];
                 }
                 __syncthreads();
-                (void)jacobi_cols(S3, br, kk, tol, 60, &sflag);
+                (void)jacobi_cols(S3, br, kk, tol, 60, ssched);
                 double mx = 0.0;
                 for (int c = threadIdx.x; c < kk; c += NT) {
                     double s = 0.0;
@@ -406,7 +456,7 @@ __global__ __launch_bounds__(1024) void k_svd_merge(SmallArgs a)
                 if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = mx;
                 __syncthreads();
                 double m2 = 0.0;
-                for (int q = 0; q < 16; ++q) m2 = fmax(m2, sred[q]);
+                for (int q = 0; q < NT / 64; ++q) m2 = fmax(m2, sred[q]);
                 sin_max = m2;
                 __syncthreads();
             }
@@ -441,6 +491,7 @@ hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
         if (e != hipSuccess) return e;
         attr = true;
     }
+    ProfScope ps(POD_K_SVD, st);
     hipLaunchKernelGGL(k_svd_merge, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
@@ -451,19 +502,19 @@ hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
 // (G_B = U_B Lambda U_B^T, so the rotated columns converge to U_B Lambda),
 // Sigma_B = sqrt(Lambda); U_B(:, 0:k) is written in the compute type.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_rr_small(RRArgs a)
+__global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
 {
     extern __shared__ double lds[];
     __shared__ double ssig[64];
     __shared__ double snorm[64];
     __shared__ int sperm[64];
-    __shared__ int sflag;
+    __shared__ short2 ssched[64 * 32];
     const int r = a.r;
     double *S = lds;
     double *Uo = lds + r * r;
     // G_B entries, one wave per entry group, lanes along n
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int e = wv; e < r * r; e += 16) {
+    for (int e = wv; e < r * r; e += NT / 64) {
         const int i = e % r, j = e / r;
         if (i > j) continue;
         double s = 0.0;
@@ -478,7 +529,7 @@ __global__ __launch_bounds__(1024) void k_rr_small(RRArgs a)
     __syncthreads();
     for (int idx = threadIdx.x; idx < r * r; idx += NT) a.GB[idx] = S[idx];
     const double tol = (double)r * 1.1102230246251565e-16;
-    const int sw = jacobi_cols(S, r, r, tol, 60, &sflag);
+    const int sw = jacobi_cols(S, r, r, tol, 60, ssched);
     if (threadIdx.x == 0 && sw < 0) atomicOr(&a.ds->flags, (int32_t)FLAG_NOCONV);
     jacobi_finish(S, r, r, ssig, Uo, r, snorm, sperm);
     for (int idx = threadIdx.x; idx < r * r; idx += NT) a.UB[idx] = Uo[idx];
@@ -496,6 +547,7 @@ hipError_t launch_rr_small(const RRArgs &a, hipStream_t st)
         if (e != hipSuccess) return e;
         attr = true;
     }
+    ProfScope ps(POD_K_RR, st);
     hipLaunchKernelGGL(k_rr_small, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
@@ -518,22 +570,28 @@ __global__ __launch_bounds__(256) void k_rr_v(const double *__restrict__ B, int6
 hipError_t launch_rr_v(const double *B, int64_t n, int32_t r, int32_t k, const double *UB, const double *sig,
                        int32_t prec, void *V, hipStream_t st)
 {
+    ProfScope ps(POD_K_RR, st);
     hipLaunchKernelGGL(k_rr_v, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, n, r, k, UB, sig, prec, V);
     return hipGetLastError();
 }
 
 // Sign convention of the outputs: u_i is negated (with v_i) unless its
-// largest-magnitude entry (lowest index on ties) is positive.
+// largest-magnitude entry (lowest index on ties) is positive.  Pass 1: each
+// workgroup (column i, chunk c) finds its chunk's candidate; pass 2: the
+// candidates of a column are combined in chunk order and the column flipped.
+constexpr int SIGN_CHUNKS = 64;
+
 template <typename T>
-__global__ __launch_bounds__(1024) void k_sign_fix(T *U, int64_t m, T *V, int64_t n)
+__global__ __launch_bounds__(256) void k_sign_partial(const T *U, int64_t m, double *cv, int64_t *ci)
 {
-    __shared__ double sv[16];
-    __shared__ int64_t si[16];
-    __shared__ int sflip;
-    T *u = U + (int64_t)blockIdx.x * m;
+    __shared__ double sv[4];
+    __shared__ int64_t si[4];
+    const int col = blockIdx.y, ch = blockIdx.x;
+    const int64_t r0 = (m * ch) / SIGN_CHUNKS, r1 = (m * (ch + 1)) / SIGN_CHUNKS;
+    const T *u = U + (int64_t)col * m;
     double best = -1.0;
-    int64_t bi = 0;
-    for (int64_t i = threadIdx.x; i < m; i += 1024) {
+    int64_t bi = r0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
         const double x = fabs((double)u[i]);
         if (x > best) {
             best = x;
@@ -557,30 +615,56 @@ __global__ __launch_bounds__(1024) void k_sign_fix(T *U, int64_t m, T *V, int64_
     if (threadIdx.x == 0) {
         double b = sv[0];
         int64_t ii = si[0];
-        for (int q = 1; q < 16; ++q)
+        for (int q = 1; q < 4; ++q)
             if (sv[q] > b || (sv[q] == b && si[q] < ii)) {
                 b = sv[q];
                 ii = si[q];
             }
-        sflip = ((double)u[ii] < 0.0);
-    }
-    __syncthreads();
-    if (sflip) {
-        for (int64_t i = threadIdx.x; i < m; i += 1024) u[i] = -u[i];
-        if (V) {
-            T *v = V + (int64_t)blockIdx.x * n;
-            for (int64_t i = threadIdx.x; i < n; i += 1024) v[i] = -v[i];
-        }
+        cv[col * SIGN_CHUNKS + ch] = (b >= 0.0) ? (double)u[ii] : 0.0;   // signed value of the candidate
+        ci[col * SIGN_CHUNKS + ch] = ii;
     }
 }
 
-hipError_t launch_sign_fix(int32_t prec, void *U, int64_t m, int32_t k, void *V, int64_t n, hipStream_t st)
+template <typename T>
+__global__ __launch_bounds__(256) void k_sign_apply(T *U, int64_t m, T *V, int64_t n, const double *cv,
+                                                   const int64_t *ci)
+{
+    const int col = blockIdx.y;
+    double b = -1.0, bs = 0.0;
+    int64_t ii = 0;
+    for (int q = 0; q < SIGN_CHUNKS; ++q) {
+        const double v = cv[col * SIGN_CHUNKS + q];
+        const int64_t i = ci[col * SIGN_CHUNKS + q];
+        if (fabs(v) > b || (fabs(v) == b && i < ii)) {
+            b = fabs(v);
+            bs = v;
+            ii = i;
+        }
+    }
+    if (!(bs < 0.0)) return;
+    const int64_t r0 = (m * blockIdx.x) / gridDim.x, r1 = (m * (blockIdx.x + 1)) / gridDim.x;
+    T *u = U + (int64_t)col * m;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) u[i] = -u[i];
+    if (V) {
+        const int64_t c0 = (n * blockIdx.x) / gridDim.x, c1 = (n * (blockIdx.x + 1)) / gridDim.x;
+        T *v = V + (int64_t)col * n;
+        for (int64_t i = c0 + threadIdx.x; i < c1; i += 256) v[i] = -v[i];
+    }
+}
+
+hipError_t launch_sign_fix(int32_t prec, void *U, int64_t m, int32_t k, void *V, int64_t n, double *cv,
+                           int64_t *ci, hipStream_t st)
 {
     if (k <= 0) return hipSuccess;
-    if (prec == POD_F64)
-        hipLaunchKernelGGL(k_sign_fix<double>, dim3(k), dim3(1024), 0, st, (double *)U, m, (double *)V, n);
-    else
-        hipLaunchKernelGGL(k_sign_fix<float>, dim3(k), dim3(1024), 0, st, (float *)U, m, (float *)V, n);
+    ProfScope ps(POD_K_SIGN, st);
+    dim3 g1(SIGN_CHUNKS, k), g2(64, k);
+    if (prec == POD_F64) {
+        hipLaunchKernelGGL(k_sign_partial<double>, g1, dim3(256), 0, st, (const double *)U, m, cv, ci);
+        hipLaunchKernelGGL(k_sign_apply<double>, g2, dim3(256), 0, st, (double *)U, m, (double *)V, n, cv, ci);
+    } else {
+        hipLaunchKernelGGL(k_sign_partial<float>, g1, dim3(256), 0, st, (const float *)U, m, cv, ci);
+        hipLaunchKernelGGL(k_sign_apply<float>, g2, dim3(256), 0, st, (float *)U, m, (float *)V, n, cv, ci);
+    }
     return hipGetLastError();
 }
 
