@@ -9,7 +9,10 @@ with Rayleigh-Ritz) on the matrix already resident in HBM.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-Prints one JSON line.
+Prints one JSON line.  Besides the timed FP32-merge path it times the plain
+FP64 GPU path, measures the dominant kernel class with HIP events during the
+timed steps (roofline), and times the FP64 CPU oracle on a bounded sample
+(cpu_baseline).
 """
 from __future__ import annotations
 
@@ -25,6 +28,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "time-to-k-modes & HBM GB/s: mixed-prec+adjoint vs plain FP64 at θ_max≤1e-5"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32_mfma": 157.3, "f64_vector": 78.6}
+CLASSES = ["colnorms", "draw", "gram", "gram_reduce", "chol", "tall", "svd", "project", "rr", "sign"]
 
 
 def parse():
@@ -38,7 +44,75 @@ def parse():
     ap.add_argument("--c", type=int, default=40)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-merges", type=int, default=12, help="oracle merges timed for the CPU baseline sample")
     return ap.parse_args()
+
+
+def kernel_work(cls, m, n, k, c, p, iters, sweeps_total, launches, prec_bytes):
+    """Algorithmic work of one launch of a kernel class, averaged over the
+    launches of one step: (bound, amount, unit) with amount in bytes or flops.
+
+    colnorms / project: one pass over A (m n 4 bytes).  gram: symmetric Gram
+    m p (p+1) flops.  tall: 2 m p p flops (Y = X0 T1 with p x p T1, and
+    U = Y Z2 with p x k Z2 averaged).  svd: FP64 flops of the p x p stage --
+    two triangular products (2 p^3 / 3 each), and per Jacobi sweep (p-1)
+    steps x p/2 pairs x p rows x 10 flops (3 dot-product FMAs, 2 rotation
+    updates) -- summed over the step's sweeps."""
+    if cls in ("colnorms",):
+        return "hbm", m * n * 4, "B"
+    if cls == "project":
+        return "hbm", m * n * 4 / max(launches, 1), "B"
+    if cls == "gram":
+        return "mfma", m * p * (p + 1), "flop"
+    if cls == "tall":
+        return "mfma", m * p * (p + k), "flop"
+    if cls == "svd":
+        jac = sweeps_total * (p - 1) * (p / 2) * p * 10.0
+        tri = iters * 4.0 * p ** 3 / 3.0
+        return "alu", (jac + tri) / max(launches, 1), "flop"
+    return None, 0, None
+
+
+def cpu_baseline(At, m, n, k, c, iters_gpu, merges):
+    """The FP64 oracle on a bounded sample of the same workload (single
+    thread): the column norms over all of A, `merges` BLOCK MERGEs of the
+    run's first draws, and the final projection on 1/5 of the columns;
+    extrapolated to the whole run (norms + iters x mean merge + 5 x sample
+    projection)."""
+    import numpy as np
+
+    import oracle
+    from oracle.isma import IsmaParams, get_update
+
+    A = np.asfortranarray(At.cpu().numpy().T.astype(np.float64))
+    prm = IsmaParams(k=k, c=c, seed=2002, theta_tol=1e-5)
+    t0 = time.perf_counter()
+    nu = oracle.col_sqnorms(A, 4)
+    wq = oracle.quantize(nu)
+    t_norm = time.perf_counter() - t0
+    inS = np.ones(n, dtype=bool)
+    U = np.zeros((m, 0), order="F")
+    s = np.zeros(0)
+    t0 = time.perf_counter()
+    for it in range(merges):
+        C, _ = get_update(A, prm, it, inS, wq, U)
+        U, s = oracle.merge(U, s, C, k)
+    t_merge = (time.perf_counter() - t0) / merges
+    nsub = max(n // 5, 1)
+    t0 = time.perf_counter()
+    oracle.project(A[:, :nsub], U, want_v=False)
+    t_proj = (time.perf_counter() - t0) * (n / nsub)
+    est = t_norm + iters_gpu * t_merge + t_proj
+    sample_s = t_norm + merges * t_merge + t_proj * nsub / n
+    return {
+        "value": round(est * 1e3, 1),
+        "unit": "ms per time-to-k-modes (extrapolated)",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"full column-norm pass ({t_norm:.2f} s), {merges} merges of the run's first draws "
+                   f"({t_merge:.2f} s each), final projection on {nsub}/{n} columns; extrapolated to "
+                   f"{iters_gpu} merges and all columns; {sample_s:.1f} s of CPU work, single thread"),
+    }
 
 
 def main():
@@ -56,38 +130,83 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     m, n, k, c = args.m, args.n, args.k, args.c
+    p = k + c
     t_gen = time.perf_counter()
     At = snapgen.travelling_waves(m, n, 60, 1.5, 1e-3, seed=1002, device="cuda")
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     A = At.T
     kw = dict(k=k, c=c, seed=2002, theta_tol=1e-5)
+    info = {}
 
     def step(precision):
-        return pod.isma(A, want_v=False, precision=precision, **kw)
+        with pod.PodContext(A, precision=precision, **kw) as ctx:
+            ctx.run()
+            inf = ctx.info()
+            ctx.project(want_v=False)
+        info["iters"], info["sweeps"] = inf.iter, inf.total_sweeps
+        return inf
 
-    def timed(precision, steps, warmup):
-        res = None
-        for _ in range(warmup):
-            res = step(precision)
+    # warm-up, then one step per kernel class with that class timed by HIP events
+    for _ in range(max(args.warmup, 1)):
+        step(pod.POD_F32)
+    torch.cuda.synchronize()
+    per_class = {}
+    for cls in CLASSES:
+        pod.profile_enable(cls)
+        step(pod.POD_F32)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            res = step(precision)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps, res
+        launches, ms = pod.profile_read()
+        per_class[cls] = (launches, ms)
+    pod.profile_enable(None)
+    dominant = max(per_class, key=lambda x: per_class[x][1])
 
-    sec32, res32 = timed(pod.POD_F32, args.steps, args.warmup)
-    sec64, res64 = timed(pod.POD_F64, args.fp64_steps, 1)
-    iters = res32.iters
-    # algorithmic HBM bytes of one step (FP32 path): column norms and the
-    # projection read A once each; every merge reads the gathered block
-    # X0 = [U | A(:, I_c)] (m x p) twice (Gram pass 1 and Q1 = X0 T1), writes
-    # and reads Q1 twice (Gram pass 2 and U_new = Q1 Z2) and writes U_new.
-    b = 4
-    p = k + c
-    per_merge = m * p * b * 2 + m * p * b * 3 + m * k * b
-    step_bytes = 2 * m * n * b + iters * per_merge
+    # timed region (FP32 merge path), dominant class timed live
+    pod.profile_enable(dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(pod.POD_F32)
+    torch.cuda.synchronize()
+    sec32 = (time.perf_counter() - t0) / args.steps
+    launches, dom_ms = pod.profile_read()
+    pod.profile_enable(None)
+    iters, sweeps = info["iters"], info["sweeps"]
+
+    # plain FP64 GPU path
+    step(pod.POD_F64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.fp64_steps):
+        step(pod.POD_F64)
+    torch.cuda.synchronize()
+    sec64 = (time.perf_counter() - t0) / args.fp64_steps
+    iters64 = info["iters"]
+
+    # roofline of the dominant kernel class
+    per_step_launches = launches / args.steps
+    avg_s = dom_ms / 1e3 / max(launches, 1)
+    bound, amount, unit = kernel_work(dominant, m, n, k, c, p, iters, sweeps, per_step_launches, 4)
+    if bound == "hbm":
+        achieved = amount / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    elif bound == "mfma":
+        achieved = amount / avg_s / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f32_mfma"],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f32_mfma"], 5), "traffic": None}
+    else:
+        achieved = amount / avg_s / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 5), "peak": PEAK_TFLOPS["f64_vector"],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64_vector"], 6), "traffic": None}
+    roof.update({"kernel_class": dominant, "avg_launch_us": round(avg_s * 1e6, 2),
+                 "launches_per_step": round(per_step_launches, 1)})
+
+    # algorithmic HBM bytes of one FP32 step: column norms and projection read
+    # A once each; every merge reads X0 = [U | A(:, I_c)] (m x p) twice,
+    # writes and reads Q1 twice, and writes U_new.
+    per_merge = m * p * 4 * 2 + m * p * 4 * 3 + m * k * 4
+    step_bytes = 2 * m * n * 4 + iters * per_merge
     out = {
         "metric": METRIC,
         "value": round(sec32 * 1e3, 4),
@@ -104,14 +223,19 @@ def main():
         "config": {"workload": f"travelling waves {m}x{n} FP32, 60 modes a_j=j^-1.5, noise var 1e-3, "
                                f"rows centred; k={k}, c={c}, theta_tol=1e-5",
                    "m": m, "n": n, "k": k, "c": c},
+        "roofline": roof,
         "iters": iters,
+        "jacobi_sweeps_per_merge": round(sweeps / max(iters, 1), 2),
         "fp64_path_ms": round(sec64 * 1e3, 4),
-        "fp64_iters": res64.iters,
+        "fp64_iters": iters64,
         "speedup_vs_fp64_path": round(sec64 / sec32, 3),
         "step_hbm_gbs": round(step_bytes / sec32 / 1e9, 1),
+        "kernel_ms_per_step": {kc: round(v[1], 3) for kc, v in per_class.items()},
         "adjoint_included": False,
         "gen_s": round(t_gen, 2),
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(At, m, n, k, c, iters, args.cpu_merges)
     print(json.dumps(out), flush=True)
 
 

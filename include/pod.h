@@ -88,7 +88,7 @@ typedef struct {
     int32_t flags;         /* bit 0: shifted Cholesky used; bit 1: non-finite;  */
                            /* bit 2: Jacobi sweep limit hit                     */
     int32_t max_sweeps;    /* most Jacobi sweeps of any merge so far            */
-    int32_t reserved;
+    int32_t total_sweeps;  /* Jacobi sweeps summed over the merges              */
     double sin_theta;      /* sine of the last convergence angle (NaN first)    */
 } pod_info;
 

@@ -49,7 +49,7 @@ class pod_info(ctypes.Structure):
     _fields_ = [
         ("iter", ctypes.c_int32), ("rank", ctypes.c_int32), ("g", ctypes.c_int32), ("h", ctypes.c_int32),
         ("exhausted", ctypes.c_int32), ("flags", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("sin_theta", ctypes.c_double),
+        ("total_sweeps", ctypes.c_int32), ("sin_theta", ctypes.c_double),
     ]
 
 

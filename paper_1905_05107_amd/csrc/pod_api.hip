@@ -430,7 +430,7 @@ pod_status pod_get_info(pod_ctx *ctx, pod_info *info)
     info->exhausted = ctx->hs.exhausted || ctx->hs.s_empty;
     info->flags = ctx->hs.flags;
     info->max_sweeps = ctx->hs.sweeps;
-    info->reserved = 0;
+    info->total_sweeps = ctx->hs.sweeps_total;
     info->sin_theta = ctx->hs.sin_theta;
     return POD_OK;
 }

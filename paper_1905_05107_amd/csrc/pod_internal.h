@@ -24,7 +24,7 @@ struct DevState {
     int32_t sweeps;     // Jacobi sweeps of the last merge
     int32_t col_log_len;// entries used in the column log
     int32_t s_empty;    // no drawable column left after the last draw
-    int32_t pad0;
+    int32_t sweeps_total; // Jacobi sweeps summed over merges
     double sin_theta;   // last convergence sine (NaN until the second merge)
     uint64_t wtot;      // total column weight of the last draw
 };

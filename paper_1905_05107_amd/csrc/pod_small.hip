@@ -392,6 +392,7 @@ __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
     const int sw = jacobi_cols(S3, p, p, tol, 60, ssched);
     if (threadIdx.x == 0) {
         ds->sweeps = (sw < 0 || ds->sweeps < 0) ? -1 : (sw > ds->sweeps ? sw : ds->sweeps);
+        ds->sweeps_total += (sw > 0) ? sw : 0;
         if (sw < 0) atomicOr(&ds->flags, (int32_t)FLAG_NOCONV);
     }
     jacobi_finish(S3, p, p, ssig, S2, p, snorm, sperm);   // S2 <- U_R (sorted), ssig <- Sigma_R
