@@ -1,16 +1,17 @@
 // pod_small.hip -- FP64 small-matrix algebra of the merge (Alg. 2) on gfx950.
 //
-// One workgroup of 1024 threads works on p x p matrices (p <= 64) held in LDS:
-// Cholesky factors of the CholeskyQR2 Grams, triangular inverses, the
-// one-sided Jacobi SVD of the merge factor R (the paper's E), the rank guard,
-// the convergence angles of Alg. 1 and the Rayleigh-Ritz step of the final
-// projection.  These kernels are latency bound; they keep everything in LDS
-// and use all 16 waves for every step.
+// One workgroup of 512 threads works on p x p matrices (p <= 64) held in LDS:
+// the Cholesky factors of the CholeskyQR2 Grams and their inverses, the SVD of
+// the merge factor R (the paper's E up to an orthogonal factor) through the
+// symmetric eigen-decomposition of R R^T (pod_symeig.h), the rank guard, the
+// convergence angles of Alg. 1 and the Rayleigh-Ritz step of the final
+// projection.  These kernels are latency bound; everything stays in LDS.
 #include "pod_internal.h"
+#include "pod_symeig.h"
 
 namespace pod {
 
-constexpr int NT = 512;
+constexpr int NT = EIG_NT;
 
 // ---------------------------------------------------------------------------
 // In-place Cholesky S = R^T R of the symmetric p x p matrix S (LDS,
@@ -20,22 +21,33 @@ constexpr int NT = 512;
 // ---------------------------------------------------------------------------
 __device__ int chol_upper(double *S, int p, double thr)
 {
+    // Step j updates the trailing block with the unscaled row j and 1/d_j,
+    // and scales row j-1 (which step j no longer reads): one barrier per step.
     for (int j = 0; j < p; ++j) {
         const double d = S[j + j * p];
         if (!(d > thr)) return 1;
-        const double rjj = sqrt(d);
-        __syncthreads();
-        for (int k = j + (int)threadIdx.x; k < p; k += NT) S[j + k * p] = (k == j) ? rjj : S[j + k * p] / rjj;
-        __syncthreads();
+        const double inv_d = 1.0 / d;
+        if (j > 0) {
+            const double rp = sqrt(S[(j - 1) + (j - 1) * p]);
+            const double irp = 1.0 / rp;
+            for (int k = j - 1 + (int)threadIdx.x; k < p; k += NT)
+                S[(j - 1) + k * p] = (k == j - 1) ? rp : S[(j - 1) + k * p] * irp;
+        }
         const int q = p - j - 1;
-        for (int idx = threadIdx.x; idx < q * q; idx += NT) {
-            const int ii = idx % q, kk = idx / q;
-            if (ii <= kk) {
-                const int i = j + 1 + ii, k = j + 1 + kk;
-                S[i + k * p] -= S[j + i * p] * S[j + k * p];
+        const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+        for (int kk = ty; kk < q; kk += NT / 32) {
+            const int k = j + 1 + kk;
+            const double sjk = S[j + k * p] * inv_d;
+            for (int ii = tx; ii <= kk; ii += 32) {
+                const int i = j + 1 + ii;
+                S[i + k * p] -= S[j + i * p] * sjk;
             }
         }
         __syncthreads();
+    }
+    {
+        const double rp = sqrt(S[(p - 1) + (p - 1) * p]);
+        if (threadIdx.x == 0) S[(p - 1) + (p - 1) * p] = rp;
     }
     for (int idx = threadIdx.x; idx < p * p; idx += NT) {
         const int i = idx % p, k = idx / p;
@@ -71,155 +83,6 @@ __device__ void trinv_upper(double *R, int p, double *tmp)
         if (threadIdx.x == 0) R[j + j * p] = inv;
         __syncthreads();
     }
-}
-
-// ---------------------------------------------------------------------------
-// Wave-local helpers: sums over aligned groups of G lanes by DPP moves
-// (mirror / half-mirror / quad permutations: no LDS traffic), and an FP64
-// reciprocal square root from the FP32 estimate refined by two Newton steps
-// (relative error below 1e-15).
-// ---------------------------------------------------------------------------
-template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-template <int G> __device__ __forceinline__ double group_sum(double v)
-{
-    if (G >= 16) v += dpp_f64<0x140>(v);   // row_mirror
-    if (G >= 8) v += dpp_f64<0x141>(v);    // row_half_mirror
-    if (G >= 4) v += dpp_f64<0x4E>(v);     // quad_perm [2,3,0,1]
-    if (G >= 2) v += dpp_f64<0xB1>(v);     // quad_perm [1,0,3,2]
-    return v;
-}
-__device__ __forceinline__ double rsqrt_f64(double x)
-{
-    // x = f 2^e with f in [0.5, 2) and e even keeps the FP32 estimate in range
-    int e;
-    double f = frexp(x, &e);
-    if (e & 1) {
-        f *= 2.0;
-        e -= 1;
-    }
-    double y = (double)__frsqrt_rn((float)f);
-    y = y * fma(-0.5 * f * y, y, 1.5);
-    y = y * fma(-0.5 * f * y, y, 1.5);
-    return ldexp(y, -e / 2);
-}
-
-// ---------------------------------------------------------------------------
-// One-sided (Hestenes) Jacobi on the columns of X (rows x cols, column-major,
-// ld = rows, LDS, rows <= 64), parallel round-robin ordering: each step
-// rotates cols/2 disjoint pairs, G threads per pair (a pair's two columns
-// are held in registers for the step).  A pair is rotated when
-// (x_a^T x_b)^2 > tol^2 |x_a|^2 |x_b|^2, with
-//   tau = |x_b|^2 - |x_a|^2, rho = 2 x_a^T x_b, h = sqrt(tau^2 + rho^2),
-//   d = |tau| + h, c = d / sqrt(d^2 + rho^2), s = sign(tau) rho / sqrt(d^2 + rho^2),
-// the closed form of the classical angle t = sign(zeta)/(|zeta| + sqrt(1+zeta^2)),
-// zeta = tau/rho, written without divisions by rho.  The sweep loop stops
-// after a sweep without rotation.  `sched` holds (cols|1)*(cols+1)/2 short2.
-// Returns the number of sweeps or -1.
-// ---------------------------------------------------------------------------
-template <int G>
-__device__ int jacobi_cols_g(double *X, int rows, int cols, double tol, int max_sweeps, short2 *sched)
-{
-    constexpr int MAXR = 64 / G;
-    const int np = (cols + 1) & ~1;
-    const int npair = np / 2;
-    for (int i = threadIdx.x; i < (np - 1) * npair; i += NT) {
-        const int s = i / npair, q = i % npair;
-        const int a = (q == 0) ? 0 : ((q - 1 + s) % (np - 1)) + 1;
-        const int b = ((np - 2 - q + s) % (np - 1)) + 1;
-        sched[i] = make_short2((short)a, (short)b);
-    }
-    __syncthreads();
-    const int q = threadIdx.x / G, gl = threadIdx.x % G;
-    const bool active = q < npair;
-    const double tol2 = tol * tol;
-    for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
-        int rotated = 0;
-        for (int s = 0; s < np - 1; ++s) {
-            const short2 ab = active ? sched[s * npair + q] : make_short2(0, 0);
-            const int a = ab.x, b = ab.y;
-            const bool real = active && a < cols && b < cols;
-            double xa[MAXR], xb[MAXR];
-            double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-            for (int i = 0; i < MAXR; ++i) {
-                const int r = gl + i * G;
-                const bool ok = real && r < rows;
-                xa[i] = ok ? X[a * rows + r] : 0.0;
-                xb[i] = ok ? X[b * rows + r] : 0.0;
-                al = fma(xa[i], xa[i], al);
-                be = fma(xb[i], xb[i], be);
-                ga = fma(xa[i], xb[i], ga);
-            }
-            al = group_sum<G>(al);
-            be = group_sum<G>(be);
-            ga = group_sum<G>(ga);
-            if (real && ga * ga > tol2 * al * be) {
-                const double tau = be - al, rho = 2.0 * ga;
-                const double x1 = fma(tau, tau, rho * rho);
-                const double h = x1 * rsqrt_f64(x1);
-                const double d = fabs(tau) + h;
-                const double iw = rsqrt_f64(fma(d, d, rho * rho));
-                const double c = d * iw;
-                const double sn = (tau >= 0.0 ? rho : -rho) * iw;
-#pragma unroll
-                for (int i = 0; i < MAXR; ++i) {
-                    const int r = gl + i * G;
-                    if (r < rows) {
-                        X[a * rows + r] = c * xa[i] - sn * xb[i];
-                        X[b * rows + r] = sn * xa[i] + c * xb[i];
-                    }
-                }
-                rotated = 1;
-            }
-            __syncthreads();
-        }
-        if (__syncthreads_or(rotated) == 0) return sweep;
-    }
-    return -1;
-}
-
-__device__ int jacobi_cols(double *X, int rows, int cols, double tol, int max_sweeps, short2 *sched)
-{
-    if (cols < 2) return 1;
-    const int npair = ((cols + 1) & ~1) / 2;
-    if (npair * 16 <= NT) return jacobi_cols_g<16>(X, rows, cols, tol, max_sweeps, sched);
-    return jacobi_cols_g<8>(X, rows, cols, tol, max_sweeps, sched);
-}
-
-// After jacobi_cols: sigma_i = |x_i|, sorted descending (ties by index);
-// out (rows x cols, ld ldo) = x_i / sigma_i in sorted order (0 if sigma = 0).
-__device__ void jacobi_finish(const double *X, int rows, int cols, double *sig_sorted, double *out, int ldo,
-                              double *snorm, int *sperm)
-{
-    for (int i = threadIdx.x; i < cols; i += NT) {
-        double s = 0.0;
-        for (int r = 0; r < rows; ++r) s += X[r + (int64_t)i * rows] * X[r + (int64_t)i * rows];
-        snorm[i] = sqrt(s);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < cols; i += NT) {
-        const double si = snorm[i];
-        int rk = 0;
-        for (int j = 0; j < cols; ++j) {
-            const double sj = snorm[j];
-            rk += (sj > si) || (sj == si && j < i);
-        }
-        sperm[rk] = i;
-        sig_sorted[rk] = si;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < rows * cols; idx += NT) {
-        const int r = idx % rows, o = idx / rows;
-        const int i = sperm[o];
-        const double s = sig_sorted[o];
-        out[r + (int64_t)o * ldo] = (s > 0.0) ? X[r + (int64_t)i * rows] / s : 0.0;
-    }
-    __syncthreads();
 }
 
 template <typename T> __device__ __forceinline__ void store_t(void *base, int64_t idx, double v)
@@ -315,33 +178,34 @@ hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 
 // ---------------------------------------------------------------------------
 // CholeskyQR pass 2 and the small SVD of the merge:
-//   R2 = chol(G2) (G2 = Y^T Y), R = R2 R1 (upper triangular, the paper's E up
-//   to an orthogonal left factor), R = U_R Sigma_R V_R^T by one-sided Jacobi
-//   on the columns of R, rank guard r' = min(r, #{sigma_i > p u sigma_1}),
-//   Z2 = R2^-1 U_R(:, 0:r') in the compute type for U_new = Y Z2,
-//   Sigma_new = Sigma_R(0:r').
+//   R2 = chol(G2) (G2 = Y^T Y), R = R2 R1 (upper triangular: the paper's E up
+//   to an orthogonal left factor), R R^T = U_R Lambda U_R^T by the symmetric
+//   eigensolver, Sigma_R = sqrt(Lambda), rank guard
+//   r' = min(r, #{lambda_i > max((p u)^2, p u_64) lambda_1}) (the sigma-domain
+//   guard sigma_i > p u sigma_1, floored at the resolution of the FP64
+//   eigenvalues), Z2 = R2^-1 U_R(:, 0:r') in the compute type for
+//   U_new = Y Z2, Sigma_new = Sigma_R(0:r').
 // Convergence (Alg. 1): the first k columns of M = [U Sigma | C] span the old
 // modes, and M = Q R with R upper triangular, so in the basis Q the old
 // subspace is span(e_1..e_k) and the new one span(U_R(:, 0:k)).  The sines of
-// the principal angles are the singular values of U_R(k:p, 0:k); the mode
+// the principal angles are the singular values of B = U_R(k:p, 0:k); the
+// largest is the square root of the largest eigenvalue of B^T B.  The mode
 // criterion compares R(:, i)/|R(:, i)| with U_R(:, i) one by one.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
 {
     extern __shared__ double lds[];
-    __shared__ double ssig[64];
-    __shared__ double snorm[64];
-    __shared__ int sperm[64];
-    __shared__ short2 ssched[64 * 32];
-    __shared__ double sred[16];
+    __shared__ double sd[64], se[64], stau[64], se2[64], spv[64], sev[64], sdots[64], ssc[8], ssin[2];
+    __shared__ __align__(8) int scl[EIG_NMAX + 8];
+    __shared__ double sred[NT / 64];
     DevState *ds = a.ds;
     if (ds->exhausted) return;
     const int p = ds->p, rs = ds->rs;
     const int pm = a.pmax;
     double *S1 = lds;              // G2 -> R2 -> R2^-1
-    double *S2 = lds + p * p;      // R1 -> U_R
-    double *S3 = lds + 2 * p * p;  // R -> scratch
-    double *tmp = lds + 3 * p * p; // p
+    double *S2 = lds + p * p;      // R1 -> H = R R^T -> reflectors -> B^T B
+    double *S3 = lds + 2 * p * p;  // R -> eigenvectors Y (p x r')
+    double *lu = lds + 3 * p * p;  // EIG_LU_THREADS x 4 p
     // ---- pass-2 Cholesky
     double tr = 0.0;
     for (int idx = threadIdx.x; idx < p * p; idx += NT) {
@@ -351,8 +215,7 @@ __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
         S2[idx] = a.R1[i + j * pm];
         if (i == j) tr += v;
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) tr += __shfl_xor(tr, o, 64);
+    tr = wave_sum(tr);
     if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = tr;
     __syncthreads();
     double trace = 0.0;
@@ -383,30 +246,34 @@ __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
     }
     __syncthreads();
     const int kk0 = (a.k < rs) ? a.k : rs;
-    if (a.criterion == POD_CRIT_MODE && kk0 > 0) {
+    if (a.criterion == POD_CRIT_MODE && kk0 > 0)
         for (int idx = threadIdx.x; idx < p * kk0; idx += NT) a.work[idx] = S3[idx];
+    // ---- H = R R^T
+    for (int idx = threadIdx.x; idx < p * p; idx += NT) {
+        const int i = idx % p, j = idx / p;
+        const int l0 = (i > j) ? i : j;
+        double s = 0.0;
+        for (int l = l0; l < p; ++l) s += S3[i + l * p] * S3[j + l * p];
+        S2[idx] = s;
     }
     __syncthreads();
-    // ---- one-sided Jacobi SVD of R
-    const double tol = (double)p * 1.1102230246251565e-16;
-    const int sw = jacobi_cols(S3, p, p, tol, 60, ssched);
-    if (threadIdx.x == 0) {
-        ds->sweeps = (sw < 0 || ds->sweeps < 0) ? -1 : (sw > ds->sweeps ? sw : ds->sweeps);
-        ds->sweeps_total += (sw > 0) ? sw : 0;
-        if (sw < 0) atomicOr(&ds->flags, (int32_t)FLAG_NOCONV);
-    }
-    jacobi_finish(S3, p, p, ssig, S2, p, snorm, sperm);   // S2 <- U_R (sorted), ssig <- Sigma_R
-    // ---- rank guard
-    int nz = 0;
-    const double thr = (double)p * a.urnd * ssig[0];
-    for (int i = 0; i < p; ++i) nz += (ssig[i] > thr);
-    const int rnew = (a.r < nz) ? a.r : nz;
+    // ---- eigen-decomposition of H
+    tridiag(S2, p, sd, se, stau, spv, ssc);
+    const int nv = (a.r < p) ? a.r : p;
+    bisect_top(sd, se, p, nv, sev, se2, ssc);
+    const double u64 = 1.1102230246251565e-16;
+    const double g1 = (double)p * a.urnd;
+    const double thr = fmax(g1 * g1, (double)p * u64) * fmax(sev[0], 0.0);
+    int nz = count_above(sd, se2, p, thr, ssc[2], scl);
+    const int rnew = (sev[0] > 0.0) ? ((nv < nz) ? nv : nz) : 0;
+    tri_invit(sd, se, p, sev, rnew, S3, lu, scl);
+    tridiag_backtransform(S2, stau, p, S3, rnew, sdots);
+    // S3 now holds U_R(:, 0:rnew) (p x rnew, ld p)
     // ---- convergence angle
     const int kk = (kk0 < rnew) ? kk0 : rnew;
     double sin_max = __builtin_nan("");
     if (kk > 0) {
         if (a.criterion == POD_CRIT_MODE) {
-            // per mode: sin of the angle between R(:,i)/|R(:,i)| and U_R(:,i)
             double mx = 0.0;
             if (threadIdx.x < 64) {
                 for (int i = 0; i < kk; ++i) {
@@ -414,65 +281,53 @@ __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
                     for (int r = threadIdx.x; r < p; r += 64) {
                         const double x = a.work[r + i * p];
                         nr += x * x;
-                        dt += x * S2[r + i * p];
+                        dt += x * S3[r + i * p];
                     }
-#pragma unroll
-                    for (int o = 32; o >= 1; o >>= 1) {
-                        nr += __shfl_xor(nr, o, 64);
-                        dt += __shfl_xor(dt, o, 64);
-                    }
+                    nr = wave_sum(nr);
+                    dt = wave_sum(dt);
                     const double inv = 1.0 / sqrt(nr);
                     double res = 0.0;
                     for (int r = threadIdx.x; r < p; r += 64) {
-                        const double d = S2[r + i * p] - a.work[r + i * p] * inv * (dt * inv);
+                        const double d = S3[r + i * p] - a.work[r + i * p] * inv * (dt * inv);
                         res += d * d;
                     }
-#pragma unroll
-                    for (int o = 32; o >= 1; o >>= 1) res += __shfl_xor(res, o, 64);
+                    res = wave_sum(res);
                     mx = fmax(mx, sqrt(res));
                 }
             }
             if (threadIdx.x == 0) sred[0] = mx;
             __syncthreads();
             sin_max = sred[0];
+            __syncthreads();
         } else {
             const int br = p - kk;
             if (br <= 0) {
                 sin_max = 0.0;
             } else {
-                for (int idx = threadIdx.x; idx < br * kk; idx += NT) {
-                    const int r = idx % br, c = idx / br;
-                    S3[idx] = S2[(kk + r) + c * p];
-                }
-                __syncthreads();
-                (void)jacobi_cols(S3, br, kk, tol, 60, ssched);
-                double mx = 0.0;
-                for (int c = threadIdx.x; c < kk; c += NT) {
+                // F = B^T B, B = U_R(kk:p, 0:kk)
+                for (int idx = threadIdx.x; idx < kk * kk; idx += NT) {
+                    const int i = idx % kk, j = idx / kk;
                     double s = 0.0;
-                    for (int r = 0; r < br; ++r) s += S3[r + c * br] * S3[r + c * br];
-                    mx = fmax(mx, sqrt(s));
+                    for (int r = kk; r < p; ++r) s += S3[r + i * p] * S3[r + j * p];
+                    S2[i + j * kk] = s;
                 }
-#pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-                if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = mx;
                 __syncthreads();
-                double m2 = 0.0;
-                for (int q = 0; q < NT / 64; ++q) m2 = fmax(m2, sred[q]);
-                sin_max = m2;
-                __syncthreads();
+                tridiag(S2, kk, sd, se, stau, spv, ssc);
+                bisect_top(sd, se, kk, 1, ssin, se2, ssc);
+                sin_max = sqrt(fmax(ssin[0], 0.0));
             }
         }
     }
     // ---- Z2 = R2^-1 U_R(:, 0:rnew)
-    trinv_upper(S1, p, tmp);
+    trinv_upper(S1, p, spv);
     for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
         const int i = idx % pm, j = idx / pm;
         double s = 0.0;
         if (i < p && j < rnew)
-            for (int l = i; l < p; ++l) s += S1[i + l * p] * S2[l + j * p];
+            for (int l = i; l < p; ++l) s += S1[i + l * p] * S3[l + j * p];
         store_c(a.Tc, a.prec, idx, s);
     }
-    for (int i = threadIdx.x; i < a.r; i += NT) a.sigma_new[i] = (i < rnew) ? ssig[i] : 0.0;
+    for (int i = threadIdx.x; i < a.r; i += NT) a.sigma_new[i] = (i < rnew) ? sqrt(fmax(sev[i], 0.0)) : 0.0;
     if (threadIdx.x == 0) {
         ds->rnew = rnew;
         ds->sin_theta = sin_max;
@@ -484,11 +339,11 @@ __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
 
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
 {
-    const size_t lds = (size_t)(3 * a.pmax * a.pmax + a.pmax) * sizeof(double);
+    const size_t lds = (size_t)(3 * a.pmax * a.pmax + EIG_LU_THREADS * (4 * a.pmax + 1)) * sizeof(double);
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)k_svd_merge, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(3 * 64 * 64 + 64) * (int)sizeof(double));
+                                           (int)(3 * 64 * 64 + EIG_LU_THREADS * (4 * 64 + 1)) * (int)sizeof(double));
         if (e != hipSuccess) return e;
         attr = true;
     }
@@ -506,13 +361,12 @@ hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
 __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
 {
     extern __shared__ double lds[];
-    __shared__ double ssig[64];
-    __shared__ double snorm[64];
-    __shared__ int sperm[64];
-    __shared__ short2 ssched[64 * 32];
-    const int r = a.r;
-    double *S = lds;
-    double *Uo = lds + r * r;
+    __shared__ double sd[64], se[64], stau[64], se2[64], spv[64], sev[64], sdots[64], ssc[8];
+    __shared__ __align__(8) int scl[EIG_NMAX + 8];
+    const int r = a.r, k = a.k;
+    double *S = lds;             // G_B -> reflectors
+    double *Y = lds + r * r;     // eigenvectors (r x k)
+    double *lu = Y + r * r;      // EIG_LU_THREADS x 4 r
     // G_B entries, one wave per entry group, lanes along n
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int e = wv; e < r * r; e += NT / 64) {
@@ -520,8 +374,7 @@ __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
         if (i > j) continue;
         double s = 0.0;
         for (int64_t c = lane; c < a.n; c += 64) s += a.B[i + c * r] * a.B[j + c * r];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+        s = wave_sum(s);
         if (lane == 0) {
             S[i + j * r] = s;
             S[j + i * r] = s;
@@ -529,22 +382,22 @@ __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < r * r; idx += NT) a.GB[idx] = S[idx];
-    const double tol = (double)r * 1.1102230246251565e-16;
-    const int sw = jacobi_cols(S, r, r, tol, 60, ssched);
-    if (threadIdx.x == 0 && sw < 0) atomicOr(&a.ds->flags, (int32_t)FLAG_NOCONV);
-    jacobi_finish(S, r, r, ssig, Uo, r, snorm, sperm);
-    for (int idx = threadIdx.x; idx < r * r; idx += NT) a.UB[idx] = Uo[idx];
-    for (int i = threadIdx.x; i < r; i += NT) a.sig[i] = sqrt(ssig[i]);
-    for (int idx = threadIdx.x; idx < r * a.k; idx += NT) store_c(a.Zc, a.prec, idx, Uo[idx]);
+    tridiag(S, r, sd, se, stau, spv, ssc);
+    bisect_top(sd, se, r, k, sev, se2, ssc);
+    tri_invit(sd, se, r, sev, k, Y, lu, scl);
+    tridiag_backtransform(S, stau, r, Y, k, sdots);
+    for (int idx = threadIdx.x; idx < r * k; idx += NT) a.UB[idx] = Y[idx];
+    for (int i = threadIdx.x; i < k; i += NT) a.sig[i] = sqrt(fmax(sev[i], 0.0));
+    for (int idx = threadIdx.x; idx < r * k; idx += NT) store_c(a.Zc, a.prec, idx, Y[idx]);
 }
 
 hipError_t launch_rr_small(const RRArgs &a, hipStream_t st)
 {
-    const size_t lds = (size_t)(2 * a.r * a.r) * sizeof(double);
+    const size_t lds = (size_t)(2 * a.r * a.r + EIG_LU_THREADS * (4 * a.r + 1)) * sizeof(double);
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)k_rr_small, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(2 * 64 * 64) * (int)sizeof(double));
+                                           (int)(2 * 64 * 64 + EIG_LU_THREADS * (4 * 64 + 1)) * (int)sizeof(double));
         if (e != hipSuccess) return e;
         attr = true;
     }
