@@ -65,9 +65,14 @@ typedef struct {
     int32_t k;             /* modes reported                                    */
     int32_t r;             /* rank kept after each merge (0 -> k), r >= k       */
     int32_t c;             /* column draws per iteration (with replacement)     */
-    int32_t w;             /* row draws per iteration; 0 = columns only (ICS)   */
-    int32_t r_update;      /* >0: keep the top r_update right singular          */
-                           /* directions of each new block before the merge     */
+    int32_t w;             /* row draws per iteration, 0..1024; 0 = columns    */
+                           /* only (ICS).  w > 0 (ICRS): the merge takes        */
+                           /* C = D V~(:, 0:r_u), V~ the right singular vectors */
+                           /* of the scaled row sample W, r_u = min(r, g, h,    */
+                           /* rank W)                                           */
+    int32_t r_update;      /* w = 0 only: >0 keeps the top r_update right      */
+                           /* singular directions of each new block D before    */
+                           /* the merge (C = D V(:, 0:r_update)); 0 merges D    */
     int32_t col_strategy;  /* pod_col_strategy                                  */
     int32_t row_strategy;  /* pod_row_strategy                                  */
     int32_t criterion;     /* pod_criterion                                     */

@@ -241,15 +241,22 @@ class PodContext:
                                    ctypes.byref(r)), "pod_get_basis")
         return Ut[:r.value].T, sig[:r.value]
 
-    def indices(self, it: int):
+    def indices(self, it: int, rows: bool = False):
+        """Distinct columns and their multiplicities drawn at merge `it`;
+        with rows=True also the distinct rows and their multiplicities."""
         import numpy as np
-        c = self.params.c
+        c, w = self.params.c, self.params.w
         cols = np.zeros(max(c, 1), dtype=np.int32)
         cnt = np.zeros(max(c, 1), dtype=np.int32)
-        g = ctypes.c_int32()
+        rws = np.zeros(max(w, 1), dtype=np.int32)
+        rcnt = np.zeros(max(w, 1), dtype=np.int32)
+        g, h = ctypes.c_int32(), ctypes.c_int32()
         P = ctypes.POINTER(ctypes.c_int32)
         _check(lib().pod_get_indices(self.h, int(it), cols.ctypes.data_as(P), cnt.ctypes.data_as(P),
-                                     ctypes.byref(g), None, None, None), "pod_get_indices")
+                                     ctypes.byref(g), rws.ctypes.data_as(P), rcnt.ctypes.data_as(P),
+                                     ctypes.byref(h)), "pod_get_indices")
+        if rows:
+            return cols[:g.value].copy(), cnt[:g.value].copy(), rws[:h.value].copy(), rcnt[:h.value].copy()
         return cols[:g.value].copy(), cnt[:g.value].copy()
 
     def col_sqnorms(self):

@@ -26,6 +26,9 @@ struct pod_ctx {
     uint8_t *inS = nullptr;
     int32_t *cols = nullptr, *ccnt = nullptr, *col_log = nullptr, *ccnt_log = nullptr, *col_log_off = nullptr;
     int32_t *forced = nullptr;
+    double *rho = nullptr, *Vt = nullptr;  // row weights (m), right factor of the new block (pmax x pmax)
+    uint64_t *wr = nullptr;
+    int32_t *rows = nullptr, *rcnt = nullptr, *row_log = nullptr, *rcnt_log = nullptr;
     void *U[2] = {nullptr, nullptr};
     double *sig[2] = {nullptr, nullptr};
     int cur = 0;
@@ -80,7 +83,8 @@ void free_all(pod_ctx *ctx)
     void *ptrs[] = {ctx->ds,   ctx->nu,   ctx->wq,    ctx->inS,  ctx->cols, ctx->ccnt, ctx->col_log, ctx->ccnt_log,
                     ctx->col_log_off, ctx->forced, ctx->U[0], ctx->U[1], ctx->sig[0], ctx->sig[1], ctx->part,
                     ctx->G,    ctx->R1,   ctx->R2,    ctx->work, ctx->Tc,   ctx->Y,    ctx->Bpart,
-                    ctx->B,    ctx->GB,   ctx->UB,    ctx->sigB, ctx->Zc, ctx->signv, ctx->signi};
+                    ctx->B,    ctx->GB,   ctx->UB,    ctx->sigB, ctx->Zc, ctx->signv, ctx->signi,
+                    ctx->rho,  ctx->Vt,   ctx->wr,    ctx->rows, ctx->rcnt, ctx->row_log, ctx->rcnt_log};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -99,6 +103,27 @@ GemmDesc gather_desc(pod_ctx *ctx)
     d.gather = 1;
     d.guard = 1;
     return d;
+}
+
+BlockEigArgs block_eig_args(pod_ctx *ctx, int32_t mode)
+{
+    BlockEigArgs b;
+    b.mode = mode;
+    b.a_dtype = ctx->prm.a_dtype;
+    b.A = ctx->A;
+    b.lda = ctx->prm.lda;
+    b.m = ctx->prm.m;
+    b.cols = ctx->cols;
+    b.rows = ctx->rows;
+    b.rcnt = ctx->rcnt;
+    b.w = ctx->prm.w;
+    b.wr = ctx->wr;
+    b.G = ctx->G;
+    b.pmax = ctx->pmax;
+    b.r_lim = (mode == 0) ? ctx->r : ctx->prm.r_update;
+    b.Vt = ctx->Vt;
+    b.ds = ctx->ds;
+    return b;
 }
 
 GemmDesc plain_desc(pod_ctx *ctx, const void *Y)
@@ -168,7 +193,9 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
     if (p.precision == POD_F32 && p.a_dtype == POD_F64) return POD_EINVAL;
     const int32_t r = p.r ? p.r : p.k;
     if (p.k < 1 || r < p.k || p.c < 1 || p.c > 1024 || p.max_iter < 1) return POD_EINVAL;
-    if (p.w != 0 || p.r_update != 0) return POD_EINVAL;
+    if (p.w < 0 || p.w > 1024 || p.r_update < 0) return POD_EINVAL;
+    if (p.w > 0 && p.row_strategy != POD_ROW_L2 && p.row_strategy != POD_ROW_LS) return POD_EINVAL;
+    if (p.w > 0 && p.m > 0x7fffffff) return POD_EINVAL;
     if (p.col_strategy != POD_COL_L2N && p.col_strategy != POD_COL_UNF) return POD_EINVAL;
     if (p.criterion != POD_CRIT_SUBSPACE && p.criterion != POD_CRIT_MODE) return POD_EINVAL;
     if (!(p.theta_tol >= 0.0)) return POD_EINVAL;
@@ -223,6 +250,15 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
     ALLOC(ctx->Zc, unsigned char, (size_t)r * r * ctx->esz);
     ALLOC(ctx->signv, double, (size_t)64 * r);
     ALLOC(ctx->signi, int64_t, (size_t)64 * r);
+    if (p.w > 0 || p.r_update > 0) ALLOC(ctx->Vt, double, (size_t)pmax * pmax);
+    if (p.w > 0) {
+        ALLOC(ctx->rho, double, m);
+        ALLOC(ctx->wr, uint64_t, m);
+        ALLOC(ctx->rows, int32_t, p.w);
+        ALLOC(ctx->rcnt, int32_t, p.w);
+        ALLOC(ctx->row_log, int32_t, (size_t)cap_iter * p.w);
+        ALLOC(ctx->rcnt_log, int32_t, (size_t)cap_iter * p.w);
+    }
 #undef ALLOC
     if (e != hipSuccess) {
         free_all(ctx);
@@ -236,6 +272,7 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
     POD_HIP(hipMemsetAsync(ctx->col_log_off, 0, sizeof(int32_t) * (cap_iter + 1), ctx->st));
     POD_HIP(hipMemsetAsync(ctx->sig[0], 0, sizeof(double) * r, ctx->st));
     POD_HIP(hipMemsetAsync(ctx->sig[1], 0, sizeof(double) * r, ctx->st));
+    if (p.w > 0) POD_HIP(hipMemsetAsync(ctx->rcnt_log, 0, sizeof(int32_t) * (size_t)cap_iter * p.w, ctx->st));
     if (p.center_rows) {
         // row means over 8 column ranges (FP64), then a_ij <- a_ij - mean_i
         const int32_t ns = 8;
@@ -247,7 +284,7 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
         POD_HIP(hipFree(scratch));
     }
     POD_HIP(launch_col_sqnorms(A_dev, p.a_dtype, m, n, p.lda, ctx->nu, ctx->st));
-    POD_HIP(launch_quantize(ctx->nu, n, ctx->wq, ctx->ds, ctx->st));
+    POD_HIP(launch_quantize(ctx->nu, n, ctx->wq, ctx->ds, 0, ctx->st));
     *out = ctx;
     return POD_OK;
 }
@@ -278,6 +315,29 @@ pod_status pod_sample(pod_ctx *ctx, int32_t *g_out, int32_t *h_out)
     a.ds = ctx->ds;
     POD_HIP(launch_draw_cols(a, ctx->st));
     ctx->forced_g = -1;
+    const pod_params &p = ctx->prm;
+    if (p.w > 0) {
+        // SAMPLE AND SCALE UNIQUE ROWS, then the right factor of the new block
+        const void *Uls = (p.row_strategy == POD_ROW_LS) ? ctx->U[ctx->cur] : nullptr;
+        POD_HIP(launch_row_sqnorms(ctx->A, p.a_dtype, p.m, p.lda, ctx->cols, Uls, p.precision, p.k, ctx->ds, ctx->rho,
+                                   ctx->st));
+        POD_HIP(launch_quantize(ctx->rho, p.m, ctx->wr, ctx->ds, 1, ctx->st));
+        RowDrawArgs ra;
+        ra.wr = ctx->wr;
+        ra.m = p.m;
+        ra.w = p.w;
+        ra.seed = p.seed;
+        ra.block = p.block;
+        ra.rows = ctx->rows;
+        ra.rcnt = ctx->rcnt;
+        ra.row_log = ctx->row_log;
+        ra.rcnt_log = ctx->rcnt_log;
+        ra.max_iter = a.max_iter;
+        ra.ds = ctx->ds;
+        POD_HIP(launch_draw_rows(ra, ctx->st));
+        BlockEigArgs ba = block_eig_args(ctx, 0);
+        POD_HIP(launch_block_eig(ba, ctx->st));
+    }
     ctx->pending = 1;
     if (g_out || h_out) {
         pod_status s = sync_state(ctx);
@@ -318,6 +378,13 @@ pod_status pod_merge(pod_ctx *ctx)
     sa.prec = p.precision;
     sa.criterion = p.criterion;
     sa.urnd = unit_roundoff(p.precision);
+    sa.Vt = ctx->Vt;
+    sa.use_vt = (p.w > 0 || p.r_update > 0);
+    if (p.w == 0 && p.r_update > 0) {
+        // the new block truncated to its leading r_update directions
+        BlockEigArgs ba = block_eig_args(ctx, 1);
+        POD_HIP(launch_block_eig(ba, ctx->st));
+    }
     POD_HIP(launch_chol_first(sa, ctx->st));
     // Q1 = X0 T1 (T1 = P R1^-1)
     POD_HIP(launch_gemm_tall(gd, ctx->ds, -1, -2, pm, pm, ctx->Tc, pm, ctx->Y, ctx->st));
@@ -453,9 +520,25 @@ pod_status pod_get_indices(pod_ctx *ctx, int32_t iter, int32_t *cols, int32_t *c
         POD_HIP(hipMemcpy(cols, ctx->col_log + off[0], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
     if (col_counts && cnt > 0)
         POD_HIP(hipMemcpy(col_counts, ctx->ccnt_log + off[0], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
-    (void)rows;
-    (void)row_counts;
-    if (h) *h = 0;
+    int32_t hh = 0;
+    if (ctx->prm.w > 0) {
+        const int32_t w = ctx->prm.w;
+        int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)w);
+        if (!buf) return POD_ENOMEM;
+        hipError_t e = hipMemcpy(buf, ctx->row_log + (size_t)iter * w, sizeof(int32_t) * w, hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            e = hipMemcpy(buf + w, ctx->rcnt_log + (size_t)iter * w, sizeof(int32_t) * w, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            free(buf);
+            ctx->failed = 1;
+            return POD_EHIP;
+        }
+        while (hh < w && buf[w + hh] > 0) ++hh;
+        if (rows) memcpy(rows, buf, sizeof(int32_t) * hh);
+        if (row_counts) memcpy(row_counts, buf + w, sizeof(int32_t) * hh);
+        free(buf);
+    }
+    if (h) *h = hh;
     return POD_OK;
 }
 

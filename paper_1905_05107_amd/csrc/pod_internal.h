@@ -27,6 +27,7 @@ struct DevState {
     int32_t sweeps_total; // Jacobi sweeps summed over merges
     double sin_theta;   // last convergence sine (NaN until the second merge)
     uint64_t wtot;      // total column weight of the last draw
+    uint64_t wrow_tot;  // total row weight of the last row draw
 };
 
 enum : int32_t { FLAG_SHIFT = 1, FLAG_NONFINITE = 2, FLAG_NOCONV = 4, FLAG_ZERO_ROWS = 8 };
@@ -95,7 +96,7 @@ hipError_t launch_row_means(const void *A, int32_t a_dtype, int64_t m, int64_t n
                             int32_t nsplit, double *mean, hipStream_t st);
 hipError_t launch_center(void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, const double *mean,
                          hipStream_t st);
-hipError_t launch_quantize(const double *v, int64_t len, uint64_t *w, DevState *ds, hipStream_t st);
+hipError_t launch_quantize(const double *v, int64_t len, uint64_t *w, DevState *ds, int32_t guard, hipStream_t st);
 
 struct DrawArgs {
     const uint64_t *wq;   // L2N weights (n)
@@ -115,6 +116,25 @@ struct DrawArgs {
     DevState *ds;
 };
 hipError_t launch_draw_cols(const DrawArgs &a, hipStream_t st);
+
+// Row squared norms of the gathered block D = A(:, cols[0..g)) (rows of D in
+// ascending column order, FP64 fma chain), g read from the device state.
+hipError_t launch_row_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t lda, const int32_t *cols,
+                              const void *U, int32_t u_prec, int32_t k_ls, const DevState *ds, double *rho,
+                              hipStream_t st);
+struct RowDrawArgs {
+    const uint64_t *wr;    // row weights (m)
+    int64_t m;
+    int32_t w;             // draws
+    uint64_t seed, block;
+    int32_t *rows;         // out: distinct rows (w)
+    int32_t *rcnt;         // out: multiplicities (w)
+    int32_t *row_log;      // out: per merge, w entries
+    int32_t *rcnt_log;
+    int32_t max_iter;
+    DevState *ds;
+};
+hipError_t launch_draw_rows(const RowDrawArgs &a, hipStream_t st);
 
 struct GemmDesc {
     int32_t prec;         // POD_F64 or POD_F32 (compute type)
@@ -141,6 +161,8 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
 
 struct SmallArgs {
     DevState *ds;
+    const double *Vt;      // right factor of the new block (g x ru, ld pmax) when use_vt
+    int32_t use_vt;
     const double *sigma;   // current Sigma (rs)
     double *sigma_new;     // Sigma after the merge (r)
     const double *G;       // reduced Gram (pmax x pmax, ld pmax)
@@ -155,6 +177,27 @@ struct SmallArgs {
     double urnd;           // unit roundoff of the merge arithmetic
 };
 hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st);
+
+// Right factor of the new block: the top right singular directions of the
+// scaled row sample W (mode 0, SAMPLE AND SCALE UNIQUE ROWS) or of D itself
+// through the D-block of the pass-1 Gram (mode 1, truncated block update):
+// eigen-decomposition of W^T W (resp. D^T D), Vt = its top ru eigenvectors,
+// ru = min(r_lim, g, h, #{lambda_i > g u lambda_1}); sets ds->ru and ds->p.
+struct BlockEigArgs {
+    int32_t mode;
+    int32_t a_dtype;
+    const void *A;
+    int64_t lda, m;
+    const int32_t *cols, *rows, *rcnt;
+    int32_t w;
+    const uint64_t *wr;
+    const double *G;       // pass-1 Gram (mode 1), pmax x pmax
+    int32_t pmax;
+    int32_t r_lim;
+    double *Vt;            // out, g x ru (ld pmax)
+    DevState *ds;
+};
+hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st);
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st);
 
 struct ProjArgs {

@@ -181,8 +181,9 @@ hipError_t launch_center(void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t
 // and zeroes every weight.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_quantize(const double *__restrict__ v, int64_t len,
-                                                   uint64_t *__restrict__ w, DevState *ds)
+                                                   uint64_t *__restrict__ w, DevState *ds, int32_t guard)
 {
+    if (guard && ds->exhausted) return;
     __shared__ double smax[16];
     __shared__ int sbad[16];
     const int t = threadIdx.x;
@@ -222,10 +223,10 @@ __global__ __launch_bounds__(1024) void k_quantize(const double *__restrict__ v,
     if (t == 0 && anybad && ds) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
 }
 
-hipError_t launch_quantize(const double *v, int64_t len, uint64_t *w, DevState *ds, hipStream_t st)
+hipError_t launch_quantize(const double *v, int64_t len, uint64_t *w, DevState *ds, int32_t guard, hipStream_t st)
 {
     ProfScope ps(POD_K_DRAW, st);
-    hipLaunchKernelGGL(k_quantize, dim3(1), dim3(1024), 0, st, v, len, w, ds);
+    hipLaunchKernelGGL(k_quantize, dim3(1), dim3(1024), 0, st, v, len, w, ds, guard);
     return hipGetLastError();
 }
 
@@ -394,6 +395,174 @@ hipError_t launch_draw_cols(const DrawArgs &a, hipStream_t st)
 {
     ProfScope ps(POD_K_DRAW, st);
     hipLaunchKernelGGL(k_draw_cols, dim3(1), dim3(1024), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// SAMPLE AND SCALE UNIQUE ROWS (Alg. 1), row probabilities.
+//   L2: rho_i = sum over the g distinct columns (ascending) of d_il^2 (the
+//       squared row norms of D, Eq. of the row-norm probabilities);
+//   LS: from the second iteration rho_i = sum_{l < min(k, r)} u_il^2, the
+//       leverage scores of the current basis (Table of sampling strategies).
+// Each sum is an fma chain in FP64 in column order.  Threads run along rows,
+// so each column read is coalesced.
+// ---------------------------------------------------------------------------
+template <typename T, typename TU>
+__global__ __launch_bounds__(256) void k_row_sqnorms(const T *__restrict__ A, int64_t m, int64_t lda,
+                                                     const int32_t *__restrict__ cols, const TU *__restrict__ U,
+                                                     int32_t k_ls, const DevState *ds, double *__restrict__ rho)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m || ds->exhausted) return;
+    double acc = 0.0;
+    if (U && ds->it > 0) {
+        const int kk = (k_ls < ds->rs) ? k_ls : ds->rs;
+        for (int l = 0; l < kk; ++l) {
+            const double x = (double)U[(int64_t)l * m + i];
+            acc = fma(x, x, acc);
+        }
+    } else {
+        const int g = ds->g;
+        for (int l = 0; l < g; ++l) {
+            const double x = (double)A[(int64_t)cols[l] * lda + i];
+            acc = fma(x, x, acc);
+        }
+    }
+    rho[i] = acc;
+}
+
+hipError_t launch_row_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t lda, const int32_t *cols,
+                              const void *U, int32_t u_prec, int32_t k_ls, const DevState *ds, double *rho,
+                              hipStream_t st)
+{
+    ProfScope ps(POD_K_DRAW, st);
+    const unsigned nb = (unsigned)((m + 255) / 256);
+    if (a_dtype == POD_F64)
+        hipLaunchKernelGGL((k_row_sqnorms<double, double>), dim3(nb), dim3(256), 0, st, (const double *)A, m, lda,
+                           cols, (const double *)U, k_ls, ds, rho);
+    else if (u_prec == POD_F64)
+        hipLaunchKernelGGL((k_row_sqnorms<float, double>), dim3(nb), dim3(256), 0, st, (const float *)A, m, lda,
+                           cols, (const double *)U, k_ls, ds, rho);
+    else
+        hipLaunchKernelGGL((k_row_sqnorms<float, float>), dim3(nb), dim3(256), 0, st, (const float *)A, m, lda,
+                           cols, (const float *)U, k_ls, ds, rho);
+    return hipGetLastError();
+}
+
+// Row draw (one workgroup of 1024 threads): w draws with replacement from the
+// integer row weights, Philox key (seed, 1), counter (it, d/4, block, 0),
+// word d mod 4; the same inverse-CDF rule as the column draw; distinct rows
+// in ascending order with their multiplicities t_hat.
+__global__ __launch_bounds__(1024) void k_draw_rows(RowDrawArgs a)
+{
+    __shared__ uint64_t sincl[1024];
+    __shared__ int64_t sdraw[1024];
+    __shared__ int64_t ssorted[1024];
+    __shared__ int32_t sflag[1024];
+    __shared__ int32_t spos[1025];
+    __shared__ uint64_t swave[16];
+    const int t = threadIdx.x;
+    DevState *ds = a.ds;
+    if (ds->exhausted) return;
+    const int32_t it = ds->it;
+    const int64_t m = a.m;
+    const int64_t chunk = (m + 1023) / 1024;
+    const int64_t j0 = (int64_t)t * chunk;
+    const int64_t j1 = (j0 + chunk < m) ? j0 + chunk : m;
+    uint64_t csum = 0;
+    for (int64_t j = j0; j < j1; ++j) csum += a.wr[j];
+    uint64_t x = csum;
+    const int lane = t & 63, wv = t >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) swave[wv] = x;
+    __syncthreads();
+    uint64_t off = 0;
+    for (int q = 0; q < wv; ++q) off += swave[q];
+    sincl[t] = x + off;
+    __syncthreads();
+    const uint64_t W = sincl[1023];
+    if (W == 0) {
+        if (t == 0) {
+            atomicOr(&ds->flags, (int32_t)FLAG_ZERO_ROWS);
+            ds->h = 0;
+            ds->wrow_tot = 0;
+        }
+        return;
+    }
+    const int32_t c = a.w;
+    for (int32_t d = t; d < c; d += 1024) {
+        uint64_t ctr[4] = {(uint64_t)it, (uint64_t)(d >> 2), a.block, 0};
+        philox4x64_10(ctr, a.seed, 1);
+        const uint64_t tg = __umul64hi(ctr[d & 3], W);
+        int lo = 0, hi = 1023;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sincl[mid] > tg) hi = mid;
+            else lo = mid + 1;
+        }
+        uint64_t run = (lo > 0) ? sincl[lo - 1] : 0;
+        const int64_t q0 = (int64_t)lo * chunk;
+        const int64_t q1 = (q0 + chunk < m) ? q0 + chunk : m;
+        int64_t sel = q1 - 1;
+        for (int64_t j = q0; j < q1; ++j) {
+            run += a.wr[j];
+            if (run > tg) {
+                sel = j;
+                break;
+            }
+        }
+        sdraw[d] = sel;
+    }
+    __syncthreads();
+    for (int32_t d = t; d < c; d += 1024) {
+        const int64_t v = sdraw[d];
+        int32_t rk = 0;
+        for (int32_t e = 0; e < c; ++e) {
+            const int64_t u = sdraw[e];
+            rk += (u < v) || (u == v && e < d);
+        }
+        ssorted[rk] = v;
+    }
+    __syncthreads();
+    for (int32_t d = t; d < c; d += 1024) sflag[d] = (d == 0) || (ssorted[d] != ssorted[d - 1]);
+    __syncthreads();
+    if (t == 0) {
+        int32_t r2 = 0;
+        for (int32_t d = 0; d < c; ++d) {
+            spos[d] = r2;
+            r2 += sflag[d];
+        }
+        spos[1024] = r2;
+    }
+    __syncthreads();
+    const int32_t h = spos[1024];
+    const bool logit = it < a.max_iter;
+    for (int32_t d = t; d < c; d += 1024) {
+        if (sflag[d]) {
+            int32_t e = d + 1;
+            while (e < c && ssorted[e] == ssorted[d]) ++e;
+            a.rows[spos[d]] = (int32_t)ssorted[d];
+            a.rcnt[spos[d]] = e - d;
+            if (logit) {
+                a.row_log[(int64_t)it * c + spos[d]] = (int32_t)ssorted[d];
+                a.rcnt_log[(int64_t)it * c + spos[d]] = e - d;
+            }
+        }
+    }
+    if (t == 0) {
+        ds->h = h;
+        ds->wrow_tot = W;
+    }
+}
+
+hipError_t launch_draw_rows(const RowDrawArgs &a, hipStream_t st)
+{
+    ProfScope ps(POD_K_DRAW, st);
+    hipLaunchKernelGGL(k_draw_rows, dim3(1), dim3(1024), 0, st, a);
     return hipGetLastError();
 }
 

@@ -109,18 +109,42 @@ __global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
     __shared__ int sbad;
     DevState *ds = a.ds;
     if (ds->exhausted) return;
-    const int p = ds->p, rs = ds->rs;
+    const int p = ds->p, rs = ds->rs, p0 = ds->p0;
     const int pm = a.pmax;
     double *S = lds;
-    double *tmp = lds + p * p;
+    double *tmp = lds + pm * pm;        // p doubles
+    double *GP = tmp + pm;              // G0 P (p0 x p), dense right factor only
     if (threadIdx.x == 0) sbad = 0;
     for (int i = threadIdx.x; i < p; i += NT) sP[i] = (i < rs) ? a.sigma[i] : 1.0;
     __syncthreads();
+    if (a.use_vt) {
+        // P = blkdiag(Sigma_r, Vt): GP = G0 P, then G1 = P^T GP into a.work
+        for (int idx = threadIdx.x; idx < p0 * p; idx += NT) {
+            const int i = idx % p0, b = idx / p0;
+            double v;
+            if (b < rs) {
+                v = a.G[i + b * pm] * sP[b];
+            } else {
+                v = 0.0;
+                for (int l = 0; l < p0 - rs; ++l) v += a.G[i + (rs + l) * pm] * a.Vt[l + (b - rs) * pm];
+            }
+            GP[i + b * p0] = v;
+        }
+        __syncthreads();
+    }
     double tr = 0.0;
     int bad = 0;
     for (int idx = threadIdx.x; idx < p * p; idx += NT) {
         const int i = idx % p, j = idx / p;
-        const double v = a.G[i + j * pm] * sP[i] * sP[j];
+        double v;
+        if (!a.use_vt) {
+            v = a.G[i + j * pm] * sP[i] * sP[j];
+        } else if (i < rs) {
+            v = sP[i] * GP[i + j * p0];
+        } else {
+            v = 0.0;
+            for (int l = 0; l < p0 - rs; ++l) v += a.Vt[l + (i - rs) * pm] * GP[(rs + l) + j * p0];
+        }
         if (!isfinite(v)) bad = 1;
         S[idx] = v;
         a.work[idx] = v;
@@ -161,16 +185,33 @@ __global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
     }
     __syncthreads();
     trinv_upper(S, p, tmp);
+    // T1 = P R1^-1 (p0 x p)
     for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
         const int i = idx % pm, j = idx / pm;
-        const double v = (i < p && j < p) ? sP[i] * S[i + j * p] : 0.0;
+        double v = 0.0;
+        if (!a.use_vt) {
+            if (i < p && j < p) v = sP[i] * S[i + j * p];
+        } else if (i < p0 && j < p) {
+            if (i < rs) {
+                v = sP[i] * S[i + j * p];
+            } else {
+                for (int l = rs; l <= j; ++l) v += a.Vt[(i - rs) + (l - rs) * pm] * S[l + j * p];
+            }
+        }
         store_c(a.Tc, a.prec, idx, v);
     }
 }
 
 hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 {
-    const size_t lds = (size_t)(a.pmax * a.pmax + a.pmax) * sizeof(double);
+    const size_t lds = (size_t)((a.use_vt ? 2 : 1) * a.pmax * a.pmax + a.pmax) * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_chol_first, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)((2 * 64 * 64 + 64) * sizeof(double)));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
     ProfScope ps(POD_K_CHOL, st);
     hipLaunchKernelGGL(k_chol_first, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
@@ -519,6 +560,100 @@ hipError_t launch_sign_fix(int32_t prec, void *U, int64_t m, int32_t k, void *V,
         hipLaunchKernelGGL(k_sign_partial<float>, g1, dim3(256), 0, st, (const float *)U, m, cv, ci);
         hipLaunchKernelGGL(k_sign_apply<float>, g2, dim3(256), 0, st, (float *)U, m, (float *)V, n, cv, ci);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Right factor of the new block (GET UPDATE of Alg. 1).  Mode 0 (rows
+// sampled): W = diag(sqrt(t_hat / (w q))) D(I_r, :) with q_i = w_i / Omega
+// (SAMPLE AND SCALE UNIQUE ROWS), G_B = W^T W.  Mode 1 (block truncated to
+// its leading directions): G_B = D^T D, the D-block of the pass-1 Gram.
+// Eigen-decomposition G_B = V Lambda V^T (descending); Vt = V(:, 0:ru) with
+// ru = min(r_lim, g, h, #{lambda_i > g u lambda_1}).  The merge then takes
+// C = D Vt: P = blkdiag(Sigma, Vt) in the CholeskyQR passes.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double sd[64], se[64], stau[64], se2[64], spv[64], sev[64], sdots[64], ssc[8];
+    __shared__ __align__(8) int scl[EIG_NMAX + 8];
+    DevState *ds = a.ds;
+    if (ds->exhausted) return;
+    const int g = ds->g, rs = ds->rs;
+    const int pm = a.pmax;
+    double *S = lds;              // G_B (g x g) -> reflectors
+    double *Y = lds + pm * pm;    // eigenvectors (g x ru)
+    double *lu = Y + pm * pm;     // EIG_LU_THREADS x (4 g + 1)
+    const int h = (a.mode == 0) ? ds->h : g;
+    if (g == 0 || h == 0) {
+        if (threadIdx.x == 0) {
+            ds->ru = 0;
+            ds->p = rs;
+        }
+        return;
+    }
+    if (a.mode == 0) {
+        const double Om = (double)ds->wrow_tot;
+        for (int idx = threadIdx.x; idx < g * g; idx += NT) {
+            const int i = idx % g, j = idx / g;
+            if (i > j) continue;
+            const int64_t ci = a.cols[i], cj = a.cols[j];
+            double s = 0.0;
+            for (int rr = 0; rr < h; ++rr) {
+                const int64_t row = a.rows[rr];
+                const double q = (double)a.wr[row] / Om;
+                const double sc = sqrt((double)a.rcnt[rr] / ((double)a.w * q));
+                double di, dj;
+                if (a.a_dtype == POD_F64) {
+                    di = reinterpret_cast<const double *>(a.A)[ci * a.lda + row];
+                    dj = reinterpret_cast<const double *>(a.A)[cj * a.lda + row];
+                } else {
+                    di = (double)reinterpret_cast<const float *>(a.A)[ci * a.lda + row];
+                    dj = (double)reinterpret_cast<const float *>(a.A)[cj * a.lda + row];
+                }
+                s += (sc * di) * (sc * dj);
+            }
+            S[i + j * g] = s;
+            S[j + i * g] = s;
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < g * g; idx += NT) {
+            const int i = idx % g, j = idx / g;
+            S[idx] = a.G[(rs + i) + (rs + j) * pm];
+        }
+    }
+    __syncthreads();
+    tridiag(S, g, sd, se, stau, spv, ssc);
+    int nv = (a.r_lim < g) ? a.r_lim : g;
+    if (nv > h) nv = h;
+    bisect_top(sd, se, g, nv, sev, se2, ssc);
+    const double thr = (double)g * 1.1102230246251565e-16 * fmax(sev[0], 0.0);
+    const int nz = count_above(sd, se2, g, thr, ssc[2], scl);
+    const int ru = (sev[0] > 0.0) ? ((nv < nz) ? nv : nz) : 0;
+    tri_invit(sd, se, g, sev, ru, Y, lu, scl);
+    tridiag_backtransform(S, stau, g, Y, ru, sdots);
+    for (int idx = threadIdx.x; idx < g * ru; idx += NT) {
+        const int i = idx % g, j = idx / g;
+        a.Vt[i + j * pm] = Y[i + j * g];
+    }
+    if (threadIdx.x == 0) {
+        ds->ru = ru;
+        ds->p = rs + ru;
+    }
+}
+
+hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st)
+{
+    const size_t lds = (size_t)(2 * a.pmax * a.pmax + EIG_LU_THREADS * (4 * a.pmax + 1)) * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_block_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(2 * 64 * 64 + EIG_LU_THREADS * (4 * 64 + 1)) * (int)sizeof(double));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    ProfScope ps(POD_K_DRAW, st);
+    hipLaunchKernelGGL(k_block_eig, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
 

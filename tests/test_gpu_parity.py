@@ -236,3 +236,64 @@ def test_waves_parity(waves_small, precision):
     print(f"  iters={res.iters} sigma_rel={rel:.3e} angle={ang:.3e} flags={res.flags}", flush=True)
     assert rel <= tol_s
     assert ang <= tol_a
+
+
+# ------------------------------------------------------------------ rows (ICRS) and truncated blocks
+
+def _check_run_parity(A, kw, gpu_kw, tol_s=1e-10, tol_a=1e-8, rows=True, elem_bytes=None, tol_sin=1e-9):
+    ref = oracle_isma(A, IsmaParams(**kw), elem_bytes=elem_bytes)
+    res = None
+    with pod.PodContext(_dev(A), **gpu_kw) as ctx:
+        sines = ctx.run()
+        assert len(sines) == len(ref.log)
+        for it, lg in enumerate(ref.log):
+            got = ctx.indices(it, rows=True)
+            assert np.array_equal(got[0], lg.cols), it
+            assert np.array_equal(got[1], lg.col_counts), it
+            if rows:
+                assert np.array_equal(got[2], lg.rows), it
+                assert np.array_equal(got[3], lg.row_counts), it
+        for g_s, lg in zip(sines[1:], ref.log[1:]):
+            assert abs(g_s - lg.sin_theta) <= tol_sin * max(1.0, lg.sin_theta) + 1e-12
+        U, s, _ = ctx.project(want_v=False)
+        res = (U.cpu().numpy(), s.cpu().numpy())
+    U, s = res
+    rel = np.max(np.abs(s - ref.sigma) / ref.sigma)
+    ang = _angles(ref.U, U)
+    print(f"  iters={len(ref.log)} sigma_rel={rel:.3e} angle={ang:.3e}", flush=True)
+    assert rel <= tol_s
+    assert ang <= tol_a
+
+
+@pytest.mark.parametrize("strategy", ["l2", "ls"])
+def test_c1_rows_parity(c1, strategy):
+    """C1 with w = 20 rows per iteration (SAMPLE AND SCALE UNIQUE ROWS):
+    columns, rows and multiplicities bit-exact, FP64 bars on the result."""
+    kw = _c1_params(w=20, row_strategy=strategy)
+    print(f"c1 rows {strategy}", flush=True)
+    rs = pod.POD_ROW_L2 if strategy == "l2" else pod.POD_ROW_LS
+    _check_run_parity(c1.A, kw, dict(_c1_params(w=20), row_strategy=rs))
+
+
+def test_rows_fewer_than_rank(c1):
+    """h < r: the block keeps at most h directions."""
+    kw = _c1_params(w=3, r=12, max_iter=8)
+    print("c1 rows w=3", flush=True)
+    _check_run_parity(c1.A, kw, dict(kw))
+
+
+def test_c1_truncated_block_parity(c1):
+    """GET UPDATE without rows, each block cut to its top r_update right
+    singular directions before the merge."""
+    kw = _c1_params(r_update=6)
+    print("c1 r_update=6", flush=True)
+    _check_run_parity(c1.A, kw, dict(kw), rows=False)
+
+
+def test_waves_rows_fp32(waves_small):
+    """FP32 path with rows: indices bit-exact (row norms of FP32 data are
+    exact), result within the FP32 bars."""
+    A = waves_small
+    kw = dict(k=20, c=40, w=200, seed=2002, theta_tol=1e-5, max_iter=12)
+    print("waves rows fp32", flush=True)
+    _check_run_parity(A, kw, dict(kw, precision=pod.POD_F32), tol_s=1e-5, tol_a=1e-5, elem_bytes=4, tol_sin=1e-5)
