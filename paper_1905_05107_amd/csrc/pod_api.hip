@@ -33,6 +33,7 @@ struct pod_ctx {
     double *sig[2] = {nullptr, nullptr};
     int cur = 0;
     double *part = nullptr, *G = nullptr, *R1 = nullptr, *R2 = nullptr, *work = nullptr;
+    double *ws = nullptr;    // small-kernel matrices when pmax > 64
     void *Tc = nullptr, *Y = nullptr;
     int32_t nblk = 0;
     double *Bpart = nullptr, *B = nullptr, *GB = nullptr, *UB = nullptr, *sigB = nullptr;
@@ -84,7 +85,8 @@ void free_all(pod_ctx *ctx)
                     ctx->col_log_off, ctx->forced, ctx->U[0], ctx->U[1], ctx->sig[0], ctx->sig[1], ctx->part,
                     ctx->G,    ctx->R1,   ctx->R2,    ctx->work, ctx->Tc,   ctx->Y,    ctx->Bpart,
                     ctx->B,    ctx->GB,   ctx->UB,    ctx->sigB, ctx->Zc, ctx->signv, ctx->signi,
-                    ctx->rho,  ctx->Vt,   ctx->wr,    ctx->rows, ctx->rcnt, ctx->row_log, ctx->rcnt_log};
+                    ctx->rho,  ctx->Vt,   ctx->wr,    ctx->rows, ctx->rcnt, ctx->row_log, ctx->rcnt_log,
+                    ctx->ws};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -122,6 +124,7 @@ BlockEigArgs block_eig_args(pod_ctx *ctx, int32_t mode)
     b.pmax = ctx->pmax;
     b.r_lim = (mode == 0) ? ctx->r : ctx->prm.r_update;
     b.Vt = ctx->Vt;
+    b.ws = ctx->ws;
     b.ds = ctx->ds;
     return b;
 }
@@ -201,7 +204,7 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
     if (!(p.theta_tol >= 0.0)) return POD_EINVAL;
     const int64_t cmax = (p.c < p.n) ? p.c : p.n;
     const int32_t pmax = (int32_t)(((r + cmax) + 15) & ~15);
-    if (pmax > 64) return POD_EINVAL;
+    if (pmax > 160) return POD_EINVAL;
 
     pod_ctx *ctx = new (std::nothrow) pod_ctx();
     if (!ctx) return POD_ENOMEM;
@@ -251,6 +254,7 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
     ALLOC(ctx->signv, double, (size_t)64 * r);
     ALLOC(ctx->signi, int64_t, (size_t)64 * r);
     if (p.w > 0 || p.r_update > 0) ALLOC(ctx->Vt, double, (size_t)pmax * pmax);
+    if (pmax > 64) ALLOC(ctx->ws, double, (size_t)3 * pmax * pmax + pmax);
     if (p.w > 0) {
         ALLOC(ctx->rho, double, m);
         ALLOC(ctx->wr, uint64_t, m);
@@ -380,6 +384,7 @@ pod_status pod_merge(pod_ctx *ctx)
     sa.urnd = unit_roundoff(p.precision);
     sa.Vt = ctx->Vt;
     sa.use_vt = (p.w > 0 || p.r_update > 0);
+    sa.ws = ctx->ws;
     if (p.w == 0 && p.r_update > 0) {
         // the new block truncated to its leading r_update directions
         BlockEigArgs ba = block_eig_args(ctx, 1);
@@ -451,6 +456,7 @@ pod_status pod_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out
     ra.UB = ctx->UB;
     ra.sig = ctx->sigB;
     ra.Zc = ctx->Zc;
+    ra.ws = ctx->ws;
     ra.prec = p.precision;
     ra.ds = ctx->ds;
     POD_HIP(launch_rr_small(ra, ctx->st));

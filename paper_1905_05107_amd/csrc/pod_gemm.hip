@@ -161,10 +161,14 @@ template <typename TC> static bool vec_ok(const SrcT<TC> &s, int64_t m)
 // set of the upper-triangular 16x16 tiles (I <= J).  The tile is written (and
 // mirrored) to part[b] (pmax x pmax, FP64); the reduction reads only P x P.
 // ---------------------------------------------------------------------------
-constexpr int MAXPW = 3;     // tiles per wave for pmax <= 64 (10 tiles / 4 waves)
-constexpr int ITEMS64 = 2;   // 64 columns x 8 groups / 256 threads
+// Width classes: pmax <= 64 (10 tiles over 4 waves: 3 per wave; a stage is
+// 64 columns x 8 groups = 2 items per thread) and pmax <= 160 (55 tiles: 14
+// per wave; 5 items per thread).
+constexpr int MAXPW64 = 3, ITEMS64 = 2;
+constexpr int MAXPW160 = 14, ITEMS160 = 5;
+constexpr int PMAX_WIDE = 160;
 
-template <typename TC>
+template <typename TC, int MAXPW, int ITEMS>
 __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, const DevState *ds, int which_p,
                                                       int pmax, double *__restrict__ part, int nblk, int vec)
 {
@@ -198,7 +202,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
     AccT acc[MAXPW];
 #pragma unroll
     for (int q = 0; q < MAXPW; ++q) acc[q] = AccT{0, 0, 0, 0};
-    Stage<TC, ITEMS64> st;
+    Stage<TC, ITEMS> st;
     if (s0 < s1) st.load(s, m, s0 * RB, P, vec);
     for (int64_t sg = s0; sg < s1; ++sg) {
         __syncthreads();
@@ -269,21 +273,28 @@ template <typename TC> static SrcT<TC> make_src(const GemmDesc &d)
     return s;
 }
 
+template <typename TC, int MAXPW, int ITEMS>
+static void gram_launch(const GemmDesc &d, const DevState *ds, int32_t which_p, int32_t pmax, double *part,
+                        int32_t nblk, hipStream_t st)
+{
+    const SrcT<TC> s = make_src<TC>(d);
+    const size_t lds = (size_t)pmax * LDSR * sizeof(TC);
+    hipLaunchKernelGGL((k_gram_partial<TC, MAXPW, ITEMS>), dim3(nblk), dim3(256), lds, st, s, d.m, ds, which_p, pmax,
+                       part, nblk, (int)vec_ok(s, d.m));
+}
+
 hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t which_p, int32_t pmax, double *part,
                                int32_t nblk, hipStream_t st)
 {
-    if (pmax > 64) return hipErrorInvalidValue;
+    if (pmax > PMAX_WIDE) return hipErrorInvalidValue;
     ProfScope ps(POD_K_GRAM, st);
+    const bool wide = pmax > 64;
     if (d.prec == POD_F64) {
-        const SrcT<double> s = make_src<double>(d);
-        const size_t lds = (size_t)pmax * LDSR * sizeof(double);
-        hipLaunchKernelGGL(k_gram_partial<double>, dim3(nblk), dim3(256), lds, st, s, d.m, ds, which_p, pmax, part,
-                           nblk, (int)vec_ok(s, d.m));
+        if (wide) gram_launch<double, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
+        else gram_launch<double, MAXPW64, ITEMS64>(d, ds, which_p, pmax, part, nblk, st);
     } else {
-        const SrcT<float> s = make_src<float>(d);
-        const size_t lds = (size_t)pmax * LDSR * sizeof(float);
-        hipLaunchKernelGGL(k_gram_partial<float>, dim3(nblk), dim3(256), lds, st, s, d.m, ds, which_p, pmax, part,
-                           nblk, (int)vec_ok(s, d.m));
+        if (wide) gram_launch<float, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
+        else gram_launch<float, MAXPW64, ITEMS64>(d, ds, which_p, pmax, part, nblk, st);
     }
     return hipGetLastError();
 }
@@ -304,8 +315,9 @@ hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax
 // consecutive rows of one output column.
 // ---------------------------------------------------------------------------
 constexpr int TALL_ST = 4;   // row stages per workgroup
+constexpr size_t TALL_T_LDS = 112 * 1024;  // largest T staged in LDS
 
-template <typename TC>
+template <typename TC, int ITEMS, bool TG>
 __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
                                                    int sel_out, int pmax_in, int pmax_out, const TC *__restrict__ T,
                                                    int ldt, TC *__restrict__ Yout, int vec)
@@ -317,17 +329,18 @@ __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const 
     s.rs = ds->rs;
     const int PI = (pin + 15) & ~15, PO = (pout + 15) & ~15;
     TC *Xs = reinterpret_cast<TC *>(lds_raw);        // pmax_in x LDSR
-    TC *Ts = Xs + pmax_in * LDSR;                    // PI x PO, row k at Ts + k * PO
+    TC *Ts = Xs + pmax_in * LDSR;                    // PI x PO, row k at Ts + k * PO (when !TG)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nst = (m + RB - 1) / RB;
     const int64_t s0 = (int64_t)blockIdx.x * TALL_ST;
     const int64_t s1 = (s0 + TALL_ST < nst) ? s0 + TALL_ST : nst;
-    for (int idx = threadIdx.x; idx < PI * PO; idx += 256) {
-        const int k = idx / PO, j = idx % PO;
-        Ts[idx] = (k < pin && j < pout) ? T[k + (int64_t)j * ldt] : (TC)0;
-    }
+    if (!TG)
+        for (int idx = threadIdx.x; idx < PI * PO; idx += 256) {
+            const int k = idx / PO, j = idx % PO;
+            Ts[idx] = (k < pin && j < pout) ? T[k + (int64_t)j * ldt] : (TC)0;
+        }
     (void)pmax_out;
-    Stage<TC, ITEMS64> st;
+    Stage<TC, ITEMS> st;
     st.load(s, m, s0 * RB, pin, vec);
     const int ntile = (RB / 16) * (PO / 16);
     for (int64_t sg = s0; sg < s1; ++sg) {
@@ -338,9 +351,19 @@ __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const 
         for (int tile = wv; tile < ntile; tile += 4) {
             const int rbk = tile % (RB / 16), jc = tile / (RB / 16);
             AccT acc = AccT{0, 0, 0, 0};
-            const TC *ta = Ts + (lane >> 4) * PO + jc * 16 + (lane & 15);
             const TC *xb = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
-            for (int k4 = 0; k4 < PI; k4 += 4) acc = mfma16x16x4(ta[k4 * PO], xb[k4 * LDSR], acc);
+            if (!TG) {
+                const TC *ta = Ts + (lane >> 4) * PO + jc * 16 + (lane & 15);
+                for (int k4 = 0; k4 < PI; k4 += 4) acc = mfma16x16x4(ta[k4 * PO], xb[k4 * LDSR], acc);
+            } else {
+                // T read from device memory (L2 resident), zero outside pin x pout
+                const int jj = jc * 16 + (lane & 15);
+                const TC *ta = T + (lane >> 4) + (int64_t)jj * ldt;
+                for (int k4 = 0; k4 < PI; k4 += 4) {
+                    const TC tv = (jj < pout && k4 + (lane >> 4) < pin) ? ta[k4] : (TC)0;
+                    acc = mfma16x16x4(tv, xb[k4 * LDSR], acc);
+                }
+            }
             const int64_t row = sg * RB + rbk * 16 + (lane & 15);
             if (row < m) {
 #pragma unroll
@@ -353,25 +376,43 @@ __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const 
     }
 }
 
+template <typename TC, int ITEMS, bool TG>
+static void tall_launch(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out, int PI, int PO,
+                        const void *T, int32_t ldt, void *Yout, unsigned nb, hipStream_t st)
+{
+    const SrcT<TC> s = make_src<TC>(d);
+    const size_t lds = (size_t)(PI * LDSR + (TG ? 0 : PI * PO)) * sizeof(TC);
+    static bool attr = false;
+    if (lds > 64 * 1024 && !attr) {
+        if (hipFuncSetAttribute((const void *)k_gemm_tall<TC, ITEMS, TG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024) != hipSuccess)
+            return;   // the launch below then fails and reports the error
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_gemm_tall<TC, ITEMS, TG>), dim3(nb), dim3(256), lds, st, s, d.m, ds, which_in, which_out,
+                       PI, PO, (const TC *)T, ldt, (TC *)Yout, (int)vec_ok(s, d.m));
+}
+
 hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
                             int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout,
                             hipStream_t st)
 {
-    if (pin_max > 64 || pout_max > 64) return hipErrorInvalidValue;
+    if (pin_max > PMAX_WIDE || pout_max > PMAX_WIDE) return hipErrorInvalidValue;
     ProfScope ps(POD_K_TALL, st);
     const int64_t nst = (d.m + RB - 1) / RB;
     const unsigned nb = (unsigned)((nst + TALL_ST - 1) / TALL_ST);
     const int PI = (pin_max + 15) & ~15, PO = (pout_max + 15) & ~15;
+    const bool wide = PI > 64;
     if (d.prec == POD_F64) {
-        const SrcT<double> s = make_src<double>(d);
-        const size_t lds = (size_t)(PI * LDSR + PI * PO) * sizeof(double);
-        hipLaunchKernelGGL(k_gemm_tall<double>, dim3(nb), dim3(256), lds, st, s, d.m, ds, which_in, which_out, PI,
-                           PO, (const double *)T, ldt, (double *)Yout, (int)vec_ok(s, d.m));
+        const bool tg = (size_t)PI * PO * sizeof(double) > TALL_T_LDS;
+        if (!wide) tall_launch<double, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
+        else if (!tg) tall_launch<double, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
+        else tall_launch<double, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
     } else {
-        const SrcT<float> s = make_src<float>(d);
-        const size_t lds = (size_t)(PI * LDSR + PI * PO) * sizeof(float);
-        hipLaunchKernelGGL(k_gemm_tall<float>, dim3(nb), dim3(256), lds, st, s, d.m, ds, which_in, which_out, PI, PO,
-                           (const float *)T, ldt, (float *)Yout, (int)vec_ok(s, d.m));
+        const bool tg = (size_t)PI * PO * sizeof(float) > TALL_T_LDS;
+        if (!wide) tall_launch<float, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
+        else if (!tg) tall_launch<float, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
+        else tall_launch<float, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
     }
     return hipGetLastError();
 }
@@ -386,7 +427,7 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
 // ---------------------------------------------------------------------------
 constexpr int PCB = 64;  // columns of A per workgroup
 
-template <typename TC, typename TA>
+template <typename TC, typename TA, int MT, int UITEMS>
 __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ U, const TA *__restrict__ A,
                                                          int64_t m, int64_t n, int64_t lda, int r, int nsplit,
                                                          int ncb, double *__restrict__ Bpart, int vec)
@@ -423,12 +464,12 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
     su.a_f64 = 0;
     su.rs = 0;
     su.guard = 0;
-    constexpr int MT = 4;  // r <= 64
-    AccT acc[MT];
+    AccT acc[MT];   // MT mode tiles: r <= 16 MT
 #pragma unroll
     for (int q = 0; q < MT; ++q) acc[q] = AccT{0, 0, 0, 0};
-    // A stage: 64 columns x 8 groups = 512 items; U stage: RP columns x 8 groups <= 512 items
-    Stage<TC, 2> sta, stu;
+    // A stage: 64 columns x 8 groups = 512 items; U stage: RP columns x 8 groups <= 256 UITEMS items
+    Stage<TC, 2> sta;
+    Stage<TC, UITEMS> stu;
     const TA *Ab = A + c0 * lda;
     auto loadA = [&](int64_t sg) {
 #pragma unroll
@@ -492,32 +533,38 @@ __global__ __launch_bounds__(256) void k_project_reduce(const double *__restrict
     B[idx] = s;
 }
 
+template <typename TC, typename TA, int MT, int UITEMS>
+static void project_launch(const ProjArgs &a, unsigned total, int ncb, int vec, hipStream_t st)
+{
+    const int RP = (a.r + 15) & ~15;
+    const size_t lds = (size_t)(PCB + RP) * LDSR * sizeof(TC);
+    hipLaunchKernelGGL((k_project_partial<TC, TA, MT, UITEMS>), dim3(total), dim3(256), lds, st, (const TC *)a.U,
+                       (const TA *)a.A, a.m, a.n, a.lda, a.r, a.nsplit, ncb, a.Bpart, vec);
+}
+
 hipError_t launch_project_partial(const ProjArgs &a, hipStream_t st)
 {
-    if (a.r > 64) return hipErrorInvalidValue;
+    if (a.r > PMAX_WIDE) return hipErrorInvalidValue;
+    if (a.prec != POD_F64 && a.a_dtype == POD_F64) return hipErrorInvalidValue;
     const int ncb = (int)((a.n + PCB - 1) / PCB);
-    const int RP = (a.r + 15) & ~15;
     const unsigned total = (unsigned)(a.nsplit * ncb);
     ProfScope ps(POD_K_PROJECT, st);
     const size_t ae = (a.a_dtype == POD_F64) ? 8 : 4;
     const size_t ce = (a.prec == POD_F64) ? 8 : 4;
     const int vec = ((uintptr_t)a.A % 16 == 0) && ((a.lda * ae) % 16 == 0) && ((uintptr_t)a.U % 16 == 0) &&
                     ((a.m * ce) % 16 == 0);
+    const bool wide = a.r > 64;
     if (a.prec == POD_F64) {
-        const size_t lds = (size_t)(PCB + RP) * LDSR * sizeof(double);
-        if (a.a_dtype == POD_F64)
-            hipLaunchKernelGGL((k_project_partial<double, double>), dim3(total), dim3(256), lds, st,
-                               (const double *)a.U, (const double *)a.A, a.m, a.n, a.lda, a.r, a.nsplit, ncb,
-                               a.Bpart, vec);
-        else
-            hipLaunchKernelGGL((k_project_partial<double, float>), dim3(total), dim3(256), lds, st,
-                               (const double *)a.U, (const float *)a.A, a.m, a.n, a.lda, a.r, a.nsplit, ncb,
-                               a.Bpart, vec);
+        if (a.a_dtype == POD_F64) {
+            if (wide) project_launch<double, double, 10, ITEMS160>(a, total, ncb, vec, st);
+            else project_launch<double, double, 4, ITEMS64>(a, total, ncb, vec, st);
+        } else {
+            if (wide) project_launch<double, float, 10, ITEMS160>(a, total, ncb, vec, st);
+            else project_launch<double, float, 4, ITEMS64>(a, total, ncb, vec, st);
+        }
     } else {
-        const size_t lds = (size_t)(PCB + RP) * LDSR * sizeof(float);
-        if (a.a_dtype == POD_F64) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_project_partial<float, float>), dim3(total), dim3(256), lds, st, (const float *)a.U,
-                           (const float *)a.A, a.m, a.n, a.lda, a.r, a.nsplit, ncb, a.Bpart, vec);
+        if (wide) project_launch<float, float, 10, ITEMS160>(a, total, ncb, vec, st);
+        else project_launch<float, float, 4, ITEMS64>(a, total, ncb, vec, st);
     }
     return hipGetLastError();
 }

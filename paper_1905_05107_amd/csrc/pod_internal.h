@@ -170,6 +170,7 @@ struct SmallArgs {
     double *R2;            // (pmax x pmax)
     void *Tc;              // transform in compute type (pmax x pmax, ld pmax)
     double *work;          // scratch (pmax x pmax)
+    double *ws;            // matrices of the kernel when pmax > 64 (3 pmax^2 + pmax)
     int32_t pmax;
     int32_t r, k;
     int32_t prec;
@@ -195,6 +196,7 @@ struct BlockEigArgs {
     int32_t pmax;
     int32_t r_lim;
     double *Vt;            // out, g x ru (ld pmax)
+    double *ws;            // matrices of the kernel when pmax > 64 (2 pmax^2)
     DevState *ds;
 };
 hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st);
@@ -220,6 +222,7 @@ struct RRArgs {
     double *UB;           // r x r (out, ld r)
     double *sig;          // r (out)
     void *Zc;             // U_B in compute type (r x k, ld r)
+    double *ws;           // matrices of the kernel when r > 64 (2 r^2)
     int32_t prec;
     DevState *ds;
 };

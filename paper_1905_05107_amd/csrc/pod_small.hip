@@ -12,6 +12,15 @@
 namespace pod {
 
 constexpr int NT = EIG_NT;
+// Matrices up to SMALL_LDS_P x SMALL_LDS_P live in LDS; larger ones in the
+// workspace `ws` (device memory, L2 resident), with only the inverse-iteration
+// scratch in LDS.
+constexpr int SMALL_LDS_P = 64;
+constexpr size_t lds_limit(bool big)
+{
+    return big ? (size_t)EIG_LU_THREADS * eig_lu_stride(EIG_NMAX) * sizeof(double)
+               : (size_t)(3 * SMALL_LDS_P * SMALL_LDS_P + EIG_LU_THREADS * eig_lu_stride(SMALL_LDS_P)) * sizeof(double);
+}
 
 // ---------------------------------------------------------------------------
 // In-place Cholesky S = R^T R of the symmetric p x p matrix S (LDS,
@@ -101,18 +110,19 @@ __device__ __forceinline__ void store_c(void *base, int prec, int64_t idx, doubl
 // R1 = chol(G1) (shifted by s = p u tr(G1) if a pivot breaks down),
 // T1 = P R1^-1 written in the compute type for the tall GEMM Y = X0 T1.
 // ---------------------------------------------------------------------------
+template <bool BIG>
 __global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
 {
     extern __shared__ double lds[];
-    __shared__ double sP[64];
+    __shared__ double sP[EIG_NMAX];
     __shared__ double sred[16];
     __shared__ int sbad;
     DevState *ds = a.ds;
     if (ds->exhausted) return;
     const int p = ds->p, rs = ds->rs, p0 = ds->p0;
     const int pm = a.pmax;
-    double *S = lds;
-    double *tmp = lds + pm * pm;        // p doubles
+    double *S = BIG ? a.ws : lds;       // p x p
+    double *tmp = S + pm * pm;          // p doubles
     double *GP = tmp + pm;              // G0 P (p0 x p), dense right factor only
     if (threadIdx.x == 0) sbad = 0;
     for (int i = threadIdx.x; i < p; i += NT) sP[i] = (i < rs) ? a.sigma[i] : 1.0;
@@ -204,16 +214,20 @@ __global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
 
 hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 {
-    const size_t lds = (size_t)((a.use_vt ? 2 : 1) * a.pmax * a.pmax + a.pmax) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_chol_first, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)((2 * 64 * 64 + 64) * sizeof(double)));
+    const bool big = a.pmax > SMALL_LDS_P;
+    const size_t lds = big ? (0) : ((size_t)((a.use_vt ? 2 : 1) * a.pmax * a.pmax + a.pmax) * sizeof(double));
+    static bool attr[2] = {false, false};
+    const void *fn = big ? (const void *)k_chol_first<true> : (const void *)k_chol_first<false>;
+    if (!attr[big]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit(big));
         if (e != hipSuccess) return e;
-        attr = true;
+        attr[big] = true;
     }
     ProfScope ps(POD_K_CHOL, st);
-    hipLaunchKernelGGL(k_chol_first, dim3(1), dim3(NT), lds, st, a);
+    if (big)
+        hipLaunchKernelGGL(k_chol_first<true>, dim3(1), dim3(NT), lds, st, a);
+    else
+        hipLaunchKernelGGL(k_chol_first<false>, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
 
@@ -233,20 +247,22 @@ hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 // largest is the square root of the largest eigenvalue of B^T B.  The mode
 // criterion compares R(:, i)/|R(:, i)| with U_R(:, i) one by one.
 // ---------------------------------------------------------------------------
+template <bool BIG>
 __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
 {
     extern __shared__ double lds[];
-    __shared__ double sd[64], se[64], stau[64], se2[64], spv[64], sev[64], sdots[64], ssc[8], ssin[2];
+    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
+        sdots[EIG_NMAX], ssc[8], ssin[2];
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     __shared__ double sred[NT / 64];
     DevState *ds = a.ds;
     if (ds->exhausted) return;
     const int p = ds->p, rs = ds->rs;
     const int pm = a.pmax;
-    double *S1 = lds;              // G2 -> R2 -> R2^-1
-    double *S2 = lds + p * p;      // R1 -> H = R R^T -> reflectors -> B^T B
-    double *S3 = lds + 2 * p * p;  // R -> eigenvectors Y (p x r')
-    double *lu = lds + 3 * p * p;  // EIG_LU_THREADS x 4 p
+    double *S1 = BIG ? a.ws : lds; // G2 -> R2 -> R2^-1
+    double *S2 = S1 + p * p;       // R1 -> H = R R^T -> reflectors -> B^T B
+    double *S3 = S1 + 2 * p * p;   // R -> eigenvectors Y (p x r')
+    double *lu = BIG ? lds : lds + 3 * p * p;  // EIG_LU_THREADS x eig_lu_stride(p)
     // ---- pass-2 Cholesky
     double tr = 0.0;
     for (int idx = threadIdx.x; idx < p * p; idx += NT) {
@@ -380,16 +396,20 @@ __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
 
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
 {
-    const size_t lds = (size_t)(3 * a.pmax * a.pmax + EIG_LU_THREADS * (4 * a.pmax + 1)) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_svd_merge, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(3 * 64 * 64 + EIG_LU_THREADS * (4 * 64 + 1)) * (int)sizeof(double));
+    const bool big = a.pmax > SMALL_LDS_P;
+    const size_t lds = big ? ((size_t)(EIG_LU_THREADS * eig_lu_stride(a.pmax)) * sizeof(double)) : ((size_t)(3 * a.pmax * a.pmax + EIG_LU_THREADS * eig_lu_stride(a.pmax)) * sizeof(double));
+    static bool attr[2] = {false, false};
+    const void *fn = big ? (const void *)k_svd_merge<true> : (const void *)k_svd_merge<false>;
+    if (!attr[big]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit(big));
         if (e != hipSuccess) return e;
-        attr = true;
+        attr[big] = true;
     }
     ProfScope ps(POD_K_SVD, st);
-    hipLaunchKernelGGL(k_svd_merge, dim3(1), dim3(NT), lds, st, a);
+    if (big)
+        hipLaunchKernelGGL(k_svd_merge<true>, dim3(1), dim3(NT), lds, st, a);
+    else
+        hipLaunchKernelGGL(k_svd_merge<false>, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
 
@@ -399,15 +419,17 @@ hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
 // (G_B = U_B Lambda U_B^T, so the rotated columns converge to U_B Lambda),
 // Sigma_B = sqrt(Lambda); U_B(:, 0:k) is written in the compute type.
 // ---------------------------------------------------------------------------
+template <bool BIG>
 __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
 {
     extern __shared__ double lds[];
-    __shared__ double sd[64], se[64], stau[64], se2[64], spv[64], sev[64], sdots[64], ssc[8];
+    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
+        sdots[EIG_NMAX], ssc[8];
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     const int r = a.r, k = a.k;
-    double *S = lds;             // G_B -> reflectors
-    double *Y = lds + r * r;     // eigenvectors (r x k)
-    double *lu = Y + r * r;      // EIG_LU_THREADS x 4 r
+    double *S = BIG ? a.ws : lds; // G_B -> reflectors
+    double *Y = S + r * r;        // eigenvectors (r x k)
+    double *lu = BIG ? lds : Y + r * r;  // EIG_LU_THREADS x eig_lu_stride(r)
     // G_B entries, one wave per entry group, lanes along n
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int e = wv; e < r * r; e += NT / 64) {
@@ -434,16 +456,20 @@ __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
 
 hipError_t launch_rr_small(const RRArgs &a, hipStream_t st)
 {
-    const size_t lds = (size_t)(2 * a.r * a.r + EIG_LU_THREADS * (4 * a.r + 1)) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_rr_small, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(2 * 64 * 64 + EIG_LU_THREADS * (4 * 64 + 1)) * (int)sizeof(double));
+    const bool big = a.r > SMALL_LDS_P;
+    const size_t lds = big ? ((size_t)(EIG_LU_THREADS * eig_lu_stride(a.r)) * sizeof(double)) : ((size_t)(2 * a.r * a.r + EIG_LU_THREADS * eig_lu_stride(a.r)) * sizeof(double));
+    static bool attr[2] = {false, false};
+    const void *fn = big ? (const void *)k_rr_small<true> : (const void *)k_rr_small<false>;
+    if (!attr[big]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit(big));
         if (e != hipSuccess) return e;
-        attr = true;
+        attr[big] = true;
     }
     ProfScope ps(POD_K_RR, st);
-    hipLaunchKernelGGL(k_rr_small, dim3(1), dim3(NT), lds, st, a);
+    if (big)
+        hipLaunchKernelGGL(k_rr_small<true>, dim3(1), dim3(NT), lds, st, a);
+    else
+        hipLaunchKernelGGL(k_rr_small<false>, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
 
@@ -572,18 +598,20 @@ hipError_t launch_sign_fix(int32_t prec, void *U, int64_t m, int32_t k, void *V,
 // ru = min(r_lim, g, h, #{lambda_i > g u lambda_1}).  The merge then takes
 // C = D Vt: P = blkdiag(Sigma, Vt) in the CholeskyQR passes.
 // ---------------------------------------------------------------------------
+template <bool BIG>
 __global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
 {
     extern __shared__ double lds[];
-    __shared__ double sd[64], se[64], stau[64], se2[64], spv[64], sev[64], sdots[64], ssc[8];
+    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
+        sdots[EIG_NMAX], ssc[8];
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     DevState *ds = a.ds;
     if (ds->exhausted) return;
     const int g = ds->g, rs = ds->rs;
     const int pm = a.pmax;
-    double *S = lds;              // G_B (g x g) -> reflectors
-    double *Y = lds + pm * pm;    // eigenvectors (g x ru)
-    double *lu = Y + pm * pm;     // EIG_LU_THREADS x (4 g + 1)
+    double *S = BIG ? a.ws : lds; // G_B (g x g) -> reflectors
+    double *Y = S + pm * pm;      // eigenvectors (g x ru)
+    double *lu = BIG ? lds : Y + pm * pm;  // EIG_LU_THREADS x eig_lu_stride(g)
     const int h = (a.mode == 0) ? ds->h : g;
     if (g == 0 || h == 0) {
         if (threadIdx.x == 0) {
@@ -644,16 +672,20 @@ __global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
 
 hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st)
 {
-    const size_t lds = (size_t)(2 * a.pmax * a.pmax + EIG_LU_THREADS * (4 * a.pmax + 1)) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_block_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(2 * 64 * 64 + EIG_LU_THREADS * (4 * 64 + 1)) * (int)sizeof(double));
+    const bool big = a.pmax > SMALL_LDS_P;
+    const size_t lds = big ? ((size_t)(EIG_LU_THREADS * eig_lu_stride(a.pmax)) * sizeof(double)) : ((size_t)(2 * a.pmax * a.pmax + EIG_LU_THREADS * eig_lu_stride(a.pmax)) * sizeof(double));
+    static bool attr[2] = {false, false};
+    const void *fn = big ? (const void *)k_block_eig<true> : (const void *)k_block_eig<false>;
+    if (!attr[big]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit(big));
         if (e != hipSuccess) return e;
-        attr = true;
+        attr[big] = true;
     }
     ProfScope ps(POD_K_DRAW, st);
-    hipLaunchKernelGGL(k_block_eig, dim3(1), dim3(NT), lds, st, a);
+    if (big)
+        hipLaunchKernelGGL(k_block_eig<true>, dim3(1), dim3(NT), lds, st, a);
+    else
+        hipLaunchKernelGGL(k_block_eig<false>, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
 

@@ -1,4 +1,4 @@
-// pod_symeig.h -- FP64 symmetric eigensolver for one workgroup (n <= 64),
+// pod_symeig.h -- FP64 symmetric eigensolver for one workgroup (n <= 160),
 // used for the small matrices of the merge (R R^T), of the convergence test
 // and of the final Rayleigh-Ritz step.  Included by pod_small.hip.
 //
@@ -23,7 +23,7 @@
 namespace pod {
 
 constexpr int EIG_NT = 512;   // threads of the workgroups that call these routines
-constexpr int EIG_NMAX = 64;
+constexpr int EIG_NMAX = 160;
 
 // 1/x from the hardware FP64 reciprocal estimate refined by two Newton steps
 // (error within a few ulp; used where the recurrences below need a quotient)
@@ -71,13 +71,14 @@ __device__ void tridiag(double *A, int n, double *d, double *e, double *tau, dou
     const int lane = t & 63;
     (void)sc;
     for (int j = 0; j + 2 < n; ++j) {
-        const int q = n - j - 1;          // length of x = A(j+1:n, j), q <= 63
+        const int q = n - j - 1;          // length of x = A(j+1:n, j)
         double *x = A + j * n + (j + 1);
         // -- reflector, computed redundantly by every wave (no barrier):
         //    alpha = -sign(x0) |x|, v = x - alpha e1, tau = 1/(alpha^2 - alpha x0)
-        const double xi = (lane < q) ? x[lane] : 0.0;
-        const double ss = wave_sum(xi * xi);
-        const double x0 = __shfl(xi, 0, 64);
+        double ss = 0.0;
+        for (int l = lane; l < q; l += 64) ss += x[l] * x[l];
+        ss = wave_sum(ss);
+        const double x0 = x[0];
         double alpha, tj;
         if (ss > 0.0 && (ss - x0 * x0) > 0.0) {
             alpha = (x0 >= 0.0) ? -sqrt(ss) : sqrt(ss);
@@ -89,17 +90,20 @@ __device__ void tridiag(double *A, int n, double *d, double *e, double *tau, dou
         const double v0 = x0 - alpha;
         if (tj != 0.0) {
             // -- p = tau * A22 v  (8 lanes per row of A22 = rows j+1.. of A)
-            const int row = t >> 3, gl = t & 7;
             double *A22 = A + (j + 1) * n + (j + 1);
-            double s = 0.0;
-            if (row < q)
+            const int gl = t & 7;
+            // the 8 lanes of a group share `row`, so a group is active or idle as a whole
+            for (int row = t >> 3; row < q; row += EIG_NT / 8) {
+                double s = 0.0;
                 for (int k = gl; k < q; k += 8) s += A22[row + k * n] * ((k == 0) ? v0 : x[k]);
-            s = group_sum<8>(s);
-            if (row < q && gl == 0) pv[row] = tj * s;
+                s = group_sum<8>(s);
+                if (gl == 0) pv[row] = tj * s;
+            }
             __syncthreads();
             // -- K = tau/2 p^T v (every wave), w = p - K v, A22 -= v w^T + w v^T
-            const double vi = (lane == 0) ? v0 : xi;
-            const double kk = 0.5 * tj * wave_sum((lane < q) ? pv[lane] * vi : 0.0);
+            double kp = 0.0;
+            for (int l = lane; l < q; l += 64) kp += pv[l] * ((l == 0) ? v0 : x[l]);
+            const double kk = 0.5 * tj * wave_sum(kp);
             const int tx = t & 31, ty = t >> 5;
             for (int b = ty; b < q; b += EIG_NT / 32) {
                 const double vb = (b == 0) ? v0 : x[b];
@@ -235,18 +239,21 @@ __device__ int count_above(const double *d, const double *e2, int n, double thr,
 // magnitude (a relative gap: the eigenvalues of R R^T span many orders of
 // magnitude, and an absolute threshold would chain all small ones into one
 // serial cluster).  One thread handles one cluster, its members in order.
-// Y (n x nv, ld n) receives unit vectors.  `lu` holds 4 n + 1 doubles per
-// active thread (odd stride: no LDS bank conflicts between threads), at most
-// EIG_LU_THREADS threads.
+// Y (n x nv, ld n) receives unit vectors.  `lu` holds eig_lu_stride(n)
+// doubles per active thread (odd stride: no LDS bank conflicts between
+// threads), at most EIG_LU_THREADS threads.
 // ---------------------------------------------------------------------------
 constexpr int EIG_LU_THREADS = 16;
+// doubles per thread of the `lu` scratch: three diagonals of U, the
+// multipliers and n interchange flags (ints, two per double), made odd
+__host__ __device__ constexpr int eig_lu_stride(int n) { return (4 * n + (n + 1) / 2) | 1; }
 
 __device__ void tri_invit(const double *d, const double *e, int n, const double *ev, int nv, double *Y, double *lu,
                           int *scl)
 {
     const int t = threadIdx.x;
     const double u = 1.1102230246251565e-16;
-    // cluster starts (thread 0), clusters listed in scl[0..nc), scl[63] = nc
+    // cluster starts (thread 0): scl[0..nc] (scl[nc] = nv), scl[EIG_NMAX + 1] = nc
     if (t == 0) {
         double tn = 0.0;
         for (int i = 0; i < nv; ++i) tn = fmax(tn, fabs(ev[i]));
@@ -256,38 +263,39 @@ __device__ void tri_invit(const double *d, const double *e, int n, const double 
             if (i == 0 || fabs(ev[i - 1] - ev[i]) > 1e-3 * fmax(fabs(ev[i - 1]), fabs(ev[i])) + 8.0 * u * tn)
                 scl[nc++] = i;
         scl[nc] = nv;
-        scl[EIG_NMAX] = nc;
+        scl[EIG_NMAX + 1] = nc;
         ((double *)(scl + EIG_NMAX + 2))[0] = tn;
     }
     __syncthreads();
-    const int nc = scl[EIG_NMAX];
+    const int nc = scl[EIG_NMAX + 1];
     const double tn = ((const double *)(scl + EIG_NMAX + 2))[0];
     for (int cb = 0; cb < nc; cb += EIG_LU_THREADS) {
         const int c = cb + t;
         if (t < EIG_LU_THREADS && c < nc) {
-            double *u1 = lu + (size_t)t * (4 * n + 1), *u2 = u1 + n, *u3 = u2 + n, *ml = u3 + n;
+            double *u1 = lu + (size_t)t * eig_lu_stride(n), *u2 = u1 + n, *u3 = u2 + n, *ml = u3 + n;
+            int *sw = reinterpret_cast<int *>(ml + n);   // row interchange at step i
             const int i0 = scl[c], i1 = scl[c + 1];
             for (int mi = i0; mi < i1; ++mi) {
                 // perturb equal eigenvalues inside a cluster so the solves differ
                 const double lam = ev[mi] + (double)(mi - i0) * 4.0 * u * tn;
                 // factor: rows (r0, r1, r2) at cols (i, i+1, i+2)
                 double r0 = d[0] - lam, r1 = (n > 1) ? e[0] : 0.0, r2 = 0.0;
-                unsigned long long swp = 0;
                 for (int i = 0; i + 1 < n; ++i) {
                     const double s0 = e[i], s1 = d[i + 1] - lam, s2 = (i + 2 < n) ? e[i + 1] : 0.0;
                     double p0, p1, p2, o1, o2, mult;
-                    if (fabs(r0) >= fabs(s0)) {
+                    const bool swap = !(fabs(r0) >= fabs(s0));
+                    if (!swap) {
                         p0 = r0; p1 = r1; p2 = r2;
                         if (p0 == 0.0) p0 = u * tn + 1e-300;
                         mult = s0 * rcp_nr(p0);
                         o1 = s1; o2 = s2;
                     } else {
-                        swp |= (1ULL << i);
                         p0 = s0; p1 = s1; p2 = s2;
                         mult = r0 * rcp_nr(p0);
                         o1 = r1; o2 = r2;
                     }
                     u1[i] = p0; u2[i] = p1; u3[i] = p2; ml[i] = mult;
+                    sw[i] = swap ? 1 : 0;
                     r0 = o1 - mult * p1;
                     r1 = o2 - mult * p2;
                     r2 = 0.0;
@@ -305,7 +313,7 @@ __device__ void tri_invit(const double *d, const double *e, int n, const double 
                     double cur = y[0];
                     for (int i = 0; i + 1 < n; ++i) {
                         double nxt = y[i + 1];
-                        if (swp & (1ULL << i)) {
+                        if (sw[i]) {
                             const double tmp = cur;
                             cur = nxt;
                             nxt = tmp;

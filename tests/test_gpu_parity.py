@@ -297,3 +297,29 @@ def test_waves_rows_fp32(waves_small):
     kw = dict(k=20, c=40, w=200, seed=2002, theta_tol=1e-5, max_iter=12)
     print("waves rows fp32", flush=True)
     _check_run_parity(A, kw, dict(kw, precision=pod.POD_F32), tol_s=1e-5, tol_a=1e-5, elem_bytes=4, tol_sin=1e-5)
+
+
+# ------------------------------------------------------------------ wide merges (p > 64: matrices outside LDS)
+
+@pytest.fixture(scope="module")
+def wide_fp64():
+    s = np.exp(-np.arange(150) / 25.0)
+    return snapgen.spectrum_matrix(3000, 700, s, 1e-8, seed=1007).A
+
+
+@pytest.mark.parametrize("precision", [pod.POD_F64, pod.POD_F32])
+def test_wide_merge_parity(wide_fp64, precision):
+    """k = 40, c = 100: merge width p = 140 (C3-like), FP64 and FP32 paths."""
+    A = wide_fp64 if precision == pod.POD_F64 else wide_fp64.astype(np.float32)
+    kw = dict(k=40, c=100, seed=2007, theta_tol=1e-9, max_iter=5)
+    print(f"wide merge precision={precision}", flush=True)
+    tol = (1e-10, 1e-8, 1e-9) if precision == pod.POD_F64 else (1e-5, 1e-5, 1e-5)
+    _check_run_parity(A, kw, dict(kw, precision=precision), tol_s=tol[0], tol_a=tol[1], rows=False,
+                      tol_sin=tol[2])
+
+
+def test_wide_rows_and_rank(wide_fp64):
+    """Rows with a wide block (g up to 100 > 64) and r = 2k."""
+    kw = dict(k=30, r=60, c=90, w=300, seed=2008, theta_tol=1e-9, max_iter=4)
+    print("wide rows", flush=True)
+    _check_run_parity(wide_fp64, kw, dict(kw))
