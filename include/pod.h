@@ -145,6 +145,49 @@ pod_status pod_get_info(pod_ctx *ctx, pod_info *info);
 pod_status pod_get_indices(pod_ctx *ctx, int32_t iter, int32_t *cols, int32_t *col_counts, int32_t *g,
                            int32_t *rows, int32_t *row_counts, int32_t *h);
 
+/* ---------------------------------------------------------------------------
+ * Alg. 3, incremental POD: ISMA on each column block (with its final step),
+ * then BLOCK MERGE of the block's leading pairs [U_b Sigma_b] into the
+ * running (U, Sigma), truncated to r.  One pass over the matrix.
+ * ------------------------------------------------------------------------- */
+typedef struct pod_inc pod_inc;
+
+typedef struct {
+    int32_t blocks;        /* blocks merged                                     */
+    int64_t columns;       /* columns seen                                      */
+    double host_bytes;     /* bytes copied from host blocks                     */
+    double copy_ms;        /* summed host-to-device copy time of those blocks   */
+    double wall_ms;        /* wall time of pod_inc_add_host_blocks calls        */
+} pod_inc_info;
+
+/* prm holds the ISMA parameters of every block; prm->n is the largest block
+ * width, prm->lda and prm->block are ignored (block b, counted from 0 in the
+ * order added, is the Philox counter word 2 of its draws) and center_rows
+ * must be 0 (rows are centred over the whole matrix beforehand).  The merged
+ * state keeps r = prm->r (or k) columns; r + r must be <= 160.  Errors:
+ * POD_EINVAL, POD_ENOMEM, POD_EHIP. */
+pod_status pod_inc_init(pod_inc **inc, const pod_params *prm, void *stream);
+
+/* One block B (device, m x nb column-major, leading dimension ldb >= m,
+ * borrowed for the duration of the call), nb <= prm->n.  Syncs. */
+pod_status pod_inc_add_block(pod_inc *inc, const void *B_dev, int64_t nb, int64_t ldb);
+
+/* `count` blocks in host memory (B_host[i]: m x nb[i], ld m, storage as
+ * prm->a_dtype; pinned memory for the copies to run asynchronously).  The
+ * library copies them through two device buffers on a side stream, the copy
+ * of block i+1 overlapping the ISMA of block i.  Syncs. */
+pod_status pod_inc_add_host_blocks(pod_inc *inc, const void *const *B_host, const int64_t *nb, int32_t count);
+
+/* First k (<= rank) modes of the merged state: U_out (device, m x k, compute
+ * type, signed as in pod_project; nullable), sigma_out (device, k FP64;
+ * nullable), *k_out (host, nullable).  POD_ESTATE before any block.  Syncs. */
+pod_status pod_inc_result(pod_inc *inc, void *U_out, double *sigma_out, int32_t *k_out);
+
+/* Counters of the streamed blocks (host). */
+pod_status pod_inc_get_info(pod_inc *inc, pod_inc_info *info);
+
+void pod_inc_destroy(pod_inc *inc);
+
 /* Column squared norms computed at init (device -> host, n FP64).  Syncs. */
 pod_status pod_get_col_sqnorms(pod_ctx *ctx, double *nu_host);
 

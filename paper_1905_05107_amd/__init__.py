@@ -25,7 +25,8 @@ POD_CRIT_SUBSPACE, POD_CRIT_MODE = 0, 1
 # every symbol include/pod.h declares
 EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project", "pod_get_basis", "pod_get_info",
            "pod_get_indices", "pod_get_col_sqnorms", "pod_col_sqnorms", "pod_sample_size", "pod_destroy",
-           "pod_status_str", "pod_profile_enable", "pod_profile_read"]
+           "pod_status_str", "pod_profile_enable", "pod_profile_read", "pod_inc_init", "pod_inc_add_block",
+           "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy"]
 
 
 class PodError(RuntimeError):
@@ -50,6 +51,13 @@ class pod_info(ctypes.Structure):
         ("iter", ctypes.c_int32), ("rank", ctypes.c_int32), ("g", ctypes.c_int32), ("h", ctypes.c_int32),
         ("exhausted", ctypes.c_int32), ("flags", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
         ("total_sweeps", ctypes.c_int32), ("sin_theta", ctypes.c_double),
+    ]
+
+
+class pod_inc_info(ctypes.Structure):
+    _fields_ = [
+        ("blocks", ctypes.c_int32), ("columns", ctypes.c_int64), ("host_bytes", ctypes.c_double),
+        ("copy_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
     ]
 
 
@@ -81,6 +89,12 @@ def lib():
             "pod_status_str": (ctypes.c_char_p, [i32]),
             "pod_profile_enable": (i32, [i32]),
             "pod_profile_read": (i32, [P(i64), P(d)]),
+            "pod_inc_init": (i32, [P(vp), P(pod_params), vp]),
+            "pod_inc_add_block": (i32, [vp, vp, i64, i64]),
+            "pod_inc_add_host_blocks": (i32, [vp, P(vp), P(i64), i32]),
+            "pod_inc_result": (i32, [vp, vp, vp, P(i32)]),
+            "pod_inc_get_info": (i32, [vp, P(pod_inc_info)]),
+            "pod_inc_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -294,6 +308,89 @@ def isma(A, k: int, c: int, want_v: bool = True, n_iter: Optional[int] = None, *
         tol = kw.get("theta_tol", 1e-10)
         conv = inf.iter >= 2 and not math.isnan(inf.sin_theta) and inf.sin_theta < math.sin(min(tol, math.pi / 2))
         return Result(U, sig, V, inf.iter, sines, bool(inf.exhausted), conv, inf.flags)
+
+
+class Incremental:
+    """Alg. 3 over column blocks (pod_inc_*): ISMA on each block, BLOCK MERGE
+    of its leading pairs into the running (U, Sigma).
+
+    ``m``, ``max_block`` (largest block width) and the ISMA parameters are
+    fixed at construction; ``dtype`` is the storage of the blocks."""
+
+    def __init__(self, m: int, max_block: int, k: int, c: int, dtype="float32", r: int = 0, w: int = 0,
+                 precision: int = POD_F32, theta_tol: float = 1e-10, col_strategy: int = POD_COL_L2N,
+                 row_strategy: int = POD_ROW_L2, criterion: int = POD_CRIT_SUBSPACE,
+                 max_iter: Optional[int] = None, seed: int = 0, r_update: int = 0, stream=None):
+        import torch
+        code = POD_F64 if str(dtype).endswith("float64") else POD_F32
+        p = pod_params()
+        p.m, p.n, p.lda, p.a_dtype, p.precision = m, max_block, m, code, precision
+        p.k, p.r, p.c, p.w, p.r_update = k, r, c, w, r_update
+        p.col_strategy, p.row_strategy, p.criterion = col_strategy, row_strategy, criterion
+        p.center_rows = 0
+        p.max_iter = int(max_iter if max_iter is not None else max_block + 1)
+        p.theta_tol = float(theta_tol)
+        p.seed = int(seed) & (2**64 - 1)
+        self.params = p
+        self.m, self.k = m, k
+        self.code = code
+        self.precision = precision
+        self._torch_dtype = torch.float64 if code == POD_F64 else torch.float32
+        self.stream = _stream_handle(stream)
+        h = ctypes.c_void_p()
+        _check(lib().pod_inc_init(ctypes.byref(h), ctypes.byref(p), self.stream), "pod_inc_init")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().pod_inc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def add_block(self, B):
+        """A device block (m x nb, contiguous columns)."""
+        ptr, m, nb, ldb, code = _a_layout(B)
+        if m != self.m or code != self.code:
+            raise ValueError("block shape or dtype does not match")
+        _check(lib().pod_inc_add_block(self.h, ctypes.c_void_p(ptr), nb, ldb), "pod_inc_add_block")
+
+    def add_host_blocks(self, blocks):
+        """Host blocks: CPU tensors of shape (nb, m) (row j = column j of the
+        block), contiguous, ideally pinned; streamed through the device."""
+        ptrs = (ctypes.c_void_p * len(blocks))()
+        nbs = (ctypes.c_int64 * len(blocks))()
+        for i, b in enumerate(blocks):
+            if b.is_cuda or not b.is_contiguous() or b.dim() != 2 or b.shape[1] != self.m or b.dtype != self._torch_dtype:
+                raise ValueError("host blocks must be contiguous CPU tensors of shape (nb, m)")
+            ptrs[i] = b.data_ptr()
+            nbs[i] = b.shape[0]
+        _check(lib().pod_inc_add_host_blocks(self.h, ptrs, nbs, len(blocks)), "pod_inc_add_host_blocks")
+
+    def result(self):
+        import torch
+        dt = torch.float64 if self.precision == POD_F64 else torch.float32
+        Ut = torch.empty((self.k, self.m), dtype=dt, device="cuda")
+        sig = torch.empty(self.k, dtype=torch.float64, device="cuda")
+        kk = ctypes.c_int32()
+        _check(lib().pod_inc_result(self.h, ctypes.c_void_p(Ut.data_ptr()), ctypes.c_void_p(sig.data_ptr()),
+                                    ctypes.byref(kk)), "pod_inc_result")
+        return Ut[:kk.value].T, sig[:kk.value]
+
+    def info(self) -> pod_inc_info:
+        inf = pod_inc_info()
+        _check(lib().pod_inc_get_info(self.h, ctypes.byref(inf)), "pod_inc_get_info")
+        return inf
 
 
 POD_K = dict(colnorms=0, draw=1, gram=2, gram_reduce=3, chol=4, tall=5, svd=6, project=7, rr=8, sign=9)

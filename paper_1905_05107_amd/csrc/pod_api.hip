@@ -9,44 +9,10 @@
 
 #include <new>
 
-#include "pod_internal.h"
+#include "pod_ctx.h"
 
 using namespace pod;
 
-struct pod_ctx {
-    pod_params prm;
-    int32_t r = 0, pmax = 0;
-    hipStream_t st = nullptr;
-    void *A = nullptr;
-    size_t esz = 8;          // bytes per element of the compute type
-    DevState *ds = nullptr;  // device
-    DevState hs{};           // host copy after the last sync
-    double *nu = nullptr;
-    uint64_t *wq = nullptr;
-    uint8_t *inS = nullptr;
-    int32_t *cols = nullptr, *ccnt = nullptr, *col_log = nullptr, *ccnt_log = nullptr, *col_log_off = nullptr;
-    int32_t *forced = nullptr;
-    double *rho = nullptr, *Vt = nullptr;  // row weights (m), right factor of the new block (pmax x pmax)
-    uint64_t *wr = nullptr;
-    int32_t *rows = nullptr, *rcnt = nullptr, *row_log = nullptr, *rcnt_log = nullptr;
-    void *U[2] = {nullptr, nullptr};
-    double *sig[2] = {nullptr, nullptr};
-    int cur = 0;
-    double *part = nullptr, *G = nullptr, *R1 = nullptr, *R2 = nullptr, *work = nullptr;
-    double *ws = nullptr;    // small-kernel matrices when pmax > 64
-    void *Tc = nullptr, *Y = nullptr;
-    int32_t nblk = 0;
-    double *Bpart = nullptr, *B = nullptr, *GB = nullptr, *UB = nullptr, *sigB = nullptr;
-    void *Zc = nullptr;
-    double *signv = nullptr;
-    int64_t *signi = nullptr;
-    int32_t nsplit = 0;
-    int pending = 0;         // a draw waits for its merge
-    int32_t merges = 0;      // merges launched
-    int exhausted = 0;       // known on the host
-    int failed = 0;          // a HIP error happened: only destroy is allowed
-    int32_t forced_g = -1;   // replay of the next draw
-};
 
 namespace {
 
@@ -137,6 +103,55 @@ GemmDesc plain_desc(pod_ctx *ctx, const void *Y)
     return d;
 }
 
+// The merge sequence of Alg. 2 on X0 = [U | source(:, cols)] (gd), the new
+// block weighted by sigma2 (nullable: 1) or, with use_vt, by its right factor
+// Vt (computed here from the pass-1 Gram when block_eig_mode1).
+pod_status merge_launch(pod_ctx *ctx, const GemmDesc &gd, const double *sigma2, bool use_vt, bool block_eig_mode1)
+{
+    const int32_t pm = ctx->pmax;
+    const pod_params &p = ctx->prm;
+    // pass 1: G0 = X0^T X0, X0 = [U | A(:, I_c)] gathered on the fly
+    POD_HIP(launch_gram_partial(gd, ctx->ds, -1, pm, ctx->part, ctx->nblk, ctx->st));
+    POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -1, ctx->G, ctx->st));
+    SmallArgs sa;
+    sa.ds = ctx->ds;
+    sa.sigma = ctx->sig[ctx->cur];
+    sa.sigma_new = ctx->sig[ctx->cur ^ 1];
+    sa.G = ctx->G;
+    sa.R1 = ctx->R1;
+    sa.R2 = ctx->R2;
+    sa.Tc = ctx->Tc;
+    sa.work = ctx->work;
+    sa.pmax = pm;
+    sa.r = ctx->r;
+    sa.k = p.k;
+    sa.prec = p.precision;
+    sa.criterion = p.criterion;
+    sa.urnd = unit_roundoff(p.precision);
+    sa.Vt = ctx->Vt;
+    sa.use_vt = use_vt;
+    sa.ws = ctx->ws;
+    sa.sigma2 = sigma2;
+    if (block_eig_mode1) {
+        // the new block truncated to its leading r_update directions
+        BlockEigArgs ba = block_eig_args(ctx, 1);
+        POD_HIP(launch_block_eig(ba, ctx->st));
+    }
+    POD_HIP(launch_chol_first(sa, ctx->st));
+    // Q1 = X0 T1 (T1 = P R1^-1)
+    POD_HIP(launch_gemm_tall(gd, ctx->ds, -1, -2, pm, pm, ctx->Tc, pm, ctx->Y, ctx->st));
+    // pass 2: G2 = Q1^T Q1
+    GemmDesc yd = plain_desc(ctx, ctx->Y);
+    POD_HIP(launch_gram_partial(yd, ctx->ds, -2, pm, ctx->part, ctx->nblk, ctx->st));
+    POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -2, ctx->G, ctx->st));
+    POD_HIP(launch_svd_merge(sa, ctx->st));
+    // U_new = Q1 R2^-1 U_R(:, 0:r')
+    POD_HIP(launch_gemm_tall(yd, ctx->ds, -2, -3, pm, ctx->r, ctx->Tc, pm, ctx->U[ctx->cur ^ 1], ctx->st));
+    ctx->cur ^= 1;
+    ctx->merges += 1;
+    return POD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -189,6 +204,24 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
 {
     if (!out || !prm || !A_dev) return POD_EINVAL;
     *out = nullptr;
+    pod_ctx *ctx = nullptr;
+    pod_status s = ctx_create(&ctx, prm, stream);
+    if (s != POD_OK) return s;
+    s = ctx_bind(ctx, A_dev, prm->n, prm->lda, prm->block);
+    if (s != POD_OK) {
+        pod_destroy(ctx);
+        return s;
+    }
+    *out = ctx;
+    return POD_OK;
+}
+
+}  // extern "C"
+
+pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
+{
+    if (!out || !prm) return POD_EINVAL;
+    *out = nullptr;
     const pod_params &p = *prm;
     if (p.m < 1 || p.n < 1 || p.lda < p.m || p.n > 0x7fffffff || p.m > ((int64_t)1 << 40)) return POD_EINVAL;
     if (p.a_dtype != POD_F64 && p.a_dtype != POD_F32) return POD_EINVAL;
@@ -213,7 +246,7 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
     ctx->r = r;
     ctx->pmax = pmax;
     ctx->st = (hipStream_t)stream;
-    ctx->A = A_dev;
+    ctx->n_cap = p.n;
     ctx->esz = (p.precision == POD_F64) ? 8 : 4;
     const int64_t m = p.m, n = p.n;
     const int32_t cap_iter = (int32_t)((p.max_iter < n) ? p.max_iter : n) + 1;
@@ -271,7 +304,41 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
     }
     DevState h{};
     h.sin_theta = __builtin_nan("");
-    POD_HIP(hipMemcpyAsync(ctx->ds, &h, sizeof(DevState), hipMemcpyHostToDevice, ctx->st));
+    ctx->hs = h;
+    e = hipMemcpyAsync(ctx->ds, &h, sizeof(DevState), hipMemcpyHostToDevice, ctx->st);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->sig[0], 0, sizeof(double) * r, ctx->st);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->sig[1], 0, sizeof(double) * r, ctx->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+    if (e != hipSuccess) {
+        free_all(ctx);
+        delete ctx;
+        return POD_EHIP;
+    }
+    *out = ctx;
+    return POD_OK;
+}
+
+pod_status pod::ctx_bind(pod_ctx *ctx, void *A_dev, int64_t n, int64_t lda, uint64_t block)
+{
+    if (!ctx || !A_dev || n < 1 || n > ctx->n_cap || lda < ctx->prm.m) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    ctx->prm.n = n;
+    ctx->prm.lda = lda;
+    ctx->prm.block = block;
+    ctx->A = A_dev;
+    ctx->cur = 0;
+    ctx->pending = 0;
+    ctx->merges = 0;
+    ctx->exhausted = 0;
+    ctx->forced_g = -1;
+    const pod_params &p = ctx->prm;
+    const int64_t m = p.m;
+    const int32_t r = ctx->r;
+    const int32_t cap_iter = (int32_t)((p.max_iter < n) ? p.max_iter : n) + 1;
+    DevState h{};
+    h.sin_theta = __builtin_nan("");
+    ctx->hs = h;   // the copy reads ctx->hs, which outlives the call
+    POD_HIP(hipMemcpyAsync(ctx->ds, &ctx->hs, sizeof(DevState), hipMemcpyHostToDevice, ctx->st));
     POD_HIP(hipMemsetAsync(ctx->inS, 1, (size_t)n, ctx->st));
     POD_HIP(hipMemsetAsync(ctx->col_log_off, 0, sizeof(int32_t) * (cap_iter + 1), ctx->st));
     POD_HIP(hipMemsetAsync(ctx->sig[0], 0, sizeof(double) * r, ctx->st));
@@ -289,9 +356,10 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
     }
     POD_HIP(launch_col_sqnorms(A_dev, p.a_dtype, m, n, p.lda, ctx->nu, ctx->st));
     POD_HIP(launch_quantize(ctx->nu, n, ctx->wq, ctx->ds, 0, ctx->st));
-    *out = ctx;
     return POD_OK;
 }
+
+extern "C" {
 
 pod_status pod_sample(pod_ctx *ctx, int32_t *g_out, int32_t *h_out)
 {
@@ -361,48 +429,10 @@ pod_status pod_merge(pod_ctx *ctx)
     if (!ctx) return POD_EINVAL;
     if (ctx->failed) return POD_EHIP;
     if (!ctx->pending) return POD_ESTATE;
-    const int32_t pm = ctx->pmax;
     const pod_params &p = ctx->prm;
-    // pass 1: G0 = X0^T X0, X0 = [U | A(:, I_c)] gathered on the fly
-    GemmDesc gd = gather_desc(ctx);
-    POD_HIP(launch_gram_partial(gd, ctx->ds, -1, pm, ctx->part, ctx->nblk, ctx->st));
-    POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -1, ctx->G, ctx->st));
-    SmallArgs sa;
-    sa.ds = ctx->ds;
-    sa.sigma = ctx->sig[ctx->cur];
-    sa.sigma_new = ctx->sig[ctx->cur ^ 1];
-    sa.G = ctx->G;
-    sa.R1 = ctx->R1;
-    sa.R2 = ctx->R2;
-    sa.Tc = ctx->Tc;
-    sa.work = ctx->work;
-    sa.pmax = pm;
-    sa.r = ctx->r;
-    sa.k = p.k;
-    sa.prec = p.precision;
-    sa.criterion = p.criterion;
-    sa.urnd = unit_roundoff(p.precision);
-    sa.Vt = ctx->Vt;
-    sa.use_vt = (p.w > 0 || p.r_update > 0);
-    sa.ws = ctx->ws;
-    if (p.w == 0 && p.r_update > 0) {
-        // the new block truncated to its leading r_update directions
-        BlockEigArgs ba = block_eig_args(ctx, 1);
-        POD_HIP(launch_block_eig(ba, ctx->st));
-    }
-    POD_HIP(launch_chol_first(sa, ctx->st));
-    // Q1 = X0 T1 (T1 = P R1^-1)
-    POD_HIP(launch_gemm_tall(gd, ctx->ds, -1, -2, pm, pm, ctx->Tc, pm, ctx->Y, ctx->st));
-    // pass 2: G2 = Q1^T Q1
-    GemmDesc yd = plain_desc(ctx, ctx->Y);
-    POD_HIP(launch_gram_partial(yd, ctx->ds, -2, pm, ctx->part, ctx->nblk, ctx->st));
-    POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -2, ctx->G, ctx->st));
-    POD_HIP(launch_svd_merge(sa, ctx->st));
-    // U_new = Q1 R2^-1 U_R(:, 0:r')
-    POD_HIP(launch_gemm_tall(yd, ctx->ds, -2, -3, pm, ctx->r, ctx->Tc, pm, ctx->U[ctx->cur ^ 1], ctx->st));
-    ctx->cur ^= 1;
+    pod_status s = merge_launch(ctx, gather_desc(ctx), nullptr, p.w > 0 || p.r_update > 0, p.w == 0 && p.r_update > 0);
+    if (s != POD_OK) return s;
     ctx->pending = 0;
-    ctx->merges += 1;
     return POD_OK;
 }
 
@@ -424,6 +454,13 @@ pod_status pod_converged(pod_ctx *ctx, int32_t *done, double *sin_theta_max)
 
 pod_status pod_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out)
 {
+    return ctx_project(ctx, U_out, sigma_out, V_out, 0);
+}
+
+}  // extern "C"
+
+pod_status pod::ctx_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out, int32_t kout)
+{
     if (!ctx || !U_out || !sigma_out) return POD_EINVAL;
     if (ctx->failed) return POD_EHIP;
     if (ctx->pending) return POD_ESTATE;
@@ -431,7 +468,8 @@ pod_status pod_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out
     if (s != POD_OK) return s;
     const int32_t rs = ctx->hs.rs;
     if (rs < 1) return POD_ESTATE;
-    const int32_t k = (ctx->prm.k < rs) ? ctx->prm.k : rs;
+    int32_t k = (ctx->prm.k < rs) ? ctx->prm.k : rs;
+    if (kout > 0) k = (kout < rs) ? kout : rs;
     const pod_params &p = ctx->prm;
     ProjArgs pa;
     pa.prec = p.precision;
@@ -472,6 +510,31 @@ pod_status pod_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out
     if (ctx->hs.flags & FLAG_NOCONV) return POD_ENOCONV;
     return POD_OK;
 }
+
+pod_status pod::ctx_merge_basis(pod_ctx *ctx, const void *Ub, const double *sb, int32_t rb)
+{
+    if (!ctx || !Ub || !sb || rb < 1 || rb > ctx->n_cap || rb > ctx->prm.c) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (ctx->pending) return POD_ESTATE;
+    const pod_params &p = ctx->prm;
+    const int32_t first = (ctx->merges == 0);
+    POD_HIP(launch_basis_state(ctx->ds, rb, ctx->r, first, ctx->cols, ctx->st));
+    if (first) {
+        // the first block is the state (Alg. 3)
+        const int32_t rr = (rb < ctx->r) ? rb : ctx->r;
+        POD_HIP(hipMemcpyAsync(ctx->U[ctx->cur], Ub, (size_t)p.m * rr * ctx->esz, hipMemcpyDeviceToDevice, ctx->st));
+        POD_HIP(hipMemcpyAsync(ctx->sig[ctx->cur], sb, sizeof(double) * rr, hipMemcpyDeviceToDevice, ctx->st));
+        ctx->merges = 1;
+        return POD_OK;
+    }
+    GemmDesc gd = gather_desc(ctx);
+    gd.A = Ub;
+    gd.a_dtype = p.precision == POD_F64 ? POD_F64 : POD_F32;
+    gd.lda = p.m;
+    return merge_launch(ctx, gd, sb, false, false);
+}
+
+extern "C" {
 
 pod_status pod_get_basis(pod_ctx *ctx, void *U_out, double *sigma_out, int32_t *rank_out)
 {

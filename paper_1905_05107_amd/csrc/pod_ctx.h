@@ -1,0 +1,60 @@
+// pod_ctx.h -- the context behind the opaque pod_ctx handle of the C ABI and
+// the library-internal calls shared by pod_api.hip and pod_incremental.hip.
+#pragma once
+
+#include "../../include/pod.h"
+#include "pod_internal.h"
+
+struct pod_ctx {
+    int64_t n_cap = 0;       // columns the buffers were sized for
+    pod_params prm;
+    int32_t r = 0, pmax = 0;
+    hipStream_t st = nullptr;
+    void *A = nullptr;
+    size_t esz = 8;          // bytes per element of the compute type
+    pod::DevState *ds = nullptr;  // device
+    pod::DevState hs{};           // host copy after the last sync
+    double *nu = nullptr;
+    uint64_t *wq = nullptr;
+    uint8_t *inS = nullptr;
+    int32_t *cols = nullptr, *ccnt = nullptr, *col_log = nullptr, *ccnt_log = nullptr, *col_log_off = nullptr;
+    int32_t *forced = nullptr;
+    double *rho = nullptr, *Vt = nullptr;  // row weights (m), right factor of the new block (pmax x pmax)
+    uint64_t *wr = nullptr;
+    int32_t *rows = nullptr, *rcnt = nullptr, *row_log = nullptr, *rcnt_log = nullptr;
+    void *U[2] = {nullptr, nullptr};
+    double *sig[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *part = nullptr, *G = nullptr, *R1 = nullptr, *R2 = nullptr, *work = nullptr;
+    double *ws = nullptr;    // small-kernel matrices when pmax > 64
+    void *Tc = nullptr, *Y = nullptr;
+    int32_t nblk = 0;
+    double *Bpart = nullptr, *B = nullptr, *GB = nullptr, *UB = nullptr, *sigB = nullptr;
+    void *Zc = nullptr;
+    double *signv = nullptr;
+    int64_t *signi = nullptr;
+    int32_t nsplit = 0;
+    int pending = 0;         // a draw waits for its merge
+    int32_t merges = 0;      // merges launched
+    int exhausted = 0;       // known on the host
+    int failed = 0;          // a HIP error happened: only destroy is allowed
+    int32_t forced_g = -1;   // replay of the next draw
+};
+
+namespace pod {
+
+// Validate `prm` (prm->n = the largest number of columns the context will
+// see) and allocate every buffer; no access to A.
+pod_status ctx_create(pod_ctx **out, const pod_params *prm, void *stream);
+// Start a fresh ISMA run on A (m x n, n <= n_cap, leading dimension lda):
+// reset the sampling state, optionally centre the rows, and compute the
+// column norms and weights.  `block` is the Philox counter word 2.
+pod_status ctx_bind(pod_ctx *ctx, void *A, int64_t n, int64_t lda, uint64_t block);
+// Final step of Alg. 1 writing kout <= rank Rayleigh-Ritz pairs.
+pod_status ctx_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out, int32_t kout);
+// BLOCK MERGE of the context's state with an external basis:
+// [U Sigma | Ub diag(sb)] (Ub m x rb in the compute type, ld m; sb device FP64),
+// truncated to r.  The first call on an empty state takes (Ub, sb) as is.
+pod_status ctx_merge_basis(pod_ctx *ctx, const void *Ub, const double *sb, int32_t rb);
+
+}  // namespace pod

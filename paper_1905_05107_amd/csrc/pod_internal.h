@@ -135,6 +135,10 @@ struct RowDrawArgs {
     DevState *ds;
 };
 hipError_t launch_draw_rows(const RowDrawArgs &a, hipStream_t st);
+// Device state for a merge with an external basis of rb columns (Alg. 3):
+// the first one becomes the state (rs = min(rb, r)); later ones are the new
+// block, gathered through cols = 0..rb-1.
+hipError_t launch_basis_state(DevState *ds, int32_t rb, int32_t r, int32_t first, int32_t *cols, hipStream_t st);
 
 struct GemmDesc {
     int32_t prec;         // POD_F64 or POD_F32 (compute type)
@@ -164,6 +168,7 @@ struct SmallArgs {
     const double *Vt;      // right factor of the new block (g x ru, ld pmax) when use_vt
     int32_t use_vt;
     const double *sigma;   // current Sigma (rs)
+    const double *sigma2;  // weights of the new block's columns (nullable: 1)
     double *sigma_new;     // Sigma after the merge (r)
     const double *G;       // reduced Gram (pmax x pmax, ld pmax)
     double *R1;            // (pmax x pmax)

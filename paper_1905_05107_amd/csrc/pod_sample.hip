@@ -566,4 +566,33 @@ hipError_t launch_draw_rows(const RowDrawArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_basis_state(DevState *ds, int32_t rb, int32_t r, int32_t first,
+                                                     int32_t *cols)
+{
+    for (int i = threadIdx.x; i < rb; i += 256) cols[i] = i;
+    if (threadIdx.x == 0) {
+        if (first) {
+            const int32_t rr = (rb < r) ? rb : r;
+            ds->rs = rr;
+            ds->it = 1;
+            ds->g = 0;
+            ds->p0 = rr;
+            ds->p = rr;
+        } else {
+            ds->g = rb;
+            ds->p0 = ds->rs + rb;
+            ds->p = ds->rs + rb;
+        }
+        ds->h = 0;
+        ds->exhausted = 0;
+        ds->s_empty = 0;
+    }
+}
+
+hipError_t launch_basis_state(DevState *ds, int32_t rb, int32_t r, int32_t first, int32_t *cols, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_basis_state, dim3(1), dim3(256), 0, st, ds, rb, r, first, cols);
+    return hipGetLastError();
+}
+
 }  // namespace pod

@@ -106,7 +106,9 @@ __device__ __forceinline__ void store_c(void *base, int prec, int64_t idx, doubl
 
 // ---------------------------------------------------------------------------
 // CholeskyQR pass 1 factor: G1 = P^T G0 P with P = diag(Sigma_r, I_g) (the
-// basis block enters the merge weighted by its singular values, Alg. 2),
+// basis block enters the merge weighted by its singular values, Alg. 2; a
+// merged external basis by its own, Alg. 3; a row-sampled block by its right
+// factor, P = blkdiag(Sigma_r, Vt)),
 // R1 = chol(G1) (shifted by s = p u tr(G1) if a pivot breaks down),
 // T1 = P R1^-1 written in the compute type for the tall GEMM Y = X0 T1.
 // ---------------------------------------------------------------------------
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
     double *tmp = S + pm * pm;          // p doubles
     double *GP = tmp + pm;              // G0 P (p0 x p), dense right factor only
     if (threadIdx.x == 0) sbad = 0;
-    for (int i = threadIdx.x; i < p; i += NT) sP[i] = (i < rs) ? a.sigma[i] : 1.0;
+    for (int i = threadIdx.x; i < p; i += NT) sP[i] = (i < rs) ? a.sigma[i] : (a.sigma2 ? a.sigma2[i - rs] : 1.0);
     __syncthreads();
     if (a.use_vt) {
         // P = blkdiag(Sigma_r, Vt): GP = G0 P, then G1 = P^T GP into a.work

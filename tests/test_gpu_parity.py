@@ -323,3 +323,57 @@ def test_wide_rows_and_rank(wide_fp64):
     kw = dict(k=30, r=60, c=90, w=300, seed=2008, theta_tol=1e-9, max_iter=4)
     print("wide rows", flush=True)
     _check_run_parity(wide_fp64, kw, dict(kw))
+
+
+# ------------------------------------------------------------------ Alg. 3 (incremental over column blocks)
+
+def _inc_check(A, kw, blocks, gpu_kw, host: bool, tol_s, tol_a):
+    from oracle.isma import incremental
+    Uk, sk, _, _ = incremental(A, IsmaParams(**kw), blocks, elem_bytes=A.dtype.itemsize)
+    width = max(j1 - j0 for j0, j1 in blocks)
+    m = A.shape[0]
+    with pod.Incremental(m, width, dtype=str(A.dtype), **gpu_kw) as inc:
+        if host:
+            hb = [torch.from_numpy(np.ascontiguousarray(A[:, j0:j1].T)).pin_memory() for j0, j1 in blocks]
+            inc.add_host_blocks(hb)
+            info = inc.info()
+            assert info.blocks == len(blocks) and info.columns == A.shape[1]
+            assert info.host_bytes == A.size * A.dtype.itemsize
+        else:
+            for j0, j1 in blocks:
+                inc.add_block(_dev(A[:, j0:j1]))
+        U, s = inc.result()
+    U, s = U.cpu().numpy(), s.cpu().numpy()
+    rel = np.max(np.abs(s - sk) / sk)
+    ang = _angles(Uk, U)
+    print(f"  blocks={len(blocks)} sigma_rel={rel:.3e} angle={ang:.3e}", flush=True)
+    assert U.shape == Uk.shape
+    assert rel <= tol_s
+    assert ang <= tol_a
+    for i in range(U.shape[1]):       # sign convention
+        j = int(np.argmax(np.abs(U[:, i])))
+        assert U[j, i] > 0
+
+
+def test_incremental_device_blocks_fp64(c1):
+    from oracle.isma import block_bounds
+    kw = _c1_params(theta_tol=1e-9)
+    print("incremental fp64 device blocks", flush=True)
+    _inc_check(c1.A, kw, block_bounds(c1.A.shape[1], 4), dict(kw, precision=pod.POD_F64), False, 1e-10, 1e-8)
+
+
+def test_incremental_host_blocks_ragged_fp32(waves_small):
+    """Pinned host blocks of 128 columns and a 16-column tail, FP32 path."""
+    from oracle.isma import block_bounds
+    A = waves_small
+    kw = dict(k=20, c=40, seed=2004, theta_tol=1e-5, max_iter=30)
+    print("incremental fp32 host blocks", flush=True)
+    _inc_check(A, kw, block_bounds(A.shape[1], width=128), dict(kw, precision=pod.POD_F32), True, 1e-5, 1e-5)
+
+
+def test_incremental_rows_r_above_k(c1):
+    """Blocks sampled with rows, r = 2k."""
+    from oracle.isma import block_bounds
+    kw = _c1_params(w=20, r=20, theta_tol=1e-9)
+    print("incremental rows", flush=True)
+    _inc_check(c1.A, kw, block_bounds(c1.A.shape[1], 3), dict(kw, precision=pod.POD_F64), False, 1e-10, 1e-8)
