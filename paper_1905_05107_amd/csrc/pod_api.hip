@@ -36,11 +36,10 @@ pod_status sync_state(pod_ctx *ctx)
 {
     POD_HIP(hipMemcpyAsync(&ctx->hs, ctx->ds, sizeof(DevState), hipMemcpyDeviceToHost, ctx->st));
     POD_HIP(hipStreamSynchronize(ctx->st));
-    // a merge launched on an exhausted draw is a no-op on the device
-    if (ctx->hs.it < ctx->merges) {
-        ctx->cur ^= 1;
-        ctx->merges = ctx->hs.it;
-    }
+    // the current basis is U[it & 1]; a merge launched on an exhausted draw
+    // is a no-op on the device
+    ctx->cur = ctx->hs.it & 1;
+    if (ctx->hs.it < ctx->merges) ctx->merges = ctx->hs.it;
     if (ctx->hs.exhausted || (ctx->hs.s_empty && !ctx->pending)) ctx->exhausted = 1;
     return POD_OK;
 }
@@ -63,7 +62,8 @@ GemmDesc gather_desc(pod_ctx *ctx)
     d.prec = ctx->prm.precision;
     d.a_dtype = ctx->prm.a_dtype;
     d.m = ctx->prm.m;
-    d.U = ctx->U[ctx->cur];
+    d.U = ctx->U[0];
+    d.U1 = ctx->U[1];
     d.A = ctx->A;
     d.lda = ctx->prm.lda;
     d.cols = ctx->cols;
@@ -115,8 +115,8 @@ pod_status merge_launch(pod_ctx *ctx, const GemmDesc &gd, const double *sigma2, 
     POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -1, ctx->G, ctx->st));
     SmallArgs sa;
     sa.ds = ctx->ds;
-    sa.sigma = ctx->sig[ctx->cur];
-    sa.sigma_new = ctx->sig[ctx->cur ^ 1];
+    sa.sig0 = ctx->sig[0];
+    sa.sig1 = ctx->sig[1];
     sa.G = ctx->G;
     sa.R1 = ctx->R1;
     sa.R2 = ctx->R2;
@@ -139,15 +139,15 @@ pod_status merge_launch(pod_ctx *ctx, const GemmDesc &gd, const double *sigma2, 
     }
     POD_HIP(launch_chol_first(sa, ctx->st));
     // Q1 = X0 T1 (T1 = P R1^-1)
-    POD_HIP(launch_gemm_tall(gd, ctx->ds, -1, -2, pm, pm, ctx->Tc, pm, ctx->Y, ctx->st));
+    POD_HIP(launch_gemm_tall(gd, ctx->ds, -1, -2, pm, pm, ctx->Tc, pm, ctx->Y, nullptr, ctx->st));
     // pass 2: G2 = Q1^T Q1
     GemmDesc yd = plain_desc(ctx, ctx->Y);
     POD_HIP(launch_gram_partial(yd, ctx->ds, -2, pm, ctx->part, ctx->nblk, ctx->st));
     POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -2, ctx->G, ctx->st));
     POD_HIP(launch_svd_merge(sa, ctx->st));
     // U_new = Q1 R2^-1 U_R(:, 0:r')
-    POD_HIP(launch_gemm_tall(yd, ctx->ds, -2, -3, pm, ctx->r, ctx->Tc, pm, ctx->U[ctx->cur ^ 1], ctx->st));
-    ctx->cur ^= 1;
+    // (svd_merge advanced the merge count: U[it & 1] is the new basis)
+    POD_HIP(launch_gemm_tall(yd, ctx->ds, -2, -3, pm, ctx->r, ctx->Tc, pm, ctx->U[0], ctx->U[1], ctx->st));
     ctx->merges += 1;
     return POD_OK;
 }
@@ -390,9 +390,9 @@ pod_status pod_sample(pod_ctx *ctx, int32_t *g_out, int32_t *h_out)
     const pod_params &p = ctx->prm;
     if (p.w > 0) {
         // SAMPLE AND SCALE UNIQUE ROWS, then the right factor of the new block
-        const void *Uls = (p.row_strategy == POD_ROW_LS) ? ctx->U[ctx->cur] : nullptr;
-        POD_HIP(launch_row_sqnorms(ctx->A, p.a_dtype, p.m, p.lda, ctx->cols, Uls, p.precision, p.k, ctx->ds, ctx->rho,
-                                   ctx->st));
+        const bool ls = (p.row_strategy == POD_ROW_LS);
+        POD_HIP(launch_row_sqnorms(ctx->A, p.a_dtype, p.m, p.lda, ctx->cols, ls ? ctx->U[0] : nullptr,
+                                   ls ? ctx->U[1] : nullptr, p.precision, p.k, ctx->ds, ctx->rho, ctx->st));
         POD_HIP(launch_quantize(ctx->rho, p.m, ctx->wr, ctx->ds, 1, ctx->st));
         RowDrawArgs ra;
         ra.wr = ctx->wr;
@@ -500,7 +500,7 @@ pod_status pod::ctx_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *
     POD_HIP(launch_rr_small(ra, ctx->st));
     GemmDesc ud = plain_desc(ctx, ctx->U[ctx->cur]);
     ud.guard = 0;
-    POD_HIP(launch_gemm_tall(ud, ctx->ds, rs, k, rs, k, ctx->Zc, rs, U_out, ctx->st));
+    POD_HIP(launch_gemm_tall(ud, ctx->ds, rs, k, rs, k, ctx->Zc, rs, U_out, nullptr, ctx->st));
     POD_HIP(hipMemcpyAsync(sigma_out, ctx->sigB, sizeof(double) * k, hipMemcpyDeviceToDevice, ctx->st));
     if (V_out) POD_HIP(launch_rr_v(ctx->B, p.n, rs, k, ctx->UB, ctx->sigB, p.precision, V_out, ctx->st));
     POD_HIP(launch_sign_fix(p.precision, U_out, p.m, k, V_out, p.n, ctx->signv, ctx->signi, ctx->st));
@@ -521,9 +521,10 @@ pod_status pod::ctx_merge_basis(pod_ctx *ctx, const void *Ub, const double *sb, 
     POD_HIP(launch_basis_state(ctx->ds, rb, ctx->r, first, ctx->cols, ctx->st));
     if (first) {
         // the first block is the state (Alg. 3)
+        // (the merge count becomes 1: the current basis is U[1])
         const int32_t rr = (rb < ctx->r) ? rb : ctx->r;
-        POD_HIP(hipMemcpyAsync(ctx->U[ctx->cur], Ub, (size_t)p.m * rr * ctx->esz, hipMemcpyDeviceToDevice, ctx->st));
-        POD_HIP(hipMemcpyAsync(ctx->sig[ctx->cur], sb, sizeof(double) * rr, hipMemcpyDeviceToDevice, ctx->st));
+        POD_HIP(hipMemcpyAsync(ctx->U[1], Ub, (size_t)p.m * rr * ctx->esz, hipMemcpyDeviceToDevice, ctx->st));
+        POD_HIP(hipMemcpyAsync(ctx->sig[1], sb, sizeof(double) * rr, hipMemcpyDeviceToDevice, ctx->st));
         ctx->merges = 1;
         return POD_OK;
     }

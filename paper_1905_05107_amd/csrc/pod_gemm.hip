@@ -25,6 +25,7 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <typename TC> struct SrcT {
     const TC *U;          // basis, ld = m
+    const TC *U1;         // second basis buffer (nullable): used when the merge count is odd
     const void *A;        // snapshot matrix
     int64_t lda;
     const int32_t *cols;
@@ -146,7 +147,7 @@ template <typename TC> static bool vec_ok(const SrcT<TC> &s, int64_t m)
     const size_t esz = sizeof(TC);
     bool ok = ((m * esz) % 16 == 0);
     if (s.gather) {
-        ok = ok && ((uintptr_t)s.U % 16 == 0);
+        ok = ok && ((uintptr_t)s.U % 16 == 0) && ((uintptr_t)s.U1 % 16 == 0);
         const size_t ae = s.a_f64 ? 8 : 4;
         ok = ok && ((uintptr_t)s.A % 16 == 0) && ((s.lda * ae) % 16 == 0);
     } else {
@@ -178,6 +179,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
     if (s.guard && ds->exhausted) return;
     const int P = sel_count(ds, which_p);
     s.rs = ds->rs;
+    if (s.U1 && (ds->it & 1)) s.U = s.U1;
     const int PP = (P + 15) & ~15;
     const int NT16 = PP / 16;
     const int npairs = NT16 * (NT16 + 1) / 2;
@@ -262,6 +264,7 @@ template <typename TC> static SrcT<TC> make_src(const GemmDesc &d)
 {
     SrcT<TC> s;
     s.U = reinterpret_cast<const TC *>(d.U);
+    s.U1 = reinterpret_cast<const TC *>(d.U1);
     s.A = d.A;
     s.lda = d.lda;
     s.cols = d.cols;
@@ -320,13 +323,15 @@ constexpr size_t TALL_T_LDS = 112 * 1024;  // largest T staged in LDS
 template <typename TC, int ITEMS, bool TG>
 __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
                                                    int sel_out, int pmax_in, int pmax_out, const TC *__restrict__ T,
-                                                   int ldt, TC *__restrict__ Yout, int vec)
+                                                   int ldt, TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec)
 {
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
     if (s.guard && ds->exhausted) return;
+    if (Yout1 && (ds->it & 1)) Yout = Yout1;
     const int pin = sel_count(ds, sel_in), pout = sel_count(ds, sel_out);
     s.rs = ds->rs;
+    if (s.U1 && (ds->it & 1)) s.U = s.U1;
     const int PI = (pin + 15) & ~15, PO = (pout + 15) & ~15;
     TC *Xs = reinterpret_cast<TC *>(lds_raw);        // pmax_in x LDSR
     TC *Ts = Xs + pmax_in * LDSR;                    // PI x PO, row k at Ts + k * PO (when !TG)
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const 
 
 template <typename TC, int ITEMS, bool TG>
 static void tall_launch(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out, int PI, int PO,
-                        const void *T, int32_t ldt, void *Yout, unsigned nb, hipStream_t st)
+                        const void *T, int32_t ldt, void *Yout, void *Yout1, unsigned nb, hipStream_t st)
 {
     const SrcT<TC> s = make_src<TC>(d);
     const size_t lds = (size_t)(PI * LDSR + (TG ? 0 : PI * PO)) * sizeof(TC);
@@ -390,11 +395,11 @@ static void tall_launch(const GemmDesc &d, const DevState *ds, int32_t which_in,
         attr = true;
     }
     hipLaunchKernelGGL((k_gemm_tall<TC, ITEMS, TG>), dim3(nb), dim3(256), lds, st, s, d.m, ds, which_in, which_out,
-                       PI, PO, (const TC *)T, ldt, (TC *)Yout, (int)vec_ok(s, d.m));
+                       PI, PO, (const TC *)T, ldt, (TC *)Yout, (TC *)Yout1, (int)vec_ok(s, d.m));
 }
 
 hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
-                            int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout,
+                            int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout, void *Yout1,
                             hipStream_t st)
 {
     if (pin_max > PMAX_WIDE || pout_max > PMAX_WIDE) return hipErrorInvalidValue;
@@ -405,14 +410,14 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
     const bool wide = PI > 64;
     if (d.prec == POD_F64) {
         const bool tg = (size_t)PI * PO * sizeof(double) > TALL_T_LDS;
-        if (!wide) tall_launch<double, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
-        else if (!tg) tall_launch<double, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
-        else tall_launch<double, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
+        if (!wide) tall_launch<double, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
+        else if (!tg) tall_launch<double, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
+        else tall_launch<double, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
     } else {
         const bool tg = (size_t)PI * PO * sizeof(float) > TALL_T_LDS;
-        if (!wide) tall_launch<float, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
-        else if (!tg) tall_launch<float, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
-        else tall_launch<float, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, nb, st);
+        if (!wide) tall_launch<float, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
+        else if (!tg) tall_launch<float, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
+        else tall_launch<float, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
     }
     return hipGetLastError();
 }
@@ -456,6 +461,7 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
     const int ncol = (n - c0 < PCB) ? (int)(n - c0) : PCB;
     SrcT<TC> su;
     su.U = nullptr;
+    su.U1 = nullptr;
     su.A = nullptr;
     su.lda = 0;
     su.cols = nullptr;

@@ -120,8 +120,8 @@ hipError_t launch_draw_cols(const DrawArgs &a, hipStream_t st);
 // Row squared norms of the gathered block D = A(:, cols[0..g)) (rows of D in
 // ascending column order, FP64 fma chain), g read from the device state.
 hipError_t launch_row_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t lda, const int32_t *cols,
-                              const void *U, int32_t u_prec, int32_t k_ls, const DevState *ds, double *rho,
-                              hipStream_t st);
+                              const void *U0, const void *U1, int32_t u_prec, int32_t k_ls, const DevState *ds,
+                              double *rho, hipStream_t st);
 struct RowDrawArgs {
     const uint64_t *wr;    // row weights (m)
     int64_t m;
@@ -145,6 +145,7 @@ struct GemmDesc {
     int32_t a_dtype;      // storage of A
     int64_t m;
     const void *U;        // basis (compute type), ld = m
+    const void *U1;       // nullable; when set the basis is U1 if the device merge count is odd, else U
     const void *A;
     int64_t lda;
     const int32_t *cols;
@@ -159,17 +160,17 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
 hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax, const DevState *ds,
                                   int32_t which_p, double *G, hipStream_t st);
 // Y (m x pout, ld m) = source (m x pin) * T (pin x pout, ld ldt); counts from the device state.
+// With Yout1 set, the output is Yout1 if the device merge count is odd, else Yout.
 hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
-                            int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout,
+                            int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout, void *Yout1,
                             hipStream_t st);
 
 struct SmallArgs {
     DevState *ds;
     const double *Vt;      // right factor of the new block (g x ru, ld pmax) when use_vt
     int32_t use_vt;
-    const double *sigma;   // current Sigma (rs)
+    double *sig0, *sig1;   // Sigma pair: current = sig[it & 1], the merge writes sig[(it + 1) & 1]
     const double *sigma2;  // weights of the new block's columns (nullable: 1)
-    double *sigma_new;     // Sigma after the merge (r)
     const double *G;       // reduced Gram (pmax x pmax, ld pmax)
     double *R1;            // (pmax x pmax)
     double *R2;            // (pmax x pmax)

@@ -127,7 +127,8 @@ __global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
     double *tmp = S + pm * pm;          // p doubles
     double *GP = tmp + pm;              // G0 P (p0 x p), dense right factor only
     if (threadIdx.x == 0) sbad = 0;
-    for (int i = threadIdx.x; i < p; i += NT) sP[i] = (i < rs) ? a.sigma[i] : (a.sigma2 ? a.sigma2[i - rs] : 1.0);
+    const double *sigma = (ds->it & 1) ? a.sig1 : a.sig0;
+    for (int i = threadIdx.x; i < p; i += NT) sP[i] = (i < rs) ? sigma[i] : (a.sigma2 ? a.sigma2[i - rs] : 1.0);
     __syncthreads();
     if (a.use_vt) {
         // P = blkdiag(Sigma_r, Vt): GP = G0 P, then G1 = P^T GP into a.work
@@ -260,6 +261,7 @@ __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
     DevState *ds = a.ds;
     if (ds->exhausted) return;
     const int p = ds->p, rs = ds->rs;
+    const int it0 = ds->it;   // read before thread 0 advances it at the end
     const int pm = a.pmax;
     double *S1 = BIG ? a.ws : lds; // G2 -> R2 -> R2^-1
     double *S2 = S1 + p * p;       // R1 -> H = R R^T -> reflectors -> B^T B
@@ -386,12 +388,13 @@ __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
             for (int l = i; l < p; ++l) s += S1[i + l * p] * S3[l + j * p];
         store_c(a.Tc, a.prec, idx, s);
     }
-    for (int i = threadIdx.x; i < a.r; i += NT) a.sigma_new[i] = (i < rnew) ? sqrt(fmax(sev[i], 0.0)) : 0.0;
+    double *sigma_new = (it0 & 1) ? a.sig0 : a.sig1;
+    for (int i = threadIdx.x; i < a.r; i += NT) sigma_new[i] = (i < rnew) ? sqrt(fmax(sev[i], 0.0)) : 0.0;
     if (threadIdx.x == 0) {
         ds->rnew = rnew;
         ds->sin_theta = sin_max;
         ds->rs = rnew;
-        ds->it = ds->it + 1;
+        ds->it = it0 + 1;
         ds->g = 0;
     }
 }
