@@ -188,6 +188,42 @@ pod_status pod_inc_get_info(pod_inc *inc, pod_inc_info *info);
 
 void pod_inc_destroy(pod_inc *inc);
 
+/* ---------------------------------------------------------------------------
+ * Batched ISMA: `count` independent runs of Alg. 1 on matrices of uneven m, n
+ * and k (for the callers that need many small decompositions at once).
+ * Every iteration launches each kernel once for the whole batch; from the
+ * second iteration the launch sequence is replayed from a captured HIP graph.
+ * ------------------------------------------------------------------------- */
+typedef struct pod_batch pod_batch;
+
+/* prm[i], A[i] (device, borrowed) as for pod_init, for i < count.  Rows are
+ * not sampled (w = 0, r_update = 0), the precision is the same for all, and
+ * every merge width r + min(c, n) must round up to <= 64.  The set-up pass
+ * (norms, weights) runs here.  The batch owns an internal stream.  Errors:
+ * POD_EINVAL, POD_ENOMEM, POD_EHIP. */
+pod_status pod_batch_init(pod_batch **b, int32_t count, const pod_params *prm, void *const *A);
+
+/* Measure, per (merge-width bucket of 16, floor(log2 m), compute type) present
+ * in the batch, the row-block count of the Gram passes (256 to 4096 rows per
+ * workgroup) on the batch's own buffers and use the fastest.  Call before
+ * pod_batch_run; *table_entries (nullable) gets the number of buckets. */
+pod_status pod_batch_autotune(pod_batch *b, int32_t *table_entries);
+
+/* Iterate until every matrix has stopped (the stop rule of pod_converged) or
+ * max_rounds iterations; use_graph = 1 replays a captured HIP graph.
+ * *rounds_out (nullable) gets the iterations run.  POD_ESTATE if some matrix
+ * is still running after max_rounds.  Syncs. */
+pod_status pod_batch_run(pod_batch *b, int32_t use_graph, int32_t max_rounds, int32_t *rounds_out);
+
+/* Final step of Alg. 1 for matrix i, as pod_project.  Syncs. */
+pod_status pod_batch_project(pod_batch *b, int32_t i, void *U_out, double *sigma_out, void *V_out);
+
+/* Progress of matrix i as pod_get_info; *gram_blocks (nullable) gets its
+ * row-block count from the tile table.  Syncs. */
+pod_status pod_batch_get_info(pod_batch *b, int32_t i, pod_info *info, int32_t *gram_blocks);
+
+void pod_batch_destroy(pod_batch *b);
+
 /* Column squared norms computed at init (device -> host, n FP64).  Syncs. */
 pod_status pod_get_col_sqnorms(pod_ctx *ctx, double *nu_host);
 

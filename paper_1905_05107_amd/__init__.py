@@ -26,7 +26,8 @@ POD_CRIT_SUBSPACE, POD_CRIT_MODE = 0, 1
 EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project", "pod_get_basis", "pod_get_info",
            "pod_get_indices", "pod_get_col_sqnorms", "pod_col_sqnorms", "pod_sample_size", "pod_destroy",
            "pod_status_str", "pod_profile_enable", "pod_profile_read", "pod_inc_init", "pod_inc_add_block",
-           "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy"]
+           "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy", "pod_batch_init",
+           "pod_batch_autotune", "pod_batch_run", "pod_batch_project", "pod_batch_get_info", "pod_batch_destroy"]
 
 
 class PodError(RuntimeError):
@@ -95,6 +96,12 @@ def lib():
             "pod_inc_result": (i32, [vp, vp, vp, P(i32)]),
             "pod_inc_get_info": (i32, [vp, P(pod_inc_info)]),
             "pod_inc_destroy": (None, [vp]),
+            "pod_batch_init": (i32, [P(vp), i32, P(pod_params), P(vp)]),
+            "pod_batch_autotune": (i32, [vp, P(i32)]),
+            "pod_batch_run": (i32, [vp, i32, i32, P(i32)]),
+            "pod_batch_project": (i32, [vp, i32, vp, vp, vp]),
+            "pod_batch_get_info": (i32, [vp, i32, P(pod_info), P(i32)]),
+            "pod_batch_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -391,6 +398,89 @@ class Incremental:
         inf = pod_inc_info()
         _check(lib().pod_inc_get_info(self.h, ctypes.byref(inf)), "pod_inc_get_info")
         return inf
+
+
+def _params(A, k, c, r=0, w=0, precision=POD_F64, theta_tol=1e-10, col_strategy=POD_COL_L2N,
+            row_strategy=POD_ROW_L2, criterion=POD_CRIT_SUBSPACE, max_iter=None, seed=0, block=0, r_update=0,
+            center_rows=False):
+    ptr, m, n, lda, code = _a_layout(A)
+    p = pod_params()
+    p.m, p.n, p.lda, p.a_dtype, p.precision = m, n, lda, code, precision
+    p.k, p.r, p.c, p.w, p.r_update = k, r, c, w, r_update
+    p.col_strategy, p.row_strategy, p.criterion = col_strategy, row_strategy, criterion
+    p.center_rows = 1 if center_rows else 0
+    p.max_iter = int(max_iter if max_iter is not None else n + 1)
+    p.theta_tol = float(theta_tol)
+    p.seed = int(seed) & (2**64 - 1)
+    p.block = int(block)
+    return p, ptr
+
+
+class Batch:
+    """Many ISMA runs advanced together (pod_batch_*).  ``mats`` is a list of
+    device matrices (m_i x n_i, contiguous columns), ``params`` a list of
+    keyword dicts (k, c, seed, ...) or one dict for all."""
+
+    def __init__(self, mats, params):
+        if isinstance(params, dict):
+            params = [params] * len(mats)
+        self.mats = list(mats)
+        self.kw = [dict(p) for p in params]
+        arr = (pod_params * len(mats))()
+        ptrs = (ctypes.c_void_p * len(mats))()
+        for i, (A, kw) in enumerate(zip(mats, self.kw)):
+            arr[i], ptrs[i] = _params(A, **kw)
+        h = ctypes.c_void_p()
+        _check(lib().pod_batch_init(ctypes.byref(h), len(mats), arr, ptrs), "pod_batch_init")
+        self.h = h
+        self.params = arr
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().pod_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def autotune(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib().pod_batch_autotune(self.h, ctypes.byref(n)), "pod_batch_autotune")
+        return n.value
+
+    def run(self, use_graph: bool = True, max_rounds: int = 1 << 20) -> int:
+        r = ctypes.c_int32()
+        _check(lib().pod_batch_run(self.h, 1 if use_graph else 0, int(max_rounds), ctypes.byref(r)), "pod_batch_run")
+        return r.value
+
+    def info(self, i: int):
+        inf = pod_info()
+        nb = ctypes.c_int32()
+        _check(lib().pod_batch_get_info(self.h, int(i), ctypes.byref(inf), ctypes.byref(nb)), "pod_batch_get_info")
+        return inf, nb.value
+
+    def project(self, i: int, want_v: bool = False):
+        import torch
+        A = self.mats[i]
+        p = self.params[i]
+        inf, _ = self.info(i)
+        k = min(p.k, inf.rank)
+        dt = torch.float64 if p.precision == POD_F64 else torch.float32
+        Ut = torch.empty((k, p.m), dtype=dt, device=A.device)
+        sig = torch.empty(k, dtype=torch.float64, device=A.device)
+        Vt = torch.empty((k, p.n), dtype=dt, device=A.device) if want_v else None
+        _check(lib().pod_batch_project(self.h, int(i), ctypes.c_void_p(Ut.data_ptr()), ctypes.c_void_p(sig.data_ptr()),
+                                       ctypes.c_void_p(Vt.data_ptr()) if want_v else None), "pod_batch_project")
+        return Ut.T, sig, (Vt.T if want_v else None)
 
 
 POD_K = dict(colnorms=0, draw=1, gram=2, gram_reduce=3, chol=4, tall=5, svd=6, project=7, rr=8, sign=9)

@@ -109,28 +109,11 @@ GemmDesc plain_desc(pod_ctx *ctx, const void *Y)
 pod_status merge_launch(pod_ctx *ctx, const GemmDesc &gd, const double *sigma2, bool use_vt, bool block_eig_mode1)
 {
     const int32_t pm = ctx->pmax;
-    const pod_params &p = ctx->prm;
     // pass 1: G0 = X0^T X0, X0 = [U | A(:, I_c)] gathered on the fly
     POD_HIP(launch_gram_partial(gd, ctx->ds, -1, pm, ctx->part, ctx->nblk, ctx->st));
     POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -1, ctx->G, ctx->st));
-    SmallArgs sa;
-    sa.ds = ctx->ds;
-    sa.sig0 = ctx->sig[0];
-    sa.sig1 = ctx->sig[1];
-    sa.G = ctx->G;
-    sa.R1 = ctx->R1;
-    sa.R2 = ctx->R2;
-    sa.Tc = ctx->Tc;
-    sa.work = ctx->work;
-    sa.pmax = pm;
-    sa.r = ctx->r;
-    sa.k = p.k;
-    sa.prec = p.precision;
-    sa.criterion = p.criterion;
-    sa.urnd = unit_roundoff(p.precision);
-    sa.Vt = ctx->Vt;
+    SmallArgs sa = ctx_small_args(ctx);
     sa.use_vt = use_vt;
-    sa.ws = ctx->ws;
     sa.sigma2 = sigma2;
     if (block_eig_mode1) {
         // the new block truncated to its leading r_update directions
@@ -217,6 +200,56 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
 }
 
 }  // extern "C"
+
+DrawArgs pod::ctx_draw_args(pod_ctx *ctx)
+{
+    DrawArgs a;
+    a.wq = ctx->wq;
+    a.inS = ctx->inS;
+    a.n = ctx->prm.n;
+    a.c = ctx->prm.c;
+    a.unf = (ctx->prm.col_strategy == POD_COL_UNF);
+    a.seed = ctx->prm.seed;
+    a.block = ctx->prm.block;
+    a.cols = ctx->cols;
+    a.ccnt = ctx->ccnt;
+    a.col_log = ctx->col_log;
+    a.ccnt_log = ctx->ccnt_log;
+    a.col_log_off = ctx->col_log_off;
+    a.max_iter = (int32_t)((ctx->prm.max_iter < ctx->prm.n) ? ctx->prm.max_iter : ctx->prm.n);
+    a.forced = (ctx->forced_g >= 0) ? ctx->forced : nullptr;
+    a.forced_g = ctx->forced_g;
+    a.ds = ctx->ds;
+    return a;
+}
+
+SmallArgs pod::ctx_small_args(pod_ctx *ctx)
+{
+    const pod_params &p = ctx->prm;
+    SmallArgs sa;
+    sa.ds = ctx->ds;
+    sa.sig0 = ctx->sig[0];
+    sa.sig1 = ctx->sig[1];
+    sa.G = ctx->G;
+    sa.R1 = ctx->R1;
+    sa.R2 = ctx->R2;
+    sa.Tc = ctx->Tc;
+    sa.work = ctx->work;
+    sa.pmax = ctx->pmax;
+    sa.r = ctx->r;
+    sa.k = p.k;
+    sa.prec = p.precision;
+    sa.criterion = p.criterion;
+    sa.urnd = unit_roundoff(p.precision);
+    sa.Vt = ctx->Vt;
+    sa.use_vt = 0;
+    sa.sigma2 = nullptr;
+    sa.ws = ctx->ws;
+    return sa;
+}
+
+GemmDesc pod::ctx_gather_desc(pod_ctx *ctx) { return gather_desc(ctx); }
+GemmDesc pod::ctx_plain_desc(pod_ctx *ctx, const void *Y) { return plain_desc(ctx, Y); }
 
 pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
 {
@@ -368,23 +401,7 @@ pod_status pod_sample(pod_ctx *ctx, int32_t *g_out, int32_t *h_out)
     if (ctx->pending) return POD_ESTATE;
     if (ctx->exhausted) return POD_EXHAUSTED;
     if (ctx->merges >= ctx->prm.max_iter) return POD_ESTATE;
-    DrawArgs a;
-    a.wq = ctx->wq;
-    a.inS = ctx->inS;
-    a.n = ctx->prm.n;
-    a.c = ctx->prm.c;
-    a.unf = (ctx->prm.col_strategy == POD_COL_UNF);
-    a.seed = ctx->prm.seed;
-    a.block = ctx->prm.block;
-    a.cols = ctx->cols;
-    a.ccnt = ctx->ccnt;
-    a.col_log = ctx->col_log;
-    a.ccnt_log = ctx->ccnt_log;
-    a.col_log_off = ctx->col_log_off;
-    a.max_iter = (int32_t)((ctx->prm.max_iter < ctx->prm.n) ? ctx->prm.max_iter : ctx->prm.n);
-    a.forced = (ctx->forced_g >= 0) ? ctx->forced : nullptr;
-    a.forced_g = ctx->forced_g;
-    a.ds = ctx->ds;
+    DrawArgs a = ctx_draw_args(ctx);
     POD_HIP(launch_draw_cols(a, ctx->st));
     ctx->forced_g = -1;
     const pod_params &p = ctx->prm;

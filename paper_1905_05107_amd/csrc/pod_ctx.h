@@ -57,4 +57,10 @@ pod_status ctx_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out
 // truncated to r.  The first call on an empty state takes (Ub, sb) as is.
 pod_status ctx_merge_basis(pod_ctx *ctx, const void *Ub, const double *sb, int32_t rb);
 
+// Argument blocks of one context's launches (shared with the batched path).
+DrawArgs ctx_draw_args(pod_ctx *ctx);
+SmallArgs ctx_small_args(pod_ctx *ctx);
+GemmDesc ctx_gather_desc(pod_ctx *ctx);
+GemmDesc ctx_plain_desc(pod_ctx *ctx, const void *Y);
+
 }  // namespace pod

@@ -156,6 +156,22 @@ template <typename TC> static bool vec_ok(const SrcT<TC> &s, int64_t m)
     return ok;
 }
 
+template <typename TC> __host__ __device__ SrcT<TC> make_src(const GemmDesc &d)
+{
+    SrcT<TC> s;
+    s.U = reinterpret_cast<const TC *>(d.U);
+    s.U1 = reinterpret_cast<const TC *>(d.U1);
+    s.A = d.A;
+    s.lda = d.lda;
+    s.cols = d.cols;
+    s.Y = reinterpret_cast<const TC *>(d.Y);
+    s.gather = d.gather;
+    s.a_f64 = (d.a_dtype == POD_F64);
+    s.rs = 0;
+    s.guard = d.guard;
+    return s;
+}
+
 // ---------------------------------------------------------------------------
 // Partial Grams.  Workgroup b owns stages [ns b / nblk, ns (b+1) / nblk) of
 // the ns = ceil(m / 32) row stages; each of its 4 waves accumulates a fixed
@@ -170,8 +186,8 @@ constexpr int MAXPW160 = 14, ITEMS160 = 5;
 constexpr int PMAX_WIDE = 160;
 
 template <typename TC, int MAXPW, int ITEMS>
-__global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, const DevState *ds, int which_p,
-                                                      int pmax, double *__restrict__ part, int nblk, int vec)
+__device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const DevState *ds, int which_p, int pmax,
+                                                  double *__restrict__ part, int nblk, int vec, int bid)
 {
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
@@ -185,7 +201,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
     const int npairs = NT16 * (NT16 + 1) / 2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nst = (m + RB - 1) / RB;
-    const int64_t s0 = (nst * blockIdx.x) / nblk, s1 = (nst * (blockIdx.x + 1)) / nblk;
+    const int64_t s0 = (nst * bid) / nblk, s1 = (nst * (bid + 1)) / nblk;
     int tI[MAXPW], tJ[MAXPW];
 #pragma unroll
     for (int q = 0; q < MAXPW; ++q) {
@@ -221,7 +237,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
             }
         }
     }
-    double *pb = part + (int64_t)blockIdx.x * pmax * pmax;
+    double *pb = part + (int64_t)bid * pmax * pmax;
 #pragma unroll
     for (int q = 0; q < MAXPW; ++q) {
         if (tI[q] < 0) continue;
@@ -238,17 +254,34 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
     }
 }
 
+template <typename TC, int MAXPW, int ITEMS>
+__global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, const DevState *ds, int which_p,
+                                                      int pmax, double *__restrict__ part, int nblk, int vec)
+{
+    gram_partial_body<TC, MAXPW, ITEMS>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
+}
+
+// Batched: matrix blockIdx.y, its own block count; stopped matrices skipped.
+template <typename TC, int MAXPW, int ITEMS>
+__global__ __launch_bounds__(256) void k_gram_partial_b(const GramArgs *__restrict__ arr)
+{
+    const GramArgs &a = arr[blockIdx.y];
+    if ((int)blockIdx.x >= a.nblk || a.ds->done) return;
+    gram_partial_body<TC, MAXPW, ITEMS>(make_src<TC>(a.d), a.d.m, a.ds, a.which_p, a.pmax, a.part, a.nblk, a.vec,
+                                        blockIdx.x);
+}
+
 // Fixed-order reduction of the partial Grams: workgroup w owns 64 entries;
 // its 4 waves each add a contiguous quarter of the partials in order, and the
 // four quarter sums are added in order.
-__global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ part, int nblk, int pmax,
-                                                     const DevState *ds, int which_p, double *__restrict__ G)
+__device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part, int nblk, int pmax,
+                                                 const DevState *ds, int which_p, double *__restrict__ G, int bid)
 {
     __shared__ double sq[4][64];
     if (ds->exhausted) return;
     const int P = sel_count(ds, which_p);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int idx = blockIdx.x * 64 + lane;
+    const int idx = bid * 64 + lane;
     const int i = idx % pmax, j = idx / pmax;
     const bool live = idx < pmax * pmax && i < P && j < P;
     const int b0 = (nblk * wv) / 4, b1 = (nblk * (wv + 1)) / 4;
@@ -260,21 +293,19 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ 
     if (wv == 0 && idx < pmax * pmax) G[idx] = live ? ((sq[0][lane] + sq[1][lane]) + sq[2][lane]) + sq[3][lane] : 0.0;
 }
 
-template <typename TC> static SrcT<TC> make_src(const GemmDesc &d)
+__global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ part, int nblk, int pmax,
+                                                     const DevState *ds, int which_p, double *__restrict__ G)
 {
-    SrcT<TC> s;
-    s.U = reinterpret_cast<const TC *>(d.U);
-    s.U1 = reinterpret_cast<const TC *>(d.U1);
-    s.A = d.A;
-    s.lda = d.lda;
-    s.cols = d.cols;
-    s.Y = reinterpret_cast<const TC *>(d.Y);
-    s.gather = d.gather;
-    s.a_f64 = (d.a_dtype == POD_F64);
-    s.rs = 0;
-    s.guard = d.guard;
-    return s;
+    gram_reduce_body(part, nblk, pmax, ds, which_p, G, blockIdx.x);
 }
+
+__global__ __launch_bounds__(256) void k_gram_reduce_b(const GramArgs *__restrict__ arr)
+{
+    const GramArgs &a = arr[blockIdx.y];
+    if ((int)blockIdx.x * 64 >= a.pmax * a.pmax || a.ds->done) return;
+    gram_reduce_body(a.part, a.nblk, a.pmax, a.ds, a.which_p, a.G, blockIdx.x);
+}
+
 
 template <typename TC, int MAXPW, int ITEMS>
 static void gram_launch(const GemmDesc &d, const DevState *ds, int32_t which_p, int32_t pmax, double *part,
@@ -321,9 +352,9 @@ constexpr int TALL_ST = 4;   // row stages per workgroup
 constexpr size_t TALL_T_LDS = 112 * 1024;  // largest T staged in LDS
 
 template <typename TC, int ITEMS, bool TG>
-__global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
-                                                   int sel_out, int pmax_in, int pmax_out, const TC *__restrict__ T,
-                                                   int ldt, TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec)
+__device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in, int sel_out,
+                                               int pmax_in, int pmax_out, const TC *__restrict__ T, int ldt,
+                                               TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec, int bid)
 {
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
@@ -337,7 +368,7 @@ __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const 
     TC *Ts = Xs + pmax_in * LDSR;                    // PI x PO, row k at Ts + k * PO (when !TG)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nst = (m + RB - 1) / RB;
-    const int64_t s0 = (int64_t)blockIdx.x * TALL_ST;
+    const int64_t s0 = (int64_t)bid * TALL_ST;
     const int64_t s1 = (s0 + TALL_ST < nst) ? s0 + TALL_ST : nst;
     if (!TG)
         for (int idx = threadIdx.x; idx < PI * PO; idx += 256) {
@@ -379,6 +410,25 @@ __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const 
             }
         }
     }
+}
+
+template <typename TC, int ITEMS, bool TG>
+__global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
+                                                   int sel_out, int pmax_in, int pmax_out, const TC *__restrict__ T,
+                                                   int ldt, TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec)
+{
+    gemm_tall_body<TC, ITEMS, TG>(s, m, ds, sel_in, sel_out, pmax_in, pmax_out, T, ldt, Yout, Yout1, vec,
+                                  blockIdx.x);
+}
+
+template <typename TC, int ITEMS>
+__global__ __launch_bounds__(256) void k_gemm_tall_b(const TallArgs *__restrict__ arr)
+{
+    const TallArgs &a = arr[blockIdx.y];
+    if ((int)blockIdx.x >= a.nb || a.ds->done) return;
+    gemm_tall_body<TC, ITEMS, false>(make_src<TC>(a.d), a.d.m, a.ds, a.sel_in, a.sel_out, a.pin_max, a.pout_max,
+                                     reinterpret_cast<const TC *>(a.T), a.ldt, reinterpret_cast<TC *>(a.Yout),
+                                     reinterpret_cast<TC *>(a.Yout1), a.vec, blockIdx.x);
 }
 
 template <typename TC, int ITEMS, bool TG>
@@ -581,6 +631,56 @@ hipError_t launch_project_reduce(const ProjArgs &a, hipStream_t st)
     ProfScope ps(POD_K_PROJECT, st);
     hipLaunchKernelGGL(k_project_reduce, dim3((unsigned)((rn + 255) / 256)), dim3(256), 0, st, a.Bpart, rn,
                        a.nsplit, a.B);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batched launches
+
+int32_t gemm_vec_ok(const GemmDesc &d)
+{
+    if (d.prec == POD_F64) return (int32_t)vec_ok(make_src<double>(d), d.m);
+    return (int32_t)vec_ok(make_src<float>(d), d.m);
+}
+
+int32_t tall_blocks(int64_t m)
+{
+    const int64_t nst = (m + RB - 1) / RB;
+    return (int32_t)((nst + TALL_ST - 1) / TALL_ST);
+}
+
+hipError_t launch_gram_partial_b(const GramArgs *arr, int32_t count, int32_t max_nblk, int32_t pmax_max, int32_t prec,
+                                 hipStream_t st)
+{
+    if (pmax_max > 64 || count < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)max_nblk, (unsigned)count);
+    if (prec == POD_F64)
+        hipLaunchKernelGGL((k_gram_partial_b<double, MAXPW64, ITEMS64>), grid, dim3(256),
+                           (size_t)pmax_max * LDSR * sizeof(double), st, arr);
+    else
+        hipLaunchKernelGGL((k_gram_partial_b<float, MAXPW64, ITEMS64>), grid, dim3(256),
+                           (size_t)pmax_max * LDSR * sizeof(float), st, arr);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_reduce_b(const GramArgs *arr, int32_t count, int32_t pmax_max, hipStream_t st)
+{
+    if (count < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gram_reduce_b, dim3((unsigned)((pmax_max * pmax_max + 63) / 64), (unsigned)count),
+                       dim3(256), 0, st, arr);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_tall_b(const TallArgs *arr, int32_t count, int32_t max_nb, int32_t pi_max, int32_t po_max,
+                              int32_t prec, hipStream_t st)
+{
+    if (pi_max > 64 || po_max > 64 || count < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)max_nb, (unsigned)count);
+    if (prec == POD_F64)
+        hipLaunchKernelGGL((k_gemm_tall_b<double, ITEMS64>), grid, dim3(256),
+                           (size_t)(pi_max * LDSR + pi_max * po_max) * sizeof(double), st, arr);
+    else
+        hipLaunchKernelGGL((k_gemm_tall_b<float, ITEMS64>), grid, dim3(256),
+                           (size_t)(pi_max * LDSR + pi_max * po_max) * sizeof(float), st, arr);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ struct DevState {
     int32_t col_log_len;// entries used in the column log
     int32_t s_empty;    // no drawable column left after the last draw
     int32_t sweeps_total; // Jacobi sweeps summed over merges
+    int32_t done;       // batched runs: this matrix stopped (skipped by the batched kernels)
     double sin_theta;   // last convergence sine (NaN until the second merge)
     uint64_t wtot;      // total column weight of the last draw
     uint64_t wrow_tot;  // total row weight of the last row draw
@@ -116,6 +117,9 @@ struct DrawArgs {
     DevState *ds;
 };
 hipError_t launch_draw_cols(const DrawArgs &a, hipStream_t st);
+hipError_t launch_draw_cols_b(const DrawArgs *arr, int32_t count, hipStream_t st);
+hipError_t launch_batch_done(DevState *const *dss, const int32_t *max_iter, const double *sin_tol, int32_t count,
+                             int32_t *ndone, hipStream_t st);
 
 // Row squared norms of the gathered block D = A(:, cols[0..g)) (rows of D in
 // ascending column order, FP64 fma chain), g read from the device state.
@@ -165,6 +169,33 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
                             int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout, void *Yout1,
                             hipStream_t st);
 
+// Per-matrix arguments of the batched launches (device arrays, one entry per
+// matrix; blockIdx.y selects the entry).
+struct GramArgs {
+    GemmDesc d;
+    const DevState *ds;
+    int32_t which_p, pmax, nblk, vec;
+    double *part;
+    double *G;
+};
+struct TallArgs {
+    GemmDesc d;
+    const DevState *ds;
+    int32_t sel_in, sel_out, pin_max, pout_max;  // pin_max / pout_max: multiples of 16
+    const void *T;
+    int32_t ldt, vec, nb;
+    void *Yout, *Yout1;
+};
+// Batched launches (pmax <= 64 for every matrix; prec uniform).
+hipError_t launch_gram_partial_b(const GramArgs *arr, int32_t count, int32_t max_nblk, int32_t pmax_max, int32_t prec,
+                                 hipStream_t st);
+hipError_t launch_gram_reduce_b(const GramArgs *arr, int32_t count, int32_t pmax_max, hipStream_t st);
+hipError_t launch_gemm_tall_b(const TallArgs *arr, int32_t count, int32_t max_nb, int32_t pi_max, int32_t po_max,
+                              int32_t prec, hipStream_t st);
+// Host checks of one matrix's arguments
+int32_t gemm_vec_ok(const GemmDesc &d);
+int32_t tall_blocks(int64_t m);
+
 struct SmallArgs {
     DevState *ds;
     const double *Vt;      // right factor of the new block (g x ru, ld pmax) when use_vt
@@ -207,6 +238,8 @@ struct BlockEigArgs {
 };
 hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st);
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st);
+hipError_t launch_chol_first_b(const SmallArgs *arr, int32_t count, int32_t pmax_max, hipStream_t st);
+hipError_t launch_svd_merge_b(const SmallArgs *arr, int32_t count, int32_t pmax_max, hipStream_t st);
 
 struct ProjArgs {
     int32_t prec, a_dtype;

@@ -242,7 +242,7 @@ hipError_t launch_quantize(const double *v, int64_t len, uint64_t *w, DevState *
 //   Distinct indices in ascending order with multiplicities, S <- S \ I_c,
 //   appended to the column log.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_draw_cols(DrawArgs a)
+__device__ __forceinline__ void draw_cols_body(const DrawArgs &a)
 {
     __shared__ uint64_t sincl[1024];   // inclusive prefix of chunk sums
     __shared__ int64_t sdraw[1024];
@@ -389,6 +389,57 @@ __global__ __launch_bounds__(1024) void k_draw_cols(DrawArgs a)
         ds->col_log_len = base + g;
         ds->exhausted = 0;
     }
+}
+
+__global__ __launch_bounds__(1024) void k_draw_cols(DrawArgs a) { draw_cols_body(a); }
+
+// Batched: one workgroup per matrix (blockIdx.y), stopped matrices skipped.
+__global__ __launch_bounds__(1024) void k_draw_cols_b(const DrawArgs *__restrict__ arr)
+{
+    const DrawArgs a = arr[blockIdx.y];
+    if (a.ds->done) return;
+    draw_cols_body(a);
+}
+
+hipError_t launch_draw_cols_b(const DrawArgs *arr, int32_t count, hipStream_t st)
+{
+    if (count < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_draw_cols_b, dim3(1, (unsigned)count), dim3(1024), 0, st, arr);
+    return hipGetLastError();
+}
+
+// Stop test of Alg. 1 for every matrix of a batch (the host-side rule of a
+// single run): S exhausted, max_iter merges, a non-finite value, or, from
+// the second merge, a convergence sine below the tolerance.  *ndone gets the
+// number of stopped matrices.
+__global__ __launch_bounds__(256) void k_batch_done(DevState *const *__restrict__ dss,
+                                                    const int32_t *__restrict__ max_iter,
+                                                    const double *__restrict__ sin_tol, int32_t count,
+                                                    int32_t *__restrict__ ndone)
+{
+    __shared__ int32_t sw[4];
+    int32_t c = 0;
+    for (int32_t b = threadIdx.x; b < count; b += 256) {
+        DevState *ds = dss[b];
+        if (!ds->done) {
+            const bool d = ds->exhausted || ds->s_empty || ds->it >= max_iter[b] || (ds->flags & FLAG_NONFINITE) ||
+                           (ds->it >= 2 && ds->sin_theta < sin_tol[b]);
+            if (d) ds->done = 1;
+        }
+        c += ds->done ? 1 : 0;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) *ndone = ((sw[0] + sw[1]) + sw[2]) + sw[3];
+}
+
+hipError_t launch_batch_done(DevState *const *dss, const int32_t *max_iter, const double *sin_tol, int32_t count,
+                             int32_t *ndone, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_batch_done, dim3(1), dim3(256), 0, st, dss, max_iter, sin_tol, count, ndone);
+    return hipGetLastError();
 }
 
 hipError_t launch_draw_cols(const DrawArgs &a, hipStream_t st)

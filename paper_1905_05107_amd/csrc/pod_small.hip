@@ -113,7 +113,7 @@ __device__ __forceinline__ void store_c(void *base, int prec, int64_t idx, doubl
 // T1 = P R1^-1 written in the compute type for the tall GEMM Y = X0 T1.
 // ---------------------------------------------------------------------------
 template <bool BIG>
-__global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
+__device__ __forceinline__ void chol_first_body(const SmallArgs &a)
 {
     extern __shared__ double lds[];
     __shared__ double sP[EIG_NMAX];
@@ -215,6 +215,20 @@ __global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
     }
 }
 
+template <bool BIG>
+__global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
+{
+    chol_first_body<BIG>(a);
+}
+
+// Batched: one workgroup per matrix (blockIdx.y), stopped matrices skipped.
+__global__ __launch_bounds__(512) void k_chol_first_b(const SmallArgs *__restrict__ arr)
+{
+    const SmallArgs a = arr[blockIdx.y];
+    if (a.ds->done) return;
+    chol_first_body<false>(a);
+}
+
 hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 {
     const bool big = a.pmax > SMALL_LDS_P;
@@ -251,7 +265,7 @@ hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 // criterion compares R(:, i)/|R(:, i)| with U_R(:, i) one by one.
 // ---------------------------------------------------------------------------
 template <bool BIG>
-__global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
+__device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
 {
     extern __shared__ double lds[];
     __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
@@ -397,6 +411,20 @@ __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
         ds->it = it0 + 1;
         ds->g = 0;
     }
+}
+
+template <bool BIG>
+__global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
+{
+    svd_merge_body<BIG>(a);
+}
+
+// Batched: one workgroup per matrix (blockIdx.y), stopped matrices skipped.
+__global__ __launch_bounds__(512) void k_svd_merge_b(const SmallArgs *__restrict__ arr)
+{
+    const SmallArgs a = arr[blockIdx.y];
+    if (a.ds->done) return;
+    svd_merge_body<false>(a);
 }
 
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
@@ -691,6 +719,37 @@ hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st)
         hipLaunchKernelGGL(k_block_eig<true>, dim3(1), dim3(NT), lds, st, a);
     else
         hipLaunchKernelGGL(k_block_eig<false>, dim3(1), dim3(NT), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_first_b(const SmallArgs *arr, int32_t count, int32_t pmax_max, hipStream_t st)
+{
+    if (pmax_max > SMALL_LDS_P || count < 1) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_chol_first_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_limit(false));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_chol_first_b, dim3(1, (unsigned)count), dim3(NT),
+                       (size_t)(2 * pmax_max * pmax_max + pmax_max) * sizeof(double), st, arr);
+    return hipGetLastError();
+}
+
+hipError_t launch_svd_merge_b(const SmallArgs *arr, int32_t count, int32_t pmax_max, hipStream_t st)
+{
+    if (pmax_max > SMALL_LDS_P || count < 1) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_svd_merge_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_limit(false));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_svd_merge_b, dim3(1, (unsigned)count), dim3(NT),
+                       (size_t)(3 * pmax_max * pmax_max + EIG_LU_THREADS * eig_lu_stride(pmax_max)) * sizeof(double),
+                       st, arr);
     return hipGetLastError();
 }
 

@@ -377,3 +377,57 @@ def test_incremental_rows_r_above_k(c1):
     kw = _c1_params(w=20, r=20, theta_tol=1e-9)
     print("incremental rows", flush=True)
     _inc_check(c1.A, kw, block_bounds(c1.A.shape[1], 3), dict(kw, precision=pod.POD_F64), False, 1e-10, 1e-8)
+
+
+# ------------------------------------------------------------------ batched runs (one launch per kernel for all matrices)
+
+def _batch_mats(count, seed, dtype=np.float32):
+    rng = np.random.default_rng(seed)
+    mats, kws = [], []
+    for i in range(count):
+        m = int(rng.integers(3000, 12000))
+        n = int(rng.integers(120, 400))
+        k = int(rng.integers(4, 17))
+        tau = float(rng.uniform(3, 12))
+        s = np.exp(-np.arange(min(n, 200)) / tau)
+        A = snapgen.spectrum_matrix(m, n, s, 1e-8, seed=seed * 100 + i, centre=False,
+                                    v_orthogonal_to_ones=False).A.astype(dtype)
+        mats.append(A)
+        kws.append(dict(k=k, c=2 * k, seed=5000 + i, theta_tol=1e-6))
+    return mats, kws
+
+
+@pytest.mark.parametrize("precision,use_graph", [(pod.POD_F32, True), (pod.POD_F32, False), (pod.POD_F64, True)])
+def test_batch_equals_single_runs(precision, use_graph):
+    """Each matrix of a batch gives bit-for-bit the result of its own run."""
+    mats, kws = _batch_mats(6, 11, np.float32 if precision == pod.POD_F32 else np.float64)
+    print(f"batch precision={precision} graph={use_graph}", flush=True)
+    dev = [_dev(A) for A in mats]
+    with pod.Batch(dev, [dict(kw, precision=precision) for kw in kws]) as b:
+        rounds = b.run(use_graph=use_graph)
+        got = [b.project(i) for i in range(len(mats))]
+        iters = [b.info(i)[0].iter for i in range(len(mats))]
+    assert rounds >= max(iters)
+    for i, (A, kw) in enumerate(zip(dev, kws)):
+        res = pod.isma(A, precision=precision, want_v=False, **kw)
+        assert res.iters == iters[i]
+        assert torch.equal(res.U, got[i][0]), i
+        assert torch.equal(res.sigma, got[i][1]), i
+
+
+def test_batch_autotuned_matches_oracle():
+    """FP64 batch after the tile autotuner, each matrix against the oracle."""
+    mats, kws = _batch_mats(5, 12, np.float64)
+    print("batch autotune", flush=True)
+    with pod.Batch([_dev(A) for A in mats], [dict(kw, precision=pod.POD_F64) for kw in kws]) as b:
+        assert b.autotune() >= 1
+        b.run()
+        for i, (A, kw) in enumerate(zip(mats, kws)):
+            inf, nblk = b.info(i)
+            assert nblk >= 1
+            U, s, _ = b.project(i)
+            ref = oracle_isma(A, IsmaParams(**kw), n_iter=inf.iter, want_v=False)
+            rel = np.max(np.abs(s.cpu().numpy() - ref.sigma) / ref.sigma)
+            ang = _angles(ref.U, U.cpu().numpy())
+            print(f"  matrix {i}: iters={inf.iter} nblk={nblk} sigma_rel={rel:.2e} angle={ang:.2e}", flush=True)
+            assert rel <= 1e-10 and ang <= 1e-8
