@@ -1,0 +1,106 @@
+"""Adjoint of the ISMA merge chain (TEST INFRASTRUCTURE ONLY).
+
+Loss: L(A) = || A - U_k U_k^T A ||_F^2 with U_k the first k columns of the
+basis the merges of Alg. 1 (Alg. 2, BLOCK MERGE) end with, the sampled
+columns of every iteration held fixed (the draw is piecewise constant in A).
+
+Forward: merge t forms M_t = [U_{t-1} Sigma_{t-1} | A(:, I_t)], takes its full
+thin SVD M_t = U S V^T (LAPACK through numpy, a library step) and keeps
+r_t = min(r, #{s_i > p u s_1}) leading pairs (the rank guard of Alg. 2).
+
+Backward (reverse mode, every intermediate of the forward stored): the
+adjoint of a thin SVD restricted to the leading r columns (Townsend 2016,
+"Differentiating the Singular Value Decomposition"; Ionescu, Vantzos &
+Sminchisescu 2015) with V-bar = 0:
+
+    M-bar = U [ (F o (J - J^T)) S + diag(s-bar) ] V^T
+            + (I - U U^T) U-bar S_r^-1 V_r^T,       J = U^T U-bar (p x p,
+                                                     zero beyond column r),
+    F_ij = d_ij / (d_ij^2 + eta^2 s_1^4), d_ij = s_j^2 - s_i^2 (i != j), F_ii = 0
+
+(the eta term is a guard against near-equal pairs: F_ij = 1/(s_j^2 - s_i^2)
+whenever |d_ij| >> eta s_1^2).  M-bar splits into the adjoint of
+U_{t-1} Sigma_{t-1} -- giving U-bar_{t-1} = M-bar(:, :rs) Sigma_{t-1} and
+s-bar_{t-1,i} = u_i^T M-bar(:, i) -- and that of the sampled columns, added
+to dA(:, I_t).  The loss contributes 2 (A - U_k B) to dA directly and
+U-bar = -2 (A - U_k B) B^T with B = U_k^T A.
+
+Pins: central finite differences of the loss, and the closed form
+dL/dA = 2 (I - U_k U_k^T) A when one merge sees every column (the merge is
+then the exact truncated SVD, where the indirect term vanishes).
+"""
+from __future__ import annotations
+
+from typing import List, Sequence
+
+import numpy as np
+
+U_F64 = 2.0 ** -53
+
+
+def forward(A, col_sets: Sequence[np.ndarray], r: int):
+    """Merge chain on the fixed column sets.  Returns (U, s, tape)."""
+    A = np.asarray(A, dtype=np.float64)
+    m = A.shape[0]
+    U = np.zeros((m, 0))
+    s = np.zeros(0)
+    tape = []
+    for cols in col_sets:
+        cols = np.asarray(cols, dtype=np.int64)
+        M = np.hstack([U * s[None, :], A[:, cols]])
+        Uf, sf, Vt = np.linalg.svd(M, full_matrices=False)
+        p = M.shape[1]
+        rr = int(min(r, np.sum(sf > p * U_F64 * sf[0]))) if sf.size and sf[0] > 0 else 0
+        tape.append((U, s, cols, Uf, sf, Vt.T, rr))
+        U, s = Uf[:, :rr], sf[:rr]
+    return U, s, tape
+
+
+def loss(A, col_sets, k: int, r: int) -> float:
+    A = np.asarray(A, dtype=np.float64)
+    U, _, _ = forward(A, col_sets, r)
+    Uk = U[:, :k]
+    R = A - Uk @ (Uk.T @ A)
+    return float(np.sum(R * R))
+
+
+def loss_and_grad(A, col_sets, k: int, r: int, eta: float = 1e-12):
+    """(L, dL/dA) by the reverse pass described in the module docstring."""
+    A = np.asarray(A, dtype=np.float64)
+    U, s, tape = forward(A, col_sets, r)
+    kk = min(k, U.shape[1])
+    Uk = U[:, :kk]
+    B = Uk.T @ A
+    R = A - Uk @ B
+    L = float(np.sum(R * R))
+    dA = 2.0 * R
+    Ubar = np.zeros_like(U)
+    Ubar[:, :kk] = -2.0 * R @ B.T
+    sbar = np.zeros(U.shape[1])
+    for (U0, s0, cols, Uf, sf, V, rr) in reversed(tape):
+        p = sf.size
+        J = np.zeros((p, p))
+        J[:, :rr] = Uf.T @ Ubar
+        d = sf[None, :] ** 2 - sf[:, None] ** 2
+        F = d / (d * d + (eta * sf[0] ** 2) ** 2) if sf[0] > 0 else np.zeros_like(d)
+        np.fill_diagonal(F, 0.0)
+        K = (F * (J - J.T)) * sf[None, :]
+        K[np.arange(rr), np.arange(rr)] += sbar
+        Mbar = Uf @ K @ V.T
+        if rr:
+            Mbar += ((Ubar - Uf @ J[:, :rr]) / sf[None, :rr]) @ V[:, :rr].T
+        rs = s0.size
+        dA[:, cols] += Mbar[:, rs:]
+        Ubar = Mbar[:, :rs] * s0[None, :]
+        sbar = np.sum(U0 * Mbar[:, :rs], axis=0)
+    return L, dA
+
+
+def col_sets_of(logs) -> List[np.ndarray]:
+    """The column sets of a run's iteration logs (oracle.isma's IterLog)."""
+    return [np.asarray(lg.cols, dtype=np.int64) for lg in logs]
+
+
+def fd_directional(A, col_sets, k: int, r: int, E, h: float = 1e-6) -> float:
+    """Central difference (L(A + h E) - L(A - h E)) / (2 h)."""
+    return (loss(A + h * E, col_sets, k, r) - loss(A - h * E, col_sets, k, r)) / (2.0 * h)
