@@ -146,6 +146,35 @@ pod_status pod_get_indices(pod_ctx *ctx, int32_t iter, int32_t *cols, int32_t *c
                            int32_t *rows, int32_t *row_counts, int32_t *h);
 
 /* ---------------------------------------------------------------------------
+ * Reverse mode through the merge chain of Alg. 1 (ICS: w = 0, r_update = 0,
+ * merge width <= 64).  Outputs differentiated: the first k merged modes and
+ * singular values (U_k, Sigma_k) as pod_get_basis returns them (before the
+ * final step); the sampled columns are constants (the draw is piecewise
+ * constant in A).  Each merge's truncated thin SVD is differentiated with the
+ * coupling F_ij = d / (d^2 + eta^2 s_1^4), d = s_j^2 - s_i^2 (eta = 1e-12 for
+ * POD_F64, 1e-6 otherwise; F_ij = 1/(s_j^2 - s_i^2) when |d| >> eta s_1^2)
+ * (Townsend 2016; Ionescu, Vantzos & Sminchisescu 2015).
+ * ------------------------------------------------------------------------- */
+
+/* Keep what the reverse pass needs: per merge the starting basis (m x r) and
+ * Sigma, and the p x p merge factor.  Call after pod_init, before the first
+ * pod_sample.  POD_EINVAL for rows, truncated blocks or a merge width above
+ * 64; POD_ESTATE after a draw. */
+pod_status pod_enable_adjoint(pod_ctx *ctx);
+
+/* dA (device, m x n, ld m, compute type) += d<dU, U_k> + <dsigma, Sigma_k> / dA
+ * for dU (device, m x k, ld m, compute type; nullable) and dsigma (device, k
+ * FP64; nullable).  POD_ESTATE without pod_enable_adjoint or before a merge.
+ * Syncs. */
+pod_status pod_backward(pod_ctx *ctx, const void *dU, const double *dsigma, void *dA);
+
+/* Loss L = |A - U_k U_k^T A|_F^2 of the merged modes and its gradient:
+ * dA (device, m x n, ld m, compute type) is overwritten with dL/dA and
+ * *loss (host, nullable) gets L.  Two passes over A plus two per merge.
+ * Syncs. */
+pod_status pod_loss_grad(pod_ctx *ctx, void *dA, double *loss);
+
+/* ---------------------------------------------------------------------------
  * Alg. 3, incremental POD: ISMA on each column block (with its final step),
  * then BLOCK MERGE of the block's leading pairs [U_b Sigma_b] into the
  * running (U, Sigma), truncated to r.  One pass over the matrix.

@@ -64,19 +64,9 @@ def loss(A, col_sets, k: int, r: int) -> float:
     return float(np.sum(R * R))
 
 
-def loss_and_grad(A, col_sets, k: int, r: int, eta: float = 1e-12):
-    """(L, dL/dA) by the reverse pass described in the module docstring."""
-    A = np.asarray(A, dtype=np.float64)
-    U, s, tape = forward(A, col_sets, r)
-    kk = min(k, U.shape[1])
-    Uk = U[:, :kk]
-    B = Uk.T @ A
-    R = A - Uk @ B
-    L = float(np.sum(R * R))
-    dA = 2.0 * R
-    Ubar = np.zeros_like(U)
-    Ubar[:, :kk] = -2.0 * R @ B.T
-    sbar = np.zeros(U.shape[1])
+def _reverse(tape, Ubar, sbar, dA, eta):
+    """Reverse pass over the merges from the adjoints (Ubar, sbar) of the final
+    state; adds the adjoint of every sampled block to dA."""
     for (U0, s0, cols, Uf, sf, V, rr) in reversed(tape):
         p = sf.size
         J = np.zeros((p, p))
@@ -93,7 +83,38 @@ def loss_and_grad(A, col_sets, k: int, r: int, eta: float = 1e-12):
         dA[:, cols] += Mbar[:, rs:]
         Ubar = Mbar[:, :rs] * s0[None, :]
         sbar = np.sum(U0 * Mbar[:, :rs], axis=0)
+    return dA
+
+
+def loss_and_grad(A, col_sets, k: int, r: int, eta: float = 1e-12):
+    """(L, dL/dA) by the reverse pass described in the module docstring."""
+    A = np.asarray(A, dtype=np.float64)
+    U, s, tape = forward(A, col_sets, r)
+    kk = min(k, U.shape[1])
+    Uk = U[:, :kk]
+    B = Uk.T @ A
+    R = A - Uk @ B
+    L = float(np.sum(R * R))
+    Ubar = np.zeros_like(U)
+    Ubar[:, :kk] = -2.0 * R @ B.T
+    dA = _reverse(tape, Ubar, np.zeros(U.shape[1]), 2.0 * R, eta)
     return L, dA
+
+
+def vjp(A, col_sets, k: int, r: int, dU=None, dsigma=None, eta: float = 1e-12):
+    """dA for the adjoints dU (m x k) and dsigma (k) of the first k merged
+    modes and singular values (U_k, Sigma_k).  Returns (dA, U_k, Sigma_k)."""
+    A = np.asarray(A, dtype=np.float64)
+    U, s, tape = forward(A, col_sets, r)
+    kk = min(k, U.shape[1])
+    Ubar = np.zeros_like(U)
+    sbar = np.zeros(U.shape[1])
+    if dU is not None:
+        Ubar[:, :kk] = np.asarray(dU, dtype=np.float64)[:, :kk]
+    if dsigma is not None:
+        sbar[:kk] = np.asarray(dsigma, dtype=np.float64)[:kk]
+    dA = _reverse(tape, Ubar, sbar, np.zeros_like(A), eta)
+    return dA, U[:, :kk], s[:kk]
 
 
 def col_sets_of(logs) -> List[np.ndarray]:

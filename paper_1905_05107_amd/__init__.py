@@ -27,7 +27,8 @@ EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project"
            "pod_get_indices", "pod_get_col_sqnorms", "pod_col_sqnorms", "pod_sample_size", "pod_destroy",
            "pod_status_str", "pod_profile_enable", "pod_profile_read", "pod_inc_init", "pod_inc_add_block",
            "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy", "pod_batch_init",
-           "pod_batch_autotune", "pod_batch_run", "pod_batch_project", "pod_batch_get_info", "pod_batch_destroy"]
+           "pod_batch_autotune", "pod_batch_run", "pod_batch_project", "pod_batch_get_info", "pod_batch_destroy",
+           "pod_enable_adjoint", "pod_backward", "pod_loss_grad"]
 
 
 class PodError(RuntimeError):
@@ -102,6 +103,9 @@ def lib():
             "pod_batch_project": (i32, [vp, i32, vp, vp, vp]),
             "pod_batch_get_info": (i32, [vp, i32, P(pod_info), P(i32)]),
             "pod_batch_destroy": (None, [vp]),
+            "pod_enable_adjoint": (i32, [vp]),
+            "pod_backward": (i32, [vp, vp, vp, vp]),
+            "pod_loss_grad": (i32, [vp, vp, P(d)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -279,6 +283,39 @@ class PodContext:
         if rows:
             return cols[:g.value].copy(), cnt[:g.value].copy(), rws[:h.value].copy(), rcnt[:h.value].copy()
         return cols[:g.value].copy(), cnt[:g.value].copy()
+
+    # -- reverse mode
+    def enable_adjoint(self):
+        """Keep the per-merge checkpoints of the reverse pass (call first)."""
+        _check(lib().pod_enable_adjoint(self.h), "pod_enable_adjoint")
+
+    def _dA(self):
+        import torch
+        dt = torch.float64 if self.precision == POD_F64 else torch.float32
+        return torch.zeros((self.n, self.m), dtype=dt, device=self.A.device)
+
+    def loss_grad(self):
+        """(L, dL/dA) for L = |A - U_k U_k^T A|_F^2 of the merged modes."""
+        dAt = self._dA()
+        L = ctypes.c_double()
+        _check(lib().pod_loss_grad(self.h, ctypes.c_void_p(dAt.data_ptr()), ctypes.byref(L)), "pod_loss_grad")
+        return L.value, dAt.T
+
+    def backward(self, dU=None, dsigma=None, dA=None):
+        """dA += adjoint of (U_k, Sigma_k) for the output adjoints dU, dsigma."""
+        import torch
+        dAt = self._dA() if dA is None else dA.T
+        if dA is not None and not dAt.is_contiguous():
+            raise ValueError("dA must have contiguous columns (ld = m)")
+        dUt = None
+        if dU is not None:
+            dt = torch.float64 if self.precision == POD_F64 else torch.float32
+            dUt = dU.T.to(dt).contiguous()
+        ds = dsigma.to(torch.float64).contiguous() if dsigma is not None else None
+        _check(lib().pod_backward(self.h, ctypes.c_void_p(dUt.data_ptr()) if dUt is not None else None,
+                                  ctypes.c_void_p(ds.data_ptr()) if ds is not None else None,
+                                  ctypes.c_void_p(dAt.data_ptr())), "pod_backward")
+        return dAt.T
 
     def col_sqnorms(self):
         import numpy as np
@@ -481,6 +518,39 @@ class Batch:
         _check(lib().pod_batch_project(self.h, int(i), ctypes.c_void_p(Ut.data_ptr()), ctypes.c_void_p(sig.data_ptr()),
                                        ctypes.c_void_p(Vt.data_ptr()) if want_v else None), "pod_batch_project")
         return Ut.T, sig, (Vt.T if want_v else None)
+
+
+def _podfunction():
+    import torch
+
+    class PODFunction(torch.autograd.Function):
+        """(U_k, Sigma_k) of the merge chain of Alg. 1 as a differentiable
+        function of A; backward runs pod_backward (the sampled columns are
+        constants).  U_k is the basis before the final step."""
+
+        @staticmethod
+        def forward(fctx, A, k, c, kw):
+            pc = PodContext(A.detach(), k, c, **kw)
+            pc.enable_adjoint()
+            pc.run()
+            U, s = pc.basis()
+            kk = min(k, U.shape[1])
+            fctx.pc = pc
+            return U[:, :kk].clone(), s[:kk].clone()
+
+        @staticmethod
+        def backward(fctx, dU, dsigma):
+            pc = fctx.pc
+            dA = pc.backward(dU, dsigma)
+            pc.close()
+            return dA, None, None, None
+
+    return PODFunction
+
+
+def pod_function(A, k: int, c: int, **kw):
+    """Differentiable (U_k, Sigma_k) = ISMA merge chain of A (see PODFunction)."""
+    return _podfunction().apply(A, k, c, kw)
 
 
 POD_K = dict(colnorms=0, draw=1, gram=2, gram_reduce=3, chol=4, tall=5, svd=6, project=7, rr=8, sign=9)

@@ -1,0 +1,332 @@
+// pod_adjoint.hip -- reverse pass of the merge chain of Alg. 1 (ICS): the
+// gradient with respect to A of a function of the merged modes (U_k, Sigma_k),
+// the sampled columns held fixed.  The forward pass keeps, per merge, the
+// basis and Sigma it started from and the merge factor R (small); the
+// reverse pass recomputes the rest: per merge one Gram pass over
+// [U_{t-1} | A(:, I_t) | Ubar_t], the small FP64 adjoint of the truncated thin
+// SVD (k_adj_small), and one pass writing Ubar_{t-1} and adding the adjoint of
+// the sampled columns to dA(:, I_t).
+#include <math.h>
+
+#include <new>
+#include <vector>
+
+#include "pod_ctx.h"
+
+using namespace pod;
+
+namespace {
+
+#define A_HIP(call)                                                                                                   \
+    do {                                                                                                              \
+        hipError_t e_ = (call);                                                                                       \
+        if (e_ != hipSuccess) {                                                                                       \
+            ctx->failed = 1;                                                                                          \
+            return (e_ == hipErrorOutOfMemory) ? POD_ENOMEM : POD_EHIP;                                               \
+        }                                                                                                             \
+    } while (0)
+
+template <typename TC>
+__global__ __launch_bounds__(256) void k_ckpt_pre(const DevState *ds, const TC *U0, const TC *U1, const double *s0,
+                                                  const double *s1, int64_t m, int32_t r, TC *ckU, double *ckS,
+                                                  int32_t *meta, int32_t cap)
+{
+    if (ds->exhausted) return;
+    const int32_t t = ds->it;
+    if (t >= cap) return;
+    const int32_t rs = ds->rs;
+    const TC *U = (t & 1) ? U1 : U0;
+    const double *sg = (t & 1) ? s1 : s0;
+    TC *dst = ckU + (int64_t)t * m * r;
+    const int64_t total = m * rs;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256)
+        dst[idx] = U[idx];
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < rs; i += 256) ckS[(int64_t)t * r + i] = sg[i];
+        if (threadIdx.x == 0) {
+            meta[4 * t] = rs;
+            meta[4 * t + 1] = ds->g;
+            meta[4 * t + 3] = 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ckpt_post(const DevState *ds, const double *R, int32_t pm2, double *ckR,
+                                                   int32_t *meta, int32_t cap)
+{
+    if (ds->exhausted) return;
+    const int32_t t = ds->it - 1;
+    if (t < 0 || t >= cap) return;
+    for (int i = threadIdx.x; i < pm2; i += 256) ckR[(int64_t)t * pm2 + i] = R[i];
+    if (threadIdx.x == 0) {
+        meta[4 * t + 2] = ds->rnew;
+        meta[4 * t + 3] = 1;
+    }
+}
+
+__global__ void k_adj_state(DevState *ds, int32_t rs, int32_t g)
+{
+    ds->rs = rs;
+    ds->g = g;
+    ds->it = 0;
+    ds->exhausted = 0;
+    ds->done = 0;
+}
+
+// L = |A - U_k B|_F^2 (B = U_k^T A), dA = 2 (A - U_k B), Ubar = -2 (A - U_k B) B^T.
+// One thread per row, columns in order; per-workgroup loss partials.
+template <typename TC, typename TA, int KM>
+__global__ __launch_bounds__(256) void k_loss_resid(const TA *__restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                    const TC *__restrict__ U, int32_t k, const double *__restrict__ B,
+                                                    TC *__restrict__ dA, TC *__restrict__ Ubar,
+                                                    double *__restrict__ lossp)
+{
+    __shared__ double sw[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double u[KM], acc[KM];
+#pragma unroll
+    for (int l = 0; l < KM; ++l) {
+        u[l] = (i < m && l < k) ? (double)U[(int64_t)l * m + i] : 0.0;
+        acc[l] = 0.0;
+    }
+    double L = 0.0;
+    if (i < m) {
+        for (int64_t j = 0; j < n; ++j) {
+            const double *b = B + j * k;
+            double pr = 0.0;
+#pragma unroll
+            for (int l = 0; l < KM; ++l)
+                if (l < k) pr += u[l] * b[l];
+            const double R = (double)A[j * lda + i] - pr;
+            dA[j * m + i] = (TC)(2.0 * R);
+            L += R * R;
+#pragma unroll
+            for (int l = 0; l < KM; ++l)
+                if (l < k) acc[l] += R * b[l];
+        }
+#pragma unroll
+        for (int l = 0; l < KM; ++l)
+            if (l < k) Ubar[(int64_t)l * m + i] = (TC)(-2.0 * acc[l]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) L += __shfl_xor(L, o, 64);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = L;
+    __syncthreads();
+    if (threadIdx.x == 0) lossp[blockIdx.x] = ((sw[0] + sw[1]) + sw[2]) + sw[3];
+}
+
+template <typename TC, typename TA>
+hipError_t loss_resid_launch(const void *A, int64_t lda, int64_t m, int64_t n, const void *U, int32_t k,
+                             const double *B, void *dA, void *Ubar, double *lossp, hipStream_t st)
+{
+    const unsigned nb = (unsigned)((m + 255) / 256);
+    if (k <= 16)
+        hipLaunchKernelGGL((k_loss_resid<TC, TA, 16>), dim3(nb), dim3(256), 0, st, (const TA *)A, lda, m, n,
+                           (const TC *)U, k, B, (TC *)dA, (TC *)Ubar, lossp);
+    else
+        hipLaunchKernelGGL((k_loss_resid<TC, TA, 64>), dim3(nb), dim3(256), 0, st, (const TA *)A, lda, m, n,
+                           (const TC *)U, k, B, (TC *)dA, (TC *)Ubar, lossp);
+    return hipGetLastError();
+}
+
+// The reverse pass from (Ubar[0], sbar[0]) holding the adjoints of the final
+// merged state (all of its columns); dA accumulates.
+pod_status reverse_merges(pod_ctx *ctx, void *dA)
+{
+    const pod_params &p = ctx->prm;
+    const int32_t T = ctx->hs.it;
+    std::vector<int32_t> meta(4 * (size_t)(T > 0 ? T : 1)), off(T + 1);
+    if (T < 1) return POD_OK;
+    A_HIP(hipMemcpy(meta.data(), ctx->ckMeta, sizeof(int32_t) * 4 * T, hipMemcpyDeviceToHost));
+    A_HIP(hipMemcpy(off.data(), ctx->col_log_off, sizeof(int32_t) * (T + 1), hipMemcpyDeviceToHost));
+    for (int32_t t = 0; t < T; ++t)
+        if (meta[4 * t + 3] != 1) return POD_ESTATE;
+    const size_t esz = ctx->esz;
+    const double eta = (p.precision == POD_F64) ? 1e-12 : 1e-6;
+    int cur = 0;
+    for (int32_t t = T - 1; t >= 0; --t) {
+        const int32_t rs = meta[4 * t], g = meta[4 * t + 1], rz = meta[4 * t + 2];
+        const int32_t P = rs + g, Pext = P + rz;
+        hipLaunchKernelGGL(k_adj_state, dim3(1), dim3(1), 0, ctx->st, ctx->dsb, rs, g);
+        A_HIP(hipGetLastError());
+        GemmDesc gd;
+        gd.prec = p.precision;
+        gd.a_dtype = p.a_dtype;
+        gd.m = p.m;
+        gd.U = (const unsigned char *)ctx->ckU + (size_t)t * p.m * ctx->r * esz;
+        gd.U1 = nullptr;
+        gd.A = ctx->A;
+        gd.lda = p.lda;
+        gd.cols = ctx->col_log + off[t];
+        gd.Y = nullptr;
+        gd.gather = 1;
+        gd.guard = 0;
+        gd.Z = ctx->Ubar[cur];
+        A_HIP(launch_gram_partial(gd, ctx->dsb, Pext, ctx->pb, ctx->partb, ctx->nblk, ctx->st));
+        A_HIP(launch_gram_reduce_sel(ctx->partb, ctx->nblk, ctx->pb, ctx->dsb, Pext, ctx->Gext, ctx->st));
+        AdjArgs aa;
+        aa.Gext = ctx->Gext;
+        aa.pb = ctx->pb;
+        aa.R = ctx->ckR + (size_t)t * ctx->pmax * ctx->pmax;
+        aa.pm = ctx->pmax;
+        aa.sig = ctx->ckS + (size_t)t * ctx->r;
+        aa.sbar_in = ctx->sbar[cur];
+        aa.sbar_out = ctx->sbar[cur ^ 1];
+        aa.Wt = ctx->Wt;
+        aa.prec = p.precision;
+        aa.ws = ctx->adj_ws;
+        aa.rs = rs;
+        aa.g = g;
+        aa.rz = rz;
+        aa.eta = eta;
+        A_HIP(launch_adj_small(aa, ctx->st));
+        A_HIP(launch_gemm_tall_scatter(gd, ctx->dsb, Pext, P, Pext, P, ctx->Wt, ctx->pb, ctx->Ubar[cur ^ 1], rs,
+                                       ctx->col_log + off[t], dA, p.m, ctx->st));
+        cur ^= 1;
+    }
+    A_HIP(hipStreamSynchronize(ctx->st));
+    return POD_OK;
+}
+
+}  // namespace
+
+hipError_t pod::launch_ckpt_pre(pod_ctx *ctx, hipStream_t st)
+{
+    const int64_t m = ctx->prm.m;
+    const unsigned nb = (unsigned)(((m * ctx->r + 255) / 256 < 1024) ? (m * ctx->r + 255) / 256 : 1024);
+    if (ctx->esz == 8)
+        hipLaunchKernelGGL(k_ckpt_pre<double>, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, ctx->ds,
+                           (const double *)ctx->U[0], (const double *)ctx->U[1], ctx->sig[0], ctx->sig[1], m, ctx->r,
+                           (double *)ctx->ckU, ctx->ckS, ctx->ckMeta, ctx->ck_cap);
+    else
+        hipLaunchKernelGGL(k_ckpt_pre<float>, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, ctx->ds,
+                           (const float *)ctx->U[0], (const float *)ctx->U[1], ctx->sig[0], ctx->sig[1], m, ctx->r,
+                           (float *)ctx->ckU, ctx->ckS, ctx->ckMeta, ctx->ck_cap);
+    return hipGetLastError();
+}
+
+hipError_t pod::launch_ckpt_post(pod_ctx *ctx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ckpt_post, dim3(1), dim3(256), 0, st, ctx->ds, ctx->R2, ctx->pmax * ctx->pmax, ctx->ckR,
+                       ctx->ckMeta, ctx->ck_cap);
+    return hipGetLastError();
+}
+
+extern "C" {
+
+pod_status pod_enable_adjoint(pod_ctx *ctx)
+{
+    if (!ctx) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (ctx->merges > 0 || ctx->pending) return POD_ESTATE;
+    const pod_params &p = ctx->prm;
+    if (p.w != 0 || p.r_update != 0 || ctx->pmax > 64) return POD_EINVAL;
+    if (ctx->ckU) return POD_OK;
+    const int32_t cap = (int32_t)((p.max_iter < ctx->n_cap) ? p.max_iter : ctx->n_cap) + 1;
+    const int32_t pb = ((ctx->pmax + ctx->r) + 15) & ~15;
+    if (pb > 160) return POD_EINVAL;
+    ctx->ck_cap = cap;
+    ctx->pb = pb;
+    const size_t m = (size_t)p.m, r = (size_t)ctx->r, pm2 = (size_t)ctx->pmax * ctx->pmax;
+    hipError_t e = hipSuccess;
+    auto al = [&](void **q, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(q, bytes + 16);
+    };
+    al(&ctx->ckU, (size_t)cap * m * r * ctx->esz);
+    al((void **)&ctx->ckS, sizeof(double) * cap * r);
+    al((void **)&ctx->ckR, sizeof(double) * cap * pm2);
+    al((void **)&ctx->ckMeta, sizeof(int32_t) * 4 * cap);
+    al((void **)&ctx->dsb, sizeof(DevState));
+    al((void **)&ctx->partb, sizeof(double) * (size_t)ctx->nblk * pb * pb);
+    al((void **)&ctx->Gext, sizeof(double) * (size_t)pb * pb);
+    al((void **)&ctx->adj_ws, sizeof(double) * 10 * pm2);
+    al((void **)&ctx->sbar[0], sizeof(double) * r);
+    al((void **)&ctx->sbar[1], sizeof(double) * r);
+    al((void **)&ctx->lossp, sizeof(double) * ((m + 255) / 256));
+    al(&ctx->Wt, (size_t)pb * ctx->pmax * ctx->esz);
+    al(&ctx->Ubar[0], m * r * ctx->esz);
+    al(&ctx->Ubar[1], m * r * ctx->esz);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->ckMeta, 0, sizeof(int32_t) * 4 * cap, ctx->st);
+    if (e != hipSuccess) {
+        ctx->failed = 1;
+        return (e == hipErrorOutOfMemory) ? POD_ENOMEM : POD_EHIP;
+    }
+    return POD_OK;
+}
+
+pod_status pod_backward(pod_ctx *ctx, const void *dU, const double *dsigma, void *dA)
+{
+    if (!ctx || !dA) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (!ctx->ckU || ctx->pending) return POD_ESTATE;
+    pod_info info{};
+    pod_status s = pod_get_info(ctx, &info);
+    if (s != POD_OK) return s;
+    const int32_t rT = info.rank;
+    if (rT < 1) return POD_ESTATE;
+    const int32_t k = (ctx->prm.k < rT) ? ctx->prm.k : rT;
+    const size_t m = (size_t)ctx->prm.m;
+    A_HIP(hipMemsetAsync(ctx->Ubar[0], 0, m * rT * ctx->esz, ctx->st));
+    A_HIP(hipMemsetAsync(ctx->sbar[0], 0, sizeof(double) * rT, ctx->st));
+    if (dU) A_HIP(hipMemcpyAsync(ctx->Ubar[0], dU, m * k * ctx->esz, hipMemcpyDeviceToDevice, ctx->st));
+    if (dsigma) A_HIP(hipMemcpyAsync(ctx->sbar[0], dsigma, sizeof(double) * k, hipMemcpyDeviceToDevice, ctx->st));
+    return reverse_merges(ctx, dA);
+}
+
+pod_status pod_loss_grad(pod_ctx *ctx, void *dA, double *loss)
+{
+    if (!ctx || !dA) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (!ctx->ckU || ctx->pending) return POD_ESTATE;
+    pod_info info{};
+    pod_status s = pod_get_info(ctx, &info);
+    if (s != POD_OK) return s;
+    const int32_t rT = info.rank;
+    if (rT < 1) return POD_ESTATE;
+    const int32_t k = (ctx->prm.k < rT) ? ctx->prm.k : rT;
+    if (k > 64) return POD_EINVAL;
+    const pod_params &p = ctx->prm;
+    const size_t m = (size_t)p.m;
+    // B = U_k^T A (one pass over A)
+    ProjArgs pa;
+    pa.prec = p.precision;
+    pa.a_dtype = p.a_dtype;
+    pa.m = p.m;
+    pa.n = p.n;
+    pa.lda = p.lda;
+    pa.U = ctx->U[ctx->cur];
+    pa.A = ctx->A;
+    pa.r = k;
+    pa.Bpart = ctx->Bpart;
+    pa.nsplit = ctx->nsplit;
+    pa.B = ctx->B;
+    A_HIP(launch_project_partial(pa, ctx->st));
+    A_HIP(launch_project_reduce(pa, ctx->st));
+    A_HIP(hipMemsetAsync(ctx->Ubar[0], 0, m * rT * ctx->esz, ctx->st));
+    A_HIP(hipMemsetAsync(ctx->sbar[0], 0, sizeof(double) * rT, ctx->st));
+    hipError_t e;
+    if (p.precision == POD_F64) {
+        if (p.a_dtype == POD_F64)
+            e = loss_resid_launch<double, double>(ctx->A, p.lda, p.m, p.n, ctx->U[ctx->cur], k, ctx->B, dA,
+                                                  ctx->Ubar[0], ctx->lossp, ctx->st);
+        else
+            e = loss_resid_launch<double, float>(ctx->A, p.lda, p.m, p.n, ctx->U[ctx->cur], k, ctx->B, dA,
+                                                 ctx->Ubar[0], ctx->lossp, ctx->st);
+    } else {
+        e = loss_resid_launch<float, float>(ctx->A, p.lda, p.m, p.n, ctx->U[ctx->cur], k, ctx->B, dA, ctx->Ubar[0],
+                                            ctx->lossp, ctx->st);
+    }
+    A_HIP(e);
+    if (loss) {
+        const size_t nb = (m + 255) / 256;
+        std::vector<double> lp(nb);
+        A_HIP(hipMemcpyAsync(lp.data(), ctx->lossp, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->st));
+        A_HIP(hipStreamSynchronize(ctx->st));
+        double L = 0.0;
+        for (size_t i = 0; i < nb; ++i) L += lp[i];
+        *loss = L;
+    }
+    return reverse_merges(ctx, dA);
+}
+
+}  // extern "C"

@@ -51,7 +51,8 @@ void free_all(pod_ctx *ctx)
                     ctx->G,    ctx->R1,   ctx->R2,    ctx->work, ctx->Tc,   ctx->Y,    ctx->Bpart,
                     ctx->B,    ctx->GB,   ctx->UB,    ctx->sigB, ctx->Zc, ctx->signv, ctx->signi,
                     ctx->rho,  ctx->Vt,   ctx->wr,    ctx->rows, ctx->rcnt, ctx->row_log, ctx->rcnt_log,
-                    ctx->ws};
+                    ctx->ws,   ctx->ckU,  ctx->ckS,   ctx->ckR,  ctx->ckMeta, ctx->dsb, ctx->partb, ctx->Gext,
+                    ctx->adj_ws, ctx->sbar[0], ctx->sbar[1], ctx->lossp, ctx->Wt, ctx->Ubar[0], ctx->Ubar[1]};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -70,6 +71,7 @@ GemmDesc gather_desc(pod_ctx *ctx)
     d.Y = nullptr;
     d.gather = 1;
     d.guard = 1;
+    d.Z = nullptr;
     return d;
 }
 
@@ -109,6 +111,7 @@ GemmDesc plain_desc(pod_ctx *ctx, const void *Y)
 pod_status merge_launch(pod_ctx *ctx, const GemmDesc &gd, const double *sigma2, bool use_vt, bool block_eig_mode1)
 {
     const int32_t pm = ctx->pmax;
+    if (ctx->ckU) POD_HIP(launch_ckpt_pre(ctx, ctx->st));
     // pass 1: G0 = X0^T X0, X0 = [U | A(:, I_c)] gathered on the fly
     POD_HIP(launch_gram_partial(gd, ctx->ds, -1, pm, ctx->part, ctx->nblk, ctx->st));
     POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -1, ctx->G, ctx->st));
@@ -128,6 +131,7 @@ pod_status merge_launch(pod_ctx *ctx, const GemmDesc &gd, const double *sigma2, 
     POD_HIP(launch_gram_partial(yd, ctx->ds, -2, pm, ctx->part, ctx->nblk, ctx->st));
     POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -2, ctx->G, ctx->st));
     POD_HIP(launch_svd_merge(sa, ctx->st));
+    if (ctx->ckU) POD_HIP(launch_ckpt_post(ctx, ctx->st));
     // U_new = Q1 R2^-1 U_R(:, 0:r')
     // (svd_merge advanced the merge count: U[it & 1] is the new basis)
     POD_HIP(launch_gemm_tall(yd, ctx->ds, -2, -3, pm, ctx->r, ctx->Tc, pm, ctx->U[0], ctx->U[1], ctx->st));

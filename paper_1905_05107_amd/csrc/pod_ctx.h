@@ -39,6 +39,15 @@ struct pod_ctx {
     int exhausted = 0;       // known on the host
     int failed = 0;          // a HIP error happened: only destroy is allowed
     int32_t forced_g = -1;   // replay of the next draw
+    // reverse pass (pod_enable_adjoint): per-merge checkpoints and buffers
+    int32_t ck_cap = 0, pb = 0;
+    void *ckU = nullptr;     // basis before each merge (cap x m x r, compute type)
+    double *ckS = nullptr;   // Sigma before each merge (cap x r)
+    double *ckR = nullptr;   // merge factor R of each merge (cap x pmax^2)
+    int32_t *ckMeta = nullptr;  // per merge: rs, g, rank after, valid
+    pod::DevState *dsb = nullptr;
+    double *partb = nullptr, *Gext = nullptr, *adj_ws = nullptr, *sbar[2] = {nullptr, nullptr}, *lossp = nullptr;
+    void *Wt = nullptr, *Ubar[2] = {nullptr, nullptr};
 };
 
 namespace pod {
@@ -56,6 +65,11 @@ pod_status ctx_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out
 // [U Sigma | Ub diag(sb)] (Ub m x rb in the compute type, ld m; sb device FP64),
 // truncated to r.  The first call on an empty state takes (Ub, sb) as is.
 pod_status ctx_merge_basis(pod_ctx *ctx, const void *Ub, const double *sb, int32_t rb);
+
+// Checkpoints of the reverse pass around a merge (no-ops when the pending
+// draw found S exhausted).
+hipError_t launch_ckpt_pre(pod_ctx *ctx, hipStream_t st);
+hipError_t launch_ckpt_post(pod_ctx *ctx, hipStream_t st);
 
 // Argument blocks of one context's launches (shared with the batched path).
 DrawArgs ctx_draw_args(pod_ctx *ctx);

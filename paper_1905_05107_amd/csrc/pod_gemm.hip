@@ -34,6 +34,8 @@ template <typename TC> struct SrcT {
     int32_t a_f64;        // A stored in FP64
     int32_t rs;           // columns of U in X0
     int32_t guard;        // skip when the pending draw found S exhausted
+    const TC *Z;          // third block of a gathered source (nullable)
+    int32_t g;            // columns of the A block when Z is set
 };
 
 __device__ __forceinline__ int sel_count(const DevState *ds, int sel)
@@ -60,6 +62,9 @@ template <typename TC> __device__ __forceinline__ ColPtr col_ptr(const SrcT<TC> 
         r.f64 = sizeof(TC) == 8;
     } else if (c < s.rs) {
         r.p = s.U + (int64_t)c * m;
+        r.f64 = sizeof(TC) == 8;
+    } else if (s.Z && c >= s.rs + s.g) {
+        r.p = s.Z + (int64_t)(c - s.rs - s.g) * m;
         r.f64 = sizeof(TC) == 8;
     } else {
         const int64_t j = s.cols[c - s.rs];
@@ -147,7 +152,7 @@ template <typename TC> static bool vec_ok(const SrcT<TC> &s, int64_t m)
     const size_t esz = sizeof(TC);
     bool ok = ((m * esz) % 16 == 0);
     if (s.gather) {
-        ok = ok && ((uintptr_t)s.U % 16 == 0) && ((uintptr_t)s.U1 % 16 == 0);
+        ok = ok && ((uintptr_t)s.U % 16 == 0) && ((uintptr_t)s.U1 % 16 == 0) && ((uintptr_t)s.Z % 16 == 0);
         const size_t ae = s.a_f64 ? 8 : 4;
         ok = ok && ((uintptr_t)s.A % 16 == 0) && ((s.lda * ae) % 16 == 0);
     } else {
@@ -161,6 +166,8 @@ template <typename TC> __host__ __device__ SrcT<TC> make_src(const GemmDesc &d)
     SrcT<TC> s;
     s.U = reinterpret_cast<const TC *>(d.U);
     s.U1 = reinterpret_cast<const TC *>(d.U1);
+    s.Z = reinterpret_cast<const TC *>(d.Z);
+    s.g = 0;
     s.A = d.A;
     s.lda = d.lda;
     s.cols = d.cols;
@@ -195,6 +202,7 @@ __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const D
     if (s.guard && ds->exhausted) return;
     const int P = sel_count(ds, which_p);
     s.rs = ds->rs;
+    s.g = ds->g;
     if (s.U1 && (ds->it & 1)) s.U = s.U1;
     const int PP = (P + 15) & ~15;
     const int NT16 = PP / 16;
@@ -351,10 +359,21 @@ hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax
 constexpr int TALL_ST = 4;   // row stages per workgroup
 constexpr size_t TALL_T_LDS = 112 * 1024;  // largest T staged in LDS
 
-template <typename TC, int ITEMS, bool TG>
+// Scatter output (SCAT): output columns below `split` go to Yout, column
+// split + j is added to D(:, cmap[j]) (leading dimension ldd); the mapped
+// columns are distinct, so each element has one writer.
+struct TallScatter {
+    int32_t split;
+    const int32_t *cmap;
+    void *D;
+    int64_t ldd;
+};
+
+template <typename TC, int ITEMS, bool TG, bool SCAT = false>
 __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in, int sel_out,
                                                int pmax_in, int pmax_out, const TC *__restrict__ T, int ldt,
-                                               TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec, int bid)
+                                               TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec, int bid,
+                                               TallScatter sc = TallScatter{0, nullptr, nullptr, 0})
 {
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
@@ -362,6 +381,7 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
     if (Yout1 && (ds->it & 1)) Yout = Yout1;
     const int pin = sel_count(ds, sel_in), pout = sel_count(ds, sel_out);
     s.rs = ds->rs;
+    s.g = ds->g;
     if (s.U1 && (ds->it & 1)) s.U = s.U1;
     const int PI = (pin + 15) & ~15, PO = (pout + 15) & ~15;
     TC *Xs = reinterpret_cast<TC *>(lds_raw);        // pmax_in x LDSR
@@ -405,7 +425,13 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int col = jc * 16 + acc_row<TC>(lane, v);
-                    if (col < pout) Yout[(int64_t)col * m + row] = acc[v];
+                    if (col >= pout) continue;
+                    if (!SCAT || col < sc.split) {
+                        Yout[(int64_t)col * m + row] = acc[v];
+                    } else {
+                        TC *d = reinterpret_cast<TC *>(sc.D) + (int64_t)sc.cmap[col - sc.split] * sc.ldd + row;
+                        *d += acc[v];
+                    }
                 }
             }
         }
@@ -419,6 +445,15 @@ __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const 
 {
     gemm_tall_body<TC, ITEMS, TG>(s, m, ds, sel_in, sel_out, pmax_in, pmax_out, T, ldt, Yout, Yout1, vec,
                                   blockIdx.x);
+}
+
+template <typename TC, int ITEMS>
+__global__ __launch_bounds__(256) void k_gemm_tall_scatter(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
+                                                           int sel_out, int pmax_in, const TC *__restrict__ T,
+                                                           int ldt, TC *__restrict__ Yout, TallScatter sc, int vec)
+{
+    gemm_tall_body<TC, ITEMS, false, true>(s, m, ds, sel_in, sel_out, pmax_in, 0, T, ldt, Yout, nullptr, vec,
+                                           blockIdx.x, sc);
 }
 
 template <typename TC, int ITEMS>
@@ -512,6 +547,8 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
     SrcT<TC> su;
     su.U = nullptr;
     su.U1 = nullptr;
+    su.Z = nullptr;
+    su.g = 0;
     su.A = nullptr;
     su.lda = 0;
     su.cols = nullptr;
@@ -681,6 +718,56 @@ hipError_t launch_gemm_tall_b(const TallArgs *arr, int32_t count, int32_t max_nb
     else
         hipLaunchKernelGGL((k_gemm_tall_b<float, ITEMS64>), grid, dim3(256),
                            (size_t)(pi_max * LDSR + pi_max * po_max) * sizeof(float), st, arr);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
+                                    int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout,
+                                    int32_t split, const int32_t *cmap, void *D, int64_t ldd, hipStream_t st)
+{
+    const int PI = (pin_max + 15) & ~15, PO = (pout_max + 15) & ~15;
+    const size_t esz = (d.prec == POD_F64) ? 8 : 4;
+    if (PI > PMAX_WIDE || PO > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)tall_blocks(d.m);
+    const TallScatter sc{split, cmap, D, ldd};
+    const size_t lds = (size_t)(PI * LDSR + PI * PO) * esz;
+    if (d.prec == POD_F64) {
+        const SrcT<double> s = make_src<double>(d);
+        if (PI > 64) {
+            static bool attr = false;
+            if (!attr) {
+                if (hipFuncSetAttribute((const void *)k_gemm_tall_scatter<double, ITEMS160>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+                    return hipErrorInvalidValue;
+                attr = true;
+            }
+            hipLaunchKernelGGL((k_gemm_tall_scatter<double, ITEMS160>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
+                               which_in, which_out, PI, (const double *)T, ldt, (double *)Yout, sc,
+                               (int)vec_ok(s, d.m));
+        } else {
+            hipLaunchKernelGGL((k_gemm_tall_scatter<double, ITEMS64>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
+                               which_in, which_out, PI, (const double *)T, ldt, (double *)Yout, sc,
+                               (int)vec_ok(s, d.m));
+        }
+    } else {
+        const SrcT<float> s = make_src<float>(d);
+        if (PI > 64) {
+            static bool attr = false;
+            if (!attr) {
+                if (hipFuncSetAttribute((const void *)k_gemm_tall_scatter<float, ITEMS160>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+                    return hipErrorInvalidValue;
+                attr = true;
+            }
+            hipLaunchKernelGGL((k_gemm_tall_scatter<float, ITEMS160>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
+                               which_in, which_out, PI, (const float *)T, ldt, (float *)Yout, sc,
+                               (int)vec_ok(s, d.m));
+        } else {
+            hipLaunchKernelGGL((k_gemm_tall_scatter<float, ITEMS64>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
+                               which_in, which_out, PI, (const float *)T, ldt, (float *)Yout, sc,
+                               (int)vec_ok(s, d.m));
+        }
+    }
     return hipGetLastError();
 }
 

@@ -156,6 +156,8 @@ struct GemmDesc {
     const void *Y;        // contiguous m x P source (compute type), ld = m (when gather == 0)
     int32_t gather;       // 1: source is X0 = [U | A(:, cols)], 0: Y
     int32_t guard;        // 1: skip when the pending draw found S exhausted
+    const void *Z;        // nullable: gathered source extended to [U | A(:, cols) | Z] (compute type, ld m),
+                          // the A block being ds->g columns wide
 };
 // Partial Grams of the first `P` (device count) columns of the source, P <= pmax.
 // Kernels launched with guard = 1 do nothing when the pending draw found S exhausted.
@@ -196,6 +198,12 @@ hipError_t launch_gemm_tall_b(const TallArgs *arr, int32_t count, int32_t max_nb
 int32_t gemm_vec_ok(const GemmDesc &d);
 int32_t tall_blocks(int64_t m);
 
+// Y = source T as launch_gemm_tall (no parity selection), except that output
+// column split + j is added to D(:, cmap[j]) (ld ldd) instead of being stored.
+hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
+                                    int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout,
+                                    int32_t split, const int32_t *cmap, void *D, int64_t ldd, hipStream_t st);
+
 struct SmallArgs {
     DevState *ds;
     const double *Vt;      // right factor of the new block (g x ru, ld pmax) when use_vt
@@ -204,7 +212,7 @@ struct SmallArgs {
     const double *sigma2;  // weights of the new block's columns (nullable: 1)
     const double *G;       // reduced Gram (pmax x pmax, ld pmax)
     double *R1;            // (pmax x pmax)
-    double *R2;            // (pmax x pmax)
+    double *R2;            // (pmax x pmax) receives the merge factor R = R2 R1
     void *Tc;              // transform in compute type (pmax x pmax, ld pmax)
     double *work;          // scratch (pmax x pmax)
     double *ws;            // matrices of the kernel when pmax > 64 (3 pmax^2 + pmax)
@@ -240,6 +248,24 @@ hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st);
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st);
 hipError_t launch_chol_first_b(const SmallArgs *arr, int32_t count, int32_t pmax_max, hipStream_t st);
 hipError_t launch_svd_merge_b(const SmallArgs *arr, int32_t count, int32_t pmax_max, hipStream_t st);
+
+// One step of the reverse pass through merge t (adjoint of its truncated
+// thin SVD, see k_adj_small).
+struct AdjArgs {
+    const double *Gext;    // Gram of [U_{t-1} | A(:, I_t) | Ubar_t] (ld pb)
+    int32_t pb;
+    const double *R;       // merge factor of merge t (ld pm)
+    int32_t pm;
+    const double *sig;     // Sigma_{t-1} (rs)
+    const double *sbar_in; // adjoint of Sigma_t (rz)
+    double *sbar_out;      // adjoint of Sigma_{t-1} (rs)
+    void *Wt;              // out: ((p + rz) x p, ld pb, compute type)
+    int32_t prec;
+    double *ws;            // 10 pm^2 doubles
+    int32_t rs, g, rz;
+    double eta;            // gap guard
+};
+hipError_t launch_adj_small(const AdjArgs &a, hipStream_t st);
 
 struct ProjArgs {
     int32_t prec, a_dtype;

@@ -318,6 +318,7 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
         double s = 0.0;
         for (int l = i; l <= j; ++l) s += S1[i + l * p] * S2[l + j * p];
         S3[idx] = (i <= j) ? s : 0.0;
+        a.R2[i + j * pm] = (i <= j) ? s : 0.0;   // the merge factor R, kept for the adjoint
     }
     __syncthreads();
     const int kk0 = (a.k < rs) ? a.k : rs;
@@ -750,6 +751,158 @@ hipError_t launch_svd_merge_b(const SmallArgs *arr, int32_t count, int32_t pmax_
     hipLaunchKernelGGL(k_svd_merge_b, dim3(1, (unsigned)count), dim3(NT),
                        (size_t)(3 * pmax_max * pmax_max + EIG_LU_THREADS * eig_lu_stride(pmax_max)) * sizeof(double),
                        st, arr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reverse pass through one merge (adjoint of BLOCK MERGE, Alg. 2).  Forward:
+// M = X0 P (X0 = [U_{t-1} | A(:, I_t)], P = diag(Sigma_{t-1}, I)), M = Q R,
+// R = U_R S V^T, outputs U_t = Q U_R(:, 0:rz), Sigma_t = S(0:rz).  With the
+// output adjoints (Ubar, sbar) the adjoint of M is (thin-SVD adjoint,
+// Townsend 2016, V-bar = 0, guarded coupling F)
+//   Mbar = U K V^T + (I - U U^T) Ubar S_r^-1 V_r^T,   U = Q U_R,
+//   K = (F o (J - J^T)) S + diag(sbar),   J = U^T Ubar.
+// Everything reduces to small matrices: with Z = Q^T Ubar = R^-T P (X0^T Ubar)
+// and Vs = V S = R^T U_R,
+//   Mbar = Q W1 + Ubar W2,  W1 = U_R [(F o (J - J^T)) Vs^T + diag(sbar) V_r^T] - Z S_r^-2 Vs_r^T,
+//   W2 = S_r^-2 Vs_r^T,
+// and the adjoint of X0 is X0bar = Mbar P = [X0 | Ubar] Wt with
+// Wt = [P R^-1 W1 P ; W2 P].  Its first rs columns are Ubar_{t-1}; the rest
+// belong to A(:, I_t).  sbar_{t-1,i} = U_{t-1}(:, i)^T Mbar(:, i) comes from the
+// Gram of [X0 | Ubar].  The eigen-decomposition of R R^T is recomputed here.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_adj_small(AdjArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
+        sdots[EIG_NMAX], ssc[8], sS[EIG_NMAX], sP[EIG_NMAX];
+    __shared__ __align__(8) int scl[EIG_NMAX + 8];
+    const int rs = a.rs, p = a.rs + a.g, rz = a.rz, pm = a.pm, pb = a.pb;
+    const int t = threadIdx.x;
+    double *H = lds, *Y = lds + p * p, *lu = lds + 2 * p * p;
+    const int q2 = pm * pm;
+    double *wR = a.ws, *wRi = wR + q2, *wUR = wRi + q2, *wV = wUR + q2, *wZ = wV + q2, *wJ = wZ + q2, *wK = wJ + q2,
+           *wN = wK + q2, *wW = wN + q2, *wT = wW + q2;
+    for (int idx = t; idx < p * p; idx += NT) {
+        const int i = idx % p, j = idx / p;
+        const double v = a.R[i + j * pm];
+        wR[idx] = v;
+        wRi[idx] = v;
+    }
+    for (int i = t; i < p; i += NT) sP[i] = (i < rs) ? a.sig[i] : 1.0;
+    __syncthreads();
+    for (int idx = t; idx < p * p; idx += NT) {
+        const int i = idx % p, j = idx / p;
+        const int l0 = (i > j) ? i : j;
+        double s = 0.0;
+        for (int l = l0; l < p; ++l) s += wR[i + l * p] * wR[j + l * p];
+        H[idx] = s;
+    }
+    __syncthreads();
+    trinv_upper(wRi, p, spv);
+    tridiag(H, p, sd, se, stau, spv, ssc);
+    bisect_top(sd, se, p, p, sev, se2, ssc);
+    tri_invit(sd, se, p, sev, p, Y, lu, scl);
+    tridiag_backtransform(H, stau, p, Y, p, sdots);
+    for (int i = t; i < p; i += NT) sS[i] = sqrt(fmax(sev[i], 0.0));
+    for (int idx = t; idx < p * p; idx += NT) wUR[idx] = Y[idx];
+    __syncthreads();
+    // Vs = R^T U_R;  Z = R^-T (P X0^T Ubar)
+    for (int idx = t; idx < p * p; idx += NT) {
+        const int i = idx % p, j = idx / p;
+        double s = 0.0;
+        for (int l = 0; l <= i; ++l) s += wR[l + i * p] * wUR[l + j * p];
+        wV[idx] = s;
+    }
+    for (int idx = t; idx < p * rz; idx += NT) {
+        const int i = idx % p, j = idx / p;
+        double s = 0.0;
+        for (int l = 0; l <= i; ++l) s += wRi[l + i * p] * sP[l] * a.Gext[l + (p + j) * pb];
+        wZ[i + j * p] = s;
+    }
+    __syncthreads();
+    // J = U_R^T Z (p x rz)
+    for (int idx = t; idx < p * rz; idx += NT) {
+        const int i = idx % p, j = idx / p;
+        double s = 0.0;
+        for (int l = 0; l < p; ++l) s += wUR[l + i * p] * wZ[l + j * p];
+        wJ[i + j * p] = s;
+    }
+    __syncthreads();
+    // K~ = F o (J - J^T)  (J zero beyond column rz)
+    {
+        const double l1 = sS[0] * sS[0];
+        const double gl = a.eta * l1;
+        for (int idx = t; idx < p * p; idx += NT) {
+            const int i = idx % p, j = idx / p;
+            double v = 0.0;
+            if (i != j) {
+                const double d = sS[j] * sS[j] - sS[i] * sS[i];
+                const double f = d / (d * d + gl * gl);
+                const double jij = (j < rz) ? wJ[i + j * p] : 0.0;
+                const double jji = (i < rz) ? wJ[j + i * p] : 0.0;
+                v = f * (jij - jji);
+            }
+            wK[idx] = v;
+        }
+    }
+    __syncthreads();
+    // N = K~ Vs^T + diag(sbar) V_r^T   (V_r = Vs_r S_r^-1)
+    for (int idx = t; idx < p * p; idx += NT) {
+        const int i = idx % p, c = idx / p;
+        double s = 0.0;
+        for (int j = 0; j < p; ++j) s += wK[i + j * p] * wV[c + j * p];
+        if (i < rz) s += a.sbar_in[i] / sS[i] * wV[c + i * p];
+        wN[idx] = s;
+    }
+    __syncthreads();
+    // W1 = U_R N - Z S_r^-2 Vs_r^T
+    for (int idx = t; idx < p * p; idx += NT) {
+        const int r0 = idx % p, c = idx / p;
+        double s = 0.0;
+        for (int i = 0; i < p; ++i) s += wUR[r0 + i * p] * wN[i + c * p];
+        for (int j = 0; j < rz; ++j) s -= wZ[r0 + j * p] * wV[c + j * p] / (sS[j] * sS[j]);
+        wW[idx] = s;
+    }
+    __syncthreads();
+    // T = P R^-1 W1 (the factor of Mbar on X0)
+    for (int idx = t; idx < p * p; idx += NT) {
+        const int r0 = idx % p, c = idx / p;
+        double s = 0.0;
+        for (int l = r0; l < p; ++l) s += wRi[r0 + l * p] * wW[l + c * p];
+        wT[idx] = sP[r0] * s;
+    }
+    __syncthreads();
+    // Wt = [T P ; W2 P]
+    for (int idx = t; idx < (p + rz) * p; idx += NT) {
+        const int row = idx % (p + rz), c = idx / (p + rz);
+        double v;
+        if (row < p) v = wT[row + c * p] * sP[c];
+        else v = wV[c + (row - p) * p] / (sS[row - p] * sS[row - p]) * sP[c];
+        store_c(a.Wt, a.prec, row + (int64_t)c * pb, v);
+    }
+    // sbar_{t-1,i} = [X0^T X0 T + X0^T Ubar W2]_{ii}
+    for (int i = t; i < rs; i += NT) {
+        double s = 0.0;
+        for (int l = 0; l < p; ++l) s += a.Gext[i + l * pb] * wT[l + i * p];
+        for (int j = 0; j < rz; ++j) s += a.Gext[i + (p + j) * pb] * wV[i + j * p] / (sS[j] * sS[j]);
+        a.sbar_out[i] = s;
+    }
+}
+
+hipError_t launch_adj_small(const AdjArgs &a, hipStream_t st)
+{
+    const int p = a.rs + a.g;
+    if (a.pm > SMALL_LDS_P || p > a.pm) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_adj_small, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_limit(false));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const size_t lds = (size_t)(2 * p * p + EIG_LU_THREADS * eig_lu_stride(p)) * sizeof(double);
+    hipLaunchKernelGGL(k_adj_small, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
 

@@ -431,3 +431,82 @@ def test_batch_autotuned_matches_oracle():
             ang = _angles(ref.U, U.cpu().numpy())
             print(f"  matrix {i}: iters={inf.iter} nblk={nblk} sigma_rel={rel:.2e} angle={ang:.2e}", flush=True)
             assert rel <= 1e-10 and ang <= 1e-8
+
+
+# ------------------------------------------------------------------ reverse mode
+
+@pytest.fixture(scope="module")
+def adj_case():
+    from oracle import adjoint as adj
+    sm = snapgen.spectrum_matrix(500, 100, np.exp(-np.arange(100) / 6.0), 1e-8, seed=1005, centre=False,
+                                 v_orthogonal_to_ones=False)
+    kw = dict(k=4, c=8, seed=2005, theta_tol=1e-8)
+    ref = oracle_isma(sm.A, IsmaParams(**kw), final_step=False)
+    return sm.A, kw, adj.col_sets_of(ref.log)
+
+
+def test_loss_gradient_fp64_matches_oracle_and_fd(adj_case):
+    """FP64 gradient of |A - U_k U_k^T A|^2 against the oracle's reverse pass
+    and against central differences of the oracle's loss (h = 1e-6)."""
+    from oracle import adjoint as adj
+    A, kw, cs = adj_case
+    print("adjoint fp64", flush=True)
+    with pod.PodContext(_dev(A), precision=pod.POD_F64, **kw) as ctx:
+        ctx.enable_adjoint()
+        ctx.run()
+        for it, c in enumerate(cs):
+            assert np.array_equal(ctx.indices(it)[0], c)
+        L, dA = ctx.loss_grad()
+        dA = dA.cpu().numpy()
+    Lr, Gr = adj.loss_and_grad(A, cs, 4, 4)
+    rel = np.linalg.norm(dA - Gr) / np.linalg.norm(Gr)
+    print(f"  loss rel={abs(L - Lr) / Lr:.2e} grad rel={rel:.2e}", flush=True)
+    assert abs(L - Lr) <= 1e-10 * Lr
+    assert rel <= 1e-8
+    rng = np.random.default_rng(3)
+    for _ in range(8):
+        E = rng.standard_normal(A.shape)
+        E /= np.linalg.norm(E)
+        fd = adj.fd_directional(A, cs, 4, 4, E)
+        an = float(np.sum(dA * E))
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-2 * np.linalg.norm(dA))
+
+
+def test_backward_vjp_fp64_and_autograd(adj_case):
+    """pod_backward for given (dU, dsigma) against the oracle (columns of the
+    two bases may differ in sign: dU is mapped accordingly), and the same
+    through torch.autograd."""
+    from oracle import adjoint as adj
+    A, kw, cs = adj_case
+    rng = np.random.default_rng(4)
+    Ad = _dev(A).requires_grad_(True)
+    U, s = pod.pod_function(Ad, kw["k"], kw["c"], precision=pod.POD_F64, seed=kw["seed"],
+                            theta_tol=kw["theta_tol"])
+    dU = rng.standard_normal(U.shape)
+    ds = rng.standard_normal(s.shape)
+    (U * torch.from_numpy(dU).cuda()).sum().add((s * torch.from_numpy(ds).cuda()).sum()).backward()
+    got = Ad.grad.cpu().numpy()
+    _, Uo, so = adj.vjp(A, cs, 4, 4)
+    sg = np.sign(np.sum(Uo * U.detach().cpu().numpy(), axis=0))
+    want, _, _ = adj.vjp(A, cs, 4, 4, dU=dU * sg[None, :], dsigma=ds)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"  vjp rel={rel:.2e}", flush=True)
+    assert np.max(np.abs(s.detach().cpu().numpy() - so) / so) <= 1e-10
+    assert rel <= 1e-8
+
+
+def test_loss_gradient_fp32_path(adj_case):
+    """FP32 merges, the same reverse pass: within the FP32 conditioning."""
+    from oracle import adjoint as adj
+    A, kw, cs = adj_case
+    A32 = A.astype(np.float32)
+    with pod.PodContext(_dev(A32), precision=pod.POD_F32, **kw) as ctx:
+        ctx.enable_adjoint()
+        ctx.run()
+        got_cs = [ctx.indices(i)[0] for i in range(ctx.info().iter)]
+        L, dA = ctx.loss_grad()
+    Lr, Gr = adj.loss_and_grad(A32.astype(np.float64), got_cs, 4, 4)
+    rel = np.linalg.norm(dA.cpu().numpy() - Gr) / np.linalg.norm(Gr)
+    print(f"  fp32 loss rel={abs(L - Lr) / Lr:.2e} grad rel={rel:.2e}", flush=True)
+    assert abs(L - Lr) <= 1e-4 * Lr
+    assert rel <= 1e-2

@@ -83,3 +83,33 @@ def test_indirect_term_is_not_negligible(fd_case):
     Uk = U[:, :4]
     Ge = 2.0 * (A - Uk @ (Uk.T @ A))
     assert np.linalg.norm(G - Ge) >= 1e-3 * np.linalg.norm(G)
+
+
+def test_vjp_of_singular_values_matches_central_differences(fd_case):
+    """The reverse pass from Sigma-bar alone: f(A) = <w, Sigma_k(A)>."""
+    A, _, cs = fd_case
+    w = np.array([1.0, -0.5, 0.25, 2.0])
+    dA, _, _ = adj.vjp(A, cs, 4, 4, dsigma=w)
+    rng = np.random.default_rng(5)
+
+    def f(X):
+        return float(np.dot(w, adj.forward(X, cs, 4)[1][:4]))
+
+    for _ in range(8):
+        E = rng.standard_normal(A.shape)
+        E /= np.linalg.norm(E)
+        fd = (f(A + 1e-6 * E) - f(A - 1e-6 * E)) / 2e-6
+        an = float(np.sum(dA * E))
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-2 * np.linalg.norm(dA))
+
+
+def test_loss_gradient_equals_explicit_plus_vjp(fd_case):
+    """loss_and_grad = 2R + vjp(U-bar = -2 R B^T): the two entry points agree."""
+    A, _, cs = fd_case
+    L, G = adj.loss_and_grad(A, cs, 4, 4)
+    U, _, _ = adj.forward(A, cs, 4)
+    Uk = U[:, :4]
+    B = Uk.T @ A
+    R = A - Uk @ B
+    dA, _, _ = adj.vjp(A, cs, 4, 4, dU=-2.0 * R @ B.T)
+    assert np.linalg.norm(G - (2.0 * R + dA)) <= 1e-13 * np.linalg.norm(G)
