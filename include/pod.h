@@ -244,6 +244,14 @@ pod_status pod_batch_autotune(pod_batch *b, int32_t *table_entries);
  * is still running after max_rounds.  Syncs. */
 pod_status pod_batch_run(pod_batch *b, int32_t use_graph, int32_t max_rounds, int32_t *rounds_out);
 
+/* Keep the reverse-pass checkpoints of every matrix (pod_enable_adjoint for
+ * each; same restrictions); call before pod_batch_run. */
+pod_status pod_batch_enable_adjoint(pod_batch *b);
+
+/* pod_loss_grad for matrix i (dA device, m_i x n_i, ld m_i, compute type).
+ * Syncs. */
+pod_status pod_batch_loss_grad(pod_batch *b, int32_t i, void *dA, double *loss);
+
 /* Final step of Alg. 1 for matrix i, as pod_project.  Syncs. */
 pod_status pod_batch_project(pod_batch *b, int32_t i, void *U_out, double *sigma_out, void *V_out);
 

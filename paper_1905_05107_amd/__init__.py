@@ -28,7 +28,7 @@ EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project"
            "pod_status_str", "pod_profile_enable", "pod_profile_read", "pod_inc_init", "pod_inc_add_block",
            "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy", "pod_batch_init",
            "pod_batch_autotune", "pod_batch_run", "pod_batch_project", "pod_batch_get_info", "pod_batch_destroy",
-           "pod_enable_adjoint", "pod_backward", "pod_loss_grad"]
+           "pod_enable_adjoint", "pod_backward", "pod_loss_grad", "pod_batch_enable_adjoint", "pod_batch_loss_grad"]
 
 
 class PodError(RuntimeError):
@@ -106,6 +106,8 @@ def lib():
             "pod_enable_adjoint": (i32, [vp]),
             "pod_backward": (i32, [vp, vp, vp, vp]),
             "pod_loss_grad": (i32, [vp, vp, P(d)]),
+            "pod_batch_enable_adjoint": (i32, [vp]),
+            "pod_batch_loss_grad": (i32, [vp, i32, vp, P(d)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -498,6 +500,20 @@ class Batch:
         r = ctypes.c_int32()
         _check(lib().pod_batch_run(self.h, 1 if use_graph else 0, int(max_rounds), ctypes.byref(r)), "pod_batch_run")
         return r.value
+
+    def enable_adjoint(self):
+        _check(lib().pod_batch_enable_adjoint(self.h), "pod_batch_enable_adjoint")
+
+    def loss_grad(self, i: int):
+        """(L_i, dL_i/dA_i) for L_i = |A_i - U_k U_k^T A_i|_F^2 of matrix i."""
+        import torch
+        p = self.params[i]
+        dt = torch.float64 if p.precision == POD_F64 else torch.float32
+        dAt = torch.zeros((p.n, p.m), dtype=dt, device=self.mats[i].device)
+        L = ctypes.c_double()
+        _check(lib().pod_batch_loss_grad(self.h, int(i), ctypes.c_void_p(dAt.data_ptr()), ctypes.byref(L)),
+               "pod_batch_loss_grad")
+        return L.value, dAt.T
 
     def info(self, i: int):
         inf = pod_info()

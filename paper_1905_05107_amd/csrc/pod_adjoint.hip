@@ -188,6 +188,48 @@ pod_status reverse_merges(pod_ctx *ctx, void *dA)
     return POD_OK;
 }
 
+// Batched checkpoints: one entry per matrix (blockIdx.y), stopped matrices skipped.
+template <typename TC>
+__global__ __launch_bounds__(256) void k_ckpt_pre_b(const CkptArgs *__restrict__ arr)
+{
+    const CkptArgs &a = arr[blockIdx.y];
+    if (a.ds->done) return;
+    const DevState *ds = a.ds;
+    if (ds->exhausted) return;
+    const int32_t t = ds->it;
+    if (t >= a.cap) return;
+    const int32_t rs = ds->rs;
+    const TC *U = reinterpret_cast<const TC *>((t & 1) ? a.U1 : a.U0);
+    const double *sg = (t & 1) ? a.s1 : a.s0;
+    TC *dst = reinterpret_cast<TC *>(a.ckU) + (int64_t)t * a.m * a.r;
+    const int64_t total = a.m * rs;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256)
+        dst[idx] = U[idx];
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < rs; i += 256) a.ckS[(int64_t)t * a.r + i] = sg[i];
+        if (threadIdx.x == 0) {
+            a.meta[4 * t] = rs;
+            a.meta[4 * t + 1] = ds->g;
+            a.meta[4 * t + 3] = 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ckpt_post_b(const CkptArgs *__restrict__ arr)
+{
+    const CkptArgs &a = arr[blockIdx.y];
+    if (a.ds->done) return;
+    const DevState *ds = a.ds;
+    if (ds->exhausted) return;
+    const int32_t t = ds->it - 1;
+    if (t < 0 || t >= a.cap) return;
+    for (int i = threadIdx.x; i < a.pm2; i += 256) a.ckR[(int64_t)t * a.pm2 + i] = a.R[i];
+    if (threadIdx.x == 0) {
+        a.meta[4 * t + 2] = ds->rnew;
+        a.meta[4 * t + 3] = 1;
+    }
+}
+
 }  // namespace
 
 hipError_t pod::launch_ckpt_pre(pod_ctx *ctx, hipStream_t st)
@@ -209,6 +251,43 @@ hipError_t pod::launch_ckpt_post(pod_ctx *ctx, hipStream_t st)
 {
     hipLaunchKernelGGL(k_ckpt_post, dim3(1), dim3(256), 0, st, ctx->ds, ctx->R2, ctx->pmax * ctx->pmax, ctx->ckR,
                        ctx->ckMeta, ctx->ck_cap);
+    return hipGetLastError();
+}
+
+CkptArgs pod::ctx_ckpt_args(pod_ctx *ctx)
+{
+    CkptArgs a;
+    a.ds = ctx->ds;
+    a.U0 = ctx->U[0];
+    a.U1 = ctx->U[1];
+    a.s0 = ctx->sig[0];
+    a.s1 = ctx->sig[1];
+    a.m = ctx->prm.m;
+    a.r = ctx->r;
+    a.ckU = ctx->ckU;
+    a.ckS = ctx->ckS;
+    a.ckR = ctx->ckR;
+    a.R = ctx->R2;
+    a.meta = ctx->ckMeta;
+    a.cap = ctx->ck_cap;
+    a.pm2 = ctx->pmax * ctx->pmax;
+    return a;
+}
+
+hipError_t pod::launch_ckpt_pre_b(const CkptArgs *arr, int32_t count, int64_t max_mr, int32_t prec, hipStream_t st)
+{
+    const unsigned nb = (unsigned)(((max_mr + 255) / 256 < 1024) ? (max_mr + 255) / 256 : 1024);
+    const dim3 grid(nb > 0 ? nb : 1, (unsigned)count);
+    if (prec == POD_F64)
+        hipLaunchKernelGGL(k_ckpt_pre_b<double>, grid, dim3(256), 0, st, arr);
+    else
+        hipLaunchKernelGGL(k_ckpt_pre_b<float>, grid, dim3(256), 0, st, arr);
+    return hipGetLastError();
+}
+
+hipError_t pod::launch_ckpt_post_b(const CkptArgs *arr, int32_t count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ckpt_post_b, dim3(1, (unsigned)count), dim3(256), 0, st, arr);
     return hipGetLastError();
 }
 

@@ -40,6 +40,8 @@ struct pod_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t iters = 0;
+    CkptArgs *d_ck = nullptr;        // checkpoints of the reverse pass (nullable)
+    int64_t max_mr = 0;
     int failed = 0;
 };
 
@@ -61,7 +63,7 @@ void batch_free(pod_batch *b)
     for (pod_ctx *c : b->ctx)
         if (c) pod_destroy(c);
     void *ptrs[] = {b->d_draw, b->d_g1, b->d_g2, b->d_small, b->d_t1, b->d_t2, b->d_ds, b->d_maxit, b->d_sintol,
-                    b->d_ndone};
+                    b->d_ndone, b->d_ck};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (b->h_ndone) (void)hipHostFree(b->h_ndone);
@@ -81,6 +83,7 @@ pod_status enqueue_iteration(pod_batch *b)
 {
     const int32_t n = b->count;
     B_HIP(launch_draw_cols_b(b->d_draw, n, b->st));
+    if (b->d_ck) B_HIP(launch_ckpt_pre_b(b->d_ck, n, b->max_mr, b->prec, b->st));
     B_HIP(launch_gram_partial_b(b->d_g1, n, b->max_nblk, b->pmax_max, b->prec, b->st));
     B_HIP(launch_gram_reduce_b(b->d_g1, n, b->pmax_max, b->st));
     B_HIP(launch_chol_first_b(b->d_small, n, b->pmax_max, b->st));
@@ -88,6 +91,7 @@ pod_status enqueue_iteration(pod_batch *b)
     B_HIP(launch_gram_partial_b(b->d_g2, n, b->max_nblk, b->pmax_max, b->prec, b->st));
     B_HIP(launch_gram_reduce_b(b->d_g2, n, b->pmax_max, b->st));
     B_HIP(launch_svd_merge_b(b->d_small, n, b->pmax_max, b->st));
+    if (b->d_ck) B_HIP(launch_ckpt_post_b(b->d_ck, n, b->st));
     B_HIP(launch_gemm_tall_b(b->d_t2, n, b->max_nb, b->pmax_max, b->pmax_max, b->prec, b->st));
     B_HIP(launch_batch_done(b->d_ds, b->d_maxit, b->d_sintol, n, b->d_ndone, b->st));
     B_HIP(hipMemcpyAsync(b->h_ndone, b->d_ndone, sizeof(int32_t), hipMemcpyDeviceToHost, b->st));
@@ -326,6 +330,40 @@ pod_status pod_batch_run(pod_batch *b, int32_t use_graph, int32_t max_rounds, in
     b->iters += rounds;
     if (rounds_out) *rounds_out = rounds;
     return (*b->h_ndone >= b->count) ? POD_OK : POD_ESTATE;
+}
+
+pod_status pod_batch_enable_adjoint(pod_batch *b)
+{
+    if (!b) return POD_EINVAL;
+    if (b->failed) return POD_EHIP;
+    if (b->iters > 0) return POD_ESTATE;
+    if (b->d_ck) return POD_OK;
+    std::vector<CkptArgs> ck(b->count);
+    int64_t mr = 1;
+    for (int32_t i = 0; i < b->count; ++i) {
+        pod_status s = pod_enable_adjoint(b->ctx[i]);
+        if (s != POD_OK) return s;
+        ck[i] = ctx_ckpt_args(b->ctx[i]);
+        const int64_t v = b->ctx[i]->prm.m * b->ctx[i]->r;
+        mr = (v > mr) ? v : mr;
+    }
+    b->max_mr = mr;
+    B_HIP(hipMalloc((void **)&b->d_ck, sizeof(CkptArgs) * b->count));
+    B_HIP(hipMemcpy(b->d_ck, ck.data(), sizeof(CkptArgs) * b->count, hipMemcpyHostToDevice));
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+    }
+    return POD_OK;
+}
+
+pod_status pod_batch_loss_grad(pod_batch *b, int32_t i, void *dA, double *loss)
+{
+    if (!b || i < 0 || i >= b->count) return POD_EINVAL;
+    if (b->failed) return POD_EHIP;
+    return pod_loss_grad(b->ctx[i], dA, loss);
 }
 
 pod_status pod_batch_project(pod_batch *b, int32_t i, void *U_out, double *sigma_out, void *V_out)

@@ -71,6 +71,22 @@ pod_status ctx_merge_basis(pod_ctx *ctx, const void *Ub, const double *sb, int32
 hipError_t launch_ckpt_pre(pod_ctx *ctx, hipStream_t st);
 hipError_t launch_ckpt_post(pod_ctx *ctx, hipStream_t st);
 
+// Batched checkpoints (per-matrix entries in device memory).
+struct CkptArgs {
+    const pod::DevState *ds;
+    const void *U0, *U1;
+    const double *s0, *s1;
+    int64_t m;
+    int32_t r, cap, pm2;
+    void *ckU;
+    double *ckS, *ckR;
+    const double *R;
+    int32_t *meta;
+};
+CkptArgs ctx_ckpt_args(pod_ctx *ctx);
+hipError_t launch_ckpt_pre_b(const CkptArgs *arr, int32_t count, int64_t max_mr, int32_t prec, hipStream_t st);
+hipError_t launch_ckpt_post_b(const CkptArgs *arr, int32_t count, hipStream_t st);
+
 // Argument blocks of one context's launches (shared with the batched path).
 DrawArgs ctx_draw_args(pod_ctx *ctx);
 SmallArgs ctx_small_args(pod_ctx *ctx);
