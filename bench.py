@@ -45,32 +45,58 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-merges", type=int, default=12, help="oracle merges timed for the CPU baseline sample")
+    ap.add_argument("--workload", choices=["c2", "c5", "c4"], default="c2",
+                    help="c2: travelling waves 200k x 2k (default); c5: 64-matrix batch, forward + gradient; "
+                         "c4: Alg. 3 over pinned host blocks of 2M x 512")
+    ap.add_argument("--c5-count", type=int, default=64)
+    ap.add_argument("--c4-blocks", type=int, default=8, help="blocks of 512 columns (32: the full 16,000)")
     return ap.parse_args()
 
 
-def kernel_work(cls, m, n, k, c, p, iters, sweeps_total, launches, prec_bytes):
+def kernel_work(cls, m, n, k, c, p, r, launches):
     """Algorithmic work of one launch of a kernel class, averaged over the
-    launches of one step: (bound, amount, unit) with amount in bytes or flops.
+    launches of one step: (bound, amount, unit, hbm_bytes) with amount in
+    bytes or flops.
 
     colnorms / project: one pass over A (m n 4 bytes).  gram: symmetric Gram
-    m p (p+1) flops.  tall: 2 m p p flops (Y = X0 T1 with p x p T1, and
-    U = Y Z2 with p x k Z2 averaged).  svd: FP64 flops of the p x p stage --
-    two triangular products (2 p^3 / 3 each), and per Jacobi sweep (p-1)
-    steps x p/2 pairs x p rows x 10 flops (3 dot-product FMAs, 2 rotation
-    updates) -- summed over the step's sweeps."""
-    if cls in ("colnorms",):
-        return "hbm", m * n * 4, "B"
+    m p (p+1) flops, reading m p 4 bytes.  tall: Y = X0 T1 (m p p MACs) and
+    U = Y Z2 (m p r MACs), averaged: m p (p + r) flops, reading m p 4 and
+    writing m (p + r) / 2 4 bytes.  svd: FP64 flops of the p x p stage --
+    Cholesky p^3/3, R = R2 R1 p^3/3, H = R R^T p^3/3, tridiagonalisation
+    4 p^3/3, triangular inverse p^3/3, back-transformation 2 p^2 r and
+    Z2 = R2^-1 U_R p^2 r.  chol: G1 = P G0 P, Cholesky p^3/3, inverse p^3/3."""
+    if cls == "colnorms":
+        return "hbm", m * n * 4, "B", m * n * 4
     if cls == "project":
-        return "hbm", m * n * 4 / max(launches, 1), "B"
+        b = m * n * 4 / max(launches, 1)
+        return "hbm", b, "B", b
     if cls == "gram":
-        return "mfma", m * p * (p + 1), "flop"
+        return "mfma", m * p * (p + 1), "flop", m * p * 4
     if cls == "tall":
-        return "mfma", m * p * (p + k), "flop"
+        return "mfma", m * p * (p + r), "flop", m * p * 4 + m * (p + r) * 2
     if cls == "svd":
-        jac = sweeps_total * (p - 1) * (p / 2) * p * 10.0
-        tri = iters * 4.0 * p ** 3 / 3.0
-        return "alu", (jac + tri) / max(launches, 1), "flop"
-    return None, 0, None
+        return "alu", (8.0 / 3.0) * p ** 3 + 3.0 * p * p * r, "flop", 0
+    if cls == "chol":
+        return "alu", (2.0 / 3.0) * p ** 3, "flop", 0
+    return None, 0, None, 0
+
+
+def roofline_entry(bound, amount, avg_s, hbm_bytes):
+    if bound == "hbm":
+        a = amount / avg_s / 1e9
+        return {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(a / HBM_PEAK_GBS, 4)}
+    if bound == "mfma":
+        a = amount / avg_s / 1e12
+        e = {"bound": "mfma", "achieved": round(a, 3), "peak": PEAK_TFLOPS["f32_mfma"], "unit": "TFLOP/s",
+             "frac": round(a / PEAK_TFLOPS["f32_mfma"], 5)}
+        if hbm_bytes:
+            e["hbm_gbs"] = round(hbm_bytes / avg_s / 1e9, 1)
+        return e
+    a = amount / avg_s / 1e12
+    return {"bound": "alu", "achieved": round(a, 6), "peak": PEAK_TFLOPS["f64_vector"], "unit": "TFLOP/s",
+            "frac": round(a / PEAK_TFLOPS["f64_vector"], 7),
+            "frac_of_one_cu": round(a / (PEAK_TFLOPS["f64_vector"] / 256), 4)}
 
 
 def cpu_baseline(At, m, n, k, c, iters_gpu, merges):
@@ -115,6 +141,134 @@ def cpu_baseline(At, m, n, k, c, iters_gpu, merges):
     }
 
 
+def run_c5(args):
+    """64 FP32 matrices (m ~ U[10k,100k], n ~ U[200,1000], k ~ U[4,16], c = 2k,
+    s_i = exp(-i/tau), tau ~ U[3,12], Haar factors): batched ISMA to
+    theta <= 1e-5 with reverse-pass checkpoints, then the gradient of
+    sum_i |A_i - U_k U_k^T A_i|_F^2.  One step = batch set-up + forward +
+    all gradients."""
+    import torch
+
+    import paper_1905_05107_amd as pod
+    import snapgen
+
+    specs = snapgen.batch_specs(args.c5_count, seed=1005)
+    t_gen = time.perf_counter()
+    mats = [snapgen.batch_matrix_torch(it, "cuda").T for it in specs]
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    kws = [dict(k=it.k, c=it.c, seed=2005 + i, theta_tol=1e-5) for i, it in enumerate(specs)]
+    nbytes = sum(A.shape[0] * A.shape[1] * 4 for A in mats)
+
+    def step(prec):
+        t0 = time.perf_counter()
+        with pod.Batch(mats, [dict(kw, precision=prec) for kw in kws]) as b:
+            b.enable_adjoint()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rounds = b.run()
+            t2 = time.perf_counter()
+            L = 0.0
+            for i in range(len(mats)):
+                L += b.loss_grad(i)[0]
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+        return t3 - t0, t1 - t0, t2 - t1, t3 - t2, L, rounds
+
+    for _ in range(max(args.warmup, 1)):
+        step(pod.POD_F32)
+    res = [step(pod.POD_F32) for _ in range(args.steps)]
+    tot = sum(r[0] for r in res) / len(res)
+    f64 = [step(pod.POD_F64) for _ in range(max(1, min(args.steps, 3)))]
+    tot64 = sum(r[0] for r in f64) / len(f64)
+    out = {
+        "metric": METRIC, "value": round(tot * 1e3, 3),
+        "unit": "ms per batch of 64 (set-up + forward to theta<=1e-5 + gradient), FP32 merges",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tot * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch of {len(mats)} FP32 matrices, m~U[10k,100k], n~U[200,1000], k~U[4,16], "
+                               "c=2k, s_i=exp(-i/tau), tau~U[3,12]; loss sum |A-U_kU_k^TA|_F^2 with gradient",
+                   "total_bytes": nbytes},
+        "breakdown_ms": {"setup": round(sum(r[1] for r in res) / len(res) * 1e3, 3),
+                         "forward": round(sum(r[2] for r in res) / len(res) * 1e3, 3),
+                         "gradient": round(sum(r[3] for r in res) / len(res) * 1e3, 3)},
+        "rounds": res[-1][5], "loss": res[-1][4],
+        "fp64_path_ms": round(tot64 * 1e3, 3), "speedup_vs_fp64_path": round(tot64 / tot, 3),
+        "adjoint_included": True, "gen_s": round(t_gen, 2), "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_c4(args):
+    """Alg. 3 over pinned host blocks: travelling waves with 200 modes,
+    a_j = j^-1.2, noise variance 1e-3, rows centred by a pre-pass, m = 2M,
+    blocks of 512 columns; k = 40, c = 80, FP32 merges.  Reports the
+    streamed time, the host-link rate and the copy/compute overlap (against
+    the same blocks run from device memory)."""
+    import torch
+
+    import paper_1905_05107_amd as pod
+    import snapgen
+
+    m, w = 2_000_000, 512
+    n = min(16_000, w * args.c4_blocks)
+    bounds = [(j, min(j + w, n)) for j in range(0, n, w)]
+    t_gen = time.perf_counter()
+    gen = snapgen.WaveBlocks(m, n, 200, 1.2, 1e-3, seed=1004, device="cuda")
+    host = []
+    for j0, j1 in bounds:
+        hb = torch.empty((j1 - j0, m), dtype=torch.float32, pin_memory=True)
+        hb.copy_(gen.block(j0, j1))
+        host.append(hb)
+    torch.cuda.synchronize()
+    del gen
+    t_gen = time.perf_counter() - t_gen
+    kw = dict(k=40, c=80, seed=2004, theta_tol=1e-5, precision=pod.POD_F32)
+
+    def streamed():
+        with pod.Incremental(m, w, **kw) as inc:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            inc.add_host_blocks(host)
+            U, s = inc.result()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, inc.info()
+
+    def resident(dev_blocks):
+        with pod.Incremental(m, w, **kw) as inc:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for B in dev_blocks:
+                inc.add_block(B)
+            inc.result()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+    streamed()
+    res = [streamed() for _ in range(args.steps)]
+    t_s = sum(r[0] for r in res) / len(res)
+    info = res[-1][1]
+    dev_blocks = [hb.cuda().T for hb in host]
+    torch.cuda.synchronize()
+    t_r = resident(dev_blocks)
+    copy_s = info.copy_ms / 1e3
+    link = info.host_bytes / copy_s / 1e9 if copy_s > 0 else None
+    overlap = (copy_s + t_r - t_s) / min(copy_s, t_r) if copy_s > 0 else None
+    out = {
+        "metric": METRIC, "value": round(t_s * 1e3, 2),
+        "unit": "ms per incremental POD over host-resident blocks (one pass), FP32 merges",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(t_s * 1e3, 2),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"travelling waves {m}x{n} FP32 (200 modes, a_j=j^-1.2), pinned host blocks of "
+                               f"{w} columns, k=40, c=80, theta_tol=1e-5", "blocks": len(bounds)},
+        "host_link_gbs": round(link, 2) if link else None, "copy_ms": round(info.copy_ms, 2),
+        "device_resident_ms": round(t_r * 1e3, 2),
+        "copy_compute_overlap": round(overlap, 3) if overlap is not None else None,
+        "gen_s": round(t_gen, 2), "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -122,6 +276,10 @@ def main():
         print(json.dumps({"error": "single-GPU build: the hot path runs on one GPU; "
                                    "--gpus above 1 is not supported", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "c5":
+        return run_c5(args)
+    if args.workload == "c4":
+        return run_c4(args)
     import torch
 
     import paper_1905_05107_amd as pod
@@ -144,7 +302,7 @@ def main():
             ctx.run()
             inf = ctx.info()
             ctx.project(want_v=False)
-        info["iters"], info["sweeps"] = inf.iter, inf.total_sweeps
+        info["iters"] = inf.iter
         return inf
 
     # warm-up, then one step per kernel class with that class timed by HIP events
@@ -171,7 +329,7 @@ def main():
     sec32 = (time.perf_counter() - t0) / args.steps
     launches, dom_ms = pod.profile_read()
     pod.profile_enable(None)
-    iters, sweeps = info["iters"], info["sweeps"]
+    iters = info["iters"]
 
     # plain FP64 GPU path
     step(pod.POD_F64)
@@ -183,24 +341,24 @@ def main():
     sec64 = (time.perf_counter() - t0) / args.fp64_steps
     iters64 = info["iters"]
 
-    # roofline of the dominant kernel class
+    # roofline of the dominant kernel class (measured live in the timed steps)
     per_step_launches = launches / args.steps
     avg_s = dom_ms / 1e3 / max(launches, 1)
-    bound, amount, unit = kernel_work(dominant, m, n, k, c, p, iters, sweeps, per_step_launches, 4)
-    if bound == "hbm":
-        achieved = amount / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
-    elif bound == "mfma":
-        achieved = amount / avg_s / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f32_mfma"],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f32_mfma"], 5), "traffic": None}
-    else:
-        achieved = amount / avg_s / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 5), "peak": PEAK_TFLOPS["f64_vector"],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64_vector"], 6), "traffic": None}
+    bound, amount, unit, hb = kernel_work(dominant, m, n, k, c, p, k, per_step_launches)
+    roof = roofline_entry(bound, amount, avg_s, hb)
+    roof["traffic"] = None
     roof.update({"kernel_class": dominant, "avg_launch_us": round(avg_s * 1e6, 2),
                  "launches_per_step": round(per_step_launches, 1)})
+    # the other classes, from the per-class pre-pass
+    others = {}
+    for cls, (ln, ms) in per_class.items():
+        b2, a2, _, h2 = kernel_work(cls, m, n, k, c, p, k, ln)
+        if b2 is None or ln == 0:
+            continue
+        e = roofline_entry(b2, a2, ms / 1e3 / ln, h2)
+        e["avg_launch_us"] = round(ms * 1e3 / ln, 2)
+        e["launches_per_step"] = ln
+        others[cls] = e
 
     # algorithmic HBM bytes of one FP32 step: column norms and projection read
     # A once each; every merge reads X0 = [U | A(:, I_c)] (m x p) twice,
@@ -224,8 +382,8 @@ def main():
                                f"rows centred; k={k}, c={c}, theta_tol=1e-5",
                    "m": m, "n": n, "k": k, "c": c},
         "roofline": roof,
+        "kernel_rooflines": others,
         "iters": iters,
-        "jacobi_sweeps_per_merge": round(sweeps / max(iters, 1), 2),
         "fp64_path_ms": round(sec64 * 1e3, 4),
         "fp64_iters": iters64,
         "speedup_vs_fp64_path": round(sec64 / sec32, 3),

@@ -163,3 +163,84 @@ def batch_matrix(item: BatchItem, dtype=np.float32, noise_var: float = 0.0) -> S
     s = np.exp(-np.arange(q) / item.tau)
     return spectrum_matrix(item.m, item.n, s, noise_var, item.seed, centre=False, dtype=dtype,
                            v_orthogonal_to_ones=False)
+
+
+def batch_matrix_torch(item: BatchItem, device: str = "cuda", dtype=None):
+    """batch_matrix() built with torch on `device` (QR of Gaussian matrices in
+    FP64, signs fixed so diag(R) > 0), returned as the (n, m) contiguous
+    tensor At in `dtype` (default FP32).  For large batches, where the CPU
+    QR would take minutes."""
+    import torch
+
+    dtype = dtype or torch.float32
+    dev = torch.device(device)
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(item.seed))
+    f64 = torch.float64
+
+    def haar(rows, cols):
+        G = torch.randn((rows, cols), generator=g, dtype=f64, device=dev)
+        Q, R = torch.linalg.qr(G)
+        d = torch.sign(torch.diagonal(R))
+        d[d == 0] = 1.0
+        return Q * d[None, :]
+
+    q = min(item.n, item.m)
+    s = torch.exp(-torch.arange(q, dtype=f64, device=dev) / item.tau)
+    U = haar(item.m, q)
+    V = haar(item.n, q)
+    At = ((V * s[None, :]) @ U.T).to(dtype).contiguous()
+    return At
+
+
+class WaveBlocks:
+    """Column blocks of a travelling-wave matrix (the generator of
+    travelling_waves) produced one at a time on `device`: columns [j0, j1) of
+    the m x n matrix, t_j = j / n, noise drawn per block from (seed, j0), rows
+    centred with means from a pre-pass over all blocks (`centre`)."""
+
+    def __init__(self, m: int, n: int, n_modes: int, alpha: float, noise_var: float, seed: int,
+                 device: str = "cuda", centre: bool = True, chunk: int = 512):
+        import torch
+
+        self.m, self.n, self.seed, self.dev = m, n, seed, torch.device(device)
+        self.sd = math.sqrt(noise_var)
+        f64 = torch.float64
+        g = torch.Generator(device=self.dev)
+        g.manual_seed(int(seed))
+        J = n_modes
+        kappa = torch.rand(J, generator=g, dtype=f64, device=self.dev) * (200 * math.pi)
+        self.omega = torch.rand(J, generator=g, dtype=f64, device=self.dev) * (200 * math.pi)
+        self.phi = torch.rand(J, generator=g, dtype=f64, device=self.dev) * (2 * math.pi)
+        amp = torch.arange(1, J + 1, dtype=f64, device=self.dev) ** (-float(alpha))
+        x = torch.arange(m, dtype=f64, device=self.dev) / m
+        kx = x[:, None] * kappa[None, :]
+        self.X = torch.cat([torch.sin(kx) * amp, torch.cos(kx) * amp], dim=1)
+        self.mu = None
+        if centre:
+            rowsum = torch.zeros(m, dtype=f64, device=self.dev)
+            for j0 in range(0, n, chunk):
+                rowsum += self._raw(j0, min(n, j0 + chunk)).sum(dim=0)
+            self.mu = rowsum / n
+
+    def _raw(self, j0: int, j1: int):
+        import torch
+
+        t = torch.arange(j0, j1, dtype=torch.float64, device=self.dev) / self.n
+        wt = t[:, None] * self.omega[None, :] - self.phi[None, :]
+        T = torch.cat([torch.cos(wt), -torch.sin(wt)], dim=1)
+        blk = T @ self.X.T
+        if self.sd > 0:
+            g = torch.Generator(device=self.dev)
+            g.manual_seed(int(self.seed) * 1_000_003 + j0)
+            blk += self.sd * torch.randn(blk.shape, generator=g, dtype=torch.float64, device=self.dev)
+        return blk
+
+    def block(self, j0: int, j1: int, dtype=None):
+        """(j1 - j0, m) contiguous tensor: row j is column j0 + j of A."""
+        import torch
+
+        blk = self._raw(j0, j1)
+        if self.mu is not None:
+            blk -= self.mu[None, :]
+        return blk.to(dtype or torch.float32)
