@@ -113,12 +113,79 @@ __device__ __forceinline__ void load4(const ColPtr &cp, int64_t row, int64_t lim
 }
 
 // A register-held stage: item `it` of thread t is (column, 4-row group)
-// = ((t + 256 it) / GRP, (t + 256 it) % GRP).
+// = ((t + 256 it) / GRP, (t + 256 it) % GRP).  prepare() fixes the column
+// start of every item once (the columns do not change between stages); when
+// every column is stored in the compute type and 16-byte aligned, a full
+// stage is then loaded with plain vector loads and no branch, so the loads of
+// the stages in flight are not waited for until their store.  Items beyond
+// the P columns point at column 0 and are replaced by zeros at the store.
 template <typename TC, int ITEMS> struct Stage {
     TC v[ITEMS][4];
+    const TC *base[ITEMS];
+    bool fast;
+
+    __device__ __forceinline__ void prepare(const SrcT<TC> &s, int64_t m, int P, bool vec)
+    {
+        const bool same = !s.gather || (s.a_f64 != 0) == (sizeof(TC) == 8);
+        fast = vec && same;
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int idx = threadIdx.x + 256 * it;
+            const int c = idx / GRP;
+            const ColPtr cp = col_ptr<TC>(s, m, (c < P) ? c : 0);
+            base[it] = reinterpret_cast<const TC *>(cp.p);
+        }
+    }
+
+    // a full stage on the fast path (prepare() set fast, rb + RB <= m): vector
+    // loads only, no branch
+    __device__ __forceinline__ void load_full(int64_t rb)
+    {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int g = (threadIdx.x + 256 * it) % GRP;
+            const TC *q = base[it] + rb + 4 * g;
+            if (sizeof(TC) == 4) {
+                const f32x4 a = *reinterpret_cast<const f32x4 *>(q);
+                v[it][0] = a[0];
+                v[it][1] = a[1];
+                v[it][2] = a[2];
+                v[it][3] = a[3];
+            } else {
+                const f64x2 a = *reinterpret_cast<const f64x2 *>(q);
+                const f64x2 b = *reinterpret_cast<const f64x2 *>(q + 2);
+                v[it][0] = a[0];
+                v[it][1] = a[1];
+                v[it][2] = b[0];
+                v[it][3] = b[1];
+            }
+        }
+    }
 
     __device__ __forceinline__ void load(const SrcT<TC> &s, int64_t m, int64_t rb, int P, bool vec)
     {
+        if (fast && rb + RB <= m) {
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) {
+                const int g = (threadIdx.x + 256 * it) % GRP;
+                const TC *q = base[it] + rb + 4 * g;
+                if (sizeof(TC) == 4) {
+                    const f32x4 a = *reinterpret_cast<const f32x4 *>(q);
+                    v[it][0] = a[0];
+                    v[it][1] = a[1];
+                    v[it][2] = a[2];
+                    v[it][3] = a[3];
+                } else {
+                    const f64x2 a = *reinterpret_cast<const f64x2 *>(q);
+                    const f64x2 b = *reinterpret_cast<const f64x2 *>(q + 2);
+                    v[it][0] = a[0];
+                    v[it][1] = a[1];
+                    v[it][2] = b[0];
+                    v[it][3] = b[1];
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const int idx = threadIdx.x + 256 * it;
@@ -132,16 +199,31 @@ template <typename TC, int ITEMS> struct Stage {
             }
         }
     }
-    __device__ __forceinline__ void store(TC *Xs, int PP) const
+    // P: live columns (items beyond are written as zeros), PP: padded width
+    __device__ __forceinline__ void store(TC *Xs, int PP, int P) const
     {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const int idx = threadIdx.x + 256 * it;
             const int c = idx / GRP, g = idx % GRP;
             if (c < PP) {
+                const bool live = c < P;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) Xs[c * LDSR + 4 * g + q] = v[it][q];
+                for (int q = 0; q < 4; ++q) Xs[c * LDSR + 4 * g + q] = live ? v[it][q] : (TC)0;
             }
+        }
+    }
+    // every item written (the LDS stage holds all ITEMS * 256 / GRP columns):
+    // no branch between the loads and the stores
+    __device__ __forceinline__ void store_all(TC *Xs, int P) const
+    {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int idx = threadIdx.x + 256 * it;
+            const int c = idx / GRP, g = idx % GRP;
+            const bool live = c < P;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Xs[c * LDSR + 4 * g + q] = live ? v[it][q] : (TC)0;
         }
     }
 };
@@ -228,13 +310,9 @@ __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const D
     AccT acc[MAXPW];
 #pragma unroll
     for (int q = 0; q < MAXPW; ++q) acc[q] = AccT{0, 0, 0, 0};
-    Stage<TC, ITEMS> st;
-    if (s0 < s1) st.load(s, m, s0 * RB, P, vec);
-    for (int64_t sg = s0; sg < s1; ++sg) {
-        __syncthreads();
-        st.store(Xs, PP);
-        __syncthreads();
-        if (sg + 1 < s1) st.load(s, m, (sg + 1) * RB, P, vec);
+    // two register stages in flight: the loads of stages sg+1 and sg+2 overlap
+    // the MFMA work on stage sg
+    auto compute = [&]() {
 #pragma unroll
         for (int q = 0; q < MAXPW; ++q) {
             if (tI[q] >= 0) {
@@ -244,6 +322,48 @@ __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const D
                 for (int k4 = 0; k4 < RB; k4 += 4) acc[q] = mfma16x16x4(xa[k4], xb[k4], acc[q]);
             }
         }
+    };
+    Stage<TC, ITEMS> sa, sb;
+    sa.prepare(s, m, P, vec);
+    sb.fast = sa.fast;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) sb.base[it] = sa.base[it];
+    // full stages [s0, e) on the fast path: two register stages in flight (the
+    // loads of stages sg+1 and sg+2 overlap the MFMA work on stage sg; the
+    // prefetch index is clamped so every iteration issues the same loads)
+    const int64_t full_end = m / RB;   // stages entirely inside [0, m)
+    const int64_t e = sa.fast ? ((s1 < full_end) ? s1 : ((full_end > s0) ? full_end : s0)) : s0;
+    if (e > s0) {
+        const int64_t last = e - 1;
+        sa.load_full(s0 * RB);
+        sb.load_full(((s0 + 1 < last) ? s0 + 1 : last) * RB);
+        int64_t sg = s0;
+        for (; sg + 1 < e; sg += 2) {
+            __syncthreads();
+            sa.store_all(Xs, P);
+            __syncthreads();
+            sa.load_full(((sg + 2 < last) ? sg + 2 : last) * RB);
+            compute();
+            __syncthreads();
+            sb.store_all(Xs, P);
+            __syncthreads();
+            sb.load_full(((sg + 3 < last) ? sg + 3 : last) * RB);
+            compute();
+        }
+        if (sg < e) {
+            __syncthreads();
+            sa.store_all(Xs, P);
+            __syncthreads();
+            compute();
+        }
+    }
+    // remaining stages (a partial last stage, or every stage off the fast path)
+    for (int64_t sg = e; sg < s1; ++sg) {
+        sa.load(s, m, sg * RB, P, vec);
+        __syncthreads();
+        sa.store(Xs, PP, P);
+        __syncthreads();
+        compute();
     }
     double *pb = part + (int64_t)bid * pmax * pmax;
 #pragma unroll
@@ -294,8 +414,19 @@ __device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part
     const bool live = idx < pmax * pmax && i < P && j < P;
     const int b0 = (nblk * wv) / 4, b1 = (nblk * (wv + 1)) / 4;
     double s = 0.0;
-    if (live)
-        for (int b = b0; b < b1; ++b) s += part[(int64_t)b * pmax * pmax + idx];
+    if (live) {
+        // eight independent accumulators keep eight loads in flight; fixed order
+        const int64_t st = (int64_t)pmax * pmax;
+        const double *pp = part + idx;
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int b = b0;
+        for (; b + 8 <= b1; b += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += pp[(int64_t)(b + u) * st];
+        }
+        for (; b < b1; ++b) a[0] += pp[(int64_t)b * st];
+        s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
     sq[wv][lane] = s;
     __syncthreads();
     if (wv == 0 && idx < pmax * pmax) G[idx] = live ? ((sq[0][lane] + sq[1][lane]) + sq[2][lane]) + sq[3][lane] : 0.0;
@@ -320,7 +451,8 @@ static void gram_launch(const GemmDesc &d, const DevState *ds, int32_t which_p, 
                         int32_t nblk, hipStream_t st)
 {
     const SrcT<TC> s = make_src<TC>(d);
-    const size_t lds = (size_t)pmax * LDSR * sizeof(TC);
+    // the stage holds every item's column (ITEMS * 256 / GRP >= pmax)
+    const size_t lds = (size_t)(ITEMS * 256 / GRP) * LDSR * sizeof(TC);
     hipLaunchKernelGGL((k_gram_partial<TC, MAXPW, ITEMS>), dim3(nblk), dim3(256), lds, st, s, d.m, ds, which_p, pmax,
                        part, nblk, (int)vec_ok(s, d.m));
 }
@@ -396,14 +528,8 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
             Ts[idx] = (k < pin && j < pout) ? T[k + (int64_t)j * ldt] : (TC)0;
         }
     (void)pmax_out;
-    Stage<TC, ITEMS> st;
-    st.load(s, m, s0 * RB, pin, vec);
     const int ntile = (RB / 16) * (PO / 16);
-    for (int64_t sg = s0; sg < s1; ++sg) {
-        __syncthreads();
-        st.store(Xs, PI);
-        __syncthreads();
-        if (sg + 1 < s1) st.load(s, m, (sg + 1) * RB, pin, vec);
+    auto compute = [&](int64_t sg) {
         for (int tile = wv; tile < ntile; tile += 4) {
             const int rbk = tile % (RB / 16), jc = tile / (RB / 16);
             AccT acc = AccT{0, 0, 0, 0};
@@ -435,6 +561,44 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
                 }
             }
         }
+    };
+    Stage<TC, ITEMS> sa, sb;
+    sa.prepare(s, m, pin, vec);
+    sb.fast = sa.fast;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) sb.base[it] = sa.base[it];
+    const int64_t full_end = m / RB;
+    const int64_t e = sa.fast ? ((s1 < full_end) ? s1 : ((full_end > s0) ? full_end : s0)) : s0;
+    if (e > s0) {
+        const int64_t last = e - 1;
+        sa.load_full(s0 * RB);
+        sb.load_full(((s0 + 1 < last) ? s0 + 1 : last) * RB);
+        int64_t sg = s0;
+        for (; sg + 1 < e; sg += 2) {
+            __syncthreads();
+            sa.store_all(Xs, pin);
+            __syncthreads();
+            sa.load_full(((sg + 2 < last) ? sg + 2 : last) * RB);
+            compute(sg);
+            __syncthreads();
+            sb.store_all(Xs, pin);
+            __syncthreads();
+            sb.load_full(((sg + 3 < last) ? sg + 3 : last) * RB);
+            compute(sg + 1);
+        }
+        if (sg < e) {
+            __syncthreads();
+            sa.store_all(Xs, pin);
+            __syncthreads();
+            compute(sg);
+        }
+    }
+    for (int64_t sg = e; sg < s1; ++sg) {
+        sa.load(s, m, sg * RB, pin, vec);
+        __syncthreads();
+        sa.store(Xs, PI, pin);
+        __syncthreads();
+        compute(sg);
     }
 }
 
@@ -461,7 +625,7 @@ __global__ __launch_bounds__(256) void k_gemm_tall_b(const TallArgs *__restrict_
 {
     const TallArgs &a = arr[blockIdx.y];
     if ((int)blockIdx.x >= a.nb || a.ds->done) return;
-    gemm_tall_body<TC, ITEMS, false>(make_src<TC>(a.d), a.d.m, a.ds, a.sel_in, a.sel_out, a.pin_max, a.pout_max,
+    gemm_tall_body<TC, ITEMS, false>(make_src<TC>(a.d), a.d.m, a.ds, a.sel_in, a.sel_out, ITEMS * 256 / GRP, a.pout_max,
                                      reinterpret_cast<const TC *>(a.T), a.ldt, reinterpret_cast<TC *>(a.Yout),
                                      reinterpret_cast<TC *>(a.Yout1), a.vec, blockIdx.x);
 }
@@ -471,7 +635,8 @@ static void tall_launch(const GemmDesc &d, const DevState *ds, int32_t which_in,
                         const void *T, int32_t ldt, void *Yout, void *Yout1, unsigned nb, hipStream_t st)
 {
     const SrcT<TC> s = make_src<TC>(d);
-    const size_t lds = (size_t)(PI * LDSR + (TG ? 0 : PI * PO)) * sizeof(TC);
+    constexpr int CW = ITEMS * 256 / GRP;   // columns of the LDS stage (every item stored)
+    const size_t lds = (size_t)(CW * LDSR + (TG ? 0 : PI * PO)) * sizeof(TC);
     static bool attr = false;
     if (lds > 64 * 1024 && !attr) {
         if (hipFuncSetAttribute((const void *)k_gemm_tall<TC, ITEMS, TG>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -480,7 +645,7 @@ static void tall_launch(const GemmDesc &d, const DevState *ds, int32_t which_in,
         attr = true;
     }
     hipLaunchKernelGGL((k_gemm_tall<TC, ITEMS, TG>), dim3(nb), dim3(256), lds, st, s, d.m, ds, which_in, which_out,
-                       PI, PO, (const TC *)T, ldt, (TC *)Yout, (TC *)Yout1, (int)vec_ok(s, d.m));
+                       CW, PO, (const TC *)T, ldt, (TC *)Yout, (TC *)Yout1, (int)vec_ok(s, d.m));
 }
 
 hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
@@ -580,14 +745,15 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
             }
         }
     };
+    stu.prepare(su, m, r, vec);
     if (s0 < s1) {
         loadA(s0);
         stu.load(su, m, s0 * RB, r, vec);
     }
     for (int64_t sg = s0; sg < s1; ++sg) {
         __syncthreads();
-        sta.store(As, PCB);
-        stu.store(Us, RP);
+        sta.store(As, PCB, PCB);
+        stu.store(Us, RP, r);
         __syncthreads();
         if (sg + 1 < s1) {
             loadA(sg + 1);
@@ -692,10 +858,10 @@ hipError_t launch_gram_partial_b(const GramArgs *arr, int32_t count, int32_t max
     const dim3 grid((unsigned)max_nblk, (unsigned)count);
     if (prec == POD_F64)
         hipLaunchKernelGGL((k_gram_partial_b<double, MAXPW64, ITEMS64>), grid, dim3(256),
-                           (size_t)pmax_max * LDSR * sizeof(double), st, arr);
+                           (size_t)64 * LDSR * sizeof(double), st, arr);
     else
         hipLaunchKernelGGL((k_gram_partial_b<float, MAXPW64, ITEMS64>), grid, dim3(256),
-                           (size_t)pmax_max * LDSR * sizeof(float), st, arr);
+                           (size_t)64 * LDSR * sizeof(float), st, arr);
     return hipGetLastError();
 }
 
@@ -714,10 +880,10 @@ hipError_t launch_gemm_tall_b(const TallArgs *arr, int32_t count, int32_t max_nb
     const dim3 grid((unsigned)max_nb, (unsigned)count);
     if (prec == POD_F64)
         hipLaunchKernelGGL((k_gemm_tall_b<double, ITEMS64>), grid, dim3(256),
-                           (size_t)(pi_max * LDSR + pi_max * po_max) * sizeof(double), st, arr);
+                           (size_t)(64 * LDSR + pi_max * po_max) * sizeof(double), st, arr);
     else
         hipLaunchKernelGGL((k_gemm_tall_b<float, ITEMS64>), grid, dim3(256),
-                           (size_t)(pi_max * LDSR + pi_max * po_max) * sizeof(float), st, arr);
+                           (size_t)(64 * LDSR + pi_max * po_max) * sizeof(float), st, arr);
     return hipGetLastError();
 }
 
@@ -730,7 +896,8 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
     if (PI > PMAX_WIDE || PO > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)tall_blocks(d.m);
     const TallScatter sc{split, cmap, D, ldd};
-    const size_t lds = (size_t)(PI * LDSR + PI * PO) * esz;
+    const int CW = (PI > 64) ? 160 : 64;   // columns of the LDS stage of the tile class
+    const size_t lds = (size_t)(CW * LDSR + PI * PO) * esz;
     if (d.prec == POD_F64) {
         const SrcT<double> s = make_src<double>(d);
         if (PI > 64) {
@@ -742,11 +909,11 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
                 attr = true;
             }
             hipLaunchKernelGGL((k_gemm_tall_scatter<double, ITEMS160>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
-                               which_in, which_out, PI, (const double *)T, ldt, (double *)Yout, sc,
+                               which_in, which_out, CW, (const double *)T, ldt, (double *)Yout, sc,
                                (int)vec_ok(s, d.m));
         } else {
             hipLaunchKernelGGL((k_gemm_tall_scatter<double, ITEMS64>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
-                               which_in, which_out, PI, (const double *)T, ldt, (double *)Yout, sc,
+                               which_in, which_out, CW, (const double *)T, ldt, (double *)Yout, sc,
                                (int)vec_ok(s, d.m));
         }
     } else {
@@ -760,11 +927,11 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
                 attr = true;
             }
             hipLaunchKernelGGL((k_gemm_tall_scatter<float, ITEMS160>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
-                               which_in, which_out, PI, (const float *)T, ldt, (float *)Yout, sc,
+                               which_in, which_out, CW, (const float *)T, ldt, (float *)Yout, sc,
                                (int)vec_ok(s, d.m));
         } else {
             hipLaunchKernelGGL((k_gemm_tall_scatter<float, ITEMS64>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
-                               which_in, which_out, PI, (const float *)T, ldt, (float *)Yout, sc,
+                               which_in, which_out, CW, (const float *)T, ldt, (float *)Yout, sc,
                                (int)vec_ok(s, d.m));
         }
     }

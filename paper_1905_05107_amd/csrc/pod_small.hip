@@ -18,47 +18,135 @@ constexpr int NT = EIG_NT;
 constexpr int SMALL_LDS_P = 64;
 constexpr size_t lds_limit(bool big)
 {
-    return big ? (size_t)EIG_LU_THREADS * eig_lu_stride(EIG_NMAX) * sizeof(double)
-               : (size_t)(3 * SMALL_LDS_P * SMALL_LDS_P + EIG_LU_THREADS * eig_lu_stride(SMALL_LDS_P)) * sizeof(double);
+    return big ? (size_t)eig_lu_doubles(EIG_NMAX) * sizeof(double)
+               : (size_t)(3 * SMALL_LDS_P * SMALL_LDS_P + eig_lu_doubles(SMALL_LDS_P)) * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
-// In-place Cholesky S = R^T R of the symmetric p x p matrix S (LDS,
-// column-major); on success the upper triangle holds R and the strict lower
-// triangle is zeroed.  Fails (returns 1, uniformly across the block) when a
-// pivot is not above `thr`.
+// In-place Cholesky S = R^T R of the symmetric p x p matrix S (column-major,
+// ld p); on success the upper triangle holds R and the strict lower triangle
+// is zeroed.  Fails (returns 1, uniformly across the block) when a pivot is
+// not above `thr`.  Blocked right-looking form with panels of 16: the
+// diagonal block is factored by wave 0 with its columns in registers (lane c
+// holds column c; rows move between lanes by readlane), the panel rows right
+// of it are solved one column per thread, and the trailing matrix takes one
+// rank-16 update -- three barriers per panel.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// 1/sqrt(x) from the hardware estimate and two Newton steps (x > 0 normal).
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
 __device__ int chol_upper(double *S, int p, double thr)
 {
-    // Step j updates the trailing block with the unscaled row j and 1/d_j,
-    // and scales row j-1 (which step j no longer reads): one barrier per step.
-    for (int j = 0; j < p; ++j) {
-        const double d = S[j + j * p];
-        if (!(d > thr)) return 1;
-        const double inv_d = 1.0 / d;
-        if (j > 0) {
-            const double rp = sqrt(S[(j - 1) + (j - 1) * p]);
-            const double irp = 1.0 / rp;
-            for (int k = j - 1 + (int)threadIdx.x; k < p; k += NT)
-                S[(j - 1) + k * p] = (k == j - 1) ? rp : S[(j - 1) + k * p] * irp;
-        }
-        const int q = p - j - 1;
-        const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-        for (int kk = ty; kk < q; kk += NT / 32) {
-            const int k = j + 1 + kk;
-            const double sjk = S[j + k * p] * inv_d;
-            for (int ii = tx; ii <= kk; ii += 32) {
-                const int i = j + 1 + ii;
-                S[i + k * p] -= S[j + i * p] * sjk;
+    __shared__ int sfail;
+    __shared__ double srow[16], sinv[16], sW[16 * 16];
+    const int t = threadIdx.x;
+    if (t == 0) sfail = 0;
+    __syncthreads();
+    for (int J = 0; J < p; J += 16) {
+        const int nb = (p - J < 16) ? p - J : 16;
+        const int c0 = J + nb, q = p - c0;
+        if (t < 64) {
+            // diagonal block: lane c holds column J + c (rows J..J+15) in registers;
+            // row k is broadcast through srow after its scaling.  Lanes left of
+            // column k hold zeros there and lanes at or below the diagonal only
+            // touch entries that are never stored, so no lane is masked.
+            double col[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) col[i] = (t < nb && i <= t) ? S[(J + i) + (J + t) * p] : 0.0;
+            int fail = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < nb) {
+                    const double d = readlane_f64(col[k], k);
+                    if (!(d > thr)) fail = 1;
+                    const double ik = rsqrt_nr(fmax(d, 1e-300));
+                    col[k] *= ik;   // lane k: sqrt(d); lanes right of it: row k of R
+                    if (t < 16) srow[t] = col[k];
+                    if (t == k) sinv[k] = ik;
+#pragma unroll
+                    for (int i = k + 1; i < 16; ++i) col[i] -= srow[i] * col[k];
+                }
+            }
+            if (t == 0 && fail) sfail = 1;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (t < nb && i <= t) S[(J + i) + (J + t) * p] = col[i];
+            // W = R_JJ^-1 (upper, 16 x 16): lane j < nb solves column j by back
+            // substitution (fully unrolled: the loads of R are issued together);
+            // W is kept in sW (ld 16)
+            if (q > 0) {
+                const double *Rb = S + J + J * p;
+                double w[16];
+#pragma unroll
+                for (int i = 15; i >= 0; --i) {
+                    double v = (i == t) ? 1.0 : 0.0;
+#pragma unroll
+                    for (int l = i + 1; l < 16; ++l)
+                        if (l < nb) v -= Rb[i + l * p] * w[l];
+                    w[i] = (i < nb && i <= t) ? v * sinv[i] : 0.0;
+                    __builtin_amdgcn_sched_barrier(0);   // keep the loads of one row together
+                }
+                if (t < 16) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) sW[i + t * 16] = w[i];
+                }
             }
         }
         __syncthreads();
+        if (sfail) return 1;
+        if (q > 0) {
+            // rows J..J+nb of the columns right of the block: X = W^T S(J:J+nb, c0:p),
+            // one thread per column (the column is read whole before rows are written)
+            for (int c = c0 + t; c < p; c += NT) {
+                double *bc = S + J + c * p;
+                double b[16];
+#pragma unroll
+                for (int k2 = 0; k2 < 16; ++k2) b[k2] = (k2 < nb) ? bc[k2] : 0.0;
+#pragma unroll
+                for (int i = 15; i >= 0; --i) {
+                    if (i < nb) {
+                        double v = 0.0;
+#pragma unroll
+                        for (int k2 = 0; k2 <= i; ++k2) v += sW[k2 + i * 16] * b[k2];
+                        bc[i] = v;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            __syncthreads();
+            // trailing update of the upper triangle: S(i, c) -= sum_k R(k, i) R(k, c)
+            const int tx = t & 31, ty = t >> 5;
+            for (int c = c0 + ty; c < p; c += NT / 32) {
+                const double *rc = S + J + c * p;
+                for (int i = c0 + tx; i <= c; i += 32) {
+                    const double *ri = S + J + i * p;
+                    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                    for (int k2 = 0; k2 < 16; k2 += 2) {
+                        if (k2 < nb) a0 += ri[k2] * rc[k2];
+                        if (k2 + 1 < nb) a1 += ri[k2 + 1] * rc[k2 + 1];
+                    }
+                    S[i + c * p] -= a0 + a1;
+                }
+            }
+            __syncthreads();
+        }
     }
-    {
-        const double rp = sqrt(S[(p - 1) + (p - 1) * p]);
-        if (threadIdx.x == 0) S[(p - 1) + (p - 1) * p] = rp;
-    }
-    for (int idx = threadIdx.x; idx < p * p; idx += NT) {
+    for (int idx = t; idx < p * p; idx += NT) {
         const int i = idx % p, k = idx / p;
         if (i > k) S[idx] = 0.0;
     }
@@ -66,32 +154,69 @@ __device__ int chol_upper(double *S, int p, double thr)
     return 0;
 }
 
-// In-place inverse of the upper-triangular p x p matrix R (LDS, column-major).
-// Column j of the inverse: X(j,j) = 1/R(j,j), X(0:j-1, j) = -X(0:j-1,0:j-1) R(0:j-1, j) / R(j,j),
-// using the already inverted leading block.  Each of the j dot products is
-// split over G threads and combined by shuffles.  `tmp` holds p doubles.
-__device__ void trinv_upper(double *R, int p, double *tmp)
+// Broadcast of lane O of each aligned group of 8 lanes to the whole group
+// (a quad_perm broadcast, then a half-row mirror for the other quad).
+template <int O> __device__ __forceinline__ double bcast8(double v)
 {
-    int G = 64;
-    while (G > 1 && p * G > NT) G >>= 1;
-    const int row = threadIdx.x / G, gl = threadIdx.x % G;
-    for (int j = 0; j < p; ++j) {
-        const double rjj = R[j + j * p];
-        const double inv = 1.0 / rjj;
-        double s = 0.0;
-        if (row < j) {
-            // X(row, l) for l in [row, j) is already inverted; R(l, j) is still original
-            for (int l = row + gl; l < j; l += G) s += R[row + l * p] * R[l + j * p];
-        }
+    constexpr int q = O & 3;
+    constexpr int ctrl = q | (q << 2) | (q << 4) | (q << 6);
+    const double v1 = dpp_f64<ctrl>(v);
+    const double v2 = dpp_f64<0x141>(v1);
+    return (((threadIdx.x >> 2) & 1) == (O >> 2)) ? v1 : v2;
+}
+
+// X = R^-1 for the upper-triangular p x p matrix R (column-major, ld p); X
+// must not alias R.  Column j of X solves R x = e_j by back substitution in
+// one group of 8 lanes: lane gl keeps the right-hand side of rows gl, gl+8,
+// ... in registers; step i broadcasts b_i from its lane inside the group, sets
+// x_i = b_i / R_ii and updates the rows above.  No barrier between the steps;
+// `tmp` (p doubles) holds the reciprocals of the diagonal.  SL = ceil(p/8)
+// register slots.
+template <int SL> __device__ void trinv_cols(const double *R, int p, double *X, double *tmp)
+{
+    for (int i = threadIdx.x; i < p; i += NT) tmp[i] = 1.0 / R[i + i * p];
+    __syncthreads();
+    const int gl = threadIdx.x & 7;
+    for (int j = threadIdx.x >> 3; j < p; j += NT / 8) {
+        double b[SL];
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1)
-            if (o < G) s += __shfl_xor(s, o, 64);
-        if (row < j && gl == 0) tmp[row] = -s * inv;
-        __syncthreads();
-        if (row < j && gl == 0) R[row + j * p] = tmp[row];
-        if (threadIdx.x == 0) R[j + j * p] = inv;
-        __syncthreads();
+        for (int s = 0; s < SL; ++s) b[s] = (8 * s + gl == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int s = SL - 1; s >= 0; --s) {
+            if (8 * s > j) continue;   // uniform in the group
+            double bs = b[s];
+#pragma unroll 1
+            for (int o = 7; o >= 0; --o) {
+                const int i = 8 * s + o;
+                if (i > j) continue;
+                double bi;
+                switch (o) {
+                case 0: bi = bcast8<0>(bs); break;
+                case 1: bi = bcast8<1>(bs); break;
+                case 2: bi = bcast8<2>(bs); break;
+                case 3: bi = bcast8<3>(bs); break;
+                case 4: bi = bcast8<4>(bs); break;
+                case 5: bi = bcast8<5>(bs); break;
+                case 6: bi = bcast8<6>(bs); break;
+                default: bi = bcast8<7>(bs); break;
+                }
+                const double xi = bi * tmp[i];
+                if (gl == o) X[i + j * p] = xi;
+                // rows of this slot below lane o, then the earlier slots
+                if (gl < o) bs -= R[(8 * s + gl) + i * p] * xi;
+#pragma unroll
+                for (int s2 = 0; s2 < s; ++s2) b[s2] -= R[(8 * s2 + gl) + i * p] * xi;
+            }
+        }
+        for (int l = j + 1 + gl; l < p; l += 8) X[l + j * p] = 0.0;
     }
+    __syncthreads();
+}
+
+// p <= 64 (BIG = false) or p <= 160 (BIG = true)
+template <bool BIG> __device__ __forceinline__ void trinv_upper(const double *R, int p, double *X, double *tmp)
+{
+    trinv_cols<BIG ? 20 : 8>(R, p, X, tmp);
 }
 
 template <typename T> __device__ __forceinline__ void store_t(void *base, int64_t idx, double v)
@@ -125,7 +250,7 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
     const int pm = a.pmax;
     double *S = BIG ? a.ws : lds;       // p x p
     double *tmp = S + pm * pm;          // p doubles
-    double *GP = tmp + pm;              // G0 P (p0 x p), dense right factor only
+    double *GP = tmp + pm;              // G0 P (p0 x p) with a dense right factor; then R1^-1
     if (threadIdx.x == 0) sbad = 0;
     const double *sigma = (ds->it & 1) ? a.sig1 : a.sig0;
     for (int i = threadIdx.x; i < p; i += NT) sP[i] = (i < rs) ? sigma[i] : (a.sigma2 ? a.sigma2[i - rs] : 1.0);
@@ -197,18 +322,19 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
         a.R1[idx] = (i < p && j < p) ? S[i + j * p] : 0.0;
     }
     __syncthreads();
-    trinv_upper(S, p, tmp);
+    double *Xi = GP;   // R1^-1 (the G0 P product is no longer needed)
+    trinv_upper<BIG>(S, p, Xi, tmp);
     // T1 = P R1^-1 (p0 x p)
     for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
         const int i = idx % pm, j = idx / pm;
         double v = 0.0;
         if (!a.use_vt) {
-            if (i < p && j < p) v = sP[i] * S[i + j * p];
+            if (i < p && j < p) v = sP[i] * Xi[i + j * p];
         } else if (i < p0 && j < p) {
             if (i < rs) {
-                v = sP[i] * S[i + j * p];
+                v = sP[i] * Xi[i + j * p];
             } else {
-                for (int l = rs; l <= j; ++l) v += a.Vt[(i - rs) + (l - rs) * pm] * S[l + j * p];
+                for (int l = rs; l <= j; ++l) v += a.Vt[(i - rs) + (l - rs) * pm] * Xi[l + j * p];
             }
         }
         store_c(a.Tc, a.prec, idx, v);
@@ -232,7 +358,7 @@ __global__ __launch_bounds__(512) void k_chol_first_b(const SmallArgs *__restric
 hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 {
     const bool big = a.pmax > SMALL_LDS_P;
-    const size_t lds = big ? (0) : ((size_t)((a.use_vt ? 2 : 1) * a.pmax * a.pmax + a.pmax) * sizeof(double));
+    const size_t lds = big ? (0) : ((size_t)(2 * a.pmax * a.pmax + a.pmax) * sizeof(double));
     static bool attr[2] = {false, false};
     const void *fn = big ? (const void *)k_chol_first<true> : (const void *)k_chol_first<false>;
     if (!attr[big]) {
@@ -280,7 +406,7 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
     double *S1 = BIG ? a.ws : lds; // G2 -> R2 -> R2^-1
     double *S2 = S1 + p * p;       // R1 -> H = R R^T -> reflectors -> B^T B
     double *S3 = S1 + 2 * p * p;   // R -> eigenvectors Y (p x r')
-    double *lu = BIG ? lds : lds + 3 * p * p;  // EIG_LU_THREADS x eig_lu_stride(p)
+    double *lu = BIG ? lds : lds + 3 * p * p;  // eig_lu_doubles(p)
     // ---- pass-2 Cholesky
     double tr = 0.0;
     for (int idx = threadIdx.x; idx < p * p; idx += NT) {
@@ -394,13 +520,13 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
             }
         }
     }
-    // ---- Z2 = R2^-1 U_R(:, 0:rnew)
-    trinv_upper(S1, p, spv);
+    // ---- Z2 = R2^-1 U_R(:, 0:rnew)  (R2^-1 into S2, free after the sines)
+    trinv_upper<BIG>(S1, p, S2, spv);
     for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
         const int i = idx % pm, j = idx / pm;
         double s = 0.0;
         if (i < p && j < rnew)
-            for (int l = i; l < p; ++l) s += S1[i + l * p] * S3[l + j * p];
+            for (int l = i; l < p; ++l) s += S2[i + l * p] * S3[l + j * p];
         store_c(a.Tc, a.prec, idx, s);
     }
     double *sigma_new = (it0 & 1) ? a.sig0 : a.sig1;
@@ -431,7 +557,7 @@ __global__ __launch_bounds__(512) void k_svd_merge_b(const SmallArgs *__restrict
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
 {
     const bool big = a.pmax > SMALL_LDS_P;
-    const size_t lds = big ? ((size_t)(EIG_LU_THREADS * eig_lu_stride(a.pmax)) * sizeof(double)) : ((size_t)(3 * a.pmax * a.pmax + EIG_LU_THREADS * eig_lu_stride(a.pmax)) * sizeof(double));
+    const size_t lds = big ? ((size_t)(eig_lu_doubles(a.pmax)) * sizeof(double)) : ((size_t)(3 * a.pmax * a.pmax + eig_lu_doubles(a.pmax)) * sizeof(double));
     static bool attr[2] = {false, false};
     const void *fn = big ? (const void *)k_svd_merge<true> : (const void *)k_svd_merge<false>;
     if (!attr[big]) {
@@ -463,7 +589,7 @@ __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
     const int r = a.r, k = a.k;
     double *S = BIG ? a.ws : lds; // G_B -> reflectors
     double *Y = S + r * r;        // eigenvectors (r x k)
-    double *lu = BIG ? lds : Y + r * r;  // EIG_LU_THREADS x eig_lu_stride(r)
+    double *lu = BIG ? lds : Y + r * r;  // eig_lu_doubles(r)
     // G_B entries, one wave per entry group, lanes along n
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int e = wv; e < r * r; e += NT / 64) {
@@ -491,7 +617,7 @@ __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
 hipError_t launch_rr_small(const RRArgs &a, hipStream_t st)
 {
     const bool big = a.r > SMALL_LDS_P;
-    const size_t lds = big ? ((size_t)(EIG_LU_THREADS * eig_lu_stride(a.r)) * sizeof(double)) : ((size_t)(2 * a.r * a.r + EIG_LU_THREADS * eig_lu_stride(a.r)) * sizeof(double));
+    const size_t lds = big ? ((size_t)(eig_lu_doubles(a.r)) * sizeof(double)) : ((size_t)(2 * a.r * a.r + eig_lu_doubles(a.r)) * sizeof(double));
     static bool attr[2] = {false, false};
     const void *fn = big ? (const void *)k_rr_small<true> : (const void *)k_rr_small<false>;
     if (!attr[big]) {
@@ -645,7 +771,7 @@ __global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
     const int pm = a.pmax;
     double *S = BIG ? a.ws : lds; // G_B (g x g) -> reflectors
     double *Y = S + pm * pm;      // eigenvectors (g x ru)
-    double *lu = BIG ? lds : Y + pm * pm;  // EIG_LU_THREADS x eig_lu_stride(g)
+    double *lu = BIG ? lds : Y + pm * pm;  // eig_lu_doubles(g)
     const int h = (a.mode == 0) ? ds->h : g;
     if (g == 0 || h == 0) {
         if (threadIdx.x == 0) {
@@ -707,7 +833,7 @@ __global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
 hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st)
 {
     const bool big = a.pmax > SMALL_LDS_P;
-    const size_t lds = big ? ((size_t)(EIG_LU_THREADS * eig_lu_stride(a.pmax)) * sizeof(double)) : ((size_t)(2 * a.pmax * a.pmax + EIG_LU_THREADS * eig_lu_stride(a.pmax)) * sizeof(double));
+    const size_t lds = big ? ((size_t)(eig_lu_doubles(a.pmax)) * sizeof(double)) : ((size_t)(2 * a.pmax * a.pmax + eig_lu_doubles(a.pmax)) * sizeof(double));
     static bool attr[2] = {false, false};
     const void *fn = big ? (const void *)k_block_eig<true> : (const void *)k_block_eig<false>;
     if (!attr[big]) {
@@ -749,7 +875,7 @@ hipError_t launch_svd_merge_b(const SmallArgs *arr, int32_t count, int32_t pmax_
         attr = true;
     }
     hipLaunchKernelGGL(k_svd_merge_b, dim3(1, (unsigned)count), dim3(NT),
-                       (size_t)(3 * pmax_max * pmax_max + EIG_LU_THREADS * eig_lu_stride(pmax_max)) * sizeof(double),
+                       (size_t)(3 * pmax_max * pmax_max + eig_lu_doubles(pmax_max)) * sizeof(double),
                        st, arr);
     return hipGetLastError();
 }
@@ -799,7 +925,7 @@ __global__ __launch_bounds__(512) void k_adj_small(AdjArgs a)
         H[idx] = s;
     }
     __syncthreads();
-    trinv_upper(wRi, p, spv);
+    trinv_upper<false>(wR, p, wRi, spv);
     tridiag(H, p, sd, se, stau, spv, ssc);
     bisect_top(sd, se, p, p, sev, se2, ssc);
     tri_invit(sd, se, p, sev, p, Y, lu, scl);
@@ -901,7 +1027,7 @@ hipError_t launch_adj_small(const AdjArgs &a, hipStream_t st)
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const size_t lds = (size_t)(2 * p * p + EIG_LU_THREADS * eig_lu_stride(p)) * sizeof(double);
+    const size_t lds = (size_t)(2 * p * p + eig_lu_doubles(p)) * sizeof(double);
     hipLaunchKernelGGL(k_adj_small, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }

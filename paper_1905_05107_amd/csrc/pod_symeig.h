@@ -36,6 +36,14 @@ __device__ __forceinline__ double rcp_nr(double x)
     return fma(y, e, y);
 }
 
+// One Newton step only: relative error ~2^-50, enough for the Sturm counts
+// (only the signs of the pivots matter, away from the bisection tolerance).
+__device__ __forceinline__ double rcp_nr1(double x)
+{
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
 // Sums over aligned groups of G lanes by DPP moves inside a row of 16
 // (mirror, half-mirror, quad permutations: no LDS traffic), and over the 64
 // lanes of a wave (two cross-row shuffles on top).  Every lane gets the sum.
@@ -93,24 +101,36 @@ __device__ void tridiag(double *A, int n, double *d, double *e, double *tau, dou
             double *A22 = A + (j + 1) * n + (j + 1);
             const int gl = t & 7;
             // the 8 lanes of a group share `row`, so a group is active or idle as a whole
+            // (x[0] still holds x0 during this step: v = x + (v0 - x0) e1)
+            const double dv = v0 - x0;
             for (int row = t >> 3; row < q; row += EIG_NT / 8) {
-                double s = 0.0;
-                for (int k = gl; k < q; k += 8) s += A22[row + k * n] * ((k == 0) ? v0 : x[k]);
+                double s0 = 0.0, s1 = 0.0;
+                int k = gl;
+                for (; k + 8 < q; k += 16) {
+                    s0 += A22[row + k * n] * x[k];
+                    s1 += A22[row + (k + 8) * n] * x[k + 8];
+                }
+                if (k < q) s0 += A22[row + k * n] * x[k];
+                double s = s0 + s1;
+                if (gl == 0) s += A22[row] * dv;
                 s = group_sum<8>(s);
                 if (gl == 0) pv[row] = tj * s;
             }
             __syncthreads();
             // -- K = tau/2 p^T v (every wave), w = p - K v, A22 -= v w^T + w v^T
             double kp = 0.0;
-            for (int l = lane; l < q; l += 64) kp += pv[l] * ((l == 0) ? v0 : x[l]);
+            for (int l = lane; l < q; l += 64) kp += pv[l] * x[l];
+            if (lane == 0) kp += pv[0] * dv;
             const double kk = 0.5 * tj * wave_sum(kp);
             const int tx = t & 31, ty = t >> 5;
             for (int b = ty; b < q; b += EIG_NT / 32) {
-                const double vb = (b == 0) ? v0 : x[b];
+                const double xb = x[b];
+                const double vb = (b == 0) ? v0 : xb;
                 const double wb = pv[b] - kk * vb;
                 for (int a = tx; a < q; a += 32) {
-                    const double va = (a == 0) ? v0 : x[a];
-                    const double wa = pv[a] - kk * va;
+                    const double xa = x[a], pa = pv[a];
+                    const double va = (a == 0) ? v0 : xa;
+                    const double wa = pa - kk * va;
                     A22[a + b * n] -= va * wb + wa * vb;
                 }
             }
@@ -143,15 +163,15 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
     int i = 1;
     for (; i + 1 < n; i += 2) {
         const double da = d[i] - x, db = d[i + 1] - x, ea = e2[i - 1], eb = e2[i];
-        q = da - ea * rcp_nr(q);
+        q = da - ea * rcp_nr1(q);
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
-        q = db - eb * rcp_nr(q);
+        q = db - eb * rcp_nr1(q);
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
     }
     if (i < n) {
-        q = (d[i] - x) - e2[i - 1] * rcp_nr(q);
+        q = (d[i] - x) - e2[i - 1] * rcp_nr1(q);
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
     }
@@ -164,7 +184,8 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
 // each refine one eigenvalue by multisection: G Sturm counts per round at
 // equally spaced interior points, the interval shrinking to the sub-interval
 // where the count passes the eigenvalue's index.  Stops at width
-// <= 2 u max(|a|, |b|) + 4 pivmin.  `e2` holds n doubles.
+// <= max(2 u max(|a|, |b|), 4 u |T|) + 4 pivmin (|T| from the Gershgorin
+// interval).  `e2` holds n doubles.
 // ---------------------------------------------------------------------------
 __device__ void bisect_top(const double *d, const double *e, int n, int nv, double *ev, double *e2, double *sc)
 {
@@ -196,8 +217,10 @@ __device__ void bisect_top(const double *d, const double *e, int n, int nv, doub
     double a = sc[0], b = sc[1];
     // lanes of the group as a bit-field within the wave
     const int gbase = lane - gl;
+    // absolute accuracy 4 u |T| (LAPACK's default for bisection), or relative 2 u
+    const double atol = 4.0 * u * fmax(fabs(sc[0]), fabs(sc[1]));
     for (int round = 0; round < 80; ++round) {
-        const bool done = !active || (b - a) <= 2.0 * u * fmax(fabs(a), fabs(b)) + 4.0 * pivmin;
+        const bool done = !active || (b - a) <= fmax(2.0 * u * fmax(fabs(a), fabs(b)), atol) + 4.0 * pivmin;
         // all lanes of a group share `done`; a wave leaves when all its groups are done
         if (__all(done)) break;
         const double x = a + (b - a) * (double)(gl + 1) / (double)(G + 1);
@@ -247,6 +270,8 @@ constexpr int EIG_LU_THREADS = 16;
 // doubles per thread of the `lu` scratch: three diagonals of U, the
 // multipliers and n interchange flags (ints, two per double), made odd
 __host__ __device__ constexpr int eig_lu_stride(int n) { return (4 * n + (n + 1) / 2) | 1; }
+// doubles of the whole `lu` scratch for dimension n
+__host__ __device__ constexpr int eig_lu_doubles(int n) { return EIG_LU_THREADS * eig_lu_stride(n); }
 
 __device__ void tri_invit(const double *d, const double *e, int n, const double *ev, int nv, double *Y, double *lu,
                           int *scl)
@@ -278,53 +303,47 @@ __device__ void tri_invit(const double *d, const double *e, int n, const double 
             for (int mi = i0; mi < i1; ++mi) {
                 // perturb equal eigenvalues inside a cluster so the solves differ
                 const double lam = ev[mi] + (double)(mi - i0) * 4.0 * u * tn;
-                // factor: rows (r0, r1, r2) at cols (i, i+1, i+2)
+                // factor: rows (r0, r1, r2) at cols (i, i+1, i+2); u1 keeps 1 / pivot
                 double r0 = d[0] - lam, r1 = (n > 1) ? e[0] : 0.0, r2 = 0.0;
+#pragma unroll 4
                 for (int i = 0; i + 1 < n; ++i) {
                     const double s0 = e[i], s1 = d[i + 1] - lam, s2 = (i + 2 < n) ? e[i + 1] : 0.0;
-                    double p0, p1, p2, o1, o2, mult;
                     const bool swap = !(fabs(r0) >= fabs(s0));
-                    if (!swap) {
-                        p0 = r0; p1 = r1; p2 = r2;
-                        if (p0 == 0.0) p0 = u * tn + 1e-300;
-                        mult = s0 * rcp_nr(p0);
-                        o1 = s1; o2 = s2;
-                    } else {
-                        p0 = s0; p1 = s1; p2 = s2;
-                        mult = r0 * rcp_nr(p0);
-                        o1 = r1; o2 = r2;
-                    }
-                    u1[i] = p0; u2[i] = p1; u3[i] = p2; ml[i] = mult;
+                    double p0 = swap ? s0 : r0;
+                    const double p1 = swap ? s1 : r1, p2 = swap ? s2 : r2;
+                    const double o1 = swap ? r1 : s1, o2 = swap ? r2 : s2;
+                    if (p0 == 0.0) p0 = u * tn + 1e-300;
+                    const double ip = rcp_nr(p0);
+                    const double mult = (swap ? r0 : s0) * ip;
+                    u1[i] = ip; u2[i] = p1; u3[i] = p2; ml[i] = mult;
                     sw[i] = swap ? 1 : 0;
                     r0 = o1 - mult * p1;
                     r1 = o2 - mult * p2;
                     r2 = 0.0;
                 }
                 if (r0 == 0.0) r0 = u * tn + 1e-300;
-                u1[n - 1] = r0;
+                u1[n - 1] = rcp_nr(r0);
                 u2[n - 1] = 0.0;
                 u3[n - 1] = 0.0;
-                for (int i = 0; i < n; ++i) u1[i] = rcp_nr(u1[i]);   // store 1 / pivot
                 double *y = Y + (size_t)mi * n;
                 // start vector: fixed, not orthogonal to any eigenvector in practice
                 for (int i = 0; i < n; ++i) y[i] = 1.0 + 0.5 * (double)(((i + 3 * mi) * 2654435761u) % 1009u) / 1009.0;
                 for (int itn = 0; itn < 2; ++itn) {
                     // forward: the row operations, carrying the current row in a register
+                    // (loads batched by the unrolling; the chain runs through `cur`)
                     double cur = y[0];
+#pragma unroll 8
                     for (int i = 0; i + 1 < n; ++i) {
-                        double nxt = y[i + 1];
-                        if (sw[i]) {
-                            const double tmp = cur;
-                            cur = nxt;
-                            nxt = tmp;
-                        }
-                        nxt -= ml[i] * cur;
-                        y[i] = cur;
-                        cur = nxt;
+                        const double nx = y[i + 1];
+                        const bool s = sw[i] != 0;
+                        const double top = s ? nx : cur, bot = s ? cur : nx;
+                        y[i] = top;
+                        cur = bot - ml[i] * top;
                     }
                     y[n - 1] = cur;
                     // back substitution with U (3 diagonals), last two values in registers
                     double x1 = 0.0, x2 = 0.0;
+#pragma unroll 8
                     for (int i = n - 1; i >= 0; --i) {
                         const double sv = (y[i] - u2[i] * x1 - u3[i] * x2) * u1[i];
                         y[i] = sv;
@@ -335,19 +354,25 @@ __device__ void tri_invit(const double *d, const double *e, int n, const double 
                     for (int pj = i0; pj < mi; ++pj) {
                         const double *z = Y + (size_t)pj * n;
                         double dt = 0.0;
+#pragma unroll 8
                         for (int i = 0; i < n; ++i) dt += z[i] * y[i];
+#pragma unroll 8
                         for (int i = 0; i < n; ++i) y[i] -= dt * z[i];
                     }
-                    double mx = 0.0;
-                    for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(y[i]));
+                    double m4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+                    for (int i = 0; i < n; ++i) m4[i & 3] = fmax(m4[i & 3], fabs(y[i]));
+                    const double mx = fmax(fmax(m4[0], m4[1]), fmax(m4[2], m4[3]));
                     const double sm = (mx > 0.0) ? 1.0 / mx : 1.0;
-                    double nr = 0.0;
+                    double q4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
                     for (int i = 0; i < n; ++i) {
-                        y[i] *= sm;
-                        nr += y[i] * y[i];
+                        const double v = y[i] * sm;
+                        q4[i & 3] += v * v;
                     }
-                    const double inv = 1.0 / sqrt(nr);
-                    for (int i = 0; i < n; ++i) y[i] *= inv;
+                    const double f = sm / sqrt((q4[0] + q4[1]) + (q4[2] + q4[3]));
+#pragma unroll 8
+                    for (int i = 0; i < n; ++i) y[i] *= f;
                 }
             }
         }
@@ -367,12 +392,26 @@ __device__ void tridiag_backtransform(const double *A, const double *tau, int n,
         if (tj == 0.0) continue;   // uniform across the block
         const int q = n - j - 1;
         const double *v = A + j * n + (j + 1);
-        double s = 0.0;
-        if (col < nv)
-            for (int i = gl; i < q; i += G) s += v[i] * Y[(size_t)col * n + j + 1 + i];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1)
-            if (o < G) s += __shfl_xor(s, o, 64);
+        double s0 = 0.0, s1 = 0.0;
+        if (col < nv) {
+            const double *y = Y + (size_t)col * n + j + 1;
+            int i = gl;
+            for (; i + G < q; i += 2 * G) {
+                s0 += v[i] * y[i];
+                s1 += v[i + G] * y[i + G];
+            }
+            if (i < q) s0 += v[i] * y[i];
+        }
+        double s = s0 + s1;
+        switch (G) {   // groups are aligned and uniformly active
+        case 64: s = group_sum<64>(s); break;
+        case 32: s = group_sum<32>(s); break;
+        case 16: s = group_sum<16>(s); break;
+        case 8: s = group_sum<8>(s); break;
+        case 4: s = group_sum<4>(s); break;
+        case 2: s = group_sum<2>(s); break;
+        default: break;
+        }
         if (col < nv && gl == 0) dots[col] = tj * s;
         __syncthreads();
         for (int idx = t; idx < q * nv; idx += EIG_NT) {
