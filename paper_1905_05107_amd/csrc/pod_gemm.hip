@@ -488,7 +488,7 @@ hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax
 // the output as Y^T tiles = T^T X^T so that each lane's four results are
 // consecutive rows of one output column.
 // ---------------------------------------------------------------------------
-constexpr int TALL_ST = 4;   // row stages per workgroup
+constexpr int TALL_ST = 8;   // row stages per workgroup
 constexpr size_t TALL_T_LDS = 112 * 1024;  // largest T staged in LDS
 
 // Scatter output (SCAT): output columns below `split` go to Yout, column
@@ -536,7 +536,17 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
             const TC *xb = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
             if (!TG) {
                 const TC *ta = Ts + (lane >> 4) * PO + jc * 16 + (lane & 15);
-                for (int k4 = 0; k4 < PI; k4 += 4) acc = mfma16x16x4(ta[k4 * PO], xb[k4 * LDSR], acc);
+                // PI is a multiple of 16: four MFMAs with their operands loaded together
+                for (int k4 = 0; k4 < PI; k4 += 16) {
+                    TC av[4], xv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        av[u] = ta[(k4 + 4 * u) * PO];
+                        xv[u] = xb[(k4 + 4 * u) * LDSR];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc = mfma16x16x4(av[u], xv[u], acc);
+                }
             } else {
                 // T read from device memory (L2 resident), zero outside pin x pout
                 const int jj = jc * 16 + (lane & 15);
