@@ -1,0 +1,552 @@
+// pod_rl.h -- register-resident FP64 kernels for the small matrices of the
+// merge when n <= 64, for one workgroup of 512 threads (8 waves).
+//
+// Row layout: wave w keeps rows a = w + 8k (k = 0..7) of an n x n matrix in
+// r[k], lane l column l; rows and columns from n to 63 hold zeros.  The
+// factorisations below eliminate one row per step: the wave that owns it
+// finishes it, publishes it in LDS, and after one barrier every wave updates
+// its own rows in registers (no LDS round trip per matrix element).  Row-major
+// LDS copies use the odd leading dimension RL_LD.  Products of 64 x 64
+// operands run on the FP64 MFMA (16 x 16 x 4).
+#pragma once
+
+#include "pod_symeig.h"
+
+namespace pod {
+
+constexpr int RL_LD = 65;
+
+__device__ __forceinline__ int rl_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+__device__ __forceinline__ int rl_lane() { return threadIdx.x & 63; }
+// A wave-uniform int the optimiser cannot see through: tests against it stay
+// where they are written instead of being hoisted out of loops as one
+// predicate per unrolled step (which exhausts the scalar registers).
+__device__ __forceinline__ int opaque_uniform(int v)
+{
+    v = __builtin_amdgcn_readfirstlane(v);
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+// Load rows of the symmetric n x n matrix M (column-major, ld) into r: by
+// symmetry row a is column a, so the reads are contiguous.
+__device__ __forceinline__ void rl_load_sym(double (&r)[8], const double *M, int ld, int n)
+{
+    const int w = rl_wave(), l = rl_lane();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int a = w + 8 * k;
+        r[k] = (a < n && l < n) ? M[l + (size_t)a * ld] : 0.0;
+    }
+}
+
+// r <- rows of the row-major LDS matrix S (ld RL_LD, 64 rows).
+__device__ __forceinline__ void rl_load_rows(double (&r)[8], const double *S)
+{
+    const int w = rl_wave(), l = rl_lane();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = S[(w + 8 * k) * RL_LD + l];
+}
+
+// Rs = Xs = I_n (64 x 64, zero-padded).
+__device__ __forceinline__ void rl_identity(int n, double *Rs, double *Xs)
+{
+    const int w = rl_wave(), l = rl_lane();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int a = w + 8 * k;
+        const double v = (a == l && a < n) ? 1.0 : 0.0;
+        Rs[a * RL_LD + l] = v;
+        Xs[a * RL_LD + l] = v;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky G = R^T R of the symmetric matrix in r (upper triangle read) and
+// X = R^-T alongside: the rows of [G | I] are eliminated in order (outer-
+// product Cholesky, Golub & Van Loan Alg. 4.2.2, on the augmented matrix,
+// which carries out the forward substitution R^T X = I step by step).  Row j
+// is scaled by 1/sqrt(pivot) by its owner wave and published; every wave then
+// subtracts R(j, a) times it from its rows a > j.  One barrier per row.
+// On return Rs and Xs (LDS, row-major, ld RL_LD, 64 rows, zero-padded) hold R
+// and X = R^-T (so R^-1(i, j) = Xs[j * RL_LD + i]).  Returns nonzero,
+// uniformly, when a pivot is not above thr (the factors are then garbage).
+// r and x are overwritten; `sfl` is 8 ints of LDS.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int rl_cholinv(double (&r)[8], int n, double thr, double *Rs, double *Xs, int *sfl)
+{
+    const int w = rl_wave(), l = rl_lane();
+    double x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = (l == w + 8 * k && l < n) ? 1.0 : 0.0;
+    int fail = 0;
+#pragma unroll
+    for (int J = 0; J < 8; ++J) {
+        for (int w0 = 0; w0 < 8; ++w0) {
+            const int j = 8 * J + w0;
+            if (j >= n) break;
+            if (w == w0) {
+                const double d = readlane_f64(r[J], j);
+                if (!(d > thr)) fail = 1;
+                const double s = rsqrt_nr(fmax(d, 1e-300));
+                const double rv = (l >= j) ? r[J] * s : 0.0;
+                const double xv = x[J] * s;
+                r[J] = rv;
+                x[J] = xv;
+                Rs[j * RL_LD + l] = rv;
+                Xs[j * RL_LD + l] = xv;
+            }
+            __syncthreads();
+            const double rj = Rs[j * RL_LD + l], xj = Xs[j * RL_LD + l];
+#pragma unroll
+            for (int k = J; k < 8; ++k) {
+                const int a = w + 8 * k;
+                const double c = Rs[j * RL_LD + a];
+                if (a > j && a < n) {
+                    r[k] -= c * rj;
+                    x[k] -= c * xj;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int a = w + 8 * k;
+        if (a >= n) {
+            Rs[a * RL_LD + l] = 0.0;
+            Xs[a * RL_LD + l] = 0.0;
+        }
+    }
+    if (l == 0) sfl[w] = fail;
+    __syncthreads();
+    int f = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) f |= sfl[q];
+    __syncthreads();
+    return f;
+}
+
+// ---------------------------------------------------------------------------
+// Householder tridiagonalisation T = Q^T A Q of the symmetric matrix in r
+// (Golub & Van Loan Alg. 8.3.1), Q = H_0 ... H_{n-3},
+// H_j = I - tau_j v_j v_j^T.  Step j: the owner of row j (= column j) forms
+// v_j from its entries right of the diagonal and publishes it; each wave adds
+// its rows' share of p = tau A v (by symmetry a column sum over its rows);
+// after the second barrier every wave has p, K = tau/2 p^T v, w = p - K v and
+// applies A <- A - v w^T - w v^T to its rows.  Two barriers per step.
+// On return d (n), e (n - 1) and tau (n) are in LDS and v_j is row j of V
+// (row-major, ld RL_LD, zero at columns <= j).  Pp: 8 x 64 doubles of LDS.
+// r is destroyed.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void rl_tridiag(double (&r)[8], int n, double *d, double *e, double *tau, double *V, double *Pp)
+{
+    const int w = rl_wave(), l = rl_lane();
+#pragma unroll
+    for (int J = 0; J < 8; ++J) {
+        for (int w0 = 0; w0 < 8; ++w0) {
+            const int j = 8 * J + w0;
+            if (j >= n) break;
+            if (j + 2 >= n) {
+                // the trailing 2 x 2 block is already tridiagonal
+                if (w == w0) {
+                    const double dj = readlane_f64(r[J], j);
+                    const double ej = readlane_f64(r[J], (j + 1 < n) ? j + 1 : j);
+                    if (l == 0) {
+                        d[j] = dj;
+                        if (j + 1 < n) e[j] = ej;
+                        tau[j] = 0.0;
+                    }
+                }
+                continue;
+            }
+            if (w == w0) {
+                const double xr = r[J];
+                const double dj = readlane_f64(xr, j);
+                const double x0 = readlane_f64(xr, j + 1);
+                const double xv = (l > j && l < n) ? xr : 0.0;
+                const double ss = wave_sum(xv * xv);
+                double alpha, tj;
+                if (ss > 0.0 && (ss - x0 * x0) > 0.0) {
+                    alpha = (x0 >= 0.0) ? -sqrt(ss) : sqrt(ss);
+                    tj = 1.0 / (alpha * alpha - alpha * x0);
+                } else {
+                    alpha = x0;   // column already reduced
+                    tj = 0.0;
+                }
+                V[j * RL_LD + l] = (l == j + 1) ? x0 - alpha : xv;
+                if (l == 0) {
+                    tau[j] = tj;
+                    d[j] = dj;
+                    e[j] = alpha;
+                }
+            }
+            __syncthreads();
+            const double tj = tau[j];
+            if (tj != 0.0) {
+                const double vl = V[j * RL_LD + l];
+                double va[8];
+                double part = 0.0;
+#pragma unroll
+                for (int k = J; k < 8; ++k) {
+                    const int a = w + 8 * k;
+                    const double v = V[j * RL_LD + a];
+                    va[k] = (a > j && a < n) ? v : 0.0;
+                    part += r[k] * va[k];
+                }
+                Pp[w * 64 + l] = part;
+                __syncthreads();
+                double pl = 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) pl += Pp[q * 64 + l];
+                pl = (l > j && l < n) ? tj * pl : 0.0;
+                const double K = 0.5 * tj * wave_sum(pl * vl);
+                const double wl = pl - K * vl;
+#pragma unroll
+                for (int k = J; k < 8; ++k) {
+                    const int a = w + 8 * k;
+                    if (a > j && a < n) {
+                        const double wa = readlane_f64(wl, a);
+                        r[k] -= va[k] * wl + wa * vl;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Y (n x nv, LDS column-major, ld n) <- Q Y with the reflectors of
+// rl_tridiag.  A group of 8 lanes owns one column (rows g + 8t in registers)
+// and applies all reflectors to it: no barrier between reflectors.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void rl_backtransform(const double *V, const double *tau, int n, double *Y, int nv)
+{
+    const int g = threadIdx.x & 7;
+    const int c = threadIdx.x >> 3;   // whole groups share c
+    if (c < nv) {
+        double y[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) y[t] = (g + 8 * t < n) ? Y[g + 8 * t + c * n] : 0.0;
+        for (int j = n - 3; j >= 0; --j) {
+            const double tj = tau[j];
+            if (tj == 0.0) continue;   // uniform
+            double vv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) vv[t] = V[j * RL_LD + g + 8 * t];
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) s += vv[t] * y[t];
+            s = tj * group_sum<8>(s);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) y[t] -= s * vv[t];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (g + 8 * t < n) Y[g + 8 * t + c * n] = y[t];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// The tridiagonal (d, e) of rl_tridiag in registers (n <= 64): lane i holds
+// d_i and e_i (e_i couples rows i and i + 1; zero from n - 1 on), every wave
+// its own copy.  lo / hi: Gershgorin bounds widened by 2 n u |T| + 2 pivmin;
+// pivmin: the pivot floor of the Sturm counts; tn: max_i |d_i| + |e_i|.
+// ---------------------------------------------------------------------------
+struct TriRegs {
+    double d, e, lo, hi, pivmin, tn;
+};
+__device__ __forceinline__ TriRegs tri_regs(const double *d, const double *e, int n)
+{
+    const int l = rl_lane();
+    const double u = 1.1102230246251565e-16;
+    const double inf = __builtin_huge_val();
+    TriRegs t;
+    t.d = (l < n) ? d[l] : 0.0;
+    t.e = (l + 1 < n) ? e[l] : 0.0;
+    const double em = (l >= 1 && l < n) ? e[l - 1] : 0.0;
+    const double rad = fabs(em) + fabs(t.e);
+    const double lo = wave_min((l < n) ? t.d - rad : inf);
+    const double hi = wave_max((l < n) ? t.d + rad : -inf);
+    const double emax = wave_max(t.e * t.e);
+    t.pivmin = 2.2250738585072014e-308 * fmax(1.0, emax) * 4.0;
+    const double wid = fmax(fabs(lo), fabs(hi));
+    t.lo = lo - 2.0 * u * wid * n - 2.0 * t.pivmin;
+    t.hi = hi + 2.0 * u * wid * n + 2.0 * t.pivmin;
+    t.tn = wave_max((l < n) ? fabs(t.d) + fabs(t.e) : 0.0);
+    return t;
+}
+
+// Number of eigenvalues below x: negative pivots of T - x I = L D L^T
+// (q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 / q_{i-1}, |q| floored at pivmin),
+// the diagonal and couplings read from the registers by readlane.
+__device__ __forceinline__ int sturm_rl(const TriRegs &t, int n, double x)
+{
+    n = opaque_uniform(n);   // keep the bound tests inside the caller's loops
+    int cnt = 0;
+    double q = 1.0;
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        if (i >= n) break;
+        double v = readlane_f64(t.d, i) - x;
+        if (i > 0) {
+            const double ei = readlane_f64(t.e, i - 1);
+            v = v - (ei * ei) * rcp_nr1(q);
+        }
+        q = (fabs(v) < t.pivmin) ? -t.pivmin : v;
+        cnt += (q < 0.0) ? 1 : 0;
+    }
+    return cnt;
+}
+
+// The nv largest eigenvalues (descending) into ev (LDS) by multisection, as
+// bisect_top (groups of G lanes, G Sturm counts per round) with the
+// tridiagonal in registers.
+__device__ __forceinline__ void bisect_top_rl(const TriRegs &t, int n, int nv, double *ev)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const double u = 1.1102230246251565e-16;
+    int G = 64;
+    while (G > 1 && nv * G > EIG_NT) G >>= 1;
+    const int grp = tid / G, gl = tid % G;
+    const bool active = grp < nv;
+    const int idx = n - 1 - grp;   // ascending index of the target eigenvalue
+    const int gbase = lane - gl;
+    const double atol = 4.0 * u * fmax(fabs(t.lo), fabs(t.hi));
+    double a = t.lo, b = t.hi;
+    for (int round = 0; round < 80; ++round) {
+        const bool done = !active || (b - a) <= fmax(2.0 * u * fmax(fabs(a), fabs(b)), atol) + 4.0 * t.pivmin;
+        if (__all(done)) break;
+        const double x = a + (b - a) * (double)(gl + 1) / (double)(G + 1);
+        const int cnt = done ? 0 : sturm_rl(t, n, x);
+        const unsigned long long m = __ballot(!done && cnt > idx);
+        const unsigned long long gm = (G == 64) ? m : ((m >> gbase) & ((1ULL << G) - 1));
+        if (!done) {
+            if (gm == 0) {
+                a = a + (b - a) * (double)G / (double)(G + 1);
+            } else {
+                const int g0 = __ffsll((long long)gm) - 1;   // first point with count > idx
+                const double nb = a + (b - a) * (double)(g0 + 1) / (double)(G + 1);
+                const double na = (g0 == 0) ? a : a + (b - a) * (double)g0 / (double)(G + 1);
+                a = na;
+                b = nb;
+            }
+        }
+    }
+    if (active && gl == 0) ev[grp] = 0.5 * (a + b);
+    __syncthreads();
+}
+
+// Number of eigenvalues above thr (every thread computes it).
+__device__ __forceinline__ int count_above_rl(const TriRegs &t, int n, double thr)
+{
+    return n - sturm_rl(t, n, thr);
+}
+
+// ---------------------------------------------------------------------------
+// Eigenvectors for ev[0..nv) (descending) by inverse iteration, as tri_invit
+// (P L U of T - lambda I with partial pivoting, two solves from a fixed start
+// vector, re-orthogonalisation inside clusters of eigenvalues closer than 1e-3
+// of their magnitude, normalisation), for n <= 64 on wave 0: one lane per
+// cluster, the iterate in registers, the factor in LDS (`lu`, INVIT_LDS
+// doubles: per lane the reciprocal pivots, the first super-diagonal of U and
+// the multipliers; the second super-diagonal and the interchanges are
+// recomputed from e and a bit mask).  Y (n x nv, ld n, LDS) receives unit
+// vectors; `scl` holds the cluster starts.
+// ---------------------------------------------------------------------------
+constexpr int INVIT_LANES = 32;
+constexpr int INVIT_STRIDE = 3 * 64 + 1;
+constexpr int INVIT_LDS = INVIT_LANES * INVIT_STRIDE;
+
+__device__ __forceinline__ void tri_invit_rl(const TriRegs &t, int n_in, const double *ev, int nv, double *Y, double *lu,
+                                             int *scl)
+{
+    const double u = 1.1102230246251565e-16;
+    const int l = rl_lane();
+    if (threadIdx.x < 64 && nv > 0) {
+        const double evl = (l < nv) ? ev[l] : 0.0;
+        const double tn = fmax(t.tn, wave_max(fabs(evl)));
+        const double evp = (l >= 1 && l < nv) ? ev[l - 1] : 0.0;
+        const bool start =
+            (l < nv) && (l == 0 || fabs(evp - evl) > 1e-3 * fmax(fabs(evp), fabs(evl)) + 8.0 * u * tn);
+        const unsigned long long bal = __ballot(start);
+        const int nc = __popcll(bal);
+        if (start) scl[__popcll(bal & ((1ULL << l) - 1))] = l;
+        if (l == 0) scl[nc] = nv;
+        for (int cb = 0; cb < nc; cb += INVIT_LANES) {
+            const int c = cb + l;
+            if (l < INVIT_LANES && c < nc) {
+                double *u1 = lu + l * INVIT_STRIDE, *u2 = u1 + 64, *ml = u2 + 64;
+                const int i0 = scl[c], i1 = scl[c + 1];
+                for (int mi = i0; mi < i1; ++mi) {
+                    // perturb equal eigenvalues inside a cluster so the solves differ
+                    const double lam = ev[mi] + (double)(mi - i0) * 4.0 * u * tn;
+                    // (t was formed with every lane active: the lane reads below see all rows)
+                    const double td = t.d, te = t.e;
+                    int n = opaque_uniform(n_in);   // keeps the bound tests of the unrolled loops in place
+                    unsigned long long swb = 0;
+                    double r0 = readlane_f64(td, 0) - lam, r1 = readlane_f64(te, 0);
+#pragma unroll
+                    for (int i = 0; i < 63; ++i) {
+                        if (i + 1 >= n) break;
+                        if ((i & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+                        const double s0 = readlane_f64(te, i), s1 = readlane_f64(td, i + 1) - lam;
+                        const double s2 = readlane_f64(te, i + 1);
+                        const bool sw = !(fabs(r0) >= fabs(s0));
+                        double p0 = sw ? s0 : r0;
+                        const double p1 = sw ? s1 : r1, p2 = sw ? s2 : 0.0;
+                        const double o1 = sw ? r1 : s1, o2 = sw ? 0.0 : s2;
+                        if (p0 == 0.0) p0 = u * tn + 1e-300;
+                        const double ip = rcp_nr(p0);
+                        const double mult = (sw ? r0 : s0) * ip;
+                        u1[i] = ip;
+                        u2[i] = p1;
+                        ml[i] = mult;
+                        if (sw) swb |= 1ULL << i;
+                        r0 = o1 - mult * p1;
+                        r1 = o2 - mult * p2;
+                    }
+                    if (r0 == 0.0) r0 = u * tn + 1e-300;
+                    u1[n - 1] = rcp_nr(r0);
+                    u2[n - 1] = 0.0;
+                    // the iterate lives in its own column of Y; the sweeps go through it in
+                    // chunks of 8 (indices clamped to the matrix, loads issued per chunk)
+                    double *yc = Y + mi * n;
+                    const int nl = n - 1;
+#pragma unroll
+                    for (int i = 0; i < 64; ++i)
+                        if (i < n) yc[i] = 1.0 + 0.5 * (double)(((unsigned)(i + 3 * mi) * 2654435761u) % 1009u) / 1009.0;
+#pragma unroll 1
+                    for (int itn = 0; itn < 2; ++itn) {
+                        n = opaque_uniform(n);
+                        // forward: the row interchanges and multipliers
+                        double cur = yc[0];
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            if (8 * c >= nl) break;
+                            double nx[8], mv[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                const int i = 8 * c + q;
+                                nx[q] = yc[(i + 1 < n) ? i + 1 : nl];
+                                mv[q] = ml[i];
+                            }
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                const int i = 8 * c + q;
+                                if (i < nl) {
+                                    const bool sw = (swb >> i) & 1ULL;
+                                    const double top = sw ? nx[q] : cur, bot = sw ? cur : nx[q];
+                                    yc[i] = top;
+                                    cur = bot - mv[q] * top;
+                                }
+                            }
+                        }
+                        yc[nl] = cur;
+                        // back substitution with U (second super-diagonal e_{i+1} where rows were
+                        // swapped); the sum of squares and the largest magnitude come along
+                        double x1 = 0.0, x2 = 0.0, ss = 0.0, mx = 0.0;
+#pragma unroll
+                        for (int c = 7; c >= 0; --c) {
+                            if (8 * c > nl) continue;
+                            double yv[8], a1[8], a2[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                const int i = 8 * c + q;
+                                const int ic = (i < n) ? i : nl;
+                                yv[q] = yc[ic];
+                                a1[q] = u1[ic];
+                                a2[q] = u2[ic];
+                            }
+#pragma unroll
+                            for (int q = 7; q >= 0; --q) {
+                                const int i = 8 * c + q;
+                                if (i < n) {
+                                    const double u3 =
+                                        (i < 62 && i + 2 < n && ((swb >> i) & 1ULL)) ? readlane_f64(te, i + 1) : 0.0;
+                                    const double sv = (yv[q] - a2[q] * x1 - u3 * x2) * a1[q];
+                                    yc[i] = sv;
+                                    ss += sv * sv;
+                                    mx = fmax(mx, fabs(sv));
+                                    x2 = x1;
+                                    x1 = sv;
+                                }
+                            }
+                        }
+                        // re-orthogonalise inside the cluster
+                        for (int pj = i0; pj < mi; ++pj) {
+                            const double *z = Y + pj * n;
+                            double dt = 0.0;
+                            for (int i = 0; i < n; ++i) dt += z[i] * yc[i];
+                            ss = 0.0;
+                            mx = 0.0;
+                            for (int i = 0; i < n; ++i) {
+                                const double v = yc[i] - dt * z[i];
+                                yc[i] = v;
+                                ss += v * v;
+                                mx = fmax(mx, fabs(v));
+                            }
+                        }
+                        // normalise (through the largest magnitude when the plain sum of
+                        // squares left the normal range)
+                        double f;
+                        if (ss > 1e-290 && ss < 1e290) {
+                            f = 1.0 / sqrt(ss);
+                        } else {
+                            const double sm = (mx > 0.0) ? 1.0 / mx : 1.0;
+                            double q2 = 0.0;
+                            for (int i = 0; i < n; ++i) {
+                                const double v = yc[i] * sm;
+                                q2 += v * v;
+                            }
+                            f = sm / sqrt(q2);
+                        }
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            if (8 * c >= n) break;
+                            double yv[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) yv[q] = yc[(8 * c + q < n) ? 8 * c + q : nl];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q)
+                                if (8 * c + q < n) yc[8 * c + q] = yv[q] * f;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// C = A B for 64 x 64 operands on the FP64 MFMA: the 16 output tiles of
+// 16 x 16 go two to each wave.  fa(i, k) and fb(k, j) return the operands
+// (zero outside the matrices); fc(i, j, v) stores one result.  All loads of
+// a tile are issued before its 16 MFMAs.
+// ---------------------------------------------------------------------------
+template <typename FA, typename FB, typename FC>
+__device__ __forceinline__ void rl_mm64(FA fa, FB fb, FC fc)
+{
+    const int w = rl_wave(), l = rl_lane();
+    const int li = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        const int tile = 2 * w + tt, ti = tile >> 2, tj = tile & 3;
+        double av[16], bv[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            av[s] = fa(ti * 16 + li, 4 * s + lk);
+            bv[s] = fb(4 * s + lk, tj * 16 + li);
+        }
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 16; ++s) acc = mfma16x16x4(av[s], bv[s], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) fc(ti * 16 + lk + 4 * v, tj * 16 + li, acc[v]);
+    }
+}
+
+}  // namespace pod

@@ -8,6 +8,7 @@
 // projection.  These kernels are latency bound; everything stays in LDS.
 #include "pod_internal.h"
 #include "pod_symeig.h"
+#include "pod_rl.h"
 
 namespace pod {
 
@@ -16,11 +17,15 @@ constexpr int NT = EIG_NT;
 // workspace `ws` (device memory, L2 resident), with only the inverse-iteration
 // scratch in LDS.
 constexpr int SMALL_LDS_P = 64;
+// Dynamic LDS of the register-resident kernels (p <= 64, pmax = pm)
+constexpr size_t chol_first_lds_rl(int pm) { return (size_t)(2 * 64 * RL_LD + 2 * pm * pm) * sizeof(double); }
+constexpr size_t svd_merge_lds_rl(int) { return (size_t)(3 * 64 * RL_LD + 512 + INVIT_LDS) * sizeof(double); }
 constexpr size_t lds_limit(bool big)
 {
     return big ? (size_t)eig_lu_doubles(EIG_NMAX) * sizeof(double)
                : (size_t)(3 * SMALL_LDS_P * SMALL_LDS_P + eig_lu_doubles(SMALL_LDS_P)) * sizeof(double);
 }
+static_assert(chol_first_lds_rl(SMALL_LDS_P) <= lds_limit(false), "LDS budget");
 
 // ---------------------------------------------------------------------------
 // In-place Cholesky S = R^T R of the symmetric p x p matrix S (column-major,
@@ -32,23 +37,6 @@ constexpr size_t lds_limit(bool big)
 // of it are solved one column per thread, and the trailing matrix takes one
 // rank-16 update -- three barriers per panel.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double readlane_f64(double v, int lane)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
-}
-
-// 1/sqrt(x) from the hardware estimate and two Newton steps (x > 0 normal).
-__device__ __forceinline__ double rsqrt_nr(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
-    return y;
-}
-
 __device__ int chol_upper(double *S, int p, double thr)
 {
     __shared__ int sfail;
@@ -237,9 +225,130 @@ __device__ __forceinline__ void store_c(void *base, int prec, int64_t idx, doubl
 // R1 = chol(G1) (shifted by s = p u tr(G1) if a pivot breaks down),
 // T1 = P R1^-1 written in the compute type for the tall GEMM Y = X0 T1.
 // ---------------------------------------------------------------------------
+// Register-resident form for p <= 64 (pod_rl.h): the factor and its inverse
+// come out of one elimination pass.
+__device__ __forceinline__ void chol_first_rl(const SmallArgs &a)
+{
+    extern __shared__ double lds[];
+    __shared__ double sP[SMALL_LDS_P], sred[8];
+    __shared__ int sfl[8], sbadw[8];
+    DevState *ds = a.ds;
+    if (ds->exhausted) return;
+    const int p = ds->p, rs = ds->rs, p0 = ds->p0;
+    const int pm = a.pmax;
+    const int w = rl_wave(), l = rl_lane();
+    double *Rs = lds;                   // R1 (row-major)
+    double *Xs = Rs + 64 * RL_LD;       // R1^-T (row-major)
+    double *S = Xs + 64 * RL_LD;        // G1 (p x p, ld p) with a dense right factor
+    double *GP = S + pm * pm;           // G0 P (p0 x p)
+    const double *sigma = (ds->it & 1) ? a.sig1 : a.sig0;
+    for (int i = threadIdx.x; i < p; i += NT) sP[i] = (i < rs) ? sigma[i] : (a.sigma2 ? a.sigma2[i - rs] : 1.0);
+    __syncthreads();
+    double g[8];
+    if (a.use_vt) {
+        for (int idx = threadIdx.x; idx < p0 * p; idx += NT) {
+            const int i = idx % p0, b = idx / p0;
+            double v;
+            if (b < rs) {
+                v = a.G[i + b * pm] * sP[b];
+            } else {
+                v = 0.0;
+                for (int q = 0; q < p0 - rs; ++q) v += a.G[i + (rs + q) * pm] * a.Vt[q + (b - rs) * pm];
+            }
+            GP[i + b * p0] = v;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < p * p; idx += NT) {
+            const int i = idx % p, j = idx / p;
+            double v;
+            if (i < rs) {
+                v = sP[i] * GP[i + j * p0];
+            } else {
+                v = 0.0;
+                for (int q = 0; q < p0 - rs; ++q) v += a.Vt[q + (i - rs) * pm] * GP[(rs + q) + j * p0];
+            }
+            S[idx] = v;
+        }
+        __syncthreads();
+        // row a, columns >= a: the upper triangle S(a, l), as the factorisation reads it
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int ar = w + 8 * k;
+            g[k] = (ar < p && l < p) ? S[ar + l * p] : 0.0;
+        }
+    } else {
+        // G0 is stored exactly symmetric: row a of G1 is read along column a
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int ar = w + 8 * k;
+            g[k] = (ar < p && l < p) ? a.G[l + ar * pm] * sP[ar] * sP[l] : 0.0;
+        }
+    }
+    int bad = 0;
+    double td = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (!isfinite(g[k])) bad = 1;
+        if (l == w + 8 * k) td += g[k];
+    }
+    td = wave_sum(td);
+    bad = __any(bad);
+    if (l == 0) {
+        sred[w] = td;
+        sbadw[w] = bad;
+    }
+    __syncthreads();
+    double trace = 0.0;
+    bad = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        trace += sred[q];
+        bad |= sbadw[q];
+    }
+    double r[8];
+    if (bad) {
+        if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
+        rl_identity(p, Rs, Xs);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) r[k] = g[k];
+        int fail = rl_cholinv(r, p, a.urnd * trace * 1e-3, Rs, Xs, sfl);
+        if (fail) {
+            const double shift = (double)p * a.urnd * trace;
+            if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) r[k] = g[k] + ((l == w + 8 * k && l < p) ? shift : 0.0);
+            fail = rl_cholinv(r, p, 0.0, Rs, Xs, sfl);
+            if (fail) {
+                if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
+                rl_identity(p, Rs, Xs);
+            }
+        }
+    }
+    // R1 (column-major, ld pm, zero-padded) and T1 = P R1^-1 in the compute type
+    for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
+        const int i = idx % pm, j = idx / pm;
+        a.R1[idx] = (i < p && j < p) ? Rs[i * RL_LD + j] : 0.0;
+        double v = 0.0;
+        if (!a.use_vt) {
+            if (i < p && j < p) v = sP[i] * Xs[j * RL_LD + i];
+        } else if (i < p0 && j < p) {
+            if (i < rs) {
+                v = sP[i] * Xs[j * RL_LD + i];
+            } else {
+                for (int q = rs; q <= j; ++q) v += a.Vt[(i - rs) + (q - rs) * pm] * Xs[j * RL_LD + q];
+            }
+        }
+        store_c(a.Tc, a.prec, idx, v);
+    }
+}
+
 template <bool BIG>
 __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
 {
+    if constexpr (!BIG) {
+        chol_first_rl(a);
+    } else {
     extern __shared__ double lds[];
     __shared__ double sP[EIG_NMAX];
     __shared__ double sred[16];
@@ -339,6 +448,7 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
         }
         store_c(a.Tc, a.prec, idx, v);
     }
+    }
 }
 
 template <bool BIG>
@@ -358,7 +468,7 @@ __global__ __launch_bounds__(512) void k_chol_first_b(const SmallArgs *__restric
 hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 {
     const bool big = a.pmax > SMALL_LDS_P;
-    const size_t lds = big ? (0) : ((size_t)(2 * a.pmax * a.pmax + a.pmax) * sizeof(double));
+    const size_t lds = big ? (0) : chol_first_lds_rl(a.pmax);
     static bool attr[2] = {false, false};
     const void *fn = big ? (const void *)k_chol_first<true> : (const void *)k_chol_first<false>;
     if (!attr[big]) {
@@ -390,9 +500,155 @@ hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 // largest is the square root of the largest eigenvalue of B^T B.  The mode
 // criterion compares R(:, i)/|R(:, i)| with U_R(:, i) one by one.
 // ---------------------------------------------------------------------------
+// Register-resident form for p <= 64 (pod_rl.h).  LDS: bufA holds R2, then
+// H = R R^T, then the eigenvectors Y; bufB holds R, then the reflectors of the
+// tridiagonalisation, then B^T B and its reflectors; Xs holds R2^-T.
+__device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
+{
+    extern __shared__ double lds[];
+    __shared__ double sd[SMALL_LDS_P], se[SMALL_LDS_P], stau[SMALL_LDS_P], sev[SMALL_LDS_P], ssin[2], sred[8];
+    __shared__ __align__(8) int scl[EIG_NMAX + 8];
+    __shared__ int sfl[8];
+    DevState *ds = a.ds;
+    if (ds->exhausted) return;
+    const int p = ds->p, rs = ds->rs;
+    const int it0 = ds->it;   // read before thread 0 advances it at the end
+    const int pm = a.pmax;
+    const int w = rl_wave(), l = rl_lane();
+    double *bufA = lds;
+    double *bufB = bufA + 64 * RL_LD;
+    double *Xs = bufB + 64 * RL_LD;
+    double *Pp = Xs + 64 * RL_LD;    // 8 x 64
+    double *lu = Pp + 512;           // INVIT_LDS
+    // ---- pass-2 Cholesky R2 and R2^-T
+    double g[8], r[8];
+    rl_load_sym(g, a.G, pm, p);
+    const double trace = wave_sum((l < p) ? a.G[l + l * pm] : 0.0);
+    int fail = 1;
+    if (isfinite(trace)) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) r[k] = g[k];
+        fail = rl_cholinv(r, p, a.urnd * trace * 1e-3, bufA, Xs, sfl);
+    }
+    if (fail) {
+        const double shift = (double)p * a.urnd * (isfinite(trace) ? trace : 1.0);
+        if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
+        fail = 1;
+        if (isfinite(trace)) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) r[k] = g[k] + ((l == w + 8 * k && l < p) ? shift : 0.0);
+            fail = rl_cholinv(r, p, 0.0, bufA, Xs, sfl);
+        }
+        if (fail) {
+            if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
+            rl_identity(p, bufA, Xs);
+        }
+    }
+    // ---- R = R2 R1 (both upper triangular) into bufB
+    rl_mm64([&](int i, int k) { return bufA[i * RL_LD + k]; },
+            [&](int k, int j) { return (k < p && j < p) ? a.R1[k + j * pm] : 0.0; },
+            [&](int i, int j, double v) { bufB[i * RL_LD + j] = v; });
+    __syncthreads();
+    // the merge factor R, kept for the adjoint (ld pm, zero-padded)
+    for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
+        const int i = idx % pm, j = idx / pm;
+        a.R2[idx] = (i < p && j < p) ? bufB[i * RL_LD + j] : 0.0;
+    }
+    const int kk0 = (a.k < rs) ? a.k : rs;
+    if (a.criterion == POD_CRIT_MODE && kk0 > 0)
+        for (int idx = threadIdx.x; idx < p * kk0; idx += NT) a.work[idx] = bufB[(idx % p) * RL_LD + idx / p];
+    // ---- H = R R^T into bufA, then into registers
+    rl_mm64([&](int i, int q) { return bufB[i * RL_LD + q]; },
+            [&](int q, int j) { return bufB[j * RL_LD + q]; },
+            [&](int i, int j, double v) { bufA[i * RL_LD + j] = v; });
+    __syncthreads();
+    rl_load_rows(r, bufA);
+    __syncthreads();
+    // ---- eigen-decomposition of H
+    rl_tridiag(r, p, sd, se, stau, bufB, Pp);
+    const int nv = (a.r < p) ? a.r : p;
+    const TriRegs tt = tri_regs(sd, se, p);
+    bisect_top_rl(tt, p, nv, sev);
+    const double u64 = 1.1102230246251565e-16;
+    const double g1 = (double)p * a.urnd;
+    const double thr = fmax(g1 * g1, (double)p * u64) * fmax(sev[0], 0.0);
+    const int nz = count_above_rl(tt, p, thr);
+    const int rnew = (sev[0] > 0.0) ? ((nv < nz) ? nv : nz) : 0;
+    double *Y = bufA;
+    tri_invit_rl(tt, p, sev, rnew, Y, lu, scl);
+    rl_backtransform(bufB, stau, p, Y, rnew);
+    // Y now holds U_R(:, 0:rnew) (p x rnew, ld p)
+    // ---- convergence angle
+    const int kk = (kk0 < rnew) ? kk0 : rnew;
+    double sin_max = __builtin_nan("");
+    if (kk > 0) {
+        if (a.criterion == POD_CRIT_MODE) {
+            double mx = 0.0;
+            if (threadIdx.x < 64) {
+                for (int i = 0; i < kk; ++i) {
+                    double nr = 0.0, dt = 0.0;
+                    for (int q = threadIdx.x; q < p; q += 64) {
+                        const double x = a.work[q + i * p];
+                        nr += x * x;
+                        dt += x * Y[q + i * p];
+                    }
+                    nr = wave_sum(nr);
+                    dt = wave_sum(dt);
+                    const double inv = 1.0 / sqrt(nr);
+                    double res = 0.0;
+                    for (int q = threadIdx.x; q < p; q += 64) {
+                        const double dd = Y[q + i * p] - a.work[q + i * p] * inv * (dt * inv);
+                        res += dd * dd;
+                    }
+                    res = wave_sum(res);
+                    mx = fmax(mx, sqrt(res));
+                }
+            }
+            if (threadIdx.x == 0) sred[0] = mx;
+            __syncthreads();
+            sin_max = sred[0];
+            __syncthreads();
+        } else {
+            const int br = p - kk;
+            if (br <= 0) {
+                sin_max = 0.0;
+            } else {
+                // F = B^T B (kk x kk), B = U_R(kk:p, 0:kk)
+                rl_mm64([&](int i, int q) { return (i < kk && q < br) ? Y[kk + q + i * p] : 0.0; },
+                        [&](int q, int j) { return (q < br && j < kk) ? Y[kk + q + j * p] : 0.0; },
+                        [&](int i, int j, double v) { bufB[i * RL_LD + j] = v; });
+                __syncthreads();
+                rl_load_rows(r, bufB);
+                __syncthreads();
+                rl_tridiag(r, kk, sd, se, stau, bufB, Pp);
+                bisect_top_rl(tri_regs(sd, se, kk), kk, 1, ssin);
+                sin_max = sqrt(fmax(ssin[0], 0.0));
+            }
+        }
+    }
+    // ---- Z2 = R2^-1 U_R(:, 0:rnew) in the compute type: Z2^T(c, i) = sum_m Y(m, c) R2^-T(m, i)
+    rl_mm64([&](int c, int q) { return (c < rnew && q < p) ? Y[q + c * p] : 0.0; },
+            [&](int q, int i) { return Xs[q * RL_LD + i]; },
+            [&](int c, int i, double v) {
+                if (c < pm && i < pm) store_c(a.Tc, a.prec, i + c * pm, v);
+            });
+    double *sigma_new = (it0 & 1) ? a.sig0 : a.sig1;
+    for (int i = threadIdx.x; i < a.r; i += NT) sigma_new[i] = (i < rnew) ? sqrt(fmax(sev[i], 0.0)) : 0.0;
+    if (threadIdx.x == 0) {
+        ds->rnew = rnew;
+        ds->sin_theta = sin_max;
+        ds->rs = rnew;
+        ds->it = it0 + 1;
+        ds->g = 0;
+    }
+}
+
 template <bool BIG>
 __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
 {
+    if constexpr (!BIG) {
+        svd_merge_rl(a);
+    } else {
     extern __shared__ double lds[];
     __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
         sdots[EIG_NMAX], ssc[8], ssin[2];
@@ -538,6 +794,7 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
         ds->it = it0 + 1;
         ds->g = 0;
     }
+    }
 }
 
 template <bool BIG>
@@ -557,11 +814,12 @@ __global__ __launch_bounds__(512) void k_svd_merge_b(const SmallArgs *__restrict
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
 {
     const bool big = a.pmax > SMALL_LDS_P;
-    const size_t lds = big ? ((size_t)(eig_lu_doubles(a.pmax)) * sizeof(double)) : ((size_t)(3 * a.pmax * a.pmax + eig_lu_doubles(a.pmax)) * sizeof(double));
+    const size_t lds = big ? ((size_t)(eig_lu_doubles(a.pmax)) * sizeof(double)) : svd_merge_lds_rl(a.pmax);
     static bool attr[2] = {false, false};
     const void *fn = big ? (const void *)k_svd_merge<true> : (const void *)k_svd_merge<false>;
     if (!attr[big]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit(big));
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(big ? lds_limit(true) : svd_merge_lds_rl(SMALL_LDS_P)));
         if (e != hipSuccess) return e;
         attr[big] = true;
     }
@@ -860,7 +1118,7 @@ hipError_t launch_chol_first_b(const SmallArgs *arr, int32_t count, int32_t pmax
         attr = true;
     }
     hipLaunchKernelGGL(k_chol_first_b, dim3(1, (unsigned)count), dim3(NT),
-                       (size_t)(2 * pmax_max * pmax_max + pmax_max) * sizeof(double), st, arr);
+                       chol_first_lds_rl(pmax_max), st, arr);
     return hipGetLastError();
 }
 
@@ -870,13 +1128,12 @@ hipError_t launch_svd_merge_b(const SmallArgs *arr, int32_t count, int32_t pmax_
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)k_svd_merge_b, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_limit(false));
+                                           (int)svd_merge_lds_rl(SMALL_LDS_P));
         if (e != hipSuccess) return e;
         attr = true;
     }
     hipLaunchKernelGGL(k_svd_merge_b, dim3(1, (unsigned)count), dim3(NT),
-                       (size_t)(3 * pmax_max * pmax_max + eig_lu_doubles(pmax_max)) * sizeof(double),
-                       st, arr);
+                       svd_merge_lds_rl(pmax_max), st, arr);
     return hipGetLastError();
 }
 

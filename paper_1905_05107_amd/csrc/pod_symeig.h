@@ -44,26 +44,76 @@ __device__ __forceinline__ double rcp_nr1(double x)
     return fma(y, fma(-x, y, 1.0), y);
 }
 
-// Sums over aligned groups of G lanes by DPP moves inside a row of 16
-// (mirror, half-mirror, quad permutations: no LDS traffic), and over the 64
-// lanes of a wave (two cross-row shuffles on top).  Every lane gets the sum.
+// Reductions over aligned groups of G lanes by DPP moves inside a row of 16
+// (mirror, half-mirror, quad permutations) and, across rows, the gfx950 lane
+// swaps (v_permlane16_swap / v_permlane32_swap exchange the odd 16-lane rows
+// with the even ones, the upper 32 lanes with the lower ones): no LDS
+// traffic.  Every lane of a group gets the result.
 template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
 {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
-template <int G> __device__ __forceinline__ double group_sum(double v)
+// {a, b} = {v[l], v[l ^ W]} in every lane l (W = 16 or 32; order unspecified)
+template <int W> __device__ __forceinline__ void xor_pair(double v, double &a, double &b)
 {
-    if (G >= 16) v += dpp_f64<0x140>(v);   // row_mirror
-    if (G >= 8) v += dpp_f64<0x141>(v);    // row_half_mirror
-    if (G >= 4) v += dpp_f64<0x4E>(v);     // quad_perm [2,3,0,1]
-    if (G >= 2) v += dpp_f64<0xB1>(v);     // quad_perm [1,0,3,2]
-    if (G >= 32) v += __shfl_xor(v, 16, 64);
-    if (G >= 64) v += __shfl_xor(v, 32, 64);
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    if constexpr (W == 16) {
+        const auto x = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto y = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        a = __hiloint2double((int)y[0], (int)x[0]);
+        b = __hiloint2double((int)y[1], (int)x[1]);
+    } else {
+        const auto x = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto y = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        a = __hiloint2double((int)y[0], (int)x[0]);
+        b = __hiloint2double((int)y[1], (int)x[1]);
+    }
+}
+struct OpSum { __device__ static double f(double a, double b) { return a + b; } };
+struct OpMax { __device__ static double f(double a, double b) { return fmax(a, b); } };
+struct OpMin { __device__ static double f(double a, double b) { return fmin(a, b); } };
+template <int G, typename Op> __device__ __forceinline__ double group_reduce(double v)
+{
+    if (G >= 16) v = Op::f(v, dpp_f64<0x140>(v));   // row_mirror
+    if (G >= 8) v = Op::f(v, dpp_f64<0x141>(v));    // row_half_mirror
+    if (G >= 4) v = Op::f(v, dpp_f64<0x4E>(v));     // quad_perm [2,3,0,1]
+    if (G >= 2) v = Op::f(v, dpp_f64<0xB1>(v));     // quad_perm [1,0,3,2]
+    if (G >= 32) {
+        double a, b;
+        xor_pair<16>(v, a, b);
+        v = Op::f(a, b);
+    }
+    if (G >= 64) {
+        double a, b;
+        xor_pair<32>(v, a, b);
+        v = Op::f(a, b);
+    }
     return v;
 }
-__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
+template <int G> __device__ __forceinline__ double group_sum(double v) { return group_reduce<G, OpSum>(v); }
+__device__ __forceinline__ double wave_sum(double v) { return group_reduce<64, OpSum>(v); }
+__device__ __forceinline__ double wave_max(double v) { return group_reduce<64, OpMax>(v); }
+__device__ __forceinline__ double wave_min(double v) { return group_reduce<64, OpMin>(v); }
+
+// The value of lane `lane` (a wave-uniform index) in every lane.
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// 1/sqrt(x) from the hardware estimate and two Newton steps (x > 0 normal).
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
 
 // ---------------------------------------------------------------------------
 // Householder tridiagonalisation of the symmetric n x n matrix A (LDS,
