@@ -18,6 +18,8 @@ constexpr int RL_LD = 65;
 
 __device__ __forceinline__ int rl_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 __device__ __forceinline__ int rl_lane() { return threadIdx.x & 63; }
+// Binary exponent e with |v| in [2^(e-1), 2^e) (frexp; 0 for v = 0).
+__device__ __forceinline__ int frexp_e(double v) { return __builtin_amdgcn_frexp_exp(v); }
 // A wave-uniform int the optimiser cannot see through: tests against it stay
 // where they are written instead of being hoisted out of loops as one
 // predicate per unrolled step (which exhausts the scalar registers).
@@ -168,8 +170,9 @@ __device__ __forceinline__ void rl_tridiag(double (&r)[8], int n, double *d, dou
                 const double ss = wave_sum(xv * xv);
                 double alpha, tj;
                 if (ss > 0.0 && (ss - x0 * x0) > 0.0) {
-                    alpha = (x0 >= 0.0) ? -sqrt(ss) : sqrt(ss);
-                    tj = 1.0 / (alpha * alpha - alpha * x0);
+                    const double nrm = ss * rsqrt_nr(ss);
+                    alpha = (x0 >= 0.0) ? -nrm : nrm;
+                    tj = rcp_nr(alpha * alpha - alpha * x0);   // > 0: alpha^2 - alpha x0 = ss + |alpha x0|
                 } else {
                     alpha = x0;   // column already reduced
                     tj = 0.0;
@@ -186,19 +189,20 @@ __device__ __forceinline__ void rl_tridiag(double (&r)[8], int n, double *d, dou
             if (tj != 0.0) {
                 const double vl = V[j * RL_LD + l];
                 double va[8];
-                double part = 0.0;
+                double pa[4] = {0.0, 0.0, 0.0, 0.0};   // four partial sums: a shorter dependency chain
 #pragma unroll
                 for (int k = J; k < 8; ++k) {
                     const int a = w + 8 * k;
                     const double v = V[j * RL_LD + a];
                     va[k] = (a > j && a < n) ? v : 0.0;
-                    part += r[k] * va[k];
+                    pa[k & 3] += r[k] * va[k];
                 }
-                Pp[w * 64 + l] = part;
+                Pp[w * 64 + l] = (pa[0] + pa[1]) + (pa[2] + pa[3]);
                 __syncthreads();
-                double pl = 0.0;
+                double pq[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) pl += Pp[q * 64 + l];
+                for (int q = 0; q < 8; ++q) pq[q] = Pp[q * 64 + l];
+                double pl = ((pq[0] + pq[1]) + (pq[2] + pq[3])) + ((pq[4] + pq[5]) + (pq[6] + pq[7]));
                 pl = (l > j && l < n) ? tj * pl : 0.0;
                 const double K = 0.5 * tj * wave_sum(pl * vl);
                 const double wl = pl - K * vl;
@@ -257,8 +261,12 @@ __device__ __forceinline__ void rl_backtransform(const double *V, const double *
 // ---------------------------------------------------------------------------
 struct TriRegs {
     double d, e, lo, hi, pivmin, tn;
+    double sc;          // power of two with sc * max(|lo|, |hi|) in [0.5, 1)
+    const double *sde;  // LDS: sc d_i (72, padded with 4) then (sc e_i)^2 floored at 2^-200 (72, padded with 0)
 };
-__device__ __forceinline__ TriRegs tri_regs(const double *d, const double *e, int n)
+constexpr int TRI_SDE = 144;   // doubles of the `sde` scratch
+// Every thread calls this (it ends with a barrier); `sde`: TRI_SDE doubles of LDS.
+__device__ __forceinline__ TriRegs tri_regs(const double *d, const double *e, int n, double *sde)
 {
     const int l = rl_lane();
     const double u = 1.1102230246251565e-16;
@@ -276,29 +284,85 @@ __device__ __forceinline__ TriRegs tri_regs(const double *d, const double *e, in
     t.lo = lo - 2.0 * u * wid * n - 2.0 * t.pivmin;
     t.hi = hi + 2.0 * u * wid * n + 2.0 * t.pivmin;
     t.tn = wave_max((l < n) ? fabs(t.d) + fabs(t.e) : 0.0);
+    const double big = fmax(fabs(t.lo), fabs(t.hi));
+    t.sc = (big > 0.0 && big < inf) ? ldexp(1.0, -ilogb(big) - 1) : 1.0;
+    if (threadIdx.x < 64) {
+        // padded rows: d - x > 0 and no coupling (see sturm_rl)
+        const double es = t.e * t.sc;
+        sde[l] = (l < n) ? t.d * t.sc : 4.0;
+        sde[72 + l] = (l + 1 < n) ? fmax(es * es, 0x1p-200) : 0.0;
+        if (l < 8) {
+            sde[64 + l] = 4.0;
+            sde[136 + l] = 0.0;
+        }
+    }
+    t.sde = sde;
+    __syncthreads();
     return t;
 }
 
-// Number of eigenvalues below x: negative pivots of T - x I = L D L^T
-// (q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 / q_{i-1}, |q| floored at pivmin),
-// the diagonal and couplings read from the registers by readlane.
+// Number of eigenvalues below x: sign changes in the sequence of leading
+// principal minors of T - x I (Sturm), p_{-1} = 1, p_0 = d_0 - x,
+// p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2} (Wilkinson, The Algebraic
+// Eigenvalue Problem, ch. 5).  No division: one fused multiply-add per row on
+// the dependency chain, against the reciprocal of the equivalent pivot
+// recurrence q_i = p_i / p_{i-1}.  The recurrence runs on T scaled by a power
+// of two (|T| ~ 1, couplings floored at 2^-100, far below the rounding level
+// of the entries) and rescales its last two terms by a power of two every
+// fourth row (between rescalings a term changes by at most a factor 3^4 up,
+// and the floor bounds how far a pair can fall), which keeps them in range.  A zero minor takes the sign
+// opposite to its predecessor (the next one, -e^2 p_{i-1}, then has that sign
+// too, so exactly one change is counted, as for a pivot floored at -pivmin).
+// The diagonal and couplings are read from the registers by readlane.
 __device__ __forceinline__ int sturm_rl(const TriRegs &t, int n, double x)
 {
     n = opaque_uniform(n);   // keep the bound tests inside the caller's loops
-    int cnt = 0;
-    double q = 1.0;
+    const double xs = x * t.sc;
+    const double *ds = t.sde, *e2 = t.sde + 72;
+    // Step i has pm1 = p_{i-1} and mc = -e_{i-1}^2 p_{i-2}; it forms the next
+    // step's term from p_{i-1} before p_i, so that only one multiply-add per row
+    // waits on its predecessor.  A sign change between p_{i-1} and p_i is the
+    // sign bit of the exclusive or of their high words (a zero of either sign
+    // is fine: either sign gives one change across it and its successor).
+    double pm1 = 1.0, pm2 = 0.0, mc = 0.0;
+    unsigned cnt = 0;
+    // blocks of 8 rows (the next block's entries loaded ahead); the padded rows
+    // past n have d - x > 0 and no coupling, so their minors keep the sign of p_{n-1}
+    double dn[8], en[8];
 #pragma unroll
-    for (int i = 0; i < 64; ++i) {
-        if (i >= n) break;
-        double v = readlane_f64(t.d, i) - x;
-        if (i > 0) {
-            const double ei = readlane_f64(t.e, i - 1);
-            v = v - (ei * ei) * rcp_nr1(q);
-        }
-        q = (fabs(v) < t.pivmin) ? -t.pivmin : v;
-        cnt += (q < 0.0) ? 1 : 0;
+    for (int q = 0; q < 8; ++q) {
+        dn[q] = ds[q];
+        en[q] = e2[q];
     }
-    return cnt;
+    for (int b = 0; b < 64; b += 8) {
+        if (b >= n) break;
+        double dc[8], ec[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            dc[q] = dn[q];
+            ec[q] = en[q];
+            dn[q] = ds[b + 8 + q];
+            en[q] = e2[b + 8 + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double mn = -ec[q] * pm1;
+            double p = fma(dc[q] - xs, pm1, mc);
+            if ((q & 3) == 3) {
+                // power-of-two rescaling of the pair (p_i, p_{i-1}) and of the next
+                // term, by the exponent of the larger of p_{i-1}, p_{i-2}
+                const int ex = max(frexp_e(pm1), frexp_e(pm2));
+                p = ldexp(p, -ex);
+                mn = ldexp(mn, -ex);
+                pm1 = ldexp(pm1, -ex);
+            }
+            cnt += ((unsigned)(__double2hiint(p) ^ __double2hiint(pm1))) >> 31;
+            pm2 = pm1;
+            pm1 = p;
+            mc = mn;
+        }
+    }
+    return (int)cnt;
 }
 
 // The nv largest eigenvalues (descending) into ev (LDS) by multisection, as
@@ -417,7 +481,7 @@ __device__ __forceinline__ void tri_invit_rl(const TriRegs &t, int n_in, const d
                     const int nl = n - 1;
 #pragma unroll
                     for (int i = 0; i < 64; ++i)
-                        if (i < n) yc[i] = 1.0 + 0.5 * (double)(((unsigned)(i + 3 * mi) * 2654435761u) % 1009u) / 1009.0;
+                        if (i < n) yc[i] = 1.0 + (0.5 / 1009.0) * (double)(((unsigned)(i + 3 * mi) * 2654435761u) % 1009u);
 #pragma unroll 1
                     for (int itn = 0; itn < 2; ++itn) {
                         n = opaque_uniform(n);

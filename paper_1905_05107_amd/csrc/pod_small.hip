@@ -506,7 +506,8 @@ hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
 {
     extern __shared__ double lds[];
-    __shared__ double sd[SMALL_LDS_P], se[SMALL_LDS_P], stau[SMALL_LDS_P], sev[SMALL_LDS_P], ssin[2], sred[8];
+    __shared__ double sd[SMALL_LDS_P], se[SMALL_LDS_P], stau[SMALL_LDS_P], sev[SMALL_LDS_P], ssin[2], sred[8],
+        ssde[TRI_SDE];
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     __shared__ int sfl[8];
     DevState *ds = a.ds;
@@ -567,7 +568,7 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
     // ---- eigen-decomposition of H
     rl_tridiag(r, p, sd, se, stau, bufB, Pp);
     const int nv = (a.r < p) ? a.r : p;
-    const TriRegs tt = tri_regs(sd, se, p);
+    const TriRegs tt = tri_regs(sd, se, p, ssde);
     bisect_top_rl(tt, p, nv, sev);
     const double u64 = 1.1102230246251565e-16;
     const double g1 = (double)p * a.urnd;
@@ -621,7 +622,7 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
                 rl_load_rows(r, bufB);
                 __syncthreads();
                 rl_tridiag(r, kk, sd, se, stau, bufB, Pp);
-                bisect_top_rl(tri_regs(sd, se, kk), kk, 1, ssin);
+                bisect_top_rl(tri_regs(sd, se, kk, ssde), kk, 1, ssin);
                 sin_max = sqrt(fmax(ssin[0], 0.0));
             }
         }
