@@ -188,13 +188,13 @@ __device__ __forceinline__ void rl_tridiag(double (&r)[8], int n, double *d, dou
             const double tj = tau[j];
             if (tj != 0.0) {
                 const double vl = V[j * RL_LD + l];
+                // v_j is zero outside rows j+1..n-1, so rows a <= j and a >= n take
+                // no part and no update below without tests
                 double va[8];
                 double pa[4] = {0.0, 0.0, 0.0, 0.0};   // four partial sums: a shorter dependency chain
 #pragma unroll
                 for (int k = J; k < 8; ++k) {
-                    const int a = w + 8 * k;
-                    const double v = V[j * RL_LD + a];
-                    va[k] = (a > j && a < n) ? v : 0.0;
+                    va[k] = V[j * RL_LD + w + 8 * k];
                     pa[k & 3] += r[k] * va[k];
                 }
                 Pp[w * 64 + l] = (pa[0] + pa[1]) + (pa[2] + pa[3]);
@@ -208,11 +208,8 @@ __device__ __forceinline__ void rl_tridiag(double (&r)[8], int n, double *d, dou
                 const double wl = pl - K * vl;
 #pragma unroll
                 for (int k = J; k < 8; ++k) {
-                    const int a = w + 8 * k;
-                    if (a > j && a < n) {
-                        const double wa = readlane_f64(wl, a);
-                        r[k] -= va[k] * wl + wa * vl;
-                    }
+                    const double wa = readlane_f64(wl, w + 8 * k);   // zero for rows <= j and >= n
+                    r[k] -= va[k] * wl + wa * vl;
                 }
             }
         }
@@ -414,14 +411,15 @@ __device__ __forceinline__ int count_above_rl(const TriRegs &t, int n, double th
 // (P L U of T - lambda I with partial pivoting, two solves from a fixed start
 // vector, re-orthogonalisation inside clusters of eigenvalues closer than 1e-3
 // of their magnitude, normalisation), for n <= 64 on wave 0: one lane per
-// cluster, the iterate in registers, the factor in LDS (`lu`, INVIT_LDS
-// doubles: per lane the reciprocal pivots, the first super-diagonal of U and
-// the multipliers; the second super-diagonal and the interchanges are
-// recomputed from e and a bit mask).  Y (n x nv, ld n, LDS) receives unit
-// vectors; `scl` holds the cluster starts.
+// cluster, the iterate in its column of Y, the factor in LDS (`lu`, INVIT_LDS
+// doubles: per lane the reciprocal pivots, the first super-diagonal of U
+// divided by -pivot, and the multipliers; the second super-diagonal and the
+// interchanges come from e and a bit mask).  The sweeps are arranged so that
+// one multiply-add per row waits on the previous row.  Y (n x nv, ld n, LDS)
+// receives unit vectors; `scl` holds the cluster starts.
 // ---------------------------------------------------------------------------
-constexpr int INVIT_LANES = 32;
-constexpr int INVIT_STRIDE = 3 * 64 + 1;
+constexpr int INVIT_LANES = 24;
+constexpr int INVIT_STRIDE = 4 * 64 + 9;   // u1, b, ml (64 each), the iterate (72), odd
 constexpr int INVIT_LDS = INVIT_LANES * INVIT_STRIDE;
 
 __device__ __forceinline__ void tri_invit_rl(const TriRegs &t, int n_in, const double *ev, int nv, double *Y, double *lu,
@@ -442,7 +440,7 @@ __device__ __forceinline__ void tri_invit_rl(const TriRegs &t, int n_in, const d
         for (int cb = 0; cb < nc; cb += INVIT_LANES) {
             const int c = cb + l;
             if (l < INVIT_LANES && c < nc) {
-                double *u1 = lu + l * INVIT_STRIDE, *u2 = u1 + 64, *ml = u2 + 64;
+                double *u1 = lu + l * INVIT_STRIDE, *u2 = u1 + 64, *ml = u2 + 64, *yl = ml + 64;
                 const int i0 = scl[c], i1 = scl[c + 1];
                 for (int mi = i0; mi < i1; ++mi) {
                     // perturb equal eigenvalues inside a cluster so the solves differ
@@ -450,134 +448,134 @@ __device__ __forceinline__ void tri_invit_rl(const TriRegs &t, int n_in, const d
                     // (t was formed with every lane active: the lane reads below see all rows)
                     const double td = t.d, te = t.e;
                     int n = opaque_uniform(n_in);   // keeps the bound tests of the unrolled loops in place
+                    // factor P (T - lambda I) = L U: per row the reciprocal pivot u1, the
+                    // first super-diagonal divided by minus the pivot (b, in u2) and the
+                    // multiplier ml; the row interchanges go to a bit mask.  A zero
+                    // coupling is floored at u tn + 1e-300 as the pivot candidate, so that no
+                    // pivot is zero (a perturbation at the rounding level of T).
+                    const double tiny = u * tn + 1e-300;
                     unsigned long long swb = 0;
                     double r0 = readlane_f64(td, 0) - lam, r1 = readlane_f64(te, 0);
 #pragma unroll
                     for (int i = 0; i < 63; ++i) {
                         if (i + 1 >= n) break;
                         if ((i & 7) == 0) __builtin_amdgcn_sched_barrier(0);
-                        const double s0 = readlane_f64(te, i), s1 = readlane_f64(td, i + 1) - lam;
+                        const double ei = readlane_f64(te, i);
+                        const double s0 = (ei != 0.0) ? ei : tiny;
+                        const double s1 = readlane_f64(td, i + 1) - lam;
                         const double s2 = readlane_f64(te, i + 1);
                         const bool sw = !(fabs(r0) >= fabs(s0));
-                        double p0 = sw ? s0 : r0;
+                        const double p0 = sw ? s0 : r0;
                         const double p1 = sw ? s1 : r1, p2 = sw ? s2 : 0.0;
                         const double o1 = sw ? r1 : s1, o2 = sw ? 0.0 : s2;
-                        if (p0 == 0.0) p0 = u * tn + 1e-300;
-                        const double ip = rcp_nr(p0);
+                        const double ip = rcp_nr1(p0);
                         const double mult = (sw ? r0 : s0) * ip;
                         u1[i] = ip;
-                        u2[i] = p1;
+                        u2[i] = -p1 * ip;
                         ml[i] = mult;
                         if (sw) swb |= 1ULL << i;
                         r0 = o1 - mult * p1;
                         r1 = o2 - mult * p2;
                     }
-                    if (r0 == 0.0) r0 = u * tn + 1e-300;
-                    u1[n - 1] = rcp_nr(r0);
+                    if (r0 == 0.0) r0 = tiny;
+                    u1[n - 1] = rcp_nr1(r0);
                     u2[n - 1] = 0.0;
-                    // the iterate lives in its own column of Y; the sweeps go through it in
-                    // chunks of 8 (indices clamped to the matrix, loads issued per chunk)
-                    double *yc = Y + mi * n;
-                    const int nl = n - 1;
+                    ml[n - 1] = 0.0;
+                    // rows past the matrix: no multiplier (the forward sweep only carries
+                    // the value along) and a zero row of U^-1 (the back substitution
+                    // enters row n - 1 with x_n = x_{n+1} = 0)
+                    for (int i = n; i < 64; ++i) {
+                        u1[i] = 0.0;
+                        u2[i] = 0.0;
+                        ml[i] = 0.0;
+                    }
+                    // start vector: fixed, not orthogonal to any eigenvector in practice
 #pragma unroll
-                    for (int i = 0; i < 64; ++i)
-                        if (i < n) yc[i] = 1.0 + (0.5 / 1009.0) * (double)(((unsigned)(i + 3 * mi) * 2654435761u) % 1009u);
+                    for (int i = 0; i < 72; ++i)
+                        yl[i] = (i < n) ? 1.0 + 0.5 * __builtin_amdgcn_fract((double)(i + 3 * mi) * 0.6180339887498949) : 0.0;
+                    const int nb = (n + 7) >> 3;   // blocks of 8 rows
+                    double f = 1.0;                // scale of the iterate still to apply
 #pragma unroll 1
                     for (int itn = 0; itn < 2; ++itn) {
-                        n = opaque_uniform(n);
-                        // forward: the row interchanges and multipliers
-                        double cur = yc[0];
-#pragma unroll
-                        for (int c = 0; c < 8; ++c) {
-                            if (8 * c >= nl) break;
+                        // forward: row interchanges and multipliers, written so that only
+                        // cur' = A cur + C nx waits on the previous row (no swap: A = -ml,
+                        // C = 1; swap: A = 1, C = -ml); the scale f is applied on the way
+                        double cur = f * yl[0];
+                        for (int bb = 0; bb < nb; ++bb) {
+                            const double *yb = yl + 8 * bb;
+                            const double *mb = ml + 8 * bb;
+                            const unsigned sb = (unsigned)(swb >> (8 * bb));
                             double nx[8], mv[8];
 #pragma unroll
                             for (int q = 0; q < 8; ++q) {
-                                const int i = 8 * c + q;
-                                nx[q] = yc[(i + 1 < n) ? i + 1 : nl];
-                                mv[q] = ml[i];
+                                nx[q] = f * yb[q + 1];
+                                mv[q] = mb[q];
                             }
 #pragma unroll
                             for (int q = 0; q < 8; ++q) {
-                                const int i = 8 * c + q;
-                                if (i < nl) {
-                                    const bool sw = (swb >> i) & 1ULL;
-                                    const double top = sw ? nx[q] : cur, bot = sw ? cur : nx[q];
-                                    yc[i] = top;
-                                    cur = bot - mv[q] * top;
-                                }
+                                const bool sw = (sb >> q) & 1u;
+                                const double A = sw ? 1.0 : -mv[q], C = sw ? -mv[q] : 1.0;
+                                yl[8 * bb + q] = sw ? nx[q] : cur;
+                                cur = fma(A, cur, C * nx[q]);
                             }
                         }
-                        yc[nl] = cur;
-                        // back substitution with U (second super-diagonal e_{i+1} where rows were
-                        // swapped); the sum of squares and the largest magnitude come along
+                        // back substitution: x_i = u1_i y_i + b_i x_{i+1} + c_i x_{i+2}
+                        // (c_i = -U(i, i+2) / U(i, i), nonzero only after an interchange);
+                        // the sum of squares and the largest magnitude come along
                         double x1 = 0.0, x2 = 0.0, ss = 0.0, mx = 0.0;
-#pragma unroll
-                        for (int c = 7; c >= 0; --c) {
-                            if (8 * c > nl) continue;
+                        for (int bb = nb - 1; bb >= 0; --bb) {
+                            double *yb = yl + 8 * bb;
+                            const double *ab = u1 + 8 * bb, *bb2 = u2 + 8 * bb;
+                            const unsigned sb = (unsigned)(swb >> (8 * bb));
                             double yv[8], a1[8], a2[8];
 #pragma unroll
                             for (int q = 0; q < 8; ++q) {
-                                const int i = 8 * c + q;
-                                const int ic = (i < n) ? i : nl;
-                                yv[q] = yc[ic];
-                                a1[q] = u1[ic];
-                                a2[q] = u2[ic];
+                                yv[q] = yb[q];
+                                a1[q] = ab[q];
+                                a2[q] = bb2[q];
                             }
 #pragma unroll
                             for (int q = 7; q >= 0; --q) {
-                                const int i = 8 * c + q;
-                                if (i < n) {
-                                    const double u3 =
-                                        (i < 62 && i + 2 < n && ((swb >> i) & 1ULL)) ? readlane_f64(te, i + 1) : 0.0;
-                                    const double sv = (yv[q] - a2[q] * x1 - u3 * x2) * a1[q];
-                                    yc[i] = sv;
-                                    ss += sv * sv;
-                                    mx = fmax(mx, fabs(sv));
-                                    x2 = x1;
-                                    x1 = sv;
-                                }
+                                const int i2 = min(8 * bb + q + 1, 63);
+                                const double e3 = ((sb >> q) & 1u) ? readlane_f64(te, i2) : 0.0;
+                                const double sv = fma(a2[q], x1, fma(-e3 * a1[q], x2, yv[q] * a1[q]));
+                                yb[q] = sv;
+                                ss = fma(sv, sv, ss);
+                                mx = fmax(mx, fabs(sv));
+                                x2 = x1;
+                                x1 = sv;
                             }
                         }
                         // re-orthogonalise inside the cluster
                         for (int pj = i0; pj < mi; ++pj) {
                             const double *z = Y + pj * n;
                             double dt = 0.0;
-                            for (int i = 0; i < n; ++i) dt += z[i] * yc[i];
+                            for (int i = 0; i < n; ++i) dt += z[i] * yl[i];
                             ss = 0.0;
                             mx = 0.0;
                             for (int i = 0; i < n; ++i) {
-                                const double v = yc[i] - dt * z[i];
-                                yc[i] = v;
+                                const double v = yl[i] - dt * z[i];
+                                yl[i] = v;
                                 ss += v * v;
                                 mx = fmax(mx, fabs(v));
                             }
                         }
                         // normalise (through the largest magnitude when the plain sum of
-                        // squares left the normal range)
-                        double f;
+                        // squares left the normal range); the scale goes into the next
+                        // forward sweep, or into the column after the last solve
                         if (ss > 1e-290 && ss < 1e290) {
                             f = 1.0 / sqrt(ss);
                         } else {
                             const double sm = (mx > 0.0) ? 1.0 / mx : 1.0;
                             double q2 = 0.0;
                             for (int i = 0; i < n; ++i) {
-                                const double v = yc[i] * sm;
+                                const double v = yl[i] * sm;
                                 q2 += v * v;
                             }
                             f = sm / sqrt(q2);
                         }
-#pragma unroll
-                        for (int c = 0; c < 8; ++c) {
-                            if (8 * c >= n) break;
-                            double yv[8];
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) yv[q] = yc[(8 * c + q < n) ? 8 * c + q : nl];
-#pragma unroll
-                            for (int q = 0; q < 8; ++q)
-                                if (8 * c + q < n) yc[8 * c + q] = yv[q] * f;
-                        }
                     }
+                    for (int i = 0; i < n; ++i) Y[mi * n + i] = yl[i] * f;
                 }
             }
         }

@@ -1163,7 +1163,11 @@ __global__ __launch_bounds__(512) void k_adj_small(AdjArgs a)
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     const int rs = a.rs, p = a.rs + a.g, rz = a.rz, pm = a.pm, pb = a.pb;
     const int t = threadIdx.x;
-    double *H = lds, *Y = lds + p * p, *lu = lds + 2 * p * p;
+    double *H = lds;                 // R R^T (p x p, ld p), then the reflectors (64 x RL_LD)
+    double *Y = H + 64 * RL_LD;      // eigenvectors (p x p, ld p)
+    double *Pp = Y + 64 * 64;        // 8 x 64
+    double *lu = Pp + 512;           // INVIT_LDS
+    __shared__ double ssde[TRI_SDE];
     const int q2 = pm * pm;
     double *wR = a.ws, *wRi = wR + q2, *wUR = wRi + q2, *wV = wUR + q2, *wZ = wV + q2, *wJ = wZ + q2, *wK = wJ + q2,
            *wN = wK + q2, *wW = wN + q2, *wT = wW + q2;
@@ -1184,10 +1188,17 @@ __global__ __launch_bounds__(512) void k_adj_small(AdjArgs a)
     }
     __syncthreads();
     trinv_upper<false>(wR, p, wRi, spv);
-    tridiag(H, p, sd, se, stau, spv, ssc);
-    bisect_top(sd, se, p, p, sev, se2, ssc);
-    tri_invit(sd, se, p, sev, p, Y, lu, scl);
-    tridiag_backtransform(H, stau, p, Y, p, sdots);
+    // the eigensolver of the forward merge (same start vectors, so the same signs of U_R)
+    {
+        double r[8];
+        rl_load_sym(r, H, p, p);
+        __syncthreads();
+        rl_tridiag(r, p, sd, se, stau, H, Pp);
+    }
+    const TriRegs tt = tri_regs(sd, se, p, ssde);
+    bisect_top_rl(tt, p, p, sev);
+    tri_invit_rl(tt, p, sev, p, Y, lu, scl);
+    rl_backtransform(H, stau, p, Y, p);
     for (int i = t; i < p; i += NT) sS[i] = sqrt(fmax(sev[i], 0.0));
     for (int idx = t; idx < p * p; idx += NT) wUR[idx] = Y[idx];
     __syncthreads();
@@ -1285,7 +1296,7 @@ hipError_t launch_adj_small(const AdjArgs &a, hipStream_t st)
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const size_t lds = (size_t)(2 * p * p + eig_lu_doubles(p)) * sizeof(double);
+    const size_t lds = (size_t)(64 * RL_LD + 64 * 64 + 512 + INVIT_LDS) * sizeof(double);
     hipLaunchKernelGGL(k_adj_small, dim3(1), dim3(NT), lds, st, a);
     return hipGetLastError();
 }

@@ -51,8 +51,9 @@ __device__ __forceinline__ double rcp_nr1(double x)
 // traffic.  Every lane of a group gets the result.
 template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    // (the permutations used here read lanes of the same row only: no bound control needed)
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 // {a, b} = {v[l], v[l ^ W]} in every lane l (W = 16 or 32; order unspecified)
