@@ -124,6 +124,22 @@ pod_status pod_merge(pod_ctx *ctx);
  * gets the sine of that angle (NaN after the first merge). */
 pod_status pod_converged(pod_ctx *ctx, int32_t *done, double *sin_theta_max);
 
+/* The loop of Alg. 1 driven from the device: enqueue iterations (pod_sample
+ * + pod_merge + the stop test of pod_converged, evaluated by a kernel that
+ * sets a stop flag on which every later kernel of the loop returns at once)
+ * `chunk` at a time (<= 0: 8) and sync once per chunk, until the run stops
+ * or max_merges merges were done.  stop_on_converged = 0 ignores the angle
+ * test (a fixed number of merges; S exhaustion and max_iter still stop).
+ * Results are those of the host loop sample / merge / converged.
+ * sin_out (host, nullable, >= max_merges doubles) receives the convergence
+ * sine of each merge of this call (NaN for the first merge of the run);
+ * *merges_out (nullable) the number of merges done; *done_out (nullable) 1
+ * when the run stopped (converged, S exhausted, or max_iter reached).  No
+ * sample may be pending (POD_ESTATE); the context is left ready for
+ * pod_sample / pod_project.  Syncs. */
+pod_status pod_run(pod_ctx *ctx, int32_t max_merges, int32_t stop_on_converged, int32_t chunk, double *sin_out,
+                   int32_t *merges_out, int32_t *done_out);
+
 /* Final step of Alg. 1 (syncs): B = U_r^T A (one pass over A), SVD of B,
  * U <- U U_B, Sigma <- Sigma_B, V = B^T U_B Sigma_B^-1.  Writes the first
  * k modes: U_out (device, m x k column-major, FP64 for POD_F64 else FP32),

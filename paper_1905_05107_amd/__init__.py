@@ -28,7 +28,8 @@ EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project"
            "pod_status_str", "pod_profile_enable", "pod_profile_read", "pod_inc_init", "pod_inc_add_block",
            "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy", "pod_batch_init",
            "pod_batch_autotune", "pod_batch_run", "pod_batch_project", "pod_batch_get_info", "pod_batch_destroy",
-           "pod_enable_adjoint", "pod_backward", "pod_loss_grad", "pod_batch_enable_adjoint", "pod_batch_loss_grad"]
+           "pod_enable_adjoint", "pod_backward", "pod_loss_grad", "pod_batch_enable_adjoint", "pod_batch_loss_grad",
+           "pod_run"]
 
 
 class PodError(RuntimeError):
@@ -80,6 +81,7 @@ def lib():
             "pod_sample": (i32, [vp, P(i32), P(i32)]),
             "pod_merge": (i32, [vp]),
             "pod_converged": (i32, [vp, P(i32), P(d)]),
+            "pod_run": (i32, [vp, i32, i32, i32, P(d), P(i32), P(i32)]),
             "pod_project": (i32, [vp, vp, vp, vp]),
             "pod_get_basis": (i32, [vp, vp, vp, P(i32)]),
             "pod_get_info": (i32, [vp, P(pod_info)]),
@@ -325,10 +327,19 @@ class PodContext:
         _check(lib().pod_get_col_sqnorms(self.h, ctypes.c_void_p(nu.ctypes.data)), "pod_get_col_sqnorms")
         return nu
 
-    def run(self, n_iter: Optional[int] = None):
+    def run(self, n_iter: Optional[int] = None, chunk: int = 8, stepwise: bool = False):
         """Alg. 1: sample/merge until converged, S is exhausted, max_iter
         merges were done, or (when given) n_iter merges were done.  Returns
-        the convergence sines of the merges (NaN for the first)."""
+        the convergence sines of the merges (NaN for the first).  The loop runs
+        on the device (pod_run, one sync per `chunk` iterations) unless
+        stepwise, which drives pod_sample / pod_merge / pod_converged."""
+        if not stepwise:
+            cap = int(n_iter) if n_iter is not None else min(int(self.params.max_iter), self.n)
+            buf = (ctypes.c_double * max(cap, 1))()
+            merged, done = ctypes.c_int32(), ctypes.c_int32()
+            _check(lib().pod_run(self.h, cap, 1 if n_iter is None else 0, int(chunk), buf, ctypes.byref(merged),
+                                 ctypes.byref(done)), "pod_run")
+            return [buf[i] for i in range(merged.value)]
         sines = []
         while n_iter is None or len(sines) < n_iter:
             if not self.sample():

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_ckpt_pre(const DevState *ds, const TC *
                                                   const double *s1, int64_t m, int32_t r, TC *ckU, double *ckS,
                                                   int32_t *meta, int32_t cap)
 {
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int32_t t = ds->it;
     if (t >= cap) return;
     const int32_t rs = ds->rs;
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_ckpt_pre(const DevState *ds, const TC *
 __global__ __launch_bounds__(256) void k_ckpt_post(const DevState *ds, const double *R, int32_t pm2, double *ckR,
                                                    int32_t *meta, int32_t cap)
 {
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int32_t t = ds->it - 1;
     if (t < 0 || t >= cap) return;
     for (int i = threadIdx.x; i < pm2; i += 256) ckR[(int64_t)t * pm2 + i] = R[i];
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_ckpt_pre_b(const CkptArgs *__restrict__
     const CkptArgs &a = arr[blockIdx.y];
     if (a.ds->done) return;
     const DevState *ds = a.ds;
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int32_t t = ds->it;
     if (t >= a.cap) return;
     const int32_t rs = ds->rs;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_ckpt_post_b(const CkptArgs *__restrict_
     const CkptArgs &a = arr[blockIdx.y];
     if (a.ds->done) return;
     const DevState *ds = a.ds;
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int32_t t = ds->it - 1;
     if (t < 0 || t >= a.cap) return;
     for (int i = threadIdx.x; i < a.pm2; i += 256) a.ckR[(int64_t)t * a.pm2 + i] = a.R[i];

@@ -52,7 +52,8 @@ void free_all(pod_ctx *ctx)
                     ctx->B,    ctx->GB,   ctx->UB,    ctx->sigB, ctx->Zc, ctx->signv, ctx->signi,
                     ctx->rho,  ctx->Vt,   ctx->wr,    ctx->rows, ctx->rcnt, ctx->row_log, ctx->rcnt_log,
                     ctx->ws,   ctx->ckU,  ctx->ckS,   ctx->ckR,  ctx->ckMeta, ctx->dsb, ctx->partb, ctx->Gext,
-                    ctx->adj_ws, ctx->sbar[0], ctx->sbar[1], ctx->lossp, ctx->Wt, ctx->Ubar[0], ctx->Ubar[1]};
+                    ctx->adj_ws, ctx->sbar[0], ctx->sbar[1], ctx->lossp, ctx->Wt, ctx->Ubar[0], ctx->Ubar[1],
+                    ctx->sin_log};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -304,6 +305,8 @@ pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
     ALLOC(ctx->col_log, int32_t, n);
     ALLOC(ctx->ccnt_log, int32_t, n);
     ALLOC(ctx->col_log_off, int32_t, cap_iter + 1);
+    ALLOC(ctx->sin_log, double, cap_iter + 1);
+    ctx->log_cap = cap_iter;
     for (int b = 0; b < 2; ++b) {
         ALLOC(ctx->U[b], unsigned char, (size_t)m * r * ctx->esz);
         ALLOC(ctx->sig[b], double, r);
@@ -396,15 +399,10 @@ pod_status pod::ctx_bind(pod_ctx *ctx, void *A_dev, int64_t n, int64_t lda, uint
     return POD_OK;
 }
 
-extern "C" {
-
-pod_status pod_sample(pod_ctx *ctx, int32_t *g_out, int32_t *h_out)
+// The draw of one iteration of Alg. 1 (columns; rows and the right factor of
+// the new block when rows are sampled), enqueued without waiting.
+static pod_status enqueue_sample(pod_ctx *ctx)
 {
-    if (!ctx) return POD_EINVAL;
-    if (ctx->failed) return POD_EHIP;
-    if (ctx->pending) return POD_ESTATE;
-    if (ctx->exhausted) return POD_EXHAUSTED;
-    if (ctx->merges >= ctx->prm.max_iter) return POD_ESTATE;
     DrawArgs a = ctx_draw_args(ctx);
     POD_HIP(launch_draw_cols(a, ctx->st));
     ctx->forced_g = -1;
@@ -431,6 +429,21 @@ pod_status pod_sample(pod_ctx *ctx, int32_t *g_out, int32_t *h_out)
         BlockEigArgs ba = block_eig_args(ctx, 0);
         POD_HIP(launch_block_eig(ba, ctx->st));
     }
+    return POD_OK;
+}
+
+
+extern "C" {
+
+pod_status pod_sample(pod_ctx *ctx, int32_t *g_out, int32_t *h_out)
+{
+    if (!ctx) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (ctx->pending) return POD_ESTATE;
+    if (ctx->exhausted) return POD_EXHAUSTED;
+    if (ctx->merges >= ctx->prm.max_iter) return POD_ESTATE;
+    pod_status s0 = enqueue_sample(ctx);
+    if (s0 != POD_OK) return s0;
     ctx->pending = 1;
     if (g_out || h_out) {
         pod_status s = sync_state(ctx);
@@ -454,6 +467,53 @@ pod_status pod_merge(pod_ctx *ctx)
     pod_status s = merge_launch(ctx, gather_desc(ctx), nullptr, p.w > 0 || p.r_update > 0, p.w == 0 && p.r_update > 0);
     if (s != POD_OK) return s;
     ctx->pending = 0;
+    return POD_OK;
+}
+
+pod_status pod_run(pod_ctx *ctx, int32_t max_merges, int32_t stop_on_converged, int32_t chunk, double *sin_out,
+                   int32_t *merges_out, int32_t *done_out)
+{
+    if (!ctx || max_merges < 0) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (ctx->pending) return POD_ESTATE;
+    if (chunk < 1) chunk = 8;
+    pod_status s = sync_state(ctx);
+    if (s != POD_OK) return s;
+    const pod_params &p = ctx->prm;
+    const int32_t it0 = ctx->hs.it;
+    const int32_t limit = (int32_t)((int64_t)it0 + max_merges < (int64_t)p.max_iter ? it0 + max_merges : p.max_iter);
+    const double tol = p.theta_tol < 1.5707963267948966 ? sin(p.theta_tol) : 1.0;
+    const bool rows_eig = p.w > 0 || p.r_update > 0, block_mode1 = p.w == 0 && p.r_update > 0;
+    int32_t enqueued = 0;
+    while (!ctx->exhausted && ctx->hs.it < limit && !ctx->hs.done) {
+        // up to `chunk` iterations without waiting; the stop test on the device
+        // turns the rest of the chunk into no-ops
+        const int32_t todo = (limit - ctx->hs.it < chunk) ? limit - ctx->hs.it : chunk;
+        for (int32_t q = 0; q < todo; ++q) {
+            s = enqueue_sample(ctx);
+            if (s != POD_OK) return s;
+            s = merge_launch(ctx, gather_desc(ctx), nullptr, rows_eig, block_mode1);
+            if (s != POD_OK) return s;
+            POD_HIP(launch_run_done(ctx->ds, limit, tol, stop_on_converged ? 1 : 0, ctx->sin_log, ctx->log_cap,
+                                    ctx->st));
+            ++enqueued;
+        }
+        s = sync_state(ctx);
+        if (s != POD_OK) return s;
+    }
+    const int32_t merged = ctx->hs.it - it0;
+    if (done_out) *done_out = ctx->hs.done || ctx->exhausted || ctx->hs.it >= p.max_iter;
+    if (merges_out) *merges_out = merged;
+    if (sin_out && merged > 0)
+        POD_HIP(hipMemcpyAsync(sin_out, ctx->sin_log + it0, sizeof(double) * merged, hipMemcpyDeviceToHost, ctx->st));
+    // hand the context back to step-by-step use
+    ctx->merges = ctx->hs.it;
+    if (ctx->hs.done) {
+        ctx->hs.done = 0;
+        POD_HIP(hipMemcpyAsync(ctx->ds, &ctx->hs, sizeof(DevState), hipMemcpyHostToDevice, ctx->st));
+    }
+    POD_HIP(hipStreamSynchronize(ctx->st));
+    (void)enqueued;
     return POD_OK;
 }
 

@@ -39,6 +39,8 @@ struct pod_ctx {
     int exhausted = 0;       // known on the host
     int failed = 0;          // a HIP error happened: only destroy is allowed
     int32_t forced_g = -1;   // replay of the next draw
+    double *sin_log = nullptr;   // device-driven runs: convergence sine of each merge
+    int32_t log_cap = 0;
     // reverse pass (pod_enable_adjoint): per-merge checkpoints and buffers
     int32_t ck_cap = 0, pb = 0;
     void *ckU = nullptr;     // basis before each merge (cap x m x r, compute type)

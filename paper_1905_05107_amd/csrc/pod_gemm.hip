@@ -281,7 +281,7 @@ __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const D
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
     TC *Xs = reinterpret_cast<TC *>(lds_raw);
-    if (s.guard && ds->exhausted) return;
+    if (s.guard && merge_halted(ds)) return;
     const int P = sel_count(ds, which_p);
     s.rs = ds->rs;
     s.g = ds->g;
@@ -406,7 +406,7 @@ __device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part
                                                  const DevState *ds, int which_p, double *__restrict__ G, int bid)
 {
     __shared__ double sq[4][64];
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int P = sel_count(ds, which_p);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int idx = bid * 64 + lane;
@@ -509,7 +509,7 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
 {
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
-    if (s.guard && ds->exhausted) return;
+    if (s.guard && merge_halted(ds)) return;
     if (Yout1 && (ds->it & 1)) Yout = Yout1;
     const int pin = sel_count(ds, sel_in), pout = sel_count(ds, sel_out);
     s.rs = ds->rs;

@@ -25,13 +25,18 @@ struct DevState {
     int32_t col_log_len;// entries used in the column log
     int32_t s_empty;    // no drawable column left after the last draw
     int32_t sweeps_total; // Jacobi sweeps summed over merges
-    int32_t done;       // batched runs: this matrix stopped (skipped by the batched kernels)
+    int32_t done;       // batched or device-driven runs: this run stopped (merge-time kernels skip)
     double sin_theta;   // last convergence sine (NaN until the second merge)
     uint64_t wtot;      // total column weight of the last draw
     uint64_t wrow_tot;  // total row weight of the last row draw
 };
 
 enum : int32_t { FLAG_SHIFT = 1, FLAG_NONFINITE = 2, FLAG_NOCONV = 4, FLAG_ZERO_ROWS = 8 };
+
+// The merge-time kernels do nothing when the pending draw found S exhausted
+// or the run has stopped (`done`, set on the device by the stop test of a
+// batched or device-driven run).
+__device__ __forceinline__ bool merge_halted(const DevState *ds) { return ds->exhausted || ds->done; }
 
 // ---------------------------------------------------------------- Philox-4x64-10
 // Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as easy as 1, 2, 3",
@@ -118,6 +123,8 @@ struct DrawArgs {
 };
 hipError_t launch_draw_cols(const DrawArgs &a, hipStream_t st);
 hipError_t launch_draw_cols_b(const DrawArgs *arr, int32_t count, hipStream_t st);
+hipError_t launch_run_done(DevState *ds, int32_t max_iter, double tol, int32_t stop_conv, double *sin_log,
+                           int32_t log_cap, hipStream_t st);
 hipError_t launch_batch_done(DevState *const *dss, const int32_t *max_iter, const double *sin_tol, int32_t count,
                              int32_t *ndone, hipStream_t st);
 

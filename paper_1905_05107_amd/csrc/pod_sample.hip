@@ -183,7 +183,7 @@ hipError_t launch_center(void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t
 __global__ __launch_bounds__(1024) void k_quantize(const double *__restrict__ v, int64_t len,
                                                    uint64_t *__restrict__ w, DevState *ds, int32_t guard)
 {
-    if (guard && ds->exhausted) return;
+    if (guard && merge_halted(ds)) return;
     __shared__ double smax[16];
     __shared__ int sbad[16];
     const int t = threadIdx.x;
@@ -252,6 +252,7 @@ __device__ __forceinline__ void draw_cols_body(const DrawArgs &a)
     __shared__ uint64_t swave[16];
     const int t = threadIdx.x;
     DevState *ds = a.ds;
+    if (ds->done) return;   // a batched or device-driven run that has stopped
     const int32_t it = ds->it;
     const bool unf = a.unf && it > 0;
     const int64_t n = a.n;
@@ -435,6 +436,28 @@ __global__ __launch_bounds__(256) void k_batch_done(DevState *const *__restrict_
     if (threadIdx.x == 0) *ndone = ((sw[0] + sw[1]) + sw[2]) + sw[3];
 }
 
+// Stop test of a device-driven single run, after each merge: logs the merge's
+// convergence sine (sin_log[it - 1]; rewriting the same value when the draw
+// found S exhausted and nothing was merged) and sets `done` under the rule of
+// pod_converged: S exhausted, max_iter merges, or, when stop_conv is set and
+// from the second merge, a sine below tol.
+__global__ void k_run_done(DevState *ds, int32_t max_iter, double tol, int32_t stop_conv, double *sin_log,
+                           int32_t log_cap)
+{
+    if (threadIdx.x != 0 || ds->done) return;
+    const int32_t it = ds->it;
+    if (it >= 1 && it <= log_cap) sin_log[it - 1] = ds->sin_theta;
+    const bool d = ds->exhausted || ds->s_empty || it >= max_iter || (stop_conv && it >= 2 && ds->sin_theta < tol);
+    if (d) ds->done = 1;
+}
+
+hipError_t launch_run_done(DevState *ds, int32_t max_iter, double tol, int32_t stop_conv, double *sin_log,
+                           int32_t log_cap, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_run_done, dim3(1), dim3(64), 0, st, ds, max_iter, tol, stop_conv, sin_log, log_cap);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_done(DevState *const *dss, const int32_t *max_iter, const double *sin_tol, int32_t count,
                              int32_t *ndone, hipStream_t st)
 {
@@ -465,7 +488,7 @@ __global__ __launch_bounds__(256) void k_row_sqnorms(const T *__restrict__ A, in
                                                      double *__restrict__ rho)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= m || ds->exhausted) return;
+    if (i >= m || merge_halted(ds)) return;
     const TU *U = (ds->it & 1) ? U1 : U0;   // current basis
     double acc = 0.0;
     if (U && ds->it > 0) {
@@ -516,7 +539,7 @@ __global__ __launch_bounds__(1024) void k_draw_rows(RowDrawArgs a)
     __shared__ uint64_t swave[16];
     const int t = threadIdx.x;
     DevState *ds = a.ds;
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int32_t it = ds->it;
     const int64_t m = a.m;
     const int64_t chunk = (m + 1023) / 1024;

@@ -233,7 +233,7 @@ __device__ __forceinline__ void chol_first_rl(const SmallArgs &a)
     __shared__ double sP[SMALL_LDS_P], sred[8];
     __shared__ int sfl[8], sbadw[8];
     DevState *ds = a.ds;
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int p = ds->p, rs = ds->rs, p0 = ds->p0;
     const int pm = a.pmax;
     const int w = rl_wave(), l = rl_lane();
@@ -354,7 +354,7 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
     __shared__ double sred[16];
     __shared__ int sbad;
     DevState *ds = a.ds;
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int p = ds->p, rs = ds->rs, p0 = ds->p0;
     const int pm = a.pmax;
     double *S = BIG ? a.ws : lds;       // p x p
@@ -511,7 +511,7 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     __shared__ int sfl[8];
     DevState *ds = a.ds;
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int p = ds->p, rs = ds->rs;
     const int it0 = ds->it;   // read before thread 0 advances it at the end
     const int pm = a.pmax;
@@ -656,7 +656,7 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     __shared__ double sred[NT / 64];
     DevState *ds = a.ds;
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int p = ds->p, rs = ds->rs;
     const int it0 = ds->it;   // read before thread 0 advances it at the end
     const int pm = a.pmax;
@@ -1025,7 +1025,7 @@ __global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
         sdots[EIG_NMAX], ssc[8];
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     DevState *ds = a.ds;
-    if (ds->exhausted) return;
+    if (merge_halted(ds)) return;
     const int g = ds->g, rs = ds->rs;
     const int pm = a.pmax;
     double *S = BIG ? a.ws : lds; // G_B (g x g) -> reflectors

@@ -129,6 +129,29 @@ def test_c1_merge_state_each_iteration(c1):
         assert np.linalg.norm(U.T @ U - np.eye(U.shape[1])) <= 1e-12
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(precision=pod.POD_F32), dict(w=60), dict(r_update=8), dict(n_iter=5)])
+def test_device_loop_equals_stepwise_loop(c1, kw):
+    """pod_run (the loop of Alg. 1 with a device-side stop test and chunked
+    launches) gives the host loop's merges bit for bit: same sines, same basis."""
+    kw = dict(kw)
+    n_iter = kw.pop("n_iter", None)
+    print(f"device loop vs stepwise {kw} n_iter={n_iter}", flush=True)
+    A = c1.A.astype(np.float32) if kw.get("precision") == pod.POD_F32 else c1.A
+    outs = []
+    for stepwise, chunk in [(True, 8), (False, 3), (False, 64)]:
+        with pod.PodContext(_dev(A), **_c1_params(**kw)) as ctx:
+            sines = ctx.run(n_iter=n_iter, chunk=chunk, stepwise=stepwise)
+            inf = ctx.info()
+            U, sig, _ = ctx.project(want_v=False)
+            outs.append((sines, inf.iter, U.cpu().numpy(), sig.cpu().numpy()))
+    ref = outs[0]
+    assert len(ref[0]) >= 2
+    for o in outs[1:]:
+        assert o[1] == ref[1] and len(o[0]) == len(ref[0])
+        assert np.array_equal(np.array(o[0]), np.array(ref[0]), equal_nan=True)
+        assert np.array_equal(o[2], ref[2]) and np.array_equal(o[3], ref[3])
+
+
 def test_unf_strategy_and_r_larger_than_k(c1):
     A = c1.A
     kw = _c1_params(col_strategy="unf", r=30)
