@@ -81,6 +81,52 @@ def kernel_work(cls, m, n, k, c, p, r, launches):
     return None, 0, None, 0
 
 
+TRAFFIC_SOURCES = {"svd": ["pod_small.hip", "pod_rl.h", "pod_symeig.h", "pod_internal.h"],
+                   "chol": ["pod_small.hip", "pod_rl.h", "pod_symeig.h", "pod_internal.h"],
+                   "gram": ["pod_gemm.hip", "pod_internal.h"], "tall": ["pod_gemm.hip", "pod_internal.h"]}
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of a kernel class from the committed FETCH_SIZE /
+    WRITE_SIZE summary (profiles/isma_waves200k_hbm_traffic.md), scaled by the
+    copy-kernel factors recorded there; None when the class was not measured
+    or its kernel sources changed since (sha256 prefix mismatch)."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "isma_waves200k_hbm_traffic.md")
+    if cls not in TRAFFIC_SOURCES or not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES[cls]:
+        with open(os.path.join(root, "paper_1905_05107_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    cur = h.hexdigest()[:16]
+    for line in open(path):
+        parts = line.split()
+        if len(parts) >= 3 and parts[0] == "traffic" and parts[1] == cls:
+            kv = dict(p.split("=", 1) for p in parts[2:])
+            if kv.get("sources") != cur:
+                return None
+            kib = float(kv["fetch_kib"]) * float(kv["fetch_factor"]) + float(kv["write_kib"]) * float(kv["write_factor"])
+            return round(kib * 1024.0)
+    return None
+
+
+RUN_CHUNK = 8   # iterations the device-driven loop enqueues between syncs
+PER_MERGE_LAUNCHES = {"gram": 2, "gram_reduce": 2, "tall": 2, "chol": 1, "svd": 1, "draw": 1}
+
+
+def real_launches(cls, launches, iters):
+    """Launches of a class that did work in one step: the device-driven loop
+    enqueues ceil(iters / RUN_CHUNK) chunks, and the iterations past the
+    stop launch kernels that return at once."""
+    per = PER_MERGE_LAUNCHES.get(cls)
+    if per is None:
+        return launches
+    enq = -(-iters // RUN_CHUNK) * RUN_CHUNK
+    return max(launches - per * (enq - iters), 1)
+
+
 def roofline_entry(bound, amount, avg_s, hbm_bytes):
     if bound == "hbm":
         a = amount / avg_s / 1e9
@@ -299,7 +345,7 @@ def main():
 
     def step(precision):
         with pod.PodContext(A, precision=precision, **kw) as ctx:
-            ctx.run()
+            ctx.run(chunk=RUN_CHUNK)
             inf = ctx.info()
             ctx.project(want_v=False)
         info["iters"] = inf.iter
@@ -341,17 +387,20 @@ def main():
     sec64 = (time.perf_counter() - t0) / args.fp64_steps
     iters64 = info["iters"]
 
-    # roofline of the dominant kernel class (measured live in the timed steps)
-    per_step_launches = launches / args.steps
-    avg_s = dom_ms / 1e3 / max(launches, 1)
+    # roofline of the dominant kernel class (measured live in the timed steps);
+    # the device-driven loop enqueues whole chunks of iterations, and the
+    # launches after the stop return at once: count the launches that merged
+    per_step_launches = real_launches(dominant, launches / args.steps, iters)
+    avg_s = dom_ms / 1e3 / max(per_step_launches * args.steps, 1)
     bound, amount, unit, hb = kernel_work(dominant, m, n, k, c, p, k, per_step_launches)
     roof = roofline_entry(bound, amount, avg_s, hb)
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dominant)
     roof.update({"kernel_class": dominant, "avg_launch_us": round(avg_s * 1e6, 2),
                  "launches_per_step": round(per_step_launches, 1)})
     # the other classes, from the per-class pre-pass
     others = {}
     for cls, (ln, ms) in per_class.items():
+        ln = real_launches(cls, ln, iters)
         b2, a2, _, h2 = kernel_work(cls, m, n, k, c, p, k, ln)
         if b2 is None or ln == 0:
             continue
