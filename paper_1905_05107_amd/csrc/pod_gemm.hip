@@ -382,6 +382,159 @@ __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const D
     }
 }
 
+// ---------------------------------------------------------------------------
+// Partial Grams for P <= 64 straight from registers.  Lane (i, k) =
+// (l % 16, l / 16) of a wave loads rows 4k .. 4k+3 of a 16-row group, as one
+// 16-byte vector per column tile t, from column 16 t + i.  MFMA step j takes
+// row 4k + j as the k-th row of a 4-row slice (a Gram sums over its rows in
+// any order), so the A and B operands of tile (I, J) are the lanes' own values
+// of tiles I and J: no LDS staging and no barrier in the row loop.  Waves take
+// interleaved groups with two groups loaded ahead; the four wave partials of
+// a workgroup are summed in FP64 through LDS in a fixed order and written as
+// the tile pairs I <= J of part[b] (both triangles).
+// ---------------------------------------------------------------------------
+constexpr int GD_LDS = 4 * 5 * 4 * 64 * 8;   // wave partials of five tile pairs, FP64
+constexpr int GD_NB = 3;                      // register groups per wave
+
+template <typename TC> struct Vec4;
+template <> struct Vec4<float> {
+    __device__ static void load(const float *p, float v[4])
+    {
+        const f32x4 a = *reinterpret_cast<const f32x4 *>(p);
+        v[0] = a[0];
+        v[1] = a[1];
+        v[2] = a[2];
+        v[3] = a[3];
+    }
+};
+template <> struct Vec4<double> {
+    __device__ static void load(const double *p, double v[4])
+    {
+        const f64x2 a = *reinterpret_cast<const f64x2 *>(p);
+        const f64x2 b = *reinterpret_cast<const f64x2 *>(p + 2);
+        v[0] = a[0];
+        v[1] = a[1];
+        v[2] = b[0];
+        v[3] = b[1];
+    }
+};
+
+template <typename TC>
+__device__ __forceinline__ void gram_direct_body(SrcT<TC> s, int64_t m, const DevState *ds, int which_p, int pmax,
+                                                 double *__restrict__ part, int nblk, int vec, int bid)
+{
+    typedef typename Acc<TC>::type AccT;
+    extern __shared__ unsigned char lds_raw[];
+    double *red = reinterpret_cast<double *>(lds_raw);
+    if (s.guard && merge_halted(ds)) return;
+    const int P = sel_count(ds, which_p);
+    s.rs = ds->rs;
+    s.g = ds->g;
+    if (s.U1 && (ds->it & 1)) s.U = s.U1;
+    const int NT = (P + 15) >> 4;   // column tiles, <= 4
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ci = lane & 15, kr = 4 * (lane >> 4);
+    // the lane's column of every tile (tiles past P read column 0, zeroed below)
+    ColPtr cp[4];
+    bool live[4];
+    bool same = true;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int c = 16 * t + ci;
+        live[t] = c < P;
+        cp[t] = col_ptr<TC>(s, m, live[t] ? c : 0);
+        same = same && (cp[t].f64 == (sizeof(TC) == 8 ? 1 : 0));
+    }
+    // fast path: every column in the compute type and 16-byte aligned (uniform)
+    const bool fast = vec && __all(same);
+    const int64_t ngr = (m + 15) >> 4;
+    const int64_t g0 = (ngr * bid) / nblk, g1 = (ngr * (bid + 1)) / nblk;
+    const int64_t gf = (g1 < (m >> 4)) ? g1 : (m >> 4);   // groups entirely inside [0, m)
+    AccT acc[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) acc[q] = AccT{0, 0, 0, 0};
+    auto mma = [&](const TC (&v)[4][4]) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int q = 0;
+#pragma unroll
+            for (int I = 0; I < 4; ++I)
+#pragma unroll
+                for (int J = I; J < 4; ++J, ++q)
+                    if (J < NT) acc[q] = mfma16x16x4(v[I][j], v[J][j], acc[q]);
+        }
+    };
+    auto load_fast = [&](int64_t gr, TC (&v)[4][4]) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            Vec4<TC>::load(reinterpret_cast<const TC *>(cp[t].p) + gr * 16 + kr, v[t]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[t][q] = live[t] ? v[t][q] : (TC)0;
+        }
+    };
+    int64_t gstart = g0 + wv;
+    if (fast && gstart < gf) {
+        // GD_NB register groups: loads GD_NB - 1 groups ahead (indices clamped to
+        // the wave's last full group, so every iteration issues the same loads)
+        const int64_t lastg = gstart + ((gf - 1 - gstart) / 4) * 4;
+        TC vr[GD_NB][4][4];
+#pragma unroll
+        for (int b = 0; b < GD_NB - 1; ++b) load_fast((gstart + 4 * b < lastg) ? gstart + 4 * b : lastg, vr[b]);
+        for (int64_t gr = gstart;; gr += 4 * GD_NB) {
+            bool more = true;
+#pragma unroll
+            for (int b = 0; b < GD_NB; ++b) {
+                if (more) {
+                    const int64_t ld = gr + 4 * (b + GD_NB - 1);
+                    load_fast((ld < lastg) ? ld : lastg, vr[(b + GD_NB - 1) % GD_NB]);
+                    mma(vr[b]);
+                    more = gr + 4 * (b + 1) <= lastg;
+                }
+            }
+            if (!more) break;
+        }
+        gstart = lastg + 4;   // the wave's groups past the full ones
+    }
+    // the rest (a partial last group, or every group off the fast path)
+    for (int64_t gr = gstart; gr < g1; gr += 4) {
+        TC v[4][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            load4<TC>(cp[t], gr * 16 + kr, m, vec, v[t]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[t][q] = live[t] ? v[t][q] : (TC)0;
+        }
+        mma(v);
+    }
+    // sum the four wave partials in FP64 (waves in order), five tile pairs at a time
+    double *pb = part + (int64_t)bid * pmax * pmax;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        if (half) __syncthreads();
+#pragma unroll
+        for (int q5 = 0; q5 < 5; ++q5)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[((wv * 5 + q5) * 4 + v) * 64 + lane] = (double)acc[5 * half + q5][v];
+        __syncthreads();
+        for (int o = threadIdx.x; o < 5 * 256; o += 256) {
+            const int q5 = o >> 8, v = (o >> 6) & 3, ln = o & 63;
+            const int q = 5 * half + q5;
+            // pair q -> (I, J), I <= J
+            const int I = (q < 4) ? 0 : (q < 7) ? 1 : (q < 9) ? 2 : 3;
+            const int J = I + q - ((q < 4) ? 0 : (q < 7) ? 4 : (q < 9) ? 7 : 9);
+            if (J >= NT) continue;
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) sum += red[((w * 5 + q5) * 4 + v) * 64 + ln];
+            const int i = 16 * I + acc_row<TC>(ln, v), j = 16 * J + (ln & 15);
+            if (I < J || i <= j) {
+                pb[i + (int64_t)j * pmax] = sum;
+                pb[j + (int64_t)i * pmax] = sum;
+            }
+        }
+    }
+}
+
 template <typename TC, int MAXPW, int ITEMS>
 __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, const DevState *ds, int which_p,
                                                       int pmax, double *__restrict__ part, int nblk, int vec)
@@ -389,56 +542,74 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
     gram_partial_body<TC, MAXPW, ITEMS>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
 }
 
-// Batched: matrix blockIdx.y, its own block count; stopped matrices skipped.
-template <typename TC, int MAXPW, int ITEMS>
-__global__ __launch_bounds__(256) void k_gram_partial_b(const GramArgs *__restrict__ arr)
+template <typename TC>
+__global__ __launch_bounds__(256) void k_gram_direct(SrcT<TC> s, int64_t m, const DevState *ds, int which_p, int pmax,
+                                                     double *__restrict__ part, int nblk, int vec)
+{
+    gram_direct_body<TC>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
+}
+
+// Batched (P <= 64): matrix blockIdx.y, its own block count; stopped matrices skipped.
+template <typename TC>
+__global__ __launch_bounds__(256) void k_gram_direct_b(const GramArgs *__restrict__ arr)
 {
     const GramArgs &a = arr[blockIdx.y];
     if ((int)blockIdx.x >= a.nblk || a.ds->done) return;
-    gram_partial_body<TC, MAXPW, ITEMS>(make_src<TC>(a.d), a.d.m, a.ds, a.which_p, a.pmax, a.part, a.nblk, a.vec,
-                                        blockIdx.x);
+    gram_direct_body<TC>(make_src<TC>(a.d), a.d.m, a.ds, a.which_p, a.pmax, a.part, a.nblk, a.vec, blockIdx.x);
 }
 
 // Fixed-order reduction of the partial Grams: workgroup w owns 64 entries;
 // its 4 waves each add a contiguous quarter of the partials in order, and the
 // four quarter sums are added in order.
+// G = sum of the nblk partials, 64 entries per workgroup, the partials split
+// over GR_W waves (memory parallelism), wave sums combined in wave order
+// (deterministic).  Only the upper triangle is summed; it is mirrored.
+constexpr int GR_W = 16;
 __device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part, int nblk, int pmax,
                                                  const DevState *ds, int which_p, double *__restrict__ G, int bid)
 {
-    __shared__ double sq[4][64];
+    __shared__ double sq[GR_W][64];
     if (merge_halted(ds)) return;
     const int P = sel_count(ds, which_p);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int idx = bid * 64 + lane;
     const int i = idx % pmax, j = idx / pmax;
-    const bool live = idx < pmax * pmax && i < P && j < P;
-    const int b0 = (nblk * wv) / 4, b1 = (nblk * (wv + 1)) / 4;
+    const bool live = idx < pmax * pmax && i < P && j < P && i <= j;
+    const int b0 = (nblk * wv) / GR_W, b1 = (nblk * (wv + 1)) / GR_W;
     double s = 0.0;
     if (live) {
-        // eight independent accumulators keep eight loads in flight; fixed order
+        // four independent accumulators keep four loads in flight; fixed order
         const int64_t st = (int64_t)pmax * pmax;
         const double *pp = part + idx;
-        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
         int b = b0;
-        for (; b + 8 <= b1; b += 8) {
+        for (; b + 4 <= b1; b += 4) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a[u] += pp[(int64_t)(b + u) * st];
+            for (int u = 0; u < 4; ++u) a[u] += pp[(int64_t)(b + u) * st];
         }
         for (; b < b1; ++b) a[0] += pp[(int64_t)b * st];
-        s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        s = (a[0] + a[1]) + (a[2] + a[3]);
     }
     sq[wv][lane] = s;
     __syncthreads();
-    if (wv == 0 && idx < pmax * pmax) G[idx] = live ? ((sq[0][lane] + sq[1][lane]) + sq[2][lane]) + sq[3][lane] : 0.0;
+    if (wv == 0 && idx < pmax * pmax && i <= j) {
+        double g = 0.0;
+        if (live) {
+#pragma unroll
+            for (int w = 0; w < GR_W; ++w) g += sq[w][lane];
+        }
+        G[idx] = g;
+        G[j + (int64_t)i * pmax] = g;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ part, int nblk, int pmax,
+__global__ __launch_bounds__(64 * GR_W) void k_gram_reduce(const double *__restrict__ part, int nblk, int pmax,
                                                      const DevState *ds, int which_p, double *__restrict__ G)
 {
     gram_reduce_body(part, nblk, pmax, ds, which_p, G, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_gram_reduce_b(const GramArgs *__restrict__ arr)
+__global__ __launch_bounds__(64 * GR_W) void k_gram_reduce_b(const GramArgs *__restrict__ arr)
 {
     const GramArgs &a = arr[blockIdx.y];
     if ((int)blockIdx.x * 64 >= a.pmax * a.pmax || a.ds->done) return;
@@ -464,11 +635,21 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
     ProfScope ps(POD_K_GRAM, st);
     const bool wide = pmax > 64;
     if (d.prec == POD_F64) {
-        if (wide) gram_launch<double, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
-        else gram_launch<double, MAXPW64, ITEMS64>(d, ds, which_p, pmax, part, nblk, st);
+        if (wide) {
+            gram_launch<double, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
+        } else {
+            const SrcT<double> s = make_src<double>(d);
+            hipLaunchKernelGGL(k_gram_direct<double>, dim3(nblk), dim3(256), GD_LDS, st, s, d.m, ds, which_p, pmax,
+                               part, nblk, (int)vec_ok(s, d.m));
+        }
     } else {
-        if (wide) gram_launch<float, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
-        else gram_launch<float, MAXPW64, ITEMS64>(d, ds, which_p, pmax, part, nblk, st);
+        if (wide) {
+            gram_launch<float, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
+        } else {
+            const SrcT<float> s = make_src<float>(d);
+            hipLaunchKernelGGL(k_gram_direct<float>, dim3(nblk), dim3(256), GD_LDS, st, s, d.m, ds, which_p, pmax,
+                               part, nblk, (int)vec_ok(s, d.m));
+        }
     }
     return hipGetLastError();
 }
@@ -477,8 +658,8 @@ hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax
                                   int32_t which_p, double *G, hipStream_t st)
 {
     ProfScope ps(POD_K_GRAM_REDUCE, st);
-    hipLaunchKernelGGL(k_gram_reduce, dim3((pmax * pmax + 63) / 64), dim3(256), 0, st, part, nblk, pmax, ds, which_p,
-                       G);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((pmax * pmax + 63) / 64), dim3(64 * GR_W), 0, st, part, nblk, pmax, ds,
+                       which_p, G);
     return hipGetLastError();
 }
 
@@ -867,11 +1048,9 @@ hipError_t launch_gram_partial_b(const GramArgs *arr, int32_t count, int32_t max
     if (pmax_max > 64 || count < 1) return hipErrorInvalidValue;
     const dim3 grid((unsigned)max_nblk, (unsigned)count);
     if (prec == POD_F64)
-        hipLaunchKernelGGL((k_gram_partial_b<double, MAXPW64, ITEMS64>), grid, dim3(256),
-                           (size_t)64 * LDSR * sizeof(double), st, arr);
+        hipLaunchKernelGGL(k_gram_direct_b<double>, grid, dim3(256), GD_LDS, st, arr);
     else
-        hipLaunchKernelGGL((k_gram_partial_b<float, MAXPW64, ITEMS64>), grid, dim3(256),
-                           (size_t)64 * LDSR * sizeof(float), st, arr);
+        hipLaunchKernelGGL(k_gram_direct_b<float>, grid, dim3(256), GD_LDS, st, arr);
     return hipGetLastError();
 }
 
@@ -879,7 +1058,7 @@ hipError_t launch_gram_reduce_b(const GramArgs *arr, int32_t count, int32_t pmax
 {
     if (count < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gram_reduce_b, dim3((unsigned)((pmax_max * pmax_max + 63) / 64), (unsigned)count),
-                       dim3(256), 0, st, arr);
+                       dim3(64 * GR_W), 0, st, arr);
     return hipGetLastError();
 }
 
