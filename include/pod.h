@@ -300,7 +300,7 @@ typedef enum {
     POD_K_GRAM_REDUCE = 3,/* fixed-order sum of the Gram partials            */
     POD_K_CHOL = 4,       /* FP64 Cholesky + triangular inverse (pass 1)     */
     POD_K_TALL = 5,       /* tall transform Y = X T                          */
-    POD_K_SVD = 6,        /* pass-2 Cholesky + FP64 Jacobi SVD of the merge  */
+    POD_K_SVD = 6,        /* pass-2 Cholesky + FP64 SVD of the merge factor  */
     POD_K_PROJECT = 7,    /* B = U^T A (one pass over A)                     */
     POD_K_RR = 8,         /* Rayleigh-Ritz small kernels                     */
     POD_K_SIGN = 9,       /* sign convention of the outputs                  */

@@ -270,7 +270,7 @@ template <typename TC> __host__ __device__ SrcT<TC> make_src(const GemmDesc &d)
 // Width classes: pmax <= 64 (10 tiles over 4 waves: 3 per wave; a stage is
 // 64 columns x 8 groups = 2 items per thread) and pmax <= 160 (55 tiles: 14
 // per wave; 5 items per thread).
-constexpr int MAXPW64 = 3, ITEMS64 = 2;
+constexpr int ITEMS64 = 2;
 constexpr int MAXPW160 = 14, ITEMS160 = 5;
 constexpr int PMAX_WIDE = 160;
 

@@ -211,6 +211,9 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
                                     int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout,
                                     int32_t split, const int32_t *cmap, void *D, int64_t ldd, hipStream_t st);
 
+// Merge widths up to this run the register-resident small kernels.
+constexpr int SMALL_LDS_P = 64;
+
 struct SmallArgs {
     DevState *ds;
     const double *Vt;      // right factor of the new block (g x ru, ld pmax) when use_vt

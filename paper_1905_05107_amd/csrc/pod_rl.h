@@ -64,57 +64,98 @@ __device__ __forceinline__ void rl_identity(int n, double *Rs, double *Xs)
     __syncthreads();
 }
 
+// Row of register k in wave w in the layout of rl_cholinv: wave w keeps the
+// row blocks 4w..4w+3 (k = 0..3) and 32+4w..32+4w+3 (k = 4..7).
+__device__ __forceinline__ int rl_chol_row(int w, int k) { return 4 * w + 32 * (k >> 2) + (k & 3); }
+
+// rl_load_sym in the row layout of rl_cholinv.
+__device__ __forceinline__ void rl_load_sym_chol(double (&r)[8], const double *M, int ld, int n)
+{
+    const int w = rl_wave(), l = rl_lane();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int a = rl_chol_row(w, k);
+        r[k] = (a < n && l < n) ? M[l + (size_t)a * ld] : 0.0;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Cholesky G = R^T R of the symmetric matrix in r (upper triangle read) and
-// X = R^-T alongside: the rows of [G | I] are eliminated in order (outer-
-// product Cholesky, Golub & Van Loan Alg. 4.2.2, on the augmented matrix,
-// which carries out the forward substitution R^T X = I step by step).  Row j
-// is scaled by 1/sqrt(pivot) by its owner wave and published; every wave then
-// subtracts R(j, a) times it from its rows a > j.  One barrier per row.
-// On return Rs and Xs (LDS, row-major, ld RL_LD, 64 rows, zero-padded) hold R
-// and X = R^-T (so R^-1(i, j) = Xs[j * RL_LD + i]).  Returns nonzero,
-// uniformly, when a pivot is not above thr (the factors are then garbage).
-// r and x are overwritten; `sfl` is 8 ints of LDS.
+// Cholesky G = R^T R of the symmetric matrix in r (upper triangle read; rows
+// in the rl_chol_row layout) and X = R^-T alongside: the rows of [G | I] are
+// eliminated in order (outer-product Cholesky, Golub & Van Loan Alg. 4.2.2,
+// on the augmented matrix, which carries out the forward substitution
+// R^T X = I step by step).  Rows go in blocks of four held by one wave: the
+// owner scales row j by 1/sqrt(pivot) and subtracts R(j, a) times it from the
+// block's later rows a in registers, then publishes the block; after one
+// barrier every wave subtracts the block's four rows from its rows below it,
+// in row order (the same operations, in the same order, as eliminating one
+// row per barrier).  On return Rs and Xs (LDS, row-major, ld RL_LD, 64 rows,
+// zero-padded) hold R and X = R^-T (so R^-1(i, j) = Xs[j * RL_LD + i]).
+// Returns nonzero, uniformly, when a pivot is not above thr (the factors are
+// then garbage).  r is overwritten; `sfl` is 8 ints of LDS.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int rl_cholinv(double (&r)[8], int n, double thr, double *Rs, double *Xs, int *sfl)
 {
     const int w = rl_wave(), l = rl_lane();
     double x[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = (l == w + 8 * k && l < n) ? 1.0 : 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const int a = rl_chol_row(w, k);
+        x[k] = (l == a && a < n) ? 1.0 : 0.0;
+    }
     int fail = 0;
 #pragma unroll
-    for (int J = 0; J < 8; ++J) {
-        for (int w0 = 0; w0 < 8; ++w0) {
-            const int j = 8 * J + w0;
-            if (j >= n) break;
-            if (w == w0) {
-                const double d = readlane_f64(r[J], j);
-                if (!(d > thr)) fail = 1;
-                const double s = rsqrt_nr(fmax(d, 1e-300));
-                const double rv = (l >= j) ? r[J] * s : 0.0;
-                const double xv = x[J] * s;
-                r[J] = rv;
-                x[J] = xv;
-                Rs[j * RL_LD + l] = rv;
-                Xs[j * RL_LD + l] = xv;
+    for (int H = 0; H < 2; ++H) {
+        for (int b = 0; b < 8; ++b) {
+            const int j0 = 32 * H + 4 * b;   // the block's first row; wave b owns it
+            if (j0 >= n) break;
+            if (w == b) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int j = j0 + s;
+                    if (j < n) {
+                        const double d = readlane_f64(r[4 * H + s], j);
+                        if (!(d > thr)) fail = 1;
+                        const double sc = rsqrt_nr(fmax(d, 1e-300));
+                        r[4 * H + s] = (l >= j) ? r[4 * H + s] * sc : 0.0;
+                        x[4 * H + s] = x[4 * H + s] * sc;
+#pragma unroll
+                        for (int t = s + 1; t < 4; ++t) {
+                            const double c = readlane_f64(r[4 * H + s], j0 + t);   // R(j, j0 + t)
+                            if (j0 + t < n) {
+                                r[4 * H + t] -= c * r[4 * H + s];
+                                x[4 * H + t] -= c * x[4 * H + s];
+                            }
+                        }
+                    }
+                    Rs[j * RL_LD + l] = r[4 * H + s];
+                    Xs[j * RL_LD + l] = x[4 * H + s];
+                }
             }
             __syncthreads();
-            const double rj = Rs[j * RL_LD + l], xj = Xs[j * RL_LD + l];
+            double rj[4], xj[4];
 #pragma unroll
-            for (int k = J; k < 8; ++k) {
-                const int a = w + 8 * k;
-                const double c = Rs[j * RL_LD + a];
-                if (a > j && a < n) {
-                    r[k] -= c * rj;
-                    x[k] -= c * xj;
+            for (int s = 0; s < 4; ++s) {
+                rj[s] = Rs[(j0 + s) * RL_LD + l];
+                xj[s] = Xs[(j0 + s) * RL_LD + l];
+            }
+#pragma unroll
+            for (int k = 4 * H; k < 8; ++k) {
+                const int a = rl_chol_row(w, k);
+                if (a > j0 + 3 && a < n) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const double c = Rs[(j0 + s) * RL_LD + a];
+                        r[k] -= c * rj[s];
+                        x[k] -= c * xj[s];
+                    }
                 }
             }
         }
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const int a = w + 8 * k;
+        const int a = rl_chol_row(w, k);
         if (a >= n) {
             Rs[a * RL_LD + l] = 0.0;
             Xs[a * RL_LD + l] = 0.0;
@@ -185,32 +226,32 @@ __device__ __forceinline__ void rl_tridiag(double (&r)[8], int n, double *d, dou
                 }
             }
             __syncthreads();
+            // tau, v_j and the wave's entries of v_j in one LDS round trip.  With
+            // tau_j = 0 (a column already reduced) p = w = 0 and the update below
+            // leaves every row unchanged, so that step needs no branch.
             const double tj = tau[j];
-            if (tj != 0.0) {
-                const double vl = V[j * RL_LD + l];
-                // v_j is zero outside rows j+1..n-1, so rows a <= j and a >= n take
-                // no part and no update below without tests
-                double va[8];
-                double pa[4] = {0.0, 0.0, 0.0, 0.0};   // four partial sums: a shorter dependency chain
+            const double vl = V[j * RL_LD + l];
+            // v_j is zero outside rows j+1..n-1, so rows a <= j and a >= n take
+            // no part and no update below without tests
+            double va[8];
 #pragma unroll
-                for (int k = J; k < 8; ++k) {
-                    va[k] = V[j * RL_LD + w + 8 * k];
-                    pa[k & 3] += r[k] * va[k];
-                }
-                Pp[w * 64 + l] = (pa[0] + pa[1]) + (pa[2] + pa[3]);
-                __syncthreads();
-                double pq[8];
+            for (int k = J; k < 8; ++k) va[k] = V[j * RL_LD + w + 8 * k];
+            double pa[4] = {0.0, 0.0, 0.0, 0.0};   // four partial sums: a shorter dependency chain
 #pragma unroll
-                for (int q = 0; q < 8; ++q) pq[q] = Pp[q * 64 + l];
-                double pl = ((pq[0] + pq[1]) + (pq[2] + pq[3])) + ((pq[4] + pq[5]) + (pq[6] + pq[7]));
-                pl = (l > j && l < n) ? tj * pl : 0.0;
-                const double K = 0.5 * tj * wave_sum(pl * vl);
-                const double wl = pl - K * vl;
+            for (int k = J; k < 8; ++k) pa[k & 3] = fma(r[k], va[k], pa[k & 3]);
+            Pp[w * 64 + l] = (pa[0] + pa[1]) + (pa[2] + pa[3]);
+            __syncthreads();
+            double pq[8];
 #pragma unroll
-                for (int k = J; k < 8; ++k) {
-                    const double wa = readlane_f64(wl, w + 8 * k);   // zero for rows <= j and >= n
-                    r[k] -= va[k] * wl + wa * vl;
-                }
+            for (int q = 0; q < 8; ++q) pq[q] = Pp[q * 64 + l];
+            double pl = ((pq[0] + pq[1]) + (pq[2] + pq[3])) + ((pq[4] + pq[5]) + (pq[6] + pq[7]));
+            pl = (l > j && l < n) ? tj * pl : 0.0;
+            const double K = 0.5 * tj * wave_sum(pl * vl);
+            const double wl = fma(-K, vl, pl);
+#pragma unroll
+            for (int k = J; k < 8; ++k) {
+                const double wa = readlane_f64(wl, w + 8 * k);   // zero for rows <= j and >= n
+                r[k] = fma(-va[k], wl, fma(-wa, vl, r[k]));
             }
         }
     }

@@ -16,7 +16,6 @@ constexpr int NT = EIG_NT;
 // Matrices up to SMALL_LDS_P x SMALL_LDS_P live in LDS; larger ones in the
 // workspace `ws` (device memory, L2 resident), with only the inverse-iteration
 // scratch in LDS.
-constexpr int SMALL_LDS_P = 64;
 // Dynamic LDS of the register-resident kernels (p <= 64, pmax = pm)
 constexpr size_t chol_first_lds_rl(int pm) { return (size_t)(2 * 64 * RL_LD + 2 * pm * pm) * sizeof(double); }
 constexpr size_t svd_merge_lds_rl(int) { return (size_t)(3 * 64 * RL_LD + 512 + INVIT_LDS) * sizeof(double); }
@@ -273,14 +272,14 @@ __device__ __forceinline__ void chol_first_rl(const SmallArgs &a)
         // row a, columns >= a: the upper triangle S(a, l), as the factorisation reads it
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int ar = w + 8 * k;
+            const int ar = rl_chol_row(w, k);
             g[k] = (ar < p && l < p) ? S[ar + l * p] : 0.0;
         }
     } else {
         // G0 is stored exactly symmetric: row a of G1 is read along column a
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int ar = w + 8 * k;
+            const int ar = rl_chol_row(w, k);
             g[k] = (ar < p && l < p) ? a.G[l + ar * pm] * sP[ar] * sP[l] : 0.0;
         }
     }
@@ -289,7 +288,7 @@ __device__ __forceinline__ void chol_first_rl(const SmallArgs &a)
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         if (!isfinite(g[k])) bad = 1;
-        if (l == w + 8 * k) td += g[k];
+        if (l == rl_chol_row(w, k)) td += g[k];
     }
     td = wave_sum(td);
     bad = __any(bad);
@@ -317,7 +316,7 @@ __device__ __forceinline__ void chol_first_rl(const SmallArgs &a)
             const double shift = (double)p * a.urnd * trace;
             if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) r[k] = g[k] + ((l == w + 8 * k && l < p) ? shift : 0.0);
+            for (int k = 0; k < 8; ++k) r[k] = g[k] + ((l == rl_chol_row(w, k) && l < p) ? shift : 0.0);
             fail = rl_cholinv(r, p, 0.0, Rs, Xs, sfl);
             if (fail) {
                 if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
@@ -503,6 +502,68 @@ hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 // Register-resident form for p <= 64 (pod_rl.h).  LDS: bufA holds R2, then
 // H = R R^T, then the eigenvectors Y; bufB holds R, then the reflectors of the
 // tridiagonalisation, then B^T B and its reflectors; Xs holds R2^-T.
+// The convergence sine of the merge: the largest sine of the principal angles
+// between the leading kk directions before and after it, from the first kk
+// columns of U_R (Y: p x >= kk, ld p, in LDS).  With U_R
+// orthogonal, span(U_old) = span(e_0..e_kk-1) in the merge basis and the
+// sines are the singular values of B = U_R(kk:p, 0:kk): sin^2 = lambda_max
+// of B^T B.  POD_CRIT_MODE instead takes the largest residual of each new
+// direction against the matching scaled column of R (a.work).  Every thread
+// calls this; NaN for kk = 0.
+__device__ __forceinline__ double merge_sin_rl(const SmallArgs &a, const double *Y, int p, int kk, double *bufB,
+                                               double *Pp, double *sd, double *se, double *stau, double *ssde,
+                                               double *ssin, double *sred)
+{
+    double sin_max = __builtin_nan("");
+    if (kk > 0) {
+        if (a.criterion == POD_CRIT_MODE) {
+            double mx = 0.0;
+            if (threadIdx.x < 64) {
+                for (int i = 0; i < kk; ++i) {
+                    double nr = 0.0, dt = 0.0;
+                    for (int q = threadIdx.x; q < p; q += 64) {
+                        const double x = a.work[q + i * p];
+                        nr += x * x;
+                        dt += x * Y[q + i * p];
+                    }
+                    nr = wave_sum(nr);
+                    dt = wave_sum(dt);
+                    const double inv = 1.0 / sqrt(nr);
+                    double res = 0.0;
+                    for (int q = threadIdx.x; q < p; q += 64) {
+                        const double dd = Y[q + i * p] - a.work[q + i * p] * inv * (dt * inv);
+                        res += dd * dd;
+                    }
+                    res = wave_sum(res);
+                    mx = fmax(mx, sqrt(res));
+                }
+            }
+            if (threadIdx.x == 0) sred[0] = mx;
+            __syncthreads();
+            sin_max = sred[0];
+            __syncthreads();
+        } else {
+            const int br = p - kk;
+            if (br <= 0) {
+                sin_max = 0.0;
+            } else {
+                // F = B^T B (kk x kk), B = U_R(kk:p, 0:kk)
+                double r[8];
+                rl_mm64([&](int i, int q) { return (i < kk && q < br) ? Y[kk + q + i * p] : 0.0; },
+                        [&](int q, int j) { return (q < br && j < kk) ? Y[kk + q + j * p] : 0.0; },
+                        [&](int i, int j, double v) { bufB[i * RL_LD + j] = v; });
+                __syncthreads();
+                rl_load_rows(r, bufB);
+                __syncthreads();
+                rl_tridiag(r, kk, sd, se, stau, bufB, Pp);
+                bisect_top_rl(tri_regs(sd, se, kk, ssde), kk, 1, ssin);
+                sin_max = sqrt(fmax(ssin[0], 0.0));
+            }
+        }
+    }
+    return sin_max;
+}
+
 __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
 {
     extern __shared__ double lds[];
@@ -523,7 +584,7 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
     double *lu = Pp + 512;           // INVIT_LDS
     // ---- pass-2 Cholesky R2 and R2^-T
     double g[8], r[8];
-    rl_load_sym(g, a.G, pm, p);
+    rl_load_sym_chol(g, a.G, pm, p);
     const double trace = wave_sum((l < p) ? a.G[l + l * pm] : 0.0);
     int fail = 1;
     if (isfinite(trace)) {
@@ -537,7 +598,7 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
         fail = 1;
         if (isfinite(trace)) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) r[k] = g[k] + ((l == w + 8 * k && l < p) ? shift : 0.0);
+            for (int k = 0; k < 8; ++k) r[k] = g[k] + ((l == rl_chol_row(w, k) && l < p) ? shift : 0.0);
             fail = rl_cholinv(r, p, 0.0, bufA, Xs, sfl);
         }
         if (fail) {
@@ -581,52 +642,7 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
     // Y now holds U_R(:, 0:rnew) (p x rnew, ld p)
     // ---- convergence angle
     const int kk = (kk0 < rnew) ? kk0 : rnew;
-    double sin_max = __builtin_nan("");
-    if (kk > 0) {
-        if (a.criterion == POD_CRIT_MODE) {
-            double mx = 0.0;
-            if (threadIdx.x < 64) {
-                for (int i = 0; i < kk; ++i) {
-                    double nr = 0.0, dt = 0.0;
-                    for (int q = threadIdx.x; q < p; q += 64) {
-                        const double x = a.work[q + i * p];
-                        nr += x * x;
-                        dt += x * Y[q + i * p];
-                    }
-                    nr = wave_sum(nr);
-                    dt = wave_sum(dt);
-                    const double inv = 1.0 / sqrt(nr);
-                    double res = 0.0;
-                    for (int q = threadIdx.x; q < p; q += 64) {
-                        const double dd = Y[q + i * p] - a.work[q + i * p] * inv * (dt * inv);
-                        res += dd * dd;
-                    }
-                    res = wave_sum(res);
-                    mx = fmax(mx, sqrt(res));
-                }
-            }
-            if (threadIdx.x == 0) sred[0] = mx;
-            __syncthreads();
-            sin_max = sred[0];
-            __syncthreads();
-        } else {
-            const int br = p - kk;
-            if (br <= 0) {
-                sin_max = 0.0;
-            } else {
-                // F = B^T B (kk x kk), B = U_R(kk:p, 0:kk)
-                rl_mm64([&](int i, int q) { return (i < kk && q < br) ? Y[kk + q + i * p] : 0.0; },
-                        [&](int q, int j) { return (q < br && j < kk) ? Y[kk + q + j * p] : 0.0; },
-                        [&](int i, int j, double v) { bufB[i * RL_LD + j] = v; });
-                __syncthreads();
-                rl_load_rows(r, bufB);
-                __syncthreads();
-                rl_tridiag(r, kk, sd, se, stau, bufB, Pp);
-                bisect_top_rl(tri_regs(sd, se, kk, ssde), kk, 1, ssin);
-                sin_max = sqrt(fmax(ssin[0], 0.0));
-            }
-        }
-    }
+    const double sin_max = merge_sin_rl(a, Y, p, kk, bufB, Pp, sd, se, stau, ssde, ssin, sred);
     // ---- Z2 = R2^-1 U_R(:, 0:rnew) in the compute type: Z2^T(c, i) = sum_m Y(m, c) R2^-T(m, i)
     rl_mm64([&](int c, int q) { return (c < rnew && q < p) ? Y[q + c * p] : 0.0; },
             [&](int q, int i) { return Xs[q * RL_LD + i]; },
@@ -1158,8 +1174,8 @@ hipError_t launch_svd_merge_b(const SmallArgs *arr, int32_t count, int32_t pmax_
 __global__ __launch_bounds__(512) void k_adj_small(AdjArgs a)
 {
     extern __shared__ double lds[];
-    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
-        sdots[EIG_NMAX], ssc[8], sS[EIG_NMAX], sP[EIG_NMAX];
+    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX], sS[EIG_NMAX],
+        sP[EIG_NMAX];
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     const int rs = a.rs, p = a.rs + a.g, rz = a.rz, pm = a.pm, pb = a.pb;
     const int t = threadIdx.x;
