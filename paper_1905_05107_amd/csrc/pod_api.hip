@@ -125,8 +125,8 @@ pod_status merge_launch(pod_ctx *ctx, const GemmDesc &gd, const double *sigma2, 
         POD_HIP(launch_block_eig(ba, ctx->st));
     }
     POD_HIP(launch_chol_first(sa, ctx->st));
-    // Q1 = X0 T1 (T1 = P R1^-1)
-    POD_HIP(launch_gemm_tall(gd, ctx->ds, -1, -2, pm, pm, ctx->Tc, pm, ctx->Y, nullptr, ctx->st));
+    // Q1 = X0 T1 (T1 = P R1^-1, upper triangular unless the new block has a right factor)
+    POD_HIP(launch_gemm_tall(gd, ctx->ds, -1, -2, pm, pm, ctx->Tc, pm, ctx->Y, nullptr, ctx->st, use_vt ? 0 : 1));
     // pass 2: G2 = Q1^T Q1
     GemmDesc yd = plain_desc(ctx, ctx->Y);
     POD_HIP(launch_gram_partial(yd, ctx->ds, -2, pm, ctx->part, ctx->nblk, ctx->st));

@@ -200,7 +200,9 @@ pod_status pod_batch_init(pod_batch **out, int32_t count, const pod_params *prm,
             x1.nb = tall_blocks(c->prm.m);
             x1.Yout = c->Y;
             x1.Yout1 = nullptr;
+            x1.tri = 1;   // T1 = P R1^-1 (no right factor in batches)
             x2 = x1;
+            x2.tri = 0;
             x2.d = yd;
             x2.sel_in = -2;
             x2.sel_out = -3;

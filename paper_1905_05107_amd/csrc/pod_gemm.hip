@@ -432,7 +432,7 @@ __device__ __forceinline__ void gram_direct_body(SrcT<TC> s, int64_t m, const De
     s.g = ds->g;
     if (s.U1 && (ds->it & 1)) s.U = s.U1;
     const int NT = (P + 15) >> 4;   // column tiles, <= 4
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ci = lane & 15, kr = 4 * (lane >> 4);
     // the lane's column of every tile (tiles past P read column 0, zeroed below)
     ColPtr cp[4];
@@ -447,9 +447,10 @@ __device__ __forceinline__ void gram_direct_body(SrcT<TC> s, int64_t m, const De
     }
     // fast path: every column in the compute type and 16-byte aligned (uniform)
     const bool fast = vec && __all(same);
-    const int64_t ngr = (m + 15) >> 4;
-    const int64_t g0 = (ngr * bid) / nblk, g1 = (ngr * (bid + 1)) / nblk;
-    const int64_t gf = (g1 < (m >> 4)) ? g1 : (m >> 4);   // groups entirely inside [0, m)
+    // groups of 16 rows, grid-strided over the waves: group W + i NW for wave W
+    // (at each step the grid reads one contiguous span of every column)
+    const int64_t ngr = (m + 15) >> 4, nfull = m >> 4;   // groups; those entirely inside [0, m)
+    const int64_t W = (int64_t)bid * 4 + wv, NW = (int64_t)nblk * 4;
     AccT acc[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) acc[q] = AccT{0, 0, 0, 0};
@@ -472,31 +473,31 @@ __device__ __forceinline__ void gram_direct_body(SrcT<TC> s, int64_t m, const De
             for (int q = 0; q < 4; ++q) v[t][q] = live[t] ? v[t][q] : (TC)0;
         }
     };
-    int64_t gstart = g0 + wv;
-    if (fast && gstart < gf) {
+    int64_t gstart = W;
+    if (fast && gstart < nfull) {
         // GD_NB register groups: loads GD_NB - 1 groups ahead (indices clamped to
         // the wave's last full group, so every iteration issues the same loads)
-        const int64_t lastg = gstart + ((gf - 1 - gstart) / 4) * 4;
+        const int64_t lastg = gstart + ((nfull - 1 - gstart) / NW) * NW;
         TC vr[GD_NB][4][4];
 #pragma unroll
-        for (int b = 0; b < GD_NB - 1; ++b) load_fast((gstart + 4 * b < lastg) ? gstart + 4 * b : lastg, vr[b]);
-        for (int64_t gr = gstart;; gr += 4 * GD_NB) {
+        for (int b = 0; b < GD_NB - 1; ++b) load_fast((gstart + NW * b < lastg) ? gstart + NW * b : lastg, vr[b]);
+        for (int64_t gr = gstart;; gr += NW * GD_NB) {
             bool more = true;
 #pragma unroll
             for (int b = 0; b < GD_NB; ++b) {
                 if (more) {
-                    const int64_t ld = gr + 4 * (b + GD_NB - 1);
+                    const int64_t ld = gr + NW * (b + GD_NB - 1);
                     load_fast((ld < lastg) ? ld : lastg, vr[(b + GD_NB - 1) % GD_NB]);
                     mma(vr[b]);
-                    more = gr + 4 * (b + 1) <= lastg;
+                    more = gr + NW * (b + 1) <= lastg;
                 }
             }
             if (!more) break;
         }
-        gstart = lastg + 4;   // the wave's groups past the full ones
+        gstart = lastg + NW;   // the wave's groups past the full ones
     }
     // the rest (a partial last group, or every group off the fast path)
-    for (int64_t gr = gstart; gr < g1; gr += 4) {
+    for (int64_t gr = gstart; gr < ngr; gr += NW) {
         TC v[4][4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -571,7 +572,7 @@ __device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part
     __shared__ double sq[GR_W][64];
     if (merge_halted(ds)) return;
     const int P = sel_count(ds, which_p);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int idx = bid * 64 + lane;
     const int i = idx % pmax, j = idx / pmax;
     const bool live = idx < pmax * pmax && i < P && j < P && i <= j;
@@ -665,12 +666,14 @@ hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax
 
 // ---------------------------------------------------------------------------
 // Tall transform Y = X T (m x pout) with T pin x pout (ld ldt, compute type).
-// Each workgroup stages T once and TALL_ST stages of RB rows of X, producing
+// Each workgroup stages T once and about TALL_ST stages of RB rows of X
+// (grid-strided), producing
 // the output as Y^T tiles = T^T X^T so that each lane's four results are
 // consecutive rows of one output column.
 // ---------------------------------------------------------------------------
 constexpr int TALL_ST = 8;   // row stages per workgroup
 constexpr size_t TALL_T_LDS = 112 * 1024;  // largest T staged in LDS
+constexpr int TALL_DYN_LDS = 160 * 1024;   // dynamic LDS limit of the tall kernels
 
 // Scatter output (SCAT): output columns below `split` go to Yout, column
 // split + j is added to D(:, cmap[j]) (leading dimension ldd); the mapped
@@ -686,7 +689,7 @@ template <typename TC, int ITEMS, bool TG, bool SCAT = false>
 __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in, int sel_out,
                                                int pmax_in, int pmax_out, const TC *__restrict__ T, int ldt,
                                                TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec, int bid,
-                                               TallScatter sc = TallScatter{0, nullptr, nullptr, 0})
+                                               int nbk, int tri, TallScatter sc = TallScatter{0, nullptr, nullptr, 0})
 {
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
@@ -699,10 +702,12 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
     const int PI = (pin + 15) & ~15, PO = (pout + 15) & ~15;
     TC *Xs = reinterpret_cast<TC *>(lds_raw);        // pmax_in x LDSR
     TC *Ts = Xs + pmax_in * LDSR;                    // PI x PO, row k at Ts + k * PO (when !TG)
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar tile loops
+    // row stages bid, bid + nbk, bid + 2 nbk, ...: at each step the nbk
+    // workgroups together read one contiguous span of every column
     const int64_t nst = (m + RB - 1) / RB;
-    const int64_t s0 = (int64_t)bid * TALL_ST;
-    const int64_t s1 = (s0 + TALL_ST < nst) ? s0 + TALL_ST : nst;
+    const int64_t ns = (bid < nst) ? (nst - 1 - bid) / nbk + 1 : 0;   // stages of this workgroup
+    auto stage = [&](int64_t i) { return (int64_t)bid + i * nbk; };
     if (!TG)
         for (int idx = threadIdx.x; idx < PI * PO; idx += 256) {
             const int k = idx / PO, j = idx % PO;
@@ -717,8 +722,10 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
             const TC *xb = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
             if (!TG) {
                 const TC *ta = Ts + (lane >> 4) * PO + jc * 16 + (lane & 15);
-                // PI is a multiple of 16: four MFMAs with their operands loaded together
-                for (int k4 = 0; k4 < PI; k4 += 16) {
+                // PI is a multiple of 16: four MFMAs with their operands loaded together;
+                // with T upper triangular the row tiles past column tile jc are zero
+                const int ke = (tri && 16 * (jc + 1) < PI) ? 16 * (jc + 1) : PI;
+                for (int k4 = 0; k4 < ke; k4 += 16) {
                     TC av[4], xv[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -758,48 +765,52 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
     sb.fast = sa.fast;
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) sb.base[it] = sa.base[it];
+    // stages entirely inside [0, m) on the fast path (the last stage may be partial)
     const int64_t full_end = m / RB;
-    const int64_t e = sa.fast ? ((s1 < full_end) ? s1 : ((full_end > s0) ? full_end : s0)) : s0;
-    if (e > s0) {
-        const int64_t last = e - 1;
-        sa.load_full(s0 * RB);
-        sb.load_full(((s0 + 1 < last) ? s0 + 1 : last) * RB);
-        int64_t sg = s0;
-        for (; sg + 1 < e; sg += 2) {
+    int64_t nf = (bid < full_end) ? (full_end - 1 - bid) / nbk + 1 : 0;
+    if (!sa.fast) nf = 0;
+    if (nf > ns) nf = ns;
+    if (nf > 0) {
+        const int64_t last = nf - 1;
+        sa.load_full(stage(0) * RB);
+        sb.load_full(stage((1 < last) ? 1 : last) * RB);
+        int64_t i = 0;
+        for (; i + 1 < nf; i += 2) {
             __syncthreads();
             sa.store_all(Xs, pin);
             __syncthreads();
-            sa.load_full(((sg + 2 < last) ? sg + 2 : last) * RB);
-            compute(sg);
+            sa.load_full(stage((i + 2 < last) ? i + 2 : last) * RB);
+            compute(stage(i));
             __syncthreads();
             sb.store_all(Xs, pin);
             __syncthreads();
-            sb.load_full(((sg + 3 < last) ? sg + 3 : last) * RB);
-            compute(sg + 1);
+            sb.load_full(stage((i + 3 < last) ? i + 3 : last) * RB);
+            compute(stage(i + 1));
         }
-        if (sg < e) {
+        if (i < nf) {
             __syncthreads();
             sa.store_all(Xs, pin);
             __syncthreads();
-            compute(sg);
+            compute(stage(i));
         }
     }
-    for (int64_t sg = e; sg < s1; ++sg) {
-        sa.load(s, m, sg * RB, pin, vec);
+    for (int64_t i = nf; i < ns; ++i) {
+        sa.load(s, m, stage(i) * RB, pin, vec);
         __syncthreads();
         sa.store(Xs, PI, pin);
         __syncthreads();
-        compute(sg);
+        compute(stage(i));
     }
 }
 
 template <typename TC, int ITEMS, bool TG>
 __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
                                                    int sel_out, int pmax_in, int pmax_out, const TC *__restrict__ T,
-                                                   int ldt, TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec)
+                                                   int ldt, TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec,
+                                                   int tri)
 {
     gemm_tall_body<TC, ITEMS, TG>(s, m, ds, sel_in, sel_out, pmax_in, pmax_out, T, ldt, Yout, Yout1, vec,
-                                  blockIdx.x);
+                                  blockIdx.x, gridDim.x, tri);
 }
 
 template <typename TC, int ITEMS>
@@ -808,7 +819,7 @@ __global__ __launch_bounds__(256) void k_gemm_tall_scatter(SrcT<TC> s, int64_t m
                                                            int ldt, TC *__restrict__ Yout, TallScatter sc, int vec)
 {
     gemm_tall_body<TC, ITEMS, false, true>(s, m, ds, sel_in, sel_out, pmax_in, 0, T, ldt, Yout, nullptr, vec,
-                                           blockIdx.x, sc);
+                                           blockIdx.x, gridDim.x, 0, sc);
 }
 
 template <typename TC, int ITEMS>
@@ -818,12 +829,12 @@ __global__ __launch_bounds__(256) void k_gemm_tall_b(const TallArgs *__restrict_
     if ((int)blockIdx.x >= a.nb || a.ds->done) return;
     gemm_tall_body<TC, ITEMS, false>(make_src<TC>(a.d), a.d.m, a.ds, a.sel_in, a.sel_out, ITEMS * 256 / GRP, a.pout_max,
                                      reinterpret_cast<const TC *>(a.T), a.ldt, reinterpret_cast<TC *>(a.Yout),
-                                     reinterpret_cast<TC *>(a.Yout1), a.vec, blockIdx.x);
+                                     reinterpret_cast<TC *>(a.Yout1), a.vec, blockIdx.x, a.nb, a.tri);
 }
 
 template <typename TC, int ITEMS, bool TG>
 static void tall_launch(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out, int PI, int PO,
-                        const void *T, int32_t ldt, void *Yout, void *Yout1, unsigned nb, hipStream_t st)
+                        const void *T, int32_t ldt, void *Yout, void *Yout1, unsigned nb, int tri, hipStream_t st)
 {
     const SrcT<TC> s = make_src<TC>(d);
     constexpr int CW = ITEMS * 256 / GRP;   // columns of the LDS stage (every item stored)
@@ -831,17 +842,17 @@ static void tall_launch(const GemmDesc &d, const DevState *ds, int32_t which_in,
     static bool attr = false;
     if (lds > 64 * 1024 && !attr) {
         if (hipFuncSetAttribute((const void *)k_gemm_tall<TC, ITEMS, TG>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                160 * 1024) != hipSuccess)
+                                TALL_DYN_LDS) != hipSuccess)
             return;   // the launch below then fails and reports the error
         attr = true;
     }
     hipLaunchKernelGGL((k_gemm_tall<TC, ITEMS, TG>), dim3(nb), dim3(256), lds, st, s, d.m, ds, which_in, which_out,
-                       CW, PO, (const TC *)T, ldt, (TC *)Yout, (TC *)Yout1, (int)vec_ok(s, d.m));
+                       CW, PO, (const TC *)T, ldt, (TC *)Yout, (TC *)Yout1, (int)vec_ok(s, d.m), tri);
 }
 
 hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
                             int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout, void *Yout1,
-                            hipStream_t st)
+                            hipStream_t st, int32_t tri)
 {
     if (pin_max > PMAX_WIDE || pout_max > PMAX_WIDE) return hipErrorInvalidValue;
     ProfScope ps(POD_K_TALL, st);
@@ -851,14 +862,14 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
     const bool wide = PI > 64;
     if (d.prec == POD_F64) {
         const bool tg = (size_t)PI * PO * sizeof(double) > TALL_T_LDS;
-        if (!wide) tall_launch<double, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
-        else if (!tg) tall_launch<double, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
-        else tall_launch<double, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
+        if (!wide) tall_launch<double, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
+        else if (!tg) tall_launch<double, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
+        else tall_launch<double, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
     } else {
         const bool tg = (size_t)PI * PO * sizeof(float) > TALL_T_LDS;
-        if (!wide) tall_launch<float, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
-        else if (!tg) tall_launch<float, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
-        else tall_launch<float, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, st);
+        if (!wide) tall_launch<float, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
+        else if (!tg) tall_launch<float, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
+        else tall_launch<float, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
     }
     return hipGetLastError();
 }
@@ -1093,7 +1104,7 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
             static bool attr = false;
             if (!attr) {
                 if (hipFuncSetAttribute((const void *)k_gemm_tall_scatter<double, ITEMS160>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, TALL_DYN_LDS) != hipSuccess)
                     return hipErrorInvalidValue;
                 attr = true;
             }
@@ -1111,7 +1122,7 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
             static bool attr = false;
             if (!attr) {
                 if (hipFuncSetAttribute((const void *)k_gemm_tall_scatter<float, ITEMS160>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, TALL_DYN_LDS) != hipSuccess)
                     return hipErrorInvalidValue;
                 attr = true;
             }

@@ -174,9 +174,10 @@ hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax
                                   int32_t which_p, double *G, hipStream_t st);
 // Y (m x pout, ld m) = source (m x pin) * T (pin x pout, ld ldt); counts from the device state.
 // With Yout1 set, the output is Yout1 if the device merge count is odd, else Yout.
+// tri: T is upper triangular (T(k, j) = 0 for k > j); the zero tiles are skipped.
 hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
                             int32_t pin_max, int32_t pout_max, const void *T, int32_t ldt, void *Yout, void *Yout1,
-                            hipStream_t st);
+                            hipStream_t st, int32_t tri = 0);
 
 // Per-matrix arguments of the batched launches (device arrays, one entry per
 // matrix; blockIdx.y selects the entry).
@@ -193,6 +194,7 @@ struct TallArgs {
     int32_t sel_in, sel_out, pin_max, pout_max;  // pin_max / pout_max: multiples of 16
     const void *T;
     int32_t ldt, vec, nb;
+    int32_t tri;           // T upper triangular (launch_gemm_tall)
     void *Yout, *Yout1;
 };
 // Batched launches (pmax <= 64 for every matrix; prec uniform).

@@ -359,11 +359,13 @@ __device__ __forceinline__ int sturm_rl(const TriRegs &t, int n, double x)
     const double *ds = t.sde, *e2 = t.sde + 72;
     // Step i has pm1 = p_{i-1} and mc = -e_{i-1}^2 p_{i-2}; it forms the next
     // step's term from p_{i-1} before p_i, so that only one multiply-add per row
-    // waits on its predecessor.  A sign change between p_{i-1} and p_i is the
-    // sign bit of the exclusive or of their high words (a zero of either sign
-    // is fine: either sign gives one change across it and its successor).
+    // waits on its predecessor.  The sign bits of the minors are shifted into
+    // `sg` (one funnel shift per row: sg = sg << 1 | sign(p_i)); after each block
+    // of 8 rows the sign changes between neighbours are counted from it at once
+    // (a zero of either sign is fine: either sign gives one change across it and
+    // its successor).
     double pm1 = 1.0, pm2 = 0.0, mc = 0.0;
-    unsigned cnt = 0;
+    unsigned cnt = 0, sg = 0;   // bit 0: sign of p_{i-1} (p_{-1} = 1 > 0)
     // blocks of 8 rows (the next block's entries loaded ahead); the padded rows
     // past n have d - x > 0 and no coupling, so their minors keep the sign of p_{n-1}
     double dn[8], en[8];
@@ -394,11 +396,14 @@ __device__ __forceinline__ int sturm_rl(const TriRegs &t, int n, double x)
                 mn = ldexp(mn, -ex);
                 pm1 = ldexp(pm1, -ex);
             }
-            cnt += ((unsigned)(__double2hiint(p) ^ __double2hiint(pm1))) >> 31;
+            sg = __builtin_amdgcn_alignbit(sg, (unsigned)__double2hiint(p), 31);
             pm2 = pm1;
             pm1 = p;
             mc = mn;
         }
+        // bits 8..0 of sg: the signs of p_{b-1}, p_b, ..., p_{b+7}
+        cnt += __popc((sg ^ (sg >> 1)) & 0xFFu);
+        sg &= 1u;
     }
     return (int)cnt;
 }

@@ -548,11 +548,11 @@ __device__ __forceinline__ double merge_sin_rl(const SmallArgs &a, const double 
                 sin_max = 0.0;
             } else {
                 // F = B^T B (kk x kk), B = U_R(kk:p, 0:kk)
-                double r[8];
                 rl_mm64([&](int i, int q) { return (i < kk && q < br) ? Y[kk + q + i * p] : 0.0; },
                         [&](int q, int j) { return (q < br && j < kk) ? Y[kk + q + j * p] : 0.0; },
                         [&](int i, int j, double v) { bufB[i * RL_LD + j] = v; });
                 __syncthreads();
+                double r[8];
                 rl_load_rows(r, bufB);
                 __syncthreads();
                 rl_tridiag(r, kk, sd, se, stau, bufB, Pp);
