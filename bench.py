@@ -45,9 +45,9 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-merges", type=int, default=12, help="oracle merges timed for the CPU baseline sample")
-    ap.add_argument("--workload", choices=["c2", "c5", "c4"], default="c2",
-                    help="c2: travelling waves 200k x 2k (default); c5: 64-matrix batch, forward + gradient; "
-                         "c4: Alg. 3 over pinned host blocks of 2M x 512")
+    ap.add_argument("--workload", choices=["c2", "c3", "c5", "c4"], default="c2",
+                    help="c2: travelling waves 200k x 2k (default); c3: travelling waves 1M x 4k, k=50, c=100; "
+                         "c5: 64-matrix batch, forward + gradient; c4: Alg. 3 over pinned host blocks of 2M x 512")
     ap.add_argument("--c5-count", type=int, default=64)
     ap.add_argument("--c4-blocks", type=int, default=8, help="blocks of 512 columns (32: the full 16,000)")
     return ap.parse_args()
@@ -333,14 +333,18 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    m, n, k, c = args.m, args.n, args.k, args.c
-    p = k + c
+    if args.workload == "c3":
+        # 1,000,000 x 4,000 FP32 (16 GB), 200 modes, a_j = j^-1.2; k = 50, c = 100
+        m, n, k, c, modes, alpha, dseed, sseed = 1_000_000, 4_000, 50, 100, 200, 1.2, 1003, 2003
+    else:
+        m, n, k, c, modes, alpha, dseed, sseed = args.m, args.n, args.k, args.c, 60, 1.5, 1002, 2002
+    p = k + min(c, n)
     t_gen = time.perf_counter()
-    At = snapgen.travelling_waves(m, n, 60, 1.5, 1e-3, seed=1002, device="cuda")
+    At = snapgen.travelling_waves(m, n, modes, alpha, 1e-3, seed=dseed, device="cuda")
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     A = At.T
-    kw = dict(k=k, c=c, seed=2002, theta_tol=1e-5)
+    kw = dict(k=k, c=c, seed=sseed, theta_tol=1e-5)
     info = {}
 
     def step(precision):
@@ -427,7 +431,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"travelling waves {m}x{n} FP32, 60 modes a_j=j^-1.5, noise var 1e-3, "
+        "config": {"workload": f"travelling waves {m}x{n} FP32, {modes} modes a_j=j^-{alpha}, noise var 1e-3, "
                                f"rows centred; k={k}, c={c}, theta_tol=1e-5",
                    "m": m, "n": n, "k": k, "c": c},
         "roofline": roof,
@@ -441,7 +445,10 @@ def main():
         "adjoint_included": False,
         "gen_s": round(t_gen, 2),
     }
-    if not args.no_cpu_baseline:
+    if args.workload == "c3":
+        # the oracle's FP64 copy of a 1M x 4k matrix alone is 32 GB of host memory
+        out["cpu_baseline"] = None
+    elif not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(At, m, n, k, c, iters, args.cpu_merges)
     print(json.dumps(out), flush=True)
 

@@ -374,6 +374,8 @@ __device__ __forceinline__ int sturm_rl(const TriRegs &t, int n, double x)
         dn[q] = ds[q];
         en[q] = e2[q];
     }
+    // (unrolled: the next block's loads are issued a block ahead of their use)
+#pragma unroll
     for (int b = 0; b < 64; b += 8) {
         if (b >= n) break;
         double dc[8], ec[8];
