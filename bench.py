@@ -48,12 +48,14 @@ def parse():
     ap.add_argument("--workload", choices=["c2", "c3", "c5", "c4"], default="c2",
                     help="c2: travelling waves 200k x 2k (default); c3: travelling waves 1M x 4k, k=50, c=100; "
                          "c5: 64-matrix batch, forward + gradient; c4: Alg. 3 over pinned host blocks of 2M x 512")
+    ap.add_argument("--precision", choices=["f32", "bf16"], default=None,
+                    help="timed merge path: FP32 matrix cores or split-BF16 (default: f32 for c2, bf16 for c3)")
     ap.add_argument("--c5-count", type=int, default=64)
     ap.add_argument("--c4-blocks", type=int, default=8, help="blocks of 512 columns (32: the full 16,000)")
     return ap.parse_args()
 
 
-def kernel_work(cls, m, n, k, c, p, r, launches):
+def kernel_work(cls, m, n, k, c, p, r, launches, bf16=False):
     """Algorithmic work of one launch of a kernel class, averaged over the
     launches of one step: (bound, amount, unit, hbm_bytes) with amount in
     bytes or flops.
@@ -71,8 +73,14 @@ def kernel_work(cls, m, n, k, c, p, r, launches):
         b = m * n * 4 / max(launches, 1)
         return "hbm", b, "B", b
     if cls == "gram":
+        if bf16:
+            # six BF16 products per FP32-accurate one: the matrix-core roof is
+            # 2.5 PFLOP/s / 6 = 417 TFLOP/s, ridge 52 flop/B > (p+1)/4: HBM bound
+            return "hbm", m * p * 4, "B", m * p * 4
         return "mfma", m * p * (p + 1), "flop", m * p * 4
     if cls == "tall":
+        if bf16:
+            return "hbm", m * p * 4 + m * (p + r) * 2, "B", m * p * 4 + m * (p + r) * 2
         return "mfma", m * p * (p + r), "flop", m * p * 4 + m * (p + r) * 2
     if cls == "svd":
         return "alu", (8.0 / 3.0) * p ** 3 + 3.0 * p * p * r, "flop", 0
@@ -339,6 +347,10 @@ def main():
     else:
         m, n, k, c, modes, alpha, dseed, sseed = args.m, args.n, args.k, args.c, 60, 1.5, 1002, 2002
     p = k + min(c, n)
+    prec_name = args.precision or ("bf16" if args.workload == "c3" else "f32")
+    main_prec = pod.POD_BF16_REFINE if prec_name == "bf16" else pod.POD_F32
+    other_prec = pod.POD_F32 if prec_name == "bf16" else pod.POD_BF16_REFINE
+    bf16 = prec_name == "bf16"
     t_gen = time.perf_counter()
     At = snapgen.travelling_waves(m, n, modes, alpha, 1e-3, seed=dseed, device="cuda")
     torch.cuda.synchronize()
@@ -357,12 +369,12 @@ def main():
 
     # warm-up, then one step per kernel class with that class timed by HIP events
     for _ in range(max(args.warmup, 1)):
-        step(pod.POD_F32)
+        step(main_prec)
     torch.cuda.synchronize()
     per_class = {}
     for cls in CLASSES:
         pod.profile_enable(cls)
-        step(pod.POD_F32)
+        step(main_prec)
         torch.cuda.synchronize()
         launches, ms = pod.profile_read()
         per_class[cls] = (launches, ms)
@@ -374,7 +386,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(pod.POD_F32)
+        step(main_prec)
     torch.cuda.synchronize()
     sec32 = (time.perf_counter() - t0) / args.steps
     launches, dom_ms = pod.profile_read()
@@ -391,12 +403,22 @@ def main():
     sec64 = (time.perf_counter() - t0) / args.fp64_steps
     iters64 = info["iters"]
 
+    # the other reduced-precision merge path (split-BF16 or FP32)
+    step(other_prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.fp64_steps):
+        step(other_prec)
+    torch.cuda.synchronize()
+    sec_other = (time.perf_counter() - t0) / args.fp64_steps
+    iters_other = info["iters"]
+
     # roofline of the dominant kernel class (measured live in the timed steps);
     # the device-driven loop enqueues whole chunks of iterations, and the
     # launches after the stop return at once: count the launches that merged
     per_step_launches = real_launches(dominant, launches / args.steps, iters)
     avg_s = dom_ms / 1e3 / max(per_step_launches * args.steps, 1)
-    bound, amount, unit, hb = kernel_work(dominant, m, n, k, c, p, k, per_step_launches)
+    bound, amount, unit, hb = kernel_work(dominant, m, n, k, c, p, k, per_step_launches, bf16)
     roof = roofline_entry(bound, amount, avg_s, hb)
     roof["traffic"] = measured_traffic(dominant)
     roof.update({"kernel_class": dominant, "avg_launch_us": round(avg_s * 1e6, 2),
@@ -405,7 +427,7 @@ def main():
     others = {}
     for cls, (ln, ms) in per_class.items():
         ln = real_launches(cls, ln, iters)
-        b2, a2, _, h2 = kernel_work(cls, m, n, k, c, p, k, ln)
+        b2, a2, _, h2 = kernel_work(cls, m, n, k, c, p, k, ln, bf16)
         if b2 is None or ln == 0:
             continue
         e = roofline_entry(b2, a2, ms / 1e3 / ln, h2)
@@ -421,7 +443,8 @@ def main():
     out = {
         "metric": METRIC,
         "value": round(sec32 * 1e3, 4),
-        "unit": "ms per time-to-k-modes (FP32 MFMA merge path)",
+        "unit": ("ms per time-to-k-modes (split-BF16 MFMA merge path)" if bf16
+                 else "ms per time-to-k-modes (FP32 MFMA merge path)"),
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -429,7 +452,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if bf16 else "f32",
         "data": "synthetic",
         "config": {"workload": f"travelling waves {m}x{n} FP32, {modes} modes a_j=j^-{alpha}, noise var 1e-3, "
                                f"rows centred; k={k}, c={c}, theta_tol=1e-5",
@@ -440,6 +463,9 @@ def main():
         "fp64_path_ms": round(sec64 * 1e3, 4),
         "fp64_iters": iters64,
         "speedup_vs_fp64_path": round(sec64 / sec32, 3),
+        ("f32_path_ms" if bf16 else "bf16_path_ms"): round(sec_other * 1e3, 4),
+        ("f32_iters" if bf16 else "bf16_iters"): iters_other,
+        "merge_precision": prec_name,
         "step_hbm_gbs": round(step_bytes / sec32 / 1e9, 1),
         "kernel_ms_per_step": {kc: round(v[1], 3) for kc, v in per_class.items()},
         "adjoint_included": False,

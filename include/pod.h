@@ -41,7 +41,16 @@ typedef enum {
 } pod_status;
 
 /* Arithmetic of the merge / projection GEMMs.  The Cholesky factors and the
- * small SVDs are FP64 in every path. */
+ * small SVDs are FP64 in every path.
+ *   POD_F64          FP64 matrix cores, FP64 basis.
+ *   POD_F32          FP32 matrix cores, FP32 basis (A stored FP32).
+ *   POD_BF16_REFINE  the merge's m-pass products (both CholeskyQR Grams,
+ *                    Q1 = X0 T1, U_new = Q1 Z2) on BF16 matrix cores with a
+ *                    three-term split of every FP32 operand and FP32
+ *                    accumulation (FP32-accurate: the span of the merge is not
+ *                    moved by BF16 rounding); the final projection and
+ *                    Rayleigh-Ritz rotation in FP32.  A stored FP32; single
+ *                    runs and Alg. 3 only (the batch rejects it). */
 typedef enum { POD_F64 = 0, POD_F32 = 1, POD_BF16_REFINE = 2 } pod_precision;
 
 /* Column sampling from the second iteration on (first iteration: always

@@ -150,7 +150,7 @@ pod_status reverse_merges(pod_ctx *ctx, void *dA)
         hipLaunchKernelGGL(k_adj_state, dim3(1), dim3(1), 0, ctx->st, ctx->dsb, rs, g);
         A_HIP(hipGetLastError());
         GemmDesc gd;
-        gd.prec = p.precision;
+        gd.prec = (p.precision == POD_F64) ? POD_F64 : POD_F32;
         gd.a_dtype = p.a_dtype;
         gd.m = p.m;
         gd.U = (const unsigned char *)ctx->ckU + (size_t)t * p.m * ctx->r * esz;

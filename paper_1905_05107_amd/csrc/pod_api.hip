@@ -53,7 +53,7 @@ void free_all(pod_ctx *ctx)
                     ctx->rho,  ctx->Vt,   ctx->wr,    ctx->rows, ctx->rcnt, ctx->row_log, ctx->rcnt_log,
                     ctx->ws,   ctx->ckU,  ctx->ckS,   ctx->ckR,  ctx->ckMeta, ctx->dsb, ctx->partb, ctx->Gext,
                     ctx->adj_ws, ctx->sbar[0], ctx->sbar[1], ctx->lossp, ctx->Wt, ctx->Ubar[0], ctx->Ubar[1],
-                    ctx->sin_log};
+                    ctx->sin_log, ctx->tsplit};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -73,6 +73,7 @@ GemmDesc gather_desc(pod_ctx *ctx)
     d.gather = 1;
     d.guard = 1;
     d.Z = nullptr;
+    d.tsplit = ctx->tsplit;
     return d;
 }
 
@@ -263,8 +264,8 @@ pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
     const pod_params &p = *prm;
     if (p.m < 1 || p.n < 1 || p.lda < p.m || p.n > 0x7fffffff || p.m > ((int64_t)1 << 40)) return POD_EINVAL;
     if (p.a_dtype != POD_F64 && p.a_dtype != POD_F32) return POD_EINVAL;
-    if (p.precision != POD_F64 && p.precision != POD_F32) return POD_EINVAL;
-    if (p.precision == POD_F32 && p.a_dtype == POD_F64) return POD_EINVAL;
+    if (p.precision != POD_F64 && p.precision != POD_F32 && p.precision != POD_BF16_REFINE) return POD_EINVAL;
+    if (p.precision != POD_F64 && p.a_dtype == POD_F64) return POD_EINVAL;
     const int32_t r = p.r ? p.r : p.k;
     if (p.k < 1 || r < p.k || p.c < 1 || p.c > 1024 || p.max_iter < 1) return POD_EINVAL;
     if (p.w < 0 || p.w > 1024 || p.r_update < 0) return POD_EINVAL;
@@ -317,6 +318,7 @@ pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
     ALLOC(ctx->R2, double, pmax * pmax);
     ALLOC(ctx->work, double, pmax * pmax);
     ALLOC(ctx->Tc, unsigned char, (size_t)pmax * pmax * ctx->esz);
+    if (p.precision == POD_BF16_REFINE) ALLOC(ctx->tsplit, unsigned char, TSPLIT_BYTES);
     ALLOC(ctx->Y, unsigned char, (size_t)m * pmax * ctx->esz);
     ALLOC(ctx->Bpart, double, (size_t)ctx->nsplit * r * n);
     ALLOC(ctx->B, double, (size_t)r * n);
@@ -580,6 +582,7 @@ pod_status pod::ctx_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *
     ra.ds = ctx->ds;
     POD_HIP(launch_rr_small(ra, ctx->st));
     GemmDesc ud = plain_desc(ctx, ctx->U[ctx->cur]);
+    ud.prec = (p.precision == POD_F64) ? POD_F64 : POD_F32;   // the Rayleigh-Ritz rotation in FP32
     ud.guard = 0;
     POD_HIP(launch_gemm_tall(ud, ctx->ds, rs, k, rs, k, ctx->Zc, rs, U_out, nullptr, ctx->st));
     POD_HIP(hipMemcpyAsync(sigma_out, ctx->sigB, sizeof(double) * k, hipMemcpyDeviceToDevice, ctx->st));

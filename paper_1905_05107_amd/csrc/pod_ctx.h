@@ -28,6 +28,7 @@ struct pod_ctx {
     double *part = nullptr, *G = nullptr, *R1 = nullptr, *R2 = nullptr, *work = nullptr;
     double *ws = nullptr;    // small-kernel matrices when pmax > 64
     void *Tc = nullptr, *Y = nullptr;
+    void *tsplit = nullptr;   // POD_BF16_REFINE: split right factor of the tall transform
     int32_t nblk = 0;
     double *Bpart = nullptr, *B = nullptr, *GB = nullptr, *UB = nullptr, *sigB = nullptr;
     void *Zc = nullptr;

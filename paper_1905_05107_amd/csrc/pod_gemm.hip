@@ -618,6 +618,352 @@ __global__ __launch_bounds__(64 * GR_W) void k_gram_reduce_b(const GramArgs *__r
 }
 
 
+// ---------------------------------------------------------------------------
+// BF16 matrix cores with a three-term split (POD_BF16_REFINE).  Each FP32
+// operand x is written as x = h + d + l with h = bf16(x), d = bf16(x - h),
+// l = bf16(x - h - d) (round to nearest even; both differences are exact in
+// FP32, and the three terms carry the 24 significand bits of x).  A product
+// x y is taken as hh' + hd' + dh' + hl' + lh' + dd' on
+// v_mfma_f32_16x16x32_bf16: each bf16 product is exact and the sum is
+// accumulated in FP32; the dropped terms dl' + ld' + ll' are below 2^-23 |x y|,
+// the size of one FP32 rounding.  The Grams, Q1 = X0 T1 and U_new = Q1 Z2 thus
+// keep FP32 accuracy (a plain BF16 rounding of X0 would move the span of the
+// merge by about 2^-9 sigma_1 / gap) on 6/16 of the FP32 matrix-core cycles.
+//
+// Operands of the 16x16x32 instruction: lane l supplies A[l % 16][8 (l / 16) + t]
+// and B[8 (l / 16) + t][l % 16], t = 0..7, as eight packed bf16; its four
+// results are D[4 (l / 16) + v][l % 16] (acc_row<float>).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &d, __bf16 &l)
+{
+    h = (__bf16)x;
+    const float r1 = x - (float)h;
+    d = (__bf16)r1;
+    l = (__bf16)(r1 - (float)d);
+}
+
+__device__ __forceinline__ v4f mfma_bf16(const bf16x8 &a, const bf16x8 &b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// c += (ah + ad + al)(bh + bd + bl) without the three smallest cross terms
+__device__ __forceinline__ v4f mfma_split(const bf16x8 &ah, const bf16x8 &ad, const bf16x8 &al, const bf16x8 &bh,
+                                          const bf16x8 &bd, const bf16x8 &bl, v4f c)
+{
+    c = mfma_bf16(ad, bd, c);
+    c = mfma_bf16(al, bh, c);
+    c = mfma_bf16(ah, bl, c);
+    c = mfma_bf16(ad, bh, c);
+    c = mfma_bf16(ah, bd, c);
+    return mfma_bf16(ah, bh, c);
+}
+
+// Partial Grams on the split operands.  The row stage is split while it is
+// written to LDS (each value once per workgroup), column-major per term with
+// a column stride of BCS bf16 (16-byte aligned operand reads).  Per stage
+// every wave reads the three terms of all column tiles once and takes the
+// tile pairs (I <= J) whose number is congruent to its index mod 4; pair
+// numbers, operand registers and accumulators are compile-time indices.
+constexpr int BCS = 40;
+
+template <int BT, int ITEMS>
+__device__ __forceinline__ void gram_bf16_body(SrcT<float> s, int64_t m, const DevState *ds, int which_p, int pmax,
+                                               double *__restrict__ part, int nblk, int vec, int bid)
+{
+    constexpr int CW = ITEMS * 256 / GRP;   // staged columns, 16 BT
+    constexpr int NSLOT = (BT * (BT + 1) / 2 + 3) / 4;
+    static_assert(CW == 16 * BT, "stage width");
+    extern __shared__ unsigned char lds_raw[];
+    __bf16 *Xb = reinterpret_cast<__bf16 *>(lds_raw);   // [term][column][row]
+    if (s.guard && merge_halted(ds)) return;
+    const int P = sel_count(ds, which_p);
+    s.rs = ds->rs;
+    s.g = ds->g;
+    if (s.U1 && (ds->it & 1)) s.U = s.U1;
+    const int NT16 = (P + 15) >> 4;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nst = (m + RB - 1) / RB;
+    const int64_t s0 = (nst * bid) / nblk, s1 = (nst * (bid + 1)) / nblk;
+    v4f acc[NSLOT];
+#pragma unroll
+    for (int q = 0; q < NSLOT; ++q) acc[q] = v4f{0, 0, 0, 0};
+    auto store = [&](const Stage<float, ITEMS> &st) {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int idx = threadIdx.x + 256 * it;
+            const int c = idx / GRP, g = idx % GRP;
+            bf16x4 h, d, l;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                __bf16 a0, a1, a2;
+                split3((c < P) ? st.v[it][q] : 0.0f, a0, a1, a2);
+                h[q] = a0;
+                d[q] = a1;
+                l[q] = a2;
+            }
+            __bf16 *o = Xb + c * BCS + 4 * g;
+            *reinterpret_cast<bf16x4 *>(o) = h;
+            *reinterpret_cast<bf16x4 *>(o + CW * BCS) = d;
+            *reinterpret_cast<bf16x4 *>(o + 2 * CW * BCS) = l;
+        }
+    };
+    auto compute = [&]() {
+        bf16x8 oh[BT], od[BT], ol[BT];
+#pragma unroll
+        for (int t = 0; t < BT; ++t) {
+            if (t < NT16) {
+                const __bf16 *b = Xb + (16 * t + (lane & 15)) * BCS + 8 * (lane >> 4);
+                oh[t] = *reinterpret_cast<const bf16x8 *>(b);
+                od[t] = *reinterpret_cast<const bf16x8 *>(b + CW * BCS);
+                ol[t] = *reinterpret_cast<const bf16x8 *>(b + 2 * CW * BCS);
+            }
+        }
+#pragma unroll
+        for (int I = 0; I < BT; ++I) {
+#pragma unroll
+            for (int J = I; J < BT; ++J) {
+                const int pr = I * BT - I * (I - 1) / 2 + (J - I);
+                if ((pr & 3) == wv && J < NT16)
+                    acc[pr >> 2] = mfma_split(oh[I], od[I], ol[I], oh[J], od[J], ol[J], acc[pr >> 2]);
+            }
+        }
+    };
+    Stage<float, ITEMS> sa, sb;
+    sa.prepare(s, m, P, vec);
+    sb.fast = sa.fast;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) sb.base[it] = sa.base[it];
+    const int64_t full_end = m / RB;
+    const int64_t e = sa.fast ? ((s1 < full_end) ? s1 : ((full_end > s0) ? full_end : s0)) : s0;
+    if (e > s0) {
+        const int64_t last = e - 1;
+        sa.load_full(s0 * RB);
+        sb.load_full(((s0 + 1 < last) ? s0 + 1 : last) * RB);
+        int64_t sg = s0;
+        for (; sg + 1 < e; sg += 2) {
+            __syncthreads();
+            store(sa);
+            __syncthreads();
+            sa.load_full(((sg + 2 < last) ? sg + 2 : last) * RB);
+            compute();
+            __syncthreads();
+            store(sb);
+            __syncthreads();
+            sb.load_full(((sg + 3 < last) ? sg + 3 : last) * RB);
+            compute();
+        }
+        if (sg < e) {
+            __syncthreads();
+            store(sa);
+            __syncthreads();
+            compute();
+        }
+    }
+    for (int64_t sg = e; sg < s1; ++sg) {
+        sa.load(s, m, sg * RB, P, vec);
+        __syncthreads();
+        store(sa);
+        __syncthreads();
+        compute();
+    }
+    double *pb = part + (int64_t)bid * pmax * pmax;
+#pragma unroll
+    for (int I = 0; I < BT; ++I) {
+#pragma unroll
+        for (int J = I; J < BT; ++J) {
+            const int pr = I * BT - I * (I - 1) / 2 + (J - I);
+            if ((pr & 3) != wv || J >= NT16) continue;
+            const int j = J * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = I * 16 + acc_row<float>(lane, v);
+                const double x = (double)acc[pr >> 2][v];
+                if (I < J || i <= j) {
+                    pb[i + (int64_t)j * pmax] = x;
+                    pb[j + (int64_t)i * pmax] = x;
+                }
+            }
+        }
+    }
+}
+
+template <int BT, int ITEMS>
+__global__ __launch_bounds__(256) void k_gram_bf16(SrcT<float> s, int64_t m, const DevState *ds, int which_p, int pmax,
+                                                   double *__restrict__ part, int nblk, int vec)
+{
+    gram_bf16_body<BT, ITEMS>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
+}
+
+// The three terms of T (pin x pout, ld ldt; counts from the device state),
+// transposed: Tb[term][j][k] (JP x KP per term, zero outside pin x pout), so
+// that one 16-byte read gives a lane its eight k values of a B operand.
+__global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ T, int ldt, const DevState *ds, int sel_in,
+                                                 int sel_out, int KP, int JP, __bf16 *__restrict__ Tb, int guard)
+{
+    if (guard && merge_halted(ds)) return;
+    const int pin = sel_count(ds, sel_in), pout = sel_count(ds, sel_out);
+    const int tot = JP * KP;
+    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < tot; idx += gridDim.x * 256) {
+        const int j = idx / KP, k = idx % KP;
+        const float x = (k < pin && j < pout) ? T[k + (int64_t)j * ldt] : 0.0f;
+        __bf16 h, d, l;
+        split3(x, h, d, l);
+        Tb[idx] = h;
+        Tb[idx + tot] = d;
+        Tb[idx + 2 * tot] = l;
+    }
+}
+
+// Tall transform Y = X T on the split operands.  The row stage is split and
+// transposed while it is written to LDS (row-major per term, row stride
+// CW + 8 bf16), so an A operand (16 rows x 8 consecutive k) is one 16-byte
+// read; the B operands come from Tb (L2 resident).  Wave w owns the output
+// column tiles w, w + 4, w + 8 of both 16-row blocks of a stage; each lane
+// stores four consecutive rows of one output column.
+template <int ITEMS>
+__device__ __forceinline__ void gemm_tall_bf16_body(SrcT<float> s, int64_t m, const DevState *ds, int sel_in,
+                                                    int sel_out, const __bf16 *__restrict__ Tb, int KP, int JP,
+                                                    float *__restrict__ Yout, float *__restrict__ Yout1, int vec,
+                                                    int vout, int bid, int nbk, int tri)
+{
+    constexpr int CW = ITEMS * 256 / GRP;   // staged columns (k extent)
+    constexpr int RS = CW + 8;
+    extern __shared__ unsigned char lds_raw[];
+    __bf16 *Xr = reinterpret_cast<__bf16 *>(lds_raw);   // [term][row][k]
+    if (s.guard && merge_halted(ds)) return;
+    if (Yout1 && (ds->it & 1)) Yout = Yout1;
+    const int pin = sel_count(ds, sel_in), pout = sel_count(ds, sel_out);
+    s.rs = ds->rs;
+    s.g = ds->g;
+    if (s.U1 && (ds->it & 1)) s.U = s.U1;
+    const int KE = (pin + 31) & ~31;
+    const int NJ = (pout + 15) >> 4;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nst = (m + RB - 1) / RB;
+    const int64_t ns = (bid < nst) ? (nst - 1 - bid) / nbk + 1 : 0;
+    auto stage = [&](int64_t i) { return (int64_t)bid + i * nbk; };
+    const int64_t tsz = (int64_t)JP * KP;
+    auto store = [&](const Stage<float, ITEMS> &st) {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int idx = threadIdx.x + 256 * it;
+            const int c = idx / GRP, g = idx % GRP;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                __bf16 h, d, l;
+                split3((c < pin) ? st.v[it][q] : 0.0f, h, d, l);
+                __bf16 *o = Xr + (4 * g + q) * RS + c;
+                o[0] = h;
+                o[RB * RS] = d;
+                o[2 * RB * RS] = l;
+            }
+        }
+    };
+    auto compute = [&](int64_t sg) {
+        v4f acc[2][3];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl) acc[rb][sl] = v4f{0, 0, 0, 0};
+        for (int k0 = 0; k0 < KE; k0 += 32) {
+            bf16x8 ah[2], ad[2], al[2];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const __bf16 *b = Xr + (16 * rb + (lane & 15)) * RS + k0 + 8 * (lane >> 4);
+                ah[rb] = *reinterpret_cast<const bf16x8 *>(b);
+                ad[rb] = *reinterpret_cast<const bf16x8 *>(b + RB * RS);
+                al[rb] = *reinterpret_cast<const bf16x8 *>(b + 2 * RB * RS);
+            }
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl) {
+                const int jc = wv + 4 * sl;
+                // with T upper triangular the k steps past column tile jc are zero
+                if (jc < NJ && !(tri && k0 >= 16 * (jc + 1))) {
+                    const __bf16 *tb = Tb + (int64_t)(16 * jc + (lane & 15)) * KP + k0 + 8 * (lane >> 4);
+                    const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(tb);
+                    const bf16x8 bd = *reinterpret_cast<const bf16x8 *>(tb + tsz);
+                    const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(tb + 2 * tsz);
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+                        acc[rb][sl] = mfma_split(ah[rb], ad[rb], al[rb], bh, bd, bl, acc[rb][sl]);
+                }
+            }
+        }
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) {
+            const int jc = wv + 4 * sl;
+            const int col = 16 * jc + (lane & 15);
+            if (jc >= NJ || col >= pout) continue;
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const int64_t row0 = sg * RB + 16 * rb + 4 * (lane >> 4);
+                float *y = Yout + (int64_t)col * m + row0;
+                if (vout && row0 + 4 <= m) {
+                    *reinterpret_cast<f32x4 *>(y) = acc[rb][sl];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (row0 + v < m) y[v] = acc[rb][sl][v];
+                }
+            }
+        }
+    };
+    Stage<float, ITEMS> sa, sb;
+    sa.prepare(s, m, pin, vec);
+    sb.fast = sa.fast;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) sb.base[it] = sa.base[it];
+    const int64_t full_end = m / RB;
+    int64_t nf = (bid < full_end) ? (full_end - 1 - bid) / nbk + 1 : 0;
+    if (!sa.fast) nf = 0;
+    if (nf > ns) nf = ns;
+    if (nf > 0) {
+        const int64_t last = nf - 1;
+        sa.load_full(stage(0) * RB);
+        sb.load_full(stage((1 < last) ? 1 : last) * RB);
+        int64_t i = 0;
+        for (; i + 1 < nf; i += 2) {
+            __syncthreads();
+            store(sa);
+            __syncthreads();
+            sa.load_full(stage((i + 2 < last) ? i + 2 : last) * RB);
+            compute(stage(i));
+            __syncthreads();
+            store(sb);
+            __syncthreads();
+            sb.load_full(stage((i + 3 < last) ? i + 3 : last) * RB);
+            compute(stage(i + 1));
+        }
+        if (i < nf) {
+            __syncthreads();
+            store(sa);
+            __syncthreads();
+            compute(stage(i));
+        }
+    }
+    for (int64_t i = nf; i < ns; ++i) {
+        sa.load(s, m, stage(i) * RB, pin, vec);
+        __syncthreads();
+        store(sa);
+        __syncthreads();
+        compute(stage(i));
+    }
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(256) void k_gemm_tall_bf16(SrcT<float> s, int64_t m, const DevState *ds, int sel_in,
+                                                        int sel_out, const __bf16 *__restrict__ Tb, int KP, int JP,
+                                                        float *__restrict__ Yout, float *__restrict__ Yout1, int vec,
+                                                        int vout, int tri)
+{
+    gemm_tall_bf16_body<ITEMS>(s, m, ds, sel_in, sel_out, Tb, KP, JP, Yout, Yout1, vec, vout, blockIdx.x, gridDim.x,
+                               tri);
+}
+
 template <typename TC, int MAXPW, int ITEMS>
 static void gram_launch(const GemmDesc &d, const DevState *ds, int32_t which_p, int32_t pmax, double *part,
                         int32_t nblk, hipStream_t st)
@@ -635,7 +981,17 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
     if (pmax > PMAX_WIDE) return hipErrorInvalidValue;
     ProfScope ps(POD_K_GRAM, st);
     const bool wide = pmax > 64;
-    if (d.prec == POD_F64) {
+    if (d.prec == POD_BF16_REFINE) {
+        if (d.a_dtype != POD_F32) return hipErrorInvalidValue;
+        const SrcT<float> s = make_src<float>(d);
+        const int vec = (int)vec_ok(s, d.m);
+        if (wide)
+            hipLaunchKernelGGL((k_gram_bf16<10, ITEMS160>), dim3(nblk), dim3(256), 3 * 160 * BCS * sizeof(__bf16), st, s,
+                               d.m, ds, which_p, pmax, part, nblk, vec);
+        else
+            hipLaunchKernelGGL((k_gram_bf16<4, ITEMS64>), dim3(nblk), dim3(256), 3 * 64 * BCS * sizeof(__bf16), st, s,
+                               d.m, ds, which_p, pmax, part, nblk, vec);
+    } else if (d.prec == POD_F64) {
         if (wide) {
             gram_launch<double, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
         } else {
@@ -860,7 +1216,24 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
     const unsigned nb = (unsigned)((nst + TALL_ST - 1) / TALL_ST);
     const int PI = (pin_max + 15) & ~15, PO = (pout_max + 15) & ~15;
     const bool wide = PI > 64;
-    if (d.prec == POD_F64) {
+    if (d.prec == POD_BF16_REFINE) {
+        if (d.a_dtype != POD_F32 || !d.tsplit) return hipErrorInvalidValue;
+        const int KP = (pin_max + 31) & ~31, JP = PO;
+        __bf16 *Tb = reinterpret_cast<__bf16 *>(d.tsplit);
+        hipLaunchKernelGGL(k_split_t, dim3((JP * KP + 255) / 256), dim3(256), 0, st, (const float *)T, ldt, ds,
+                           which_in, which_out, KP, JP, Tb, d.guard);
+        const SrcT<float> s = make_src<float>(d);
+        const int vec = (int)vec_ok(s, d.m);
+        const int vout = (d.m % 4 == 0) && ((uintptr_t)Yout % 16 == 0) && ((uintptr_t)Yout1 % 16 == 0);
+        if (!wide)
+            hipLaunchKernelGGL((k_gemm_tall_bf16<ITEMS64>), dim3(nb), dim3(256), 3 * RB * (64 + 8) * sizeof(__bf16), st,
+                               s, d.m, ds, which_in, which_out, (const __bf16 *)Tb, KP, JP, (float *)Yout,
+                               (float *)Yout1, vec, vout, tri);
+        else
+            hipLaunchKernelGGL((k_gemm_tall_bf16<ITEMS160>), dim3(nb), dim3(256), 3 * RB * (160 + 8) * sizeof(__bf16),
+                               st, s, d.m, ds, which_in, which_out, (const __bf16 *)Tb, KP, JP, (float *)Yout,
+                               (float *)Yout1, vec, vout, tri);
+    } else if (d.prec == POD_F64) {
         const bool tg = (size_t)PI * PO * sizeof(double) > TALL_T_LDS;
         if (!wide) tall_launch<double, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
         else if (!tg) tall_launch<double, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);

@@ -152,7 +152,7 @@ hipError_t launch_draw_rows(const RowDrawArgs &a, hipStream_t st);
 hipError_t launch_basis_state(DevState *ds, int32_t rb, int32_t r, int32_t first, int32_t *cols, hipStream_t st);
 
 struct GemmDesc {
-    int32_t prec;         // POD_F64 or POD_F32 (compute type)
+    int32_t prec;         // POD_F64, POD_F32 or POD_BF16_REFINE (FP32 compute type, split-BF16 matrix cores)
     int32_t a_dtype;      // storage of A
     int64_t m;
     const void *U;        // basis (compute type), ld = m
@@ -165,7 +165,11 @@ struct GemmDesc {
     int32_t guard;        // 1: skip when the pending draw found S exhausted
     const void *Z;        // nullable: gathered source extended to [U | A(:, cols) | Z] (compute type, ld m),
                           // the A block being ds->g columns wide
+    void *tsplit = nullptr;  // POD_BF16_REFINE: workspace for the split right factor of the tall
+                             // transform (TSPLIT_BYTES)
 };
+// Workspace of the split right factor: three bf16 terms of a 160 x 160 factor.
+constexpr size_t TSPLIT_BYTES = 3 * 160 * 160 * 2;
 // Partial Grams of the first `P` (device count) columns of the source, P <= pmax.
 // Kernels launched with guard = 1 do nothing when the pending draw found S exhausted.
 hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t which_p, int32_t pmax, double *part,

@@ -129,14 +129,15 @@ def test_c1_merge_state_each_iteration(c1):
         assert np.linalg.norm(U.T @ U - np.eye(U.shape[1])) <= 1e-12
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(precision=pod.POD_F32), dict(w=60), dict(r_update=8), dict(n_iter=5)])
+@pytest.mark.parametrize("kw", [dict(), dict(precision=pod.POD_F32), dict(precision=pod.POD_BF16_REFINE), dict(w=60),
+                                dict(r_update=8), dict(n_iter=5)])
 def test_device_loop_equals_stepwise_loop(c1, kw):
     """pod_run (the loop of Alg. 1 with a device-side stop test and chunked
     launches) gives the host loop's merges bit for bit: same sines, same basis."""
     kw = dict(kw)
     n_iter = kw.pop("n_iter", None)
     print(f"device loop vs stepwise {kw} n_iter={n_iter}", flush=True)
-    A = c1.A.astype(np.float32) if kw.get("precision") == pod.POD_F32 else c1.A
+    A = c1.A.astype(np.float32) if kw.get("precision") in (pod.POD_F32, pod.POD_BF16_REFINE) else c1.A
     outs = []
     for stepwise, chunk in [(True, 8), (False, 3), (False, 64)]:
         with pod.PodContext(_dev(A), **_c1_params(**kw)) as ctx:
@@ -244,7 +245,7 @@ def test_waves_indices_bit_exact_fp32(waves_small):
             assert np.array_equal(ctx.indices(it)[0], ref.log[it].cols)
 
 
-@pytest.mark.parametrize("precision", [pod.POD_F64, pod.POD_F32])
+@pytest.mark.parametrize("precision", [pod.POD_F64, pod.POD_F32, pod.POD_BF16_REFINE])
 def test_waves_parity(waves_small, precision):
     A = waves_small
     kw = dict(k=20, c=40, seed=2002, theta_tol=1e-5)
@@ -330,9 +331,9 @@ def wide_fp64():
     return snapgen.spectrum_matrix(3000, 700, s, 1e-8, seed=1007).A
 
 
-@pytest.mark.parametrize("precision", [pod.POD_F64, pod.POD_F32])
+@pytest.mark.parametrize("precision", [pod.POD_F64, pod.POD_F32, pod.POD_BF16_REFINE])
 def test_wide_merge_parity(wide_fp64, precision):
-    """k = 40, c = 100: merge width p = 140 (C3-like), FP64 and FP32 paths."""
+    """k = 40, c = 100: merge width p = 140 (C3-like), FP64, FP32 and split-BF16 paths."""
     A = wide_fp64 if precision == pod.POD_F64 else wide_fp64.astype(np.float32)
     kw = dict(k=40, c=100, seed=2007, theta_tol=1e-9, max_iter=5)
     print(f"wide merge precision={precision}", flush=True)
@@ -383,6 +384,16 @@ def test_incremental_device_blocks_fp64(c1):
     kw = _c1_params(theta_tol=1e-9)
     print("incremental fp64 device blocks", flush=True)
     _inc_check(c1.A, kw, block_bounds(c1.A.shape[1], 4), dict(kw, precision=pod.POD_F64), False, 1e-10, 1e-8)
+
+
+def test_incremental_host_blocks_bf16_split(waves_small):
+    """Alg. 3 over pinned host blocks with the merges on split-BF16 matrix cores."""
+    from oracle.isma import block_bounds
+    A = waves_small
+    kw = dict(k=20, c=40, seed=2004, theta_tol=1e-5, max_iter=30)
+    print("incremental bf16 host blocks", flush=True)
+    _inc_check(A, kw, block_bounds(A.shape[1], width=128), dict(kw, precision=pod.POD_BF16_REFINE), True, 1e-5,
+               1e-5)
 
 
 def test_incremental_host_blocks_ragged_fp32(waves_small):
@@ -565,3 +576,50 @@ def test_batch_loss_gradients(precision):
             print(f"  matrix {i}: L={L:.4e} grad rel={rel:.2e}", flush=True)
             assert abs(L - Lr) <= 1e-9 * Lr and rel <= 1e-8
     assert total > 0
+
+
+# ------------------------------------------------------------------ split-BF16 merge path (POD_BF16_REFINE)
+
+@pytest.mark.parametrize("shape", [(20000, 400, 20, 40), (6003, 300, 50, 100)])
+def test_bf16_split_before_and_after_refinement(shape):
+    """Merge products on BF16 matrix cores with a three-term split: indices
+    bit-exact, every convergence sine within 1e-5, the merge-chain state
+    (before the final FP32 Rayleigh-Ritz step) within 1e-4 and the final
+    modes within 1e-5 of the oracle (sigma relative, largest principal
+    angle).  The second shape has p = 150 and a ragged m (not a multiple of 4
+    or of the 32-row stage)."""
+    m, n, k, c = shape
+    A = snapgen.waves_np(m, n, 60, 1.5, 1e-3, seed=1012)
+    kw = dict(k=k, c=c, seed=2012, theta_tol=1e-5, max_iter=12)
+    print(f"bf16 split m={m} n={n} k={k} c={c}", flush=True)
+    with pod.PodContext(_dev(A), precision=pod.POD_BF16_REFINE, **kw) as ctx:
+        sines = ctx.run()
+        iters = ctx.info().iter
+        idx = [ctx.indices(it)[0] for it in range(iters)]
+        Ub, sb = ctx.basis()
+        Ub, sb = Ub.cpu().numpy(), sb.cpu().numpy()
+        U, s, _ = ctx.project(want_v=False)
+        U, s = U.cpu().numpy(), s.cpu().numpy()
+    ref = oracle_isma(A, IsmaParams(**kw), n_iter=iters, elem_bytes=4)
+    assert len(ref.log) == iters
+    for it in range(iters):
+        assert np.array_equal(idx[it], ref.log[it].cols), it
+    for g_s, lg in zip(sines[1:], ref.log[1:]):
+        assert abs(g_s - lg.sin_theta) <= 1e-5 * max(1.0, lg.sin_theta) + 1e-12
+    rb = np.max(np.abs(sb[:k] - ref.s_merge[:k]) / ref.s_merge[:k])
+    ab = _angles(ref.U_merge[:, :k], Ub[:, :k])
+    rel = np.max(np.abs(s - ref.sigma) / ref.sigma)
+    ang = _angles(ref.U, U)
+    print(f"  iters={iters} before: sigma_rel={rb:.3e} angle={ab:.3e}; after: sigma_rel={rel:.3e} angle={ang:.3e}",
+          flush=True)
+    assert rb <= 1e-4 and ab <= 1e-4
+    assert rel <= 1e-5 and ang <= 1e-5
+
+
+def test_bf16_split_rejected_where_unsupported(c1):
+    """A stored in FP64 and the batched driver reject POD_BF16_REFINE."""
+    with pytest.raises(pod.PodError):
+        pod.PodContext(_dev(c1.A), k=10, c=20, precision=pod.POD_BF16_REFINE)
+    A32 = _dev(c1.A.astype(np.float32))
+    with pytest.raises(pod.PodError):
+        pod.Batch([A32], [dict(k=10, c=20, precision=pod.POD_BF16_REFINE)])
