@@ -329,7 +329,7 @@ pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
     ALLOC(ctx->signv, double, (size_t)64 * r);
     ALLOC(ctx->signi, int64_t, (size_t)64 * r);
     if (p.w > 0 || p.r_update > 0) ALLOC(ctx->Vt, double, (size_t)pmax * pmax);
-    if (pmax > 64) ALLOC(ctx->ws, double, (size_t)3 * pmax * pmax + pmax);
+    if (pmax > 64) ALLOC(ctx->ws, double, (size_t)3 * pmax * pmax + pmax + BIG_INVIT_DOUBLES);
     if (p.w > 0) {
         ALLOC(ctx->rho, double, m);
         ALLOC(ctx->wr, uint64_t, m);

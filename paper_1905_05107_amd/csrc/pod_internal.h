@@ -219,6 +219,9 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
 
 // Merge widths up to this run the register-resident small kernels.
 constexpr int SMALL_LDS_P = 64;
+// Device scratch of the inverse iteration of wide merges (p > SMALL_LDS_P):
+// six arrays of 160 rows for 64 lanes.
+constexpr size_t BIG_INVIT_DOUBLES = (size_t)6 * 160 * 64;
 
 struct SmallArgs {
     DevState *ds;

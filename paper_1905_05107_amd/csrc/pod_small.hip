@@ -9,6 +9,7 @@
 #include "pod_internal.h"
 #include "pod_symeig.h"
 #include "pod_rl.h"
+#include "pod_big.h"
 
 namespace pod {
 
@@ -409,7 +410,7 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
         __syncthreads();
     } else {
         const double thr = a.urnd * trace;
-        int fail = chol_upper(S, p, thr * 1e-3);
+        int fail = big_chol(S, p, thr * 1e-3);
         if (fail) {
             const double shift = (double)p * a.urnd * trace;
             __syncthreads();
@@ -417,7 +418,7 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
                 S[idx] = a.work[idx] + ((idx % p == idx / p) ? shift : 0.0);
             __syncthreads();
             if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
-            fail = chol_upper(S, p, 0.0);
+            fail = big_chol(S, p, 0.0);
             if (fail) {
                 if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
                 for (int idx = threadIdx.x; idx < p * p; idx += NT) S[idx] = (idx % p == idx / p) ? 1.0 : 0.0;
@@ -668,7 +669,7 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
     } else {
     extern __shared__ double lds[];
     __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
-        sdots[EIG_NMAX], ssc[8], ssin[2];
+        ssc[8], ssin[2];
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     __shared__ double sred[NT / 64];
     DevState *ds = a.ds;
@@ -679,7 +680,6 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
     double *S1 = BIG ? a.ws : lds; // G2 -> R2 -> R2^-1
     double *S2 = S1 + p * p;       // R1 -> H = R R^T -> reflectors -> B^T B
     double *S3 = S1 + 2 * p * p;   // R -> eigenvectors Y (p x r')
-    double *lu = BIG ? lds : lds + 3 * p * p;  // eig_lu_doubles(p)
     // ---- pass-2 Cholesky
     double tr = 0.0;
     for (int idx = threadIdx.x; idx < p * p; idx += NT) {
@@ -694,7 +694,7 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
     __syncthreads();
     double trace = 0.0;
     for (int q = 0; q < NT / 64; ++q) trace += sred[q];
-    int fail = isfinite(trace) ? chol_upper(S1, p, a.urnd * trace * 1e-3) : 1;
+    int fail = isfinite(trace) ? big_chol(S1, p, a.urnd * trace * 1e-3) : 1;
     if (fail) {
         const double shift = (double)p * a.urnd * (isfinite(trace) ? trace : 1.0);
         __syncthreads();
@@ -704,36 +704,42 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
         }
         __syncthreads();
         if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
-        fail = isfinite(trace) ? chol_upper(S1, p, 0.0) : 1;
+        fail = isfinite(trace) ? big_chol(S1, p, 0.0) : 1;
         if (fail) {
             if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
             for (int idx = threadIdx.x; idx < p * p; idx += NT) S1[idx] = (idx % p == idx / p) ? 1.0 : 0.0;
             __syncthreads();
         }
     }
-    // ---- R = R2 R1 (both upper triangular)
-    for (int idx = threadIdx.x; idx < p * p; idx += NT) {
-        const int i = idx % p, j = idx / p;
-        double s = 0.0;
-        for (int l = i; l <= j; ++l) s += S1[i + l * p] * S2[l + j * p];
-        S3[idx] = (i <= j) ? s : 0.0;
-        a.R2[i + j * pm] = (i <= j) ? s : 0.0;   // the merge factor R, kept for the adjoint
-    }
+    // ---- R = R2 R1 (both upper triangular: tile (I, J) sums k in [16 I, 16 J + 16))
+    big_mm(p, false,
+           [&](int i, int k) { return (i < p && k < p) ? S1[i + k * p] : 0.0; },
+           [&](int k, int j) { return (k < p && j < p) ? S2[k + j * p] : 0.0; },
+           [&](int i, int j, double v) {
+               if (i < p && j < p) {
+                   S3[i + j * p] = v;
+                   a.R2[i + j * pm] = v;   // the merge factor R, kept for the adjoint
+               }
+           },
+           [&](int ti, int tj, int &k0, int &k1) { k0 = 16 * ti; k1 = 16 * tj + 16; });
     __syncthreads();
     const int kk0 = (a.k < rs) ? a.k : rs;
     if (a.criterion == POD_CRIT_MODE && kk0 > 0)
         for (int idx = threadIdx.x; idx < p * kk0; idx += NT) a.work[idx] = S3[idx];
-    // ---- H = R R^T
-    for (int idx = threadIdx.x; idx < p * p; idx += NT) {
-        const int i = idx % p, j = idx / p;
-        const int l0 = (i > j) ? i : j;
-        double s = 0.0;
-        for (int l = l0; l < p; ++l) s += S3[i + l * p] * S3[j + l * p];
-        S2[idx] = s;
-    }
+    // ---- H = R R^T (upper tiles, mirrored; tile (I, J) sums k from 16 max(I, J))
+    big_mm(p, true,
+           [&](int i, int k) { return (i < p && k < p) ? S3[i + k * p] : 0.0; },
+           [&](int k, int j) { return (k < p && j < p) ? S3[j + k * p] : 0.0; },
+           [&](int i, int j, double v) {
+               if (i < p && j < p) {
+                   S2[i + j * p] = v;
+                   S2[j + i * p] = v;
+               }
+           },
+           [&](int ti, int tj, int &k0, int &k1) { k0 = 16 * ((ti > tj) ? ti : tj); });
     __syncthreads();
     // ---- eigen-decomposition of H
-    tridiag(S2, p, sd, se, stau, spv, ssc);
+    big_tridiag(S2, p, sd, se, stau);
     const int nv = (a.r < p) ? a.r : p;
     bisect_top(sd, se, p, nv, sev, se2, ssc);
     const double u64 = 1.1102230246251565e-16;
@@ -741,8 +747,8 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
     const double thr = fmax(g1 * g1, (double)p * u64) * fmax(sev[0], 0.0);
     int nz = count_above(sd, se2, p, thr, ssc[2], scl);
     const int rnew = (sev[0] > 0.0) ? ((nv < nz) ? nv : nz) : 0;
-    tri_invit(sd, se, p, sev, rnew, S3, lu, scl);
-    tridiag_backtransform(S2, stau, p, S3, rnew, sdots);
+    big_invit(sd, se, p, sev, rnew, S3, a.ws + 3 * pm * pm + pm, scl);
+    big_backtransform(S2, stau, p, S3, rnew);
     // S3 now holds U_R(:, 0:rnew) (p x rnew, ld p)
     // ---- convergence angle
     const int kk = (kk0 < rnew) ? kk0 : rnew;
@@ -778,6 +784,26 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
             const int br = p - kk;
             if (br <= 0) {
                 sin_max = 0.0;
+            } else if (kk <= 64) {
+                // F = B^T B (kk x kk), B = U_R(kk:p, 0:kk), on the matrix cores into a
+                // zero-padded 64 x 64 LDS matrix; register-resident eigensolver
+                double *bufB = lds, *Pp = lds + 64 * RL_LD, *ssde = Pp + 512;
+                for (int idx = threadIdx.x; idx < 64 * RL_LD; idx += NT) bufB[idx] = 0.0;
+                __syncthreads();
+                big_mm(kk, false,
+                       [&](int i, int q) { return (i < kk && q < br) ? S3[kk + q + i * p] : 0.0; },
+                       [&](int q, int j) { return (q < br && j < kk) ? S3[kk + q + j * p] : 0.0; },
+                       [&](int i, int j, double v) {
+                           if (i < kk && j < kk) bufB[i * RL_LD + j] = v;
+                       },
+                       [&](int ti, int tj, int &k0, int &k1) { (void)ti; (void)tj; k0 = 0; k1 = (br + 15) & ~15; });
+                __syncthreads();
+                double r[8];
+                rl_load_rows(r, bufB);
+                __syncthreads();
+                rl_tridiag(r, kk, sd, se, stau, bufB, Pp);
+                bisect_top_rl(tri_regs(sd, se, kk, ssde), kk, 1, ssin);
+                sin_max = sqrt(fmax(ssin[0], 0.0));
             } else {
                 // F = B^T B, B = U_R(kk:p, 0:kk)
                 for (int idx = threadIdx.x; idx < kk * kk; idx += NT) {
@@ -795,13 +821,15 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
     }
     // ---- Z2 = R2^-1 U_R(:, 0:rnew)  (R2^-1 into S2, free after the sines)
     trinv_upper<BIG>(S1, p, S2, spv);
-    for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
-        const int i = idx % pm, j = idx / pm;
-        double s = 0.0;
-        if (i < p && j < rnew)
-            for (int l = i; l < p; ++l) s += S2[i + l * p] * S3[l + j * p];
-        store_c(a.Tc, a.prec, idx, s);
-    }
+    // (R2^-1 upper triangular: tile row I sums k from 16 I; only the leading
+    // p x rnew block of Tc is read by the tall transform)
+    big_mm(p, false,
+           [&](int i, int k) { return (i < p && k < p) ? S2[i + k * p] : 0.0; },
+           [&](int k, int j) { return (k < p && j < rnew) ? S3[k + j * p] : 0.0; },
+           [&](int i, int j, double v) {
+               if (i < pm && j < pm) store_c(a.Tc, a.prec, i + j * pm, v);
+           },
+           [&](int ti, int tj, int &k0, int &k1) { (void)tj; k0 = 16 * ti; });
     double *sigma_new = (it0 & 1) ? a.sig0 : a.sig1;
     for (int i = threadIdx.x; i < a.r; i += NT) sigma_new[i] = (i < rnew) ? sqrt(fmax(sev[i], 0.0)) : 0.0;
     if (threadIdx.x == 0) {
@@ -831,7 +859,9 @@ __global__ __launch_bounds__(512) void k_svd_merge_b(const SmallArgs *__restrict
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
 {
     const bool big = a.pmax > SMALL_LDS_P;
-    const size_t lds = big ? ((size_t)(eig_lu_doubles(a.pmax)) * sizeof(double)) : svd_merge_lds_rl(a.pmax);
+    // wide merges: the convergence eigenproblem (kk <= 64) in LDS, the rest in
+    // registers, static LDS and the workspace
+    const size_t lds = big ? (size_t)(64 * RL_LD + 512 + TRI_SDE) * sizeof(double) : svd_merge_lds_rl(a.pmax);
     static bool attr[2] = {false, false};
     const void *fn = big ? (const void *)k_svd_merge<true> : (const void *)k_svd_merge<false>;
     if (!attr[big]) {
