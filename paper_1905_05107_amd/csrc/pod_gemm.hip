@@ -662,23 +662,28 @@ __device__ __forceinline__ v4f mfma_split(const bf16x8 &ah, const bf16x8 &ad, co
     return mfma_bf16(ah, bh, c);
 }
 
-// Partial Grams on the split operands.  The row stage is split while it is
-// written to LDS (each value once per workgroup), column-major per term with
-// a column stride of BCS bf16 (16-byte aligned operand reads).  Per stage
-// every wave reads the three terms of all column tiles once and takes the
-// tile pairs (I <= J) whose number is congruent to its index mod 4; pair
-// numbers, operand registers and accumulators are compile-time indices.
-constexpr int BCS = 40;
+// tile pairs per round of the final LDS reduction, and that reduction's LDS
+// (4 waves x CH pairs x 256 FP64 values, within the 64 KiB default)
+constexpr int gram_bf16_direct_ch(int bt) { return (bt * (bt + 1) / 2 + 7) / 8; }
+constexpr size_t gram_bf16_direct_lds(int bt) { return (size_t)4 * gram_bf16_direct_ch(bt) * 4 * 64 * sizeof(double); }
 
-template <int BT, int ITEMS>
-__device__ __forceinline__ void gram_bf16_body(SrcT<float> s, int64_t m, const DevState *ds, int which_p, int pmax,
-                                               double *__restrict__ part, int nblk, int vec, int bid)
+// Partial Grams on the split operands straight from registers (the layout of
+// gram_direct_body with 32-row groups): lane (i, k) = (l % 16, l / 16) of a
+// wave loads rows 8k .. 8k+7 of a 32-row group from column 16 t + i of every
+// column tile t, splits them into three bf16x8 terms, and MFMA step (I, J)
+// takes the lane's own terms of tiles I and J -- no LDS staging and no
+// barrier in the row loop.  Groups are grid-strided over the waves, one group
+// loaded ahead; the four wave partials of a workgroup are summed in FP64
+// through LDS in a fixed order, CH tile pairs at a time.
+template <int BT>
+__device__ __forceinline__ void gram_bf16_direct_body(SrcT<float> s, int64_t m, const DevState *ds, int which_p,
+                                                      int pmax, double *__restrict__ part, int nblk, int vec,
+                                                      int bid)
 {
-    constexpr int CW = ITEMS * 256 / GRP;   // staged columns, 16 BT
-    constexpr int NSLOT = (BT * (BT + 1) / 2 + 3) / 4;
-    static_assert(CW == 16 * BT, "stage width");
+    constexpr int NPAIR = BT * (BT + 1) / 2;
+    constexpr int CH = gram_bf16_direct_ch(BT);   // pairs per LDS reduction round
     extern __shared__ unsigned char lds_raw[];
-    __bf16 *Xb = reinterpret_cast<__bf16 *>(lds_raw);   // [term][column][row]
+    double *red = reinterpret_cast<double *>(lds_raw);   // 4 waves x CH pairs x 4 x 64
     if (s.guard && merge_halted(ds)) return;
     const int P = sel_count(ds, which_p);
     s.rs = ds->rs;
@@ -686,116 +691,134 @@ __device__ __forceinline__ void gram_bf16_body(SrcT<float> s, int64_t m, const D
     if (s.U1 && (ds->it & 1)) s.U = s.U1;
     const int NT16 = (P + 15) >> 4;
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t nst = (m + RB - 1) / RB;
-    const int64_t s0 = (nst * bid) / nblk, s1 = (nst * (bid + 1)) / nblk;
-    v4f acc[NSLOT];
+    const int ci = lane & 15, kr = 8 * (lane >> 4);
+    const float *cpt[BT];
+    bool live[BT];
+    bool same = true;
 #pragma unroll
-    for (int q = 0; q < NSLOT; ++q) acc[q] = v4f{0, 0, 0, 0};
-    auto store = [&](const Stage<float, ITEMS> &st) {
+    for (int t = 0; t < BT; ++t) {
+        const int c = 16 * t + ci;
+        live[t] = c < P;
+        const ColPtr cp = col_ptr<float>(s, m, live[t] ? c : 0);
+        cpt[t] = reinterpret_cast<const float *>(cp.p);
+        same = same && (cp.f64 == 0);
+    }
+    const bool fast = vec && __all(same);
+    const int64_t ngr = (m + 31) >> 5, nfull = m >> 5;
+    const int64_t W = (int64_t)bid * 4 + wv, NW = (int64_t)nblk * 4;
+    v4f acc[NPAIR];
 #pragma unroll
-        for (int it = 0; it < ITEMS; ++it) {
-            const int idx = threadIdx.x + 256 * it;
-            const int c = idx / GRP, g = idx % GRP;
-            bf16x4 h, d, l;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                __bf16 a0, a1, a2;
-                split3((c < P) ? st.v[it][q] : 0.0f, a0, a1, a2);
-                h[q] = a0;
-                d[q] = a1;
-                l[q] = a2;
-            }
-            __bf16 *o = Xb + c * BCS + 4 * g;
-            *reinterpret_cast<bf16x4 *>(o) = h;
-            *reinterpret_cast<bf16x4 *>(o + CW * BCS) = d;
-            *reinterpret_cast<bf16x4 *>(o + 2 * CW * BCS) = l;
-        }
-    };
-    auto compute = [&]() {
-        bf16x8 oh[BT], od[BT], ol[BT];
+    for (int q = 0; q < NPAIR; ++q) acc[q] = v4f{0, 0, 0, 0};
+    auto split = [&](const float (&v)[BT][8], bf16x8 (&oh)[BT], bf16x8 (&od)[BT], bf16x8 (&ol)[BT]) {
 #pragma unroll
         for (int t = 0; t < BT; ++t) {
-            if (t < NT16) {
-                const __bf16 *b = Xb + (16 * t + (lane & 15)) * BCS + 8 * (lane >> 4);
-                oh[t] = *reinterpret_cast<const bf16x8 *>(b);
-                od[t] = *reinterpret_cast<const bf16x8 *>(b + CW * BCS);
-                ol[t] = *reinterpret_cast<const bf16x8 *>(b + 2 * CW * BCS);
-            }
-        }
 #pragma unroll
-        for (int I = 0; I < BT; ++I) {
-#pragma unroll
-            for (int J = I; J < BT; ++J) {
-                const int pr = I * BT - I * (I - 1) / 2 + (J - I);
-                if ((pr & 3) == wv && J < NT16)
-                    acc[pr >> 2] = mfma_split(oh[I], od[I], ol[I], oh[J], od[J], ol[J], acc[pr >> 2]);
+            for (int q = 0; q < 8; ++q) {
+                __bf16 a0, a1, a2;
+                split3(v[t][q], a0, a1, a2);
+                oh[t][q] = a0;
+                od[t][q] = a1;
+                ol[t][q] = a2;
             }
         }
     };
-    Stage<float, ITEMS> sa, sb;
-    sa.prepare(s, m, P, vec);
-    sb.fast = sa.fast;
+    auto mma = [&](const bf16x8 (&oh)[BT], const bf16x8 (&od)[BT], const bf16x8 (&ol)[BT]) {
+        int q = 0;
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) sb.base[it] = sa.base[it];
-    const int64_t full_end = m / RB;
-    const int64_t e = sa.fast ? ((s1 < full_end) ? s1 : ((full_end > s0) ? full_end : s0)) : s0;
-    if (e > s0) {
-        const int64_t last = e - 1;
-        sa.load_full(s0 * RB);
-        sb.load_full(((s0 + 1 < last) ? s0 + 1 : last) * RB);
-        int64_t sg = s0;
-        for (; sg + 1 < e; sg += 2) {
-            __syncthreads();
-            store(sa);
-            __syncthreads();
-            sa.load_full(((sg + 2 < last) ? sg + 2 : last) * RB);
-            compute();
-            __syncthreads();
-            store(sb);
-            __syncthreads();
-            sb.load_full(((sg + 3 < last) ? sg + 3 : last) * RB);
-            compute();
+        for (int I = 0; I < BT; ++I)
+#pragma unroll
+            for (int J = I; J < BT; ++J, ++q)
+                if (J < NT16) acc[q] = mfma_split(oh[I], od[I], ol[I], oh[J], od[J], ol[J], acc[q]);
+    };
+    auto load_fast = [&](int64_t gr, float (&v)[BT][8]) {
+#pragma unroll
+        for (int t = 0; t < BT; ++t) {
+            const float *p = cpt[t] + gr * 32 + kr;
+            const f32x4 a = *reinterpret_cast<const f32x4 *>(p);
+            const f32x4 b = *reinterpret_cast<const f32x4 *>(p + 4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v[t][q] = live[t] ? a[q] : 0.0f;
+                v[t][4 + q] = live[t] ? b[q] : 0.0f;
+            }
         }
-        if (sg < e) {
-            __syncthreads();
-            store(sa);
-            __syncthreads();
-            compute();
+    };
+    int64_t gstart = W;
+    if (fast && gstart < nfull) {
+        // one group in flight: a group is split into its terms, then the raw
+        // registers take the next group's loads (index clamped to the wave's last
+        // full group) while the matrix cores work on the terms
+        const int64_t lastg = gstart + ((nfull - 1 - gstart) / NW) * NW;
+        float vr[BT][8];
+        load_fast(gstart, vr);
+        for (int64_t gr = gstart;; gr += NW) {
+            bf16x8 oh[BT], od[BT], ol[BT];
+            split(vr, oh, od, ol);
+            const int64_t nx = gr + NW;
+            load_fast((nx < lastg) ? nx : lastg, vr);
+            mma(oh, od, ol);
+            if (gr >= lastg) break;
         }
+        gstart = lastg + NW;
     }
-    for (int64_t sg = e; sg < s1; ++sg) {
-        sa.load(s, m, sg * RB, P, vec);
-        __syncthreads();
-        store(sa);
-        __syncthreads();
-        compute();
+    for (int64_t gr = gstart; gr < ngr; gr += NW) {
+        float v[BT][8];
+#pragma unroll
+        for (int t = 0; t < BT; ++t) {
+            const ColPtr cp = col_ptr<float>(s, m, live[t] ? 16 * t + ci : 0);
+            float a[4], b[4];
+            load4<float>(cp, gr * 32 + kr, m, vec, a);
+            load4<float>(cp, gr * 32 + kr + 4, m, vec, b);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v[t][q] = live[t] ? a[q] : 0.0f;
+                v[t][4 + q] = live[t] ? b[q] : 0.0f;
+            }
+        }
+        bf16x8 oh[BT], od[BT], ol[BT];
+        split(v, oh, od, ol);
+        mma(oh, od, ol);
     }
+    // sum the four wave partials in FP64 (waves in order), CH tile pairs at a time
     double *pb = part + (int64_t)bid * pmax * pmax;
 #pragma unroll
-    for (int I = 0; I < BT; ++I) {
+    for (int r0 = 0; r0 < NPAIR; r0 += CH) {
+        if (r0) __syncthreads();
 #pragma unroll
-        for (int J = I; J < BT; ++J) {
-            const int pr = I * BT - I * (I - 1) / 2 + (J - I);
-            if ((pr & 3) != wv || J >= NT16) continue;
-            const int j = J * 16 + (lane & 15);
+        for (int qc = 0; qc < CH; ++qc)
+            if (r0 + qc < NPAIR)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = I * 16 + acc_row<float>(lane, v);
-                const double x = (double)acc[pr >> 2][v];
-                if (I < J || i <= j) {
-                    pb[i + (int64_t)j * pmax] = x;
-                    pb[j + (int64_t)i * pmax] = x;
-                }
+                for (int v = 0; v < 4; ++v) red[((wv * CH + qc) * 4 + v) * 64 + lane] = (double)acc[r0 + qc][v];
+        __syncthreads();
+        for (int o = threadIdx.x; o < CH * 256; o += 256) {
+            const int qc = o >> 8, v = (o >> 6) & 3, ln = o & 63;
+            const int q = r0 + qc;
+            if (q >= NPAIR) continue;
+            // pair q -> (I, J), I <= J, in the order of the accumulation loop
+            int I = 0, rem = q;
+            while (rem >= BT - I) {
+                rem -= BT - I;
+                ++I;
+            }
+            const int J = I + rem;
+            if (J >= NT16) continue;
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) sum += red[((w * CH + qc) * 4 + v) * 64 + ln];
+            const int i = 16 * I + acc_row<float>(ln, v), j = 16 * J + (ln & 15);
+            if (I < J || i <= j) {
+                pb[i + (int64_t)j * pmax] = sum;
+                pb[j + (int64_t)i * pmax] = sum;
             }
         }
     }
 }
 
-template <int BT, int ITEMS>
-__global__ __launch_bounds__(256) void k_gram_bf16(SrcT<float> s, int64_t m, const DevState *ds, int which_p, int pmax,
-                                                   double *__restrict__ part, int nblk, int vec)
+template <int BT>
+__global__ __launch_bounds__(256) void k_gram_bf16_direct(SrcT<float> s, int64_t m, const DevState *ds, int which_p,
+                                                          int pmax, double *__restrict__ part, int nblk, int vec)
 {
-    gram_bf16_body<BT, ITEMS>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
+    gram_bf16_direct_body<BT>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
 }
 
 // The three terms of T (pin x pout, ld ldt; counts from the device state),
@@ -986,11 +1009,11 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
         const SrcT<float> s = make_src<float>(d);
         const int vec = (int)vec_ok(s, d.m);
         if (wide)
-            hipLaunchKernelGGL((k_gram_bf16<10, ITEMS160>), dim3(nblk), dim3(256), 3 * 160 * BCS * sizeof(__bf16), st, s,
-                               d.m, ds, which_p, pmax, part, nblk, vec);
+            hipLaunchKernelGGL((k_gram_bf16_direct<10>), dim3(nblk), dim3(256), gram_bf16_direct_lds(10), st, s, d.m,
+                               ds, which_p, pmax, part, nblk, vec);
         else
-            hipLaunchKernelGGL((k_gram_bf16<4, ITEMS64>), dim3(nblk), dim3(256), 3 * 64 * BCS * sizeof(__bf16), st, s,
-                               d.m, ds, which_p, pmax, part, nblk, vec);
+            hipLaunchKernelGGL((k_gram_bf16_direct<4>), dim3(nblk), dim3(256), gram_bf16_direct_lds(4), st, s, d.m, ds,
+                               which_p, pmax, part, nblk, vec);
     } else if (d.prec == POD_F64) {
         if (wide) {
             gram_launch<double, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
