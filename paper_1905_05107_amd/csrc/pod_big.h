@@ -476,3 +476,144 @@ __device__ __forceinline__ void big_invit(const double *d, const double *e, int 
 }
 
 }  // namespace pod
+
+namespace pod {
+
+// ---------------------------------------------------------------------------
+// Sturm counts and multisection for the tridiagonal of a wide merge
+// (n <= 160): the division-free minor recurrence of sturm_rl on the same
+// power-of-two scaled tridiagonal, its entries in LDS (`sde`: BIG_SDE_LD
+// scaled diagonal entries, padded, then as many scaled squared couplings).
+// ---------------------------------------------------------------------------
+constexpr int BIG_SDE_LD = EIG_NMAX + 8;
+constexpr int BIG_TRI_SDE = 2 * BIG_SDE_LD;
+
+struct BigTri {
+    double lo, hi, pivmin, tn;
+    double sc;          // power of two with sc * max(|lo|, |hi|) in [0.5, 1)
+    const double *sde;
+};
+
+// Every thread calls this (it ends with a barrier).
+__device__ __forceinline__ BigTri big_tri(const double *d, const double *e, int n, double *sde)
+{
+    const int l = rl_lane();
+    const double u = 1.1102230246251565e-16;
+    const double inf = __builtin_huge_val();
+    double lo = inf, hi = -inf, emax = 0.0, tn = 0.0;
+#pragma unroll
+    for (int s = 0; s < BIG_NS; ++s) {
+        const int i = l + 64 * s;
+        if (i < n) {
+            const double di = d[i], ei = (i + 1 < n) ? e[i] : 0.0, em = (i >= 1) ? e[i - 1] : 0.0;
+            const double rad = fabs(em) + fabs(ei);
+            lo = fmin(lo, di - rad);
+            hi = fmax(hi, di + rad);
+            emax = fmax(emax, ei * ei);
+            tn = fmax(tn, fabs(di) + fabs(ei));
+        }
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    emax = wave_max(emax);
+    BigTri t;
+    t.tn = wave_max(tn);
+    t.pivmin = 2.2250738585072014e-308 * fmax(1.0, emax) * 4.0;
+    const double wid = fmax(fabs(lo), fabs(hi));
+    t.lo = lo - 2.0 * u * wid * n - 2.0 * t.pivmin;
+    t.hi = hi + 2.0 * u * wid * n + 2.0 * t.pivmin;
+    const double big = fmax(fabs(t.lo), fabs(t.hi));
+    t.sc = (big > 0.0 && big < inf) ? ldexp(1.0, -ilogb(big) - 1) : 1.0;
+    for (int i = threadIdx.x; i < BIG_SDE_LD; i += EIG_NT) {
+        // padded rows: d - x > 0 and no coupling (see sturm_rl)
+        const double es = (i + 1 < n) ? e[i] * t.sc : 0.0;
+        sde[i] = (i < n) ? d[i] * t.sc : 4.0;
+        sde[BIG_SDE_LD + i] = (i + 1 < n) ? fmax(es * es, 0x1p-200) : 0.0;
+    }
+    t.sde = sde;
+    __syncthreads();
+    return t;
+}
+
+// Number of eigenvalues below x (the recurrence and sign counting of sturm_rl).
+__device__ __forceinline__ int big_sturm(const BigTri &t, int n, double x)
+{
+    n = opaque_uniform(n);
+    const double xs = x * t.sc;
+    const double *ds = t.sde, *e2 = t.sde + BIG_SDE_LD;
+    double pm1 = 1.0, pm2 = 0.0, mc = 0.0;
+    unsigned cnt = 0, sg = 0;
+    double dn[8], en[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        dn[q] = ds[q];
+        en[q] = e2[q];
+    }
+    for (int b = 0; b < n; b += 8) {   // (the next block's entries are loaded a block ahead)
+        double dc[8], ec[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            dc[q] = dn[q];
+            ec[q] = en[q];
+            dn[q] = ds[b + 8 + q];
+            en[q] = e2[b + 8 + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double mn = -ec[q] * pm1;
+            double p = fma(dc[q] - xs, pm1, mc);
+            if ((q & 3) == 3) {
+                const int ex = max(frexp_e(pm1), frexp_e(pm2));
+                p = ldexp(p, -ex);
+                mn = ldexp(mn, -ex);
+                pm1 = ldexp(pm1, -ex);
+            }
+            sg = __builtin_amdgcn_alignbit(sg, (unsigned)__double2hiint(p), 31);
+            pm2 = pm1;
+            pm1 = p;
+            mc = mn;
+        }
+        cnt += __popc((sg ^ (sg >> 1)) & 0xFFu);
+        sg &= 1u;
+    }
+    return (int)cnt;
+}
+
+// The nv largest eigenvalues (descending) into ev by multisection (the
+// rounds of bisect_top_rl with big_sturm).
+__device__ __forceinline__ void big_bisect_top(const BigTri &t, int n, int nv, double *ev)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const double u = 1.1102230246251565e-16;
+    int G = 64;
+    while (G > 1 && nv * G > EIG_NT) G >>= 1;
+    const int grp = tid / G, gl = tid % G;
+    const bool active = grp < nv;
+    const int idx = n - 1 - grp;   // ascending index of the target eigenvalue
+    const int gbase = lane - gl;
+    const double atol = 4.0 * u * fmax(fabs(t.lo), fabs(t.hi));
+    double a = t.lo, b = t.hi;
+    for (int round = 0; round < 80; ++round) {
+        const bool done = !active || (b - a) <= fmax(2.0 * u * fmax(fabs(a), fabs(b)), atol) + 4.0 * t.pivmin;
+        if (__all(done)) break;
+        const double x = a + (b - a) * (double)(gl + 1) / (double)(G + 1);
+        const int cnt = done ? 0 : big_sturm(t, n, x);
+        const unsigned long long m = __ballot(!done && cnt > idx);
+        const unsigned long long gm = (G == 64) ? m : ((m >> gbase) & ((1ULL << G) - 1));
+        if (!done) {
+            if (gm == 0) {
+                a = a + (b - a) * (double)G / (double)(G + 1);
+            } else {
+                const int g0 = __ffsll((long long)gm) - 1;   // first point with count > idx
+                const double nb = a + (b - a) * (double)(g0 + 1) / (double)(G + 1);
+                const double na = (g0 == 0) ? a : a + (b - a) * (double)g0 / (double)(G + 1);
+                a = na;
+                b = nb;
+            }
+        }
+    }
+    if (active && gl == 0) ev[grp] = 0.5 * (a + b);
+    __syncthreads();
+}
+
+}  // namespace pod

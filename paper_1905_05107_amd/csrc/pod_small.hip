@@ -741,11 +741,12 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
     // ---- eigen-decomposition of H
     big_tridiag(S2, p, sd, se, stau);
     const int nv = (a.r < p) ? a.r : p;
-    bisect_top(sd, se, p, nv, sev, se2, ssc);
+    const BigTri bt = big_tri(sd, se, p, lds);   // (the dynamic LDS is free until the convergence test)
+    big_bisect_top(bt, p, nv, sev);
     const double u64 = 1.1102230246251565e-16;
     const double g1 = (double)p * a.urnd;
     const double thr = fmax(g1 * g1, (double)p * u64) * fmax(sev[0], 0.0);
-    int nz = count_above(sd, se2, p, thr, ssc[2], scl);
+    const int nz = p - big_sturm(bt, p, thr);
     const int rnew = (sev[0] > 0.0) ? ((nv < nz) ? nv : nz) : 0;
     big_invit(sd, se, p, sev, rnew, S3, a.ws + 3 * pm * pm + pm, scl);
     big_backtransform(S2, stau, p, S3, rnew);
