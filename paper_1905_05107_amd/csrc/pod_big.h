@@ -9,6 +9,17 @@
 
 namespace pod {
 
+// Broadcast of lane O of each aligned group of 8 lanes to the whole group
+// (a quad_perm broadcast, then a half-row mirror for the other quad).
+template <int O> __device__ __forceinline__ double bcast8(double v)
+{
+    constexpr int q = O & 3;
+    constexpr int ctrl = q | (q << 2) | (q << 4) | (q << 6);
+    const double v1 = dpp_f64<ctrl>(v);
+    const double v2 = dpp_f64<0x141>(v1);
+    return (((threadIdx.x >> 2) & 1) == (O >> 2)) ? v1 : v2;
+}
+
 constexpr int BIG_NR = 20;   // rows per wave: row a = w + 8 k, k < BIG_NR (n <= 160)
 constexpr int BIG_NS = 3;    // column slots per lane: column l + 64 s
 
@@ -613,6 +624,66 @@ __device__ __forceinline__ void big_bisect_top(const BigTri &t, int n, int nv, d
         }
     }
     if (active && gl == 0) ev[grp] = 0.5 * (a + b);
+    __syncthreads();
+}
+
+}  // namespace pod
+
+namespace pod {
+
+// LDS of a packed upper triangle of the widest merge
+constexpr int BIG_PACKED = EIG_NMAX * (EIG_NMAX + 1) / 2;
+
+// ---------------------------------------------------------------------------
+// X = R^-1 for the upper-triangular n x n matrix R (n <= 160; column-major,
+// ld n, device memory; X must not alias R): the column-by-column back
+// substitution of trinv_cols (one group of 8 lanes per column of X, its
+// right-hand side in registers, no barrier between the steps) with R's upper
+// triangle first copied to LDS, packed by columns (column i at i (i + 1) / 2:
+// Rp, BIG_PACKED doubles), so that every step reads LDS instead of L2.
+// `tmp` (n doubles of LDS) holds the reciprocals of the diagonal.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void big_trinv(const double *R, int n, double *X, double *Rp, double *tmp)
+{
+    for (int i = threadIdx.x; i < n; i += EIG_NT) tmp[i] = 1.0 / R[i + i * n];
+    for (int c = rl_wave(); c < n; c += 8)
+        for (int r = rl_lane(); r <= c; r += 64) Rp[c * (c + 1) / 2 + r] = R[r + (size_t)c * n];
+    __syncthreads();
+    const int gl = threadIdx.x & 7;
+    for (int j = threadIdx.x >> 3; j < n; j += EIG_NT / 8) {
+        double b[BIG_NR];
+#pragma unroll
+        for (int s = 0; s < BIG_NR; ++s) b[s] = (8 * s + gl == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int s = BIG_NR - 1; s >= 0; --s) {
+            if (8 * s > j) continue;   // uniform in the group
+            double bs = b[s];
+#pragma unroll 1
+            for (int o = 7; o >= 0; --o) {
+                const int i = 8 * s + o;
+                if (i > j) continue;
+                double bi;
+                switch (o) {
+                case 0: bi = bcast8<0>(bs); break;
+                case 1: bi = bcast8<1>(bs); break;
+                case 2: bi = bcast8<2>(bs); break;
+                case 3: bi = bcast8<3>(bs); break;
+                case 4: bi = bcast8<4>(bs); break;
+                case 5: bi = bcast8<5>(bs); break;
+                case 6: bi = bcast8<6>(bs); break;
+                default: bi = bcast8<7>(bs); break;
+                }
+                const double xi = bi * tmp[i];
+                if (gl == o) X[i + (size_t)j * n] = xi;
+                // rows of this slot below lane o, then the earlier slots (all above row i)
+                const double *col = Rp + i * (i + 1) / 2;
+                if (gl < o) bs -= col[8 * s + gl] * xi;
+#pragma unroll
+                for (int s2 = 0; s2 < s; ++s2) b[s2] -= col[8 * s2 + gl] * xi;
+            }
+        }
+        for (int l = j + 1 + gl; l < n; l += 8) X[l + (size_t)j * n] = 0.0;
+    }
     __syncthreads();
 }
 

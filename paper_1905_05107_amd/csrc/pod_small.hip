@@ -1,11 +1,14 @@
 // pod_small.hip -- FP64 small-matrix algebra of the merge (Alg. 2) on gfx950.
 //
-// One workgroup of 512 threads works on p x p matrices (p <= 64) held in LDS:
-// the Cholesky factors of the CholeskyQR2 Grams and their inverses, the SVD of
+// One workgroup of 512 threads works on the p x p matrices of a merge: the
+// Cholesky factors of the CholeskyQR2 Grams and their inverses, the SVD of
 // the merge factor R (the paper's E up to an orthogonal factor) through the
-// symmetric eigen-decomposition of R R^T (pod_symeig.h), the rank guard, the
-// convergence angles of Alg. 1 and the Rayleigh-Ritz step of the final
-// projection.  These kernels are latency bound; everything stays in LDS.
+// symmetric eigen-decomposition of R R^T, the rank guard, the convergence
+// angles of Alg. 1 and the Rayleigh-Ritz step of the final projection.  These
+// kernels are latency bound.  For p <= 64 the matrices live in registers and
+// LDS (pod_rl.h); for wider merges the merge kernels keep them in the device
+// workspace between stages and in registers / LDS within a stage
+// (pod_big.h), and the other kernels use pod_symeig.h.
 #include "pod_internal.h"
 #include "pod_symeig.h"
 #include "pod_rl.h"
@@ -15,14 +18,13 @@ namespace pod {
 
 constexpr int NT = EIG_NT;
 // Matrices up to SMALL_LDS_P x SMALL_LDS_P live in LDS; larger ones in the
-// workspace `ws` (device memory, L2 resident), with only the inverse-iteration
-// scratch in LDS.
+// workspace `ws` (device memory, L2 resident).
 // Dynamic LDS of the register-resident kernels (p <= 64, pmax = pm)
 constexpr size_t chol_first_lds_rl(int pm) { return (size_t)(2 * 64 * RL_LD + 2 * pm * pm) * sizeof(double); }
 constexpr size_t svd_merge_lds_rl(int) { return (size_t)(3 * 64 * RL_LD + 512 + INVIT_LDS) * sizeof(double); }
 constexpr size_t lds_limit(bool big)
 {
-    return big ? (size_t)eig_lu_doubles(EIG_NMAX) * sizeof(double)
+    return big ? (size_t)(BIG_PACKED + EIG_NMAX) * sizeof(double)
                : (size_t)(3 * SMALL_LDS_P * SMALL_LDS_P + eig_lu_doubles(SMALL_LDS_P)) * sizeof(double);
 }
 static_assert(chol_first_lds_rl(SMALL_LDS_P) <= lds_limit(false), "LDS budget");
@@ -140,17 +142,6 @@ __device__ int chol_upper(double *S, int p, double thr)
     }
     __syncthreads();
     return 0;
-}
-
-// Broadcast of lane O of each aligned group of 8 lanes to the whole group
-// (a quad_perm broadcast, then a half-row mirror for the other quad).
-template <int O> __device__ __forceinline__ double bcast8(double v)
-{
-    constexpr int q = O & 3;
-    constexpr int ctrl = q | (q << 2) | (q << 4) | (q << 6);
-    const double v1 = dpp_f64<ctrl>(v);
-    const double v2 = dpp_f64<0x141>(v1);
-    return (((threadIdx.x >> 2) & 1) == (O >> 2)) ? v1 : v2;
 }
 
 // X = R^-1 for the upper-triangular p x p matrix R (column-major, ld p); X
@@ -432,7 +423,7 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
     }
     __syncthreads();
     double *Xi = GP;   // R1^-1 (the G0 P product is no longer needed)
-    trinv_upper<BIG>(S, p, Xi, tmp);
+    big_trinv(S, p, Xi, lds, lds + BIG_PACKED);
     // T1 = P R1^-1 (p0 x p)
     for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
         const int i = idx % pm, j = idx / pm;
@@ -468,7 +459,7 @@ __global__ __launch_bounds__(512) void k_chol_first_b(const SmallArgs *__restric
 hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
 {
     const bool big = a.pmax > SMALL_LDS_P;
-    const size_t lds = big ? (0) : chol_first_lds_rl(a.pmax);
+    const size_t lds = big ? (size_t)(BIG_PACKED + EIG_NMAX) * sizeof(double) : chol_first_lds_rl(a.pmax);
     static bool attr[2] = {false, false};
     const void *fn = big ? (const void *)k_chol_first<true> : (const void *)k_chol_first<false>;
     if (!attr[big]) {
@@ -821,7 +812,7 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
         }
     }
     // ---- Z2 = R2^-1 U_R(:, 0:rnew)  (R2^-1 into S2, free after the sines)
-    trinv_upper<BIG>(S1, p, S2, spv);
+    big_trinv(S1, p, S2, lds, spv);
     // (R2^-1 upper triangular: tile row I sums k from 16 I; only the leading
     // p x rnew block of Tc is read by the tall transform)
     big_mm(p, false,
@@ -862,7 +853,8 @@ hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
     const bool big = a.pmax > SMALL_LDS_P;
     // wide merges: the convergence eigenproblem (kk <= 64) in LDS, the rest in
     // registers, static LDS and the workspace
-    const size_t lds = big ? (size_t)(64 * RL_LD + 512 + TRI_SDE) * sizeof(double) : svd_merge_lds_rl(a.pmax);
+    const size_t lds = big ? (size_t)max(64 * RL_LD + 512 + TRI_SDE, BIG_PACKED) * sizeof(double)
+                           : svd_merge_lds_rl(a.pmax);
     static bool attr[2] = {false, false};
     const void *fn = big ? (const void *)k_svd_merge<true> : (const void *)k_svd_merge<false>;
     if (!attr[big]) {
