@@ -369,13 +369,13 @@ namespace pod {
 // arithmetic of tri_invit (LU with partial pivoting of T - lambda I, two
 // solves from a fixed start vector, re-orthogonalisation inside clusters of
 // relatively close eigenvalues), with one lane of wave 0 per cluster (64 at
-// a time) and each lane's factors and iterate in the device scratch W
-// (BIG_INVIT_DOUBLES, element i of lane t at i * 64 + t: the lanes, which
-// walk the rows in step, touch consecutive addresses).  Y (n x nv, ld n)
-// receives unit vectors.
+// a time), each lane's factors in the device scratch W (BIG_INVIT_DOUBLES)
+// and its iterate in LDS (yl, EIG_NMAX * 64 doubles), element i of lane t at
+// i * 64 + t (the lanes, which walk the rows in step, touch consecutive
+// addresses).  Y (n x nv, ld n) receives unit vectors.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void big_invit(const double *d, const double *e, int n, const double *ev, int nv,
-                                          double *Y, double *W, int *scl)
+                                          double *Y, double *W, double *yl, int *scl)
 {
     constexpr int S = 64;
     constexpr size_t A = (size_t)EIG_NMAX * S;   // one array of the scratch
@@ -400,7 +400,7 @@ __device__ __forceinline__ void big_invit(const double *d, const double *e, int 
     for (int cb = 0; cb < nc; cb += S) {
         const int c = cb + t;
         if (t < S && c < nc) {
-            double *u1 = W + t, *u2 = u1 + A, *u3 = u2 + A, *ml = u3 + A, *sw = ml + A, *y = sw + A;
+            double *u1 = W + t, *u2 = u1 + A, *u3 = u2 + A, *ml = u3 + A, *sw = ml + A, *y = yl + t;
             const int i0 = scl[c], i1 = scl[c + 1];
             for (int mi = i0; mi < i1; ++mi) {
                 // perturb equal eigenvalues inside a cluster so the solves differ

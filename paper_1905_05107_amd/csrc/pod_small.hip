@@ -28,6 +28,7 @@ constexpr size_t lds_limit(bool big)
                : (size_t)(3 * SMALL_LDS_P * SMALL_LDS_P + eig_lu_doubles(SMALL_LDS_P)) * sizeof(double);
 }
 static_assert(chol_first_lds_rl(SMALL_LDS_P) <= lds_limit(false), "LDS budget");
+static_assert(EIG_NMAX * 64 <= BIG_PACKED, "the wide merge's iterate scratch fits its dynamic LDS");
 
 // ---------------------------------------------------------------------------
 // In-place Cholesky S = R^T R of the symmetric p x p matrix S (column-major,
@@ -739,7 +740,7 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
     const double thr = fmax(g1 * g1, (double)p * u64) * fmax(sev[0], 0.0);
     const int nz = p - big_sturm(bt, p, thr);
     const int rnew = (sev[0] > 0.0) ? ((nv < nz) ? nv : nz) : 0;
-    big_invit(sd, se, p, sev, rnew, S3, a.ws + 3 * pm * pm + pm, scl);
+    big_invit(sd, se, p, sev, rnew, S3, a.ws + 3 * pm * pm + pm, lds, scl);
     big_backtransform(S2, stau, p, S3, rnew);
     // S3 now holds U_R(:, 0:rnew) (p x rnew, ld p)
     // ---- convergence angle
