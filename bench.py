@@ -89,8 +89,8 @@ def kernel_work(cls, m, n, k, c, p, r, launches, bf16=False):
     return None, 0, None, 0
 
 
-TRAFFIC_SOURCES = {"svd": ["pod_small.hip", "pod_rl.h", "pod_symeig.h", "pod_internal.h"],
-                   "chol": ["pod_small.hip", "pod_rl.h", "pod_symeig.h", "pod_internal.h"],
+TRAFFIC_SOURCES = {"svd": ["pod_small.hip", "pod_rl.h", "pod_big.h", "pod_symeig.h", "pod_internal.h"],
+                   "chol": ["pod_small.hip", "pod_rl.h", "pod_big.h", "pod_symeig.h", "pod_internal.h"],
                    "gram": ["pod_gemm.hip", "pod_internal.h"], "tall": ["pod_gemm.hip", "pod_internal.h"]}
 
 
