@@ -419,7 +419,7 @@ template <> struct Vec4<double> {
     }
 };
 
-template <typename TC>
+template <typename TC, int NWV>
 __device__ __forceinline__ void gram_direct_body(SrcT<TC> s, int64_t m, const DevState *ds, int which_p, int pmax,
                                                  double *__restrict__ part, int nblk, int vec, int bid)
 {
@@ -450,7 +450,7 @@ __device__ __forceinline__ void gram_direct_body(SrcT<TC> s, int64_t m, const De
     // groups of 16 rows, grid-strided over the waves: group W + i NW for wave W
     // (at each step the grid reads one contiguous span of every column)
     const int64_t ngr = (m + 15) >> 4, nfull = m >> 4;   // groups; those entirely inside [0, m)
-    const int64_t W = (int64_t)bid * 4 + wv, NW = (int64_t)nblk * 4;
+    const int64_t W = (int64_t)bid * NWV + wv, NW = (int64_t)nblk * NWV;
     AccT acc[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) acc[q] = AccT{0, 0, 0, 0};
@@ -507,26 +507,28 @@ __device__ __forceinline__ void gram_direct_body(SrcT<TC> s, int64_t m, const De
         }
         mma(v);
     }
-    // sum the four wave partials in FP64 (waves in order), five tile pairs at a time
+    // sum the wave partials in FP64 (waves in order), CP tile pairs at a time
+    // (CP = 5 for 4 waves, 2 for 8: at most 40 KiB of LDS)
+    constexpr int CP = (NWV == 4) ? 5 : 2;
     double *pb = part + (int64_t)bid * pmax * pmax;
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
+    for (int half = 0; half < 10 / CP; ++half) {
         if (half) __syncthreads();
 #pragma unroll
-        for (int q5 = 0; q5 < 5; ++q5)
+        for (int q5 = 0; q5 < CP; ++q5)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) red[((wv * 5 + q5) * 4 + v) * 64 + lane] = (double)acc[5 * half + q5][v];
+            for (int v = 0; v < 4; ++v) red[((wv * CP + q5) * 4 + v) * 64 + lane] = (double)acc[CP * half + q5][v];
         __syncthreads();
-        for (int o = threadIdx.x; o < 5 * 256; o += 256) {
+        for (int o = threadIdx.x; o < CP * 256; o += NWV * 64) {
             const int q5 = o >> 8, v = (o >> 6) & 3, ln = o & 63;
-            const int q = 5 * half + q5;
+            const int q = CP * half + q5;
             // pair q -> (I, J), I <= J
             const int I = (q < 4) ? 0 : (q < 7) ? 1 : (q < 9) ? 2 : 3;
             const int J = I + q - ((q < 4) ? 0 : (q < 7) ? 4 : (q < 9) ? 7 : 9);
             if (J >= NT) continue;
             double sum = 0.0;
 #pragma unroll
-            for (int w = 0; w < 4; ++w) sum += red[((w * 5 + q5) * 4 + v) * 64 + ln];
+            for (int w = 0; w < NWV; ++w) sum += red[((w * CP + q5) * 4 + v) * 64 + ln];
             const int i = 16 * I + acc_row<TC>(ln, v), j = 16 * J + (ln & 15);
             if (I < J || i <= j) {
                 pb[i + (int64_t)j * pmax] = sum;
@@ -543,20 +545,21 @@ __global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, con
     gram_partial_body<TC, MAXPW, ITEMS>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
 }
 
+// 8 waves per workgroup (two per SIMD at one workgroup per CU).
 template <typename TC>
-__global__ __launch_bounds__(256) void k_gram_direct(SrcT<TC> s, int64_t m, const DevState *ds, int which_p, int pmax,
+__global__ __launch_bounds__(512) void k_gram_direct(SrcT<TC> s, int64_t m, const DevState *ds, int which_p, int pmax,
                                                      double *__restrict__ part, int nblk, int vec)
 {
-    gram_direct_body<TC>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
+    gram_direct_body<TC, 8>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
 }
 
 // Batched (P <= 64): matrix blockIdx.y, its own block count; stopped matrices skipped.
 template <typename TC>
-__global__ __launch_bounds__(256) void k_gram_direct_b(const GramArgs *__restrict__ arr)
+__global__ __launch_bounds__(512) void k_gram_direct_b(const GramArgs *__restrict__ arr)
 {
     const GramArgs &a = arr[blockIdx.y];
     if ((int)blockIdx.x >= a.nblk || a.ds->done) return;
-    gram_direct_body<TC>(make_src<TC>(a.d), a.d.m, a.ds, a.which_p, a.pmax, a.part, a.nblk, a.vec, blockIdx.x);
+    gram_direct_body<TC, 8>(make_src<TC>(a.d), a.d.m, a.ds, a.which_p, a.pmax, a.part, a.nblk, a.vec, blockIdx.x);
 }
 
 // Fixed-order reduction of the partial Grams: workgroup w owns 64 entries;
@@ -1019,7 +1022,7 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
             gram_launch<double, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
         } else {
             const SrcT<double> s = make_src<double>(d);
-            hipLaunchKernelGGL(k_gram_direct<double>, dim3(nblk), dim3(256), GD_LDS, st, s, d.m, ds, which_p, pmax,
+            hipLaunchKernelGGL(k_gram_direct<double>, dim3(nblk), dim3(512), GD_LDS, st, s, d.m, ds, which_p, pmax,
                                part, nblk, (int)vec_ok(s, d.m));
         }
     } else {
@@ -1027,7 +1030,7 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
             gram_launch<float, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
         } else {
             const SrcT<float> s = make_src<float>(d);
-            hipLaunchKernelGGL(k_gram_direct<float>, dim3(nblk), dim3(256), GD_LDS, st, s, d.m, ds, which_p, pmax,
+            hipLaunchKernelGGL(k_gram_direct<float>, dim3(nblk), dim3(512), GD_LDS, st, s, d.m, ds, which_p, pmax,
                                part, nblk, (int)vec_ok(s, d.m));
         }
     }
@@ -1455,9 +1458,9 @@ hipError_t launch_gram_partial_b(const GramArgs *arr, int32_t count, int32_t max
     if (pmax_max > 64 || count < 1) return hipErrorInvalidValue;
     const dim3 grid((unsigned)max_nblk, (unsigned)count);
     if (prec == POD_F64)
-        hipLaunchKernelGGL(k_gram_direct_b<double>, grid, dim3(256), GD_LDS, st, arr);
+        hipLaunchKernelGGL(k_gram_direct_b<double>, grid, dim3(512), GD_LDS, st, arr);
     else
-        hipLaunchKernelGGL(k_gram_direct_b<float>, grid, dim3(256), GD_LDS, st, arr);
+        hipLaunchKernelGGL(k_gram_direct_b<float>, grid, dim3(512), GD_LDS, st, arr);
     return hipGetLastError();
 }
 
