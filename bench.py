@@ -222,9 +222,7 @@ def run_c5(args):
             t1 = time.perf_counter()
             rounds = b.run()
             t2 = time.perf_counter()
-            L = 0.0
-            for i in range(len(mats)):
-                L += b.loss_grad(i)[0]
+            L = sum(li for li, _ in b.loss_grad_all())
             torch.cuda.synchronize()
             t3 = time.perf_counter()
         return t3 - t0, t1 - t0, t2 - t1, t3 - t2, L, rounds

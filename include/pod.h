@@ -277,6 +277,16 @@ pod_status pod_batch_enable_adjoint(pod_batch *b);
  * Syncs. */
 pod_status pod_batch_loss_grad(pod_batch *b, int32_t i, void *dA, double *loss);
 
+/* pod_batch_loss_grad for every matrix at once: dA[i] (device, m_i x n_i,
+ * ld m_i, compute type; accumulated, so zero it first) receives dL_i/dA_i and
+ * loss[i] (host, nullable) L_i.  The reverse steps of all matrices run
+ * together (reverse step s takes the (T_i - s)-th merge of each matrix that
+ * has one, in one launch per kernel); the gradients equal those of
+ * pod_batch_loss_grad bit for bit.  Wider reverse steps (p + r > 64) fall
+ * back to one matrix after another.  Same errors as pod_batch_loss_grad.
+ * Syncs. */
+pod_status pod_batch_loss_grad_all(pod_batch *b, void *const *dA, double *loss);
+
 /* Final step of Alg. 1 for matrix i, as pod_project.  Syncs. */
 pod_status pod_batch_project(pod_batch *b, int32_t i, void *U_out, double *sigma_out, void *V_out);
 

@@ -28,7 +28,7 @@ EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project"
            "pod_status_str", "pod_profile_enable", "pod_profile_read", "pod_inc_init", "pod_inc_add_block",
            "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy", "pod_batch_init",
            "pod_batch_autotune", "pod_batch_run", "pod_batch_project", "pod_batch_get_info", "pod_batch_destroy",
-           "pod_enable_adjoint", "pod_backward", "pod_loss_grad", "pod_batch_enable_adjoint", "pod_batch_loss_grad",
+           "pod_enable_adjoint", "pod_backward", "pod_loss_grad", "pod_batch_enable_adjoint", "pod_batch_loss_grad", "pod_batch_loss_grad_all",
            "pod_run"]
 
 
@@ -110,6 +110,7 @@ def lib():
             "pod_loss_grad": (i32, [vp, vp, P(d)]),
             "pod_batch_enable_adjoint": (i32, [vp]),
             "pod_batch_loss_grad": (i32, [vp, i32, vp, P(d)]),
+            "pod_batch_loss_grad_all": (i32, [vp, P(vp), P(d)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -525,6 +526,19 @@ class Batch:
         _check(lib().pod_batch_loss_grad(self.h, int(i), ctypes.c_void_p(dAt.data_ptr()), ctypes.byref(L)),
                "pod_batch_loss_grad")
         return L.value, dAt.T
+
+    def loss_grad_all(self):
+        """[(L_i, dL_i/dA_i)] for every matrix, the reverse steps of all matrices
+        launched together (equal to loss_grad(i) bit for bit)."""
+        import torch
+        dAts = []
+        for i, p in enumerate(self.params):
+            dt = torch.float64 if p.precision == POD_F64 else torch.float32
+            dAts.append(torch.zeros((p.n, p.m), dtype=dt, device=self.mats[i].device))
+        ptrs = (ctypes.c_void_p * len(dAts))(*[t.data_ptr() for t in dAts])
+        losses = (ctypes.c_double * len(dAts))()
+        _check(lib().pod_batch_loss_grad_all(self.h, ptrs, losses), "pod_batch_loss_grad_all")
+        return [(losses[i], dAts[i].T) for i in range(len(dAts))]
 
     def info(self, i: int):
         inf = pod_info()

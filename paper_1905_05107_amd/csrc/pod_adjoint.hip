@@ -73,6 +73,23 @@ __global__ void k_adj_state(DevState *ds, int32_t rs, int32_t g)
     ds->done = 0;
 }
 
+struct AdjStateArg {
+    DevState *ds;
+    int32_t rs, g;
+};
+// Batched: entry blockIdx.x.
+__global__ void k_adj_state_b(const AdjStateArg *__restrict__ arr)
+{
+    const AdjStateArg a = arr[blockIdx.x];
+    if (threadIdx.x == 0) {
+        a.ds->rs = a.rs;
+        a.ds->g = a.g;
+        a.ds->it = 0;
+        a.ds->exhausted = 0;
+        a.ds->done = 0;
+    }
+}
+
 // L = |A - U_k B|_F^2 (B = U_k^T A), dA = 2 (A - U_k B), Ubar = -2 (A - U_k B) B^T.
 // One thread per row, columns in order; per-workgroup loss partials.
 template <typename TC, typename TA, int KM>
@@ -232,6 +249,150 @@ __global__ __launch_bounds__(256) void k_ckpt_post_b(const CkptArgs *__restrict_
 
 }  // namespace
 
+// The reverse passes of many runs together (a batch; every run with merge
+// widths p + r <= 64 and one stream): reverse step s takes merge T_i - 1 - s of
+// every run i that has one, and each of the five launches of a step covers all
+// of those runs at once (blockIdx selects the run).  Per run the kernels, their
+// arguments and their order are those of reverse_merges, so the gradients are
+// the same bit for bit; only the runs' small stages now share the GPU.
+pod_status pod::reverse_merges_batch(pod_ctx *const *ctxs, int32_t count, void *const *dA, hipStream_t st)
+{
+    struct Run {
+        std::vector<int32_t> meta, off;
+        int32_t T;
+    };
+    std::vector<Run> run(count);
+    int32_t maxT = 0, pb_max = 0, max_nblk = 0, max_nb = 0, p_max = 0;
+    const int32_t prec = ctxs[0]->prm.precision;
+    for (int32_t i = 0; i < count; ++i) {
+        pod_ctx *ctx = ctxs[i];
+        Run &R = run[i];
+        R.T = ctx->hs.it;
+        if (ctx->prm.precision != prec || ctx->pb > 64 || ctx->pmax > 64) return POD_EINVAL;
+        if (R.T < 1) continue;
+        R.meta.resize(4 * (size_t)R.T);
+        R.off.resize(R.T + 1);
+        A_HIP(hipMemcpy(R.meta.data(), ctx->ckMeta, sizeof(int32_t) * 4 * R.T, hipMemcpyDeviceToHost));
+        A_HIP(hipMemcpy(R.off.data(), ctx->col_log_off, sizeof(int32_t) * (R.T + 1), hipMemcpyDeviceToHost));
+        for (int32_t t = 0; t < R.T; ++t)
+            if (R.meta[4 * t + 3] != 1) return POD_ESTATE;
+        maxT = (R.T > maxT) ? R.T : maxT;
+        pb_max = (ctx->pb > pb_max) ? ctx->pb : pb_max;
+        p_max = (ctx->pmax > p_max) ? ctx->pmax : p_max;
+        max_nblk = (ctx->nblk > max_nblk) ? ctx->nblk : max_nblk;
+        const int32_t nb = tall_blocks(ctx->prm.m);
+        max_nb = (nb > max_nb) ? nb : max_nb;
+    }
+    if (maxT < 1) return POD_OK;
+    // every step's arguments, built on the host and uploaded once
+    std::vector<AdjStateArg> hs;
+    std::vector<GramArgs> hg;
+    std::vector<AdjArgs> ha;
+    std::vector<ScatterArgs> hc;
+    std::vector<int32_t> first(maxT + 1, 0);
+    const double eta = (prec == POD_F64) ? 1e-12 : 1e-6;
+    for (int32_t sidx = 0; sidx < maxT; ++sidx) {
+        first[sidx] = (int32_t)hs.size();
+        const int cur = sidx & 1;
+        for (int32_t i = 0; i < count; ++i) {
+            pod_ctx *ctx = ctxs[i];
+            const Run &R = run[i];
+            const int32_t t = R.T - 1 - sidx;
+            if (t < 0) continue;
+            const pod_params &p = ctx->prm;
+            const int32_t rs = R.meta[4 * t], g = R.meta[4 * t + 1], rz = R.meta[4 * t + 2];
+            const int32_t P = rs + g, Pext = P + rz;
+            if (P > ctx->pmax) return POD_ESTATE;
+            hs.push_back(AdjStateArg{ctx->dsb, rs, g});
+            GemmDesc gd;
+            gd.prec = (p.precision == POD_F64) ? POD_F64 : POD_F32;
+            gd.a_dtype = p.a_dtype;
+            gd.m = p.m;
+            gd.U = (const unsigned char *)ctx->ckU + (size_t)t * p.m * ctx->r * ctx->esz;
+            gd.U1 = nullptr;
+            gd.A = ctx->A;
+            gd.lda = p.lda;
+            gd.cols = ctx->col_log + R.off[t];
+            gd.Y = nullptr;
+            gd.gather = 1;
+            gd.guard = 0;
+            gd.Z = ctx->Ubar[cur];
+            GramArgs ga;
+            ga.d = gd;
+            ga.ds = ctx->dsb;
+            ga.which_p = Pext;
+            ga.pmax = ctx->pb;
+            ga.nblk = ctx->nblk;
+            ga.vec = gemm_vec_ok(gd);
+            ga.part = ctx->partb;
+            ga.G = ctx->Gext;
+            hg.push_back(ga);
+            AdjArgs aa;
+            aa.Gext = ctx->Gext;
+            aa.pb = ctx->pb;
+            aa.R = ctx->ckR + (size_t)t * ctx->pmax * ctx->pmax;
+            aa.pm = ctx->pmax;
+            aa.sig = ctx->ckS + (size_t)t * ctx->r;
+            aa.sbar_in = ctx->sbar[cur];
+            aa.sbar_out = ctx->sbar[cur ^ 1];
+            aa.Wt = ctx->Wt;
+            aa.prec = p.precision;
+            aa.ws = ctx->adj_ws;
+            aa.rs = rs;
+            aa.g = g;
+            aa.rz = rz;
+            aa.eta = eta;
+            ha.push_back(aa);
+            ScatterArgs sa;
+            sa.d = gd;
+            sa.ds = ctx->dsb;
+            sa.which_in = Pext;
+            sa.which_out = P;
+            sa.T = ctx->Wt;
+            sa.ldt = ctx->pb;
+            sa.Yout = ctx->Ubar[cur ^ 1];
+            sa.split = rs;
+            sa.cmap = ctx->col_log + R.off[t];
+            sa.D = dA[i];
+            sa.ldd = p.m;
+            sa.vec = gemm_vec_ok(gd);
+            sa.nb = tall_blocks(p.m);
+            hc.push_back(sa);
+        }
+    }
+    first[maxT] = (int32_t)hs.size();
+    const size_t ne = hs.size();
+    AdjStateArg *ds_ = nullptr;
+    GramArgs *dg = nullptr;
+    AdjArgs *da = nullptr;
+    ScatterArgs *dc = nullptr;
+    hipError_t e = hipMalloc((void **)&ds_, sizeof(AdjStateArg) * ne);
+    if (e == hipSuccess) e = hipMalloc((void **)&dg, sizeof(GramArgs) * ne);
+    if (e == hipSuccess) e = hipMalloc((void **)&da, sizeof(AdjArgs) * ne);
+    if (e == hipSuccess) e = hipMalloc((void **)&dc, sizeof(ScatterArgs) * ne);
+    if (e == hipSuccess) e = hipMemcpy(ds_, hs.data(), sizeof(AdjStateArg) * ne, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dg, hg.data(), sizeof(GramArgs) * ne, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(da, ha.data(), sizeof(AdjArgs) * ne, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dc, hc.data(), sizeof(ScatterArgs) * ne, hipMemcpyHostToDevice);
+    for (int32_t sidx = 0; sidx < maxT && e == hipSuccess; ++sidx) {
+        const int32_t f = first[sidx], cnt = first[sidx + 1] - f;
+        if (cnt < 1) continue;
+        hipLaunchKernelGGL(k_adj_state_b, dim3((unsigned)cnt), dim3(64), 0, st, ds_ + f);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = launch_gram_partial_b(dg + f, cnt, max_nblk, pb_max, prec, st);
+        if (e == hipSuccess) e = launch_gram_reduce_b(dg + f, cnt, pb_max, st);
+        if (e == hipSuccess) e = launch_adj_small_b(da + f, cnt, st);
+        if (e == hipSuccess) e = launch_gemm_tall_scatter_b(dc + f, cnt, max_nb, pb_max, p_max, prec, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(ds_);
+    (void)hipFree(dg);
+    (void)hipFree(da);
+    (void)hipFree(dc);
+    return (e == hipSuccess) ? POD_OK : POD_EHIP;
+}
+
+
 hipError_t pod::launch_ckpt_pre(pod_ctx *ctx, hipStream_t st)
 {
     const int64_t m = ctx->prm.m;
@@ -354,6 +515,18 @@ pod_status pod_backward(pod_ctx *ctx, const void *dU, const double *dsigma, void
 
 pod_status pod_loss_grad(pod_ctx *ctx, void *dA, double *loss)
 {
+    const pod_status s = loss_enqueue(ctx, dA, loss);
+    if (s != POD_OK) return s;
+    return reverse_merges(ctx, dA);
+}
+
+}  // extern "C"
+
+// The loss L = |A - U_k U_k^T A|_F^2 and the explicit part of its gradient
+// (dA = 2 (A - U_k B), Ubar = -2 (A - U_k B) B^T, B = U_k^T A) enqueued on the
+// run's stream; with `loss` set, L is read back (a synchronisation).
+pod_status pod::loss_enqueue(pod_ctx *ctx, void *dA, double *loss)
+{
     if (!ctx || !dA) return POD_EINVAL;
     if (ctx->failed) return POD_EHIP;
     if (!ctx->ckU || ctx->pending) return POD_ESTATE;
@@ -405,7 +578,5 @@ pod_status pod_loss_grad(pod_ctx *ctx, void *dA, double *loss)
         for (size_t i = 0; i < nb; ++i) L += lp[i];
         *loss = L;
     }
-    return reverse_merges(ctx, dA);
+    return POD_OK;
 }
-
-}  // extern "C"

@@ -369,6 +369,30 @@ pod_status pod_batch_loss_grad(pod_batch *b, int32_t i, void *dA, double *loss)
     return pod_loss_grad(b->ctx[i], dA, loss);
 }
 
+pod_status pod_batch_loss_grad_all(pod_batch *b, void *const *dA, double *loss)
+{
+    if (!b || !dA) return POD_EINVAL;
+    if (b->failed) return POD_EHIP;
+    bool together = true;
+    for (int32_t i = 0; i < b->count; ++i) {
+        if (!dA[i]) return POD_EINVAL;
+        if (!b->ctx[i]->ckU) return POD_ESTATE;
+        together = together && b->ctx[i]->pb <= 64;
+    }
+    if (!together) {   // wide reverse steps: one matrix after another
+        for (int32_t i = 0; i < b->count; ++i) {
+            const pod_status s = pod_loss_grad(b->ctx[i], dA[i], loss ? &loss[i] : nullptr);
+            if (s != POD_OK) return s;
+        }
+        return POD_OK;
+    }
+    for (int32_t i = 0; i < b->count; ++i) {
+        const pod_status s = loss_enqueue(b->ctx[i], dA[i], loss ? &loss[i] : nullptr);
+        if (s != POD_OK) return s;
+    }
+    return reverse_merges_batch(b->ctx.data(), b->count, dA, b->st);
+}
+
 pod_status pod_batch_project(pod_batch *b, int32_t i, void *U_out, double *sigma_out, void *V_out)
 {
     if (!b || i < 0 || i >= b->count) return POD_EINVAL;

@@ -1204,6 +1204,18 @@ __global__ __launch_bounds__(256) void k_gemm_tall_scatter(SrcT<TC> s, int64_t m
                                            blockIdx.x, gridDim.x, 0, sc);
 }
 
+// Batched scatter (P <= 64): matrix blockIdx.y, its own block count.
+template <typename TC>
+__global__ __launch_bounds__(256) void k_gemm_tall_scatter_b(const ScatterArgs *__restrict__ arr)
+{
+    const ScatterArgs &a = arr[blockIdx.y];
+    if ((int)blockIdx.x >= a.nb) return;
+    const TallScatter sc{a.split, a.cmap, a.D, a.ldd};
+    gemm_tall_body<TC, ITEMS64, false, true>(make_src<TC>(a.d), a.d.m, a.ds, a.which_in, a.which_out, 64, 0,
+                                             reinterpret_cast<const TC *>(a.T), a.ldt, reinterpret_cast<TC *>(a.Yout),
+                                             nullptr, a.vec, blockIdx.x, a.nb, 0, sc);
+}
+
 template <typename TC, int ITEMS>
 __global__ __launch_bounds__(256) void k_gemm_tall_b(const TallArgs *__restrict__ arr)
 {
@@ -1483,6 +1495,21 @@ hipError_t launch_gemm_tall_b(const TallArgs *arr, int32_t count, int32_t max_nb
     else
         hipLaunchKernelGGL((k_gemm_tall_b<float, ITEMS64>), grid, dim3(256),
                            (size_t)(64 * LDSR + pi_max * po_max) * sizeof(float), st, arr);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_tall_scatter_b(const ScatterArgs *arr, int32_t count, int32_t max_nb, int32_t pi_max,
+                                      int32_t po_max, int32_t prec, hipStream_t st)
+{
+    const int PI = (pi_max + 15) & ~15, PO = (po_max + 15) & ~15;
+    if (PI > 64 || PO > 64 || count < 1) return hipErrorInvalidValue;
+    const size_t esz = (prec == POD_F64) ? 8 : 4;
+    const size_t lds = (size_t)(64 * LDSR + PI * PO) * esz;
+    const dim3 grid((unsigned)max_nb, (unsigned)count);
+    if (prec == POD_F64)
+        hipLaunchKernelGGL(k_gemm_tall_scatter_b<double>, grid, dim3(256), lds, st, arr);
+    else
+        hipLaunchKernelGGL(k_gemm_tall_scatter_b<float>, grid, dim3(256), lds, st, arr);
     return hipGetLastError();
 }
 

@@ -285,6 +285,27 @@ struct AdjArgs {
     double eta;            // gap guard
 };
 hipError_t launch_adj_small(const AdjArgs &a, hipStream_t st);
+// Batched reverse-pass launches (one entry per matrix, blockIdx selects it).
+hipError_t launch_adj_small_b(const AdjArgs *arr, int32_t count, hipStream_t st);
+struct ScatterArgs {       // one launch_gemm_tall_scatter of the reverse pass (P <= 64)
+    GemmDesc d;
+    const DevState *ds;
+    int32_t which_in, which_out;
+    const void *T;
+    int32_t ldt;
+    void *Yout;
+    int32_t split;
+    const int32_t *cmap;
+    void *D;
+    int64_t ldd;
+    int32_t vec, nb;
+};
+hipError_t launch_gemm_tall_scatter_b(const ScatterArgs *arr, int32_t count, int32_t max_nb, int32_t pi_max,
+                                      int32_t po_max, int32_t prec, hipStream_t st);
+// Reverse pass of the loss gradient: its first part for one run, and the
+// merge-chain part of many runs together (same stream; p + r <= 64).
+pod_status loss_enqueue(pod_ctx *ctx, void *dA, double *loss);
+pod_status reverse_merges_batch(pod_ctx *const *ctxs, int32_t count, void *const *dA, hipStream_t st);
 
 struct ProjArgs {
     int32_t prec, a_dtype;

@@ -1195,7 +1195,21 @@ hipError_t launch_svd_merge_b(const SmallArgs *arr, int32_t count, int32_t pmax_
 // belong to A(:, I_t).  sbar_{t-1,i} = U_{t-1}(:, i)^T Mbar(:, i) comes from the
 // Gram of [X0 | Ubar].  The eigen-decomposition of R R^T is recomputed here.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void adj_small_body(const AdjArgs &a);
+
 __global__ __launch_bounds__(512) void k_adj_small(AdjArgs a)
+{
+    adj_small_body(a);
+}
+
+// Batched: one workgroup per matrix (blockIdx.x).
+__global__ __launch_bounds__(512) void k_adj_small_b(const AdjArgs *__restrict__ arr)
+{
+    const AdjArgs a = arr[blockIdx.x];
+    adj_small_body(a);
+}
+
+__device__ __forceinline__ void adj_small_body(const AdjArgs &a)
 {
     extern __shared__ double lds[];
     __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX], sS[EIG_NMAX],
@@ -1338,6 +1352,21 @@ hipError_t launch_adj_small(const AdjArgs &a, hipStream_t st)
     }
     const size_t lds = (size_t)(64 * RL_LD + 64 * 64 + 512 + INVIT_LDS) * sizeof(double);
     hipLaunchKernelGGL(k_adj_small, dim3(1), dim3(NT), lds, st, a);
+    return hipGetLastError();
+}
+
+// Every entry must satisfy launch_adj_small's bounds (checked by the caller).
+hipError_t launch_adj_small_b(const AdjArgs *arr, int32_t count, hipStream_t st)
+{
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_adj_small_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_limit(false));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const size_t lds = (size_t)(64 * RL_LD + 64 * 64 + 512 + INVIT_LDS) * sizeof(double);
+    hipLaunchKernelGGL(k_adj_small_b, dim3((unsigned)count), dim3(NT), lds, st, arr);
     return hipGetLastError();
 }
 

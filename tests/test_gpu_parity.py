@@ -578,6 +578,28 @@ def test_batch_loss_gradients(precision):
     assert total > 0
 
 
+@pytest.mark.parametrize("precision", [pod.POD_F64, pod.POD_F32])
+def test_batch_loss_gradients_together(precision):
+    """The reverse steps of all matrices launched together (loss_grad_all):
+    losses and gradients equal to the matrix-by-matrix reverse passes bit for
+    bit, for matrices with different merge counts."""
+    dtype = np.float64 if precision == pod.POD_F64 else np.float32
+    mats, kws = _batch_mats(5, 23, dtype)
+    print(f"batch gradients together precision={precision}", flush=True)
+    dev = [_dev(A) for A in mats]
+    with pod.Batch(dev, [dict(kw, precision=precision) for kw in kws]) as b:
+        b.enable_adjoint()
+        b.run()
+        iters = [b.info(i)[0].iter for i in range(len(mats))]
+        each = [b.loss_grad(i) for i in range(len(mats))]
+        together = b.loss_grad_all()
+    print(f"  merges per matrix {iters}", flush=True)
+    assert len(set(iters)) > 1
+    for (L1, G1), (L2, G2) in zip(each, together):
+        assert L1 == L2
+        assert torch.equal(G1, G2)
+
+
 # ------------------------------------------------------------------ split-BF16 merge path (POD_BF16_REFINE)
 
 @pytest.mark.parametrize("shape", [(20000, 400, 20, 40), (6003, 300, 50, 100)])
