@@ -148,15 +148,19 @@ __device__ __forceinline__ void big_tridiag(double *A, int n, double *d, double 
             __syncthreads();
             // tau_j = 0 (a column already reduced) gives p = w = 0: no update, no branch
             const double tj = tau[j];
+            // column slots s < s0 = J / 8 lie entirely left of column j + 1, where v, p
+            // and w vanish: they take no part (s0 is fixed by the unrolled J)
+            const int s0 = J >> 3;
             double vl[BIG_NS];
 #pragma unroll
-            for (int s = 0; s < BIG_NS; ++s) vl[s] = vs[l + 64 * s];
+            for (int s = 0; s < BIG_NS; ++s) vl[s] = (s >= s0) ? vs[l + 64 * s] : 0.0;
             // v_j is zero outside rows j+1..n-1: rows a <= j (k < J) take no part
             double va[BIG_NR];
 #pragma unroll
             for (int k = J; k < BIG_NR; ++k) va[k] = vs[w + 8 * k];
 #pragma unroll
             for (int s = 0; s < BIG_NS; ++s) {
+                if (s < s0) continue;
                 double pa[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int k = J; k < BIG_NR; ++k) pa[k & 3] = fma(r[k][s], va[k], pa[k & 3]);
@@ -166,6 +170,8 @@ __device__ __forceinline__ void big_tridiag(double *A, int n, double *d, double 
             double pl[BIG_NS], kp = 0.0;
 #pragma unroll
             for (int s = 0; s < BIG_NS; ++s) {
+                pl[s] = 0.0;
+                if (s < s0) continue;
                 const int c = l + 64 * s;
                 double pq[8];
 #pragma unroll
@@ -180,10 +186,11 @@ __device__ __forceinline__ void big_tridiag(double *A, int n, double *d, double 
             for (int s = 0; s < BIG_NS; ++s) wl[s] = fma(-K, vl[s], pl[s]);
 #pragma unroll
             for (int k = J; k < BIG_NR; ++k) {
-                // w at column a = w + 8k: slot (8k) / 64 is fixed by k (w < 8)
+                // w at column a = w + 8k: slot (8k) / 64 = k / 8 >= s0 is fixed by k (w < 8)
                 const double wa = readlane_f64(wl[(8 * k) >> 6], (w + 8 * k) & 63);   // zero for a <= j, a >= n
 #pragma unroll
-                for (int s = 0; s < BIG_NS; ++s) r[k][s] = fma(-va[k], wl[s], fma(-wa, vl[s], r[k][s]));
+                for (int s = 0; s < BIG_NS; ++s)
+                    if (s >= s0) r[k][s] = fma(-va[k], wl[s], fma(-wa, vl[s], r[k][s]));
             }
         }
     }
@@ -309,7 +316,8 @@ __device__ __forceinline__ int big_chol(double *S, int n, double thr)
                             const double cf = readlane_f64(r[4 * H + t][sj], (j0 + u) & 63);   // R(j, j0 + u)
                             if (j0 + u < n) {
 #pragma unroll
-                                for (int s = 0; s < BIG_NS; ++s) r[4 * H + u][s] = fma(-cf, r[4 * H + t][s], r[4 * H + u][s]);
+                                for (int s = sj; s < BIG_NS; ++s)
+                                    r[4 * H + u][s] = fma(-cf, r[4 * H + t][s], r[4 * H + u][s]);
                             }
                         }
                     }
@@ -318,11 +326,13 @@ __device__ __forceinline__ int big_chol(double *S, int n, double thr)
                 }
             }
             __syncthreads();
+            // (the block's rows vanish left of column j0 >= 32 H: slots s < sj = H / 2
+            // take no part)
             double rj[4][BIG_NS];
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int s = 0; s < BIG_NS; ++s) rj[t][s] = Rs[t][l + 64 * s];
+                for (int s = sj; s < BIG_NS; ++s) rj[t][s] = Rs[t][l + 64 * s];
 #pragma unroll
             for (int k = 4 * H; k < BIG_NR; ++k) {
                 const int a = big_chol_row(w, k);
@@ -331,7 +341,7 @@ __device__ __forceinline__ int big_chol(double *S, int n, double thr)
                     for (int t = 0; t < 4; ++t) {
                         const double cf = Rs[t][a];   // R(j0 + t, a)
 #pragma unroll
-                        for (int s = 0; s < BIG_NS; ++s) r[k][s] = fma(-cf, rj[t][s], r[k][s]);
+                        for (int s = sj; s < BIG_NS; ++s) r[k][s] = fma(-cf, rj[t][s], r[k][s]);
                     }
                 }
             }
