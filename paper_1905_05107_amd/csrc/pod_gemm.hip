@@ -1338,11 +1338,12 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
     AccT acc[MT];   // MT mode tiles: r <= 16 MT
 #pragma unroll
     for (int q = 0; q < MT; ++q) acc[q] = AccT{0, 0, 0, 0};
-    // A stage: 64 columns x 8 groups = 512 items; U stage: RP columns x 8 groups <= 256 UITEMS items
-    Stage<TC, 2> sta;
-    Stage<TC, UITEMS> stu;
+    // A stage: 64 columns x 8 groups = 512 items; U stage: RP columns x 8 groups <= 256 UITEMS items;
+    // two register stages in flight (stages sg + 1 and sg + 2 load while sg is on the matrix cores)
+    Stage<TC, 2> sta[2];
+    Stage<TC, UITEMS> stu[2];
     const TA *Ab = A + c0 * lda;
-    auto loadA = [&](int64_t sg) {
+    auto loadA = [&](int64_t sg, Stage<TC, 2> &st) {
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
             const int idx = threadIdx.x + 256 * it;
@@ -1351,27 +1352,25 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
                 ColPtr cp;
                 cp.p = Ab + (int64_t)c * lda;
                 cp.f64 = sizeof(TA) == 8;
-                load4<TC>(cp, sg * RB + 4 * g, m, vec, sta.v[it]);
+                load4<TC>(cp, sg * RB + 4 * g, m, vec, st.v[it]);
             } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) sta.v[it][q] = (TC)0;
+                for (int q = 0; q < 4; ++q) st.v[it][q] = (TC)0;
             }
         }
     };
-    stu.prepare(su, m, r, vec);
-    if (s0 < s1) {
-        loadA(s0);
-        stu.load(su, m, s0 * RB, r, vec);
-    }
-    for (int64_t sg = s0; sg < s1; ++sg) {
-        __syncthreads();
-        sta.store(As, PCB, PCB);
-        stu.store(Us, RP, r);
-        __syncthreads();
-        if (sg + 1 < s1) {
-            loadA(sg + 1);
-            stu.load(su, m, (sg + 1) * RB, r, vec);
+    stu[0].prepare(su, m, r, vec);
+    stu[1].fast = stu[0].fast;
+#pragma unroll
+    for (int it = 0; it < UITEMS; ++it) stu[1].base[it] = stu[0].base[it];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        if (s0 + b < s1) {
+            loadA(s0 + b, sta[b]);
+            stu[b].load(su, m, (s0 + b) * RB, r, vec);
         }
+    }
+    auto compute = [&]() {
         const TC *xb = As + (wv * 16 + (lane & 15)) * LDSR + (lane >> 4);
 #pragma unroll
         for (int q = 0; q < MT; ++q) {
@@ -1379,6 +1378,22 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
                 const TC *ua = Us + (q * 16 + (lane & 15)) * LDSR + (lane >> 4);
 #pragma unroll
                 for (int k4 = 0; k4 < RB; k4 += 4) acc[q] = mfma16x16x4(ua[k4], xb[k4], acc[q]);
+            }
+        }
+    };
+    for (int64_t sg = s0; sg < s1; sg += 2) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            if (sg + b < s1) {   // uniform
+                __syncthreads();
+                sta[b].store(As, PCB, PCB);
+                stu[b].store(Us, RP, r);
+                __syncthreads();
+                if (sg + b + 2 < s1) {
+                    loadA(sg + b + 2, sta[b]);
+                    stu[b].load(su, m, (sg + b + 2) * RB, r, vec);
+                }
+                compute();
             }
         }
     }
