@@ -19,6 +19,9 @@ namespace pod {
 constexpr int RB = 32;       // rows per LDS stage
 constexpr int LDSR = RB + 1; // padded stride (elements) of one staged column
 constexpr int GRP = RB / 4;  // 4-row groups per staged column
+constexpr int TALL_ST = 8;                 // row stages per workgroup of the tall transforms
+constexpr size_t TALL_T_LDS = 112 * 1024;  // largest T staged in LDS
+constexpr int TALL_DYN_LDS = 160 * 1024;   // dynamic LDS limit of the tall kernels
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -844,150 +847,177 @@ __global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ T, in
     }
 }
 
-// Tall transform Y = X T on the split operands.  The row stage is split and
-// transposed while it is written to LDS (row-major per term, row stride
-// CW + 8 bf16), so an A operand (16 rows x 8 consecutive k) is one 16-byte
-// read; the B operands come from Tb (L2 resident).  Wave w owns the output
-// column tiles w, w + 4, w + 8 of both 16-row blocks of a stage; each lane
-// stores four consecutive rows of one output column.
-template <int ITEMS>
-__device__ __forceinline__ void gemm_tall_bf16_body(SrcT<float> s, int64_t m, const DevState *ds, int sel_in,
-                                                    int sel_out, const __bf16 *__restrict__ Tb, int KP, int JP,
-                                                    float *__restrict__ Yout, float *__restrict__ Yout1, int vec,
-                                                    int vout, int bid, int nbk, int tri)
+
+// Packed LDS layout of the split factor: column tile jc keeps its 16 columns of
+// kmax(jc) k values (tri: only k < 16 (jc + 1), rounded up to 32).
+__host__ __device__ __forceinline__ int tall_kmax(int jc, int KP, int tri)
 {
-    constexpr int CW = ITEMS * 256 / GRP;   // staged columns (k extent)
-    constexpr int RS = CW + 8;
+    const int k = 32 * ((jc + 2) / 2);
+    return (tri && k < KP) ? k : KP;
+}
+__host__ __device__ __forceinline__ int tall_koff(int jc, int KP, int tri)
+{
+    int o = 0;
+    for (int c = 0; c < jc; ++c) o += 16 * tall_kmax(c, KP, tri);
+    return o;
+}
+
+// Tall transform Y = X T on the split operands straight from registers.  Each
+// wave takes whole 32-row groups (grid-strided): lane (i, kq) = (l % 16, l / 16)
+// loads X(row, k) for rows 16 rb + i and k = 32 ks + 8 kq + t (eight columns of
+// a k step, through column pointers kept in LDS), one group ahead, splits them
+// into three bf16 terms per k step and accumulates every output tile of its
+// rows (2 row blocks x NJM column tiles) against the split factor, which the
+// workgroup copies to LDS once (packed; B operands by 16-byte reads).  No
+// barrier in the row loop; each lane stores four consecutive rows of one output
+// column.
+template <int KS, int NJM>
+__global__ __launch_bounds__(256) void k_gemm_tall_bf16_direct(SrcT<float> s, int64_t m, const DevState *ds,
+                                                               int sel_in, int sel_out, const __bf16 *__restrict__ Tb,
+                                                               int KP, int JP, float *__restrict__ Yout,
+                                                               float *__restrict__ Yout1, int vout, int tri)
+{
     extern __shared__ unsigned char lds_raw[];
-    __bf16 *Xr = reinterpret_cast<__bf16 *>(lds_raw);   // [term][row][k]
+    const float **cptr = reinterpret_cast<const float **>(lds_raw);   // KS * 32 column pointers
+    __bf16 *Ts = reinterpret_cast<__bf16 *>(lds_raw + KS * 32 * sizeof(const float *));
     if (s.guard && merge_halted(ds)) return;
     if (Yout1 && (ds->it & 1)) Yout = Yout1;
     const int pin = sel_count(ds, sel_in), pout = sel_count(ds, sel_out);
     s.rs = ds->rs;
     s.g = ds->g;
     if (s.U1 && (ds->it & 1)) s.U = s.U1;
-    const int KE = (pin + 31) & ~31;
-    const int NJ = (pout + 15) >> 4;
+    const int NKS = (pin + 31) >> 5;   // k steps used (<= KS)
+    const int NJ = (pout + 15) >> 4;   // output column tiles used (<= NJM)
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t nst = (m + RB - 1) / RB;
-    const int64_t ns = (bid < nst) ? (nst - 1 - bid) / nbk + 1 : 0;
-    auto stage = [&](int64_t i) { return (int64_t)bid + i * nbk; };
-    const int64_t tsz = (int64_t)JP * KP;
-    auto store = [&](const Stage<float, ITEMS> &st) {
+    const int ci = lane & 15, kq = lane >> 4;
+    for (int k = threadIdx.x; k < KS * 32; k += 256)
+        cptr[k] = reinterpret_cast<const float *>(col_ptr<float>(s, m, (k < pin) ? k : 0).p);
+    const int tot = tall_koff(JP / 16, KP, tri);   // packed elements per term
+    {
+        const int64_t tsz = (int64_t)JP * KP;
+        const int k8 = KP / 8;
+        for (int idx = threadIdx.x; idx < 3 * JP * k8; idx += 256) {
+            const int t = idx / (JP * k8), rem = idx % (JP * k8);
+            const int j = rem / k8, k = 8 * (rem % k8);
+            const int jc = j >> 4, km = tall_kmax(jc, KP, tri);
+            if (k < km)
+                *reinterpret_cast<bf16x8 *>(Ts + t * tot + tall_koff(jc, KP, tri) + (j & 15) * km + k) =
+                    *reinterpret_cast<const bf16x8 *>(Tb + t * tsz + (int64_t)j * KP + k);
+        }
+    }
+    __syncthreads();
+    int toff[NJM], tkm[NJM];
 #pragma unroll
-        for (int it = 0; it < ITEMS; ++it) {
-            const int idx = threadIdx.x + 256 * it;
-            const int c = idx / GRP, g = idx % GRP;
+    for (int jc = 0; jc < NJM; ++jc) {
+        tkm[jc] = tall_kmax(jc, KP, tri);
+        toff[jc] = tall_koff(jc, KP, tri);
+    }
+    const int64_t ngr = (m + 31) >> 5;
+    const int64_t W = (int64_t)blockIdx.x * 4 + wv, NW = (int64_t)gridDim.x * 4;
+    auto load = [&](int64_t gr, float (&x)[2][KS][8]) {
+        const bool full = (gr + 1) * 32 <= m;   // uniform
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                __bf16 h, d, l;
-                split3((c < pin) ? st.v[it][q] : 0.0f, h, d, l);
-                __bf16 *o = Xr + (4 * g + q) * RS + c;
-                o[0] = h;
-                o[RB * RS] = d;
-                o[2 * RB * RS] = l;
+        for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int k = 32 * ks + 8 * kq + t;
+                const float *cp = cptr[k];
+                const bool kin = k < pin;
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) {
+                    const int64_t row = gr * 32 + 16 * rb + ci;
+                    x[rb][ks][t] = (ks < NKS && kin && (full || row < m)) ? cp[row] : 0.0f;
+                }
             }
         }
     };
-    auto compute = [&](int64_t sg) {
-        v4f acc[2][3];
+    auto process = [&](int64_t gr, const float (&x)[2][KS][8]) {
+        v4f acc[2][NJM];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-            for (int sl = 0; sl < 3; ++sl) acc[rb][sl] = v4f{0, 0, 0, 0};
-        for (int k0 = 0; k0 < KE; k0 += 32) {
+            for (int jc = 0; jc < NJM; ++jc) acc[rb][jc] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (ks >= NKS) continue;   // uniform
             bf16x8 ah[2], ad[2], al[2];
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                const __bf16 *b = Xr + (16 * rb + (lane & 15)) * RS + k0 + 8 * (lane >> 4);
-                ah[rb] = *reinterpret_cast<const bf16x8 *>(b);
-                ad[rb] = *reinterpret_cast<const bf16x8 *>(b + RB * RS);
-                al[rb] = *reinterpret_cast<const bf16x8 *>(b + 2 * RB * RS);
-            }
+            for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-            for (int sl = 0; sl < 3; ++sl) {
-                const int jc = wv + 4 * sl;
+                for (int t = 0; t < 8; ++t) {
+                    __bf16 a0, a1, a2;
+                    split3(x[rb][ks][t], a0, a1, a2);
+                    ah[rb][t] = a0;
+                    ad[rb][t] = a1;
+                    al[rb][t] = a2;
+                }
+#pragma unroll
+            for (int jc = 0; jc < NJM; ++jc) {
                 // with T upper triangular the k steps past column tile jc are zero
-                if (jc < NJ && !(tri && k0 >= 16 * (jc + 1))) {
-                    const __bf16 *tb = Tb + (int64_t)(16 * jc + (lane & 15)) * KP + k0 + 8 * (lane >> 4);
+                if (jc < NJ && !(tri && 32 * ks >= 16 * (jc + 1))) {
+                    const __bf16 *tb = Ts + toff[jc] + ci * tkm[jc] + 32 * ks + 8 * kq;
                     const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(tb);
-                    const bf16x8 bd = *reinterpret_cast<const bf16x8 *>(tb + tsz);
-                    const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(tb + 2 * tsz);
+                    const bf16x8 bd = *reinterpret_cast<const bf16x8 *>(tb + tot);
+                    const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(tb + 2 * tot);
 #pragma unroll
                     for (int rb = 0; rb < 2; ++rb)
-                        acc[rb][sl] = mfma_split(ah[rb], ad[rb], al[rb], bh, bd, bl, acc[rb][sl]);
+                        acc[rb][jc] = mfma_split(ah[rb], ad[rb], al[rb], bh, bd, bl, acc[rb][jc]);
                 }
             }
         }
 #pragma unroll
-        for (int sl = 0; sl < 3; ++sl) {
-            const int jc = wv + 4 * sl;
-            const int col = 16 * jc + (lane & 15);
+        for (int jc = 0; jc < NJM; ++jc) {
+            const int col = 16 * jc + ci;
             if (jc >= NJ || col >= pout) continue;
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
-                const int64_t row0 = sg * RB + 16 * rb + 4 * (lane >> 4);
+                const int64_t row0 = gr * 32 + 16 * rb + 4 * kq;
                 float *y = Yout + (int64_t)col * m + row0;
                 if (vout && row0 + 4 <= m) {
-                    *reinterpret_cast<f32x4 *>(y) = acc[rb][sl];
+                    *reinterpret_cast<f32x4 *>(y) = acc[rb][jc];
                 } else {
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        if (row0 + v < m) y[v] = acc[rb][sl][v];
+                        if (row0 + v < m) y[v] = acc[rb][jc][v];
                 }
             }
         }
     };
-    Stage<float, ITEMS> sa, sb;
-    sa.prepare(s, m, pin, vec);
-    sb.fast = sa.fast;
+    if (W < ngr) {
+        float xa[2][KS][8];
+        load(W, xa);
+        for (int64_t gr = W; gr < ngr; gr += NW) {
+            float xc[2][KS][8];
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) sb.base[it] = sa.base[it];
-    const int64_t full_end = m / RB;
-    int64_t nf = (bid < full_end) ? (full_end - 1 - bid) / nbk + 1 : 0;
-    if (!sa.fast) nf = 0;
-    if (nf > ns) nf = ns;
-    if (nf > 0) {
-        const int64_t last = nf - 1;
-        sa.load_full(stage(0) * RB);
-        sb.load_full(stage((1 < last) ? 1 : last) * RB);
-        int64_t i = 0;
-        for (; i + 1 < nf; i += 2) {
-            __syncthreads();
-            store(sa);
-            __syncthreads();
-            sa.load_full(stage((i + 2 < last) ? i + 2 : last) * RB);
-            compute(stage(i));
-            __syncthreads();
-            store(sb);
-            __syncthreads();
-            sb.load_full(stage((i + 3 < last) ? i + 3 : last) * RB);
-            compute(stage(i + 1));
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) xc[rb][ks][t] = xa[rb][ks][t];
+            if (gr + NW < ngr) load(gr + NW, xa);
+            process(gr, xc);
         }
-        if (i < nf) {
-            __syncthreads();
-            store(sa);
-            __syncthreads();
-            compute(stage(i));
-        }
-    }
-    for (int64_t i = nf; i < ns; ++i) {
-        sa.load(s, m, stage(i) * RB, pin, vec);
-        __syncthreads();
-        store(sa);
-        __syncthreads();
-        compute(stage(i));
     }
 }
 
-template <int ITEMS>
-__global__ __launch_bounds__(256) void k_gemm_tall_bf16(SrcT<float> s, int64_t m, const DevState *ds, int sel_in,
-                                                        int sel_out, const __bf16 *__restrict__ Tb, int KP, int JP,
-                                                        float *__restrict__ Yout, float *__restrict__ Yout1, int vec,
-                                                        int vout, int tri)
+template <int KS, int NJM>
+static void tall_bf16_direct_launch(const SrcT<float> &s, int64_t m, const DevState *ds, int which_in,
+                                    int which_out, const __bf16 *Tb, int KP, int JP, void *Yout, void *Yout1,
+                                    int vout, int tri, hipStream_t st)
 {
-    gemm_tall_bf16_body<ITEMS>(s, m, ds, sel_in, sel_out, Tb, KP, JP, Yout, Yout1, vec, vout, blockIdx.x, gridDim.x,
-                               tri);
+    const size_t lds = (size_t)KS * 32 * sizeof(const float *) + (size_t)3 * tall_koff(JP / 16, KP, tri) * 2;
+    static bool attr = false;
+    if (!attr) {
+        if (hipFuncSetAttribute((const void *)k_gemm_tall_bf16_direct<KS, NJM>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, TALL_DYN_LDS) != hipSuccess)
+            return;   // the launch below then fails and reports the error
+        attr = true;
+    }
+    const int64_t ngr = (m + 31) >> 5;
+    const int64_t want = (ngr + 3) / 4;
+    const unsigned nb = (unsigned)((want < 256) ? ((want > 0) ? want : 1) : 256);
+    hipLaunchKernelGGL((k_gemm_tall_bf16_direct<KS, NJM>), dim3(nb), dim3(256), lds, st, s, m, ds, which_in,
+                       which_out, Tb, KP, JP, (float *)Yout, (float *)Yout1, vout, tri);
 }
 
 template <typename TC, int MAXPW, int ITEMS>
@@ -1053,9 +1083,6 @@ hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax
 // the output as Y^T tiles = T^T X^T so that each lane's four results are
 // consecutive rows of one output column.
 // ---------------------------------------------------------------------------
-constexpr int TALL_ST = 8;   // row stages per workgroup
-constexpr size_t TALL_T_LDS = 112 * 1024;  // largest T staged in LDS
-constexpr int TALL_DYN_LDS = 160 * 1024;   // dynamic LDS limit of the tall kernels
 
 // Scatter output (SCAT): output columns below `split` go to Yout, column
 // split + j is added to D(:, cmap[j]) (leading dimension ldd); the mapped
@@ -1261,16 +1288,11 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
         hipLaunchKernelGGL(k_split_t, dim3((JP * KP + 255) / 256), dim3(256), 0, st, (const float *)T, ldt, ds,
                            which_in, which_out, KP, JP, Tb, d.guard);
         const SrcT<float> s = make_src<float>(d);
-        const int vec = (int)vec_ok(s, d.m);
         const int vout = (d.m % 4 == 0) && ((uintptr_t)Yout % 16 == 0) && ((uintptr_t)Yout1 % 16 == 0);
-        if (!wide)
-            hipLaunchKernelGGL((k_gemm_tall_bf16<ITEMS64>), dim3(nb), dim3(256), 3 * RB * (64 + 8) * sizeof(__bf16), st,
-                               s, d.m, ds, which_in, which_out, (const __bf16 *)Tb, KP, JP, (float *)Yout,
-                               (float *)Yout1, vec, vout, tri);
+        if (KP <= 64 && JP <= 64)
+            tall_bf16_direct_launch<2, 4>(s, d.m, ds, which_in, which_out, Tb, KP, JP, Yout, Yout1, vout, tri, st);
         else
-            hipLaunchKernelGGL((k_gemm_tall_bf16<ITEMS160>), dim3(nb), dim3(256), 3 * RB * (160 + 8) * sizeof(__bf16),
-                               st, s, d.m, ds, which_in, which_out, (const __bf16 *)Tb, KP, JP, (float *)Yout,
-                               (float *)Yout1, vec, vout, tri);
+            tall_bf16_direct_launch<5, 10>(s, d.m, ds, which_in, which_out, Tb, KP, JP, Yout, Yout1, vout, tri, st);
     } else if (d.prec == POD_F64) {
         const bool tg = (size_t)PI * PO * sizeof(double) > TALL_T_LDS;
         if (!wide) tall_launch<double, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
