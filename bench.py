@@ -94,15 +94,16 @@ TRAFFIC_SOURCES = {"svd": ["pod_small.hip", "pod_rl.h", "pod_big.h", "pod_symeig
                    "gram": ["pod_gemm.hip", "pod_internal.h"], "tall": ["pod_gemm.hip", "pod_internal.h"]}
 
 
-def measured_traffic(cls):
+def measured_traffic(cls, workload):
     """HBM bytes per launch of a kernel class from the committed FETCH_SIZE /
     WRITE_SIZE summary (profiles/isma_waves200k_hbm_traffic.md), scaled by the
-    copy-kernel factors recorded there; None when the class was not measured
-    or its kernel sources changed since (sha256 prefix mismatch)."""
+    copy-kernel factors recorded there; None when the class was not measured,
+    the workload is not the 200,000 x 2,000 one the counters were taken on, or
+    the kernel sources changed since (sha256 prefix mismatch)."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "isma_waves200k_hbm_traffic.md")
-    if cls not in TRAFFIC_SOURCES or not os.path.exists(path):
+    if workload != "c2" or cls not in TRAFFIC_SOURCES or not os.path.exists(path):
         return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES[cls]:
@@ -418,7 +419,7 @@ def main():
     avg_s = dom_ms / 1e3 / max(per_step_launches * args.steps, 1)
     bound, amount, unit, hb = kernel_work(dominant, m, n, k, c, p, k, per_step_launches, bf16)
     roof = roofline_entry(bound, amount, avg_s, hb)
-    roof["traffic"] = measured_traffic(dominant)
+    roof["traffic"] = measured_traffic(dominant, args.workload)
     roof.update({"kernel_class": dominant, "avg_launch_us": round(avg_s * 1e6, 2),
                  "launches_per_step": round(per_step_launches, 1)})
     # the other classes, from the per-class pre-pass
