@@ -378,3 +378,66 @@ def test_incremental_exact_on_low_rank():
     assert np.max(np.abs(sk - s) / s) < 1e-12
     assert oracle.subspace_sines(sm.U, Uk).max() < 1e-11
     assert block_bounds(1100, width=512) == [(0, 512), (512, 1024), (1024, 1100)]
+
+
+# ---------------------------------------------------------------- quality measure (Eq. ang_meas)
+def _orth(X):
+    Q, _ = np.linalg.qr(X)
+    return Q
+
+
+def test_wedin_zero_for_exact_triplets():
+    """The exact top-k singular triplets leave R = S = 0 (rounding only)."""
+    from oracle.wedin import wedin_measure
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((300, 80)) @ np.diag(0.9 ** np.arange(80)) @ _orth(rng.standard_normal((80, 80)))
+    U, s, Vt = np.linalg.svd(A, full_matrices=False)
+    k = 6
+    rn, sn, om, b = wedin_measure(A, U[:, :k], s[:k], Vt[:k].T, s[k])
+    assert rn < 1e-12 * s[0] and sn < 1e-12 * s[0]
+    assert om == pytest.approx(min(s[k - 1] - s[k], s[k - 1]), rel=1e-15)
+    assert b < 1e-10
+
+
+def test_wedin_closed_form_rotation():
+    """A = diag(d); the k-th left vector turned by theta towards e_{k+1}, the
+    rest exact: ||R|| = d_k 2 sin(theta/2), ||S||^2 = d_k^2 (1 - cos theta)^2
+    + d_{k+1}^2 sin^2 theta."""
+    from oracle.wedin import wedin_measure
+    m, n, k, th = 40, 30, 4, 0.03
+    d = np.array([10.0, 7.0, 5.0, 3.0, 2.0] + [1.0 / (i + 2) for i in range(n - 5)])
+    A = np.zeros((m, n))
+    A[np.arange(n), np.arange(n)] = d
+    U = np.eye(m)[:, :k].copy()
+    U[:, k - 1] = math.cos(th) * np.eye(m)[:, k - 1] + math.sin(th) * np.eye(m)[:, k]
+    V = np.eye(n)[:, :k]
+    rn, sn, om, b = wedin_measure(A, U, d[:k], V, d[k])
+    assert rn == pytest.approx(d[k - 1] * 2 * math.sin(th / 2), rel=1e-13)
+    assert sn == pytest.approx(math.sqrt(d[k - 1] ** 2 * (1 - math.cos(th)) ** 2 + d[k] ** 2 * math.sin(th) ** 2),
+                               rel=1e-13)
+    assert om == pytest.approx(min(d[k - 1] - d[k], d[k - 1]))
+    assert b == pytest.approx(math.sqrt(rn * rn + sn * sn) / om, rel=1e-15)
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-4, 1e-2])
+def test_wedin_theorem_holds(eps):
+    """Wedin's theorem: with omega from the exact singular values, the
+    measure bounds the Frobenius norm of the sines of the principal angles
+    between exact and perturbed subspaces (left and right)."""
+    from oracle.wedin import wedin_measure
+    rng = np.random.default_rng(int(-math.log10(eps)))
+    m, n, k = 200, 60, 5
+    s_true = np.concatenate([[20.0, 15.0, 11.0, 8.0, 6.0], 3.0 * 0.8 ** np.arange(n - 5)])
+    Ux = _orth(rng.standard_normal((m, n)))
+    Vx = _orth(rng.standard_normal((n, n)))
+    A = (Ux * s_true) @ Vx.T
+    Ut = _orth(Ux[:, :k] + eps * rng.standard_normal((m, k)))
+    Vt = _orth(Vx[:, :k] + eps * rng.standard_normal((n, k)))
+    st = s_true[:k] * (1 + eps * rng.standard_normal(k))
+    rn, sn, _, _ = wedin_measure(A, Ut, st, Vt, s_true[k])
+    omega = min(np.min(np.abs(st[-1] - s_true[k:])), st[-1])
+    sin_t = scipy.linalg.subspace_angles(Ux[:, :k], Ut)
+    sin_p = scipy.linalg.subspace_angles(Vx[:, :k], Vt)
+    lhs = math.sqrt(np.sum(np.sin(sin_t) ** 2) + np.sum(np.sin(sin_p) ** 2))
+    assert lhs <= math.sqrt(rn * rn + sn * sn) / omega * (1 + 1e-9)
+    assert lhs > 0.0
