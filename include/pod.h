@@ -156,6 +156,23 @@ pod_status pod_run(pod_ctx *ctx, int32_t max_merges, int32_t stop_on_converged, 
  * Each u_i is signed so that its largest-magnitude entry is positive. */
 pod_status pod_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out);
 
+/* Quality measure of the converged modes (Sec. "Quality of converged
+ * solution", Eq. ang_meas): with the k pairs (U_k, Sigma_k, V_k) that the last
+ * pod_project wrote (U_k device m x k, V_k device n x k, both column-major in
+ * the compute type: FP64 for POD_F64 else FP32; Sigma_k and sigma_{k+1} are
+ * the Rayleigh-Ritz values the context keeps),
+ *   R = A V_k - U_k Sigma_k,  S = A^T U_k - V_k Sigma_k,
+ *   out[0] = ||R||_F, out[1] = ||S||_F,
+ *   out[2] = omega^ = min(|sigma_k - sigma_{k+1}|, sigma_k),
+ *   out[3] = sqrt(out[0]^2 + out[1]^2) / omega^ (+inf when omega^ = 0),
+ * Wedin's bound on the sines of the principal angles between the exact and
+ * the computed dominant subspaces (out: host, 4 doubles).  Two passes over A,
+ * FP64 accumulation, fixed summation order.  The first call allocates a
+ * workspace (m k + k n doubles and partials) that the context keeps.
+ * POD_ESTATE unless pod_project ran after the last merge; POD_EINVAL when the
+ * rank r is not above k (sigma_{k+1} is needed) or k > 64.  Syncs. */
+pod_status pod_wedin_bound(pod_ctx *ctx, const void *U_k, const void *V_k, double *out);
+
 /* Copy the current merged basis (before the final step) to caller device
  * buffers: U_out m x rank (ld = m, precision as in pod_project) and
  * sigma_out (device, rank FP64); *rank_out (host) gets the rank.  Syncs. */

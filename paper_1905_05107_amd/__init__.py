@@ -23,7 +23,7 @@ POD_ROW_L2, POD_ROW_LS = 0, 1
 POD_CRIT_SUBSPACE, POD_CRIT_MODE = 0, 1
 
 # every symbol include/pod.h declares
-EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project", "pod_get_basis", "pod_get_info",
+EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project", "pod_wedin_bound", "pod_get_basis", "pod_get_info",
            "pod_get_indices", "pod_get_col_sqnorms", "pod_col_sqnorms", "pod_sample_size", "pod_destroy",
            "pod_status_str", "pod_profile_enable", "pod_profile_read", "pod_inc_init", "pod_inc_add_block",
            "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy", "pod_batch_init",
@@ -83,6 +83,7 @@ def lib():
             "pod_converged": (i32, [vp, P(i32), P(d)]),
             "pod_run": (i32, [vp, i32, i32, i32, P(d), P(i32), P(i32)]),
             "pod_project": (i32, [vp, vp, vp, vp]),
+            "pod_wedin_bound": (i32, [vp, vp, vp, P(d)]),
             "pod_get_basis": (i32, [vp, vp, vp, P(i32)]),
             "pod_get_info": (i32, [vp, P(pod_info)]),
             "pod_get_indices": (i32, [vp, i32, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)]),
@@ -258,6 +259,17 @@ class PodContext:
         _check(lib().pod_project(self.h, ctypes.c_void_p(Ut.data_ptr()), ctypes.c_void_p(sig.data_ptr()),
                                  ctypes.c_void_p(Vt.data_ptr()) if want_v else None), "pod_project")
         return Ut.T, sig, (Vt.T if want_v else None)
+
+    def wedin_bound(self, U, V):
+        """Quality measure of Eq. (ang_meas) for the pairs the last project()
+        returned: (||R||_F, ||S||_F, omega^, bound).  Needs r > k."""
+        Ut, Vt = U.T, V.T
+        if not (Ut.is_contiguous() and Vt.is_contiguous()):
+            raise ValueError("U and V must be the column-major outputs of project()")
+        out = (ctypes.c_double * 4)()
+        _check(lib().pod_wedin_bound(self.h, ctypes.c_void_p(Ut.data_ptr()), ctypes.c_void_p(Vt.data_ptr()), out),
+               "pod_wedin_bound")
+        return tuple(out)
 
     def basis(self):
         import torch

@@ -53,7 +53,7 @@ void free_all(pod_ctx *ctx)
                     ctx->rho,  ctx->Vt,   ctx->wr,    ctx->rows, ctx->rcnt, ctx->row_log, ctx->rcnt_log,
                     ctx->ws,   ctx->ckU,  ctx->ckS,   ctx->ckR,  ctx->ckMeta, ctx->dsb, ctx->partb, ctx->Gext,
                     ctx->adj_ws, ctx->sbar[0], ctx->sbar[1], ctx->lossp, ctx->Wt, ctx->Ubar[0], ctx->Ubar[1],
-                    ctx->sin_log, ctx->tsplit};
+                    ctx->sin_log, ctx->tsplit, ctx->qws};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -364,6 +364,7 @@ pod_status pod::ctx_bind(pod_ctx *ctx, void *A_dev, int64_t n, int64_t lda, uint
 {
     if (!ctx || !A_dev || n < 1 || n > ctx->n_cap || lda < ctx->prm.m) return POD_EINVAL;
     if (ctx->failed) return POD_EHIP;
+    ctx->proj_it = -1;   // a fresh run: no Rayleigh-Ritz values yet
     ctx->prm.n = n;
     ctx->prm.lda = lda;
     ctx->prm.block = block;
@@ -592,6 +593,9 @@ pod_status pod::ctx_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *
     if (s != POD_OK) return s;
     if (ctx->hs.flags & FLAG_NONFINITE) return POD_ENONFINITE;
     if (ctx->hs.flags & FLAG_NOCONV) return POD_ENOCONV;
+    ctx->proj_it = ctx->hs.it;
+    ctx->proj_k = k;
+    ctx->proj_rank = rs;
     return POD_OK;
 }
 

@@ -51,6 +51,11 @@ struct pod_ctx {
     pod::DevState *dsb = nullptr;
     double *partb = nullptr, *Gext = nullptr, *adj_ws = nullptr, *sbar[2] = {nullptr, nullptr}, *lossp = nullptr;
     void *Wt = nullptr, *Ubar[2] = {nullptr, nullptr};
+    // the last pod_project (merge count, pairs written, Rayleigh-Ritz rank)
+    // and the workspace of pod_wedin_bound (allocated at its first call)
+    int32_t proj_it = -1, proj_k = 0, proj_rank = 0;
+    double *qws = nullptr;
+    size_t qws_n = 0;
 };
 
 namespace pod {

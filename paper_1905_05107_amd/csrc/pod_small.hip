@@ -905,11 +905,13 @@ __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
     __syncthreads();
     for (int idx = threadIdx.x; idx < r * r; idx += NT) a.GB[idx] = S[idx];
     tridiag(S, r, sd, se, stau, spv, ssc);
-    bisect_top(sd, se, r, k, sev, se2, ssc);
+    // one value more than the k pairs when r > k: sigma_{k+1} of the quality measure
+    const int kv = (k < r) ? k + 1 : k;
+    bisect_top(sd, se, r, kv, sev, se2, ssc);
     tri_invit(sd, se, r, sev, k, Y, lu, scl);
     tridiag_backtransform(S, stau, r, Y, k, sdots);
     for (int idx = threadIdx.x; idx < r * k; idx += NT) a.UB[idx] = Y[idx];
-    for (int i = threadIdx.x; i < k; i += NT) a.sig[i] = sqrt(fmax(sev[i], 0.0));
+    for (int i = threadIdx.x; i < kv; i += NT) a.sig[i] = sqrt(fmax(sev[i], 0.0));
     for (int idx = threadIdx.x; idx < r * k; idx += NT) store_c(a.Zc, a.prec, idx, Y[idx]);
 }
 

@@ -645,3 +645,64 @@ def test_bf16_split_rejected_where_unsupported(c1):
     A32 = _dev(c1.A.astype(np.float32))
     with pytest.raises(pod.PodError):
         pod.Batch([A32], [dict(k=10, c=20, precision=pod.POD_BF16_REFINE)])
+
+
+# ------------------------------------------------------------------ quality measure (Eq. ang_meas)
+
+def _wedin_case(A, kw, precision, tol_rs, tol_om):
+    from oracle.wedin import wedin_measure
+    ref = oracle_isma(A, IsmaParams(**kw), elem_bytes=np.asarray(A).dtype.itemsize)
+    _, s_or, _ = oracle.project(np.asarray(A, np.float64), ref.U_merge, want_v=False)
+    k = kw["k"]
+    with pod.PodContext(_dev(A), precision=precision, **kw) as ctx:
+        ctx.run()
+        U, sig, V = ctx.project(want_v=True)
+        out = ctx.wedin_bound(U, V)
+        rn, sn, _, _ = wedin_measure(A, U.cpu().numpy(), sig.cpu().numpy(), V.cpu().numpy(), s_or[k])
+    s = sig.cpu().numpy()
+    om = min(abs(s[k - 1] - s_or[k]), s[k - 1])
+    # R and S from the same modes: only the summation order differs (FP64 on both sides)
+    assert out[0] == pytest.approx(rn, rel=tol_rs)
+    assert out[1] == pytest.approx(sn, rel=tol_rs, abs=1e-12 * s[0])
+    assert out[2] == pytest.approx(om, rel=tol_om)
+    assert out[3] == pytest.approx(math.sqrt(out[0] ** 2 + out[1] ** 2) / out[2], rel=1e-12)
+    return out
+
+
+def test_wedin_bound_fp64(c1):
+    """C1 (2000 x 500, FP64; ragged against the 256-row stripes and the
+    64-column chunks), r = 2k."""
+    print("wedin fp64 c1", flush=True)
+    out = _wedin_case(c1.A, _c1_params(r=20), pod.POD_F64, 1e-9, 1e-9)
+    assert 0.0 < out[3] < math.sqrt(2 * 10)
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_wedin_bound_fp32_paths(waves_small, precision):
+    """20000 x 400 FP32 travelling waves, k = 20, r = 30: the modes in FP32,
+    the residuals in FP64; omega^ agrees with the oracle's Rayleigh-Ritz
+    values to the FP32 path's accuracy."""
+    prec = pod.POD_F32 if precision == "f32" else pod.POD_BF16_REFINE
+    kw = dict(k=20, c=40, r=30, seed=2002, theta_tol=1e-5)
+    print("wedin", precision, flush=True)
+    _wedin_case(waves_small, kw, prec, 1e-7, 1e-4)
+
+
+def test_wedin_bound_state_errors(c1):
+    """Before pod_project: POD_ESTATE; with r = k there is no sigma_{k+1}:
+    POD_EINVAL."""
+    A = _dev(c1.A)
+    print("wedin errors", flush=True)
+    with pod.PodContext(A, precision=pod.POD_F64, **_c1_params(r=20)) as ctx:
+        ctx.run(n_iter=3)
+        U0 = torch.zeros((c1.A.shape[0], 10), dtype=torch.float64, device="cuda")
+        V0 = torch.zeros((c1.A.shape[1], 10), dtype=torch.float64, device="cuda")
+        with pytest.raises(pod.PodError) as e:
+            ctx.wedin_bound(U0.T.contiguous().T, V0.T.contiguous().T)
+        assert e.value.status == pod.POD_ESTATE
+    with pod.PodContext(A, precision=pod.POD_F64, **_c1_params()) as ctx:
+        ctx.run(n_iter=3)
+        U, _, V = ctx.project(want_v=True)
+        with pytest.raises(pod.PodError) as e:
+            ctx.wedin_bound(U, V)
+        assert e.value.status == pod.POD_EINVAL
