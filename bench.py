@@ -422,6 +422,25 @@ def main():
     roof["traffic"] = measured_traffic(dominant, args.workload)
     roof.update({"kernel_class": dominant, "avg_launch_us": round(avg_s * 1e6, 2),
                  "launches_per_step": round(per_step_launches, 1)})
+    # quality measure of Eq. (ang_meas) on the converged modes, outside the
+    # timed steps: a run with r = 2k (omega^ needs sigma_{k+1}), then
+    # pod_wedin_bound (two passes over A, FP64 accumulation) timed alone
+    quality = None
+    if args.workload == "c2" and 2 * k + c <= 160:
+        with pod.PodContext(A, precision=main_prec, r=2 * k, **kw) as ctx:
+            ctx.run(chunk=RUN_CHUNK)
+            Uq, _, Vq = ctx.project(want_v=True)
+            ctx.wedin_bound(Uq, Vq)   # the first call allocates the workspace
+            reps = 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                q = ctx.wedin_bound(Uq, Vq)
+            wed_s = (time.perf_counter() - t0) / reps
+        wb = 2 * m * n * 4
+        quality = {"r": 2 * k, "norm_R": q[0], "norm_S": q[1], "omega": q[2], "bound": q[3],
+                   "ms": round(wed_s * 1e3, 3), "hbm_bytes_algorithmic": wb,
+                   "hbm_gbs": round(wb / wed_s / 1e9, 1), "hbm_frac": round(wb / wed_s / 1e9 / HBM_PEAK_GBS, 4)}
+
     # the other classes, from the per-class pre-pass
     others = {}
     for cls, (ln, ms) in per_class.items():
@@ -469,6 +488,7 @@ def main():
         "kernel_ms_per_step": {kc: round(v[1], 3) for kc, v in per_class.items()},
         "adjoint_included": False,
         "gen_s": round(t_gen, 2),
+        "quality_measure": quality,
     }
     if args.workload == "c3":
         # the oracle's FP64 copy of a 1M x 4k matrix alone is 32 GB of host memory

@@ -158,7 +158,9 @@ void launch_r_k(const pod_ctx *ctx, const void *V, const void *U, int k, double 
 {
     if (k <= 8) launch_r<8, TA, TV>(ctx, V, U, k, part, nb);
     else if (k <= 16) launch_r<16, TA, TV>(ctx, V, U, k, part, nb);
+    else if (k <= 24) launch_r<24, TA, TV>(ctx, V, U, k, part, nb);
     else if (k <= 32) launch_r<32, TA, TV>(ctx, V, U, k, part, nb);
+    else if (k <= 48) launch_r<48, TA, TV>(ctx, V, U, k, part, nb);
     else launch_r<64, TA, TV>(ctx, V, U, k, part, nb);
 }
 
