@@ -706,3 +706,24 @@ def test_wedin_bound_state_errors(c1):
         with pytest.raises(pod.PodError) as e:
             ctx.wedin_bound(U, V)
         assert e.value.status == pod.POD_EINVAL
+
+
+def test_wedin_bound_full_size():
+    """The measured workload's size (200,000 x 2,000 FP32 travelling waves,
+    k = 20, c = 40, r = 40): ||R|| and ||S|| against FP64 numpy on the same
+    modes, omega^ and the bound consistent with the returned values."""
+    from oracle.wedin import wedin_measure
+    At = snapgen.travelling_waves(200_000, 2_000, 60, 1.5, 1e-3, seed=1002, device="cuda")
+    A = At.T
+    print("wedin full size", flush=True)
+    with pod.PodContext(A, precision=pod.POD_F32, k=20, c=40, r=40, seed=2002, theta_tol=1e-5) as ctx:
+        ctx.run()
+        U, sig, V = ctx.project(want_v=True)
+        out = ctx.wedin_bound(U, V)
+    s = sig.cpu().numpy()
+    rn, sn, _, _ = wedin_measure(A.cpu().numpy(), U.cpu().numpy(), s, V.cpu().numpy(), 0.0)
+    assert out[0] == pytest.approx(rn, rel=1e-8)
+    assert out[1] == pytest.approx(sn, rel=1e-6, abs=1e-10 * s[0])
+    assert 0.0 < out[2] <= s[-1]
+    assert out[3] == pytest.approx(math.sqrt(out[0] ** 2 + out[1] ** 2) / out[2], rel=1e-12)
+    assert out[3] < math.sqrt(2 * 20)
