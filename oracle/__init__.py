@@ -8,7 +8,11 @@ never calls the oracle.
 
 The numerical primitives live in ``pod_oracle.c`` (plain C, FP64, single
 thread, no BLAS/LAPACK); ``isma.py`` strings them together in the order of
-the paper's Alg. 1 (ISMA), Alg. 2 (BLOCK MERGE) and Alg. 3 (incremental POD).
+the paper's Alg. 1 (ISMA, with the UNF / L2N / ORT column and L2 / LS row
+strategies and the optional row centring), Alg. 2 (BLOCK MERGE) and Alg. 3
+(incremental POD); ``oneshot.py`` follows Alg. 4 (LTSVD) and Alg. 5 (CTSVD) of
+Appendix A; ``adjoint.py`` the reverse pass of the merge chain; ``wedin.py``
+the quality measure of Eq. (ang_meas).
 """
 from __future__ import annotations
 

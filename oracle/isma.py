@@ -17,6 +17,8 @@ from . import (col_sqnorms, draw, jacobi_eig, merge, project, quantize, row_sqno
                subspace_sines, unique)
 
 U_F64 = 2.0 ** -53
+# ORT residuals at or below this fraction of |a_i|^2 count as zero (FP64 runs)
+ORT_FLOOR_F64 = 1e-12
 
 
 @dataclass
@@ -37,7 +39,7 @@ class IsmaParams:
     w: int = 0
     r: Optional[int] = None
     theta_tol: float = 1e-10
-    col_strategy: str = "l2n"      # "l2n" | "unf"
+    col_strategy: str = "l2n"      # "l2n" | "unf" | "ort"
     row_strategy: str = "l2"       # "l2" | "ls"
     criterion: str = "subspace"    # "subspace" | "mode"
     max_iter: int = 1 << 30
@@ -98,14 +100,63 @@ def sign_normalise(U, V=None):
     return U, V
 
 
-def _mode_sines(Uold, Unew):
-    """Sine of the angle between u_old,i and u_new,i (sign free), per mode."""
+def mode_sines(Uold, Unew):
+    """The "mode" convergence criterion of Alg. 1 (xi_i = u~_i^T u^_i): the sine
+    of the angle between u_old,i and u_new,i for each mode i, measured sign
+    free as |u_new,i - u_old,i (u_old,i^T u_new,i)| (both unit vectors).
+    Reading: sines rather than the paper's cosines, which cannot resolve
+    angles below ~1e-8 in FP64."""
     out = np.zeros(Uold.shape[1])
     for i in range(Uold.shape[1]):
         a, b = Uold[:, i], Unew[:, i]
         d = b - a * float(a @ b)
         out[i] = float(np.sqrt(d @ d))
     return out
+
+
+def center_rows(A):
+    """Row centring of the snapshot matrix (Sec. 1: the POD is taken of the
+    mean-subtracted snapshots).  mean_i = (sum_j a_ij) / n, summed in FP64 in
+    column order; returns (A - mean 1^T rounded to A's dtype, mean)."""
+    A = np.asarray(A)
+    X = np.asarray(A, dtype=np.float64)
+    m, n = X.shape
+    mean = np.zeros(m)
+    for j in range(n):
+        mean += X[:, j]
+    mean /= float(n)
+    out = np.asfortranarray((X - mean[:, None]).astype(A.dtype))
+    return out, mean
+
+
+def ls_row_weights(U_state, k: int):
+    """Leverage-score row weights of GET UPDATE (Alg. 1, rows branch, second
+    iteration on): q_i proportional to |u^i|^2, the squared norm of row i of
+    the current first k modes U~_k (the paper's q_i = |u^i|^2 / k, whose
+    normalisation the integer weights absorb).  Columns beyond the k-th of the
+    state do not enter."""
+    kk = min(int(k), U_state.shape[1])
+    return row_sqnorms(np.asfortranarray(U_state[:, :kk]))
+
+
+def ort_col_weights(X, U_state, inS, rel_floor: float = ORT_FLOOR_F64):
+    """ORT column weights of Alg. 1 (Sec. "Column sampling" (c)):
+    p_i proportional to |a_i - U~ U~^T a_i|^2 over the unsampled set S, with U~
+    the whole current state (r' columns), the residual formed explicitly in
+    FP64.  Columns outside S get 0.  Readings: a residual at or below
+    rel_floor |a_i|^2 is zero (the column lies in the current subspace to
+    working accuracy; without this floor rounding noise would decide the
+    draw), and the weights are quantised after this masking (their maximum is
+    taken over S)."""
+    X = np.asarray(X, dtype=np.float64)
+    U = np.asarray(U_state, dtype=np.float64)
+    rho = np.zeros(X.shape[1])
+    for i in np.flatnonzero(inS):
+        a = X[:, i]
+        res = a - U @ (U.T @ a)
+        v = float(res @ res)
+        rho[i] = v if v > rel_floor * float(a @ a) else 0.0
+    return rho
 
 
 def sample_and_scale_unique_rows(D, wr, w, seed, it, block=0, forced=None):
@@ -133,7 +184,9 @@ def get_update(X, prm: IsmaParams, it: int, inS: np.ndarray, wq: np.ndarray, U_s
     column of S can be drawn (S empty, or every weight in S is zero).
 
     Column weights: L2N every iteration; UNF uniform over S from the second
-    iteration (Table of sampling strategies).  Rows (w > 0): L2 norms of the
+    iteration; ORT the squared residuals of the columns of S against the
+    current state from the second iteration (Table of sampling strategies,
+    Sec. "Column sampling").  Rows (w > 0): L2 norms of the
     rows of D, or, from the second iteration, leverage scores |u^i|^2 of the
     current U_k (LS)."""
     n = X.shape[1]
@@ -143,6 +196,8 @@ def get_update(X, prm: IsmaParams, it: int, inS: np.ndarray, wq: np.ndarray, U_s
     else:
         if prm.col_strategy == "unf" and it > 0:
             wcol = inS.astype(np.uint64)
+        elif prm.col_strategy == "ort" and it > 0 and U_state.shape[1] > 0:
+            wcol = quantize(ort_col_weights(X, U_state, inS))
         else:
             wcol = np.where(inS, wq, np.uint64(0)).astype(np.uint64)
         if int(wcol.astype(object).sum()) == 0:
@@ -155,7 +210,7 @@ def get_update(X, prm: IsmaParams, it: int, inS: np.ndarray, wq: np.ndarray, U_s
     log = IterLog(cols=cols, col_counts=ccnt)
     if prm.w > 0:
         if prm.row_strategy == "ls" and it > 0:
-            rho = row_sqnorms(U_state[:, :min(prm.k, U_state.shape[1])])
+            rho = ls_row_weights(U_state, prm.k)
         else:
             rho = row_sqnorms(D)
         wr = quantize(rho)
@@ -222,7 +277,7 @@ def isma(A, prm: IsmaParams, elem_bytes: Optional[int] = None, n_iter: Optional[
         if it > 0 and U.shape[1] > 0 and Unew.shape[1] > 0:
             kk = min(k, U.shape[1], Unew.shape[1])
             if prm.criterion == "mode":
-                log.sin_theta = float(np.max(_mode_sines(U[:, :kk], Unew[:, :kk])))
+                log.sin_theta = float(np.max(mode_sines(U[:, :kk], Unew[:, :kk])))
             else:
                 log.sin_theta = float(np.max(subspace_sines(U[:, :kk], Unew[:, :kk])))
         log.rank = Unew.shape[1]

@@ -1,13 +1,13 @@
 """CPU-side checks of the C ABI: the library loads, exports every entry point
 declared in include/pod.h, and its host-only helpers agree with the paper's
-formulas as the oracle states them.  No device work is launched here."""
+formulas (hand-derived values).  No device work is launched here."""
 import os
 import re
 
 import pytest
 
 import paper_1905_05107_amd as pod
-from oracle.isma import sample_size_ctsvd, sample_size_ltsvd
+from test_oracle_pins_sampling import CTSVD_TABLE, LTSVD_TABLE
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -33,12 +33,26 @@ def test_library_exports_every_declared_symbol():
     assert set(pod.EXPORTS) == declared
 
 
-@pytest.mark.parametrize("k,eps,delta", [(10, 0.7, 0.6), (2, 0.7, 0.6), (20, 0.6, 0.6), (5, 0.6, 0.6), (10, 1.0, 0.75)])
-def test_sample_size_helpers(k, eps, delta):
+@pytest.mark.parametrize("args,want", LTSVD_TABLE)
+def test_sample_size_ltsvd_hand_derived(args, want):
     if not os.path.exists(pod.LIB_PATH):
         pytest.skip("libpod.so not built")
-    assert pod.sample_size("ltsvd", k, eps, delta) == sample_size_ltsvd(k, eps, delta)
-    assert pod.sample_size("ctsvd", k, eps, delta) == sample_size_ctsvd(k, eps, delta)
+    assert pod.sample_size("ltsvd", *args) == want
+
+
+@pytest.mark.parametrize("args,want", CTSVD_TABLE)
+def test_sample_size_ctsvd_hand_derived(args, want):
+    if not os.path.exists(pod.LIB_PATH):
+        pytest.skip("libpod.so not built")
+    assert pod.sample_size("ctsvd", *args) == want
+
+
+def test_sample_size_rejects_invalid_arguments():
+    if not os.path.exists(pod.LIB_PATH):
+        pytest.skip("libpod.so not built")
+    for kind, k, eps, delta in [("ltsvd", 0, 0.5, 0.5), ("ltsvd", 3, 0.0, 0.5), ("ltsvd", 3, 0.5, 1.0),
+                                ("ctsvd", 3, 0.5, 2.0), ("ctsvd", 3, -1.0, 0.5)]:
+        assert pod.sample_size(kind, k, eps, delta) == -1
 
 
 def test_status_strings():
