@@ -1,24 +1,29 @@
 """Time-to-k-modes of the iterative sample-and-merge POD on one MI355X.
 
-Workload: 200,000 x 2,000 FP32 snapshot matrix (60 travelling waves,
-a_j = j^-1.5, N(0, 1e-3) noise, rows centred), k = 20 modes, c = 40 column
-draws per iteration, stop at a largest principal angle below 1e-5 between
-successive estimates.  One step = one whole ISMA run (set-up pass with the
-column norms, sample/merge iterations until convergence, final projection
+Default workload: 1,000,000 x 4,000 FP32 snapshot matrix (16 GB; 200
+travelling waves, a_j = j^-1.2, N(0, 1e-3) noise, rows centred), k = 50 modes,
+c = 100 column draws per iteration (merge width 150), stop at a largest
+principal angle below 1e-5 between successive estimates (or when every column
+has been drawn).  One step = one whole ISMA run (set-up pass with the column
+norms, sample/merge iterations until the stop rule holds, final projection
 with Rayleigh-Ritz) on the matrix already resident in HBM.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c3|c2|c4|c5]
 
-Prints one JSON line.  Besides the timed FP32-merge path it times the plain
-FP64 GPU path, measures the dominant kernel class with HIP events during the
-timed steps (roofline), and times the FP64 CPU oracle on a bounded sample
-(cpu_baseline).
+Prints one JSON line.  `value` is the plain FP64 GPU path (FP64 matrix cores,
+FP64 basis).  Beside it: the split-BF16 and FP32 merge paths, each with its
+time, merge count, stop reason, singular-value error and largest principal
+angle against the FP64 path's modes, and its speedup over the FP64 path
+(reported only where that angle is within 1e-5); the dominant m-pass kernel
+class of the FP64 path against its roof, timed with HIP events during the
+timed steps; the latency of the small FP64 stages; and the FP64 CPU oracle
+timed on row subsamples of the same matrix at one thread and at the host's
+threads (cpu_baseline).
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,91 +34,103 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-k-modes & HBM GB/s: mixed-prec+adjoint vs plain FP64 at θ_max≤1e-5"
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"f64": 78.6, "f32_mfma": 157.3, "f64_vector": 78.6}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 CLASSES = ["colnorms", "draw", "gram", "gram_reduce", "chol", "tall", "svd", "project", "rr", "sign"]
+MPASS = ["colnorms", "gram", "tall", "project"]
+SMALL = ["draw", "gram_reduce", "chol", "svd", "rr", "sign"]
+ANGLE_TOL = 1e-5
+
+WORKLOADS = {
+    # travelling waves: rows, columns, modes reported, draws per iteration,
+    # waves, amplitude exponent, data seed, sampling seed
+    "c3": dict(m=1_000_000, n=4_000, k=50, c=100, modes=200, alpha=1.2, dseed=1003, sseed=2003),
+    "c2": dict(m=200_000, n=2_000, k=20, c=40, modes=60, alpha=1.5, dseed=1002, sseed=2002),
+}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--m", type=int, default=200_000)
-    ap.add_argument("--n", type=int, default=2_000)
-    ap.add_argument("--k", type=int, default=20)
-    ap.add_argument("--c", type=int, default=40)
-    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5, help="timed steps of the FP64 path")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--other-steps", type=int, default=5, help="timed steps of each reduced-precision path")
+    ap.add_argument("--workload", choices=["c3", "c2", "c5", "c4"], default="c3",
+                    help="c3: travelling waves 1M x 4k, k=50, c=100 (default); c2: travelling waves 200k x 2k, "
+                         "k=20, c=40; c5: 64-matrix batch, forward + gradient; c4: Alg. 3 over pinned host "
+                         "blocks of 2M x 512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-merges", type=int, default=12, help="oracle merges timed for the CPU baseline sample")
-    ap.add_argument("--workload", choices=["c2", "c3", "c5", "c4"], default="c2",
-                    help="c2: travelling waves 200k x 2k (default); c3: travelling waves 1M x 4k, k=50, c=100; "
-                         "c5: 64-matrix batch, forward + gradient; c4: Alg. 3 over pinned host blocks of 2M x 512")
-    ap.add_argument("--precision", choices=["f32", "bf16"], default=None,
-                    help="timed merge path: FP32 matrix cores or split-BF16 (default: f32 for c2, bf16 for c3)")
+    ap.add_argument("--cpu-rows", type=int, default=20_000, help="rows of the oracle's larger row subsample")
+    ap.add_argument("--cpu-merges", type=int, default=4, help="oracle merges timed per row subsample")
     ap.add_argument("--c5-count", type=int, default=64)
     ap.add_argument("--c4-blocks", type=int, default=8, help="blocks of 512 columns (32: the full 16,000)")
     return ap.parse_args()
 
 
-def kernel_work(cls, m, n, k, c, p, r, launches, bf16=False):
-    """Algorithmic work of one launch of a kernel class, averaged over the
-    launches of one step: (bound, amount, unit, hbm_bytes) with amount in
-    bytes or flops.
+def kernel_work(cls, path, m, n, k, p, r, launches):
+    """Algorithmic work of one launch of a kernel class on a precision path,
+    averaged over the launches of one step: (bound, amount, unit, hbm_bytes,
+    peak key).
 
-    colnorms / project: one pass over A (m n 4 bytes).  gram: symmetric Gram
-    m p (p+1) flops, reading m p 4 bytes.  tall: Y = X0 T1 (m p p MACs) and
-    U = Y Z2 (m p r MACs), averaged: m p (p + r) flops, reading m p 4 and
-    writing m (p + r) / 2 4 bytes.  svd: FP64 flops of the p x p stage --
-    Cholesky p^3/3, R = R2 R1 p^3/3, H = R R^T p^3/3, tridiagonalisation
-    4 p^3/3, triangular inverse p^3/3, back-transformation 2 p^2 r and
-    Z2 = R2^-1 U_R p^2 r.  chol: G1 = P G0 P, Cholesky p^3/3, inverse p^3/3."""
+    colnorms / project: one pass over A (m n 4 bytes; A is stored FP32).
+    gram: symmetric Gram m p (p+1) flops reading the m x p block (4 bytes per
+    element from A, the basis in the compute type: counted at its own width
+    e).  tall: Y = X0 T1 (m p p MACs) and U = Y Z2 (m p r MACs) averaged:
+    m p (p + r) flops, reading m p e and writing m (p + r) / 2 e bytes.  The
+    split-BF16 path's Gram and tall transforms are HBM bound (six bf16
+    products per FP32-accurate one put the matrix-core roof at 2.5 PFLOP/s / 6
+    and its ridge at 52 flop/B, above (p+1)/4).  svd: FP64 flops of the p x p
+    stage (Cholesky p^3/3, R = R2 R1 p^3/3, H = R R^T p^3/3,
+    tridiagonalisation 4 p^3/3, triangular inverse p^3/3, back-transformation
+    2 p^2 r, Z2 p^2 r, U_R^T R p^2 r); chol: G1 = P G0 P, Cholesky, inverse."""
+    e = 8 if path == "f64" else 4
     if cls == "colnorms":
-        return "hbm", m * n * 4, "B", m * n * 4
+        return "hbm", m * n * 4, "B", m * n * 4, None
     if cls == "project":
         b = m * n * 4 / max(launches, 1)
-        return "hbm", b, "B", b
+        return "hbm", b, "B", b, None
     if cls == "gram":
-        if bf16:
-            # six BF16 products per FP32-accurate one: the matrix-core roof is
-            # 2.5 PFLOP/s / 6 = 417 TFLOP/s, ridge 52 flop/B > (p+1)/4: HBM bound
-            return "hbm", m * p * 4, "B", m * p * 4
-        return "mfma", m * p * (p + 1), "flop", m * p * 4
+        if path == "bf16":
+            return "hbm", m * p * 4, "B", m * p * 4, None
+        return "mfma", m * p * (p + 1), "flop", m * p * e, path
     if cls == "tall":
-        if bf16:
-            return "hbm", m * p * 4 + m * (p + r) * 2, "B", m * p * 4 + m * (p + r) * 2
-        return "mfma", m * p * (p + r), "flop", m * p * 4 + m * (p + r) * 2
+        hb = m * p * e + m * (p + r) * e // 2
+        if path == "bf16":
+            return "hbm", hb, "B", hb, None
+        return "mfma", m * p * (p + r), "flop", hb, path
     if cls == "svd":
-        return "alu", (8.0 / 3.0) * p ** 3 + 3.0 * p * p * r, "flop", 0
+        return "alu", (8.0 / 3.0) * p ** 3 + 4.0 * p * p * r, "flop", 0, "f64"
     if cls == "chol":
-        return "alu", (2.0 / 3.0) * p ** 3, "flop", 0
-    return None, 0, None, 0
+        return "alu", (2.0 / 3.0) * p ** 3, "flop", 0, "f64"
+    return None, 0, None, 0, None
 
 
+TRAFFIC_FILES = {"c2": "isma_waves200k_hbm_traffic.md", "c3": "isma_waves1M_hbm_traffic.md"}
 TRAFFIC_SOURCES = {"svd": ["pod_small.hip", "pod_rl.h", "pod_big.h", "pod_symeig.h", "pod_internal.h"],
                    "chol": ["pod_small.hip", "pod_rl.h", "pod_big.h", "pod_symeig.h", "pod_internal.h"],
-                   "gram": ["pod_gemm.hip", "pod_internal.h"], "tall": ["pod_gemm.hip", "pod_internal.h"]}
+                   "gram": ["pod_gemm.hip", "pod_internal.h"], "tall": ["pod_gemm.hip", "pod_internal.h"],
+                   "project": ["pod_gemm.hip", "pod_internal.h"], "colnorms": ["pod_sample.hip", "pod_internal.h"]}
 
 
-def measured_traffic(cls, workload):
+def measured_traffic(cls, path, workload):
     """HBM bytes per launch of a kernel class from the committed FETCH_SIZE /
-    WRITE_SIZE summary (profiles/isma_waves200k_hbm_traffic.md), scaled by the
-    copy-kernel factors recorded there; None when the class was not measured,
-    the workload is not the 200,000 x 2,000 one the counters were taken on, or
-    the kernel sources changed since (sha256 prefix mismatch)."""
+    WRITE_SIZE summary of the workload (profiles/), scaled by the copy-kernel
+    factors recorded there; None when the class was not measured on that
+    path and workload, or the kernel sources changed since (sha256 prefix
+    mismatch)."""
     import hashlib
-    root = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(root, "profiles", "isma_waves200k_hbm_traffic.md")
-    if workload != "c2" or cls not in TRAFFIC_SOURCES or not os.path.exists(path):
+    fn = TRAFFIC_FILES.get(workload)
+    path_md = os.path.join(ROOT, "profiles", fn) if fn else None
+    if not path_md or cls not in TRAFFIC_SOURCES or not os.path.exists(path_md):
         return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES[cls]:
-        with open(os.path.join(root, "paper_1905_05107_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_1905_05107_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     cur = h.hexdigest()[:16]
-    for line in open(path):
+    for line in open(path_md):
         parts = line.split()
-        if len(parts) >= 3 and parts[0] == "traffic" and parts[1] == cls:
-            kv = dict(p.split("=", 1) for p in parts[2:])
+        if len(parts) >= 3 and parts[0] == "traffic" and parts[1] == f"{path}:{cls}":
+            kv = dict(q.split("=", 1) for q in parts[2:])
             if kv.get("sources") != cur:
                 return None
             kib = float(kv["fetch_kib"]) * float(kv["fetch_factor"]) + float(kv["write_kib"]) * float(kv["write_factor"])
@@ -136,64 +153,224 @@ def real_launches(cls, launches, iters):
     return max(launches - per * (enq - iters), 1)
 
 
-def roofline_entry(bound, amount, avg_s, hbm_bytes):
+def roofline_entry(bound, amount, avg_s, hbm_bytes, peak_key):
     if bound == "hbm":
         a = amount / avg_s / 1e9
         return {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(a / HBM_PEAK_GBS, 4)}
     if bound == "mfma":
         a = amount / avg_s / 1e12
-        e = {"bound": "mfma", "achieved": round(a, 3), "peak": PEAK_TFLOPS["f32_mfma"], "unit": "TFLOP/s",
-             "frac": round(a / PEAK_TFLOPS["f32_mfma"], 5)}
+        pk = PEAK_TFLOPS[peak_key]
+        e = {"bound": "mfma", "achieved": round(a, 3), "peak": pk, "unit": "TFLOP/s", "frac": round(a / pk, 4),
+             "peak_dtype": peak_key}
         if hbm_bytes:
             e["hbm_gbs"] = round(hbm_bytes / avg_s / 1e9, 1)
         return e
     a = amount / avg_s / 1e12
-    return {"bound": "alu", "achieved": round(a, 6), "peak": PEAK_TFLOPS["f64_vector"], "unit": "TFLOP/s",
-            "frac": round(a / PEAK_TFLOPS["f64_vector"], 7),
-            "frac_of_one_cu": round(a / (PEAK_TFLOPS["f64_vector"] / 256), 4)}
+    return {"bound": "alu", "achieved": round(a, 6), "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
+            "frac": round(a / PEAK_TFLOPS["f64"], 7), "frac_of_one_cu": round(a / (PEAK_TFLOPS["f64"] / 256), 4)}
 
 
-def cpu_baseline(At, m, n, k, c, iters_gpu, merges):
-    """The FP64 oracle on a bounded sample of the same workload (single
-    thread): the column norms over all of A, `merges` BLOCK MERGEs of the
-    run's first draws, and the final projection on 1/5 of the columns;
-    extrapolated to the whole run (norms + iters x mean merge + 5 x sample
-    projection)."""
+def cpu_baseline(At, wl, iters, draws, rows_big, merges):
+    """The FP64 oracle on row subsamples of the same matrix (rows_big evenly
+    spaced rows and every second of them), timed at one thread and at the
+    host's threads: the column-norm pass over all columns, `merges` BLOCK
+    MERGEs with the GPU run's own draws (the draws do not depend on the path),
+    and the final projection on 1/8 of the columns.  Extrapolated to the
+    whole run: norms and projection linearly in m (and n), the merge cost as
+    a + b m fitted through the two subsample sizes (a: the p x p work, b: the
+    m-length work), times the run's merge count."""
     import numpy as np
 
     import oracle
-    from oracle.isma import IsmaParams, get_update
 
-    A = np.asfortranarray(At.cpu().numpy().T.astype(np.float64))
-    prm = IsmaParams(k=k, c=c, seed=2002, theta_tol=1e-5)
-    t0 = time.perf_counter()
-    nu = oracle.col_sqnorms(A, 4)
-    wq = oracle.quantize(nu)
-    t_norm = time.perf_counter() - t0
-    inS = np.ones(n, dtype=bool)
-    U = np.zeros((m, 0), order="F")
-    s = np.zeros(0)
-    t0 = time.perf_counter()
-    for it in range(merges):
-        C, _ = get_update(A, prm, it, inS, wq, U)
-        U, s = oracle.merge(U, s, C, k)
-    t_merge = (time.perf_counter() - t0) / merges
-    nsub = max(n // 5, 1)
-    t0 = time.perf_counter()
-    oracle.project(A[:, :nsub], U, want_v=False)
-    t_proj = (time.perf_counter() - t0) * (n / nsub)
-    est = t_norm + iters_gpu * t_merge + t_proj
-    sample_s = t_norm + merges * t_merge + t_proj * nsub / n
+    m, n, k = wl["m"], wl["n"], wl["k"]
+    stride = max(m // rows_big, 1)
+    X2 = np.asfortranarray(At[:, ::stride][:, :rows_big].cpu().numpy().T.astype(np.float64))
+    X1 = np.asfortranarray(X2[::2])
+    m2, m1 = X2.shape[0], X1.shape[0]
+    nsub = max(n // 8, 1)
+    nmerge = min(merges, len(draws))
+    host_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = {}
+    for th in sorted({1, host_threads}):
+        oracle.set_threads(th)
+        t0 = time.perf_counter()
+        oracle.col_sqnorms(X2, 4)
+        t_norm = time.perf_counter() - t0
+        per = []
+        for X in (X1, X2):
+            U = np.zeros((X.shape[0], 0), order="F")
+            s = np.zeros(0)
+            t0 = time.perf_counter()
+            for it in range(nmerge):
+                U, s = oracle.merge(U, s, np.asfortranarray(X[:, draws[it]]), k)
+            per.append((time.perf_counter() - t0) / nmerge)
+        t0 = time.perf_counter()
+        oracle.project(X2[:, :nsub], U, want_v=False)
+        t_proj = time.perf_counter() - t0
+        b = (per[1] - per[0]) / (m2 - m1)
+        a = per[1] - b * m2
+        est = t_norm * (m / m2) + iters * max(a + b * m, per[1]) + t_proj * (m / m2) * (n / nsub)
+        sample_s = t_norm + nmerge * (per[0] + per[1]) + t_proj
+        out[th] = (est, t_norm, per, t_proj, sample_s)
+    oracle.set_threads(host_threads)
+    th = max(out)
+    est, t_norm, per, t_proj, sample_s = out[th]
     return {
         "value": round(est * 1e3, 1),
         "unit": "ms per time-to-k-modes (extrapolated)",
-        "cores": 1,
+        "cores": th,
         "kind": "oracle",
-        "sample": (f"full column-norm pass ({t_norm:.2f} s), {merges} merges of the run's first draws "
-                   f"({t_merge:.2f} s each), final projection on {nsub}/{n} columns; extrapolated to "
-                   f"{iters_gpu} merges and all columns; {sample_s:.1f} s of CPU work, single thread"),
+        "single_thread_value": round(out[1][0] * 1e3, 1),
+        "sample": (f"rows {m2} (every {stride}th) and {m1}, all {n} columns, FP64: column-norm pass "
+                   f"{t_norm:.2f} s, {nmerge} merges with the run's draws at {per[0]:.3f} / {per[1]:.3f} s each, "
+                   f"projection on {nsub} columns {t_proj:.2f} s at {th} threads ({sample_s:.1f} s; "
+                   f"{out[1][4]:.1f} s at 1 thread); extrapolated to {m} rows, {n} columns and {iters} merges "
+                   f"(merge cost a + b m through the two row counts)"),
     }
+
+
+def compare_modes(U, s, U64, s64):
+    """(largest relative singular-value difference, sine of the largest
+    principal angle) of (U, s) against the FP64 path's (U64, s64), in FP64 on
+    the device: sines from the residual U - U64 (U64^T U)."""
+    import torch
+    kk = min(U.shape[1], U64.shape[1])
+    Ud = U[:, :kk].to(torch.float64)
+    P = U64[:, :kk].T @ Ud
+    R = Ud - U64[:, :kk] @ P
+    sin2 = torch.linalg.eigvalsh(R.T @ R).max().clamp_min(0.0)
+    rel = ((s[:kk] - s64[:kk]).abs() / s64[:kk]).max()
+    return float(rel), float(sin2.sqrt())
+
+
+def run_single(args):
+    import torch
+
+    import paper_1905_05107_amd as pod
+    import snapgen
+
+    wl = WORKLOADS[args.workload]
+    m, n, k, c = wl["m"], wl["n"], wl["k"], wl["c"]
+    p = k + min(c, n)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    At = snapgen.travelling_waves(m, n, wl["modes"], wl["alpha"], 1e-3, seed=wl["dseed"], device="cuda")
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    A = At.T
+    kw = dict(k=k, c=c, seed=wl["sseed"], theta_tol=ANGLE_TOL)
+    precs = {"f64": pod.POD_F64, "bf16": pod.POD_BF16_REFINE, "f32": pod.POD_F32}
+
+    def step(path):
+        with pod.PodContext(A, precision=precs[path], **kw) as ctx:
+            ctx.run(chunk=RUN_CHUNK)
+            inf = ctx.info()
+            U, s, _ = ctx.project(want_v=False)
+        return U, s, inf
+
+    def classes(path, iters):
+        """Per-class HIP-event time of one step (one class timed per step)."""
+        per = {}
+        for cls in CLASSES:
+            pod.profile_enable(cls)
+            step(path)
+            torch.cuda.synchronize()
+            per[cls] = pod.profile_read()
+        pod.profile_enable(None)
+        rows = {}
+        for cls, (ln, ms) in per.items():
+            ln = real_launches(cls, ln, iters)
+            b, amt, _, hb, pk = kernel_work(cls, path, m, n, k, p, k, ln)
+            e = {"ms_per_step": round(ms, 3), "launches_per_step": ln, "avg_launch_us": round(ms * 1e3 / max(ln, 1), 2)}
+            if b is not None and ln > 0:
+                e.update(roofline_entry(b, amt, ms / 1e3 / ln, hb, pk))
+            rows[cls] = e
+        return rows
+
+    def timed(path, steps, prof_cls=None):
+        for _ in range(max(args.warmup, 1)):
+            step(path)
+        if prof_cls:
+            pod.profile_enable(prof_cls)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = step(path)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        prof = pod.profile_read() if prof_cls else None
+        pod.profile_enable(None)
+        return sec, out, prof
+
+    # per-class pre-pass of the FP64 path picks its dominant m-pass class
+    U64, s64, inf64 = step("f64")
+    iters64 = inf64.iter
+    cls64 = classes("f64", iters64)
+    dominant = max(MPASS, key=lambda q: cls64[q]["ms_per_step"])
+
+    # timed region: the plain FP64 path, its dominant class timed live
+    sec64, (U64, s64, inf64), (dl, dms) = timed("f64", args.steps, dominant)
+    per_step = real_launches(dominant, dl / args.steps, inf64.iter)
+    avg_s = dms / 1e3 / max(per_step * args.steps, 1)
+    b, amt, _, hb, pk = kernel_work(dominant, "f64", m, n, k, p, k, per_step)
+    roof = roofline_entry(b, amt, avg_s, hb, pk)
+    roof["traffic"] = measured_traffic(dominant, "f64", args.workload)
+    roof.update({"kernel_class": dominant, "path": "f64", "avg_launch_us": round(avg_s * 1e6, 2),
+                 "launches_per_step": round(per_step, 1)})
+
+    paths = {"f64": {"ms": round(sec64 * 1e3, 3), "merges": inf64.iter,
+                     "stopped_by": pod.STOP_NAMES.get(inf64.stop_reason, "unknown")}}
+    mixed_classes = None
+    for path in ("bf16", "f32"):
+        sec, (U, s, inf), _ = timed(path, args.other_steps)
+        rel, ang = compare_modes(U, s, U64, s64)
+        ok = ang <= ANGLE_TOL
+        paths[path] = {"ms": round(sec * 1e3, 3), "merges": inf.iter,
+                       "stopped_by": pod.STOP_NAMES.get(inf.stop_reason, "unknown"),
+                       "sigma_rel_vs_f64": rel, "angle_vs_f64": ang,
+                       "speedup_vs_f64": round(sec64 / sec, 3) if ok else None,
+                       "speedup_note": None if ok else f"largest angle {ang:.2e} > {ANGLE_TOL:g}: unmeasured"}
+        if path == "bf16":
+            mixed_classes = classes("bf16", inf.iter)
+
+    out = {
+        "metric": METRIC,
+        "value": round(sec64 * 1e3, 3),
+        "unit": "ms per time-to-k-modes (plain FP64 GPU path)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec64 * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"travelling waves {m}x{n} FP32 storage, {wl['modes']} modes a_j=j^-{wl['alpha']}, "
+                               f"noise var 1e-3, rows centred; k={k}, c={c}, theta_tol={ANGLE_TOL:g}",
+                   "m": m, "n": n, "k": k, "c": c, "merge_width": p},
+        "roofline": roof,
+        "paths": paths,
+        "kernel_rooflines_f64": cls64,
+        "kernel_rooflines_bf16": mixed_classes,
+        "small_stage_us_per_launch": {q: {"f64": cls64[q]["avg_launch_us"],
+                                          "bf16": mixed_classes[q]["avg_launch_us"]} for q in SMALL},
+        "adjoint_included": False,
+        "adjoint_note": ("the reverse pass covers merge widths up to 64; this workload merges "
+                         f"{p} columns. The batched workload (--workload c5) times forward plus gradient"),
+        "gen_s": round(t_gen, 2),
+    }
+    if args.no_cpu_baseline:
+        out["cpu_baseline"] = None
+    else:
+        with pod.PodContext(A, precision=pod.POD_F64, **kw) as ctx:
+            ctx.run(n_iter=args.cpu_merges, chunk=RUN_CHUNK)
+            draws = [ctx.indices(t)[0] for t in range(ctx.info().iter)]
+        out["cpu_baseline"] = cpu_baseline(At, wl, inf64.iter, draws, min(args.cpu_rows, m), args.cpu_merges)
+    print(json.dumps(out), flush=True)
 
 
 def run_c5(args):
@@ -333,169 +510,7 @@ def main():
         return run_c5(args)
     if args.workload == "c4":
         return run_c4(args)
-    import torch
-
-    import paper_1905_05107_amd as pod
-    import snapgen
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    if args.workload == "c3":
-        # 1,000,000 x 4,000 FP32 (16 GB), 200 modes, a_j = j^-1.2; k = 50, c = 100
-        m, n, k, c, modes, alpha, dseed, sseed = 1_000_000, 4_000, 50, 100, 200, 1.2, 1003, 2003
-    else:
-        m, n, k, c, modes, alpha, dseed, sseed = args.m, args.n, args.k, args.c, 60, 1.5, 1002, 2002
-    p = k + min(c, n)
-    prec_name = args.precision or ("bf16" if args.workload == "c3" else "f32")
-    main_prec = pod.POD_BF16_REFINE if prec_name == "bf16" else pod.POD_F32
-    other_prec = pod.POD_F32 if prec_name == "bf16" else pod.POD_BF16_REFINE
-    bf16 = prec_name == "bf16"
-    t_gen = time.perf_counter()
-    At = snapgen.travelling_waves(m, n, modes, alpha, 1e-3, seed=dseed, device="cuda")
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
-    A = At.T
-    kw = dict(k=k, c=c, seed=sseed, theta_tol=1e-5)
-    info = {}
-
-    def step(precision):
-        with pod.PodContext(A, precision=precision, **kw) as ctx:
-            ctx.run(chunk=RUN_CHUNK)
-            inf = ctx.info()
-            ctx.project(want_v=False)
-        info["iters"] = inf.iter
-        return inf
-
-    # warm-up, then one step per kernel class with that class timed by HIP events
-    for _ in range(max(args.warmup, 1)):
-        step(main_prec)
-    torch.cuda.synchronize()
-    per_class = {}
-    for cls in CLASSES:
-        pod.profile_enable(cls)
-        step(main_prec)
-        torch.cuda.synchronize()
-        launches, ms = pod.profile_read()
-        per_class[cls] = (launches, ms)
-    pod.profile_enable(None)
-    dominant = max(per_class, key=lambda x: per_class[x][1])
-
-    # timed region (FP32 merge path), dominant class timed live
-    pod.profile_enable(dominant)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(main_prec)
-    torch.cuda.synchronize()
-    sec32 = (time.perf_counter() - t0) / args.steps
-    launches, dom_ms = pod.profile_read()
-    pod.profile_enable(None)
-    iters = info["iters"]
-
-    # plain FP64 GPU path
-    step(pod.POD_F64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.fp64_steps):
-        step(pod.POD_F64)
-    torch.cuda.synchronize()
-    sec64 = (time.perf_counter() - t0) / args.fp64_steps
-    iters64 = info["iters"]
-
-    # the other reduced-precision merge path (split-BF16 or FP32)
-    step(other_prec)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.fp64_steps):
-        step(other_prec)
-    torch.cuda.synchronize()
-    sec_other = (time.perf_counter() - t0) / args.fp64_steps
-    iters_other = info["iters"]
-
-    # roofline of the dominant kernel class (measured live in the timed steps);
-    # the device-driven loop enqueues whole chunks of iterations, and the
-    # launches after the stop return at once: count the launches that merged
-    per_step_launches = real_launches(dominant, launches / args.steps, iters)
-    avg_s = dom_ms / 1e3 / max(per_step_launches * args.steps, 1)
-    bound, amount, unit, hb = kernel_work(dominant, m, n, k, c, p, k, per_step_launches, bf16)
-    roof = roofline_entry(bound, amount, avg_s, hb)
-    roof["traffic"] = measured_traffic(dominant, args.workload)
-    roof.update({"kernel_class": dominant, "avg_launch_us": round(avg_s * 1e6, 2),
-                 "launches_per_step": round(per_step_launches, 1)})
-    # quality measure of Eq. (ang_meas) on the converged modes, outside the
-    # timed steps: a run with r = 2k (omega^ needs sigma_{k+1}), then
-    # pod_wedin_bound (two passes over A, FP64 accumulation) timed alone
-    quality = None
-    if args.workload == "c2" and 2 * k + c <= 160:
-        with pod.PodContext(A, precision=main_prec, r=2 * k, **kw) as ctx:
-            ctx.run(chunk=RUN_CHUNK)
-            Uq, _, Vq = ctx.project(want_v=True)
-            ctx.wedin_bound(Uq, Vq)   # the first call allocates the workspace
-            reps = 5
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                q = ctx.wedin_bound(Uq, Vq)
-            wed_s = (time.perf_counter() - t0) / reps
-        wb = 2 * m * n * 4
-        quality = {"r": 2 * k, "norm_R": q[0], "norm_S": q[1], "omega": q[2], "bound": q[3],
-                   "ms": round(wed_s * 1e3, 3), "hbm_bytes_algorithmic": wb,
-                   "hbm_gbs": round(wb / wed_s / 1e9, 1), "hbm_frac": round(wb / wed_s / 1e9 / HBM_PEAK_GBS, 4)}
-
-    # the other classes, from the per-class pre-pass
-    others = {}
-    for cls, (ln, ms) in per_class.items():
-        ln = real_launches(cls, ln, iters)
-        b2, a2, _, h2 = kernel_work(cls, m, n, k, c, p, k, ln, bf16)
-        if b2 is None or ln == 0:
-            continue
-        e = roofline_entry(b2, a2, ms / 1e3 / ln, h2)
-        e["avg_launch_us"] = round(ms * 1e3 / ln, 2)
-        e["launches_per_step"] = ln
-        others[cls] = e
-
-    # algorithmic HBM bytes of one FP32 step: column norms and projection read
-    # A once each; every merge reads X0 = [U | A(:, I_c)] (m x p) twice,
-    # writes and reads Q1 twice, and writes U_new.
-    per_merge = m * p * 4 * 2 + m * p * 4 * 3 + m * k * 4
-    step_bytes = 2 * m * n * 4 + iters * per_merge
-    out = {
-        "metric": METRIC,
-        "value": round(sec32 * 1e3, 4),
-        "unit": ("ms per time-to-k-modes (split-BF16 MFMA merge path)" if bf16
-                 else "ms per time-to-k-modes (FP32 MFMA merge path)"),
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(sec32 * 1e3, 4),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16" if bf16 else "f32",
-        "data": "synthetic",
-        "config": {"workload": f"travelling waves {m}x{n} FP32, {modes} modes a_j=j^-{alpha}, noise var 1e-3, "
-                               f"rows centred; k={k}, c={c}, theta_tol=1e-5",
-                   "m": m, "n": n, "k": k, "c": c},
-        "roofline": roof,
-        "kernel_rooflines": others,
-        "iters": iters,
-        "fp64_path_ms": round(sec64 * 1e3, 4),
-        "fp64_iters": iters64,
-        "speedup_vs_fp64_path": round(sec64 / sec32, 3),
-        ("f32_path_ms" if bf16 else "bf16_path_ms"): round(sec_other * 1e3, 4),
-        ("f32_iters" if bf16 else "bf16_iters"): iters_other,
-        "merge_precision": prec_name,
-        "step_hbm_gbs": round(step_bytes / sec32 / 1e9, 1),
-        "kernel_ms_per_step": {kc: round(v[1], 3) for kc, v in per_class.items()},
-        "adjoint_included": False,
-        "gen_s": round(t_gen, 2),
-        "quality_measure": quality,
-    }
-    if args.workload == "c3":
-        # the oracle's FP64 copy of a 1M x 4k matrix alone is 32 GB of host memory
-        out["cpu_baseline"] = None
-    elif not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(At, m, n, k, c, iters, args.cpu_merges)
-    print(json.dumps(out), flush=True)
+    return run_single(args)
 
 
 if __name__ == "__main__":

@@ -92,6 +92,20 @@ typedef struct {
     uint64_t block;        /* Philox counter word 2 (column block of Alg. 3)    */
 } pod_params;
 
+/* Why a run of Alg. 1 stops (pod_info.stop_reason): the stop rule of
+ * pod_converged evaluated on the current state, in this priority order. */
+typedef enum {
+    POD_STOP_NONE = 0,       /* no rule holds: more merges can follow          */
+    POD_STOP_NONFINITE = 1,  /* a NaN/Inf was met (POD_ENONFINITE)             */
+    POD_STOP_CONVERGED = 2,  /* from the second merge on, the largest angle     */
+                             /* between successive estimates is below theta_tol */
+    POD_STOP_EXHAUSTED = 3,  /* S has no drawable column left                   */
+    POD_STOP_MAX_ITER = 4,   /* max_iter merges were done                       */
+    POD_STOP_BREAKDOWN = 5   /* a Cholesky of the merge broke down even after   */
+                             /* the shifted retry (POD_ENOTPD); ranked after     */
+                             /* POD_STOP_NONFINITE                               */
+} pod_stop_reason;
+
 /* Host-readable progress of a context (pod_get_info, syncs). */
 typedef struct {
     int32_t iter;          /* merges done                                       */
@@ -100,10 +114,13 @@ typedef struct {
     int32_t h;             /* distinct rows of the last draw                    */
     int32_t exhausted;     /* S had no drawable column at the last pod_sample   */
     int32_t flags;         /* bit 0: shifted Cholesky used; bit 1: non-finite;  */
-                           /* bit 2: Jacobi sweep limit hit                     */
+                           /* bit 2: sweep limit hit; bit 3: all row weights    */
+                           /* zero; bit 4: Cholesky breakdown after the shift   */
     int32_t max_sweeps;    /* most Jacobi sweeps of any merge so far            */
     int32_t total_sweeps;  /* Jacobi sweeps summed over the merges              */
     double sin_theta;      /* sine of the last convergence angle (NaN first)    */
+    int32_t stop_reason;   /* pod_stop_reason of the current state              */
+    int32_t reserved;      /* 0                                                 */
 } pod_info;
 
 /* Create a context for A (device, borrowed) and run the set-up pass:
@@ -129,8 +146,11 @@ pod_status pod_merge(pod_ctx *ctx);
 
 /* Convergence test of Alg. 1 (syncs): *done = 1 when the largest angle
  * between the first k modes of the last two estimates is below theta_tol,
- * S is exhausted, or max_iter merges were done.  *sin_theta_max (nullable)
- * gets the sine of that angle (NaN after the first merge). */
+ * S is exhausted, max_iter merges were done, or the run failed.
+ * *sin_theta_max (nullable) gets the sine of that angle (NaN after the first
+ * merge).  Returns POD_ENONFINITE after a NaN/Inf in A or a computed
+ * quantity, POD_ENOTPD after a Cholesky breakdown that the shifted retry did
+ * not cure (e.g. a merge block whose Gram is zero); *done is 1 then. */
 pod_status pod_converged(pod_ctx *ctx, int32_t *done, double *sin_theta_max);
 
 /* The loop of Alg. 1 driven from the device: enqueue iterations (pod_sample
@@ -143,9 +163,10 @@ pod_status pod_converged(pod_ctx *ctx, int32_t *done, double *sin_theta_max);
  * sin_out (host, nullable, >= max_merges doubles) receives the convergence
  * sine of each merge of this call (NaN for the first merge of the run);
  * *merges_out (nullable) the number of merges done; *done_out (nullable) 1
- * when the run stopped (converged, S exhausted, or max_iter reached).  No
- * sample may be pending (POD_ESTATE); the context is left ready for
- * pod_sample / pod_project.  Syncs. */
+ * when the run stopped (converged, S exhausted, max_iter reached, or a
+ * failure: the status is then that of pod_converged).  No sample may be
+ * pending (POD_ESTATE); the context is left ready for pod_sample /
+ * pod_project.  Syncs. */
 pod_status pod_run(pod_ctx *ctx, int32_t max_merges, int32_t stop_on_converged, int32_t chunk, double *sin_out,
                    int32_t *merges_out, int32_t *done_out);
 
@@ -186,6 +207,26 @@ pod_status pod_get_info(pod_ctx *ctx, pod_info *info);
  * may be NULL.  *g / *h (host, nullable) get their numbers.  Syncs. */
 pod_status pod_get_indices(pod_ctx *ctx, int32_t iter, int32_t *cols, int32_t *col_counts, int32_t *g,
                            int32_t *rows, int32_t *row_counts, int32_t *h);
+
+/* Replay of a draw (parity checks against a reference run, finite
+ * differences with frozen indices): the next pod_sample (or the first draw of
+ * the next pod_run), which is the draw of merge `iter` (iter must equal the
+ * merges done), takes these indices instead of drawing from the Philox
+ * stream.  GET UPDATE of Alg. 1 then continues as after a draw: the columns
+ * leave S, the column log records them, and with w > 0 SAMPLE AND SCALE
+ * UNIQUE ROWS scales the given rows by sqrt(t^_i / (w q_i)), q_i from the
+ * current row weights (Eq. CTSVD_prob, or leverage scores), followed by the
+ * small SVD of W^T W.
+ *   cols (host): g >= 1 distinct columns of S in ascending order, g <= c;
+ *   col_counts (host, nullable = all 1): their multiplicities (>= 1, logged);
+ *   rows, row_counts (host; required when w > 0, ignored otherwise): h >= 1
+ *   distinct rows in ascending order, h <= w, multiplicities >= 1 summing to w.
+ * A row whose current weight is zero makes the scale infinite: the merge then
+ * reports POD_ENONFINITE.  POD_EINVAL for indices out of range, unsorted,
+ * repeated or (columns) no longer in S; POD_ESTATE while a draw is pending or
+ * when iter is not the next merge.  Syncs. */
+pod_status pod_set_indices(pod_ctx *ctx, int32_t iter, const int32_t *cols, const int32_t *col_counts, int32_t g,
+                           const int32_t *rows, const int32_t *row_counts, int32_t h);
 
 /* ---------------------------------------------------------------------------
  * Reverse mode through the merge chain of Alg. 1 (ICS: w = 0, r_update = 0,

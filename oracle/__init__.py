@@ -6,8 +6,9 @@ library in ``paper_1905_05107_amd``.  Only ``tests/``, the smoke check in
 It shares no code with the GPU path and never calls it; the product path
 never calls the oracle.
 
-The numerical primitives live in ``pod_oracle.c`` (plain C, FP64, single
-thread, no BLAS/LAPACK); ``isma.py`` strings them together in the order of
+The numerical primitives live in ``pod_oracle.c`` (plain C, FP64, no
+BLAS/LAPACK; OpenMP splits only loops over independent columns, so every
+result is bitwise the same for any thread count); ``isma.py`` strings them together in the order of
 the paper's Alg. 1 (ISMA, with the UNF / L2N / ORT column and L2 / LS row
 strategies and the optional row centring), Alg. 2 (BLOCK MERGE) and Alg. 3
 (incremental POD); ``oneshot.py`` follows Alg. 4 (LTSVD) and Alg. 5 (CTSVD) of
@@ -34,7 +35,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-shared", "-fPIC",
+            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-Wall", "-shared", "-fPIC",
              "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -61,6 +62,7 @@ def lib():
             "or_merge": (i32, [pd, pd, i64, i32, pd, i32, i32, pd, pd]),
             "or_subspace_sines": (ctypes.c_int, [pd, pd, i64, i32, pd]),
             "or_project": (ctypes.c_int, [pd, i64, i64, i64, pd, i32, pd, pd, pd]),
+            "or_set_threads": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -77,6 +79,12 @@ def _p(a, ct):
 def _f64(a):
     """Column-major FP64 copy (values of FP32 inputs are represented exactly)."""
     return np.asfortranarray(np.asarray(a, dtype=np.float64))
+
+
+def set_threads(n: int) -> None:
+    """Threads of the C oracle's column-parallel loops (results do not depend
+    on it: only independent columns are split between threads)."""
+    lib().or_set_threads(int(n))
 
 
 # ---------------------------------------------------------------- primitives

@@ -36,6 +36,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_U64_EPS (1.1102230246251565e-16) /* unit roundoff 2^-53 */
 
@@ -43,6 +46,17 @@
 /* Philox-4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).  One block maps a     */
 /* 256-bit counter and a 128-bit key to four 64-bit words.                  */
 /* ------------------------------------------------------------------------ */
+/* Threads of the OpenMP loops (over independent columns only, so every
+ * result is bitwise the same for any count).  Used to time the oracle. */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 void or_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
 {
     uint64_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
@@ -110,6 +124,7 @@ static double or_fixed_order_sumsq(const double *x, int64_t m, int elem_bytes)
 
 void or_col_sqnorms(const double *A, int64_t m, int64_t n, int64_t lda, int elem_bytes, double *nu)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n; ++j) nu[j] = or_fixed_order_sumsq(A + j * lda, m, elem_bytes);
 }
 
@@ -246,6 +261,8 @@ void or_householder_qr(const double *X, int64_t m, int64_t p, double *R, double 
         double vn2 = 0.0;
         for (int64_t i = j; i < m; ++i) vn2 += v[i] * v[i];
         beta[j] = (vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+        /* columns are updated independently: any thread count gives the same bits */
+#pragma omp parallel for schedule(static) if ((m - j) * (p - j) > 65536)
         for (int64_t k = j; k < p; ++k) {
             double *a = A + k * m;
             double s = 0.0;
@@ -264,6 +281,7 @@ void or_householder_qr(const double *X, int64_t m, int64_t p, double *R, double 
     for (int64_t j = p - 1; j >= 0; --j) {
         if (beta[j] == 0.0) continue;
         const double *v = Vh + j * m;
+#pragma omp parallel for schedule(static) if ((m - j) * (p - j) > 65536)
         for (int64_t k = j; k < p; ++k) {
             double *q = Q + k * m;
             double s = 0.0;
@@ -470,6 +488,7 @@ int32_t or_merge(const double *U1, const double *s1, int64_t m, int32_t r1, cons
         for (int64_t i = 0; i < p; ++i)
             if (sE[i] > thr) ++nz;
         rr = (r < nz) ? r : nz;
+#pragma omp parallel for schedule(static)
         for (int32_t c = 0; c < rr; ++c) {
             sout[c] = sE[c];
             for (int64_t i = 0; i < m; ++i) {
@@ -522,6 +541,7 @@ int or_project(const double *A, int64_t m, int64_t n, int64_t lda, const double 
                double *sigma, double *Vout)
 {
     double *Y = (double *)malloc(sizeof(double) * (size_t)(n * r));
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n; ++j) {
         const double *a = A + j * lda;
         for (int32_t c = 0; c < r; ++c) {
@@ -537,6 +557,7 @@ int or_project(const double *A, int64_t m, int64_t n, int64_t lda, const double 
     double *UR = (double *)malloc(sizeof(double) * (size_t)(r * r));
     double *VR = (double *)malloc(sizeof(double) * (size_t)(r * r));
     int sw = or_jacobi_svd(R, r, r, sigma, UR, VR, 100);
+#pragma omp parallel for schedule(static)
     for (int32_t c = 0; c < r; ++c)
         for (int64_t i = 0; i < m; ++i) {
             double s = 0.0;

@@ -8,7 +8,6 @@ the library is not built this module raises on first use.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from dataclasses import dataclass
 from typing import List, Optional
@@ -21,6 +20,10 @@ POD_F64, POD_F32, POD_BF16_REFINE = 0, 1, 2
 POD_COL_L2N, POD_COL_UNF = 0, 1
 POD_ROW_L2, POD_ROW_LS = 0, 1
 POD_CRIT_SUBSPACE, POD_CRIT_MODE = 0, 1
+POD_STOP_NONE, POD_STOP_NONFINITE, POD_STOP_CONVERGED, POD_STOP_EXHAUSTED, POD_STOP_MAX_ITER, POD_STOP_BREAKDOWN = \
+    range(6)
+STOP_NAMES = {POD_STOP_NONE: "running", POD_STOP_NONFINITE: "nonfinite", POD_STOP_CONVERGED: "converged",
+              POD_STOP_EXHAUSTED: "exhausted", POD_STOP_MAX_ITER: "max_iter", POD_STOP_BREAKDOWN: "breakdown"}
 
 # every symbol include/pod.h declares
 EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project", "pod_wedin_bound", "pod_get_basis", "pod_get_info",
@@ -29,7 +32,7 @@ EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project"
            "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy", "pod_batch_init",
            "pod_batch_autotune", "pod_batch_run", "pod_batch_project", "pod_batch_get_info", "pod_batch_destroy",
            "pod_enable_adjoint", "pod_backward", "pod_loss_grad", "pod_batch_enable_adjoint", "pod_batch_loss_grad", "pod_batch_loss_grad_all",
-           "pod_run"]
+           "pod_run", "pod_set_indices"]
 
 
 class PodError(RuntimeError):
@@ -54,6 +57,7 @@ class pod_info(ctypes.Structure):
         ("iter", ctypes.c_int32), ("rank", ctypes.c_int32), ("g", ctypes.c_int32), ("h", ctypes.c_int32),
         ("exhausted", ctypes.c_int32), ("flags", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
         ("total_sweeps", ctypes.c_int32), ("sin_theta", ctypes.c_double),
+        ("stop_reason", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -87,6 +91,7 @@ def lib():
             "pod_get_basis": (i32, [vp, vp, vp, P(i32)]),
             "pod_get_info": (i32, [vp, P(pod_info)]),
             "pod_get_indices": (i32, [vp, i32, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)]),
+            "pod_set_indices": (i32, [vp, i32, P(i32), P(i32), i32, P(i32), P(i32), i32]),
             "pod_get_col_sqnorms": (i32, [vp, vp]),
             "pod_col_sqnorms": (i32, [vp, i32, i64, i64, i64, vp, vp]),
             "pod_sample_size": (i64, [i32, i32, d, d]),
@@ -173,6 +178,7 @@ class Result:
     exhausted: bool
     converged: bool
     flags: int
+    stopped_by: str = "running"
 
 
 class PodContext:
@@ -258,14 +264,17 @@ class PodContext:
         Vt = torch.empty((k, self.n), dtype=self._out_dtype(), device=dev) if want_v else None
         _check(lib().pod_project(self.h, ctypes.c_void_p(Ut.data_ptr()), ctypes.c_void_p(sig.data_ptr()),
                                  ctypes.c_void_p(Vt.data_ptr()) if want_v else None), "pod_project")
+        self._proj_k = k
         return Ut.T, sig, (Vt.T if want_v else None)
 
     def wedin_bound(self, U, V):
         """Quality measure of Eq. (ang_meas) for the pairs the last project()
         returned: (||R||_F, ||S||_F, omega^, bound).  Needs r > k."""
+        k = getattr(self, "_proj_k", None)
+        if k is None:
+            raise ValueError("wedin_bound needs the pairs of a project() call")
+        check_pairs(U, V, self.m, self.n, k, self._out_dtype(), self.A.device)
         Ut, Vt = U.T, V.T
-        if not (Ut.is_contiguous() and Vt.is_contiguous()):
-            raise ValueError("U and V must be the column-major outputs of project()")
         out = (ctypes.c_double * 4)()
         _check(lib().pod_wedin_bound(self.h, ctypes.c_void_p(Ut.data_ptr()), ctypes.c_void_p(Vt.data_ptr()), out),
                "pod_wedin_bound")
@@ -300,6 +309,39 @@ class PodContext:
         if rows:
             return cols[:g.value].copy(), cnt[:g.value].copy(), rws[:h.value].copy(), rcnt[:h.value].copy()
         return cols[:g.value].copy(), cnt[:g.value].copy()
+
+    def set_indices(self, it: int, cols, col_counts=None, rows=None, row_counts=None):
+        """Replay: the next draw (that of merge `it`) takes these distinct
+        columns (ascending; multiplicities optional) and, with row sampling,
+        these distinct rows and multiplicities instead of drawing."""
+        import numpy as np
+        P = ctypes.POINTER(ctypes.c_int32)
+        c = np.ascontiguousarray(cols, dtype=np.int32)
+        cc = None if col_counts is None else np.ascontiguousarray(col_counts, dtype=np.int32)
+        rw = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+        rc = None if row_counts is None else np.ascontiguousarray(row_counts, dtype=np.int32)
+        if cc is not None and cc.shape != c.shape or (rw is None) != (rc is None) or \
+                (rw is not None and rw.shape != rc.shape):
+            raise ValueError("indices and their counts must have the same length")
+        _check(lib().pod_set_indices(self.h, int(it), c.ctypes.data_as(P),
+                                     cc.ctypes.data_as(P) if cc is not None else None, int(c.shape[0]),
+                                     rw.ctypes.data_as(P) if rw is not None else None,
+                                     rc.ctypes.data_as(P) if rc is not None else None,
+                                     int(rw.shape[0]) if rw is not None else 0), "pod_set_indices")
+
+    def replay(self, draws):
+        """Merges with given draws: ``draws`` is a list of (cols, col_counts)
+        or (cols, col_counts, rows, row_counts) per iteration, e.g. from a
+        reference run.  Returns the convergence sines (NaN for the first)."""
+        sines = []
+        for d in draws:
+            self.set_indices(self.info().iter, *d)
+            if not self.sample():
+                break
+            self.merge()
+            _, sn = self.converged()
+            sines.append(sn)
+        return sines
 
     # -- reverse mode
     def enable_adjoint(self):
@@ -368,6 +410,20 @@ class PodContext:
         return sines
 
 
+def check_pairs(U, V, m: int, n: int, k: int, dtype, device):
+    """The kernels behind wedin_bound read k columns of m (U) and n (V) rows
+    in the context's output type: refuse anything else before the call."""
+    for name, X, rows in (("U", U, m), ("V", V, n)):
+        if tuple(X.shape) != (rows, k):
+            raise ValueError(f"{name} must be {rows} x {k} (the pairs of the last project()), got {tuple(X.shape)}")
+        if X.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {X.dtype}")
+        if X.device != device:
+            raise ValueError(f"{name} must live on {device}, got {X.device}")
+        if not X.T.is_contiguous():
+            raise ValueError(f"{name} must have contiguous columns (ld = {rows})")
+
+
 def isma(A, k: int, c: int, want_v: bool = True, n_iter: Optional[int] = None, **kw) -> Result:
     """Run Alg. 1 on the device matrix A (m x n, contiguous columns) and the
     final projection; returns the first k modes."""
@@ -375,9 +431,8 @@ def isma(A, k: int, c: int, want_v: bool = True, n_iter: Optional[int] = None, *
         sines = ctx.run(n_iter=n_iter)
         inf = ctx.info()
         U, sig, V = ctx.project(want_v=want_v)
-        tol = kw.get("theta_tol", 1e-10)
-        conv = inf.iter >= 2 and not math.isnan(inf.sin_theta) and inf.sin_theta < math.sin(min(tol, math.pi / 2))
-        return Result(U, sig, V, inf.iter, sines, bool(inf.exhausted), conv, inf.flags)
+        return Result(U, sig, V, inf.iter, sines, bool(inf.exhausted), inf.stop_reason == POD_STOP_CONVERGED,
+                      inf.flags, STOP_NAMES.get(inf.stop_reason, "unknown"))
 
 
 class Incremental:

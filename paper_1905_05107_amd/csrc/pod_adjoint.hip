@@ -154,6 +154,7 @@ pod_status reverse_merges(pod_ctx *ctx, void *dA)
     const int32_t T = ctx->hs.it;
     std::vector<int32_t> meta(4 * (size_t)(T > 0 ? T : 1)), off(T + 1);
     if (T < 1) return POD_OK;
+    if (ctx->ck_lost || T > ctx->ck_cap) return POD_ENOMEM;   // merges without checkpoints
     A_HIP(hipMemcpy(meta.data(), ctx->ckMeta, sizeof(int32_t) * 4 * T, hipMemcpyDeviceToHost));
     A_HIP(hipMemcpy(off.data(), ctx->col_log_off, sizeof(int32_t) * (T + 1), hipMemcpyDeviceToHost));
     for (int32_t t = 0; t < T; ++t)
@@ -270,6 +271,7 @@ pod_status pod::reverse_merges_batch(pod_ctx *const *ctxs, int32_t count, void *
         R.T = ctx->hs.it;
         if (ctx->prm.precision != prec || ctx->pb > 64 || ctx->pmax > 64) return POD_EINVAL;
         if (R.T < 1) continue;
+        if (ctx->ck_lost || R.T > ctx->ck_cap) return POD_ENOMEM;
         R.meta.resize(4 * (size_t)R.T);
         R.off.resize(R.T + 1);
         A_HIP(hipMemcpy(R.meta.data(), ctx->ckMeta, sizeof(int32_t) * 4 * R.T, hipMemcpyDeviceToHost));
@@ -452,6 +454,57 @@ hipError_t pod::launch_ckpt_post_b(const CkptArgs *arr, int32_t count, hipStream
     return hipGetLastError();
 }
 
+pod_status pod::ckpt_reserve(pod_ctx *ctx, int32_t need)
+{
+    if (need > ctx->ck_max) need = ctx->ck_max;
+    if (need <= ctx->ck_cap) return POD_OK;
+    int32_t cap = 2 * ctx->ck_cap;
+    if (cap < need) cap = need;
+    if (cap > ctx->ck_max) cap = ctx->ck_max;
+    const size_t mr = (size_t)ctx->prm.m * ctx->r, r = (size_t)ctx->r, pm2 = (size_t)ctx->pmax * ctx->pmax;
+    void *nU = nullptr;
+    double *nS = nullptr, *nR = nullptr;
+    int32_t *nM = nullptr;
+    hipError_t e = hipMalloc(&nU, (size_t)cap * mr * ctx->esz + 16);
+    if (e == hipSuccess) e = hipMalloc((void **)&nS, sizeof(double) * cap * r + 16);
+    if (e == hipSuccess) e = hipMalloc((void **)&nR, sizeof(double) * cap * pm2 + 16);
+    if (e == hipSuccess) e = hipMalloc((void **)&nM, sizeof(int32_t) * 4 * cap + 16);
+    if (e != hipSuccess) {
+        (void)hipFree(nU);
+        (void)hipFree(nS);
+        (void)hipFree(nR);
+        (void)hipFree(nM);
+        (void)hipGetLastError();
+        if (e != hipErrorOutOfMemory) ctx->failed = 1;
+        return (e == hipErrorOutOfMemory) ? POD_ENOMEM : POD_EHIP;
+    }
+    const size_t old = (size_t)ctx->ck_cap;
+    if (e == hipSuccess) e = hipMemsetAsync(nM, 0, sizeof(int32_t) * 4 * cap, ctx->st);
+    if (old > 0) {
+        // checkpoints written by merges already enqueued land in the old
+        // buffers before these stream-ordered copies
+        if (e == hipSuccess) e = hipMemcpyAsync(nU, ctx->ckU, old * mr * ctx->esz, hipMemcpyDeviceToDevice, ctx->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(nS, ctx->ckS, sizeof(double) * old * r, hipMemcpyDeviceToDevice, ctx->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(nR, ctx->ckR, sizeof(double) * old * pm2, hipMemcpyDeviceToDevice, ctx->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(nM, ctx->ckMeta, sizeof(int32_t) * 4 * old, hipMemcpyDeviceToDevice, ctx->st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+    if (e != hipSuccess) {
+        ctx->failed = 1;
+        return POD_EHIP;
+    }
+    (void)hipFree(ctx->ckU);
+    (void)hipFree(ctx->ckS);
+    (void)hipFree(ctx->ckR);
+    (void)hipFree(ctx->ckMeta);
+    ctx->ckU = nU;
+    ctx->ckS = nS;
+    ctx->ckR = nR;
+    ctx->ckMeta = nM;
+    ctx->ck_cap = cap;
+    return POD_OK;
+}
+
 extern "C" {
 
 pod_status pod_enable_adjoint(pod_ctx *ctx)
@@ -462,20 +515,20 @@ pod_status pod_enable_adjoint(pod_ctx *ctx)
     const pod_params &p = ctx->prm;
     if (p.w != 0 || p.r_update != 0 || ctx->pmax > 64) return POD_EINVAL;
     if (ctx->ckU) return POD_OK;
-    const int32_t cap = (int32_t)((p.max_iter < ctx->n_cap) ? p.max_iter : ctx->n_cap) + 1;
     const int32_t pb = ((ctx->pmax + ctx->r) + 15) & ~15;
     if (pb > 160) return POD_EINVAL;
-    ctx->ck_cap = cap;
     ctx->pb = pb;
+    // checkpoints for about twice the merges a run takes when every draw is
+    // distinct (n / c); later merges grow them (ckpt_reserve)
+    ctx->ck_max = (int32_t)((p.max_iter < ctx->n_cap) ? p.max_iter : ctx->n_cap) + 1;
+    const int64_t guess = 2 * ((ctx->n_cap + p.c - 1) / p.c) + 8;
+    ctx->ck_cap = 0;
+    ctx->ck_lost = 0;
     const size_t m = (size_t)p.m, r = (size_t)ctx->r, pm2 = (size_t)ctx->pmax * ctx->pmax;
     hipError_t e = hipSuccess;
     auto al = [&](void **q, size_t bytes) {
         if (e == hipSuccess) e = hipMalloc(q, bytes + 16);
     };
-    al(&ctx->ckU, (size_t)cap * m * r * ctx->esz);
-    al((void **)&ctx->ckS, sizeof(double) * cap * r);
-    al((void **)&ctx->ckR, sizeof(double) * cap * pm2);
-    al((void **)&ctx->ckMeta, sizeof(int32_t) * 4 * cap);
     al((void **)&ctx->dsb, sizeof(DevState));
     al((void **)&ctx->partb, sizeof(double) * (size_t)ctx->nblk * pb * pb);
     al((void **)&ctx->Gext, sizeof(double) * (size_t)pb * pb);
@@ -486,12 +539,23 @@ pod_status pod_enable_adjoint(pod_ctx *ctx)
     al(&ctx->Wt, (size_t)pb * ctx->pmax * ctx->esz);
     al(&ctx->Ubar[0], m * r * ctx->esz);
     al(&ctx->Ubar[1], m * r * ctx->esz);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->ckMeta, 0, sizeof(int32_t) * 4 * cap, ctx->st);
-    if (e != hipSuccess) {
-        ctx->failed = 1;
-        return (e == hipErrorOutOfMemory) ? POD_ENOMEM : POD_EHIP;
-    }
-    return POD_OK;
+    pod_status s = (e == hipSuccess) ? POD_OK : (e == hipErrorOutOfMemory) ? POD_ENOMEM : POD_EHIP;
+    if (s == POD_OK) s = ckpt_reserve(ctx, (int32_t)(guess < ctx->ck_max ? guess : ctx->ck_max));
+    if (s == POD_OK && ctx->ckU) return POD_OK;
+    // the forward run stays usable: release what was taken
+    void *ptrs[] = {ctx->dsb, ctx->partb, ctx->Gext, ctx->adj_ws, ctx->sbar[0], ctx->sbar[1], ctx->lossp,
+                    ctx->Wt, ctx->Ubar[0], ctx->Ubar[1], ctx->ckU, ctx->ckS, ctx->ckR, ctx->ckMeta};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    ctx->dsb = nullptr;
+    ctx->partb = ctx->Gext = ctx->adj_ws = ctx->sbar[0] = ctx->sbar[1] = ctx->lossp = nullptr;
+    ctx->Wt = ctx->Ubar[0] = ctx->Ubar[1] = ctx->ckU = nullptr;
+    ctx->ckS = ctx->ckR = nullptr;
+    ctx->ckMeta = nullptr;
+    ctx->ck_cap = 0;
+    (void)hipGetLastError();
+    if (s == POD_EHIP) ctx->failed = 1;
+    return (s == POD_OK) ? POD_ENOMEM : s;
 }
 
 pod_status pod_backward(pod_ctx *ctx, const void *dU, const double *dsigma, void *dA)

@@ -44,6 +44,28 @@ pod_status sync_state(pod_ctx *ctx)
     return POD_OK;
 }
 
+// Status of the error flags a run raised on the device.
+pod_status flag_status(int32_t flags)
+{
+    if (flags & FLAG_NONFINITE) return POD_ENONFINITE;
+    if (flags & FLAG_NOTPD) return POD_ENOTPD;
+    if (flags & FLAG_NOCONV) return POD_ENOCONV;
+    return POD_OK;
+}
+
+// The stop rule of pod_converged on the state of the last sync.
+int32_t stop_reason(const pod_ctx *ctx)
+{
+    const DevState &h = ctx->hs;
+    const double tol = ctx->prm.theta_tol < 1.5707963267948966 ? sin(ctx->prm.theta_tol) : 1.0;
+    if (h.flags & FLAG_NONFINITE) return POD_STOP_NONFINITE;
+    if (h.flags & FLAG_NOTPD) return POD_STOP_BREAKDOWN;
+    if (h.it >= 2 && h.sin_theta < tol) return POD_STOP_CONVERGED;
+    if (h.exhausted || h.s_empty || ctx->exhausted) return POD_STOP_EXHAUSTED;
+    if (h.it >= ctx->prm.max_iter) return POD_STOP_MAX_ITER;
+    return POD_STOP_NONE;
+}
+
 void free_all(pod_ctx *ctx)
 {
     void *ptrs[] = {ctx->ds,   ctx->nu,   ctx->wq,    ctx->inS,  ctx->cols, ctx->ccnt, ctx->col_log, ctx->ccnt_log,
@@ -113,7 +135,15 @@ GemmDesc plain_desc(pod_ctx *ctx, const void *Y)
 pod_status merge_launch(pod_ctx *ctx, const GemmDesc &gd, const double *sigma2, bool use_vt, bool block_eig_mode1)
 {
     const int32_t pm = ctx->pmax;
-    if (ctx->ckU) POD_HIP(launch_ckpt_pre(ctx, ctx->st));
+    if (ctx->ckU) {
+        // room for this merge's checkpoint (merge index <= merges launched)
+        if (!ctx->ck_lost) {
+            const pod_status s = ckpt_reserve(ctx, ctx->merges + 1);
+            if (s == POD_ENOMEM) ctx->ck_lost = 1;   // the forward run goes on; the reverse pass is refused
+            else if (s != POD_OK) return s;
+        }
+        POD_HIP(launch_ckpt_pre(ctx, ctx->st));
+    }
     // pass 1: G0 = X0^T X0, X0 = [U | A(:, I_c)] gathered on the fly
     POD_HIP(launch_gram_partial(gd, ctx->ds, -1, pm, ctx->part, ctx->nblk, ctx->st));
     POD_HIP(launch_gram_reduce_sel(ctx->part, ctx->nblk, pm, ctx->ds, -1, ctx->G, ctx->st));
@@ -302,7 +332,7 @@ pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
     ALLOC(ctx->inS, uint8_t, n);
     ALLOC(ctx->cols, int32_t, 1024);
     ALLOC(ctx->ccnt, int32_t, 1024);
-    ALLOC(ctx->forced, int32_t, 1024);
+    ALLOC(ctx->forced, int32_t, 4096);
     ALLOC(ctx->col_log, int32_t, n);
     ALLOC(ctx->ccnt_log, int32_t, n);
     ALLOC(ctx->col_log_off, int32_t, cap_iter + 1);
@@ -374,6 +404,7 @@ pod_status pod::ctx_bind(pod_ctx *ctx, void *A_dev, int64_t n, int64_t lda, uint
     ctx->merges = 0;
     ctx->exhausted = 0;
     ctx->forced_g = -1;
+    ctx->forced_h = 0;
     const pod_params &p = ctx->prm;
     const int64_t m = p.m;
     const int32_t r = ctx->r;
@@ -392,10 +423,12 @@ pod_status pod::ctx_bind(pod_ctx *ctx, void *A_dev, int64_t n, int64_t lda, uint
         const int32_t ns = 8;
         double *scratch = nullptr;
         POD_HIP(hipMalloc((void **)&scratch, sizeof(double) * (size_t)(ns + 1) * m));
-        POD_HIP(launch_row_means(A_dev, p.a_dtype, m, n, p.lda, scratch, ns, scratch + (size_t)ns * m, ctx->st));
-        POD_HIP(launch_center(A_dev, p.a_dtype, m, n, p.lda, scratch + (size_t)ns * m, ctx->st));
-        POD_HIP(hipStreamSynchronize(ctx->st));
-        POD_HIP(hipFree(scratch));
+        hipError_t e = launch_row_means(A_dev, p.a_dtype, m, n, p.lda, scratch, ns, scratch + (size_t)ns * m, ctx->st);
+        if (e == hipSuccess) e = launch_center(A_dev, p.a_dtype, m, n, p.lda, scratch + (size_t)ns * m, ctx->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+        const hipError_t ef = hipFree(scratch);
+        POD_HIP(e);
+        POD_HIP(ef);
     }
     POD_HIP(launch_col_sqnorms(A_dev, p.a_dtype, m, n, p.lda, ctx->nu, ctx->st));
     POD_HIP(launch_quantize(ctx->nu, n, ctx->wq, ctx->ds, 0, ctx->st));
@@ -408,7 +441,6 @@ static pod_status enqueue_sample(pod_ctx *ctx)
 {
     DrawArgs a = ctx_draw_args(ctx);
     POD_HIP(launch_draw_cols(a, ctx->st));
-    ctx->forced_g = -1;
     const pod_params &p = ctx->prm;
     if (p.w > 0) {
         // SAMPLE AND SCALE UNIQUE ROWS, then the right factor of the new block
@@ -427,11 +459,15 @@ static pod_status enqueue_sample(pod_ctx *ctx)
         ra.row_log = ctx->row_log;
         ra.rcnt_log = ctx->rcnt_log;
         ra.max_iter = a.max_iter;
+        ra.forced = (ctx->forced_g >= 0) ? ctx->forced : nullptr;
+        ra.forced_h = ctx->forced_h;
         ra.ds = ctx->ds;
         POD_HIP(launch_draw_rows(ra, ctx->st));
         BlockEigArgs ba = block_eig_args(ctx, 0);
         POD_HIP(launch_block_eig(ba, ctx->st));
     }
+    ctx->forced_g = -1;
+    ctx->forced_h = 0;
     return POD_OK;
 }
 
@@ -517,7 +553,7 @@ pod_status pod_run(pod_ctx *ctx, int32_t max_merges, int32_t stop_on_converged, 
     }
     POD_HIP(hipStreamSynchronize(ctx->st));
     (void)enqueued;
-    return POD_OK;
+    return flag_status(ctx->hs.flags);
 }
 
 pod_status pod_converged(pod_ctx *ctx, int32_t *done, double *sin_theta_max)
@@ -530,10 +566,9 @@ pod_status pod_converged(pod_ctx *ctx, int32_t *done, double *sin_theta_max)
     const DevState &h = ctx->hs;
     if (sin_theta_max) *sin_theta_max = h.sin_theta;
     const double tol = ctx->prm.theta_tol < 1.5707963267948966 ? sin(ctx->prm.theta_tol) : 1.0;
-    *done = h.exhausted || h.s_empty || h.it >= ctx->prm.max_iter || (h.it >= 2 && h.sin_theta < tol);
-    if (h.flags & FLAG_NONFINITE) return POD_ENONFINITE;
-    if (h.flags & FLAG_NOCONV) return POD_ENOCONV;
-    return POD_OK;
+    *done = h.exhausted || h.s_empty || h.it >= ctx->prm.max_iter || (h.it >= 2 && h.sin_theta < tol) ||
+            (h.flags & FLAG_FATAL) != 0;
+    return flag_status(h.flags);
 }
 
 pod_status pod_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *V_out)
@@ -591,8 +626,8 @@ pod_status pod::ctx_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *
     POD_HIP(launch_sign_fix(p.precision, U_out, p.m, k, V_out, p.n, ctx->signv, ctx->signi, ctx->st));
     s = sync_state(ctx);
     if (s != POD_OK) return s;
-    if (ctx->hs.flags & FLAG_NONFINITE) return POD_ENONFINITE;
-    if (ctx->hs.flags & FLAG_NOCONV) return POD_ENOCONV;
+    s = flag_status(ctx->hs.flags);
+    if (s != POD_OK) return s;
     ctx->proj_it = ctx->hs.it;
     ctx->proj_k = k;
     ctx->proj_rank = rs;
@@ -657,6 +692,77 @@ pod_status pod_get_info(pod_ctx *ctx, pod_info *info)
     info->max_sweeps = ctx->hs.sweeps;
     info->total_sweeps = ctx->hs.sweeps_total;
     info->sin_theta = ctx->hs.sin_theta;
+    info->stop_reason = stop_reason(ctx);
+    info->reserved = 0;
+    return POD_OK;
+}
+
+pod_status pod_set_indices(pod_ctx *ctx, int32_t iter, const int32_t *cols, const int32_t *col_counts, int32_t g,
+                           const int32_t *rows, const int32_t *row_counts, int32_t h)
+{
+    if (!ctx || !cols || g < 1) return POD_EINVAL;
+    if (ctx->failed) return POD_EHIP;
+    if (ctx->pending) return POD_ESTATE;
+    pod_status s = sync_state(ctx);
+    if (s != POD_OK) return s;
+    const pod_params &p = ctx->prm;
+    if (iter != ctx->hs.it || ctx->exhausted || ctx->hs.it >= p.max_iter) return POD_ESTATE;
+    if (g > p.c || g > 1024) return POD_EINVAL;
+    for (int32_t d = 0; d < g; ++d) {
+        if (cols[d] < 0 || cols[d] >= p.n || (d > 0 && cols[d] <= cols[d - 1])) return POD_EINVAL;
+        if (col_counts && col_counts[d] < 1) return POD_EINVAL;
+    }
+    if (p.w > 0) {
+        if (!rows || !row_counts || h < 1 || h > p.w) return POD_EINVAL;
+        int64_t tot = 0;
+        for (int32_t d = 0; d < h; ++d) {
+            if (rows[d] < 0 || rows[d] >= p.m || (d > 0 && rows[d] <= rows[d - 1]) || row_counts[d] < 1)
+                return POD_EINVAL;
+            tot += row_counts[d];
+        }
+        if (tot != p.w) return POD_EINVAL;
+    }
+    // the columns must still be in S
+    uint8_t *in = (uint8_t *)malloc((size_t)p.n);
+    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * 4096);
+    if (!in || !buf) {
+        free(in);
+        free(buf);
+        return POD_ENOMEM;
+    }
+    hipError_t e = hipMemcpyAsync(in, ctx->inS, (size_t)p.n, hipMemcpyDeviceToHost, ctx->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+    bool ok = (e == hipSuccess);
+    for (int32_t d = 0; ok && d < g; ++d) ok = in[cols[d]] != 0;
+    free(in);
+    if (e != hipSuccess) {
+        free(buf);
+        ctx->failed = 1;
+        return POD_EHIP;
+    }
+    if (!ok) {
+        free(buf);
+        return POD_EINVAL;
+    }
+    memset(buf, 0, sizeof(int32_t) * 4096);
+    for (int32_t d = 0; d < g; ++d) {
+        buf[d] = cols[d];
+        buf[1024 + d] = col_counts ? col_counts[d] : 1;
+    }
+    if (p.w > 0)
+        for (int32_t d = 0; d < h; ++d) {
+            buf[2048 + d] = rows[d];
+            buf[3072 + d] = row_counts[d];
+        }
+    e = hipMemcpyAsync(ctx->forced, buf, sizeof(int32_t) * 4096, hipMemcpyHostToDevice, ctx->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+    free(buf);
+    if (e != hipSuccess) {
+        ctx->failed = 1;
+        return POD_EHIP;
+    }
+    ctx->forced_g = g;
+    ctx->forced_h = (p.w > 0) ? h : 0;
     return POD_OK;
 }
 

@@ -321,6 +321,24 @@ pod_status pod_batch_run(pod_batch *b, int32_t use_graph, int32_t max_rounds, in
         }
     }
     while (rounds < max_rounds && *b->h_ndone < b->count) {
+        if (b->d_ck) {
+            // room for this round's checkpoints: a matrix merges at most once
+            // per round; the captured launches read the argument array
+            bool grown = false;
+            for (int32_t i = 0; i < b->count; ++i) {
+                pod_ctx *c = b->ctx[i];
+                const int32_t before = c->ck_cap;
+                const pod_status s = ckpt_reserve(c, b->iters + rounds + 1);
+                if (s == POD_ENOMEM) c->ck_lost = 1;
+                else if (s != POD_OK) return s;
+                grown = grown || c->ck_cap != before;
+            }
+            if (grown) {
+                std::vector<CkptArgs> ck(b->count);
+                for (int32_t i = 0; i < b->count; ++i) ck[i] = ctx_ckpt_args(b->ctx[i]);
+                B_HIP(hipMemcpy(b->d_ck, ck.data(), sizeof(CkptArgs) * b->count, hipMemcpyHostToDevice));
+            }
+        }
         if (use_graph) {
             B_HIP(hipGraphLaunch(b->exec, b->st));
         } else {

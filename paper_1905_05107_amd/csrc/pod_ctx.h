@@ -39,11 +39,14 @@ struct pod_ctx {
     int32_t merges = 0;      // merges launched
     int exhausted = 0;       // known on the host
     int failed = 0;          // a HIP error happened: only destroy is allowed
-    int32_t forced_g = -1;   // replay of the next draw
+    int32_t forced_g = -1;   // replay of the next draw: distinct columns (-1: draw)
+    int32_t forced_h = 0;    // and distinct rows (w > 0); forced = [cols | counts | rows | counts], 1024 each
     double *sin_log = nullptr;   // device-driven runs: convergence sine of each merge
     int32_t log_cap = 0;
     // reverse pass (pod_enable_adjoint): per-merge checkpoints and buffers
     int32_t ck_cap = 0, pb = 0;
+    int32_t ck_max = 0;      // merges a run can do: min(max_iter, n) + 1
+    int ck_lost = 0;         // a checkpoint could not be grown: no reverse pass
     void *ckU = nullptr;     // basis before each merge (cap x m x r, compute type)
     double *ckS = nullptr;   // Sigma before each merge (cap x r)
     double *ckR = nullptr;   // merge factor R of each merge (cap x pmax^2)
@@ -77,6 +80,10 @@ pod_status ctx_merge_basis(pod_ctx *ctx, const void *Ub, const double *sb, int32
 // Checkpoints of the reverse pass around a merge (no-ops when the pending
 // draw found S exhausted).
 hipError_t launch_ckpt_pre(pod_ctx *ctx, hipStream_t st);
+// Grow the per-merge checkpoints to at least `need` merges (capped at
+// ck_max), keeping what they hold.  Syncs the context's stream when it grows.
+// POD_ENOMEM leaves the context usable (the old checkpoints stay).
+pod_status ckpt_reserve(pod_ctx *ctx, int32_t need);
 hipError_t launch_ckpt_post(pod_ctx *ctx, hipStream_t st);
 
 // Batched checkpoints (per-matrix entries in device memory).

@@ -20,7 +20,8 @@ struct DevState {
     int32_t p;          // rs + ru: columns of M = X0 P
     int32_t rnew;       // rank after the pending merge
     int32_t exhausted;  // no drawable column at the last draw
-    int32_t flags;      // bit0 shifted Cholesky, bit1 non-finite, bit2 Jacobi limit, bit3 zero row weights
+    int32_t flags;      // bit0 shifted Cholesky, bit1 non-finite, bit2 Jacobi limit, bit3 zero row weights,
+                        // bit4 Cholesky breakdown after the shifted retry
     int32_t sweeps;     // Jacobi sweeps of the last merge
     int32_t col_log_len;// entries used in the column log
     int32_t s_empty;    // no drawable column left after the last draw
@@ -31,7 +32,9 @@ struct DevState {
     uint64_t wrow_tot;  // total row weight of the last row draw
 };
 
-enum : int32_t { FLAG_SHIFT = 1, FLAG_NONFINITE = 2, FLAG_NOCONV = 4, FLAG_ZERO_ROWS = 8 };
+enum : int32_t { FLAG_SHIFT = 1, FLAG_NONFINITE = 2, FLAG_NOCONV = 4, FLAG_ZERO_ROWS = 8, FLAG_NOTPD = 16 };
+// Flags that end a run (the merged state is no longer meaningful).
+constexpr int32_t FLAG_FATAL = FLAG_NONFINITE | FLAG_NOTPD;
 
 // The merge-time kernels do nothing when the pending draw found S exhausted
 // or the run has stopped (`done`, set on the device by the stop test of a
@@ -117,7 +120,7 @@ struct DrawArgs {
     int32_t *ccnt_log;    // out: their multiplicities (n)
     int32_t *col_log_off; // out: offsets per merge (max_iter + 1)
     int32_t max_iter;
-    const int32_t *forced;// replayed columns (nullable)
+    const int32_t *forced;// replayed columns and their counts (forced + 1024) (nullable)
     int32_t forced_g;
     DevState *ds;
 };
@@ -143,6 +146,8 @@ struct RowDrawArgs {
     int32_t *row_log;      // out: per merge, w entries
     int32_t *rcnt_log;
     int32_t max_iter;
+    const int32_t *forced;   // replayed rows and their counts (forced + 1024) (nullable)
+    int32_t forced_h;
     DevState *ds;
 };
 hipError_t launch_draw_rows(const RowDrawArgs &a, hipStream_t st);

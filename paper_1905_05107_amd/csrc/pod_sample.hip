@@ -266,7 +266,7 @@ __device__ __forceinline__ void draw_cols_body(const DrawArgs &a)
         g = a.forced_g;
         for (int32_t d = t; d < g; d += 1024) {
             a.cols[d] = a.forced[d];
-            a.ccnt[d] = 1;
+            a.ccnt[d] = a.forced[1024 + d];
         }
         __syncthreads();
     } else {
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(256) void k_batch_done(DevState *const *__restrict_
     for (int32_t b = threadIdx.x; b < count; b += 256) {
         DevState *ds = dss[b];
         if (!ds->done) {
-            const bool d = ds->exhausted || ds->s_empty || ds->it >= max_iter[b] || (ds->flags & FLAG_NONFINITE) ||
+            const bool d = ds->exhausted || ds->s_empty || ds->it >= max_iter[b] || (ds->flags & FLAG_FATAL) ||
                            (ds->it >= 2 && ds->sin_theta < sin_tol[b]);
             if (d) ds->done = 1;
         }
@@ -439,15 +439,17 @@ __global__ __launch_bounds__(256) void k_batch_done(DevState *const *__restrict_
 // Stop test of a device-driven single run, after each merge: logs the merge's
 // convergence sine (sin_log[it - 1]; rewriting the same value when the draw
 // found S exhausted and nothing was merged) and sets `done` under the rule of
-// pod_converged: S exhausted, max_iter merges, or, when stop_conv is set and
-// from the second merge, a sine below tol.
+// pod_converged: a non-finite value or a Cholesky breakdown, S exhausted,
+// max_iter merges, or, when stop_conv is set and from the second merge, a
+// sine below tol.
 __global__ void k_run_done(DevState *ds, int32_t max_iter, double tol, int32_t stop_conv, double *sin_log,
                            int32_t log_cap)
 {
     if (threadIdx.x != 0 || ds->done) return;
     const int32_t it = ds->it;
     if (it >= 1 && it <= log_cap) sin_log[it - 1] = ds->sin_theta;
-    const bool d = ds->exhausted || ds->s_empty || it >= max_iter || (stop_conv && it >= 2 && ds->sin_theta < tol);
+    const bool d = ds->exhausted || ds->s_empty || it >= max_iter || (ds->flags & FLAG_FATAL) ||
+                   (stop_conv && it >= 2 && ds->sin_theta < tol);
     if (d) ds->done = 1;
 }
 
@@ -570,6 +572,30 @@ __global__ __launch_bounds__(1024) void k_draw_rows(RowDrawArgs a)
         return;
     }
     const int32_t c = a.w;
+    if (a.forced) {
+        // replay: the caller's distinct rows (ascending) and multiplicities;
+        // a row of zero weight would get an infinite scale
+        const int32_t h = a.forced_h;
+        const bool logit = it < a.max_iter;
+        int zero = 0;
+        for (int32_t d = t; d < h; d += 1024) {
+            const int32_t row = a.forced[2048 + d], cnt = a.forced[3072 + d];
+            a.rows[d] = row;
+            a.rcnt[d] = cnt;
+            zero |= (a.wr[row] == 0);
+            if (logit) {
+                a.row_log[(int64_t)it * c + d] = row;
+                a.rcnt_log[(int64_t)it * c + d] = cnt;
+            }
+        }
+        zero = __syncthreads_or(zero);
+        if (t == 0) {
+            if (zero) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
+            ds->h = h;
+            ds->wrow_tot = W;
+        }
+        return;
+    }
     for (int32_t d = t; d < c; d += 1024) {
         uint64_t ctr[4] = {(uint64_t)it, (uint64_t)(d >> 2), a.block, 0};
         philox4x64_10(ctr, a.seed, 1);

@@ -312,7 +312,7 @@ __device__ __forceinline__ void chol_first_rl(const SmallArgs &a)
             for (int k = 0; k < 8; ++k) r[k] = g[k] + ((l == rl_chol_row(w, k) && l < p) ? shift : 0.0);
             fail = rl_cholinv(r, p, 0.0, Rs, Xs, sfl);
             if (fail) {
-                if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
+                if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NOTPD);
                 rl_identity(p, Rs, Xs);
             }
         }
@@ -412,7 +412,7 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
             if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
             fail = big_chol(S, p, 0.0);
             if (fail) {
-                if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
+                if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NOTPD);
                 for (int idx = threadIdx.x; idx < p * p; idx += NT) S[idx] = (idx % p == idx / p) ? 1.0 : 0.0;
                 __syncthreads();
             }
@@ -595,7 +595,7 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
             fail = rl_cholinv(r, p, 0.0, bufA, Xs, sfl);
         }
         if (fail) {
-            if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
+            if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)(isfinite(trace) ? FLAG_NOTPD : FLAG_NONFINITE));
             rl_identity(p, bufA, Xs);
         }
     }
@@ -642,8 +642,20 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
             [&](int c, int i, double v) {
                 if (c < pm && i < pm) store_c(a.Tc, a.prec, i + c * pm, v);
             });
+    // ---- Sigma_new(i) = |U_R(:, i)^T R| (the rows of U_R^T R = Sigma_R V_R^T):
+    // accurate to about p u sigma_1 where sqrt(lambda_i) loses p u sigma_1^2 / sigma_i
+    __syncthreads();
+    rl_mm64([&](int i, int q) { return (i < rnew && q < p) ? Y[q + i * p] : 0.0; },
+            [&](int q, int j) { return (q < p && j < p) ? a.R2[q + j * pm] : 0.0; },
+            [&](int i, int j, double v) { bufB[i * RL_LD + j] = v; });
+    __syncthreads();
     double *sigma_new = (it0 & 1) ? a.sig0 : a.sig1;
-    for (int i = threadIdx.x; i < a.r; i += NT) sigma_new[i] = (i < rnew) ? sqrt(fmax(sev[i], 0.0)) : 0.0;
+    for (int i = threadIdx.x; i < a.r; i += NT) {
+        double v = 0.0;
+        if (i < rnew)
+            for (int j = 0; j < p; ++j) v = fma(bufB[i * RL_LD + j], bufB[i * RL_LD + j], v);
+        sigma_new[i] = sqrt(v);
+    }
     if (threadIdx.x == 0) {
         ds->rnew = rnew;
         ds->sin_theta = sin_max;
@@ -698,7 +710,7 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
         if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
         fail = isfinite(trace) ? big_chol(S1, p, 0.0) : 1;
         if (fail) {
-            if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
+            if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)(isfinite(trace) ? FLAG_NOTPD : FLAG_NONFINITE));
             for (int idx = threadIdx.x; idx < p * p; idx += NT) S1[idx] = (idx % p == idx / p) ? 1.0 : 0.0;
             __syncthreads();
         }
@@ -823,8 +835,24 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
                if (i < pm && j < pm) store_c(a.Tc, a.prec, i + j * pm, v);
            },
            [&](int ti, int tj, int &k0, int &k1) { (void)tj; k0 = 16 * ti; });
+    // ---- Sigma_new(i) = |U_R(:, i)^T R| (rows of U_R^T R = Sigma_R V_R^T) into S1
+    // (free after the inverse); R upper triangular: tile column J sums k < 16 J + 16
+    __syncthreads();
+    big_mm(p, false,
+           [&](int i, int k) { return (i < rnew && k < p) ? S3[k + i * p] : 0.0; },
+           [&](int k, int j) { return (k < p && j < p) ? a.R2[k + j * pm] : 0.0; },
+           [&](int i, int j, double v) {
+               if (i < p && j < p) S1[i + j * p] = v;
+           },
+           [&](int ti, int tj, int &k0, int &k1) { (void)ti; k0 = 0; k1 = 16 * tj + 16; });
+    __syncthreads();
     double *sigma_new = (it0 & 1) ? a.sig0 : a.sig1;
-    for (int i = threadIdx.x; i < a.r; i += NT) sigma_new[i] = (i < rnew) ? sqrt(fmax(sev[i], 0.0)) : 0.0;
+    for (int i = threadIdx.x; i < a.r; i += NT) {
+        double v = 0.0;
+        if (i < rnew)
+            for (int j = 0; j < p; ++j) v = fma(S1[i + j * p], S1[i + j * p], v);
+        sigma_new[i] = sqrt(v);
+    }
     if (threadIdx.x == 0) {
         ds->rnew = rnew;
         ds->sin_theta = sin_max;
@@ -908,11 +936,32 @@ __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
     // one value more than the k pairs when r > k: sigma_{k+1} of the quality measure
     const int kv = (k < r) ? k + 1 : k;
     bisect_top(sd, se, r, kv, sev, se2, ssc);
-    tri_invit(sd, se, r, sev, k, Y, lu, scl);
-    tridiag_backtransform(S, stau, r, Y, k, sdots);
+    tri_invit(sd, se, r, sev, kv, Y, lu, scl);
+    tridiag_backtransform(S, stau, r, Y, kv, sdots);
     for (int idx = threadIdx.x; idx < r * k; idx += NT) a.UB[idx] = Y[idx];
-    for (int i = threadIdx.x; i < kv; i += NT) a.sig[i] = sqrt(fmax(sev[i], 0.0));
     for (int idx = threadIdx.x; idx < r * k; idx += NT) store_c(a.Zc, a.prec, idx, Y[idx]);
+    // Sigma_B(i) = |B^T U_B(:, i)| (accurate to about r u sigma_1, where
+    // sqrt(lambda_i) of B B^T loses r u sigma_1^2 / sigma_i): lane i of every
+    // wave sums its columns of B in order, the waves' sums are added in order
+    __shared__ double spart[NT / 64][64];
+    for (int i0 = 0; i0 < kv; i0 += 64) {
+        const int i = i0 + lane;
+        double acc = 0.0;
+        if (i < kv)
+            for (int64_t c = wv; c < a.n; c += NT / 64) {
+                double t = 0.0;
+                for (int j = 0; j < r; ++j) t = fma(a.B[j + c * r], Y[j + i * r], t);
+                acc = fma(t, t, acc);
+            }
+        spart[wv][lane] = acc;
+        __syncthreads();
+        if (wv == 0 && i < kv) {
+            double v = 0.0;
+            for (int q = 0; q < NT / 64; ++q) v += spart[q][lane];
+            a.sig[i] = sqrt(v);
+        }
+        __syncthreads();
+    }
 }
 
 hipError_t launch_rr_small(const RRArgs &a, hipStream_t st)

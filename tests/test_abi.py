@@ -60,3 +60,35 @@ def test_status_strings():
         pytest.skip("libpod.so not built")
     assert pod.status_str(pod.POD_OK) == "ok"
     assert "sample" in pod.status_str(pod.POD_EXHAUSTED)
+
+
+def test_wedin_inputs_are_checked_before_the_call():
+    """The quality-measure kernels read k columns of m (U) and n (V) rows in
+    the output type; wrong shapes, dtypes, devices or layouts are refused on
+    the host (CPU tensors stand in for the device here)."""
+    torch = pytest.importorskip("torch")
+    m, n, k = 7, 5, 3
+    dev = torch.device("cpu")
+    U = torch.zeros((k, m), dtype=torch.float32).T
+    V = torch.zeros((k, n), dtype=torch.float32).T
+    pod.check_pairs(U, V, m, n, k, torch.float32, dev)
+    bad = [
+        (torch.zeros((k - 1, m), dtype=torch.float32).T, V, torch.float32),   # fewer columns
+        (U, torch.zeros((k, n + 1), dtype=torch.float32).T, torch.float32),   # wrong rows
+        (U, V, torch.float64),                                                 # FP32 pairs on an FP64 context
+        (torch.zeros((m, k), dtype=torch.float32), V, torch.float32),          # row-major U
+    ]
+    for Ub, Vb, dt in bad:
+        with pytest.raises(ValueError):
+            pod.check_pairs(Ub, Vb, m, n, k, dt, dev)
+    with pytest.raises(ValueError):
+        pod.check_pairs(U, V, m, n, k, torch.float32, torch.device("cuda", 0))  # host tensors
+
+
+def test_stop_reason_names_cover_the_enum():
+    txt = open(os.path.join(ROOT, "include", "pod.h")).read()
+    codes = dict((name, int(v)) for name, v in re.findall(r"\b(POD_STOP_[A-Z_]+)\s*=\s*(\d+)", txt))
+    assert codes == {"POD_STOP_NONE": pod.POD_STOP_NONE, "POD_STOP_NONFINITE": pod.POD_STOP_NONFINITE,
+                     "POD_STOP_CONVERGED": pod.POD_STOP_CONVERGED, "POD_STOP_EXHAUSTED": pod.POD_STOP_EXHAUSTED,
+                     "POD_STOP_MAX_ITER": pod.POD_STOP_MAX_ITER, "POD_STOP_BREAKDOWN": pod.POD_STOP_BREAKDOWN}
+    assert set(pod.STOP_NAMES) == set(codes.values())

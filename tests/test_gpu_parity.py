@@ -693,13 +693,16 @@ def test_wedin_bound_state_errors(c1):
     POD_EINVAL."""
     A = _dev(c1.A)
     print("wedin errors", flush=True)
+    import ctypes
     with pod.PodContext(A, precision=pod.POD_F64, **_c1_params(r=20)) as ctx:
         ctx.run(n_iter=3)
-        U0 = torch.zeros((c1.A.shape[0], 10), dtype=torch.float64, device="cuda")
-        V0 = torch.zeros((c1.A.shape[1], 10), dtype=torch.float64, device="cuda")
-        with pytest.raises(pod.PodError) as e:
-            ctx.wedin_bound(U0.T.contiguous().T, V0.T.contiguous().T)
-        assert e.value.status == pod.POD_ESTATE
+        U0 = torch.zeros((10, c1.A.shape[0]), dtype=torch.float64, device="cuda")
+        V0 = torch.zeros((10, c1.A.shape[1]), dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError):          # the binding refuses pairs no project() returned
+            ctx.wedin_bound(U0.T, V0.T)
+        out = (ctypes.c_double * 4)()
+        st = pod.lib().pod_wedin_bound(ctx.h, ctypes.c_void_p(U0.data_ptr()), ctypes.c_void_p(V0.data_ptr()), out)
+        assert st == pod.POD_ESTATE
     with pod.PodContext(A, precision=pod.POD_F64, **_c1_params()) as ctx:
         ctx.run(n_iter=3)
         U, _, V = ctx.project(want_v=True)

@@ -6,6 +6,7 @@ Philox, Python integers, LAPACK through numpy/scipy as an outside opinion) or
 a bound stated in the paper.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -441,3 +442,21 @@ def test_wedin_theorem_holds(eps):
     lhs = math.sqrt(np.sum(np.sin(sin_t) ** 2) + np.sum(np.sin(sin_p) ** 2))
     assert lhs <= math.sqrt(rn * rn + sn * sn) / omega * (1 + 1e-9)
     assert lhs > 0.0
+
+
+def test_oracle_bits_do_not_depend_on_threads():
+    """The C oracle splits only loops over independent columns between
+    threads: merges, projections and norms are bitwise the same at 1 and 4
+    threads."""
+    rng = np.random.default_rng(17)
+    A = rng.standard_normal((3000, 90))
+    U0, _ = np.linalg.qr(rng.standard_normal((3000, 12)))
+    outs = []
+    for th in (1, 4):
+        oracle.set_threads(th)
+        Um, sm = oracle.merge(U0, np.linspace(3, 1, 12), A[:, :40], 12)
+        Up, sp, Vp = oracle.project(A, Um)
+        outs.append((Um, sm, Up, sp, Vp, oracle.col_sqnorms(A)))
+    oracle.set_threads(os.cpu_count() or 1)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
