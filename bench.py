@@ -59,8 +59,8 @@ def parse():
                          "k=20, c=40; c5: 64-matrix batch, forward + gradient; c4: Alg. 3 over pinned host "
                          "blocks of 2M x 512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=20_000, help="rows of the oracle's larger row subsample")
-    ap.add_argument("--cpu-merges", type=int, default=4, help="oracle merges timed per row subsample")
+    ap.add_argument("--cpu-rows", type=int, default=50_000, help="rows of the oracle's larger row subsample")
+    ap.add_argument("--cpu-merges", type=int, default=6, help="oracle merges timed per row subsample")
     ap.add_argument("--c5-count", type=int, default=64)
     ap.add_argument("--c4-blocks", type=int, default=8, help="blocks of 512 columns (32: the full 16,000)")
     return ap.parse_args()

@@ -363,6 +363,16 @@ pod_status pod_get_col_sqnorms(pod_ctx *ctx, double *nu_host);
 pod_status pod_col_sqnorms(const void *A_dev, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
                            double *nu_dev, void *stream);
 
+/* Row centring of an m x n device matrix in place (the snapshots are
+ * mean-subtracted before the POD, Sec. 1): mean_i = (1/n) sum_j a_ij summed in
+ * FP64 (rows along threads; the columns split into s = min(8, max(1,
+ * ceil(2048 / ceil(m / 256)))) ranges whose sums are added in order), then
+ * a_ij <- a_ij - mean_i rounded to the storage type.  What
+ * pod_init does with center_rows = 1; Alg. 3 needs it over the whole matrix
+ * before the blocks are streamed.  Allocates a scratch of s m doubles for the
+ * call.  Syncs `stream`.  POD_EINVAL for bad sizes or types. */
+pod_status pod_center_rows(void *A_dev, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, void *stream);
+
 /* Sample sizes of Eqs. (c_LTSVD) and (c_w_CTSVD), rounded up:
  * kind 0: c = 4k (1 + sqrt(8 ln(1/delta)))^2 / eps^2;
  * kind 1: c = w = k^2 (1 + sqrt(ln(2/delta)))^2 / eps^4.

@@ -32,7 +32,7 @@ EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project"
            "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy", "pod_batch_init",
            "pod_batch_autotune", "pod_batch_run", "pod_batch_project", "pod_batch_get_info", "pod_batch_destroy",
            "pod_enable_adjoint", "pod_backward", "pod_loss_grad", "pod_batch_enable_adjoint", "pod_batch_loss_grad", "pod_batch_loss_grad_all",
-           "pod_run", "pod_set_indices"]
+           "pod_run", "pod_set_indices", "pod_center_rows"]
 
 
 class PodError(RuntimeError):
@@ -94,6 +94,7 @@ def lib():
             "pod_set_indices": (i32, [vp, i32, P(i32), P(i32), i32, P(i32), P(i32), i32]),
             "pod_get_col_sqnorms": (i32, [vp, vp]),
             "pod_col_sqnorms": (i32, [vp, i32, i64, i64, i64, vp, vp]),
+            "pod_center_rows": (i32, [vp, i32, i64, i64, i64, vp]),
             "pod_sample_size": (i64, [i32, i32, d, d]),
             "pod_destroy": (None, [vp]),
             "pod_status_str": (ctypes.c_char_p, [i32]),
@@ -675,6 +676,14 @@ def profile_read():
     n, ms = ctypes.c_int64(), ctypes.c_double()
     _check(lib().pod_profile_read(ctypes.byref(n), ctypes.byref(ms)), "pod_profile_read")
     return n.value, ms.value
+
+
+def center_rows(A, stream=None):
+    """Subtract the FP64 row means of the device matrix A (m x n, contiguous
+    columns) in place (pod_center_rows)."""
+    ptr, m, n, lda, code = _a_layout(A)
+    _check(lib().pod_center_rows(ctypes.c_void_p(ptr), code, m, n, lda, _stream_handle(stream)), "pod_center_rows")
+    return A
 
 
 def col_sqnorms(A, stream=None):

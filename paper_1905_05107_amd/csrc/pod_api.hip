@@ -419,16 +419,12 @@ pod_status pod::ctx_bind(pod_ctx *ctx, void *A_dev, int64_t n, int64_t lda, uint
     POD_HIP(hipMemsetAsync(ctx->sig[1], 0, sizeof(double) * r, ctx->st));
     if (p.w > 0) POD_HIP(hipMemsetAsync(ctx->rcnt_log, 0, sizeof(int32_t) * (size_t)cap_iter * p.w, ctx->st));
     if (p.center_rows) {
-        // row means over 8 column ranges (FP64), then a_ij <- a_ij - mean_i
-        const int32_t ns = 8;
-        double *scratch = nullptr;
-        POD_HIP(hipMalloc((void **)&scratch, sizeof(double) * (size_t)(ns + 1) * m));
-        hipError_t e = launch_row_means(A_dev, p.a_dtype, m, n, p.lda, scratch, ns, scratch + (size_t)ns * m, ctx->st);
-        if (e == hipSuccess) e = launch_center(A_dev, p.a_dtype, m, n, p.lda, scratch + (size_t)ns * m, ctx->st);
-        if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
-        const hipError_t ef = hipFree(scratch);
-        POD_HIP(e);
-        POD_HIP(ef);
+        // row means (FP64), then a_ij <- a_ij - mean_i
+        const pod_status sc = pod_center_rows(A_dev, p.a_dtype, m, n, p.lda, ctx->st);
+        if (sc != POD_OK) {
+            if (sc == POD_EHIP) ctx->failed = 1;
+            return sc;
+        }
     }
     POD_HIP(launch_col_sqnorms(A_dev, p.a_dtype, m, n, p.lda, ctx->nu, ctx->st));
     POD_HIP(launch_quantize(ctx->nu, n, ctx->wq, ctx->ds, 0, ctx->st));

@@ -101,10 +101,10 @@ struct ProfScope {
 
 hipError_t launch_col_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *nu,
                               hipStream_t st);
-hipError_t launch_row_means(const void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *part,
-                            int32_t nsplit, double *mean, hipStream_t st);
-hipError_t launch_center(void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, const double *mean,
-                         hipStream_t st);
+// Row centring of A in place; scratch holds center_splits(m) * m doubles.
+int32_t center_splits(int64_t m);
+hipError_t launch_center_rows(void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *scratch,
+                              hipStream_t st);
 hipError_t launch_quantize(const double *v, int64_t len, uint64_t *w, DevState *ds, int32_t guard, hipStream_t st);
 
 struct DrawArgs {

@@ -1,4 +1,4 @@
-// pod_sample.hip -- column squared norms, row centring, integer sampling weights
+// pod_sample.hip -- column squared norms, integer sampling weights
 // and the Philox column draw of GET UPDATE (Alg. 1) for gfx950.
 //
 // The column norms and the draw must reproduce the same integers on every
@@ -104,72 +104,6 @@ hipError_t launch_col_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t
                            nu);
     else
         hipLaunchKernelGGL(k_col_sqnorms<float>, dim3((unsigned)n), dim3(256), 0, st, (const float *)A, m, lda, nu);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Row centring (optional set-up step): mean_i = (1/n) sum_j a_ij in FP64, then
-// a_ij <- a_ij - mean_i rounded to the storage type.  Threads run along rows
-// (coalesced in column-major storage); the n columns are split into `nsplit`
-// ranges whose partial sums are added in range order.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_row_partial(const T *__restrict__ A, int64_t m, int64_t n, int64_t lda,
-                                                     int32_t nsplit, double *__restrict__ part)
-{
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= m) return;
-    const int32_t sp = blockIdx.y;
-    const int64_t j0 = (n * sp) / nsplit, j1 = (n * (sp + 1)) / nsplit;
-    double acc = 0.0;
-    for (int64_t j = j0; j < j1; ++j) acc += (double)A[j * lda + i];
-    part[(int64_t)sp * m + i] = acc;
-}
-
-__global__ __launch_bounds__(256) void k_row_mean(const double *__restrict__ part, int64_t m, int64_t n,
-                                                  int32_t nsplit, double *__restrict__ mean)
-{
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= m) return;
-    double acc = 0.0;
-    for (int32_t sp = 0; sp < nsplit; ++sp) acc += part[(int64_t)sp * m + i];
-    mean[i] = acc / (double)n;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_center(T *__restrict__ A, int64_t m, int64_t lda,
-                                                const double *__restrict__ mean)
-{
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= m) return;
-    T *a = A + (int64_t)blockIdx.y * lda + i;
-    *a = (T)((double)*a - mean[i]);
-}
-
-hipError_t launch_row_means(const void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double *part,
-                            int32_t nsplit, double *mean, hipStream_t st)
-{
-    dim3 g1((unsigned)((m + 255) / 256), (unsigned)nsplit);
-    if (a_dtype == POD_F64)
-        hipLaunchKernelGGL(k_row_partial<double>, g1, dim3(256), 0, st, (const double *)A, m, n, lda, nsplit, part);
-    else
-        hipLaunchKernelGGL(k_row_partial<float>, g1, dim3(256), 0, st, (const float *)A, m, n, lda, nsplit, part);
-    hipLaunchKernelGGL(k_row_mean, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, part, m, n, nsplit, mean);
-    return hipGetLastError();
-}
-
-hipError_t launch_center(void *A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, const double *mean,
-                         hipStream_t st)
-{
-    // one grid row per column; n <= 65535 per launch in y, so split larger n
-    for (int64_t j0 = 0; j0 < n; j0 += 65535) {
-        const int64_t nj = (n - j0 < 65535) ? (n - j0) : 65535;
-        dim3 g((unsigned)((m + 255) / 256), (unsigned)nj);
-        if (a_dtype == POD_F64)
-            hipLaunchKernelGGL(k_center<double>, g, dim3(256), 0, st, (double *)A + j0 * lda, m, lda, mean);
-        else
-            hipLaunchKernelGGL(k_center<float>, g, dim3(256), 0, st, (float *)A + j0 * lda, m, lda, mean);
-    }
     return hipGetLastError();
 }
 

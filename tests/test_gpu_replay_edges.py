@@ -260,8 +260,10 @@ def test_center_rows_parity(dtype):
     print(f"center rows {dtype.__name__}", flush=True)
     want, mean = center_rows(raw)
     Ad = _dev(raw)
+    Bd = pod.center_rows(_dev(raw))                  # the stand-alone entry point, same kernels
     with pod.PodContext(Ad, precision=prec, center_rows=True, **kw) as ctx:
         got = Ad.cpu().numpy()
+        assert torch.equal(Ad, Bd)
         ctx.run()
         T = ctx.info().iter
         cols = [ctx.indices(t)[0] for t in range(T)]
