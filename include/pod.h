@@ -373,6 +373,17 @@ pod_status pod_col_sqnorms(const void *A_dev, int32_t a_dtype, int64_t m, int64_
  * call.  Syncs `stream`.  POD_EINVAL for bad sizes or types. */
 pod_status pod_center_rows(void *A_dev, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, void *stream);
 
+/* pod_center_rows for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result bit for bit, with the scratch in a device
+ * array of the library (2^23 doubles = 64 MiB per device, kept until the
+ * process ends), so s m <= 2^23 (s as in pod_center_rows; m <= 4,194,304
+ * rows), else POD_EINVAL.  Runs on the current device, which must own A and
+ * `stream`.  Stream-ordered, no sync, no allocation.  The array is shared by
+ * every call on a device: calls that overlap on one device (other streams or
+ * threads) race. */
+pod_status pod_center_rows_noalloc(void *A_dev, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, void *stream);
+
 /* Sample sizes of Eqs. (c_LTSVD) and (c_w_CTSVD), rounded up:
  * kind 0: c = 4k (1 + sqrt(8 ln(1/delta)))^2 / eps^2;
  * kind 1: c = w = k^2 (1 + sqrt(ln(2/delta)))^2 / eps^4.

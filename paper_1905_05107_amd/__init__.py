@@ -32,7 +32,7 @@ EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project"
            "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy", "pod_batch_init",
            "pod_batch_autotune", "pod_batch_run", "pod_batch_project", "pod_batch_get_info", "pod_batch_destroy",
            "pod_enable_adjoint", "pod_backward", "pod_loss_grad", "pod_batch_enable_adjoint", "pod_batch_loss_grad", "pod_batch_loss_grad_all",
-           "pod_run", "pod_set_indices", "pod_center_rows"]
+           "pod_run", "pod_set_indices", "pod_center_rows", "pod_center_rows_noalloc"]
 
 
 class PodError(RuntimeError):
@@ -95,6 +95,7 @@ def lib():
             "pod_get_col_sqnorms": (i32, [vp, vp]),
             "pod_col_sqnorms": (i32, [vp, i32, i64, i64, i64, vp, vp]),
             "pod_center_rows": (i32, [vp, i32, i64, i64, i64, vp]),
+            "pod_center_rows_noalloc": (i32, [vp, i32, i64, i64, i64, vp]),
             "pod_sample_size": (i64, [i32, i32, d, d]),
             "pod_destroy": (None, [vp]),
             "pod_status_str": (ctypes.c_char_p, [i32]),
@@ -683,6 +684,15 @@ def center_rows(A, stream=None):
     columns) in place (pod_center_rows)."""
     ptr, m, n, lda, code = _a_layout(A)
     _check(lib().pod_center_rows(ctypes.c_void_p(ptr), code, m, n, lda, _stream_handle(stream)), "pod_center_rows")
+    return A
+
+
+def center_rows_noalloc(A, stream=None):
+    """center_rows without any device allocation (the library's own device
+    scratch, m <= 4,194,304 rows); stream-ordered, no sync."""
+    ptr, m, n, lda, code = _a_layout(A)
+    _check(lib().pod_center_rows_noalloc(ctypes.c_void_p(ptr), code, m, n, lda, _stream_handle(stream)),
+           "pod_center_rows_noalloc")
     return A
 
 

@@ -2,6 +2,8 @@
 // the mean-subtracted snapshots, Sec. 1): mean_i = (1/n) sum_j a_ij in FP64,
 // then a_ij <- a_ij - mean_i rounded to the storage type.  Used by pod_init
 // (center_rows = 1) and by the stand-alone pod_center_rows.
+#include <mutex>
+
 #include "pod_ctx.h"
 
 #pragma clang fp contract(off)
@@ -80,6 +82,34 @@ hipError_t launch_center_rows(void *A, int32_t a_dtype, int64_t m, int64_t n, in
 
 using namespace pod;
 
+// Device scratch of pod_center_rows_noalloc: 2^23 doubles (64 MiB), one copy
+// per device, held until the process ends.  Host code never uses this name
+// as an address: the per-device pointers below come from hipGetSymbolAddress.
+constexpr size_t CENTER_SCRATCH_DOUBLES = (size_t)1 << 23;
+static __device__ __align__(256) double scratch[CENTER_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double *scratch_ptr[MAX_DEVICES] = {};
+
+// The current device's copy of `scratch`, looked up once per device.
+pod_status scratch_for_current_device(double **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return POD_EHIP;
+    if (dev < 0 || dev >= MAX_DEVICES) return POD_EINVAL;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return POD_EHIP;
+        scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = scratch_ptr[dev];
+    return POD_OK;
+}
+}  // namespace
+
 extern "C" {
 
 pod_status pod_center_rows(void *A_dev, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, void *stream)
@@ -94,6 +124,18 @@ pod_status pod_center_rows(void *A_dev, int32_t a_dtype, int64_t m, int64_t n, i
     const hipError_t ef = hipFree(scratch);
     if (e == hipSuccess) e = ef;
     return (e == hipSuccess) ? POD_OK : POD_EHIP;
+}
+
+pod_status pod_center_rows_noalloc(void *A_dev, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, void *stream)
+{
+    if (!A_dev || m < 1 || n < 1 || lda < m || (a_dtype != POD_F64 && a_dtype != POD_F32)) return POD_EINVAL;
+    if ((size_t)center_splits(m) * (size_t)m > CENTER_SCRATCH_DOUBLES) return POD_EINVAL;
+    double *ws = nullptr;
+    const pod_status s = scratch_for_current_device(&ws);
+    if (s != POD_OK) return s;
+    // every scratch entry the kernels read is written first in the same call
+    return (launch_center_rows(A_dev, a_dtype, m, n, lda, ws, (hipStream_t)stream) == hipSuccess) ? POD_OK
+                                                                                                   : POD_EHIP;
 }
 
 }  // extern "C"
