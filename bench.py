@@ -71,7 +71,11 @@ def kernel_work(cls, path, m, n, k, p, r, launches):
     averaged over the launches of one step: (bound, amount, unit, hbm_bytes,
     peak key).
 
-    colnorms / project: one pass over A (m n 4 bytes; A is stored FP32).
+    colnorms: one pass over A (m n 4 bytes; A is stored FP32).  project:
+    B = U^T A, 2 m n k flops (one launch of the pair partial + reduce counts
+    half), reading A once: arithmetic intensity 2 k / 4 = 25 flop/B at k = 50,
+    above the FP64 (9.8) and FP32 (19.7) ridges, so matrix-core bound (FP32 on
+    the split-BF16 path, whose final step runs in FP32).
     gram: symmetric Gram m p (p+1) flops reading the m x p block (4 bytes per
     element from A, the basis in the compute type: counted at its own width
     e).  tall: Y = X0 T1 (m p p MACs) and U = Y Z2 (m p r MACs) averaged:
@@ -87,7 +91,7 @@ def kernel_work(cls, path, m, n, k, p, r, launches):
         return "hbm", m * n * 4, "B", m * n * 4, None
     if cls == "project":
         b = m * n * 4 / max(launches, 1)
-        return "hbm", b, "B", b, None
+        return "mfma", 2.0 * m * n * k / max(launches, 1), "flop", b, "f64" if path == "f64" else "f32"
     if cls == "gram":
         if path == "bf16":
             return "hbm", m * p * 4, "B", m * p * 4, None

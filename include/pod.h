@@ -54,8 +54,16 @@ typedef enum {
 typedef enum { POD_F64 = 0, POD_F32 = 1, POD_BF16_REFINE = 2 } pod_precision;
 
 /* Column sampling from the second iteration on (first iteration: always
- * column-norm probabilities, Eq. LTSVD_prob). */
-typedef enum { POD_COL_L2N = 0, POD_COL_UNF = 1 } pod_col_strategy;
+ * column-norm probabilities, Eq. LTSVD_prob):
+ *   POD_COL_L2N  squared column norms over S;
+ *   POD_COL_UNF  uniform over S;
+ *   POD_COL_ORT  squared residuals |a_j - U U^T a_j|^2 of the columns of S
+ *                against the current merged basis (Sec. "Column sampling"
+ *                (c)), formed as nu_j - |U^T a_j|^2 from one pass over A per
+ *                iteration (FP64 sums); residuals at or below 1e-12 nu_j
+ *                (FP64 basis) or 16 u_32 nu_j (FP32 basis) count as zero.
+ *                Single runs and Alg. 3 (the batch rejects it). */
+typedef enum { POD_COL_L2N = 0, POD_COL_UNF = 1, POD_COL_ORT = 2 } pod_col_strategy;
 
 /* Row sampling when w > 0: squared row norms of the sampled columns
  * (Eq. CTSVD_prob) or leverage scores of the current modes (second

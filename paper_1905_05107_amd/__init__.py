@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpod.so")
 
 POD_OK, POD_EINVAL, POD_ENOMEM, POD_EHIP, POD_ENOTPD, POD_ESTATE, POD_EXHAUSTED, POD_ENONFINITE, POD_ENOCONV = range(9)
 POD_F64, POD_F32, POD_BF16_REFINE = 0, 1, 2
-POD_COL_L2N, POD_COL_UNF = 0, 1
+POD_COL_L2N, POD_COL_UNF, POD_COL_ORT = 0, 1, 2
 POD_ROW_L2, POD_ROW_LS = 0, 1
 POD_CRIT_SUBSPACE, POD_CRIT_MODE = 0, 1
 POD_STOP_NONE, POD_STOP_NONFINITE, POD_STOP_CONVERGED, POD_STOP_EXHAUSTED, POD_STOP_MAX_ITER, POD_STOP_BREAKDOWN = \

@@ -23,6 +23,11 @@ template <typename T> hipError_t dalloc(T **p, size_t count)
 
 double unit_roundoff(int32_t prec) { return prec == POD_F64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08; }
 
+// ORT residuals nu_j - |U^T a_j|^2 at or below this fraction of nu_j count as
+// zero: the column lies in the current subspace to the accuracy of the basis
+// (FP64: the oracle's 1e-12; FP32 bases: 16 u_32, the size of the cancellation)
+double ort_floor(int32_t prec) { return prec == POD_F64 ? 1e-12 : 16.0 * 5.9604644775390625e-08; }
+
 #define POD_HIP(call)                                                                                                 \
     do {                                                                                                              \
         hipError_t e_ = (call);                                                                                       \
@@ -75,7 +80,7 @@ void free_all(pod_ctx *ctx)
                     ctx->rho,  ctx->Vt,   ctx->wr,    ctx->rows, ctx->rcnt, ctx->row_log, ctx->rcnt_log,
                     ctx->ws,   ctx->ckU,  ctx->ckS,   ctx->ckR,  ctx->ckMeta, ctx->dsb, ctx->partb, ctx->Gext,
                     ctx->adj_ws, ctx->sbar[0], ctx->sbar[1], ctx->lossp, ctx->Wt, ctx->Ubar[0], ctx->Ubar[1],
-                    ctx->sin_log, ctx->tsplit, ctx->qws};
+                    ctx->sin_log, ctx->tsplit, ctx->qws, ctx->rho_ort, ctx->wort};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -240,7 +245,8 @@ pod_status pod_init(pod_ctx **out, const pod_params *prm, void *A_dev, void *str
 DrawArgs pod::ctx_draw_args(pod_ctx *ctx)
 {
     DrawArgs a;
-    a.wq = ctx->wq;
+    a.wq = (ctx->prm.col_strategy == POD_COL_ORT) ? ctx->wort : ctx->wq;
+    a.wq_left = ctx->wq;
     a.inS = ctx->inS;
     a.n = ctx->prm.n;
     a.c = ctx->prm.c;
@@ -301,7 +307,8 @@ pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
     if (p.w < 0 || p.w > 1024 || p.r_update < 0) return POD_EINVAL;
     if (p.w > 0 && p.row_strategy != POD_ROW_L2 && p.row_strategy != POD_ROW_LS) return POD_EINVAL;
     if (p.w > 0 && p.m > 0x7fffffff) return POD_EINVAL;
-    if (p.col_strategy != POD_COL_L2N && p.col_strategy != POD_COL_UNF) return POD_EINVAL;
+    if (p.col_strategy != POD_COL_L2N && p.col_strategy != POD_COL_UNF && p.col_strategy != POD_COL_ORT)
+        return POD_EINVAL;
     if (p.criterion != POD_CRIT_SUBSPACE && p.criterion != POD_CRIT_MODE) return POD_EINVAL;
     if (!(p.theta_tol >= 0.0)) return POD_EINVAL;
     const int64_t cmax = (p.c < p.n) ? p.c : p.n;
@@ -359,6 +366,10 @@ pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
     ALLOC(ctx->signv, double, (size_t)64 * r);
     ALLOC(ctx->signi, int64_t, (size_t)64 * r);
     if (p.w > 0 || p.r_update > 0) ALLOC(ctx->Vt, double, (size_t)pmax * pmax);
+    if (p.col_strategy == POD_COL_ORT) {
+        ALLOC(ctx->rho_ort, double, n);
+        ALLOC(ctx->wort, uint64_t, n);
+    }
     if (pmax > 64) ALLOC(ctx->ws, double, (size_t)3 * pmax * pmax + pmax + BIG_INVIT_DOUBLES);
     if (p.w > 0) {
         ALLOC(ctx->rho, double, m);
@@ -435,6 +446,31 @@ pod_status pod::ctx_bind(pod_ctx *ctx, void *A_dev, int64_t n, int64_t lda, uint
 // the new block when rows are sampled), enqueued without waiting.
 static pod_status enqueue_sample(pod_ctx *ctx)
 {
+    if (ctx->prm.col_strategy == POD_COL_ORT) {
+        // ORT weights from the second iteration: B = U^T A over every column
+        // (the live rank and the current basis are picked on the device),
+        // residuals nu_j - |B(:, j)|^2 over S, integer weights
+        const pod_params &p = ctx->prm;
+        ProjArgs pa;
+        pa.prec = p.precision;
+        pa.a_dtype = p.a_dtype;
+        pa.m = p.m;
+        pa.n = p.n;
+        pa.lda = p.lda;
+        pa.U = ctx->U[0];
+        pa.U1 = ctx->U[1];
+        pa.ds = ctx->ds;
+        pa.A = ctx->A;
+        pa.r = ctx->r;
+        pa.Bpart = ctx->Bpart;
+        pa.nsplit = ctx->nsplit;
+        pa.B = ctx->B;
+        POD_HIP(launch_project_partial(pa, ctx->st));
+        POD_HIP(launch_project_reduce(pa, ctx->st));
+        POD_HIP(launch_ort_resid(ctx->nu, ctx->B, ctx->r, p.n, ctx->inS, ort_floor(p.precision), ctx->ds, ctx->rho_ort,
+                                 ctx->st));
+        POD_HIP(launch_quantize(ctx->rho_ort, p.n, ctx->wort, ctx->ds, 0, ctx->st));
+    }
     DrawArgs a = ctx_draw_args(ctx);
     POD_HIP(launch_draw_cols(a, ctx->st));
     const pod_params &p = ctx->prm;
@@ -605,6 +641,7 @@ pod_status pod::ctx_project(pod_ctx *ctx, void *U_out, double *sigma_out, void *
     ra.n = p.n;
     ra.r = rs;
     ra.k = k;
+    ra.part = ctx->Bpart;   // free once B is reduced
     ra.GB = ctx->GB;
     ra.UB = ctx->UB;
     ra.sig = ctx->sigB;

@@ -127,6 +127,7 @@ pod_status pod_batch_init(pod_batch **out, int32_t count, const pod_params *prm,
         if (prm[i].w != 0 || prm[i].r_update != 0) return POD_EINVAL;
         if (prm[i].precision != prm[0].precision) return POD_EINVAL;
         if (prm[i].precision == POD_BF16_REFINE) return POD_EINVAL;   // batched kernels: FP64 / FP32
+        if (prm[i].col_strategy == POD_COL_ORT) return POD_EINVAL;    // batched draws: L2N / UNF
     }
     pod_batch *b = new (std::nothrow) pod_batch();
     if (!b) return POD_ENOMEM;

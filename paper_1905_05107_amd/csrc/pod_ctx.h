@@ -20,6 +20,8 @@ struct pod_ctx {
     int32_t *cols = nullptr, *ccnt = nullptr, *col_log = nullptr, *ccnt_log = nullptr, *col_log_off = nullptr;
     int32_t *forced = nullptr;
     double *rho = nullptr, *Vt = nullptr;  // row weights (m), right factor of the new block (pmax x pmax)
+    double *rho_ort = nullptr;             // ORT column residuals (n)
+    uint64_t *wort = nullptr;              // their integer weights (n)
     uint64_t *wr = nullptr;
     int32_t *rows = nullptr, *rcnt = nullptr, *row_log = nullptr, *rcnt_log = nullptr;
     void *U[2] = {nullptr, nullptr};

@@ -20,6 +20,7 @@ constexpr int RB = 32;       // rows per LDS stage
 constexpr int LDSR = RB + 1; // padded stride (elements) of one staged column
 constexpr int GRP = RB / 4;  // 4-row groups per staged column
 constexpr int TALL_ST = 8;                 // row stages per workgroup of the tall transforms
+constexpr int TALL_ST_WIDE = 16;           // the same for inputs wider than 64 (T staged once per 16 stages)
 constexpr size_t TALL_T_LDS = 112 * 1024;  // largest T staged in LDS
 constexpr int TALL_DYN_LDS = 160 * 1024;   // dynamic LDS limit of the tall kernels
 
@@ -118,37 +119,46 @@ __device__ __forceinline__ void load4(const ColPtr &cp, int64_t row, int64_t lim
 // A register-held stage: item `it` of thread t is (column, 4-row group)
 // = ((t + 256 it) / GRP, (t + 256 it) % GRP).  prepare() fixes the column
 // start of every item once (the columns do not change between stages); when
-// every column is stored in the compute type and 16-byte aligned, a full
-// stage is then loaded with plain vector loads and no branch, so the loads of
-// the stages in flight are not waited for until their store.  Items beyond
-// the P columns point at column 0 and are replaced by zeros at the store.
+// every column is 16-byte aligned, a full stage is then loaded with plain
+// vector loads (FP32 columns of A widened to FP64 on the FP64 path), so the
+// loads of the stages in flight are not waited for until their store.  Items
+// beyond the P columns point at column 0 and are replaced by zeros at the
+// store.
 template <typename TC, int ITEMS> struct Stage {
     TC v[ITEMS][4];
     const TC *base[ITEMS];
+    uint32_t f32col;   // bit it: item it reads an FP32 column while TC is double
     bool fast;
 
     __device__ __forceinline__ void prepare(const SrcT<TC> &s, int64_t m, int P, bool vec)
     {
-        const bool same = !s.gather || (s.a_f64 != 0) == (sizeof(TC) == 8);
-        fast = vec && same;
+        fast = vec;
+        f32col = 0;
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const int idx = threadIdx.x + 256 * it;
             const int c = idx / GRP;
             const ColPtr cp = col_ptr<TC>(s, m, (c < P) ? c : 0);
             base[it] = reinterpret_cast<const TC *>(cp.p);
+            if (sizeof(TC) == 8 && !cp.f64) f32col |= 1u << it;
         }
     }
 
     // a full stage on the fast path (prepare() set fast, rb + RB <= m): vector
-    // loads only, no branch
+    // loads only
     __device__ __forceinline__ void load_full(int64_t rb)
     {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const int g = (threadIdx.x + 256 * it) % GRP;
             const TC *q = base[it] + rb + 4 * g;
-            if (sizeof(TC) == 4) {
+            if (sizeof(TC) == 8 && ((f32col >> it) & 1u)) {
+                const f32x4 a = *(reinterpret_cast<const f32x4 *>(reinterpret_cast<const float *>(base[it]) + rb) + g);
+                v[it][0] = a[0];
+                v[it][1] = a[1];
+                v[it][2] = a[2];
+                v[it][3] = a[3];
+            } else if (sizeof(TC) == 4) {
                 const f32x4 a = *reinterpret_cast<const f32x4 *>(q);
                 v[it][0] = a[0];
                 v[it][1] = a[1];
@@ -168,25 +178,7 @@ template <typename TC, int ITEMS> struct Stage {
     __device__ __forceinline__ void load(const SrcT<TC> &s, int64_t m, int64_t rb, int P, bool vec)
     {
         if (fast && rb + RB <= m) {
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it) {
-                const int g = (threadIdx.x + 256 * it) % GRP;
-                const TC *q = base[it] + rb + 4 * g;
-                if (sizeof(TC) == 4) {
-                    const f32x4 a = *reinterpret_cast<const f32x4 *>(q);
-                    v[it][0] = a[0];
-                    v[it][1] = a[1];
-                    v[it][2] = a[2];
-                    v[it][3] = a[3];
-                } else {
-                    const f64x2 a = *reinterpret_cast<const f64x2 *>(q);
-                    const f64x2 b = *reinterpret_cast<const f64x2 *>(q + 2);
-                    v[it][0] = a[0];
-                    v[it][1] = a[1];
-                    v[it][2] = b[0];
-                    v[it][3] = b[1];
-                }
-            }
+            load_full(rb);
             return;
         }
 #pragma unroll
@@ -329,6 +321,7 @@ __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const D
     Stage<TC, ITEMS> sa, sb;
     sa.prepare(s, m, P, vec);
     sb.fast = sa.fast;
+    sb.f32col = sa.f32col;
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) sb.base[it] = sa.base[it];
     // full stages [s0, e) on the fast path: two register stages in flight (the
@@ -1081,8 +1074,13 @@ hipError_t launch_gram_reduce_sel(const double *part, int32_t nblk, int32_t pmax
 // Each workgroup stages T once and about TALL_ST stages of RB rows of X
 // (grid-strided), producing
 // the output as Y^T tiles = T^T X^T so that each lane's four results are
-// consecutive rows of one output column.
+// consecutive rows of one output column.  T is staged in LDS in full, or,
+// when it is upper triangular and square (T1 = R1^-1 of the first pass) and
+// too large for that (FP64, 160 x 160), as its 16 x 16 tiles (kt, jt) with
+// kt <= jt packed column by column (tile jt (jt + 1) / 2 + kt, rows of 16
+// inside a tile); otherwise it is read from device memory (L2).
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int tri_tiles(int nt) { return nt * (nt + 1) / 2; }
 
 // Scatter output (SCAT): output columns below `split` go to Yout, column
 // split + j is added to D(:, cmap[j]) (leading dimension ldd); the mapped
@@ -1094,7 +1092,7 @@ struct TallScatter {
     int64_t ldd;
 };
 
-template <typename TC, int ITEMS, bool TG, bool SCAT = false>
+template <typename TC, int ITEMS, bool TG, bool SCAT = false, bool TP = false>
 __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in, int sel_out,
                                                int pmax_in, int pmax_out, const TC *__restrict__ T, int ldt,
                                                TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec, int bid,
@@ -1117,61 +1115,110 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
     const int64_t nst = (m + RB - 1) / RB;
     const int64_t ns = (bid < nst) ? (nst - 1 - bid) / nbk + 1 : 0;   // stages of this workgroup
     auto stage = [&](int64_t i) { return (int64_t)bid + i * nbk; };
-    if (!TG)
-        for (int idx = threadIdx.x; idx < PI * PO; idx += 256) {
-            const int k = idx / PO, j = idx % PO;
-            Ts[idx] = (k < pin && j < pout) ? T[k + (int64_t)j * ldt] : (TC)0;
+    // T is read down its columns (16 consecutive k per 16 threads) and
+    // written to LDS in the layout of the MFMA operand reads
+    if (TP) {
+        // packed upper-triangular tiles (PI == PO)
+        const int nt = PO / 16;
+        for (int idx = threadIdx.x; idx < tri_tiles(nt) * 256; idx += 256) {
+            const int t = idx >> 8, e = idx & 255;
+            int jt = 0;
+            while (tri_tiles(jt + 1) <= t) ++jt;
+            const int kt = t - tri_tiles(jt);
+            const int kk = e & 15, jj = e >> 4;
+            const int k = 16 * kt + kk, j = 16 * jt + jj;
+            Ts[t * 256 + kk * 16 + jj] = (k < pin && j < pout && k <= j) ? T[k + (int64_t)j * ldt] : (TC)0;
         }
+    } else if (!TG) {
+        for (int idx = threadIdx.x; idx < PI * PO; idx += 256) {
+            const int k = idx % PI, j = idx / PI;
+            Ts[k * PO + j] = (k < pin && j < pout) ? T[k + (int64_t)j * ldt] : (TC)0;
+        }
+    }
     (void)pmax_out;
     const int ntile = (RB / 16) * (PO / 16);
+    // one output tile (rows rbk of the stage, columns jc) to Y (or the scatter target)
+    auto store_tile = [&](int64_t sg, int rbk, int jc, const AccT &acc) {
+        const int64_t row = sg * RB + rbk * 16 + (lane & 15);
+        if (row < m) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = jc * 16 + acc_row<TC>(lane, v);
+                if (col >= pout) continue;
+                if (!SCAT || col < sc.split) {
+                    Yout[(int64_t)col * m + row] = acc[v];
+                } else {
+                    TC *d = reinterpret_cast<TC *>(sc.D) + (int64_t)sc.cmap[col - sc.split] * sc.ldd + row;
+                    *d += acc[v];
+                }
+            }
+        }
+    };
+    // T in LDS: wave wv owns the tiles of row block rbk = wv % 2 and column
+    // tiles jc = wv / 2 + 2 i; each X operand read from LDS feeds the MFMAs of
+    // all of them, which accumulate independently (no chained MFMAs)
+    constexpr int MAXJ = (ITEMS * 256 / GRP) / 32;
+    auto compute_lds = [&](int64_t sg) {
+        const int rbk = wv & 1, j0 = wv >> 1;
+        const int nj = (PO / 16 > j0) ? (PO / 16 - j0 + 1) / 2 : 0;
+        // k extent: T upper triangular ends column tile jc at row 16 (jc + 1)
+        const int jlast = j0 + 2 * (nj - 1);
+        const int ke = (tri && nj > 0 && 16 * (jlast + 1) < PI) ? 16 * (jlast + 1) : PI;
+        if (nj == 0) return;
+        AccT acc[MAXJ];
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i) acc[i] = AccT{0, 0, 0, 0};
+        const TC *xb = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
+        for (int k4 = 0; k4 < ke; k4 += 16) {
+            TC xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = xb[(k4 + 4 * u) * LDSR];
+#pragma unroll
+            for (int i = 0; i < MAXJ; ++i) {
+                const int jc = j0 + 2 * i;
+                if (i < nj && (!tri || k4 < 16 * (jc + 1))) {
+                    TC av[4];
+                    if (TP) {
+                        const TC *tp = Ts + (tri_tiles(jc) + k4 / 16) * 256 + (lane >> 4) * 16 + (lane & 15);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) av[u] = tp[64 * u];
+                    } else {
+                        const TC *ta = Ts + (k4 + (lane >> 4)) * PO + jc * 16 + (lane & 15);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) av[u] = ta[4 * u * PO];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[i] = mfma16x16x4(av[u], xv[u], acc[i]);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i)
+            if (i < nj) store_tile(sg, rbk, j0 + 2 * i, acc[i]);
+    };
     auto compute = [&](int64_t sg) {
+        if (!TG) {
+            compute_lds(sg);
+            return;
+        }
         for (int tile = wv; tile < ntile; tile += 4) {
             const int rbk = tile % (RB / 16), jc = tile / (RB / 16);
             AccT acc = AccT{0, 0, 0, 0};
             const TC *xb = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
-            if (!TG) {
-                const TC *ta = Ts + (lane >> 4) * PO + jc * 16 + (lane & 15);
-                // PI is a multiple of 16: four MFMAs with their operands loaded together;
-                // with T upper triangular the row tiles past column tile jc are zero
-                const int ke = (tri && 16 * (jc + 1) < PI) ? 16 * (jc + 1) : PI;
-                for (int k4 = 0; k4 < ke; k4 += 16) {
-                    TC av[4], xv[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        av[u] = ta[(k4 + 4 * u) * PO];
-                        xv[u] = xb[(k4 + 4 * u) * LDSR];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) acc = mfma16x16x4(av[u], xv[u], acc);
-                }
-            } else {
-                // T read from device memory (L2 resident), zero outside pin x pout
-                const int jj = jc * 16 + (lane & 15);
-                const TC *ta = T + (lane >> 4) + (int64_t)jj * ldt;
-                for (int k4 = 0; k4 < PI; k4 += 4) {
-                    const TC tv = (jj < pout && k4 + (lane >> 4) < pin) ? ta[k4] : (TC)0;
-                    acc = mfma16x16x4(tv, xb[k4 * LDSR], acc);
-                }
+            // T read from device memory (L2 resident), zero outside pin x pout
+            const int jj = jc * 16 + (lane & 15);
+            const TC *ta = T + (lane >> 4) + (int64_t)jj * ldt;
+            for (int k4 = 0; k4 < PI; k4 += 4) {
+                const TC tv = (jj < pout && k4 + (lane >> 4) < pin) ? ta[k4] : (TC)0;
+                acc = mfma16x16x4(tv, xb[k4 * LDSR], acc);
             }
-            const int64_t row = sg * RB + rbk * 16 + (lane & 15);
-            if (row < m) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int col = jc * 16 + acc_row<TC>(lane, v);
-                    if (col >= pout) continue;
-                    if (!SCAT || col < sc.split) {
-                        Yout[(int64_t)col * m + row] = acc[v];
-                    } else {
-                        TC *d = reinterpret_cast<TC *>(sc.D) + (int64_t)sc.cmap[col - sc.split] * sc.ldd + row;
-                        *d += acc[v];
-                    }
-                }
-            }
+            store_tile(sg, rbk, jc, acc);
         }
     };
     Stage<TC, ITEMS> sa, sb;
     sa.prepare(s, m, pin, vec);
     sb.fast = sa.fast;
+    sb.f32col = sa.f32col;
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) sb.base[it] = sa.base[it];
     // stages entirely inside [0, m) on the fast path (the last stage may be partial)
@@ -1212,14 +1259,14 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
     }
 }
 
-template <typename TC, int ITEMS, bool TG>
+template <typename TC, int ITEMS, bool TG, bool TP>
 __global__ __launch_bounds__(256) void k_gemm_tall(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
                                                    int sel_out, int pmax_in, int pmax_out, const TC *__restrict__ T,
                                                    int ldt, TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec,
                                                    int tri)
 {
-    gemm_tall_body<TC, ITEMS, TG>(s, m, ds, sel_in, sel_out, pmax_in, pmax_out, T, ldt, Yout, Yout1, vec,
-                                  blockIdx.x, gridDim.x, tri);
+    gemm_tall_body<TC, ITEMS, TG, false, TP>(s, m, ds, sel_in, sel_out, pmax_in, pmax_out, T, ldt, Yout, Yout1, vec,
+                                             blockIdx.x, gridDim.x, tri);
 }
 
 template <typename TC, int ITEMS>
@@ -1253,22 +1300,23 @@ __global__ __launch_bounds__(256) void k_gemm_tall_b(const TallArgs *__restrict_
                                      reinterpret_cast<TC *>(a.Yout1), a.vec, blockIdx.x, a.nb, a.tri);
 }
 
-template <typename TC, int ITEMS, bool TG>
+template <typename TC, int ITEMS, bool TG, bool TP = false>
 static void tall_launch(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out, int PI, int PO,
                         const void *T, int32_t ldt, void *Yout, void *Yout1, unsigned nb, int tri, hipStream_t st)
 {
     const SrcT<TC> s = make_src<TC>(d);
     constexpr int CW = ITEMS * 256 / GRP;   // columns of the LDS stage (every item stored)
-    const size_t lds = (size_t)(CW * LDSR + (TG ? 0 : PI * PO)) * sizeof(TC);
+    const size_t tsz = TP ? (size_t)tri_tiles(PO / 16) * 256 : (TG ? 0 : (size_t)PI * PO);
+    const size_t lds = (CW * LDSR + tsz) * sizeof(TC);
     static bool attr = false;
     if (lds > 64 * 1024 && !attr) {
-        if (hipFuncSetAttribute((const void *)k_gemm_tall<TC, ITEMS, TG>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                TALL_DYN_LDS) != hipSuccess)
+        if (hipFuncSetAttribute((const void *)k_gemm_tall<TC, ITEMS, TG, TP>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, TALL_DYN_LDS) != hipSuccess)
             return;   // the launch below then fails and reports the error
         attr = true;
     }
-    hipLaunchKernelGGL((k_gemm_tall<TC, ITEMS, TG>), dim3(nb), dim3(256), lds, st, s, d.m, ds, which_in, which_out,
-                       CW, PO, (const TC *)T, ldt, (TC *)Yout, (TC *)Yout1, (int)vec_ok(s, d.m), tri);
+    hipLaunchKernelGGL((k_gemm_tall<TC, ITEMS, TG, TP>), dim3(nb), dim3(256), lds, st, s, d.m, ds, which_in,
+                       which_out, CW, PO, (const TC *)T, ldt, (TC *)Yout, (TC *)Yout1, (int)vec_ok(s, d.m), tri);
 }
 
 hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
@@ -1278,9 +1326,11 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
     if (pin_max > PMAX_WIDE || pout_max > PMAX_WIDE) return hipErrorInvalidValue;
     ProfScope ps(POD_K_TALL, st);
     const int64_t nst = (d.m + RB - 1) / RB;
-    const unsigned nb = (unsigned)((nst + TALL_ST - 1) / TALL_ST);
     const int PI = (pin_max + 15) & ~15, PO = (pout_max + 15) & ~15;
     const bool wide = PI > 64;
+    if (!wide && PO > 64) return hipErrorInvalidValue;   // the narrow class holds 4 column tiles
+    const int stw = wide ? TALL_ST_WIDE : TALL_ST;
+    const unsigned nb = (unsigned)((nst + stw - 1) / stw);
     if (d.prec == POD_BF16_REFINE) {
         if (d.a_dtype != POD_F32 || !d.tsplit) return hipErrorInvalidValue;
         const int KP = (pin_max + 31) & ~31, JP = PO;
@@ -1295,8 +1345,13 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
             tall_bf16_direct_launch<5, 10>(s, d.m, ds, which_in, which_out, Tb, KP, JP, Yout, Yout1, vout, tri, st);
     } else if (d.prec == POD_F64) {
         const bool tg = (size_t)PI * PO * sizeof(double) > TALL_T_LDS;
+        // an upper-triangular square T packs into LDS beside the stage
+        const bool tp = tg && tri && PI == PO &&
+                        (size_t)(ITEMS160 * 256 / GRP * LDSR + tri_tiles(PO / 16) * 256) * sizeof(double) <=
+                            (size_t)TALL_DYN_LDS;
         if (!wide) tall_launch<double, ITEMS64, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
         else if (!tg) tall_launch<double, ITEMS160, false>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
+        else if (tp) tall_launch<double, ITEMS160, false, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
         else tall_launch<double, ITEMS160, true>(d, ds, which_in, which_out, PI, PO, T, ldt, Yout, Yout1, nb, tri, st);
     } else {
         const bool tg = (size_t)PI * PO * sizeof(float) > TALL_T_LDS;
@@ -1320,11 +1375,20 @@ constexpr int PCB = 64;  // columns of A per workgroup
 template <typename TC, typename TA, int MT, int UITEMS>
 __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ U, const TA *__restrict__ A,
                                                          int64_t m, int64_t n, int64_t lda, int r, int nsplit,
-                                                         int ncb, double *__restrict__ Bpart, int vec)
+                                                         int ncb, double *__restrict__ Bpart, int vec,
+                                                         const TC *__restrict__ U1, const DevState *ds)
 {
     typedef typename Acc<TC>::type AccT;
     extern __shared__ unsigned char lds_raw[];
     const int RP = (r + 15) & ~15;
+    // device-selected basis (ORT weights during the loop): the live rank, the
+    // current buffer, nothing on the first iteration or after the stop
+    int rl = r;
+    if (ds) {
+        if (ds->it == 0 || merge_halted(ds)) return;
+        rl = (ds->rs < r) ? ds->rs : r;
+        if (U1 && (ds->it & 1)) U = U1;
+    }
     TC *As = reinterpret_cast<TC *>(lds_raw);   // PCB x LDSR
     TC *Us = As + PCB * LDSR;                   // RP x LDSR
     const int total = nsplit * ncb;
@@ -1381,15 +1445,16 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
             }
         }
     };
-    stu[0].prepare(su, m, r, vec);
+    stu[0].prepare(su, m, rl, vec);
     stu[1].fast = stu[0].fast;
+    stu[1].f32col = stu[0].f32col;
 #pragma unroll
     for (int it = 0; it < UITEMS; ++it) stu[1].base[it] = stu[0].base[it];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         if (s0 + b < s1) {
             loadA(s0 + b, sta[b]);
-            stu[b].load(su, m, (s0 + b) * RB, r, vec);
+            stu[b].load(su, m, (s0 + b) * RB, rl, vec);
         }
     }
     auto compute = [&]() {
@@ -1409,11 +1474,11 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
             if (sg + b < s1) {   // uniform
                 __syncthreads();
                 sta[b].store(As, PCB, PCB);
-                stu[b].store(Us, RP, r);
+                stu[b].store(Us, RP, rl);
                 __syncthreads();
                 if (sg + b + 2 < s1) {
                     loadA(sg + b + 2, sta[b]);
-                    stu[b].load(su, m, (sg + b + 2) * RB, r, vec);
+                    stu[b].load(su, m, (sg + b + 2) * RB, rl, vec);
                 }
                 compute();
             }
@@ -1448,7 +1513,7 @@ static void project_launch(const ProjArgs &a, unsigned total, int ncb, int vec, 
     const int RP = (a.r + 15) & ~15;
     const size_t lds = (size_t)(PCB + RP) * LDSR * sizeof(TC);
     hipLaunchKernelGGL((k_project_partial<TC, TA, MT, UITEMS>), dim3(total), dim3(256), lds, st, (const TC *)a.U,
-                       (const TA *)a.A, a.m, a.n, a.lda, a.r, a.nsplit, ncb, a.Bpart, vec);
+                       (const TA *)a.A, a.m, a.n, a.lda, a.r, a.nsplit, ncb, a.Bpart, vec, (const TC *)a.U1, a.ds);
 }
 
 hipError_t launch_project_partial(const ProjArgs &a, hipStream_t st)
@@ -1461,7 +1526,7 @@ hipError_t launch_project_partial(const ProjArgs &a, hipStream_t st)
     const size_t ae = (a.a_dtype == POD_F64) ? 8 : 4;
     const size_t ce = (a.prec == POD_F64) ? 8 : 4;
     const int vec = ((uintptr_t)a.A % 16 == 0) && ((a.lda * ae) % 16 == 0) && ((uintptr_t)a.U % 16 == 0) &&
-                    ((a.m * ce) % 16 == 0);
+                    ((uintptr_t)a.U1 % 16 == 0) && ((a.m * ce) % 16 == 0);
     const bool wide = a.r > 64;
     if (a.prec == POD_F64) {
         if (a.a_dtype == POD_F64) {
@@ -1557,6 +1622,7 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
     const int PI = (pin_max + 15) & ~15, PO = (pout_max + 15) & ~15;
     const size_t esz = (d.prec == POD_F64) ? 8 : 4;
     if (PI > PMAX_WIDE || PO > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS) return hipErrorInvalidValue;
+    if (PI <= 64 && PO > 64) return hipErrorInvalidValue;   // the narrow class holds 4 column tiles
     const unsigned nb = (unsigned)tall_blocks(d.m);
     const TallScatter sc{split, cmap, D, ldd};
     const int CW = (PI > 64) ? 160 : 64;   // columns of the LDS stage of the tile class

@@ -108,7 +108,8 @@ hipError_t launch_center_rows(void *A, int32_t a_dtype, int64_t m, int64_t n, in
 hipError_t launch_quantize(const double *v, int64_t len, uint64_t *w, DevState *ds, int32_t guard, hipStream_t st);
 
 struct DrawArgs {
-    const uint64_t *wq;   // L2N weights (n)
+    const uint64_t *wq;   // weights of the draw (n): L2N, or ORT from the second iteration
+    const uint64_t *wq_left; // weights that decide whether S keeps a drawable column (nullable: wq)
     uint8_t *inS;         // membership of S (n)
     int64_t n;
     int32_t c;
@@ -316,6 +317,9 @@ struct ProjArgs {
     int32_t prec, a_dtype;
     int64_t m, n, lda;
     const void *U;        // basis m x r (compute type)
+    const void *U1 = nullptr;      // with ds set: the basis is U1 when the merge count is odd
+    const DevState *ds = nullptr;  // set: the live columns are ds->rs (<= r); nothing is done on the
+                                   // first iteration or once the run has stopped
     const void *A;
     int32_t r;
     double *Bpart;        // partial B (nsplit x r x n)
@@ -324,10 +328,17 @@ struct ProjArgs {
 };
 hipError_t launch_project_partial(const ProjArgs &a, hipStream_t st);
 hipError_t launch_project_reduce(const ProjArgs &a, hipStream_t st);
+// ORT column weights of GET UPDATE from the second iteration: for j in S,
+// rho_j = nu_j - |U^T a_j|^2 (B = U^T A, r x n, ld r; the live rows ds->rs),
+// zero when at most floor_rel nu_j; zero outside S; rho = nu on the first
+// iteration.
+hipError_t launch_ort_resid(const double *nu, const double *B, int32_t r, int64_t n, const uint8_t *inS,
+                            double floor_rel, const DevState *ds, double *rho, hipStream_t st);
 struct RRArgs {
     const double *B;      // r x n
     int64_t n;
     int32_t r, k;
+    double *part;         // scratch of the chunked sums: rr_part_doubles(n, r)
     double *GB;           // r x r
     double *UB;           // r x r (out, ld r)
     double *sig;          // r (out)
@@ -336,6 +347,15 @@ struct RRArgs {
     int32_t prec;
     DevState *ds;
 };
+// Columns of B per workgroup of the chunked Rayleigh-Ritz sums, and the
+// scratch they need (Gram partials, then the sigma partials).
+constexpr int RR_CHUNK = 64;
+inline size_t rr_part_doubles(int64_t n, int32_t r)
+{
+    return (size_t)((n + RR_CHUNK - 1) / RR_CHUNK) * (size_t)r * (size_t)r;
+}
+// G_B = B B^T (chunked partials, summed in chunk order), its
+// eigen-decomposition, then Sigma_B(i) = |B^T U_B(:, i)| (chunked, in order).
 hipError_t launch_rr_small(const RRArgs &a, hipStream_t st);
 hipError_t launch_rr_v(const double *B, int64_t n, int32_t r, int32_t k, const double *UB, const double *sig,
                        int32_t prec, void *V, hipStream_t st);

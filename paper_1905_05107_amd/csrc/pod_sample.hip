@@ -307,8 +307,9 @@ __device__ __forceinline__ void draw_cols_body(const DrawArgs &a)
     __syncthreads();
     // does S keep a drawable column for the next iteration?
     int left = 0;
+    const uint64_t *wl = a.wq_left ? a.wq_left : a.wq;
     for (int64_t j = j0; j < j1; ++j)
-        if (a.inS[j] && (a.unf || a.wq[j] != 0)) left = 1;
+        if (a.inS[j] && (a.unf || wl[j] != 0)) left = 1;
     left = __syncthreads_or(left);
     if (t == 0) {
         ds->s_empty = !left;
@@ -398,6 +399,37 @@ hipError_t launch_batch_done(DevState *const *dss, const int32_t *max_iter, cons
                              int32_t *ndone, hipStream_t st)
 {
     hipLaunchKernelGGL(k_batch_done, dim3(1), dim3(256), 0, st, dss, max_iter, sin_tol, count, ndone);
+    return hipGetLastError();
+}
+
+// ORT weights (see launch_ort_resid), one thread per column.
+__global__ __launch_bounds__(256) void k_ort_resid(const double *__restrict__ nu, const double *__restrict__ B,
+                                                   int32_t r, int64_t n, const uint8_t *__restrict__ inS,
+                                                   double floor_rel, const DevState *ds, double *__restrict__ rho)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n || merge_halted(ds)) return;
+    if (ds->it == 0) {
+        rho[j] = nu[j];
+        return;
+    }
+    double v = 0.0;
+    if (inS[j]) {
+        const int rs = ds->rs;
+        double s = 0.0;
+        for (int i = 0; i < rs; ++i) s = fma(B[i + j * r], B[i + j * r], s);
+        const double res = nu[j] - s;
+        v = (res > floor_rel * nu[j]) ? res : 0.0;
+    }
+    rho[j] = v;
+}
+
+hipError_t launch_ort_resid(const double *nu, const double *B, int32_t r, int64_t n, const uint8_t *inS,
+                            double floor_rel, const DevState *ds, double *rho, hipStream_t st)
+{
+    ProfScope ps(POD_K_DRAW, st);
+    hipLaunchKernelGGL(k_ort_resid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nu, B, r, n, inS, floor_rel,
+                       ds, rho);
     return hipGetLastError();
 }
 

@@ -901,11 +901,75 @@ hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// Rayleigh-Ritz of the final step: G_B = B B^T (r x r) with B = U^T A, its
-// eigen-decomposition by one-sided Jacobi on the columns of G_B
-// (G_B = U_B Lambda U_B^T, so the rotated columns converge to U_B Lambda),
-// Sigma_B = sqrt(Lambda); U_B(:, 0:k) is written in the compute type.
+// Rayleigh-Ritz of the final step on B = U^T A (r x n, ld r):
+//   k_rr_gram: G_B = B B^T over chunks of RR_CHUNK columns (one workgroup
+//     each, the chunk staged in LDS), partials part[chunk] (upper triangle);
+//   k_rr_small: the partials summed in chunk order, eigen-decomposition
+//     G_B = U_B Lambda U_B^T (tridiagonalisation, bisection, inverse
+//     iteration), U_B(:, 0:kv) (kv = k + 1 when r > k: sigma_{k+1} for the
+//     quality measure) and U_B(:, 0:k) in the compute type;
+//   k_rr_sig: per chunk and pair index i, sum over its columns c of
+//     (B^T U_B)(c, i)^2; k_rr_sig_sum adds the chunks in order:
+//     Sigma_B(i) = |B^T U_B(:, i)|, accurate to about r u sigma_1, where
+//     sqrt(lambda_i) would lose r u sigma_1^2 / sigma_i.
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rr_gram(const double *__restrict__ B, int64_t n, int32_t r,
+                                                 double *__restrict__ part)
+{
+    extern __shared__ double bs[];   // RR_CHUNK x r (column c at bs + c r)
+    const int64_t c0 = (int64_t)blockIdx.x * RR_CHUNK;
+    const int nc = (n - c0 < RR_CHUNK) ? (int)(n - c0) : RR_CHUNK;
+    for (int idx = threadIdx.x; idx < nc * r; idx += 256) bs[idx] = B[c0 * r + idx];
+    __syncthreads();
+    double *pb = part + (int64_t)blockIdx.x * r * r;
+    for (int idx = threadIdx.x; idx < r * r; idx += 256) {
+        const int i = idx % r, j = idx / r;
+        if (i > j) continue;
+        double s = 0.0;
+        for (int c = 0; c < nc; ++c) s = fma(bs[i + c * r], bs[j + c * r], s);
+        pb[idx] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rr_sig(const double *__restrict__ B, int64_t n, int32_t r, int32_t kv,
+                                                const double *__restrict__ UB, double *__restrict__ part)
+{
+    extern __shared__ double bs[];   // RR_CHUNK x r, then RR_CHUNK x 64 squares
+    double *sq = bs + RR_CHUNK * r;
+    const int64_t c0 = (int64_t)blockIdx.x * RR_CHUNK;
+    const int nc = (n - c0 < RR_CHUNK) ? (int)(n - c0) : RR_CHUNK;
+    for (int idx = threadIdx.x; idx < nc * r; idx += 256) bs[idx] = B[c0 * r + idx];
+    __syncthreads();
+    double *pb = part + (int64_t)blockIdx.x * kv;
+    for (int i0 = 0; i0 < kv; i0 += 64) {
+        // thread (c, l): t = (B^T U_B)(c0 + c, i0 + l)
+        for (int idx = threadIdx.x; idx < RR_CHUNK * 64; idx += 256) {
+            const int c = idx / 64, l = idx % 64, i = i0 + l;
+            double t = 0.0;
+            if (c < nc && i < kv)
+                for (int j = 0; j < r; ++j) t = fma(bs[j + c * r], UB[j + (int64_t)i * r], t);
+            sq[idx] = t * t;
+        }
+        __syncthreads();
+        if (threadIdx.x < 64 && i0 + threadIdx.x < kv) {
+            double v = 0.0;
+            for (int c = 0; c < nc; ++c) v += sq[c * 64 + threadIdx.x];
+            pb[i0 + threadIdx.x] = v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rr_sig_sum(const double *__restrict__ part, int32_t nch, int32_t kv,
+                                                    double *__restrict__ sig)
+{
+    for (int i = threadIdx.x; i < kv; i += 256) {
+        double v = 0.0;
+        for (int b = 0; b < nch; ++b) v += part[(int64_t)b * kv + i];
+        sig[i] = sqrt(v);
+    }
+}
+
 template <bool BIG>
 __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
 {
@@ -915,53 +979,27 @@ __global__ __launch_bounds__(512) void k_rr_small(RRArgs a)
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
     const int r = a.r, k = a.k;
     double *S = BIG ? a.ws : lds; // G_B -> reflectors
-    double *Y = S + r * r;        // eigenvectors (r x k)
+    double *Y = S + r * r;        // eigenvectors (r x kv)
     double *lu = BIG ? lds : Y + r * r;  // eig_lu_doubles(r)
-    // G_B entries, one wave per entry group, lanes along n
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int e = wv; e < r * r; e += NT / 64) {
-        const int i = e % r, j = e / r;
+    // G_B: the chunk partials summed in chunk order (upper triangle, mirrored)
+    const int nch = (int)((a.n + RR_CHUNK - 1) / RR_CHUNK);
+    for (int idx = threadIdx.x; idx < r * r; idx += NT) {
+        const int i = idx % r, j = idx / r;
         if (i > j) continue;
         double s = 0.0;
-        for (int64_t c = lane; c < a.n; c += 64) s += a.B[i + c * r] * a.B[j + c * r];
-        s = wave_sum(s);
-        if (lane == 0) {
-            S[i + j * r] = s;
-            S[j + i * r] = s;
-        }
+        for (int b = 0; b < nch; ++b) s += a.part[(int64_t)b * r * r + idx];
+        S[i + j * r] = s;
+        S[j + i * r] = s;
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < r * r; idx += NT) a.GB[idx] = S[idx];
     tridiag(S, r, sd, se, stau, spv, ssc);
-    // one value more than the k pairs when r > k: sigma_{k+1} of the quality measure
     const int kv = (k < r) ? k + 1 : k;
     bisect_top(sd, se, r, kv, sev, se2, ssc);
     tri_invit(sd, se, r, sev, kv, Y, lu, scl);
     tridiag_backtransform(S, stau, r, Y, kv, sdots);
-    for (int idx = threadIdx.x; idx < r * k; idx += NT) a.UB[idx] = Y[idx];
+    for (int idx = threadIdx.x; idx < r * kv; idx += NT) a.UB[idx] = Y[idx];
     for (int idx = threadIdx.x; idx < r * k; idx += NT) store_c(a.Zc, a.prec, idx, Y[idx]);
-    // Sigma_B(i) = |B^T U_B(:, i)| (accurate to about r u sigma_1, where
-    // sqrt(lambda_i) of B B^T loses r u sigma_1^2 / sigma_i): lane i of every
-    // wave sums its columns of B in order, the waves' sums are added in order
-    __shared__ double spart[NT / 64][64];
-    for (int i0 = 0; i0 < kv; i0 += 64) {
-        const int i = i0 + lane;
-        double acc = 0.0;
-        if (i < kv)
-            for (int64_t c = wv; c < a.n; c += NT / 64) {
-                double t = 0.0;
-                for (int j = 0; j < r; ++j) t = fma(a.B[j + c * r], Y[j + i * r], t);
-                acc = fma(t, t, acc);
-            }
-        spart[wv][lane] = acc;
-        __syncthreads();
-        if (wv == 0 && i < kv) {
-            double v = 0.0;
-            for (int q = 0; q < NT / 64; ++q) v += spart[q][lane];
-            a.sig[i] = sqrt(v);
-        }
-        __syncthreads();
-    }
 }
 
 hipError_t launch_rr_small(const RRArgs &a, hipStream_t st)
@@ -975,11 +1013,29 @@ hipError_t launch_rr_small(const RRArgs &a, hipStream_t st)
         if (e != hipSuccess) return e;
         attr[big] = true;
     }
+    static bool attr_chunk = false;
+    if (!attr_chunk) {
+        // chunk staging beyond the default 64 KiB of dynamic LDS (r up to 160)
+        hipError_t e = hipFuncSetAttribute((const void *)k_rr_gram, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           RR_CHUNK * 160 * (int)sizeof(double));
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_rr_sig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    RR_CHUNK * (160 + 64) * (int)sizeof(double));
+        if (e != hipSuccess) return e;
+        attr_chunk = true;
+    }
     ProfScope ps(POD_K_RR, st);
+    const unsigned nch = (unsigned)((a.n + RR_CHUNK - 1) / RR_CHUNK);
+    hipLaunchKernelGGL(k_rr_gram, dim3(nch), dim3(256), (size_t)RR_CHUNK * a.r * sizeof(double), st, a.B, a.n, a.r,
+                       a.part);
     if (big)
         hipLaunchKernelGGL(k_rr_small<true>, dim3(1), dim3(NT), lds, st, a);
     else
         hipLaunchKernelGGL(k_rr_small<false>, dim3(1), dim3(NT), lds, st, a);
+    const int kv = (a.k < a.r) ? a.k + 1 : a.k;
+    hipLaunchKernelGGL(k_rr_sig, dim3(nch), dim3(256), (size_t)RR_CHUNK * (a.r + 64) * sizeof(double), st, a.B, a.n,
+                       a.r, kv, a.UB, a.part);
+    hipLaunchKernelGGL(k_rr_sig_sum, dim3(1), dim3(256), 0, st, a.part, (int32_t)nch, kv, a.sig);
     return hipGetLastError();
 }
 
