@@ -392,6 +392,30 @@ pod_status pod_center_rows(void *A_dev, int32_t a_dtype, int64_t m, int64_t n, i
  * threads) race. */
 pod_status pod_center_rows_noalloc(void *A_dev, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, void *stream);
 
+/* One-shot sampled SVDs of Appendix A, the methods the iteration builds on
+ * (device, stream-ordered on `stream`, syncs):
+ *   Alg. 4 (LTSVD, prm->w = 0): c draws over the columns of A with the norm
+ *   probabilities of Eq. (LTSVD_prob) (Philox key (seed, 0), counter
+ *   (0, d/4, block, 0): the first draw of pod_sample), folded into the g
+ *   distinct columns, each scaled by sqrt(t_j / (c p_j)) (t_j draws, p_j its
+ *   probability): C (m x g); V Sigma^2 V^T = eig(C^T C);
+ *   l = min(k, #{lambda_i > g u lambda_1}); u_i = C v_i / sigma_i.
+ *   Alg. 5 (CTSVD, prm->w > 0): as Alg. 4 for C, then w draws over the rows
+ *   with q_i = |c^i|^2 / |C|_F^2 (Eq. CTSVD_prob_col; key (seed, 1)), folded
+ *   into the h distinct rows, each scaled by sqrt(t_i / (w q_i)): W (h x g);
+ *   V Sigma^2 V^T = eig(W^T W); gamma = eps / (100 k);
+ *   l = min(k, max{r : sigma_r^2 >= gamma |W|_F^2}); u_i = C v_i / sigma_i
+ *   (not orthonormal in general).
+ * prm as for pod_init (m, n, lda, a_dtype, precision, k, c, w, seed, block,
+ * center_rows; the merge width k + min(c, n) must be <= 160).  U_out (device,
+ * m x k column-major, FP64 for POD_F64 else FP32; columns past l are zero,
+ * each u_i signed as in pod_project), sigma_out (device, k FP64, zero past l),
+ * *l_out (host, nullable).  POD_EXHAUSTED when no column (or, for Alg. 5, no
+ * row) has a non-zero weight; POD_EINVAL for bad parameters or eps <= 0 with
+ * w > 0. */
+pod_status pod_oneshot(const pod_params *prm, const void *A_dev, double eps, void *U_out, double *sigma_out,
+                       int32_t *l_out, void *stream);
+
 /* Sample sizes of Eqs. (c_LTSVD) and (c_w_CTSVD), rounded up:
  * kind 0: c = 4k (1 + sqrt(8 ln(1/delta)))^2 / eps^2;
  * kind 1: c = w = k^2 (1 + sqrt(ln(2/delta)))^2 / eps^4.

@@ -32,7 +32,8 @@ EXPORTS = ["pod_init", "pod_sample", "pod_merge", "pod_converged", "pod_project"
            "pod_inc_add_host_blocks", "pod_inc_result", "pod_inc_get_info", "pod_inc_destroy", "pod_batch_init",
            "pod_batch_autotune", "pod_batch_run", "pod_batch_project", "pod_batch_get_info", "pod_batch_destroy",
            "pod_enable_adjoint", "pod_backward", "pod_loss_grad", "pod_batch_enable_adjoint", "pod_batch_loss_grad", "pod_batch_loss_grad_all",
-           "pod_run", "pod_set_indices", "pod_center_rows", "pod_center_rows_noalloc"]
+           "pod_run", "pod_set_indices", "pod_center_rows", "pod_center_rows_noalloc",
+           "pod_oneshot"]
 
 
 class PodError(RuntimeError):
@@ -95,6 +96,7 @@ def lib():
             "pod_get_col_sqnorms": (i32, [vp, vp]),
             "pod_col_sqnorms": (i32, [vp, i32, i64, i64, i64, vp, vp]),
             "pod_center_rows": (i32, [vp, i32, i64, i64, i64, vp]),
+            "pod_oneshot": (i32, [P(pod_params), vp, d, vp, vp, P(i32), vp]),
             "pod_center_rows_noalloc": (i32, [vp, i32, i64, i64, i64, vp]),
             "pod_sample_size": (i64, [i32, i32, d, d]),
             "pod_destroy": (None, [vp]),
@@ -677,6 +679,22 @@ def profile_read():
     n, ms = ctypes.c_int64(), ctypes.c_double()
     _check(lib().pod_profile_read(ctypes.byref(n), ctypes.byref(ms)), "pod_profile_read")
     return n.value, ms.value
+
+
+def oneshot(A, k: int, c: int, w: int = 0, eps: float = 0.6, seed: int = 0, precision: int = POD_F64,
+            block: int = 0, center_rows: bool = False, stream=None):
+    """One-shot sampled SVD of Appendix A on the device matrix A: Alg. 4
+    (LTSVD) for w = 0, Alg. 5 (CTSVD) for w > 0.  Returns (U (m x k), sigma (k),
+    l): the first l columns and values are the method's output, the rest zero."""
+    import torch
+    p, ptr = _params(A, k, c, w=w, precision=precision, seed=seed, block=block, center_rows=center_rows)
+    dt = torch.float64 if precision == POD_F64 else torch.float32
+    Ut = torch.empty((k, p.m), dtype=dt, device=A.device)
+    sig = torch.empty(k, dtype=torch.float64, device=A.device)
+    l = ctypes.c_int32()
+    _check(lib().pod_oneshot(ctypes.byref(p), ctypes.c_void_p(ptr), float(eps), ctypes.c_void_p(Ut.data_ptr()),
+                             ctypes.c_void_p(sig.data_ptr()), ctypes.byref(l), _stream_handle(stream)), "pod_oneshot")
+    return Ut.T, sig, l.value
 
 
 def center_rows(A, stream=None):

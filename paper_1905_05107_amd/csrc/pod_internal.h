@@ -136,7 +136,7 @@ hipError_t launch_batch_done(DevState *const *dss, const int32_t *max_iter, cons
 // ascending column order, FP64 fma chain), g read from the device state.
 hipError_t launch_row_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t lda, const int32_t *cols,
                               const void *U0, const void *U1, int32_t u_prec, int32_t k_ls, const DevState *ds,
-                              double *rho, hipStream_t st);
+                              double *rho, hipStream_t st, const double *cscale = nullptr);
 struct RowDrawArgs {
     const uint64_t *wr;    // row weights (m)
     int64_t m;
@@ -268,6 +268,13 @@ struct BlockEigArgs {
     double *Vt;            // out, g x ru (ld pmax)
     double *ws;            // matrices of the kernel when pmax > 64 (2 pmax^2)
     DevState *ds;
+    // one-shot sampled SVDs (Appendix A): column scales of the block (nullable),
+    // the kept eigenvalues (nullable), and the rule for ru: 0 the rank rule
+    // above, 1 ru = min(r_lim, max{r : lambda_r >= gamma trace(G_B)})
+    const double *cscale = nullptr;
+    double *evals = nullptr;
+    int32_t crit = 0;
+    double gamma = 0.0;
 };
 hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st);
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st);

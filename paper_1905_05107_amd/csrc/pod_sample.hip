@@ -453,7 +453,7 @@ template <typename T, typename TU>
 __global__ __launch_bounds__(256) void k_row_sqnorms(const T *__restrict__ A, int64_t m, int64_t lda,
                                                      const int32_t *__restrict__ cols, const TU *__restrict__ U0,
                                                      const TU *__restrict__ U1, int32_t k_ls, const DevState *ds,
-                                                     double *__restrict__ rho)
+                                                     double *__restrict__ rho, const double *__restrict__ cscale)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= m || merge_halted(ds)) return;
@@ -468,7 +468,8 @@ __global__ __launch_bounds__(256) void k_row_sqnorms(const T *__restrict__ A, in
     } else {
         const int g = ds->g;
         for (int l = 0; l < g; ++l) {
-            const double x = (double)A[(int64_t)cols[l] * lda + i];
+            double x = (double)A[(int64_t)cols[l] * lda + i];
+            if (cscale) x *= cscale[l];   // rows of the scaled sample C (one-shot CTSVD)
             acc = fma(x, x, acc);
         }
     }
@@ -477,19 +478,19 @@ __global__ __launch_bounds__(256) void k_row_sqnorms(const T *__restrict__ A, in
 
 hipError_t launch_row_sqnorms(const void *A, int32_t a_dtype, int64_t m, int64_t lda, const int32_t *cols,
                               const void *U0, const void *U1, int32_t u_prec, int32_t k_ls, const DevState *ds,
-                              double *rho, hipStream_t st)
+                              double *rho, hipStream_t st, const double *cscale)
 {
     ProfScope ps(POD_K_DRAW, st);
     const unsigned nb = (unsigned)((m + 255) / 256);
     if (a_dtype == POD_F64)
         hipLaunchKernelGGL((k_row_sqnorms<double, double>), dim3(nb), dim3(256), 0, st, (const double *)A, m, lda,
-                           cols, (const double *)U0, (const double *)U1, k_ls, ds, rho);
+                           cols, (const double *)U0, (const double *)U1, k_ls, ds, rho, cscale);
     else if (u_prec == POD_F64)
         hipLaunchKernelGGL((k_row_sqnorms<float, double>), dim3(nb), dim3(256), 0, st, (const float *)A, m, lda,
-                           cols, (const double *)U0, (const double *)U1, k_ls, ds, rho);
+                           cols, (const double *)U0, (const double *)U1, k_ls, ds, rho, cscale);
     else
         hipLaunchKernelGGL((k_row_sqnorms<float, float>), dim3(nb), dim3(256), 0, st, (const float *)A, m, lda,
-                           cols, (const float *)U0, (const float *)U1, k_ls, ds, rho);
+                           cols, (const float *)U0, (const float *)U1, k_ls, ds, rho, cscale);
     return hipGetLastError();
 }
 

@@ -1205,6 +1205,10 @@ __global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
                     di = (double)reinterpret_cast<const float *>(a.A)[ci * a.lda + row];
                     dj = (double)reinterpret_cast<const float *>(a.A)[cj * a.lda + row];
                 }
+                if (a.cscale) {
+                    di *= a.cscale[i];
+                    dj *= a.cscale[j];
+                }
                 s += (sc * di) * (sc * dj);
             }
             S[i + j * g] = s;
@@ -1213,15 +1217,26 @@ __global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
     } else {
         for (int idx = threadIdx.x; idx < g * g; idx += NT) {
             const int i = idx % g, j = idx / g;
-            S[idx] = a.G[(rs + i) + (rs + j) * pm];
+            double v = a.G[(rs + i) + (rs + j) * pm];
+            if (a.cscale) v = (a.cscale[i] * v) * a.cscale[j];
+            S[idx] = v;
         }
     }
+    __syncthreads();
+    // trace of G_B (= |W|_F^2 of the one-shot CTSVD rule), in index order
+    if (threadIdx.x == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < g; ++i) tr += S[i + i * g];
+        ssc[7] = tr;
+    }
+    __syncthreads();
+    const double trace = ssc[7];
     __syncthreads();
     tridiag(S, g, sd, se, stau, spv, ssc);
     int nv = (a.r_lim < g) ? a.r_lim : g;
     if (nv > h) nv = h;
     bisect_top(sd, se, g, nv, sev, se2, ssc);
-    const double thr = (double)g * 1.1102230246251565e-16 * fmax(sev[0], 0.0);
+    const double thr = (a.crit == 1) ? a.gamma * trace : (double)g * 1.1102230246251565e-16 * fmax(sev[0], 0.0);
     const int nz = count_above(sd, se2, g, thr, ssc[2], scl);
     const int ru = (sev[0] > 0.0) ? ((nv < nz) ? nv : nz) : 0;
     tri_invit(sd, se, g, sev, ru, Y, lu, scl);
@@ -1230,6 +1245,8 @@ __global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
         const int i = idx % g, j = idx / g;
         a.Vt[i + j * pm] = Y[i + j * g];
     }
+    if (a.evals)
+        for (int i = threadIdx.x; i < ru; i += NT) a.evals[i] = sev[i];
     if (threadIdx.x == 0) {
         ds->ru = ru;
         ds->p = rs + ru;
