@@ -59,6 +59,10 @@ def parse():
                          "k=20, c=40; c5: 64-matrix batch, forward + gradient; c4: Alg. 3 over pinned host "
                          "blocks of 2M x 512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paths", default="f64,bf16,f32",
+                    help="precision paths run (f64 first; the reduced ones are compared against it)")
+    ap.add_argument("--no-class-breakdown", action="store_true",
+                    help="skip the per-class HIP-event pre-pass (for profiler runs)")
     ap.add_argument("--cpu-rows", type=int, default=50_000, help="rows of the oracle's larger row subsample")
     ap.add_argument("--cpu-merges", type=int, default=6, help="oracle merges timed per row subsample")
     ap.add_argument("--c5-count", type=int, default=64)
@@ -312,8 +316,8 @@ def run_single(args):
     # per-class pre-pass of the FP64 path picks its dominant m-pass class
     U64, s64, inf64 = step("f64")
     iters64 = inf64.iter
-    cls64 = classes("f64", iters64)
-    dominant = max(MPASS, key=lambda q: cls64[q]["ms_per_step"])
+    cls64 = None if args.no_class_breakdown else classes("f64", iters64)
+    dominant = "tall" if cls64 is None else max(MPASS, key=lambda q: cls64[q]["ms_per_step"])
 
     # timed region: the plain FP64 path, its dominant class timed live
     sec64, (U64, s64, inf64), (dl, dms) = timed("f64", args.steps, dominant)
@@ -328,7 +332,7 @@ def run_single(args):
     paths = {"f64": {"ms": round(sec64 * 1e3, 3), "merges": inf64.iter,
                      "stopped_by": pod.STOP_NAMES.get(inf64.stop_reason, "unknown")}}
     mixed_classes = None
-    for path in ("bf16", "f32"):
+    for path in [q for q in ("bf16", "f32") if q in args.paths.split(",")]:
         sec, (U, s, inf), _ = timed(path, args.other_steps)
         rel, ang = compare_modes(U, s, U64, s64)
         ok = ang <= ANGLE_TOL
@@ -337,7 +341,7 @@ def run_single(args):
                        "sigma_rel_vs_f64": rel, "angle_vs_f64": ang,
                        "speedup_vs_f64": round(sec64 / sec, 3) if ok else None,
                        "speedup_note": None if ok else f"largest angle {ang:.2e} > {ANGLE_TOL:g}: unmeasured"}
-        if path == "bf16":
+        if path == "bf16" and not args.no_class_breakdown:
             mixed_classes = classes("bf16", inf.iter)
 
     out = {
@@ -360,8 +364,9 @@ def run_single(args):
         "paths": paths,
         "kernel_rooflines_f64": cls64,
         "kernel_rooflines_bf16": mixed_classes,
-        "small_stage_us_per_launch": {q: {"f64": cls64[q]["avg_launch_us"],
-                                          "bf16": mixed_classes[q]["avg_launch_us"]} for q in SMALL},
+        "small_stage_us_per_launch": ({q: {"f64": cls64[q]["avg_launch_us"],
+                                           "bf16": mixed_classes[q]["avg_launch_us"] if mixed_classes else None}
+                                       for q in SMALL} if cls64 else None),
         "adjoint_included": False,
         "adjoint_note": ("the reverse pass covers merge widths up to 64; this workload merges "
                          f"{p} columns. The batched workload (--workload c5) times forward plus gradient"),

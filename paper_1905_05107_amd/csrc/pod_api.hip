@@ -370,7 +370,7 @@ pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
         ALLOC(ctx->rho_ort, double, n);
         ALLOC(ctx->wort, uint64_t, n);
     }
-    if (pmax > 64) ALLOC(ctx->ws, double, (size_t)3 * pmax * pmax + pmax + BIG_INVIT_DOUBLES);
+    if (pmax > 64) ALLOC(ctx->ws, double, big_dinv_offset(pmax) + BIG_DINV_DOUBLES);
     if (p.w > 0) {
         ALLOC(ctx->rho, double, m);
         ALLOC(ctx->wr, uint64_t, m);

@@ -24,37 +24,89 @@ constexpr int BIG_NR = 20;   // rows per wave: row a = w + 8 k, k < BIG_NR (n <=
 constexpr int BIG_NS = 3;    // column slots per lane: column l + 64 s
 
 // ---------------------------------------------------------------------------
-// C = A B for n x n operands (n <= 160) on v_mfma_f64_16x16x4: the 16 x 16
-// output tiles are dealt to the 8 waves, operands read through accessors
-// (zero outside n x n), the k range of tile (I, J) set by krange(I, J, k0, k1)
+// One 16 x 16 tile (ti, tj) of C = A B on v_mfma_f64_16x16x4 by one wave,
+// summing k over [k0, k1) (multiples of 16), operands read through accessors
+// fa(i, k), fb(k, j) that return zero outside the matrices; the operands of
+// step k + 16 are loaded before the products of step k.  The result goes to
+// fc(i, j, v) for the tile's 256 entries.
+// ---------------------------------------------------------------------------
+template <typename FA, typename FB, typename FC>
+__device__ __forceinline__ void mm_tile(int ti, int tj, int k0, int k1, FA fa, FB fb, FC fc)
+{
+    const int l = rl_lane();
+    const int li = l & 15, lk = l >> 4;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    double av[4], bv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        av[s] = fa(ti * 16 + li, k0 + 4 * s + lk);
+        bv[s] = fb(k0 + 4 * s + lk, tj * 16 + li);
+    }
+    for (int k = k0; k < k1; k += 16) {
+        double an[4], bn[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kk = k + 16 + 4 * s + lk;
+            an[s] = (k + 16 < k1) ? fa(ti * 16 + li, kk) : 0.0;
+            bn[s] = (k + 16 < k1) ? fb(kk, tj * 16 + li) : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = mfma16x16x4(av[s], bv[s], acc);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            av[s] = an[s];
+            bv[s] = bn[s];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fc(ti * 16 + acc_row<double>(l, v), tj * 16 + li, acc[v]);
+}
+
+// The same with every operand of the tile loaded before the first product
+// (k1 - k0 <= 16 KS): one round trip to memory per tile, for the kernels whose
+// operands come from other workgroups' writes (L2 misses).
+template <int KS, typename FA, typename FB, typename FC>
+__device__ __forceinline__ void mm_tile_all(int ti, int tj, int k0, int k1, FA fa, FB fb, FC fc)
+{
+    const int l = rl_lane();
+    const int li = l & 15, lk = l >> 4;
+    double av[KS][4], bv[KS][4];
+#pragma unroll
+    for (int q = 0; q < KS; ++q)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kk = k0 + 16 * q + 4 * s + lk;
+            const bool in = k0 + 16 * q < k1;
+            av[q][s] = in ? fa(ti * 16 + li, kk) : 0.0;
+            bv[q][s] = in ? fb(kk, tj * 16 + li) : 0.0;
+        }
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < KS; ++q)
+        if (k0 + 16 * q < k1)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = mfma16x16x4(av[q][s], bv[q][s], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fc(ti * 16 + acc_row<double>(l, v), tj * 16 + li, acc[v]);
+}
+
+// ---------------------------------------------------------------------------
+// C = A B for n x n operands (n <= 160): the 16 x 16 output tiles of mm_tile
+// dealt to the 8 waves, the k range of tile (I, J) set by krange(I, J, k0, k1)
 // to [k0, k1) (multiples of 16; default [0, 16 ceil(n / 16))) for triangular
 // factors.  `upper`: only tiles I <= J.  No barrier; the caller synchronises.
 // ---------------------------------------------------------------------------
 template <typename FA, typename FB, typename FC, typename FK>
 __device__ __forceinline__ void big_mm(int n, bool upper, FA fa, FB fb, FC fc, FK krange)
 {
-    const int w = rl_wave(), l = rl_lane();
-    const int li = l & 15, lk = l >> 4;
+    const int w = rl_wave();
     const int nt = (n + 15) >> 4;
     for (int tile = w; tile < nt * nt; tile += 8) {
         const int ti = tile / nt, tj = tile % nt;
         if (upper && ti > tj) continue;
         int k0 = 0, k1 = 16 * nt;
         krange(ti, tj, k0, k1);
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int k = k0; k < k1; k += 16) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int kk = k + 4 * s + lk;
-                av[s] = fa(ti * 16 + li, kk);
-                bv[s] = fb(kk, tj * 16 + li);
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s) acc = mfma16x16x4(av[s], bv[s], acc);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) fc(ti * 16 + acc_row<double>(l, v), tj * 16 + li, acc[v]);
+        mm_tile(ti, tj, k0, k1, fa, fb, fc);
     }
 }
 
@@ -212,11 +264,24 @@ __device__ __forceinline__ void big_backtransform(const double *A, const double 
     const int g = threadIdx.x & 7;
     const int nref = n - 2;                       // reflectors j = 0 .. n-3, applied from the last
     const int nblk = (nref + BT_NB - 1) / BT_NB;
-    auto stage = [&](int q, int buf) {
-        for (int idx = threadIdx.x; idx < BT_NB * BIG_NS * 64; idx += EIG_NT) {
+    // a block of reflectors is loaded into registers while the previous one
+    // is applied, and written to LDS after it
+    constexpr int PER = (BT_NB * BIG_NS * 64 + EIG_NT - 1) / EIG_NT;
+    double pre[PER];
+    auto fetch = [&](int q) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = threadIdx.x + u * EIG_NT;
             const int i = idx / (BIG_NS * 64), row = idx % (BIG_NS * 64);
             const int j = n - 3 - (BT_NB * q + i);
-            Vb[buf][i][row] = (j >= 0 && row > j && row < n) ? A[row + (size_t)j * n] : 0.0;
+            pre[u] = (idx < BT_NB * BIG_NS * 64 && j >= 0 && row > j && row < n) ? A[row + (size_t)j * n] : 0.0;
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = threadIdx.x + u * EIG_NT;
+            if (idx < BT_NB * BIG_NS * 64) Vb[buf][idx / (BIG_NS * 64)][idx % (BIG_NS * 64)] = pre[u];
         }
     };
     for (int cb = 0; cb < nv; cb += EIG_NT / 8) {
@@ -225,10 +290,11 @@ __device__ __forceinline__ void big_backtransform(const double *A, const double 
         double y[BIG_NR];
 #pragma unroll
         for (int t = 0; t < BIG_NR; ++t) y[t] = (act && g + 8 * t < n) ? Y[g + 8 * t + (size_t)c * n] : 0.0;
-        stage(0, 0);
+        fetch(0);
+        put(0);
         __syncthreads();
         for (int q = 0; q < nblk; ++q) {
-            if (q + 1 < nblk) stage(q + 1, (q + 1) & 1);
+            if (q + 1 < nblk) fetch(q + 1);
             const double(*V)[BIG_NS * 64] = Vb[q & 1];
 #pragma unroll
             for (int i = 0; i < BT_NB; ++i) {
@@ -245,6 +311,7 @@ __device__ __forceinline__ void big_backtransform(const double *A, const double 
 #pragma unroll
                 for (int t = 0; t < BIG_NR; ++t) y[t] = fma(-s, V[i][g + 8 * t], y[t]);
             }
+            if (q + 1 < nblk) put((q + 1) & 1);
             __syncthreads();
         }
 #pragma unroll
@@ -263,19 +330,21 @@ namespace pod {
 __device__ __forceinline__ int big_chol_row(int w, int k) { return 32 * (k >> 2) + 4 * w + (k & 3); }
 
 // ---------------------------------------------------------------------------
-// In-place Cholesky S = R^T R of the symmetric n x n matrix S (64 < n <= 160;
-// column-major, ld n, device memory; the upper triangle is read), the
-// contract of chol_upper: on success the upper triangle holds R and the
-// strict lower triangle is zero; returns nonzero, uniformly, when a pivot is
-// not above thr.  Outer-product Cholesky (Golub & Van Loan Alg. 4.2.2) with
-// the matrix in registers (lane l columns l + 64 s), rows in blocks of four
-// held by one wave: the owner scales row j by 1/sqrt(pivot) and subtracts
-// R(j, a) times it from the block's later rows a, then publishes the block;
-// after one barrier every wave subtracts the block's rows from its rows
-// below it.  The published blocks alternate between two LDS buffers, so one
-// barrier per block suffices.
+// Cholesky S = R^T R of the symmetric n x n matrix S (64 < n <= 160), read
+// through load(i, j) for i <= j (the upper triangle; each entry is read once,
+// all of a thread's loads in flight together) and written through
+// store(a, c, v) for every c >= a (v = R(a, c)).  Returns, uniformly, bit 1
+// when a pivot is not above thr and bit 2 when an entry of S is not finite.
+// Outer-product Cholesky (Golub & Van Loan Alg. 4.2.2) with the matrix in
+// registers (lane l columns l + 64 s), rows in blocks of four held by one
+// wave: the owner scales row j by 1/sqrt(pivot) and subtracts R(j, a) times
+// it from the block's later rows a, then publishes the block; after one
+// barrier every wave subtracts the block's rows from its rows below it.  The
+// published blocks alternate between two LDS buffers, so one barrier per
+// block suffices.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int big_chol(double *S, int n, double thr)
+template <typename FL, typename FS>
+__device__ __forceinline__ int big_chol(int n, double thr, FL load, FS store)
 {
     __shared__ double Rb[2][4][BIG_NS * 64];
     __shared__ int sfl[8];
@@ -287,10 +356,15 @@ __device__ __forceinline__ int big_chol(double *S, int n, double thr)
 #pragma unroll
         for (int s = 0; s < BIG_NS; ++s) {
             const int c = l + 64 * s;
-            r[k][s] = (a < n && c < n) ? S[(c < a ? c + (size_t)a * n : a + (size_t)c * n)] : 0.0;
+            r[k][s] = (a < n && c < n) ? (c < a ? load(c, a) : load(a, c)) : 0.0;
         }
     }
     int fail = 0;
+#pragma unroll
+    for (int k = 0; k < BIG_NR; ++k)
+#pragma unroll
+        for (int s = 0; s < BIG_NS; ++s)
+            if (!isfinite(r[k][s])) fail = 2;
 #pragma unroll
     for (int H = 0; H < BIG_NR / 4; ++H) {
         const int sj = H >> 1;   // column slot of the block's rows 32 H .. 32 H + 31
@@ -304,7 +378,7 @@ __device__ __forceinline__ int big_chol(double *S, int n, double thr)
                     const int j = j0 + t;
                     if (j < n) {
                         const double d = readlane_f64(r[4 * H + t][sj], j & 63);
-                        if (!(d > thr)) fail = 1;
+                        if (!(d > thr)) fail |= 1;
                         const double sc = rsqrt_nr(fmax(d, 1e-300));
 #pragma unroll
                         for (int s = 0; s < BIG_NS; ++s) {
@@ -354,13 +428,13 @@ __device__ __forceinline__ int big_chol(double *S, int n, double thr)
 #pragma unroll
             for (int s = 0; s < BIG_NS; ++s) {
                 const int c = l + 64 * s;
-                if (c < n) {
-                    S[a + (size_t)c * n] = (c >= a) ? r[k][s] : 0.0;
-                    if (c > a) S[c + (size_t)a * n] = 0.0;
-                }
+                if (c < n && c >= a) store(a, c, r[k][s]);
             }
         }
     }
+    // (a wave's flag bits: the pivot test is uniform in the owner wave, the
+    // finiteness test per lane)
+    fail = (__ballot((fail & 1) != 0) ? 1 : 0) | (__ballot((fail & 2) != 0) ? 2 : 0);
     if (l == 0) sfl[w] = fail;
     __syncthreads();
     int f = 0;
@@ -388,6 +462,7 @@ __device__ __forceinline__ void big_invit(const double *d, const double *e, int 
                                           double *Y, double *W, double *yl, int *scl)
 {
     constexpr int S = 64;
+    constexpr int FB = 6;                         // rows per block of the solves
     constexpr size_t A = (size_t)EIG_NMAX * S;   // one array of the scratch
     const int t = threadIdx.x;
     const double u = 1.1102230246251565e-16;
@@ -444,25 +519,79 @@ __device__ __forceinline__ void big_invit(const double *d, const double *e, int 
                 for (int i = 0; i < n; ++i)
                     y[i * S] = 1.0 + 0.5 * (double)(((i + 3 * mi) * 2654435761u) % 1009u) / 1009.0;
                 for (int itn = 0; itn < 2; ++itn) {
-                    // forward: the row operations, carrying the current row in a register
+                    // forward: the row operations, carrying the current row in a
+                    // register; the operands of the next FB rows are loaded before
+                    // the current FB rows are processed (they are rows those do not write)
                     double cur = y[0];
-#pragma unroll 8
-                    for (int i = 0; i + 1 < n; ++i) {
-                        const double nx = y[(i + 1) * S];
-                        const bool s = sw[i * S] != 0.0;
-                        const double top = s ? nx : cur, bot = s ? cur : nx;
-                        y[i * S] = top;
-                        cur = bot - ml[i * S] * top;
+                    double nxb[FB], swb[FB], mlb[FB];
+                    auto fwd_load = [&](int i0, double *nx_, double *sw_, double *ml_) {
+#pragma unroll
+                        for (int q = 0; q < FB; ++q) {
+                            const int i = i0 + q;
+                            const bool ok = i + 1 < n;
+                            nx_[q] = ok ? y[(i + 1) * S] : 0.0;
+                            sw_[q] = ok ? sw[i * S] : 0.0;
+                            ml_[q] = ok ? ml[i * S] : 0.0;
+                        }
+                    };
+                    fwd_load(0, nxb, swb, mlb);
+                    for (int i0 = 0; i0 + 1 < n; i0 += FB) {
+                        double nxn[FB], swn[FB], mln[FB];
+                        fwd_load(i0 + FB, nxn, swn, mln);
+#pragma unroll
+                        for (int q = 0; q < FB; ++q) {
+                            const int i = i0 + q;
+                            if (i + 1 < n) {
+                                const bool s = swb[q] != 0.0;
+                                const double top = s ? nxb[q] : cur, bot = s ? cur : nxb[q];
+                                y[i * S] = top;
+                                cur = bot - mlb[q] * top;
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < FB; ++q) {
+                            nxb[q] = nxn[q];
+                            swb[q] = swn[q];
+                            mlb[q] = mln[q];
+                        }
                     }
                     y[(n - 1) * S] = cur;
-                    // back substitution with U (3 diagonals), last two values in registers
+                    // back substitution with U (3 diagonals), last two values in
+                    // registers, the next FB rows' operands loaded ahead
                     double x1 = 0.0, x2 = 0.0;
-#pragma unroll 8
-                    for (int i = n - 1; i >= 0; --i) {
-                        const double sv = (y[i * S] - u2[i * S] * x1 - u3[i * S] * x2) * u1[i * S];
-                        y[i * S] = sv;
-                        x2 = x1;
-                        x1 = sv;
+                    double yb[FB], ab1[FB], ab2[FB], ab3[FB];
+                    auto back_load = [&](int i0, double *y_, double *a1, double *a2, double *a3) {
+#pragma unroll
+                        for (int q = 0; q < FB; ++q) {
+                            const int i = i0 - q;
+                            const bool ok = i >= 0;
+                            y_[q] = ok ? y[i * S] : 0.0;
+                            a1[q] = ok ? u1[i * S] : 0.0;
+                            a2[q] = ok ? u2[i * S] : 0.0;
+                            a3[q] = ok ? u3[i * S] : 0.0;
+                        }
+                    };
+                    back_load(n - 1, yb, ab1, ab2, ab3);
+                    for (int i0 = n - 1; i0 >= 0; i0 -= FB) {
+                        double yn[FB], an1[FB], an2[FB], an3[FB];
+                        back_load(i0 - FB, yn, an1, an2, an3);
+#pragma unroll
+                        for (int q = 0; q < FB; ++q) {
+                            const int i = i0 - q;
+                            if (i >= 0) {
+                                const double sv = (yb[q] - ab2[q] * x1 - ab3[q] * x2) * ab1[q];
+                                y[i * S] = sv;
+                                x2 = x1;
+                                x1 = sv;
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < FB; ++q) {
+                            yb[q] = yn[q];
+                            ab1[q] = an1[q];
+                            ab2[q] = an2[q];
+                            ab3[q] = an3[q];
+                        }
                     }
                     // re-orthogonalise inside the cluster, normalise
                     for (int pj = i0; pj < mi; ++pj) {
@@ -489,7 +618,14 @@ __device__ __forceinline__ void big_invit(const double *d, const double *e, int 
                     for (int i = 0; i < n; ++i) y[i * S] *= f;
                 }
                 double *yo = Y + (size_t)mi * n;
-                for (int i = 0; i < n; ++i) yo[i] = y[i * S];
+                for (int i0 = 0; i0 < n; i0 += FB) {
+                    double v[FB];
+#pragma unroll
+                    for (int q = 0; q < FB; ++q) v[q] = (i0 + q < n) ? y[(i0 + q) * S] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < FB; ++q)
+                        if (i0 + q < n) yo[i0 + q] = v[q];
+                }
             }
         }
         __syncthreads();
@@ -645,56 +781,135 @@ namespace pod {
 constexpr int BIG_PACKED = EIG_NMAX * (EIG_NMAX + 1) / 2;
 
 // ---------------------------------------------------------------------------
-// X = R^-1 for the upper-triangular n x n matrix R (n <= 160; column-major,
-// ld n, device memory; X must not alias R): the column-by-column back
-// substitution of trinv_cols (one group of 8 lanes per column of X, its
-// right-hand side in registers, no barrier between the steps) with R's upper
-// triangle first copied to LDS, packed by columns (column i at i (i + 1) / 2:
-// Rp, BIG_PACKED doubles), so that every step reads LDS instead of L2.
-// `tmp` (n doubles of LDS) holds the reciprocals of the diagonal.
+// X = R^-1 for the upper-triangular n x n matrix R (n <= 160): the
+// column-by-column back substitution of trinv_cols (one group of 8 lanes per
+// column of X, its right-hand side in registers, no barrier between the
+// steps) on R's upper triangle packed by columns in LDS (column i at
+// i (i + 1) / 2: Rp, BIG_PACKED doubles), so that every step reads LDS
+// instead of L2; `tmp` (n doubles of LDS) holds the reciprocals of the
+// diagonal.  big_trinv_solve hands X(i, j) to store(i, j, x) for every
+// i, j < n (zero below the diagonal); no barrier on entry, one on return.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void big_trinv(const double *R, int n, double *X, double *Rp, double *tmp)
+// Column j of X = R^-1 by the aligned group of 8 lanes that calls it (j < n):
+// the back substitution of trinv_cols with the right-hand side e_j in
+// registers (row 8 s + g in slot s of group lane g); X(i, j) goes to
+// store(i, j, x) for every i < n.
+template <typename FS>
+__device__ __forceinline__ void trinv_col8(const double *Rp, const double *tmp, int n, int j, FS store)
 {
-    for (int i = threadIdx.x; i < n; i += EIG_NT) tmp[i] = 1.0 / R[i + i * n];
-    for (int c = rl_wave(); c < n; c += 8)
-        for (int r = rl_lane(); r <= c; r += 64) Rp[c * (c + 1) / 2 + r] = R[r + (size_t)c * n];
-    __syncthreads();
     const int gl = threadIdx.x & 7;
-    for (int j = threadIdx.x >> 3; j < n; j += EIG_NT / 8) {
-        double b[BIG_NR];
+    double b[BIG_NR];
 #pragma unroll
-        for (int s = 0; s < BIG_NR; ++s) b[s] = (8 * s + gl == j) ? 1.0 : 0.0;
+    for (int s = 0; s < BIG_NR; ++s) b[s] = (8 * s + gl == j) ? 1.0 : 0.0;
 #pragma unroll
-        for (int s = BIG_NR - 1; s >= 0; --s) {
-            if (8 * s > j) continue;   // uniform in the group
-            double bs = b[s];
+    for (int s = BIG_NR - 1; s >= 0; --s) {
+        if (8 * s > j) continue;   // uniform in the group
+        double bs = b[s];
 #pragma unroll 1
-            for (int o = 7; o >= 0; --o) {
-                const int i = 8 * s + o;
-                if (i > j) continue;
-                double bi;
-                switch (o) {
-                case 0: bi = bcast8<0>(bs); break;
-                case 1: bi = bcast8<1>(bs); break;
-                case 2: bi = bcast8<2>(bs); break;
-                case 3: bi = bcast8<3>(bs); break;
-                case 4: bi = bcast8<4>(bs); break;
-                case 5: bi = bcast8<5>(bs); break;
-                case 6: bi = bcast8<6>(bs); break;
-                default: bi = bcast8<7>(bs); break;
-                }
-                const double xi = bi * tmp[i];
-                if (gl == o) X[i + (size_t)j * n] = xi;
-                // rows of this slot below lane o, then the earlier slots (all above row i)
-                const double *col = Rp + i * (i + 1) / 2;
-                if (gl < o) bs -= col[8 * s + gl] * xi;
+        for (int o = 7; o >= 0; --o) {
+            const int i = 8 * s + o;
+            if (i > j) continue;
+            double bi;
+            switch (o) {
+            case 0: bi = bcast8<0>(bs); break;
+            case 1: bi = bcast8<1>(bs); break;
+            case 2: bi = bcast8<2>(bs); break;
+            case 3: bi = bcast8<3>(bs); break;
+            case 4: bi = bcast8<4>(bs); break;
+            case 5: bi = bcast8<5>(bs); break;
+            case 6: bi = bcast8<6>(bs); break;
+            default: bi = bcast8<7>(bs); break;
+            }
+            const double xi = bi * tmp[i];
+            if (gl == o) store(i, j, xi);
+            // rows of this slot below lane o, then the earlier slots (all above row i)
+            const double *col = Rp + i * (i + 1) / 2;
+            if (gl < o) bs -= col[8 * s + gl] * xi;
 #pragma unroll
-                for (int s2 = 0; s2 < s; ++s2) b[s2] -= col[8 * s2 + gl] * xi;
+            for (int s2 = 0; s2 < s; ++s2) b[s2] -= col[8 * s2 + gl] * xi;
+        }
+    }
+    for (int l = j + 1 + gl; l < n; l += 8) store(l, j, 0.0);
+}
+
+template <typename FS>
+__device__ __forceinline__ void big_trinv_solve(const double *Rp, const double *tmp, int n, FS store)
+{
+    for (int j = threadIdx.x >> 3; j < n; j += EIG_NT / 8) trinv_col8(Rp, tmp, n, j, store);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Inverses of the 16 x 16 diagonal blocks of the upper-triangular n x n R
+// (n <= 160; read through rd(i, k) for i <= k < n; identity beyond n), each
+// column-major into dinv + 256 I: wave w takes blocks I = w, w + 8, ..., lane
+// c < 16 solves column c by back substitution.  No barrier.
+// ---------------------------------------------------------------------------
+template <typename FR>
+__device__ __forceinline__ void diag_inv16(int n, FR rd, double *dinv)
+{
+    const int l = rl_lane(), c = l & 15;
+    const int nt = (n + 15) >> 4;
+    for (int I = rl_wave(); I < nt; I += EIG_NT / 64) {
+        const int o = 16 * I;
+        auto R = [&](int i, int k) -> double { return (o + k < n) ? rd(o + i, o + k) : ((i == k) ? 1.0 : 0.0); };
+        double x[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) x[k] = 0.0;
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+            if (i > c) continue;
+            double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = i + 1; k < 16; ++k) s -= R(i, k) * x[k];   // x[k] = 0 for k > c
+            x[i] = s / R(i, i);
+        }
+        if (l < 16)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) dinv[256 * I + 16 * c + i] = x[i];
+    }
+}
+
+// Column j of the packed upper triangle that holds packed index q.
+__device__ __forceinline__ int packed_col(int q)
+{
+    int c = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+    if (c * (c + 1) / 2 > q) --c;
+    if ((c + 1) * (c + 2) / 2 <= q) ++c;
+    return c;
+}
+
+// Rp and tmp of big_trinv_solve from R (column-major, ld n, device memory),
+// eight loads in flight per thread; ends with a barrier.
+__device__ __forceinline__ void big_tri_pack(const double *R, int n, double *Rp, double *tmp)
+{
+    const int np = n * (n + 1) / 2;
+    for (int q0 = threadIdx.x; q0 < np; q0 += 8 * EIG_NT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * EIG_NT;
+            const int c = packed_col(q);
+            v[u] = (q < np) ? R[(q - c * (c + 1) / 2) + (size_t)c * n] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * EIG_NT;
+            if (q < np) {
+                Rp[q] = v[u];
+                const int c = packed_col(q);
+                if (q - c * (c + 1) / 2 == c) tmp[c] = 1.0 / v[u];
             }
         }
-        for (int l = j + 1 + gl; l < n; l += 8) X[l + (size_t)j * n] = 0.0;
     }
     __syncthreads();
+}
+
+// X = R^-1 (X column-major, ld n, device memory, not aliasing R).
+__device__ __forceinline__ void big_trinv(const double *R, int n, double *X, double *Rp, double *tmp)
+{
+    big_tri_pack(R, n, Rp, tmp);
+    big_trinv_solve(Rp, tmp, n, [&](int i, int j, double x) { X[i + (size_t)j * n] = x; });
 }
 
 }  // namespace pod

@@ -228,6 +228,12 @@ constexpr int SMALL_LDS_P = 64;
 // Device scratch of the inverse iteration of wide merges (p > SMALL_LDS_P):
 // six arrays of 160 rows for 64 lanes.
 constexpr size_t BIG_INVIT_DOUBLES = (size_t)6 * 160 * 64;
+// inverses of the 16 x 16 diagonal blocks of a wide merge's triangular factor
+constexpr size_t BIG_DINV_DOUBLES = (size_t)(160 / 16) * 256;
+__host__ __device__ constexpr size_t big_dinv_offset(int pmax)
+{
+    return (size_t)3 * pmax * pmax + pmax + BIG_INVIT_DOUBLES;
+}
 
 struct SmallArgs {
     DevState *ds;

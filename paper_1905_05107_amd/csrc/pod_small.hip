@@ -344,20 +344,18 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
     extern __shared__ double lds[];
     __shared__ double sP[EIG_NMAX];
     __shared__ double sred[16];
-    __shared__ int sbad;
     DevState *ds = a.ds;
     if (merge_halted(ds)) return;
     const int p = ds->p, rs = ds->rs, p0 = ds->p0;
     const int pm = a.pmax;
-    double *S = BIG ? a.ws : lds;       // p x p
-    double *tmp = S + pm * pm;          // p doubles
-    double *GP = tmp + pm;              // G0 P (p0 x p) with a dense right factor; then R1^-1
-    if (threadIdx.x == 0) sbad = 0;
+    double *S = a.ws;                   // G1 (p x p) when the right factor is dense
+    double *GP = S + pm * pm + pm;      // G0 P (p0 x p) with a dense right factor; then R1^-1
+    double *Rp = lds, *rdiag = lds + BIG_PACKED;   // R1 packed by columns, 1 / diag(R1)
     const double *sigma = (ds->it & 1) ? a.sig1 : a.sig0;
     for (int i = threadIdx.x; i < p; i += NT) sP[i] = (i < rs) ? sigma[i] : (a.sigma2 ? a.sigma2[i - rs] : 1.0);
     __syncthreads();
     if (a.use_vt) {
-        // P = blkdiag(Sigma_r, Vt): GP = G0 P, then G1 = P^T GP into a.work
+        // P = blkdiag(Sigma_r, Vt): GP = G0 P, then G1 = P^T GP into S
         for (int idx = threadIdx.x; idx < p0 * p; idx += NT) {
             const int i = idx % p0, b = idx / p0;
             double v;
@@ -370,75 +368,77 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
             GP[i + b * p0] = v;
         }
         __syncthreads();
-    }
-    double tr = 0.0;
-    int bad = 0;
-    for (int idx = threadIdx.x; idx < p * p; idx += NT) {
-        const int i = idx % p, j = idx / p;
-        double v;
-        if (!a.use_vt) {
-            v = a.G[i + j * pm] * sP[i] * sP[j];
-        } else if (i < rs) {
-            v = sP[i] * GP[i + j * p0];
-        } else {
-            v = 0.0;
-            for (int l = 0; l < p0 - rs; ++l) v += a.Vt[l + (i - rs) * pm] * GP[(rs + l) + j * p0];
+        for (int idx = threadIdx.x; idx < p * p; idx += NT) {
+            const int i = idx % p, j = idx / p;
+            double v;
+            if (i < rs) {
+                v = sP[i] * GP[i + j * p0];
+            } else {
+                v = 0.0;
+                for (int l = 0; l < p0 - rs; ++l) v += a.Vt[l + (i - rs) * pm] * GP[(rs + l) + j * p0];
+            }
+            S[idx] = v;
         }
-        if (!isfinite(v)) bad = 1;
-        S[idx] = v;
-        a.work[idx] = v;
-        if (i == j) tr += v;
+        __syncthreads();
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) tr += __shfl_xor(tr, o, 64);
+    // G1 = P^T G0 P, read where the Cholesky needs it
+    auto g1 = [&](int i, int j) -> double {
+        return a.use_vt ? S[i + j * p] : a.G[i + j * pm] * sP[i] * sP[j];
+    };
+    double tr = (threadIdx.x < p) ? g1(threadIdx.x, threadIdx.x) : 0.0;
+    tr = wave_sum(tr);
     if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = tr;
-    if (bad) sbad = 1;
     __syncthreads();
     double trace = 0.0;
     for (int q = 0; q < NT / 64; ++q) trace += sred[q];
-    if (sbad) {
-        if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NONFINITE);
-        for (int idx = threadIdx.x; idx < p * p; idx += NT) S[idx] = (idx % p == idx / p) ? 1.0 : 0.0;
+    // R1 into Rp; a failed pivot is retried once with the diagonal shifted by
+    // p u tr(G1)
+    int fail = isfinite(trace) ? 0 : 2;
+    for (int attempt = 0; attempt < 2 && fail != 2; ++attempt) {
+        const double shift = attempt ? (double)p * a.urnd * trace : 0.0;
+        const double thr = attempt ? 0.0 : a.urnd * trace * 1e-3;
+        fail = big_chol(
+            p, thr, [&](int i, int j) { return g1(i, j) + ((i == j) ? shift : 0.0); },
+            [&](int r, int c, double v) {
+                Rp[c * (c + 1) / 2 + r] = v;
+                if (r == c) rdiag[c] = 1.0 / v;
+            });
+        if (fail != 1) break;
+        if (attempt == 0 && threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
+    }
+    if (fail) {
+        if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)((fail & 2) ? FLAG_NONFINITE : FLAG_NOTPD));
+        for (int q = threadIdx.x; q < p * (p + 1) / 2; q += NT) {
+            const int c = packed_col(q);
+            Rp[q] = (q - c * (c + 1) / 2 == c) ? 1.0 : 0.0;
+        }
+        for (int i = threadIdx.x; i < p; i += NT) rdiag[i] = 1.0;
         __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
+        const int i = idx % pm, j = idx / pm;
+        a.R1[idx] = (i <= j && j < p) ? Rp[j * (j + 1) / 2 + i] : 0.0;
+    }
+    // T1 = P R1^-1 (p0 x p, zero-padded to pmax x pmax); without a right
+    // factor P is diagonal and k_wide_trsm<0> forms T1 on the matrix cores
+    // from R1 and the inverses of its diagonal blocks
+    if (!a.use_vt) {
+        diag_inv16(p, [&](int i, int k) { return Rp[k * (k + 1) / 2 + i]; }, a.ws + big_dinv_offset(pm));
     } else {
-        const double thr = a.urnd * trace;
-        int fail = big_chol(S, p, thr * 1e-3);
-        if (fail) {
-            const double shift = (double)p * a.urnd * trace;
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < p * p; idx += NT)
-                S[idx] = a.work[idx] + ((idx % p == idx / p) ? shift : 0.0);
-            __syncthreads();
-            if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
-            fail = big_chol(S, p, 0.0);
-            if (fail) {
-                if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_NOTPD);
-                for (int idx = threadIdx.x; idx < p * p; idx += NT) S[idx] = (idx % p == idx / p) ? 1.0 : 0.0;
-                __syncthreads();
+        double *Xi = GP;   // R1^-1 (the G0 P product is no longer needed)
+        big_trinv_solve(Rp, rdiag, p, [&](int i, int j, double x) { Xi[i + j * p] = x; });
+        for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
+            const int i = idx % pm, j = idx / pm;
+            double v = 0.0;
+            if (i < p0 && j < p) {
+                if (i < rs) {
+                    v = sP[i] * Xi[i + j * p];
+                } else {
+                    for (int l = rs; l <= j; ++l) v += a.Vt[(i - rs) + (l - rs) * pm] * Xi[l + j * p];
+                }
             }
+            store_c(a.Tc, a.prec, idx, v);
         }
-    }
-    for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
-        const int i = idx % pm, j = idx / pm;
-        a.R1[idx] = (i < p && j < p) ? S[i + j * p] : 0.0;
-    }
-    __syncthreads();
-    double *Xi = GP;   // R1^-1 (the G0 P product is no longer needed)
-    big_trinv(S, p, Xi, lds, lds + BIG_PACKED);
-    // T1 = P R1^-1 (p0 x p)
-    for (int idx = threadIdx.x; idx < pm * pm; idx += NT) {
-        const int i = idx % pm, j = idx / pm;
-        double v = 0.0;
-        if (!a.use_vt) {
-            if (i < p && j < p) v = sP[i] * Xi[i + j * p];
-        } else if (i < p0 && j < p) {
-            if (i < rs) {
-                v = sP[i] * Xi[i + j * p];
-            } else {
-                for (int l = rs; l <= j; ++l) v += a.Vt[(i - rs) + (l - rs) * pm] * Xi[l + j * p];
-            }
-        }
-        store_c(a.Tc, a.prec, idx, v);
     }
     }
 }
@@ -447,6 +447,130 @@ template <bool BIG>
 __global__ __launch_bounds__(512) void k_chol_first(SmallArgs a)
 {
     chol_first_body<BIG>(a);
+}
+
+// ---------------------------------------------------------------------------
+// Triangular solves of a wide merge on the matrix cores, X = R^-1 B for the
+// upper-triangular p x p factor R (M = 0: R1 (a.R1, ld pmax), B = I, into Tc
+// as T1 = diag(sP) X, zero outside p x p; M = 1: R2 (S1, ld p), B = U_R (S3,
+// p x r'), into the leading p x r' block of Tc as Z2).  Blocked back
+// substitution over 16 x 16 tiles: wave w of workgroup b owns the column
+// tile J = 4 b + w of X and, for the row tiles I from the last up,
+//   X(I, J) = D_I (B(I, J) - sum_{K > I} R(I, K) X(K, J)),
+// D_I the inverse of the diagonal block (BIG_DINV_DOUBLES at
+// big_dinv_offset, written by the Cholesky kernel), each product a chain of
+// v_mfma_f64_16x16x4.  The solved tiles stay in registers: the FP64
+// accumulator layout (rows l / 16 + 4 v) is the layout of the B operand's
+// four k-chunks.  R's upper tiles and the D_I are staged in LDS in the
+// A-operand layout (tile (I, K) at (K (K + 1) / 2 + I) 256, chunk s, lane).
+// ---------------------------------------------------------------------------
+constexpr int TRSM_NT = EIG_NMAX / 16;                          // row tiles of the widest merge
+constexpr int TRSM_TILES = TRSM_NT * (TRSM_NT + 1) / 2;
+constexpr size_t TRSM_LDS = (size_t)(TRSM_TILES + TRSM_NT) * 256 * sizeof(double);
+constexpr int TRSM_BATCH = 32;                                   // staging loads in flight per thread
+
+template <int M>
+__global__ __launch_bounds__(256) void k_wide_trsm(SmallArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double sP[EIG_NMAX];
+    const DevState *ds = a.ds;
+    if (merge_halted(ds)) return;
+    const int p = ds->p, pm = a.pmax;
+    const int ncol = (M == 0) ? p : ds->rnew;
+    const int nt = (p + 15) >> 4;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int J = 4 * blockIdx.x + w;
+    const double *Rm = (M == 0) ? a.R1 : a.ws;
+    const int ldr = (M == 0) ? pm : p;
+    const double *dinv = a.ws + big_dinv_offset(pm);
+    // (Ts: the upper tiles of the first nt tile columns, packed; Ds right after them)
+    if (M == 0) {
+        const int rs = ds->rs;
+        const double *sigma = (ds->it & 1) ? a.sig1 : a.sig0;
+        for (int i = threadIdx.x; i < p; i += 256) sP[i] = (i < rs) ? sigma[i] : (a.sigma2 ? a.sigma2[i - rs] : 1.0);
+    }
+    // stage R's upper tiles, then the D_I: thread e takes entry e of every
+    // tile, TRSM_BATCH tiles (loads in flight) at a time
+    const int ntri = nt * (nt + 1) / 2;
+    const int e = threadIdx.x;
+    const int erow = e & 15, ecol = 4 * (e >> 6) + ((e >> 4) & 3);   // (m, k) of entry e in the operand layout
+    int tI = 0, tK = 0;                                               // tile (I, K) of t = t0
+    for (int t0 = 0; t0 < ntri + nt; t0 += TRSM_BATCH) {
+        double v[TRSM_BATCH];
+        int I = tI, K = tK;
+#pragma unroll
+        for (int u = 0; u < TRSM_BATCH; ++u) {
+            const int t = t0 + u;
+            double x = 0.0;
+            if (t < ntri) {
+                const int row = 16 * I + erow, col = 16 * K + ecol;
+                if (row < p && col < p && row <= col) x = Rm[row + (size_t)col * ldr];
+                if (++I > K) {
+                    ++K;
+                    I = 0;
+                }
+            } else if (t < ntri + nt) {
+                x = dinv[256 * (t - ntri) + e];
+            }
+            v[u] = x;
+        }
+        tI = I;
+        tK = K;
+#pragma unroll
+        for (int u = 0; u < TRSM_BATCH; ++u) {
+            const int t = t0 + u;
+            if (t < ntri + nt) lds[256 * t + e] = v[u];
+        }
+    }
+    __syncthreads();
+    if (16 * J >= pm) return;
+    const int jc = 16 * J + (l & 15);   // this lane's column of X
+    double X[TRSM_NT][4];
+#pragma unroll
+    for (int I = 0; I < TRSM_NT; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * I + (l >> 4) + 4 * v;
+            if (M == 0)
+                X[I][v] = (row == jc && row < p) ? 1.0 : 0.0;
+            else
+                X[I][v] = (row < p && jc < ncol) ? a.ws[2 * (size_t)p * p + row + (size_t)jc * p] : 0.0;
+        }
+    if (16 * J < ncol) {
+#pragma unroll
+        for (int I = TRSM_NT - 1; I >= 0; --I) {
+            if (I >= nt || (M == 0 && I > J)) continue;
+            v4d acc = {X[I][0], X[I][1], X[I][2], X[I][3]};
+#pragma unroll
+            for (int K = I + 1; K < TRSM_NT; ++K) {
+                if (K >= nt || (M == 0 && K > J)) continue;
+                const double *ta = lds + (K * (K + 1) / 2 + I) * 256 + l;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc = mfma16x16x4(-ta[64 * s], X[K][s], acc);
+            }
+            v4d x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) x = mfma16x16x4(lds[256 * (ntri + I) + 64 * s + l], acc[s], x);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) X[I][v] = x[v];
+        }
+    }
+    // out: T1 over all of pmax x pmax (zero outside p x p and below the
+    // diagonal tiles), Z2 on its leading p x r' block
+#pragma unroll
+    for (int I = 0; I < TRSM_NT; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * I + (l >> 4) + 4 * v;
+            if (M == 0) {
+                if (row < pm && jc < pm)
+                    store_c(a.Tc, a.prec, row + (size_t)jc * pm,
+                            (row < p && jc < p && I <= J) ? sP[row] * X[I][v] : 0.0);
+            } else if (row < p && jc < ncol) {
+                store_c(a.Tc, a.prec, row + (size_t)jc * pm, X[I][v]);
+            }
+        }
 }
 
 // Batched: one workgroup per matrix (blockIdx.y), stopped matrices skipped.
@@ -468,11 +592,21 @@ hipError_t launch_chol_first(const SmallArgs &a, hipStream_t st)
         if (e != hipSuccess) return e;
         attr[big] = true;
     }
+    static bool attr_t1 = false;
+    if (big && !a.use_vt && !attr_t1) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_wide_trsm<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)TRSM_LDS);
+        if (e != hipSuccess) return e;
+        attr_t1 = true;
+    }
     ProfScope ps(POD_K_CHOL, st);
-    if (big)
+    if (big) {
         hipLaunchKernelGGL(k_chol_first<true>, dim3(1), dim3(NT), lds, st, a);
-    else
+        if (!a.use_vt)
+            hipLaunchKernelGGL(k_wide_trsm<0>, dim3((unsigned)((a.pmax + 63) / 64)), dim3(256), TRSM_LDS, st, a);
+    } else {
         hipLaunchKernelGGL(k_chol_first<false>, dim3(1), dim3(NT), lds, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -665,12 +799,107 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
     }
 }
 
-template <bool BIG>
-__device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
+// ---------------------------------------------------------------------------
+// Wide merges (64 < p <= 160): the small stage of Alg. 2 as a chain of
+// kernels over the workspace ws (S1 = R2, S2 = H, S3 = R then U_R, each
+// p x p, ld p), so that the products and the triangular solves spread over
+// many workgroups and only the inherently sequential factorisations
+// (Cholesky, tridiagonalisation, eigenvectors) keep one workgroup:
+//   k_wide_chol2   G2 = R2^T R2 (one workgroup)
+//   k_wide_mm<0>   R = R2 R1 (one 16 x 16 tile per workgroup)
+//   k_wide_mm<1>   H = R R^T
+//   k_wide_eig     the top r' eigenpairs of H (U_R) and the convergence
+//                  sines (one workgroup); sets rnew and sin_theta
+//   k_wide_trsm<1> Z2 = R2^-1 U_R into Tc (blocked, on the matrix cores)
+//   k_wide_sig     Sigma_new(i) = |U_R(:, i)^T R| and the merge count (one
+//                  workgroup)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_wide_chol2(SmallArgs a)
 {
-    if constexpr (!BIG) {
-        svd_merge_rl(a);
+    __shared__ double sred[NT / 64];
+    DevState *ds = a.ds;
+    if (merge_halted(ds)) return;
+    const int p = ds->p;
+    const int pm = a.pmax;
+    double *S1 = a.ws;
+    // G2 = R2^T R2 into S1, read from G; a failed pivot is retried once with
+    // the diagonal shifted by p u tr(G2)
+    double tr = (threadIdx.x < p) ? a.G[threadIdx.x + threadIdx.x * pm] : 0.0;
+    tr = wave_sum(tr);
+    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = tr;
+    __syncthreads();
+    double trace = 0.0;
+    for (int q = 0; q < NT / 64; ++q) trace += sred[q];
+    int fail = isfinite(trace) ? 0 : 2;
+    for (int attempt = 0; attempt < 2 && fail != 2; ++attempt) {
+        const double shift = attempt ? (double)p * a.urnd * trace : 0.0;
+        const double thr = attempt ? 0.0 : a.urnd * trace * 1e-3;
+        fail = big_chol(
+            p, thr, [&](int i, int j) { return a.G[i + j * pm] + ((i == j) ? shift : 0.0); },
+            [&](int r, int c, double v) {
+                S1[r + c * p] = v;
+                if (c > r) S1[c + r * p] = 0.0;
+            });
+        if (fail != 1) break;
+        if (attempt == 0 && threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
+    }
+    if (fail) {
+        if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)((fail & 2) ? FLAG_NONFINITE : FLAG_NOTPD));
+        for (int idx = threadIdx.x; idx < p * p; idx += NT) S1[idx] = (idx % p == idx / p) ? 1.0 : 0.0;
+        __syncthreads();
+    }
+    diag_inv16(p, [&](int i, int k) { return S1[i + k * p]; }, a.ws + big_dinv_offset(pm));
+}
+
+// R = R2 R1 (M = 0; both upper triangular: tile (I, J) sums k in
+// [16 I, 16 J + 16)), kept in R2 for the singular values and, for the mode
+// criterion, its first min(k, r_s) columns in work; H = R R^T (M = 1: upper
+// tiles, mirrored; tile (I, J) sums k from 16 max(I, J)).  Grid: the tiles
+// of pmax x pmax; tiles outside p x p return at once.
+template <int M>
+__global__ __launch_bounds__(64) void k_wide_mm(SmallArgs a)
+{
+    const DevState *ds = a.ds;
+    if (merge_halted(ds)) return;
+    const int p = ds->p, rs = ds->rs, pm = a.pmax;
+    const int nt = (p + 15) >> 4;
+    const int ti = (int)blockIdx.x % TRSM_NT, tj = (int)blockIdx.x / TRSM_NT;
+    if (ti >= nt || tj >= nt) return;
+    double *S1 = a.ws, *S2 = S1 + p * p, *S3 = S1 + 2 * p * p;
+    if (M == 0) {
+        const int kk0 = (a.k < rs) ? a.k : rs;
+        const bool keep = a.criterion == POD_CRIT_MODE;
+        mm_tile_all<EIG_NMAX / 16>(
+            ti, tj, 16 * ti, 16 * tj + 16, [&](int i, int k) { return (i < p && k < p) ? S1[i + k * p] : 0.0; },
+            [&](int k, int j) { return (k < p && j < p) ? a.R1[k + j * pm] : 0.0; },
+            [&](int i, int j, double v) {
+                if (i < p && j < p) {
+                    S3[i + j * p] = v;
+                    a.R2[i + j * pm] = v;
+                    if (keep && j < kk0) a.work[i + j * p] = v;
+                }
+            });
     } else {
+        if (ti > tj) return;
+        mm_tile_all<EIG_NMAX / 16>(
+            ti, tj, 16 * ((ti > tj) ? ti : tj), 16 * nt,
+            [&](int i, int k) { return (i < p && k < p) ? S3[i + k * p] : 0.0; },
+            [&](int k, int j) { return (k < p && j < p) ? S3[j + k * p] : 0.0; },
+            [&](int i, int j, double v) {
+                if (i < p && j < p) {
+                    S2[i + j * p] = v;
+                    S2[j + i * p] = v;
+                }
+            });
+    }
+}
+
+// The top r' = min(r, p, #{lambda_i > max((p u)^2, p u64) lambda_1})
+// eigenpairs of H (S2): tridiagonalisation, multisection, inverse iteration,
+// back-transformation into S3 (p x r'); then the convergence sines against
+// the previous basis.  Sets ds->rnew and ds->sin_theta.
+__global__ __launch_bounds__(512) void k_wide_eig(SmallArgs a)
+{
     extern __shared__ double lds[];
     __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
         ssc[8], ssin[2];
@@ -679,70 +908,10 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
     DevState *ds = a.ds;
     if (merge_halted(ds)) return;
     const int p = ds->p, rs = ds->rs;
-    const int it0 = ds->it;   // read before thread 0 advances it at the end
     const int pm = a.pmax;
-    double *S1 = BIG ? a.ws : lds; // G2 -> R2 -> R2^-1
-    double *S2 = S1 + p * p;       // R1 -> H = R R^T -> reflectors -> B^T B
-    double *S3 = S1 + 2 * p * p;   // R -> eigenvectors Y (p x r')
-    // ---- pass-2 Cholesky
-    double tr = 0.0;
-    for (int idx = threadIdx.x; idx < p * p; idx += NT) {
-        const int i = idx % p, j = idx / p;
-        const double v = a.G[i + j * pm];
-        S1[idx] = v;
-        S2[idx] = a.R1[i + j * pm];
-        if (i == j) tr += v;
-    }
-    tr = wave_sum(tr);
-    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = tr;
-    __syncthreads();
-    double trace = 0.0;
-    for (int q = 0; q < NT / 64; ++q) trace += sred[q];
-    int fail = isfinite(trace) ? big_chol(S1, p, a.urnd * trace * 1e-3) : 1;
-    if (fail) {
-        const double shift = (double)p * a.urnd * (isfinite(trace) ? trace : 1.0);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < p * p; idx += NT) {
-            const int i = idx % p, j = idx / p;
-            S1[idx] = a.G[i + j * pm] + ((i == j) ? shift : 0.0);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
-        fail = isfinite(trace) ? big_chol(S1, p, 0.0) : 1;
-        if (fail) {
-            if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)(isfinite(trace) ? FLAG_NOTPD : FLAG_NONFINITE));
-            for (int idx = threadIdx.x; idx < p * p; idx += NT) S1[idx] = (idx % p == idx / p) ? 1.0 : 0.0;
-            __syncthreads();
-        }
-    }
-    // ---- R = R2 R1 (both upper triangular: tile (I, J) sums k in [16 I, 16 J + 16))
-    big_mm(p, false,
-           [&](int i, int k) { return (i < p && k < p) ? S1[i + k * p] : 0.0; },
-           [&](int k, int j) { return (k < p && j < p) ? S2[k + j * p] : 0.0; },
-           [&](int i, int j, double v) {
-               if (i < p && j < p) {
-                   S3[i + j * p] = v;
-                   a.R2[i + j * pm] = v;   // the merge factor R, kept for the adjoint
-               }
-           },
-           [&](int ti, int tj, int &k0, int &k1) { k0 = 16 * ti; k1 = 16 * tj + 16; });
-    __syncthreads();
+    double *S2 = a.ws + p * p;       // H -> reflectors -> B^T B
+    double *S3 = a.ws + 2 * p * p;   // eigenvectors U_R (p x r')
     const int kk0 = (a.k < rs) ? a.k : rs;
-    if (a.criterion == POD_CRIT_MODE && kk0 > 0)
-        for (int idx = threadIdx.x; idx < p * kk0; idx += NT) a.work[idx] = S3[idx];
-    // ---- H = R R^T (upper tiles, mirrored; tile (I, J) sums k from 16 max(I, J))
-    big_mm(p, true,
-           [&](int i, int k) { return (i < p && k < p) ? S3[i + k * p] : 0.0; },
-           [&](int k, int j) { return (k < p && j < p) ? S3[j + k * p] : 0.0; },
-           [&](int i, int j, double v) {
-               if (i < p && j < p) {
-                   S2[i + j * p] = v;
-                   S2[j + i * p] = v;
-               }
-           },
-           [&](int ti, int tj, int &k0, int &k1) { k0 = 16 * ((ti > tj) ? ti : tj); });
-    __syncthreads();
-    // ---- eigen-decomposition of H
     big_tridiag(S2, p, sd, se, stau);
     const int nv = (a.r < p) ? a.r : p;
     const BigTri bt = big_tri(sd, se, p, lds);   // (the dynamic LDS is free until the convergence test)
@@ -824,79 +993,109 @@ __device__ __forceinline__ void svd_merge_body(const SmallArgs &a)
             }
         }
     }
-    // ---- Z2 = R2^-1 U_R(:, 0:rnew)  (R2^-1 into S2, free after the sines)
-    big_trinv(S1, p, S2, lds, spv);
-    // (R2^-1 upper triangular: tile row I sums k from 16 I; only the leading
-    // p x rnew block of Tc is read by the tall transform)
-    big_mm(p, false,
-           [&](int i, int k) { return (i < p && k < p) ? S2[i + k * p] : 0.0; },
-           [&](int k, int j) { return (k < p && j < rnew) ? S3[k + j * p] : 0.0; },
-           [&](int i, int j, double v) {
-               if (i < pm && j < pm) store_c(a.Tc, a.prec, i + j * pm, v);
-           },
-           [&](int ti, int tj, int &k0, int &k1) { (void)tj; k0 = 16 * ti; });
-    // ---- Sigma_new(i) = |U_R(:, i)^T R| (rows of U_R^T R = Sigma_R V_R^T) into S1
-    // (free after the inverse); R upper triangular: tile column J sums k < 16 J + 16
-    __syncthreads();
-    big_mm(p, false,
-           [&](int i, int k) { return (i < rnew && k < p) ? S3[k + i * p] : 0.0; },
-           [&](int k, int j) { return (k < p && j < p) ? a.R2[k + j * pm] : 0.0; },
-           [&](int i, int j, double v) {
-               if (i < p && j < p) S1[i + j * p] = v;
-           },
-           [&](int ti, int tj, int &k0, int &k1) { (void)ti; k0 = 0; k1 = 16 * tj + 16; });
-    __syncthreads();
-    double *sigma_new = (it0 & 1) ? a.sig0 : a.sig1;
-    for (int i = threadIdx.x; i < a.r; i += NT) {
-        double v = 0.0;
-        if (i < rnew)
-            for (int j = 0; j < p; ++j) v = fma(S1[i + j * p], S1[i + j * p], v);
-        sigma_new[i] = sqrt(v);
-    }
     if (threadIdx.x == 0) {
         ds->rnew = rnew;
         ds->sin_theta = sin_max;
+    }
+}
+
+// Sigma_new(i) = |row i of W = U_R^T R| (i < r'; zero for r' <= i < r), R
+// upper triangular in R2 (ld pmax): the tiles of W dealt to the 8 waves, each
+// wave summing the squares of its tiles' rows into its own partials, the
+// partials added in wave order.  Then the merge count and rank advance.
+constexpr int SIG_NT = 512;
+__global__ __launch_bounds__(SIG_NT) void k_wide_sig(SmallArgs a)
+{
+    __shared__ double part[SIG_NT / 64][EIG_NMAX];
+    DevState *ds = a.ds;
+    if (merge_halted(ds)) return;
+    const int p = ds->p, rnew = ds->rnew, it0 = ds->it, pm = a.pmax;
+    const double *S3 = a.ws + 2 * p * p;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int idx = threadIdx.x; idx < (SIG_NT / 64) * EIG_NMAX; idx += SIG_NT) part[idx / EIG_NMAX][idx % EIG_NMAX] = 0.0;
+    __syncthreads();
+    const int nti = (rnew + 15) >> 4, ntj = (p + 15) >> 4;
+    for (int tile = w; tile < nti * ntj; tile += SIG_NT / 64) {
+        const int ti = tile / ntj, tj = tile % ntj;
+        mm_tile_all<EIG_NMAX / 16>(
+            ti, tj, 0, 16 * tj + 16, [&](int i, int k) { return (i < rnew && k < p) ? S3[k + i * p] : 0.0; },
+            [&](int k, int j) { return (k < p && j < p) ? a.R2[k + j * pm] : 0.0; },
+            [&](int i, int j, double v) {
+                // the 16 lanes of a row group hold the 16 columns of its rows
+                const double sq = group_reduce<16, OpSum>(v * v);
+                if ((l & 15) == 0 && i < EIG_NMAX) part[w][i] += sq;
+                (void)j;
+            });
+    }
+    __syncthreads();
+    double *sigma_new = (it0 & 1) ? a.sig0 : a.sig1;
+    for (int i = threadIdx.x; i < a.r; i += SIG_NT) {
+        double v = 0.0;
+        if (i < rnew)
+            for (int q = 0; q < SIG_NT / 64; ++q) v += part[q][i];
+        sigma_new[i] = sqrt(v);
+    }
+    if (threadIdx.x == 0) {
         ds->rs = rnew;
         ds->it = it0 + 1;
         ds->g = 0;
     }
-    }
 }
 
-template <bool BIG>
+__device__ __forceinline__ void svd_merge_body(const SmallArgs &a) { svd_merge_rl(a); }
+
 __global__ __launch_bounds__(512) void k_svd_merge(SmallArgs a)
 {
-    svd_merge_body<BIG>(a);
+    svd_merge_body(a);
 }
-
 // Batched: one workgroup per matrix (blockIdx.y), stopped matrices skipped.
 __global__ __launch_bounds__(512) void k_svd_merge_b(const SmallArgs *__restrict__ arr)
 {
     const SmallArgs a = arr[blockIdx.y];
     if (a.ds->done) return;
-    svd_merge_body<false>(a);
+    svd_merge_body(a);
 }
 
 hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
 {
     const bool big = a.pmax > SMALL_LDS_P;
-    // wide merges: the convergence eigenproblem (kk <= 64) in LDS, the rest in
-    // registers, static LDS and the workspace
-    const size_t lds = big ? (size_t)max(64 * RL_LD + 512 + TRI_SDE, BIG_PACKED) * sizeof(double)
-                           : svd_merge_lds_rl(a.pmax);
-    static bool attr[2] = {false, false};
-    const void *fn = big ? (const void *)k_svd_merge<true> : (const void *)k_svd_merge<false>;
-    if (!attr[big]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(big ? lds_limit(true) : svd_merge_lds_rl(SMALL_LDS_P)));
-        if (e != hipSuccess) return e;
-        attr[big] = true;
+    if (!big) {
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute((const void *)k_svd_merge, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)svd_merge_lds_rl(SMALL_LDS_P));
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        ProfScope ps(POD_K_SVD, st);
+        hipLaunchKernelGGL(k_svd_merge, dim3(1), dim3(NT), svd_merge_lds_rl(a.pmax), st, a);
+        return hipGetLastError();
     }
+    // wide merges: the eigensolver's convergence eigenproblem (kk <= 64) and
+    // the multisection tables in dynamic LDS
+    const size_t lds = (size_t)max(64 * RL_LD + 512 + TRI_SDE, BIG_PACKED) * sizeof(double);
+    static bool attr_big = false;
+    if (!attr_big) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_wide_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_limit(true));
+        if (e != hipSuccess) return e;
+        attr_big = true;
+    }
+    static bool attr_z2 = false;
+    if (!attr_z2) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_wide_trsm<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)TRSM_LDS);
+        if (e != hipSuccess) return e;
+        attr_z2 = true;
+    }
+    const unsigned tiles = (unsigned)(TRSM_NT * TRSM_NT);
     ProfScope ps(POD_K_SVD, st);
-    if (big)
-        hipLaunchKernelGGL(k_svd_merge<true>, dim3(1), dim3(NT), lds, st, a);
-    else
-        hipLaunchKernelGGL(k_svd_merge<false>, dim3(1), dim3(NT), lds, st, a);
+    hipLaunchKernelGGL(k_wide_chol2, dim3(1), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(k_wide_mm<0>, dim3(tiles), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_wide_mm<1>, dim3(tiles), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_wide_eig, dim3(1), dim3(NT), lds, st, a);
+    hipLaunchKernelGGL(k_wide_trsm<1>, dim3((unsigned)((max(a.r, 1) + 63) / 64)), dim3(256), TRSM_LDS, st, a);
+    hipLaunchKernelGGL(k_wide_sig, dim3(1), dim3(SIG_NT), 0, st, a);
     return hipGetLastError();
 }
 
