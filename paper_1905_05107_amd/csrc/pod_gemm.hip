@@ -12,6 +12,8 @@
 // operand row hit distinct banks).  Stages are loaded as 16-byte vectors
 // into registers one stage ahead of the MFMA work on the current stage.
 // Partial sums are FP64 and reduced in a fixed order (deterministic results).
+#include <algorithm>
+
 #include "pod_internal.h"
 
 namespace pod {
@@ -1300,6 +1302,138 @@ __global__ __launch_bounds__(256) void k_gemm_tall_b(const TallArgs *__restrict_
                                      reinterpret_cast<TC *>(a.Yout1), a.vec, blockIdx.x, a.nb, a.tri);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 tall transform Y = X T (X: m x pin gathered source, T: pin x pout,
+// pin <= 16 KT, pout <= 16 NJ) with the X operands loaded straight into the
+// matrix-core registers: wave w of a workgroup takes the 16-row tiles
+// 8 b + w, 8 (b + nb) + w, ... and for each computes all of the output's
+// column tiles as Y^T = T^T X^T on v_mfma_f64_16x16x4.  The B operand (X^T,
+// four k-chunks per 16 columns of X) is read from device memory, 16
+// consecutive rows of one column per 16 lanes; the A operand (T^T) from T
+// staged once per workgroup in LDS, tile (kt, jt) at jt (jt + 1) / 2 + kt (TP:
+// upper triangular, kt <= jt) or jt KT + kt, 256 doubles in the operand
+// layout.  The products of a row tile run k-chunk by k-chunk across the
+// column tiles' accumulators (independent chains), each accumulator in k
+// order: the arithmetic of the staged kernel, bit for bit.  Two waves per
+// SIMD overlap one tile's loads with another's products; no barrier after
+// the staging.  The lane's results are rows l % 16 of columns
+// 16 jt + l / 16 + 4 v.  Column sources come from a table (LDS) of base
+// addresses, bit 0 marking an FP32 column of A.
+// ---------------------------------------------------------------------------
+constexpr int T64_WAVES = 8;
+
+template <int KT, int NJ, bool TP>
+__global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64_t m, const DevState *ds, int sel_in,
+                                                           int sel_out, const double *__restrict__ T, int ldt,
+                                                           double *Yout, double *Yout1, int tri)
+{
+    extern __shared__ double tl[];
+    __shared__ uint64_t cptr[16 * KT];
+    if (s.guard && merge_halted(ds)) return;
+    if (Yout1 && (ds->it & 1)) Yout = Yout1;
+    const int pin = sel_count(ds, sel_in), pout = sel_count(ds, sel_out);
+    s.rs = ds->rs;
+    s.g = ds->g;
+    if (s.U1 && (ds->it & 1)) s.U = s.U1;
+    const int KI = (pin + 15) >> 4, JO = (pout + 15) >> 4;   // live tiles of T
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // entry 64 q + l of tile (kt, jt) is T(16 kt + 4 q + l / 16, 16 jt + l % 16)
+    const int ntl = TP ? JO * (JO + 1) / 2 : KT * JO;
+    for (int idx = threadIdx.x; idx < ntl * 256; idx += 64 * T64_WAVES) {
+        const int t = idx >> 8, e = idx & 255;
+        int kt, jt;
+        if (TP) {
+            jt = 0;
+            while ((jt + 1) * (jt + 2) / 2 <= t) ++jt;
+            kt = t - jt * (jt + 1) / 2;
+        } else {
+            jt = t / KT;
+            kt = t % KT;
+        }
+        const int k = 16 * kt + 4 * (e >> 6) + ((e >> 4) & 3), j = 16 * jt + (e & 15);
+        tl[idx] = (k < pin && j < pout && (!tri || k <= j)) ? T[k + (int64_t)j * ldt] : 0.0;
+    }
+    for (int c = threadIdx.x; c < 16 * KT; c += 64 * T64_WAVES) {
+        uint64_t v = 0;
+        if (c < pin) {
+            const ColPtr cp = col_ptr<double>(s, m, c);
+            v = (uint64_t)(uintptr_t)cp.p | (cp.f64 ? 0u : 1u);
+        }
+        cptr[c] = v;
+    }
+    __syncthreads();
+    const int64_t ntile = (m + 15) >> 4;
+    const int r16 = lane & 15, cg = lane >> 4;
+    for (int64_t rt = (int64_t)blockIdx.x * T64_WAVES + wv; rt < ntile; rt += (int64_t)gridDim.x * T64_WAVES) {
+        const int64_t row = 16 * rt + r16;
+        const bool rin = row < m;
+        // X^T chunks: X(row, 16 kt + 4 q + l / 16)
+        double x[KT][4];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                x[kt][q] = 0.0;
+                if (kt < KI) {
+                    const uint64_t cpv = cptr[16 * kt + 4 * q + cg];
+                    if (cpv && rin) {
+                        if (cpv & 1u)
+                            x[kt][q] = (double)reinterpret_cast<const float *>(cpv & ~(uint64_t)1)[row];
+                        else
+                            x[kt][q] = reinterpret_cast<const double *>(cpv)[row];
+                    }
+                }
+            }
+        v4d acc[NJ];
+#pragma unroll
+        for (int jt = 0; jt < NJ; ++jt) acc[jt] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            if (kt >= KI) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int jt = 0; jt < NJ; ++jt) {
+                    if (jt >= JO || ((TP || tri) && kt > jt)) continue;
+                    const int t = TP ? jt * (jt + 1) / 2 + kt : jt * KT + kt;
+                    acc[jt] = mfma16x16x4(tl[256 * t + 64 * q + lane], x[kt][q], acc[jt]);
+                }
+        }
+        if (rin) {
+#pragma unroll
+            for (int jt = 0; jt < NJ; ++jt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int col = 16 * jt + cg + 4 * v;
+                    if (jt < JO && col < pout) Yout[(int64_t)col * m + row] = acc[jt][v];
+                }
+        }
+    }
+}
+
+template <int KT, int NJ, bool TP>
+static void tall64_launch(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out, const void *T,
+                          int32_t ldt, void *Yout, void *Yout1, int tri, hipStream_t st)
+{
+    const SrcT<double> s = make_src<double>(d);
+    const size_t lds = (size_t)(TP ? NJ * (NJ + 1) / 2 : KT * NJ) * 256 * sizeof(double);
+    static bool attr = false;
+    if (lds > 64 * 1024 && !attr) {
+        if (hipFuncSetAttribute((const void *)k_tall64<KT, NJ, TP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds) != hipSuccess)
+            return;   // the launch below then fails and reports the error
+        attr = true;
+    }
+    // one workgroup per CU where T fills most of the LDS, more where it is
+    // small; at least four row tiles per wave, so that staging T pays off
+    const int per_cu = (lds > 80 * 1024) ? 1 : (lds > 40 * 1024 ? 2 : 4);
+    const int64_t ntile = (d.m + 15) / 16;
+    const int64_t want = (ntile + 4 * T64_WAVES - 1) / (4 * T64_WAVES);
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * per_cu));
+    hipLaunchKernelGGL((k_tall64<KT, NJ, TP>), dim3(nb), dim3(64 * T64_WAVES), lds, st, s, d.m, ds, which_in,
+                       which_out, (const double *)T, ldt, (double *)Yout, (double *)Yout1, tri);
+}
+
 template <typename TC, int ITEMS, bool TG, bool TP = false>
 static void tall_launch(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out, int PI, int PO,
                         const void *T, int32_t ldt, void *Yout, void *Yout1, unsigned nb, int tri, hipStream_t st)
@@ -1344,6 +1478,16 @@ hipError_t launch_gemm_tall(const GemmDesc &d, const DevState *ds, int32_t which
         else
             tall_bf16_direct_launch<5, 10>(s, d.m, ds, which_in, which_out, Tb, KP, JP, Yout, Yout1, vout, tri, st);
     } else if (d.prec == POD_F64) {
+        // (inputs up to 64 wide: the staged kernel below is faster there, with
+        // little work per loaded element)
+        if (wide && PO <= 64) {
+            tall64_launch<10, 4, false>(d, ds, which_in, which_out, T, ldt, Yout, Yout1, tri, st);
+            return hipGetLastError();
+        }
+        if (wide && tri && PI == PO) {
+            tall64_launch<10, 10, true>(d, ds, which_in, which_out, T, ldt, Yout, Yout1, tri, st);
+            return hipGetLastError();
+        }
         const bool tg = (size_t)PI * PO * sizeof(double) > TALL_T_LDS;
         // an upper-triangular square T packs into LDS beside the stage
         const bool tp = tg && tri && PI == PO &&
