@@ -80,10 +80,11 @@ def kernel_work(cls, path, m, n, k, p, r, launches):
     half), reading A once: arithmetic intensity 2 k / 4 = 25 flop/B at k = 50,
     above the FP64 (9.8) and FP32 (19.7) ridges, so matrix-core bound (FP32 on
     the split-BF16 path, whose final step runs in FP32).
-    gram: symmetric Gram m p (p+1) flops reading the m x p block (4 bytes per
-    element from A, the basis in the compute type: counted at its own width
-    e).  tall: Y = X0 T1 (m p p MACs) and U = Y Z2 (m p r MACs) averaged:
-    m p (p + r) flops, reading m p e and writing m (p + r) / 2 e bytes.  The
+    gram: symmetric Gram m p (p+1) flops, the mean of pass 1 (reading X0 =
+    [U | A(:, I)]: r basis columns at the compute width e, p - r columns of
+    A at 4 bytes) and pass 2 (reading Y, m p e).  tall: the mean of
+    Y = X0 T1 with T1 upper triangular (m p (p+1) flops; X0 read, Y written)
+    and U = Y Z2 (2 m p r flops; Y read, U written).  The
     split-BF16 path's Gram and tall transforms are HBM bound (six bf16
     products per FP32-accurate one put the matrix-core roof at 2.5 PFLOP/s / 6
     and its ridge at 52 flop/B, above (p+1)/4).  svd: FP64 flops of the p x p
@@ -96,15 +97,17 @@ def kernel_work(cls, path, m, n, k, p, r, launches):
     if cls == "project":
         b = m * n * 4 / max(launches, 1)
         return "mfma", 2.0 * m * n * k / max(launches, 1), "flop", b, "f64" if path == "f64" else "f32"
+    x0 = m * (r * e + (p - r) * 4)   # bytes of X0 = [U | A(:, I)]
     if cls == "gram":
-        if path == "bf16":
-            return "hbm", m * p * 4, "B", m * p * 4, None
-        return "mfma", m * p * (p + 1), "flop", m * p * e, path
-    if cls == "tall":
-        hb = m * p * e + m * (p + r) * e // 2
+        hb = (x0 + m * p * e) // 2
         if path == "bf16":
             return "hbm", hb, "B", hb, None
-        return "mfma", m * p * (p + r), "flop", hb, path
+        return "mfma", m * p * (p + 1), "flop", hb, path
+    if cls == "tall":
+        hb = (x0 + m * p * e + m * p * e + m * r * e) // 2
+        if path == "bf16":
+            return "hbm", hb, "B", hb, None
+        return "mfma", (m * p * (p + 1) + 2 * m * p * r) / 2, "flop", hb, path
     if cls == "svd":
         return "alu", (8.0 / 3.0) * p ** 3 + 4.0 * p * p * r, "flop", 0, "f64"
     if cls == "chol":
