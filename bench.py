@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=50_000, help="rows of the oracle's larger row subsample")
     ap.add_argument("--cpu-merges", type=int, default=6, help="oracle merges timed per row subsample")
     ap.add_argument("--c5-count", type=int, default=64)
-    ap.add_argument("--c4-blocks", type=int, default=8, help="blocks of 512 columns (32: the full 16,000)")
+    ap.add_argument("--c4-blocks", type=int, default=32, help="blocks of 512 columns (32: the full 16,000)")
     return ap.parse_args()
 
 
@@ -442,11 +442,23 @@ def run_c5(args):
 
 
 def run_c4(args):
-    """Alg. 3 over pinned host blocks: travelling waves with 200 modes,
-    a_j = j^-1.2, noise variance 1e-3, rows centred by a pre-pass, m = 2M,
-    blocks of 512 columns; k = 40, c = 80, FP32 merges.  Reports the
-    streamed time, the host-link rate and the copy/compute overlap (against
-    the same blocks run from device memory)."""
+    """Alg. 3 over host blocks: travelling waves with 200 modes, a_j = j^-1.2,
+    noise variance 1e-3, rows centred (generator pre-pass), m = 2M, blocks of
+    512 columns (the last of 128 at n = 16,000); k = 40, c = 80, FP32 merges.
+
+    The snapshots are generated once into device memory (untimed: 128 GB at
+    the full size) and reach the library as host blocks through a ring of
+    2 G pinned buffers (G = 4): a producer thread copies the next group of G
+    blocks to the free half of the ring (device to host, its own stream)
+    while the library copies the current group to the device (one call,
+    which overlaps the copy of each block with the compute of the one
+    before) and runs ISMA on it.  The timed region
+    is the whole pass with the producer running.  Reported beside it: the
+    host-link rate of the library's copies, the same blocks from device
+    memory (compute only) and the copy/compute overlap inside the library
+    (its wall time against copy + compute)."""
+    import threading
+
     import torch
 
     import paper_1905_05107_amd as pod
@@ -457,56 +469,87 @@ def run_c4(args):
     bounds = [(j, min(j + w, n)) for j in range(0, n, w)]
     t_gen = time.perf_counter()
     gen = snapgen.WaveBlocks(m, n, 200, 1.2, 1e-3, seed=1004, device="cuda")
-    host = []
+    Adev = torch.empty((n, m), dtype=torch.float32, device="cuda")   # row j = snapshot j
     for j0, j1 in bounds:
-        hb = torch.empty((j1 - j0, m), dtype=torch.float32, pin_memory=True)
-        hb.copy_(gen.block(j0, j1))
-        host.append(hb)
-    torch.cuda.synchronize()
+        Adev[j0:j1].copy_(gen.block(j0, j1))
     del gen
+    torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
+    G = 4
+    slots = [torch.empty((w, m), dtype=torch.float32, pin_memory=True) for _ in range(2 * G)]
+    pstream = torch.cuda.Stream()
     kw = dict(k=40, c=80, seed=2004, theta_tol=1e-5, precision=pod.POD_F32)
 
+    def fill(bs, half):
+        """Blocks bs into the buffers of half `half` of the ring (producer side)."""
+        with torch.cuda.stream(pstream):
+            for i, b in enumerate(bs):
+                j0, j1 = bounds[b]
+                slots[G * half + i][:j1 - j0].copy_(Adev[j0:j1], non_blocking=True)
+        pstream.synchronize()
+
+    pairs = [list(range(b, min(b + G, len(bounds)))) for b in range(0, len(bounds), G)]
+
     def streamed():
+        fill(pairs[0], 0)
+        prod_s = 0.0
         with pod.Incremental(m, w, **kw) as inc:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            inc.add_host_blocks(host)
+            for i, bs in enumerate(pairs):
+                th = None
+                if i + 1 < len(pairs):
+                    def producer(bs_next=pairs[i + 1], pair=(i + 1) & 1):
+                        nonlocal prod_s
+                        tp = time.perf_counter()
+                        fill(bs_next, pair)
+                        prod_s += time.perf_counter() - tp
+                    th = threading.Thread(target=producer)
+                    th.start()
+                views = [slots[G * (i & 1) + q][:bounds[b][1] - bounds[b][0]] for q, b in enumerate(bs)]
+                inc.add_host_blocks(views)
+                if th is not None:
+                    th.join()
             U, s = inc.result()
             torch.cuda.synchronize()
-            return time.perf_counter() - t0, inc.info()
+            return time.perf_counter() - t0, inc.info(), prod_s
 
-    def resident(dev_blocks):
+    def resident():
+        """The same blocks from device memory: compute only."""
         with pod.Incremental(m, w, **kw) as inc:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for B in dev_blocks:
-                inc.add_block(B)
+            for j0, j1 in bounds:
+                inc.add_block(Adev[j0:j1].T)
             inc.result()
             torch.cuda.synchronize()
             return time.perf_counter() - t0
 
-    streamed()
+    for _ in range(max(args.warmup, 0)):
+        streamed()
     res = [streamed() for _ in range(args.steps)]
     t_s = sum(r[0] for r in res) / len(res)
-    info = res[-1][1]
-    dev_blocks = [hb.cuda().T for hb in host]
-    torch.cuda.synchronize()
-    t_r = resident(dev_blocks)
+    info, prod_s = res[-1][1], res[-1][2]
+    t_r = resident()
     copy_s = info.copy_ms / 1e3
+    wall_s = info.wall_ms / 1e3
     link = info.host_bytes / copy_s / 1e9 if copy_s > 0 else None
-    overlap = (copy_s + t_r - t_s) / min(copy_s, t_r) if copy_s > 0 else None
+    # copy/compute overlap inside the library: the share of the shorter of
+    # (copy, compute) hidden behind the other
+    overlap = (copy_s + t_r - wall_s) / min(copy_s, t_r) if copy_s > 0 and t_r > 0 else None
     out = {
         "metric": METRIC, "value": round(t_s * 1e3, 2),
         "unit": "ms per incremental POD over host-resident blocks (one pass), FP32 merges",
-        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(t_s * 1e3, 2),
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_s * 1e3, 2),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"travelling waves {m}x{n} FP32 (200 modes, a_j=j^-1.2), pinned host blocks of "
-                               f"{w} columns, k=40, c=80, theta_tol=1e-5", "blocks": len(bounds)},
-        "host_link_gbs": round(link, 2) if link else None, "copy_ms": round(info.copy_ms, 2),
-        "device_resident_ms": round(t_r * 1e3, 2),
+        "config": {"workload": f"travelling waves {m}x{n} FP32 (200 modes, a_j=j^-1.2), blocks of {w} columns from a "
+                               f"ring of {2 * G} pinned host buffers filled by a producer thread, k=40, c=80, theta_tol=1e-5",
+                   "blocks": len(bounds), "m": m, "n": n},
+        "host_bytes": info.host_bytes, "host_link_gbs": round(link, 2) if link else None,
+        "copy_ms": round(info.copy_ms, 2), "library_wall_ms": round(info.wall_ms, 2),
+        "device_resident_ms": round(t_r * 1e3, 2), "producer_ms": round(prod_s * 1e3, 2),
         "copy_compute_overlap": round(overlap, 3) if overlap is not None else None,
-        "gen_s": round(t_gen, 2), "roofline": None, "cpu_baseline": None,
+        "gen_setup_s": round(t_gen, 2), "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
