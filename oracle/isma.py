@@ -58,6 +58,7 @@ class IterLog:
     col_counts: np.ndarray
     rows: Optional[np.ndarray] = None
     row_counts: Optional[np.ndarray] = None
+    row_scales: Optional[np.ndarray] = None   # sqrt(t_hat_i / (w q_i)) of the kept rows
     r_u: int = 0
     rank: int = 0
     sin_theta: float = float("nan")
@@ -218,6 +219,8 @@ def get_update(X, prm: IsmaParams, it: int, inS: np.ndarray, wq: np.ndarray, U_s
         if replay is not None and replay.rows is not None:
             forced = (np.asarray(replay.rows, np.int64), np.asarray(replay.row_counts, np.int32))
         rows, rcnt, W = sample_and_scale_unique_rows(D, wr, prm.w, prm.seed, it, prm.block, forced)
+        Omega = float(int(np.asarray(wr, dtype=np.uint64).astype(object).sum()))
+        log.row_scales = np.sqrt(rcnt.astype(np.float64) / (float(prm.w) * (wr[rows].astype(np.float64) / Omega)))
         G = W.T @ W
         ev, Vt = jacobi_eig(G)
         h = rows.shape[0]
