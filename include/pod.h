@@ -237,11 +237,17 @@ pod_status pod_set_indices(pod_ctx *ctx, int32_t iter, const int32_t *cols, cons
                            const int32_t *rows, const int32_t *row_counts, int32_t h);
 
 /* ---------------------------------------------------------------------------
- * Reverse mode through the merge chain of Alg. 1 (ICS: w = 0, r_update = 0,
- * merge width <= 64).  Outputs differentiated: the first k merged modes and
- * singular values (U_k, Sigma_k) as pod_get_basis returns them (before the
- * final step); the sampled columns are constants (the draw is piecewise
- * constant in A).  Each merge's truncated thin SVD is differentiated with the
+ * Reverse mode through the merge chain of Alg. 1 (ICS, and ICRS with rows:
+ * w > 0; r_update = 0, merge width <= 64).  Outputs differentiated: the first
+ * k merged modes and singular values (U_k, Sigma_k) as pod_get_basis returns
+ * them (before the final step); the sampled columns and rows and the row
+ * scales are constants (draws and quantised weights are piecewise constant in
+ * A).  A row-sampled merge runs on [U Sigma | D V_u], V_u the leading r_u
+ * eigenvectors of W^T W, W = diag(s) D(rows, :) (Alg. 1, GET UPDATE with
+ * rows); its adjoint adds the eigenvector term
+ * dA(rows, cols) += 2 diag(s)^2 A(rows, cols) G-bar, G-bar = sym(V K V^T),
+ * K_ij = v_i^T Vbar_j d / (d^2 + eta^2 lambda_1^2), d = lambda_j - lambda_i
+ * (j < r_u, i != j) over the full eigenbasis of W^T W.  Each merge's truncated thin SVD is differentiated with the
  * coupling F_ij = d / (d^2 + eta^2 s_1^4), d = s_j^2 - s_i^2 (eta = 1e-12 for
  * POD_F64, 1e-6 otherwise; F_ij = 1/(s_j^2 - s_i^2) when |d| >> eta s_1^2)
  * (Townsend 2016; Ionescu, Vantzos & Sminchisescu 2015).
@@ -249,8 +255,9 @@ pod_status pod_set_indices(pod_ctx *ctx, int32_t iter, const int32_t *cols, cons
 
 /* Keep what the reverse pass needs: per merge the starting basis (m x r) and
  * Sigma, and the p x p merge factor.  Call after pod_init, before the first
- * pod_sample.  POD_EINVAL for rows, truncated blocks or a merge width above
- * 64; POD_ESTATE after a draw. */
+ * pod_sample; with rows also V_u, the rows and the row scales of each merge.
+ * POD_EINVAL for truncated blocks (r_update > 0) or a merge width above 64;
+ * POD_ESTATE after a draw. */
 pod_status pod_enable_adjoint(pod_ctx *ctx);
 
 /* dA (device, m x n, ld m, compute type) += d<dU, U_k> + <dsigma, Sigma_k> / dA

@@ -64,6 +64,31 @@ __global__ __launch_bounds__(256) void k_ckpt_post(const DevState *ds, const dou
     }
 }
 
+// Row-sampled merge about to run (merge ds->it): its right factor V_u
+// (g x r_u, ld pm), the scales and distinct rows of its row draw, and (r_u, h).
+__global__ __launch_bounds__(256) void k_ckpt_rows(const DevState *ds, const double *Vt, const double *sc,
+                                                   const int32_t *rows, int32_t pm, int32_t w, double *ckV,
+                                                   double *ckSc, int32_t *ckRows, int32_t *ckRH, int32_t cap)
+{
+    if (merge_halted(ds)) return;
+    const int32_t t = ds->it;
+    if (t >= cap) return;
+    const int32_t g = ds->g, ru = ds->ru, h = ds->h;
+    double *v = ckV + (int64_t)t * pm * pm;
+    for (int idx = threadIdx.x; idx < g * ru; idx += 256) {
+        const int i = idx % g, j = idx / g;
+        v[i + j * pm] = Vt[i + j * pm];
+    }
+    for (int q = threadIdx.x; q < h; q += 256) {
+        ckSc[(int64_t)t * w + q] = sc[q];
+        ckRows[(int64_t)t * w + q] = rows[q];
+    }
+    if (threadIdx.x == 0) {
+        ckRH[2 * t] = ru;
+        ckRH[2 * t + 1] = h;
+    }
+}
+
 __global__ void k_adj_state(DevState *ds, int32_t rs, int32_t g)
 {
     ds->rs = rs;
@@ -159,6 +184,9 @@ pod_status reverse_merges(pod_ctx *ctx, void *dA)
     A_HIP(hipMemcpy(off.data(), ctx->col_log_off, sizeof(int32_t) * (T + 1), hipMemcpyDeviceToHost));
     for (int32_t t = 0; t < T; ++t)
         if (meta[4 * t + 3] != 1) return POD_ESTATE;
+    const bool rowm = p.w > 0;
+    std::vector<int32_t> rh(rowm ? 2 * (size_t)T : 0);
+    if (rowm) A_HIP(hipMemcpy(rh.data(), ctx->ckRH, sizeof(int32_t) * 2 * T, hipMemcpyDeviceToHost));
     const size_t esz = ctx->esz;
     const double eta = (p.precision == POD_F64) ? 1e-12 : 1e-6;
     int cur = 0;
@@ -197,9 +225,42 @@ pod_status reverse_merges(pod_ctx *ctx, void *dA)
         aa.g = g;
         aa.rz = rz;
         aa.eta = eta;
+        AdjRowsArgs ra;
+        const int32_t pm = ctx->pmax;
+        if (rowm) {
+            // merge t ran on X0 P with P = blkdiag(Sigma, V_u): the eigenbasis of
+            // G = W^T W first, for the adjoint of V_u
+            const int32_t ru = rh[2 * t], h = rh[2 * t + 1];
+            if (rs + ru > pm || h > p.w) return POD_ESTATE;
+            ra.A = ctx->A;
+            ra.a_dtype = p.a_dtype;
+            ra.lda = p.lda;
+            ra.cols = ctx->col_log + off[t];
+            ra.rows = ctx->ckRows + (size_t)t * p.w;
+            ra.scales = ctx->ckSc + (size_t)t * p.w;
+            ra.vt = ctx->ckV + (size_t)t * pm * pm;
+            ra.g = g;
+            ra.h = h;
+            ra.ru = ru;
+            ra.pm = pm;
+            ra.vfull = ctx->adj_rows;
+            ra.gbar = ctx->adj_rows + (size_t)pm * pm;
+            ra.lam = ctx->adj_rows + 2 * (size_t)pm * pm;
+            ra.dA = dA;
+            ra.ldd = p.m;
+            ra.prec = p.precision;
+            if (ru > 0) A_HIP(launch_adj_rows_eig(ra, ctx->st));
+            aa.vt = ra.vt;
+            aa.ru = ru;
+            aa.vfull = ra.vfull;
+            aa.lam = ra.lam;
+            aa.gbar = ctx->adj_rows + (size_t)pm * pm;
+        }
         A_HIP(launch_adj_small(aa, ctx->st));
         A_HIP(launch_gemm_tall_scatter(gd, ctx->dsb, Pext, P, Pext, P, ctx->Wt, ctx->pb, ctx->Ubar[cur ^ 1], rs,
                                        ctx->col_log + off[t], dA, p.m, ctx->st));
+        // the part of dA(rows, cols) through G = W^T W
+        if (rowm && ra.ru > 0) A_HIP(launch_adj_rows_update(ra, ctx->st));
         cur ^= 1;
     }
     A_HIP(hipStreamSynchronize(ctx->st));
@@ -269,7 +330,7 @@ pod_status pod::reverse_merges_batch(pod_ctx *const *ctxs, int32_t count, void *
         pod_ctx *ctx = ctxs[i];
         Run &R = run[i];
         R.T = ctx->hs.it;
-        if (ctx->prm.precision != prec || ctx->pb > 64 || ctx->pmax > 64) return POD_EINVAL;
+        if (ctx->prm.precision != prec || ctx->pb > 64 || ctx->pmax > 64 || ctx->prm.w != 0) return POD_EINVAL;
         if (R.T < 1) continue;
         if (ctx->ck_lost || R.T > ctx->ck_cap) return POD_ENOMEM;
         R.meta.resize(4 * (size_t)R.T);
@@ -410,6 +471,13 @@ hipError_t pod::launch_ckpt_pre(pod_ctx *ctx, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t pod::launch_ckpt_rows(pod_ctx *ctx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ckpt_rows, dim3(1), dim3(256), 0, st, ctx->ds, ctx->Vt, ctx->rscale, ctx->rows, ctx->pmax,
+                       ctx->prm.w, ctx->ckV, ctx->ckSc, ctx->ckRows, ctx->ckRH, ctx->ck_cap);
+    return hipGetLastError();
+}
+
 hipError_t pod::launch_ckpt_post(pod_ctx *ctx, hipStream_t st)
 {
     hipLaunchKernelGGL(k_ckpt_post, dim3(1), dim3(256), 0, st, ctx->ds, ctx->R2, ctx->pmax * ctx->pmax, ctx->ckR,
@@ -462,18 +530,29 @@ pod_status pod::ckpt_reserve(pod_ctx *ctx, int32_t need)
     if (cap < need) cap = need;
     if (cap > ctx->ck_max) cap = ctx->ck_max;
     const size_t mr = (size_t)ctx->prm.m * ctx->r, r = (size_t)ctx->r, pm2 = (size_t)ctx->pmax * ctx->pmax;
+    const size_t w = (size_t)ctx->prm.w;
     void *nU = nullptr;
-    double *nS = nullptr, *nR = nullptr;
-    int32_t *nM = nullptr;
+    double *nS = nullptr, *nR = nullptr, *nV = nullptr, *nSc = nullptr;
+    int32_t *nM = nullptr, *nRH = nullptr, *nRows = nullptr;
     hipError_t e = hipMalloc(&nU, (size_t)cap * mr * ctx->esz + 16);
     if (e == hipSuccess) e = hipMalloc((void **)&nS, sizeof(double) * cap * r + 16);
     if (e == hipSuccess) e = hipMalloc((void **)&nR, sizeof(double) * cap * pm2 + 16);
     if (e == hipSuccess) e = hipMalloc((void **)&nM, sizeof(int32_t) * 4 * cap + 16);
+    if (w > 0) {
+        if (e == hipSuccess) e = hipMalloc((void **)&nV, sizeof(double) * cap * pm2 + 16);
+        if (e == hipSuccess) e = hipMalloc((void **)&nSc, sizeof(double) * cap * w + 16);
+        if (e == hipSuccess) e = hipMalloc((void **)&nRows, sizeof(int32_t) * cap * w + 16);
+        if (e == hipSuccess) e = hipMalloc((void **)&nRH, sizeof(int32_t) * 2 * cap + 16);
+    }
     if (e != hipSuccess) {
         (void)hipFree(nU);
         (void)hipFree(nS);
         (void)hipFree(nR);
         (void)hipFree(nM);
+        (void)hipFree(nV);
+        (void)hipFree(nSc);
+        (void)hipFree(nRows);
+        (void)hipFree(nRH);
         (void)hipGetLastError();
         if (e != hipErrorOutOfMemory) ctx->failed = 1;
         return (e == hipErrorOutOfMemory) ? POD_ENOMEM : POD_EHIP;
@@ -487,6 +566,13 @@ pod_status pod::ckpt_reserve(pod_ctx *ctx, int32_t need)
         if (e == hipSuccess) e = hipMemcpyAsync(nS, ctx->ckS, sizeof(double) * old * r, hipMemcpyDeviceToDevice, ctx->st);
         if (e == hipSuccess) e = hipMemcpyAsync(nR, ctx->ckR, sizeof(double) * old * pm2, hipMemcpyDeviceToDevice, ctx->st);
         if (e == hipSuccess) e = hipMemcpyAsync(nM, ctx->ckMeta, sizeof(int32_t) * 4 * old, hipMemcpyDeviceToDevice, ctx->st);
+        if (w > 0) {
+            if (e == hipSuccess) e = hipMemcpyAsync(nV, ctx->ckV, sizeof(double) * old * pm2, hipMemcpyDeviceToDevice, ctx->st);
+            if (e == hipSuccess) e = hipMemcpyAsync(nSc, ctx->ckSc, sizeof(double) * old * w, hipMemcpyDeviceToDevice, ctx->st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(nRows, ctx->ckRows, sizeof(int32_t) * old * w, hipMemcpyDeviceToDevice, ctx->st);
+            if (e == hipSuccess) e = hipMemcpyAsync(nRH, ctx->ckRH, sizeof(int32_t) * 2 * old, hipMemcpyDeviceToDevice, ctx->st);
+        }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
     if (e != hipSuccess) {
@@ -497,10 +583,18 @@ pod_status pod::ckpt_reserve(pod_ctx *ctx, int32_t need)
     (void)hipFree(ctx->ckS);
     (void)hipFree(ctx->ckR);
     (void)hipFree(ctx->ckMeta);
+    (void)hipFree(ctx->ckV);
+    (void)hipFree(ctx->ckSc);
+    (void)hipFree(ctx->ckRows);
+    (void)hipFree(ctx->ckRH);
     ctx->ckU = nU;
     ctx->ckS = nS;
     ctx->ckR = nR;
     ctx->ckMeta = nM;
+    ctx->ckV = nV;
+    ctx->ckSc = nSc;
+    ctx->ckRows = nRows;
+    ctx->ckRH = nRH;
     ctx->ck_cap = cap;
     return POD_OK;
 }
@@ -513,7 +607,7 @@ pod_status pod_enable_adjoint(pod_ctx *ctx)
     if (ctx->failed) return POD_EHIP;
     if (ctx->merges > 0 || ctx->pending) return POD_ESTATE;
     const pod_params &p = ctx->prm;
-    if (p.w != 0 || p.r_update != 0 || ctx->pmax > 64) return POD_EINVAL;
+    if (p.r_update != 0 || ctx->pmax > 64) return POD_EINVAL;
     if (ctx->ckU) return POD_OK;
     const int32_t pb = ((ctx->pmax + ctx->r) + 15) & ~15;
     if (pb > 160) return POD_EINVAL;
@@ -532,7 +626,8 @@ pod_status pod_enable_adjoint(pod_ctx *ctx)
     al((void **)&ctx->dsb, sizeof(DevState));
     al((void **)&ctx->partb, sizeof(double) * (size_t)ctx->nblk * pb * pb);
     al((void **)&ctx->Gext, sizeof(double) * (size_t)pb * pb);
-    al((void **)&ctx->adj_ws, sizeof(double) * 10 * pm2);
+    al((void **)&ctx->adj_ws, sizeof(double) * 12 * pm2);
+    if (p.w > 0) al((void **)&ctx->adj_rows, sizeof(double) * (2 * pm2 + (size_t)ctx->pmax));
     al((void **)&ctx->sbar[0], sizeof(double) * r);
     al((void **)&ctx->sbar[1], sizeof(double) * r);
     al((void **)&ctx->lossp, sizeof(double) * ((m + 255) / 256));
@@ -544,14 +639,15 @@ pod_status pod_enable_adjoint(pod_ctx *ctx)
     if (s == POD_OK && ctx->ckU) return POD_OK;
     // the forward run stays usable: release what was taken
     void *ptrs[] = {ctx->dsb, ctx->partb, ctx->Gext, ctx->adj_ws, ctx->sbar[0], ctx->sbar[1], ctx->lossp,
-                    ctx->Wt, ctx->Ubar[0], ctx->Ubar[1], ctx->ckU, ctx->ckS, ctx->ckR, ctx->ckMeta};
+                    ctx->Wt, ctx->Ubar[0], ctx->Ubar[1], ctx->ckU, ctx->ckS, ctx->ckR, ctx->ckMeta,
+                    ctx->adj_rows, ctx->ckV, ctx->ckSc, ctx->ckRows, ctx->ckRH};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     ctx->dsb = nullptr;
     ctx->partb = ctx->Gext = ctx->adj_ws = ctx->sbar[0] = ctx->sbar[1] = ctx->lossp = nullptr;
     ctx->Wt = ctx->Ubar[0] = ctx->Ubar[1] = ctx->ckU = nullptr;
-    ctx->ckS = ctx->ckR = nullptr;
-    ctx->ckMeta = nullptr;
+    ctx->ckS = ctx->ckR = ctx->adj_rows = ctx->ckV = ctx->ckSc = nullptr;
+    ctx->ckMeta = ctx->ckRows = ctx->ckRH = nullptr;
     ctx->ck_cap = 0;
     (void)hipGetLastError();
     if (s == POD_EHIP) ctx->failed = 1;

@@ -80,7 +80,8 @@ void free_all(pod_ctx *ctx)
                     ctx->rho,  ctx->Vt,   ctx->wr,    ctx->rows, ctx->rcnt, ctx->row_log, ctx->rcnt_log,
                     ctx->ws,   ctx->ckU,  ctx->ckS,   ctx->ckR,  ctx->ckMeta, ctx->dsb, ctx->partb, ctx->Gext,
                     ctx->adj_ws, ctx->sbar[0], ctx->sbar[1], ctx->lossp, ctx->Wt, ctx->Ubar[0], ctx->Ubar[1],
-                    ctx->sin_log, ctx->tsplit, ctx->qws, ctx->rho_ort, ctx->wort};
+                    ctx->sin_log, ctx->tsplit, ctx->qws, ctx->rho_ort, ctx->wort,
+                    ctx->ckV,  ctx->ckSc, ctx->ckRH,  ctx->rscale, ctx->adj_rows, ctx->ckRows};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -123,6 +124,7 @@ BlockEigArgs block_eig_args(pod_ctx *ctx, int32_t mode)
     b.Vt = ctx->Vt;
     b.ws = ctx->ws;
     b.ds = ctx->ds;
+    if (mode == 0) b.scales = ctx->rscale;
     return b;
 }
 
@@ -148,6 +150,7 @@ pod_status merge_launch(pod_ctx *ctx, const GemmDesc &gd, const double *sigma2, 
             else if (s != POD_OK) return s;
         }
         POD_HIP(launch_ckpt_pre(ctx, ctx->st));
+        if (ctx->prm.w > 0) POD_HIP(launch_ckpt_rows(ctx, ctx->st));
     }
     // pass 1: G0 = X0^T X0, X0 = [U | A(:, I_c)] gathered on the fly
     POD_HIP(launch_gram_partial(gd, ctx->ds, -1, pm, ctx->part, ctx->nblk, ctx->st));
@@ -377,6 +380,7 @@ pod_status pod::ctx_create(pod_ctx **out, const pod_params *prm, void *stream)
         ALLOC(ctx->rows, int32_t, p.w);
         ALLOC(ctx->rcnt, int32_t, p.w);
         ALLOC(ctx->row_log, int32_t, (size_t)cap_iter * p.w);
+        ALLOC(ctx->rscale, double, (size_t)p.w);
         ALLOC(ctx->rcnt_log, int32_t, (size_t)cap_iter * p.w);
     }
 #undef ALLOC

@@ -53,6 +53,12 @@ struct pod_ctx {
     double *ckS = nullptr;   // Sigma before each merge (cap x r)
     double *ckR = nullptr;   // merge factor R of each merge (cap x pmax^2)
     int32_t *ckMeta = nullptr;  // per merge: rs, g, rank after, valid
+    // row-sampled merges (w > 0): the right factor V_u of the block (cap x pmax^2),
+    // the row scales and the distinct rows (cap x w each) and (r_u, h) per merge (cap x 2)
+    double *ckV = nullptr, *ckSc = nullptr;
+    int32_t *ckRH = nullptr, *ckRows = nullptr;
+    double *rscale = nullptr;    // scales of the last row draw (w), written by the block eigensolver
+    double *adj_rows = nullptr;  // reverse pass of a row-sampled merge: full eigenbasis, eigenvalues, G-bar
     pod::DevState *dsb = nullptr;
     double *partb = nullptr, *Gext = nullptr, *adj_ws = nullptr, *sbar[2] = {nullptr, nullptr}, *lossp = nullptr;
     void *Wt = nullptr, *Ubar[2] = {nullptr, nullptr};
@@ -87,6 +93,8 @@ hipError_t launch_ckpt_pre(pod_ctx *ctx, hipStream_t st);
 // POD_ENOMEM leaves the context usable (the old checkpoints stay).
 pod_status ckpt_reserve(pod_ctx *ctx, int32_t need);
 hipError_t launch_ckpt_post(pod_ctx *ctx, hipStream_t st);
+// row-sampled merges: V_u, the row scales, the rows and (r_u, h) of the merge about to run
+hipError_t launch_ckpt_rows(pod_ctx *ctx, hipStream_t st);
 
 // Batched checkpoints (per-matrix entries in device memory).
 struct CkptArgs {

@@ -280,6 +280,7 @@ struct BlockEigArgs {
     const double *cscale = nullptr;
     double *evals = nullptr;
     int32_t crit = 0;
+    double *scales = nullptr;  // out (mode 0, nullable): the h row scales sqrt(t_hat / (w q))
     double gamma = 0.0;
 };
 hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st);
@@ -302,8 +303,35 @@ struct AdjArgs {
     double *ws;            // 10 pm^2 doubles
     int32_t rs, g, rz;
     double eta;            // gap guard
+    // row-sampled merge (vt set): P = blkdiag(Sigma, V_u), V_u = vt (g x ru, ld pm);
+    // vfull / lam the full eigenbasis (g x g, ld pm) and eigenvalues of G = W^T W;
+    // gbar receives the symmetric adjoint of G (g x g, ld pm)
+    const double *vt = nullptr;
+    int32_t ru = 0;
+    const double *vfull = nullptr, *lam = nullptr;
+    double *gbar = nullptr;
 };
 hipError_t launch_adj_small(const AdjArgs &a, hipStream_t st);
+// Reverse pass of a row-sampled merge: G = W^T W (W = diag(s) A(rows, cols)),
+// its full eigen-decomposition (descending) into vfull (g x g, ld pm) and lam,
+// the first ru columns signed like vt; then, after the small adjoint,
+// dA(rows, cols) += 2 diag(s)^2 A(rows, cols) Gbar.
+struct AdjRowsArgs {
+    const void *A;
+    int32_t a_dtype;
+    int64_t lda;
+    const int32_t *cols, *rows;
+    const double *scales;
+    const double *vt;
+    int32_t g, h, ru, pm;
+    double *vfull, *lam;
+    const double *gbar;
+    void *dA;              // m x n gradient (compute type), ld ldd
+    int64_t ldd;
+    int32_t prec;
+};
+hipError_t launch_adj_rows_eig(const AdjRowsArgs &a, hipStream_t st);
+hipError_t launch_adj_rows_update(const AdjRowsArgs &a, hipStream_t st);
 // Batched reverse-pass launches (one entry per matrix, blockIdx selects it).
 hipError_t launch_adj_small_b(const AdjArgs *arr, int32_t count, hipStream_t st);
 struct ScatterArgs {       // one launch_gemm_tall_scatter of the reverse pass (P <= 64)

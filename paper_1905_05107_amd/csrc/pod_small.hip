@@ -1413,6 +1413,11 @@ __global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
             S[i + j * g] = s;
             S[j + i * g] = s;
         }
+        if (a.scales)
+            for (int rr = threadIdx.x; rr < h; rr += NT) {
+                const double q = (double)a.wr[a.rows[rr]] / Om;
+                a.scales[rr] = sqrt((double)a.rcnt[rr] / ((double)a.w * q));
+            }
     } else {
         for (int idx = threadIdx.x; idx < g * g; idx += NT) {
             const int i = idx % g, j = idx / g;
@@ -1450,6 +1455,105 @@ __global__ __launch_bounds__(512) void k_block_eig(BlockEigArgs a)
         ds->ru = ru;
         ds->p = rs + ru;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse pass of a row-sampled merge (p <= 64, one workgroup): G = W^T W with
+// W = diag(s) A(rows, cols), summed as the forward's block eigensolver sums
+// it, then all g eigenpairs (descending) by the same routines; the first ru
+// eigenvectors take the signs of the forward's right factor vt.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_adj_rows_eig(AdjRowsArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
+        sdots[EIG_NMAX], ssc[8];
+    __shared__ __align__(8) int scl[EIG_NMAX + 8];
+    const int g = a.g, h = a.h, pm = a.pm;
+    double *S = lds, *Y = S + pm * pm, *lu = Y + pm * pm;
+    for (int idx = threadIdx.x; idx < g * g; idx += NT) {
+        const int i = idx % g, j = idx / g;
+        if (i > j) continue;
+        const int64_t ci = a.cols[i], cj = a.cols[j];
+        double sum = 0.0;
+        for (int rr = 0; rr < h; ++rr) {
+            const int64_t row = a.rows[rr];
+            const double sc = a.scales[rr];
+            double di, dj;
+            if (a.a_dtype == POD_F64) {
+                di = reinterpret_cast<const double *>(a.A)[ci * a.lda + row];
+                dj = reinterpret_cast<const double *>(a.A)[cj * a.lda + row];
+            } else {
+                di = (double)reinterpret_cast<const float *>(a.A)[ci * a.lda + row];
+                dj = (double)reinterpret_cast<const float *>(a.A)[cj * a.lda + row];
+            }
+            sum += (sc * di) * (sc * dj);
+        }
+        S[i + j * g] = sum;
+        S[j + i * g] = sum;
+    }
+    __syncthreads();
+    tridiag(S, g, sd, se, stau, spv, ssc);
+    bisect_top(sd, se, g, g, sev, se2, ssc);
+    tri_invit(sd, se, g, sev, g, Y, lu, scl);
+    tridiag_backtransform(S, stau, g, Y, g, sdots);
+    // signs of the first ru columns: those of the forward's factor
+    for (int j = threadIdx.x >> 6; j < g; j += NT / 64) {
+        double d = 0.0;
+        if (j < a.ru)
+            for (int i = threadIdx.x & 63; i < g; i += 64) d += Y[i + j * g] * a.vt[i + j * pm];
+        d = wave_sum(d);
+        const double sg = (d < 0.0) ? -1.0 : 1.0;
+        for (int i = threadIdx.x & 63; i < g; i += 64) a.vfull[i + j * pm] = sg * Y[i + j * g];
+    }
+    for (int i = threadIdx.x; i < g; i += NT) a.lam[i] = sev[i];
+}
+
+hipError_t launch_adj_rows_eig(const AdjRowsArgs &a, hipStream_t st)
+{
+    if (a.pm > SMALL_LDS_P || a.g > a.pm) return hipErrorInvalidValue;
+    const size_t lds = (size_t)(2 * a.pm * a.pm + eig_lu_doubles(a.pm)) * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_adj_rows_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_limit(false));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_adj_rows_eig, dim3(1), dim3(NT), lds, st, a);
+    return hipGetLastError();
+}
+
+// dA(rows[q], cols[j]) += 2 s_q^2 sum_l A(rows[q], cols[l]) Gbar(l, j): one
+// thread per (q, j); the (row, column) pairs are distinct.
+template <typename TC>
+__global__ __launch_bounds__(256) void k_adj_rows_update(AdjRowsArgs a)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.h * a.g) return;
+    const int q = idx % a.h, j = idx / a.h;
+    const int64_t row = a.rows[q];
+    double v = 0.0;
+    for (int l = 0; l < a.g; ++l) {
+        const int64_t cl = a.cols[l];
+        const double x = (a.a_dtype == POD_F64) ? reinterpret_cast<const double *>(a.A)[cl * a.lda + row]
+                                                : (double)reinterpret_cast<const float *>(a.A)[cl * a.lda + row];
+        v = fma(x, a.gbar[l + j * a.pm], v);
+    }
+    const double sc = a.scales[q];
+    TC *d = reinterpret_cast<TC *>(a.dA) + (int64_t)a.cols[j] * a.ldd + row;
+    *d += (TC)(2.0 * sc * sc * v);
+}
+
+hipError_t launch_adj_rows_update(const AdjRowsArgs &a, hipStream_t st)
+{
+    const int n = a.h * a.g;
+    if (n <= 0) return hipSuccess;
+    if (a.prec == POD_F64)
+        hipLaunchKernelGGL(k_adj_rows_update<double>, dim3((n + 255) / 256), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_adj_rows_update<float>, dim3((n + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_block_eig(const BlockEigArgs &a, hipStream_t st)
@@ -1538,7 +1642,11 @@ __device__ __forceinline__ void adj_small_body(const AdjArgs &a)
     __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX], sS[EIG_NMAX],
         sP[EIG_NMAX];
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
-    const int rs = a.rs, p = a.rs + a.g, rz = a.rz, pm = a.pm, pb = a.pb;
+    // p: columns of M = X0 P (the merge factor R is p x p); p0: columns of X0.
+    // Column-only merges: P = diag(Sigma, I), p0 = p.  Row-sampled merges:
+    // P = blkdiag(Sigma, V_u) with V_u = a.vt (g x ru).
+    const bool rowm = a.vt != nullptr;
+    const int rs = a.rs, p = a.rs + (rowm ? a.ru : a.g), p0 = a.rs + a.g, rz = a.rz, pm = a.pm, pb = a.pb;
     const int t = threadIdx.x;
     double *H = lds;                 // R R^T (p x p, ld p), then the reflectors (64 x RL_LD)
     double *Y = H + 64 * RL_LD;      // eigenvectors (p x p, ld p)
@@ -1547,7 +1655,16 @@ __device__ __forceinline__ void adj_small_body(const AdjArgs &a)
     __shared__ double ssde[TRI_SDE];
     const int q2 = pm * pm;
     double *wR = a.ws, *wRi = wR + q2, *wUR = wRi + q2, *wV = wUR + q2, *wZ = wV + q2, *wJ = wZ + q2, *wK = wJ + q2,
-           *wN = wK + q2, *wW = wN + q2, *wT = wW + q2;
+           *wN = wK + q2, *wW = wN + q2, *wT = wW + q2, *wP = wT + q2, *wQ = wP + q2;
+    // P (p0 x p, ld p0) of a row-sampled merge
+    if (rowm)
+        for (int idx = t; idx < p0 * p; idx += NT) {
+            const int i = idx % p0, j = idx / p0;
+            double v = 0.0;
+            if (i < rs && j < rs) v = (i == j) ? a.sig[i] : 0.0;
+            else if (i >= rs && j >= rs) v = a.vt[(i - rs) + (j - rs) * pm];
+            wP[idx] = v;
+        }
     for (int idx = t; idx < p * p; idx += NT) {
         const int i = idx % p, j = idx / p;
         const double v = a.R[i + j * pm];
@@ -1586,11 +1703,28 @@ __device__ __forceinline__ void adj_small_body(const AdjArgs &a)
         for (int l = 0; l <= i; ++l) s += wR[l + i * p] * wUR[l + j * p];
         wV[idx] = s;
     }
-    for (int idx = t; idx < p * rz; idx += NT) {
-        const int i = idx % p, j = idx / p;
-        double s = 0.0;
-        for (int l = 0; l <= i; ++l) s += wRi[l + i * p] * sP[l] * a.Gext[l + (p + j) * pb];
-        wZ[i + j * p] = s;
+    if (!rowm) {
+        for (int idx = t; idx < p * rz; idx += NT) {
+            const int i = idx % p, j = idx / p;
+            double s = 0.0;
+            for (int l = 0; l <= i; ++l) s += wRi[l + i * p] * sP[l] * a.Gext[l + (p + j) * pb];
+            wZ[i + j * p] = s;
+        }
+    } else {
+        // Q = P^T X0^T Ubar (p x rz), then Z = R^-T Q
+        for (int idx = t; idx < p * rz; idx += NT) {
+            const int i = idx % p, j = idx / p;
+            double s = 0.0;
+            for (int l = 0; l < p0; ++l) s += wP[l + i * p0] * a.Gext[l + (p0 + j) * pb];
+            wQ[i + j * p] = s;
+        }
+        __syncthreads();
+        for (int idx = t; idx < p * rz; idx += NT) {
+            const int i = idx % p, j = idx / p;
+            double s = 0.0;
+            for (int l = 0; l <= i; ++l) s += wRi[l + i * p] * wQ[l + j * p];
+            wZ[i + j * p] = s;
+        }
     }
     __syncthreads();
     // J = U_R^T Z (p x rz)
@@ -1637,28 +1771,113 @@ __device__ __forceinline__ void adj_small_body(const AdjArgs &a)
         wW[idx] = s;
     }
     __syncthreads();
-    // T = P R^-1 W1 (the factor of Mbar on X0)
-    for (int idx = t; idx < p * p; idx += NT) {
-        const int r0 = idx % p, c = idx / p;
-        double s = 0.0;
-        for (int l = r0; l < p; ++l) s += wRi[r0 + l * p] * wW[l + c * p];
-        wT[idx] = sP[r0] * s;
+    // T = P R^-1 W1 (the factor of Mbar on X0; p0 x p, ld p0)
+    if (!rowm) {
+        for (int idx = t; idx < p * p; idx += NT) {
+            const int r0 = idx % p, c = idx / p;
+            double s = 0.0;
+            for (int l = r0; l < p; ++l) s += wRi[r0 + l * p] * wW[l + c * p];
+            wT[idx] = sP[r0] * s;
+        }
+    } else {
+        for (int idx = t; idx < p * p; idx += NT) {
+            const int r0 = idx % p, c = idx / p;
+            double s = 0.0;
+            for (int l = r0; l < p; ++l) s += wRi[r0 + l * p] * wW[l + c * p];
+            wQ[idx] = s;
+        }
+        __syncthreads();
+        for (int idx = t; idx < p0 * p; idx += NT) {
+            const int r0 = idx % p0, c = idx / p0;
+            double s = 0.0;
+            for (int l = 0; l < p; ++l) s += wP[r0 + l * p0] * wQ[l + c * p];
+            wT[idx] = s;
+        }
     }
     __syncthreads();
-    // Wt = [T P ; W2 P]
-    for (int idx = t; idx < (p + rz) * p; idx += NT) {
-        const int row = idx % (p + rz), c = idx / (p + rz);
-        double v;
-        if (row < p) v = wT[row + c * p] * sP[c];
-        else v = wV[c + (row - p) * p] / (sS[row - p] * sS[row - p]) * sP[c];
+    if (!rowm) {
+        // Wt = [T P ; W2 P]
+        for (int idx = t; idx < (p + rz) * p; idx += NT) {
+            const int row = idx % (p + rz), c = idx / (p + rz);
+            double v;
+            if (row < p) v = wT[row + c * p] * sP[c];
+            else v = wV[c + (row - p) * p] / (sS[row - p] * sS[row - p]) * sP[c];
+            store_c(a.Wt, a.prec, row + (int64_t)c * pb, v);
+        }
+        // sbar_{t-1,i} = [X0^T X0 T + X0^T Ubar W2]_{ii}
+        for (int i = t; i < rs; i += NT) {
+            double s = 0.0;
+            for (int l = 0; l < p; ++l) s += a.Gext[i + l * pb] * wT[l + i * p];
+            for (int j = 0; j < rz; ++j) s += a.Gext[i + (p + j) * pb] * wV[i + j * p] / (sS[j] * sS[j]);
+            a.sbar_out[i] = s;
+        }
+        return;
+    }
+    // row-sampled merge: Wt = [T P^T ; W2 P^T] ((p0 + rz) x p0), W2(j, l) = Vs(l, j) / s_j^2
+    for (int idx = t; idx < (p0 + rz) * p0; idx += NT) {
+        const int row = idx % (p0 + rz), c = idx / (p0 + rz);
+        double v = 0.0;
+        if (row < p0)
+            for (int l = 0; l < p; ++l) v += wT[row + l * p0] * wP[c + l * p0];
+        else
+            for (int l = 0; l < p; ++l) v += wV[l + (row - p0) * p] / (sS[row - p0] * sS[row - p0]) * wP[c + l * p0];
         store_c(a.Wt, a.prec, row + (int64_t)c * pb, v);
     }
-    // sbar_{t-1,i} = [X0^T X0 T + X0^T Ubar W2]_{ii}
     for (int i = t; i < rs; i += NT) {
         double s = 0.0;
-        for (int l = 0; l < p; ++l) s += a.Gext[i + l * pb] * wT[l + i * p];
-        for (int j = 0; j < rz; ++j) s += a.Gext[i + (p + j) * pb] * wV[i + j * p] / (sS[j] * sS[j]);
+        for (int l = 0; l < p0; ++l) s += a.Gext[i + l * pb] * wT[l + i * p0];
+        for (int j = 0; j < rz; ++j) s += a.Gext[i + (p0 + j) * pb] * wV[i + j * p] / (sS[j] * sS[j]);
         a.sbar_out[i] = s;
+    }
+    // adjoint of V_u: Vbar = [X0^T Mbar](rs:p0, rs:p), X0^T Mbar = Gext(0:p0, :) [T ; W2]
+    const int g = a.g, ru = a.ru;
+    if (ru == 0) {   // no retained direction: V_u is empty and so is its adjoint
+        for (int idx = t; idx < g * g; idx += NT) a.gbar[(idx % g) + (idx / g) * pm] = 0.0;
+        return;
+    }
+    double *wVb = wJ, *wKg = wK, *wG = wN;
+    for (int idx = t; idx < g * ru; idx += NT) {
+        const int i = idx % g, b = idx / g;
+        const int row = rs + i, col = rs + b;
+        double s = 0.0;
+        for (int l = 0; l < p0; ++l) s += a.Gext[row + l * pb] * wT[l + col * p0];
+        for (int j = 0; j < rz; ++j) s += a.Gext[row + (p0 + j) * pb] * wV[col + j * p] / (sS[j] * sS[j]);
+        wVb[i + b * g] = s;
+    }
+    __syncthreads();
+    // K(i, j) = (v_i^T Vbar_j) / (lambda_j - lambda_i) (i != j, j < ru; eta guard), G-bar = V K V^T
+    {
+        const double gl = a.eta * fabs(a.lam[0]);
+        for (int idx = t; idx < g * g; idx += NT) {
+            const int i = idx % g, j = idx / g;
+            double v = 0.0;
+            if (i != j && j < ru) {
+                double dt = 0.0;
+                for (int l = 0; l < g; ++l) dt += a.vfull[l + i * pm] * wVb[l + j * g];
+                const double d = a.lam[j] - a.lam[i];
+                v = (d == 0.0) ? 0.0 : dt * (d / (d * d + gl * gl));
+            }
+            wKg[idx] = v;
+        }
+    }
+    __syncthreads();
+    for (int idx = t; idx < g * g; idx += NT) {   // V K
+        const int i = idx % g, j = idx / g;
+        double s = 0.0;
+        for (int l = 0; l < g; ++l) s += a.vfull[i + l * pm] * wKg[l + j * g];
+        wG[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = t; idx < g * g; idx += NT) {   // (V K) V^T
+        const int i = idx % g, j = idx / g;
+        double s = 0.0;
+        for (int l = 0; l < g; ++l) s += wG[i + l * g] * a.vfull[j + l * pm];
+        wKg[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = t; idx < g * g; idx += NT) {
+        const int i = idx % g, j = idx / g;
+        a.gbar[i + j * pm] = 0.5 * (wKg[i + j * g] + wKg[j + i * g]);
     }
 }
 
