@@ -28,6 +28,7 @@ constexpr int TALL_DYN_LDS = 160 * 1024;   // dynamic LDS limit of the tall kern
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const f64x2 gf64x2;
 
 template <typename TC> struct SrcT {
     const TC *U;          // basis, ld = m
@@ -147,19 +148,29 @@ template <typename TC, int ITEMS> struct Stage {
     }
 
     // a full stage on the fast path (prepare() set fast, rb + RB <= m): vector
-    // loads only
+    // loads only.  On the FP64 path every item issues the same two 16-byte
+    // loads with no branch (an FP32 item's second one repeats its first), and
+    // an FP32 item's four floats stay as raw bits in v[it][0..1] until
+    // store_all widens them: a value used inside a divergent branch would be
+    // waited for there, and with it every load issued before it, the next
+    // stages' prefetches included.
     __device__ __forceinline__ void load_full(int64_t rb)
     {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const int g = (threadIdx.x + 256 * it) % GRP;
             const TC *q = base[it] + rb + 4 * g;
-            if (sizeof(TC) == 8 && ((f32col >> it) & 1u)) {
-                const f32x4 a = *(reinterpret_cast<const f32x4 *>(reinterpret_cast<const float *>(base[it]) + rb) + g);
+            if (sizeof(TC) == 8) {
+                const bool f32 = (f32col >> it) & 1u;
+                const char *b = reinterpret_cast<const char *>(base[it]);
+                const char *q0 = b + (f32 ? 4 : 8) * (rb + 4 * g);
+                const char *q1 = f32 ? q0 : q0 + 16;
+                const f64x2 a = *reinterpret_cast<const gf64x2 *>((uintptr_t)q0);
+                const f64x2 c = *reinterpret_cast<const gf64x2 *>((uintptr_t)q1);
                 v[it][0] = a[0];
                 v[it][1] = a[1];
-                v[it][2] = a[2];
-                v[it][3] = a[3];
+                v[it][2] = c[0];
+                v[it][3] = c[1];
             } else if (sizeof(TC) == 4) {
                 const f32x4 a = *reinterpret_cast<const f32x4 *>(q);
                 v[it][0] = a[0];
@@ -220,7 +231,16 @@ template <typename TC, int ITEMS> struct Stage {
             const int c = idx / GRP, g = idx % GRP;
             const bool live = c < P;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Xs[c * LDSR + 4 * g + q] = live ? v[it][q] : (TC)0;
+            for (int q = 0; q < 4; ++q) {
+                TC x = v[it][q];
+                if (sizeof(TC) == 8) {
+                    // (an FP32 item: float q in half q & 1 of v[it][q >> 1])
+                    const uint64_t w = (uint64_t)__double_as_longlong((double)v[it][q >> 1]);
+                    const float f = __uint_as_float((uint32_t)((q & 1) ? (w >> 32) : w));
+                    x = ((f32col >> it) & 1u) ? (TC)f : x;
+                }
+                Xs[c * LDSR + 4 * g + q] = live ? x : (TC)0;
+            }
         }
     }
 };
@@ -1322,7 +1342,10 @@ __global__ __launch_bounds__(256) void k_gemm_tall_b(const TallArgs *__restrict_
 // ---------------------------------------------------------------------------
 constexpr int T64_WAVES = 8;
 
-template <int KT, int NJ, bool TP>
+typedef __attribute__((address_space(1))) const double gdouble;
+typedef __attribute__((address_space(1))) const uint32_t gu32;
+
+template <int KT, int NJ, bool TP, bool MIX>
 __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64_t m, const DevState *ds, int sel_in,
                                                            int sel_out, const double *__restrict__ T, int ldt,
                                                            double *Yout, double *Yout1, int tri)
@@ -1335,10 +1358,9 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
     s.rs = ds->rs;
     s.g = ds->g;
     if (s.U1 && (ds->it & 1)) s.U = s.U1;
-    const int KI = (pin + 15) >> 4, JO = (pout + 15) >> 4;   // live tiles of T
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // entry 64 q + l of tile (kt, jt) is T(16 kt + 4 q + l / 16, 16 jt + l % 16)
-    const int ntl = TP ? JO * (JO + 1) / 2 : KT * JO;
+    const int ntl = TP ? NJ * (NJ + 1) / 2 : KT * NJ;   // every tile, zero outside pin x pout
     for (int idx = threadIdx.x; idx < ntl * 256; idx += 64 * T64_WAVES) {
         const int t = idx >> 8, e = idx & 255;
         int kt, jt;
@@ -1367,36 +1389,75 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
     for (int64_t rt = (int64_t)blockIdx.x * T64_WAVES + wv; rt < ntile; rt += (int64_t)gridDim.x * T64_WAVES) {
         const int64_t row = 16 * rt + r16;
         const bool rin = row < m;
-        // X^T chunks: X(row, 16 kt + 4 q + l / 16)
+        // X^T chunks: X(row, 16 kt + 4 q + l / 16).  The loads are issued first,
+        // as raw bits, and FP32 values widened afterwards: a value used inside
+        // a branch would be waited for there, one load after another.  A
+        // chunk's columns are all FP64 (left of rs), all FP32 (gathered FP32
+        // columns) or, once, mixed (both loads, the one that does not apply
+        // from a fixed valid address); the first two are wave-uniform branches.
+        // Columns at or beyond pin (a zero table entry) read T(0, 0) and meet
+        // zero rows of the staged T; rows past m read row m - 1 and feed only
+        // output rows that are not stored.
+        const int64_t rowc = rin ? row : m - 1;
         double x[KT][4];
+        uint32_t sel[KT];   // bit q: FP32 column
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
+        for (int kt = 0; kt < KT; ++kt) {
+            sel[kt] = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                x[kt][q] = 0.0;
-                if (kt < KI) {
-                    const uint64_t cpv = cptr[16 * kt + 4 * q + cg];
-                    if (cpv && rin) {
-                        if (cpv & 1u)
-                            x[kt][q] = (double)reinterpret_cast<const float *>(cpv & ~(uint64_t)1)[row];
-                        else
-                            x[kt][q] = reinterpret_cast<const double *>(cpv)[row];
+                const int c0 = 16 * kt + 4 * q;
+                const uint64_t cpv = cptr[c0 + cg];
+                const bool f32 = MIX && (cpv & 1u);
+                const uint64_t a64 = (cpv && !f32) ? cpv + 8 * (uint64_t)rowc : (uint64_t)(uintptr_t)T;
+                if (!MIX || c0 + 3 < s.rs) {
+                    x[kt][q] = *reinterpret_cast<const gdouble *>(a64);
+                } else {
+                    const uint64_t a32 = f32 ? (cpv & ~(uint64_t)1) + 4 * (uint64_t)rowc : (uint64_t)(uintptr_t)T;
+                    if (c0 >= s.rs) {
+                        x[kt][q] = __longlong_as_double((long long)*reinterpret_cast<const gu32 *>(a32));
+                    } else {
+                        const double b64 = *reinterpret_cast<const gdouble *>(a64);
+                        const uint32_t b32 = *reinterpret_cast<const gu32 *>(a32);
+                        x[kt][q] = f32 ? __longlong_as_double((long long)b32) : b64;
                     }
                 }
+                sel[kt] |= f32 ? 1u << q : 0u;
             }
+            // (keeps the address arithmetic of later chunks from being hoisted
+            // here, which would hold every address in registers at once)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (MIX) {
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if ((sel[kt] >> q) & 1u)
+                        x[kt][q] = (double)__uint_as_float((uint32_t)__double_as_longlong(x[kt][q]));
+        }
+        // T's operands are read from LDS anew for every row tile (a base offset
+        // the compiler cannot see through keeps them from being hoisted out of
+        // the row loop into registers)
+        int toff = 0;
+        asm volatile("" : "+s"(toff));
+        const double *tlr = tl + toff;
         v4d acc[NJ];
 #pragma unroll
         for (int jt = 0; jt < NJ; ++jt) acc[jt] = v4d{0.0, 0.0, 0.0, 0.0};
+        // (every tile of the template's shape, with no test of the live widths:
+        // the staged T is zero outside them, so the extra products add zeros,
+        // and a branch here would cost more, in register copies of the
+        // accumulators, than the products it saves)
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
-            if (kt >= KI) continue;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int jt = 0; jt < NJ; ++jt) {
-                    if (jt >= JO || ((TP || tri) && kt > jt)) continue;
+                    if (TP && kt > jt) continue;
                     const int t = TP ? jt * (jt + 1) / 2 + kt : jt * KT + kt;
-                    acc[jt] = mfma16x16x4(tl[256 * t + 64 * q + lane], x[kt][q], acc[jt]);
+                    acc[jt] = mfma16x16x4(tlr[256 * t + 64 * q + lane], x[kt][q], acc[jt]);
                 }
         }
         if (rin) {
@@ -1405,21 +1466,21 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int col = 16 * jt + cg + 4 * v;
-                    if (jt < JO && col < pout) Yout[(int64_t)col * m + row] = acc[jt][v];
+                    if (col < pout) Yout[(int64_t)col * m + row] = acc[jt][v];
                 }
         }
     }
 }
 
-template <int KT, int NJ, bool TP>
-static void tall64_launch(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out, const void *T,
+template <int KT, int NJ, bool TP, bool MIX>
+static void tall64_launch_t(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out, const void *T,
                           int32_t ldt, void *Yout, void *Yout1, int tri, hipStream_t st)
 {
     const SrcT<double> s = make_src<double>(d);
     const size_t lds = (size_t)(TP ? NJ * (NJ + 1) / 2 : KT * NJ) * 256 * sizeof(double);
     static bool attr = false;
     if (lds > 64 * 1024 && !attr) {
-        if (hipFuncSetAttribute((const void *)k_tall64<KT, NJ, TP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        if (hipFuncSetAttribute((const void *)k_tall64<KT, NJ, TP, MIX>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds) != hipSuccess)
             return;   // the launch below then fails and reports the error
         attr = true;
@@ -1430,8 +1491,19 @@ static void tall64_launch(const GemmDesc &d, const DevState *ds, int32_t which_i
     const int64_t ntile = (d.m + 15) / 16;
     const int64_t want = (ntile + 4 * T64_WAVES - 1) / (4 * T64_WAVES);
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * per_cu));
-    hipLaunchKernelGGL((k_tall64<KT, NJ, TP>), dim3(nb), dim3(64 * T64_WAVES), lds, st, s, d.m, ds, which_in,
+    hipLaunchKernelGGL((k_tall64<KT, NJ, TP, MIX>), dim3(nb), dim3(64 * T64_WAVES), lds, st, s, d.m, ds, which_in,
                        which_out, (const double *)T, ldt, (double *)Yout, (double *)Yout1, tri);
+}
+
+// MIX: some columns of the source are FP32 (gathered columns of an FP32 A)
+template <int KT, int NJ, bool TP>
+static void tall64_launch(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out, const void *T,
+                          int32_t ldt, void *Yout, void *Yout1, int tri, hipStream_t st)
+{
+    if (d.gather && d.a_dtype != POD_F64)
+        tall64_launch_t<KT, NJ, TP, true>(d, ds, which_in, which_out, T, ldt, Yout, Yout1, tri, st);
+    else
+        tall64_launch_t<KT, NJ, TP, false>(d, ds, which_in, which_out, T, ldt, Yout, Yout1, tri, st);
 }
 
 template <typename TC, int ITEMS, bool TG, bool TP = false>
