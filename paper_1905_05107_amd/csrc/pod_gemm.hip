@@ -1461,12 +1461,16 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
                 }
         }
         if (rin) {
+            // (the column stride laundered per row tile: the forty column
+            // addresses are not hoisted out of the row loop into registers)
+            int64_t ms = m;
+            asm volatile("" : "+s"(ms));
 #pragma unroll
             for (int jt = 0; jt < NJ; ++jt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int col = 16 * jt + cg + 4 * v;
-                    if (col < pout) Yout[(int64_t)col * m + row] = acc[jt][v];
+                    if (col < pout) Yout[(int64_t)col * ms + row] = acc[jt][v];
                 }
         }
     }
@@ -1642,23 +1646,47 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
     for (int q = 0; q < MT; ++q) acc[q] = AccT{0, 0, 0, 0};
     // A stage: 64 columns x 8 groups = 512 items; U stage: RP columns x 8 groups <= 256 UITEMS items;
     // two register stages in flight (stages sg + 1 and sg + 2 load while sg is on the matrix cores)
-    Stage<TC, 2> sta[2];
+    // A's stage is held in its storage type and widened at the LDS store: a
+    // value converted inside a branch would be waited for there, and with it
+    // the other stage's loads.  Columns past n read column 0 and are stored as
+    // zeros.
+    TA ast[2][2][4];
     Stage<TC, UITEMS> stu[2];
     const TA *Ab = A + c0 * lda;
-    auto loadA = [&](int64_t sg, Stage<TC, 2> &st) {
+    auto loadA = [&](int64_t sg, TA (&st)[2][4]) {
+        const int64_t r0 = sg * RB;
+        const bool full = vec && r0 + RB <= m;   // uniform
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
             const int idx = threadIdx.x + 256 * it;
             const int c = idx / GRP, g = idx % GRP;
-            if (c < ncol) {
-                ColPtr cp;
-                cp.p = Ab + (int64_t)c * lda;
-                cp.f64 = sizeof(TA) == 8;
-                load4<TC>(cp, sg * RB + 4 * g, m, vec, st.v[it]);
+            const TA *p = Ab + (int64_t)((c < ncol) ? c : 0) * lda + r0 + 4 * g;
+            if (full) {
+                if (sizeof(TA) == 4) {
+                    const f32x4 a = *reinterpret_cast<const f32x4 *>(p);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) st[it][q] = (TA)a[q];
+                } else {
+                    const f64x2 a = *reinterpret_cast<const f64x2 *>(p);
+                    const f64x2 b = *reinterpret_cast<const f64x2 *>(p + 2);
+                    st[it][0] = (TA)a[0];
+                    st[it][1] = (TA)a[1];
+                    st[it][2] = (TA)b[0];
+                    st[it][3] = (TA)b[1];
+                }
             } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) st.v[it][q] = (TC)0;
+                for (int q = 0; q < 4; ++q) st[it][q] = (r0 + 4 * g + q < m) ? p[q] : (TA)0;
             }
+        }
+    };
+    auto storeA = [&](const TA (&st)[2][4]) {
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int idx = threadIdx.x + 256 * it;
+            const int c = idx / GRP, g = idx % GRP;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) As[c * LDSR + 4 * g + q] = (c < ncol) ? (TC)st[it][q] : (TC)0;
         }
     };
     stu[0].prepare(su, m, rl, vec);
@@ -1669,7 +1697,7 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         if (s0 + b < s1) {
-            loadA(s0 + b, sta[b]);
+            loadA(s0 + b, ast[b]);
             stu[b].load(su, m, (s0 + b) * RB, rl, vec);
         }
     }
@@ -1689,11 +1717,11 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
         for (int b = 0; b < 2; ++b) {
             if (sg + b < s1) {   // uniform
                 __syncthreads();
-                sta[b].store(As, PCB, PCB);
+                storeA(ast[b]);
                 stu[b].store(Us, RP, rl);
                 __syncthreads();
                 if (sg + b + 2 < s1) {
-                    loadA(sg + b + 2, sta[b]);
+                    loadA(sg + b + 2, ast[b]);
                     stu[b].load(su, m, (sg + b + 2) * RB, rl, vec);
                 }
                 compute();
