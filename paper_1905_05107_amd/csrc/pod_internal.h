@@ -27,6 +27,7 @@ struct DevState {
     int32_t s_empty;    // no drawable column left after the last draw
     int32_t sweeps_total; // Jacobi sweeps summed over merges
     int32_t done;       // batched or device-driven runs: this run stopped (merge-time kernels skip)
+    int32_t tail_done;  // workgroups of the wide merge's tail kernel finished (0 between launches)
     double sin_theta;   // last convergence sine (NaN until the second merge)
     uint64_t wtot;      // total column weight of the last draw
     uint64_t wrow_tot;  // total row weight of the last row draw

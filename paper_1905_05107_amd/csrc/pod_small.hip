@@ -469,18 +469,17 @@ constexpr int TRSM_TILES = TRSM_NT * (TRSM_NT + 1) / 2;
 constexpr size_t TRSM_LDS = (size_t)(TRSM_TILES + TRSM_NT) * 256 * sizeof(double);
 constexpr int TRSM_BATCH = 32;                                   // staging loads in flight per thread
 
-template <int M>
-__global__ __launch_bounds__(256) void k_wide_trsm(SmallArgs a)
+// (NTH threads: NTH / 64 column tiles per workgroup; blk the workgroup's
+// index among those doing this solve; sP: LDS for the column weights, M = 0)
+template <int M, int NTH>
+__device__ __forceinline__ void wide_trsm_body(const SmallArgs &a, int blk, double *lds, double *sP)
 {
-    extern __shared__ double lds[];
-    __shared__ double sP[EIG_NMAX];
     const DevState *ds = a.ds;
-    if (merge_halted(ds)) return;
     const int p = ds->p, pm = a.pmax;
     const int ncol = (M == 0) ? p : ds->rnew;
     const int nt = (p + 15) >> 4;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int J = 4 * blockIdx.x + w;
+    const int J = (NTH / 64) * blk + w;
     const double *Rm = (M == 0) ? a.R1 : a.ws;
     const int ldr = (M == 0) ? pm : p;
     const double *dinv = a.ws + big_dinv_offset(pm);
@@ -488,38 +487,47 @@ __global__ __launch_bounds__(256) void k_wide_trsm(SmallArgs a)
     if (M == 0) {
         const int rs = ds->rs;
         const double *sigma = (ds->it & 1) ? a.sig1 : a.sig0;
-        for (int i = threadIdx.x; i < p; i += 256) sP[i] = (i < rs) ? sigma[i] : (a.sigma2 ? a.sigma2[i - rs] : 1.0);
+        for (int i = threadIdx.x; i < p; i += NTH) sP[i] = (i < rs) ? sigma[i] : (a.sigma2 ? a.sigma2[i - rs] : 1.0);
     }
     // stage R's upper tiles, then the D_I: thread e takes entry e of every
-    // tile, TRSM_BATCH tiles (loads in flight) at a time
+    // (NTH / 256)-th tile from its first, TRSM_BATCH tiles (loads in flight)
+    // at a time
+    constexpr int TS = NTH / 256;   // tiles per pass
     const int ntri = nt * (nt + 1) / 2;
-    const int e = threadIdx.x;
+    const int e = threadIdx.x & 255, toff = threadIdx.x >> 8;
     const int erow = e & 15, ecol = 4 * (e >> 6) + ((e >> 4) & 3);   // (m, k) of entry e in the operand layout
-    int tI = 0, tK = 0;                                               // tile (I, K) of t = t0
-    for (int t0 = 0; t0 < ntri + nt; t0 += TRSM_BATCH) {
+    int tI = 0, tK = 0;                                               // tile (I, K) of t = t0 + toff
+    for (int q = 0; q < toff; ++q)
+        if (++tI > tK) {
+            ++tK;
+            tI = 0;
+        }
+    for (int t0 = 0; t0 < ntri + nt; t0 += TS * TRSM_BATCH) {
         double v[TRSM_BATCH];
         int I = tI, K = tK;
 #pragma unroll
         for (int u = 0; u < TRSM_BATCH; ++u) {
-            const int t = t0 + u;
+            const int t = t0 + TS * u + toff;
             double x = 0.0;
             if (t < ntri) {
                 const int row = 16 * I + erow, col = 16 * K + ecol;
                 if (row < p && col < p && row <= col) x = Rm[row + (size_t)col * ldr];
+            } else if (t < ntri + nt) {
+                x = dinv[256 * (t - ntri) + e];
+            }
+#pragma unroll
+            for (int q = 0; q < TS; ++q)
                 if (++I > K) {
                     ++K;
                     I = 0;
                 }
-            } else if (t < ntri + nt) {
-                x = dinv[256 * (t - ntri) + e];
-            }
             v[u] = x;
         }
         tI = I;
         tK = K;
 #pragma unroll
         for (int u = 0; u < TRSM_BATCH; ++u) {
-            const int t = t0 + u;
+            const int t = t0 + TS * u + toff;
             if (t < ntri + nt) lds[256 * t + e] = v[u];
         }
     }
@@ -571,6 +579,15 @@ __global__ __launch_bounds__(256) void k_wide_trsm(SmallArgs a)
                 store_c(a.Tc, a.prec, row + (size_t)jc * pm, X[I][v]);
             }
         }
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void k_wide_trsm(SmallArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double sP[EIG_NMAX];
+    if (merge_halted(a.ds)) return;
+    wide_trsm_body<M, 256>(a, blockIdx.x, lds, sP);
 }
 
 // Batched: one workgroup per matrix (blockIdx.y), stopped matrices skipped.
@@ -808,11 +825,11 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
 //   k_wide_chol2   G2 = R2^T R2 (one workgroup)
 //   k_wide_mm<0>   R = R2 R1 (one 16 x 16 tile per workgroup)
 //   k_wide_mm<1>   H = R R^T
-//   k_wide_eig     the top r' eigenpairs of H (U_R) and the convergence
-//                  sines (one workgroup); sets rnew and sin_theta
-//   k_wide_trsm<1> Z2 = R2^-1 U_R into Tc (blocked, on the matrix cores)
-//   k_wide_sig     Sigma_new(i) = |U_R(:, i)^T R| and the merge count (one
-//                  workgroup)
+//   k_wide_eig     the top r' eigenpairs of H (U_R) (one workgroup); sets rnew
+//   k_wide_tail    side by side: Z2 = R2^-1 U_R into Tc (blocked, on the
+//                  matrix cores), Sigma_new(i) = |U_R(:, i)^T R| and the
+//                  convergence sine (one workgroup each); then the merge
+//                  count and rank advance
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(512) void k_wide_chol2(SmallArgs a)
 {
@@ -896,22 +913,18 @@ __global__ __launch_bounds__(64) void k_wide_mm(SmallArgs a)
 
 // The top r' = min(r, p, #{lambda_i > max((p u)^2, p u64) lambda_1})
 // eigenpairs of H (S2): tridiagonalisation, multisection, inverse iteration,
-// back-transformation into S3 (p x r'); then the convergence sines against
-// the previous basis.  Sets ds->rnew and ds->sin_theta.
+// back-transformation into S3 (p x r').  Sets ds->rnew.
 __global__ __launch_bounds__(512) void k_wide_eig(SmallArgs a)
 {
     extern __shared__ double lds[];
-    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], sev[EIG_NMAX],
-        ssc[8], ssin[2];
+    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], sev[EIG_NMAX];
     __shared__ __align__(8) int scl[EIG_NMAX + 8];
-    __shared__ double sred[NT / 64];
     DevState *ds = a.ds;
     if (merge_halted(ds)) return;
-    const int p = ds->p, rs = ds->rs;
+    const int p = ds->p;
     const int pm = a.pmax;
-    double *S2 = a.ws + p * p;       // H -> reflectors -> B^T B
+    double *S2 = a.ws + p * p;       // H -> reflectors
     double *S3 = a.ws + 2 * p * p;   // eigenvectors U_R (p x r')
-    const int kk0 = (a.k < rs) ? a.k : rs;
     big_tridiag(S2, p, sd, se, stau);
     const int nv = (a.r < p) ? a.r : p;
     const BigTri bt = big_tri(sd, se, p, lds);   // (the dynamic LDS is free until the convergence test)
@@ -923,8 +936,61 @@ __global__ __launch_bounds__(512) void k_wide_eig(SmallArgs a)
     const int rnew = (sev[0] > 0.0) ? ((nv < nz) ? nv : nz) : 0;
     big_invit(sd, se, p, sev, rnew, S3, a.ws + 3 * pm * pm + pm, lds, scl);
     big_backtransform(S2, stau, p, S3, rnew);
-    // S3 now holds U_R(:, 0:rnew) (p x rnew, ld p)
-    // ---- convergence angle
+    // S3 now holds U_R(:, 0:rnew) (p x rnew, ld p); the convergence sines
+    // follow in k_wide_tail
+    if (threadIdx.x == 0) ds->rnew = rnew;
+}
+
+// Sigma_new(i) = |row i of W = U_R^T R| (i < r'; zero for r' <= i < r), R
+// upper triangular in R2 (ld pmax): the tiles of W dealt to the 8 waves, each
+// wave summing the squares of its tiles' rows into its own partials, the
+// partials added in wave order.  Then the merge count and rank advance.
+constexpr int SIG_NT = 512;
+// (part: SIG_NT / 64 x EIG_NMAX doubles of LDS)
+__device__ __forceinline__ void wide_sig_body(const SmallArgs &a, double *part)
+{
+    const DevState *ds = a.ds;
+    const int p = ds->p, rnew = ds->rnew, it0 = ds->it, pm = a.pmax;
+    const double *S3 = a.ws + 2 * p * p;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int idx = threadIdx.x; idx < (SIG_NT / 64) * EIG_NMAX; idx += SIG_NT) part[idx] = 0.0;
+    __syncthreads();
+    const int nti = (rnew + 15) >> 4, ntj = (p + 15) >> 4;
+    for (int tile = w; tile < nti * ntj; tile += SIG_NT / 64) {
+        const int ti = tile / ntj, tj = tile % ntj;
+        mm_tile_all<EIG_NMAX / 16>(
+            ti, tj, 0, 16 * tj + 16, [&](int i, int k) { return (i < rnew && k < p) ? S3[k + i * p] : 0.0; },
+            [&](int k, int j) { return (k < p && j < p) ? a.R2[k + j * pm] : 0.0; },
+            [&](int i, int j, double v) {
+                // the 16 lanes of a row group hold the 16 columns of its rows
+                const double sq = group_reduce<16, OpSum>(v * v);
+                if ((l & 15) == 0 && i < EIG_NMAX) part[w * EIG_NMAX + i] += sq;
+                (void)j;
+            });
+    }
+    __syncthreads();
+    double *sigma_new = (it0 & 1) ? a.sig0 : a.sig1;
+    for (int i = threadIdx.x; i < a.r; i += SIG_NT) {
+        double v = 0.0;
+        if (i < rnew)
+            for (int q = 0; q < SIG_NT / 64; ++q) v += part[q * EIG_NMAX + i];
+        sigma_new[i] = sqrt(v);
+    }
+}
+
+// The convergence sine of the merge (Sec. "Convergence", largest principal
+// angle between the leading k modes before and after it) from U_R (S3) and,
+// for the mode criterion, the first columns of R (work).  Every thread gets
+// the value.  (lds: 64 RL_LD + 512 + TRI_SDE doubles of LDS)
+__device__ __forceinline__ double wide_sines(const SmallArgs &a, double *lds)
+{
+    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], se2[EIG_NMAX], spv[EIG_NMAX], ssc[8], ssin[2];
+    __shared__ double sred[NT / 64];
+    const DevState *ds = a.ds;
+    const int p = ds->p, rs = ds->rs, rnew = ds->rnew;
+    double *S2 = a.ws + p * p;       // free: B^T B for k > 64
+    const double *S3 = a.ws + 2 * p * p;
+    const int kk0 = (a.k < rs) ? a.k : rs;
     const int kk = (kk0 < rnew) ? kk0 : rnew;
     double sin_max = __builtin_nan("");
     if (kk > 0) {
@@ -993,52 +1059,41 @@ __global__ __launch_bounds__(512) void k_wide_eig(SmallArgs a)
             }
         }
     }
-    if (threadIdx.x == 0) {
-        ds->rnew = rnew;
-        ds->sin_theta = sin_max;
-    }
+    return sin_max;
 }
 
-// Sigma_new(i) = |row i of W = U_R^T R| (i < r'; zero for r' <= i < r), R
-// upper triangular in R2 (ld pmax): the tiles of W dealt to the 8 waves, each
-// wave summing the squares of its tiles' rows into its own partials, the
-// partials added in wave order.  Then the merge count and rank advance.
-constexpr int SIG_NT = 512;
-__global__ __launch_bounds__(SIG_NT) void k_wide_sig(SmallArgs a)
+// The tail of a wide merge in one launch of NT-thread workgroups, whose parts
+// depend only on U_R and the factors and so run side by side: workgroups
+// [0, ntr) solve Z2 = R2^-1 U_R (k_wide_trsm<1>, NT / 64 column tiles each),
+// workgroup ntr computes Sigma_new, workgroup ntr + 1 the convergence sine.
+// The last workgroup to finish (a counter in the device state, reset by it)
+// advances the merge count and rank.
+__global__ __launch_bounds__(NT) void k_wide_tail(SmallArgs a, int ntr)
 {
-    __shared__ double part[SIG_NT / 64][EIG_NMAX];
+    extern __shared__ double lds[];
     DevState *ds = a.ds;
     if (merge_halted(ds)) return;
-    const int p = ds->p, rnew = ds->rnew, it0 = ds->it, pm = a.pmax;
-    const double *S3 = a.ws + 2 * p * p;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    for (int idx = threadIdx.x; idx < (SIG_NT / 64) * EIG_NMAX; idx += SIG_NT) part[idx / EIG_NMAX][idx % EIG_NMAX] = 0.0;
-    __syncthreads();
-    const int nti = (rnew + 15) >> 4, ntj = (p + 15) >> 4;
-    for (int tile = w; tile < nti * ntj; tile += SIG_NT / 64) {
-        const int ti = tile / ntj, tj = tile % ntj;
-        mm_tile_all<EIG_NMAX / 16>(
-            ti, tj, 0, 16 * tj + 16, [&](int i, int k) { return (i < rnew && k < p) ? S3[k + i * p] : 0.0; },
-            [&](int k, int j) { return (k < p && j < p) ? a.R2[k + j * pm] : 0.0; },
-            [&](int i, int j, double v) {
-                // the 16 lanes of a row group hold the 16 columns of its rows
-                const double sq = group_reduce<16, OpSum>(v * v);
-                if ((l & 15) == 0 && i < EIG_NMAX) part[w][i] += sq;
-                (void)j;
-            });
+    const int blk = blockIdx.x;
+    if (blk < ntr) {
+        wide_trsm_body<1, NT>(a, blk, lds, nullptr);
+    } else if (blk == ntr) {
+        wide_sig_body(a, lds);
+    } else {
+        const double sn = wide_sines(a, lds);
+        if (threadIdx.x == 0) ds->sin_theta = sn;
     }
     __syncthreads();
-    double *sigma_new = (it0 & 1) ? a.sig0 : a.sig1;
-    for (int i = threadIdx.x; i < a.r; i += SIG_NT) {
-        double v = 0.0;
-        if (i < rnew)
-            for (int q = 0; q < SIG_NT / 64; ++q) v += part[q][i];
-        sigma_new[i] = sqrt(v);
-    }
     if (threadIdx.x == 0) {
-        ds->rs = rnew;
-        ds->it = it0 + 1;
-        ds->g = 0;
+        __threadfence();
+        const int prev = atomicAdd(&ds->tail_done, 1);
+        if (prev == (int)gridDim.x - 1) {
+            __threadfence();
+            const int it0 = ds->it;
+            ds->rs = ds->rnew;
+            ds->it = it0 + 1;
+            ds->g = 0;
+            ds->tail_done = 0;
+        }
     }
 }
 
@@ -1083,7 +1138,7 @@ hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
     }
     static bool attr_z2 = false;
     if (!attr_z2) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_wide_trsm<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        hipError_t e = hipFuncSetAttribute((const void *)k_wide_tail, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)TRSM_LDS);
         if (e != hipSuccess) return e;
         attr_z2 = true;
@@ -1094,8 +1149,8 @@ hipError_t launch_svd_merge(const SmallArgs &a, hipStream_t st)
     hipLaunchKernelGGL(k_wide_mm<0>, dim3(tiles), dim3(64), 0, st, a);
     hipLaunchKernelGGL(k_wide_mm<1>, dim3(tiles), dim3(64), 0, st, a);
     hipLaunchKernelGGL(k_wide_eig, dim3(1), dim3(NT), lds, st, a);
-    hipLaunchKernelGGL(k_wide_trsm<1>, dim3((unsigned)((max(a.r, 1) + 63) / 64)), dim3(256), TRSM_LDS, st, a);
-    hipLaunchKernelGGL(k_wide_sig, dim3(1), dim3(SIG_NT), 0, st, a);
+    const int ntr = (max(a.r, 1) + 16 * (NT / 64) - 1) / (16 * (NT / 64));   // trsm workgroups
+    hipLaunchKernelGGL(k_wide_tail, dim3((unsigned)(ntr + 2)), dim3(NT), TRSM_LDS, st, a, ntr);
     return hipGetLastError();
 }
 
