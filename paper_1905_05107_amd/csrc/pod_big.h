@@ -350,13 +350,17 @@ __device__ __forceinline__ int big_chol(int n, double thr, FL load, FS store)
     __shared__ int sfl[8];
     const int w = rl_wave(), l = rl_lane();
     double r[BIG_NR][BIG_NS];
+    // (every load issued without a branch, from (0, 0) outside the matrix:
+    // a load inside a divergent branch would be waited for there)
 #pragma unroll
     for (int k = 0; k < BIG_NR; ++k) {
         const int a = big_chol_row(w, k);
 #pragma unroll
         for (int s = 0; s < BIG_NS; ++s) {
             const int c = l + 64 * s;
-            r[k][s] = (a < n && c < n) ? (c < a ? load(c, a) : load(a, c)) : 0.0;
+            const bool in = a < n && c < n;
+            const double v = load(in ? min(a, c) : 0, in ? max(a, c) : 0);
+            r[k][s] = in ? v : 0.0;
         }
     }
     int fail = 0;

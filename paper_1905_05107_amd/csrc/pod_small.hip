@@ -382,9 +382,11 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
         __syncthreads();
     }
     // G1 = P^T G0 P, read where the Cholesky needs it
-    auto g1 = [&](int i, int j) -> double {
-        return a.use_vt ? S[i + j * p] : a.G[i + j * pm] * sP[i] * sP[j];
-    };
+    // (two forms, chosen outside the factorisation, so that its loads are
+    // straight-line code and stay in flight together)
+    auto g1d = [&](int i, int j) -> double { return a.G[i + j * pm] * (sP[i] * sP[j]); };
+    auto g1v = [&](int i, int j) -> double { return S[i + j * p]; };
+    auto g1 = [&](int i, int j) -> double { return a.use_vt ? g1v(i, j) : g1d(i, j); };
     double tr = (threadIdx.x < p) ? g1(threadIdx.x, threadIdx.x) : 0.0;
     tr = wave_sum(tr);
     if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = tr;
@@ -397,12 +399,14 @@ __device__ __forceinline__ void chol_first_body(const SmallArgs &a)
     for (int attempt = 0; attempt < 2 && fail != 2; ++attempt) {
         const double shift = attempt ? (double)p * a.urnd * trace : 0.0;
         const double thr = attempt ? 0.0 : a.urnd * trace * 1e-3;
-        fail = big_chol(
-            p, thr, [&](int i, int j) { return g1(i, j) + ((i == j) ? shift : 0.0); },
-            [&](int r, int c, double v) {
-                Rp[c * (c + 1) / 2 + r] = v;
-                if (r == c) rdiag[c] = 1.0 / v;
-            });
+        auto st = [&](int r, int c, double v) {
+            Rp[c * (c + 1) / 2 + r] = v;
+            if (r == c) rdiag[c] = 1.0 / v;
+        };
+        if (a.use_vt)
+            fail = big_chol(p, thr, [&](int i, int j) { return g1v(i, j) + ((i == j) ? shift : 0.0); }, st);
+        else
+            fail = big_chol(p, thr, [&](int i, int j) { return g1d(i, j) + ((i == j) ? shift : 0.0); }, st);
         if (fail != 1) break;
         if (attempt == 0 && threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
     }
@@ -508,13 +512,15 @@ __device__ __forceinline__ void wide_trsm_body(const SmallArgs &a, int blk, doub
 #pragma unroll
         for (int u = 0; u < TRSM_BATCH; ++u) {
             const int t = t0 + TS * u + toff;
-            double x = 0.0;
-            if (t < ntri) {
-                const int row = 16 * I + erow, col = 16 * K + ecol;
-                if (row < p && col < p && row <= col) x = Rm[row + (size_t)col * ldr];
-            } else if (t < ntri + nt) {
-                x = dinv[256 * (t - ntri) + e];
-            }
+            // (no branch around the load: a load inside a divergent branch is
+            // waited for there, and the batch would not be in flight together)
+            const int row = 16 * I + erow, col = 16 * K + ecol;
+            const bool tri = t < ntri, dg = !tri && t < ntri + nt;
+            const bool ok = tri && row < p && col < p && row <= col;
+            const double *src = tri ? Rm : dinv;
+            const size_t off = ok ? row + (size_t)col * ldr : (dg ? (size_t)256 * (t - ntri) + e : 0);
+            const double ld = src[off];
+            const double x = (ok || dg) ? ld : 0.0;
 #pragma unroll
             for (int q = 0; q < TS; ++q)
                 if (++I > K) {
@@ -834,6 +840,7 @@ __device__ __forceinline__ void svd_merge_rl(const SmallArgs &a)
 __global__ __launch_bounds__(512) void k_wide_chol2(SmallArgs a)
 {
     __shared__ double sred[NT / 64];
+    __shared__ double sdg[TRSM_NT * 256];   // the diagonal 16 x 16 blocks of R2 (column-major), for their inverses
     DevState *ds = a.ds;
     if (merge_halted(ds)) return;
     const int p = ds->p;
@@ -856,6 +863,7 @@ __global__ __launch_bounds__(512) void k_wide_chol2(SmallArgs a)
             [&](int r, int c, double v) {
                 S1[r + c * p] = v;
                 if (c > r) S1[c + r * p] = 0.0;
+                if ((r >> 4) == (c >> 4)) sdg[256 * (r >> 4) + 16 * (c & 15) + (r & 15)] = v;
             });
         if (fail != 1) break;
         if (attempt == 0 && threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)FLAG_SHIFT);
@@ -863,9 +871,12 @@ __global__ __launch_bounds__(512) void k_wide_chol2(SmallArgs a)
     if (fail) {
         if (threadIdx.x == 0) atomicOr(&ds->flags, (int32_t)((fail & 2) ? FLAG_NONFINITE : FLAG_NOTPD));
         for (int idx = threadIdx.x; idx < p * p; idx += NT) S1[idx] = (idx % p == idx / p) ? 1.0 : 0.0;
-        __syncthreads();
+        for (int idx = threadIdx.x; idx < TRSM_NT * 256; idx += NT)
+            sdg[idx] = ((idx & 15) == ((idx >> 4) & 15)) ? 1.0 : 0.0;
     }
-    diag_inv16(p, [&](int i, int k) { return S1[i + k * p]; }, a.ws + big_dinv_offset(pm));
+    __syncthreads();
+    diag_inv16(p, [&](int i, int k) { return sdg[256 * (i >> 4) + 16 * (k & 15) + (i & 15)]; },
+               a.ws + big_dinv_offset(pm));
 }
 
 // R = R2 R1 (M = 0; both upper triangular: tile (I, J) sums k in
