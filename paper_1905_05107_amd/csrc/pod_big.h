@@ -136,7 +136,9 @@ __device__ __forceinline__ void big_tridiag(double *A, int n, double *d, double 
 #pragma unroll
         for (int s = 0; s < BIG_NS; ++s) {
             const int c = l + 64 * s;
-            r[k][s] = (a < n && c < n) ? A[c + (size_t)a * n] : 0.0;   // row a = column a
+            const bool in = a < n && c < n;
+            const double v = A[in ? c + (size_t)a * n : 0];   // row a = column a
+            r[k][s] = in ? v : 0.0;
         }
     }
     __syncthreads();   // every wave has read A before the reflectors overwrite it
@@ -418,8 +420,11 @@ __device__ __forceinline__ int big_chol(int n, double thr, FL load, FS store)
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const double cf = Rs[t][a];   // R(j0 + t, a)
+                        // (slots left of row a's diagonal hold its lower triangle,
+                        // which no later step reads: slot a / 64 = k / 8 onwards)
 #pragma unroll
-                        for (int s = sj; s < BIG_NS; ++s) r[k][s] = fma(-cf, rj[t][s], r[k][s]);
+                        for (int s = (sj > (k >> 3)) ? sj : (k >> 3); s < BIG_NS; ++s)
+                            r[k][s] = fma(-cf, rj[t][s], r[k][s]);
                     }
                 }
             }
