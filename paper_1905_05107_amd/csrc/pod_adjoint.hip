@@ -126,20 +126,34 @@ __global__ __launch_bounds__(256) void k_loss_resid(const TA *__restrict__ A, in
     __shared__ double sw[4];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double u[KM], acc[KM];
+    // (loads without branches, from index 0 where out of range, so that they
+    // are in flight together)
 #pragma unroll
     for (int l = 0; l < KM; ++l) {
-        u[l] = (i < m && l < k) ? (double)U[(int64_t)l * m + i] : 0.0;
+        const bool ok = i < m && l < k;
+        const TC v = U[ok ? (int64_t)l * m + i : 0];
+        u[l] = ok ? (double)v : 0.0;
         acc[l] = 0.0;
     }
     double L = 0.0;
     if (i < m) {
+        // A(i, j) read four columns ahead of its use
+        constexpr int AH = 4;
+        double ah[AH];
+#pragma unroll
+        for (int q = 0; q < AH; ++q) ah[q] = (q < n) ? (double)A[(int64_t)q * lda + i] : 0.0;
         for (int64_t j = 0; j < n; ++j) {
+            const double aij = ah[0];
+#pragma unroll
+            for (int q = 0; q + 1 < AH; ++q) ah[q] = ah[q + 1];
+            const int64_t jn = (j + AH < n) ? j + AH : n - 1;
+            ah[AH - 1] = (double)A[jn * lda + i];
             const double *b = B + j * k;
             double pr = 0.0;
 #pragma unroll
             for (int l = 0; l < KM; ++l)
                 if (l < k) pr += u[l] * b[l];
-            const double R = (double)A[j * lda + i] - pr;
+            const double R = aij - pr;
             dA[j * m + i] = (TC)(2.0 * R);
             L += R * R;
 #pragma unroll

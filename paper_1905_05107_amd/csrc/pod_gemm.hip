@@ -1163,15 +1163,39 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
     auto store_tile = [&](int64_t sg, int rbk, int jc, const AccT &acc) {
         const int64_t row = sg * RB + rbk * 16 + (lane & 15);
         if (row < m) {
+            if (!SCAT) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int col = jc * 16 + acc_row<TC>(lane, v);
-                if (col >= pout) continue;
-                if (!SCAT || col < sc.split) {
-                    Yout[(int64_t)col * m + row] = acc[v];
-                } else {
-                    TC *d = reinterpret_cast<TC *>(sc.D) + (int64_t)sc.cmap[col - sc.split] * sc.ldd + row;
-                    *d += acc[v];
+                for (int v = 0; v < 4; ++v) {
+                    const int col = jc * 16 + acc_row<TC>(lane, v);
+                    if (col < pout) Yout[(int64_t)col * m + row] = acc[v];
+                }
+            } else {
+                // the scattered read-modify-writes: the column map and the old
+                // values are read for all four first, with no branch (entries
+                // that are not scattered read index 0 and D(row, column 0)),
+                // so that the loads are in flight together
+                int ci[4];
+                TC *dst[4];
+                TC old[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int col = jc * 16 + acc_row<TC>(lane, v);
+                    const bool sct = col >= sc.split && col < pout;
+                    ci[v] = sc.cmap[sct ? col - sc.split : 0];
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int col = jc * 16 + acc_row<TC>(lane, v);
+                    const bool sct = col >= sc.split && col < pout;
+                    dst[v] = reinterpret_cast<TC *>(sc.D) + (sct ? (int64_t)ci[v] * sc.ldd : 0) + row;
+                    old[v] = *dst[v];
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int col = jc * 16 + acc_row<TC>(lane, v);
+                    if (col >= pout) continue;
+                    if (col < sc.split) Yout[(int64_t)col * m + row] = acc[v];
+                    else *dst[v] = old[v] + acc[v];
                 }
             }
         }
