@@ -329,14 +329,35 @@ __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const D
     for (int q = 0; q < MAXPW; ++q) acc[q] = AccT{0, 0, 0, 0};
     // two register stages in flight: the loads of stages sg+1 and sg+2 overlap
     // the MFMA work on stage sg
+    // tiles in groups of four whose products alternate (independent chains:
+    // a product that waits for the one before it on the same tile stalls the
+    // matrix core); each tile still sums its k in order.  A wave's live tiles
+    // are a prefix of its slots.
     auto compute = [&]() {
 #pragma unroll
-        for (int q = 0; q < MAXPW; ++q) {
-            if (tI[q] >= 0) {
-                const TC *xa = Xs + (tI[q] * 16 + (lane & 15)) * LDSR + (lane >> 4);
-                const TC *xb = Xs + (tJ[q] * 16 + (lane & 15)) * LDSR + (lane >> 4);
+        for (int q0 = 0; q0 < MAXPW; q0 += 4) {
+            if (q0 + 3 < MAXPW && tI[q0 + 3] >= 0) {
+                const TC *xa[4], *xb[4];
 #pragma unroll
-                for (int k4 = 0; k4 < RB; k4 += 4) acc[q] = mfma16x16x4(xa[k4], xb[k4], acc[q]);
+                for (int u = 0; u < 4; ++u) {
+                    xa[u] = Xs + (tI[q0 + u] * 16 + (lane & 15)) * LDSR + (lane >> 4);
+                    xb[u] = Xs + (tJ[q0 + u] * 16 + (lane & 15)) * LDSR + (lane >> 4);
+                }
+#pragma unroll
+                for (int k4 = 0; k4 < RB; k4 += 4)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[q0 + u] = mfma16x16x4(xa[u][k4], xb[u][k4], acc[q0 + u]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = q0 + u;
+                    if (q < MAXPW && tI[q] >= 0) {
+                        const TC *xa = Xs + (tI[q] * 16 + (lane & 15)) * LDSR + (lane >> 4);
+                        const TC *xb = Xs + (tJ[q] * 16 + (lane & 15)) * LDSR + (lane >> 4);
+#pragma unroll
+                        for (int k4 = 0; k4 < RB; k4 += 4) acc[q] = mfma16x16x4(xa[k4], xb[k4], acc[q]);
+                    }
+                }
             }
         }
     };
