@@ -1746,16 +1746,18 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
             stu[b].load(su, m, (s0 + b) * RB, rl, vec);
         }
     }
+    // (k-chunk outer, mode tiles inner: independent chains alternate; each
+    // tile still sums its k in order)
     auto compute = [&]() {
         const TC *xb = As + (wv * 16 + (lane & 15)) * LDSR + (lane >> 4);
 #pragma unroll
-        for (int q = 0; q < MT; ++q) {
-            if (q * 16 < RP) {
-                const TC *ua = Us + (q * 16 + (lane & 15)) * LDSR + (lane >> 4);
+        for (int k4 = 0; k4 < RB; k4 += 4)
 #pragma unroll
-                for (int k4 = 0; k4 < RB; k4 += 4) acc[q] = mfma16x16x4(ua[k4], xb[k4], acc[q]);
-            }
-        }
+            for (int q = 0; q < MT; ++q)
+                if (q * 16 < RP) {
+                    const TC *ua = Us + (q * 16 + (lane & 15)) * LDSR + (lane >> 4);
+                    acc[q] = mfma16x16x4(ua[k4], xb[k4], acc[q]);
+                }
     };
     for (int64_t sg = s0; sg < s1; sg += 2) {
 #pragma unroll
