@@ -1431,41 +1431,32 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
     __syncthreads();
     const int64_t ntile = (m + 15) >> 4;
     const int r16 = lane & 15, cg = lane >> 4;
-    for (int64_t rt = (int64_t)blockIdx.x * T64_WAVES + wv; rt < ntile; rt += (int64_t)gridDim.x * T64_WAVES) {
+    // one row tile: its X operands (raw bits, FP32 columns widened by widen),
+    // then the products and the stores
+    auto load_tile = [&](int64_t rt, double (&x)[KT][4], uint32_t (&xf)[KT][4], uint32_t (&sel)[KT]) {
         const int64_t row = 16 * rt + r16;
         const bool rin = row < m;
-        // X^T chunks: X(row, 16 kt + 4 q + l / 16).  The loads are issued first,
-        // as raw bits, and FP32 values widened afterwards: a value used inside
-        // a branch would be waited for there, one load after another.  A
-        // chunk's columns are all FP64 (left of rs), all FP32 (gathered FP32
-        // columns) or, once, mixed (both loads, the one that does not apply
-        // from a fixed valid address); the first two are wave-uniform branches.
-        // Columns at or beyond pin (a zero table entry) read T(0, 0) and meet
-        // zero rows of the staged T; rows past m read row m - 1 and feed only
-        // output rows that are not stored.
+        // X^T chunks: X(row, 16 kt + 4 q + l / 16).  Every load is issued with
+        // no branch around it (a load inside a branch, even a wave-uniform one,
+        // is waited for where the branch ends): with FP32 columns in the
+        // source (MIX) both the FP64 and the FP32 read of every element, the
+        // one that does not apply from a fixed valid address, selected and
+        // widened afterwards.  Columns at or beyond pin (a zero table entry)
+        // read T(0, 0) and meet zero rows of the staged T; rows past m read
+        // row m - 1 and feed only output rows that are not stored.
         const int64_t rowc = rin ? row : m - 1;
-        double x[KT][4];
-        uint32_t sel[KT];   // bit q: FP32 column
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
             sel[kt] = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int c0 = 16 * kt + 4 * q;
-                const uint64_t cpv = cptr[c0 + cg];
+                const uint64_t cpv = cptr[16 * kt + 4 * q + cg];
                 const bool f32 = MIX && (cpv & 1u);
                 const uint64_t a64 = (cpv && !f32) ? cpv + 8 * (uint64_t)rowc : (uint64_t)(uintptr_t)T;
-                if (!MIX || c0 + 3 < s.rs) {
-                    x[kt][q] = *reinterpret_cast<const gdouble *>(a64);
-                } else {
+                x[kt][q] = *reinterpret_cast<const gdouble *>(a64);
+                if (MIX) {
                     const uint64_t a32 = f32 ? (cpv & ~(uint64_t)1) + 4 * (uint64_t)rowc : (uint64_t)(uintptr_t)T;
-                    if (c0 >= s.rs) {
-                        x[kt][q] = __longlong_as_double((long long)*reinterpret_cast<const gu32 *>(a32));
-                    } else {
-                        const double b64 = *reinterpret_cast<const gdouble *>(a64);
-                        const uint32_t b32 = *reinterpret_cast<const gu32 *>(a32);
-                        x[kt][q] = f32 ? __longlong_as_double((long long)b32) : b64;
-                    }
+                    xf[kt][q] = *reinterpret_cast<const gu32 *>(a32);
                 }
                 sel[kt] |= f32 ? 1u << q : 0u;
             }
@@ -1473,14 +1464,19 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
             // here, which would hold every address in registers at once)
             __builtin_amdgcn_sched_barrier(0);
         }
+    };
+    auto widen = [&](double (&x)[KT][4], const uint32_t (&xf)[KT][4], const uint32_t (&sel)[KT]) {
         if (MIX) {
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if ((sel[kt] >> q) & 1u)
-                        x[kt][q] = (double)__uint_as_float((uint32_t)__double_as_longlong(x[kt][q]));
+                    x[kt][q] = ((sel[kt] >> q) & 1u) ? (double)__uint_as_float(xf[kt][q]) : x[kt][q];
         }
+    };
+    auto mma_store = [&](int64_t rt, const double (&x)[KT][4]) {
+        const int64_t row = 16 * rt + r16;
+        const bool rin = row < m;
         // T's operands are read from LDS anew for every row tile (a base offset
         // the compiler cannot see through keeps them from being hoisted out of
         // the row loop into registers)
@@ -1518,6 +1514,15 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
                     if (col < pout) Yout[(int64_t)col * ms + row] = acc[jt][v];
                 }
         }
+    };
+    const int64_t stride = (int64_t)gridDim.x * T64_WAVES;
+    int64_t rt = (int64_t)blockIdx.x * T64_WAVES + wv;
+    for (; rt < ntile; rt += stride) {
+        double x[KT][4];
+        uint32_t xf[KT][4], sel[KT];
+        load_tile(rt, x, xf, sel);
+        widen(x, xf, sel);
+        mma_store(rt, x);
     }
 }
 
