@@ -127,7 +127,7 @@ __device__ __forceinline__ void load4(const ColPtr &cp, int64_t row, int64_t lim
 // loads of the stages in flight are not waited for until their store.  Items
 // beyond the P columns point at column 0 and are replaced by zeros at the
 // store.
-template <typename TC, int ITEMS> struct Stage {
+template <typename TC, int ITEMS, int NTH = 256> struct Stage {
     TC v[ITEMS][4];
     const TC *base[ITEMS];
     uint32_t f32col;   // bit it: item it reads an FP32 column while TC is double
@@ -139,7 +139,7 @@ template <typename TC, int ITEMS> struct Stage {
         f32col = 0;
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const int idx = threadIdx.x + 256 * it;
+            const int idx = threadIdx.x + NTH * it;
             const int c = idx / GRP;
             const ColPtr cp = col_ptr<TC>(s, m, (c < P) ? c : 0);
             base[it] = reinterpret_cast<const TC *>(cp.p);
@@ -158,7 +158,7 @@ template <typename TC, int ITEMS> struct Stage {
     {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const int g = (threadIdx.x + 256 * it) % GRP;
+            const int g = (threadIdx.x + NTH * it) % GRP;
             const TC *q = base[it] + rb + 4 * g;
             if (sizeof(TC) == 8) {
                 const bool f32 = (f32col >> it) & 1u;
@@ -196,7 +196,7 @@ template <typename TC, int ITEMS> struct Stage {
         }
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const int idx = threadIdx.x + 256 * it;
+            const int idx = threadIdx.x + NTH * it;
             const int c = idx / GRP, g = idx % GRP;
             if (c < P) {
                 const ColPtr cp = col_ptr<TC>(s, m, c);
@@ -212,7 +212,7 @@ template <typename TC, int ITEMS> struct Stage {
     {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const int idx = threadIdx.x + 256 * it;
+            const int idx = threadIdx.x + NTH * it;
             const int c = idx / GRP, g = idx % GRP;
             if (c < PP) {
                 const bool live = c < P;
@@ -221,13 +221,13 @@ template <typename TC, int ITEMS> struct Stage {
             }
         }
     }
-    // every item written (the LDS stage holds all ITEMS * 256 / GRP columns):
+    // every item written (the LDS stage holds all ITEMS * NTH / GRP columns):
     // no branch between the loads and the stores
     __device__ __forceinline__ void store_all(TC *Xs, int P) const
     {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const int idx = threadIdx.x + 256 * it;
+            const int idx = threadIdx.x + NTH * it;
             const int c = idx / GRP, g = idx % GRP;
             const bool live = c < P;
 #pragma unroll
@@ -289,9 +289,12 @@ template <typename TC> __host__ __device__ SrcT<TC> make_src(const GemmDesc &d)
 // per wave; 5 items per thread).
 constexpr int ITEMS64 = 2;
 constexpr int MAXPW160 = 14, ITEMS160 = 5;
+// FP64: 8 waves per workgroup (7 tile pairs and 3 items each), whose smaller
+// accumulator and stage sets leave room for two waves per SIMD
+constexpr int MAXPW160_8 = 7, ITEMS160_8 = 3;
 constexpr int PMAX_WIDE = 160;
 
-template <typename TC, int MAXPW, int ITEMS>
+template <typename TC, int MAXPW, int ITEMS, int NWV = 4>
 __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const DevState *ds, int which_p, int pmax,
                                                   double *__restrict__ part, int nblk, int vec, int bid)
 {
@@ -312,7 +315,7 @@ __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const D
     int tI[MAXPW], tJ[MAXPW];
 #pragma unroll
     for (int q = 0; q < MAXPW; ++q) {
-        int pr = wv + 4 * q, I = 0;
+        int pr = wv + NWV * q, I = 0;
         tI[q] = -1;
         tJ[q] = -1;
         if (pr < npairs) {
@@ -361,7 +364,7 @@ __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const D
             }
         }
     };
-    Stage<TC, ITEMS> sa, sb;
+    Stage<TC, ITEMS, 64 * NWV> sa, sb;
     sa.prepare(s, m, P, vec);
     sb.fast = sa.fast;
     sb.f32col = sa.f32col;
@@ -577,11 +580,11 @@ __device__ __forceinline__ void gram_direct_body(SrcT<TC> s, int64_t m, const De
     }
 }
 
-template <typename TC, int MAXPW, int ITEMS>
-__global__ __launch_bounds__(256) void k_gram_partial(SrcT<TC> s, int64_t m, const DevState *ds, int which_p,
+template <typename TC, int MAXPW, int ITEMS, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_gram_partial(SrcT<TC> s, int64_t m, const DevState *ds, int which_p,
                                                       int pmax, double *__restrict__ part, int nblk, int vec)
 {
-    gram_partial_body<TC, MAXPW, ITEMS>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
+    gram_partial_body<TC, MAXPW, ITEMS, NWV>(s, m, ds, which_p, pmax, part, nblk, vec, blockIdx.x);
 }
 
 // 8 waves per workgroup (two per SIMD at one workgroup per CU).
@@ -1056,15 +1059,15 @@ static void tall_bf16_direct_launch(const SrcT<float> &s, int64_t m, const DevSt
                        which_out, Tb, KP, JP, (float *)Yout, (float *)Yout1, vout, tri);
 }
 
-template <typename TC, int MAXPW, int ITEMS>
+template <typename TC, int MAXPW, int ITEMS, int NWV>
 static void gram_launch(const GemmDesc &d, const DevState *ds, int32_t which_p, int32_t pmax, double *part,
                         int32_t nblk, hipStream_t st)
 {
     const SrcT<TC> s = make_src<TC>(d);
-    // the stage holds every item's column (ITEMS * 256 / GRP >= pmax)
-    const size_t lds = (size_t)(ITEMS * 256 / GRP) * LDSR * sizeof(TC);
-    hipLaunchKernelGGL((k_gram_partial<TC, MAXPW, ITEMS>), dim3(nblk), dim3(256), lds, st, s, d.m, ds, which_p, pmax,
-                       part, nblk, (int)vec_ok(s, d.m));
+    // the stage holds every item's column (ITEMS * 64 NWV / GRP >= pmax)
+    const size_t lds = (size_t)(ITEMS * 64 * NWV / GRP) * LDSR * sizeof(TC);
+    hipLaunchKernelGGL((k_gram_partial<TC, MAXPW, ITEMS, NWV>), dim3(nblk), dim3(64 * NWV), lds, st, s, d.m, ds,
+                       which_p, pmax, part, nblk, (int)vec_ok(s, d.m));
 }
 
 hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t which_p, int32_t pmax, double *part,
@@ -1085,7 +1088,7 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
                                which_p, pmax, part, nblk, vec);
     } else if (d.prec == POD_F64) {
         if (wide) {
-            gram_launch<double, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
+            gram_launch<double, MAXPW160_8, ITEMS160_8, 8>(d, ds, which_p, pmax, part, nblk, st);
         } else {
             const SrcT<double> s = make_src<double>(d);
             hipLaunchKernelGGL(k_gram_direct<double>, dim3(nblk), dim3(512), GD_LDS, st, s, d.m, ds, which_p, pmax,
@@ -1093,7 +1096,7 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
         }
     } else {
         if (wide) {
-            gram_launch<float, MAXPW160, ITEMS160>(d, ds, which_p, pmax, part, nblk, st);
+            gram_launch<float, MAXPW160, ITEMS160, 4>(d, ds, which_p, pmax, part, nblk, st);
         } else {
             const SrcT<float> s = make_src<float>(d);
             hipLaunchKernelGGL(k_gram_direct<float>, dim3(nblk), dim3(512), GD_LDS, st, s, d.m, ds, which_p, pmax,
