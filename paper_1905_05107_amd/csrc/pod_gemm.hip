@@ -280,17 +280,17 @@ template <typename TC> __host__ __device__ SrcT<TC> make_src(const GemmDesc &d)
 
 // ---------------------------------------------------------------------------
 // Partial Grams.  Workgroup b owns stages [ns b / nblk, ns (b+1) / nblk) of
-// the ns = ceil(m / 32) row stages; each of its 4 waves accumulates a fixed
+// the ns = ceil(m / 32) row stages; each of its NWV waves accumulates a fixed
 // set of the upper-triangular 16x16 tiles (I <= J).  The tile is written (and
 // mirrored) to part[b] (pmax x pmax, FP64); the reduction reads only P x P.
 // ---------------------------------------------------------------------------
-// Width classes: pmax <= 64 (10 tiles over 4 waves: 3 per wave; a stage is
-// 64 columns x 8 groups = 2 items per thread) and pmax <= 160 (55 tiles: 14
-// per wave; 5 items per thread).
+// Width classes of the staged kernels: pmax <= 64 (a stage is 64 columns x 8
+// groups = 2 items per thread of 256) and pmax <= 160 (5 items per thread of
+// 256).  The wide Gram runs 8 waves per workgroup (55 tiles: 7 per wave; 3
+// items per thread of 512), whose accumulator and stage sets leave room for
+// two waves per SIMD.
 constexpr int ITEMS64 = 2;
-constexpr int MAXPW160 = 14, ITEMS160 = 5;
-// FP64: 8 waves per workgroup (7 tile pairs and 3 items each), whose smaller
-// accumulator and stage sets leave room for two waves per SIMD
+constexpr int ITEMS160 = 5;
 constexpr int MAXPW160_8 = 7, ITEMS160_8 = 3;
 constexpr int PMAX_WIDE = 160;
 
@@ -1096,7 +1096,7 @@ hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t wh
         }
     } else {
         if (wide) {
-            gram_launch<float, MAXPW160, ITEMS160, 4>(d, ds, which_p, pmax, part, nblk, st);
+            gram_launch<float, MAXPW160_8, ITEMS160_8, 8>(d, ds, which_p, pmax, part, nblk, st);
         } else {
             const SrcT<float> s = make_src<float>(d);
             hipLaunchKernelGGL(k_gram_direct<float>, dim3(nblk), dim3(512), GD_LDS, st, s, d.m, ds, which_p, pmax,
