@@ -237,8 +237,9 @@ pod_status pod_set_indices(pod_ctx *ctx, int32_t iter, const int32_t *cols, cons
                            const int32_t *rows, const int32_t *row_counts, int32_t h);
 
 /* ---------------------------------------------------------------------------
- * Reverse mode through the merge chain of Alg. 1 (ICS, and ICRS with rows:
- * w > 0; r_update = 0, merge width <= 64).  Outputs differentiated: the first
+ * Reverse mode through the merge chain of Alg. 1 (ICS with merge widths up to
+ * 160 and p + r <= 208; ICRS with rows, w > 0, merge width <= 64; r_update =
+ * 0).  Outputs differentiated: the first
  * k merged modes and singular values (U_k, Sigma_k) as pod_get_basis returns
  * them (before the final step); the sampled columns and rows and the row
  * scales are constants (draws and quantised weights are piecewise constant in
@@ -256,8 +257,9 @@ pod_status pod_set_indices(pod_ctx *ctx, int32_t iter, const int32_t *cols, cons
 /* Keep what the reverse pass needs: per merge the starting basis (m x r) and
  * Sigma, and the p x p merge factor.  Call after pod_init, before the first
  * pod_sample; with rows also V_u, the rows and the row scales of each merge.
- * POD_EINVAL for truncated blocks (r_update > 0) or a merge width above 64;
- * POD_ESTATE after a draw. */
+ * POD_EINVAL for truncated blocks (r_update > 0), for row draws with a merge
+ * width above 64, or when the merge width plus r exceeds 208 (the Gram of
+ * [U | A(:, I) | Ubar] of a reverse step); POD_ESTATE after a draw. */
 pod_status pod_enable_adjoint(pod_ctx *ctx);
 
 /* dA (device, m x n, ld m, compute type) += d<dU, U_k> + <dsigma, Sigma_k> / dA

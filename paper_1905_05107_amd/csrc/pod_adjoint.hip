@@ -4,7 +4,8 @@
 // basis and Sigma it started from and the merge factor R (small); the
 // reverse pass recomputes the rest: per merge one Gram pass over
 // [U_{t-1} | A(:, I_t) | Ubar_t], the small FP64 adjoint of the truncated thin
-// SVD (k_adj_small), and one pass writing Ubar_{t-1} and adding the adjoint of
+// SVD (k_adj_small; for merges wider than 64 columns k_adj_wide_eig and the
+// k_adj_wide_step launches), and one pass writing Ubar_{t-1} and adding the adjoint of
 // the sampled columns to dA(:, I_t).
 #include <math.h>
 
@@ -270,7 +271,8 @@ pod_status reverse_merges(pod_ctx *ctx, void *dA)
             aa.lam = ra.lam;
             aa.gbar = ctx->adj_rows + (size_t)pm * pm;
         }
-        A_HIP(launch_adj_small(aa, ctx->st));
+        if (ctx->pmax > SMALL_LDS_P) A_HIP(launch_adj_wide(aa, ctx->st));
+        else A_HIP(launch_adj_small(aa, ctx->st));
         A_HIP(launch_gemm_tall_scatter(gd, ctx->dsb, Pext, P, Pext, P, ctx->Wt, ctx->pb, ctx->Ubar[cur ^ 1], rs,
                                        ctx->col_log + off[t], dA, p.m, ctx->st));
         // the part of dA(rows, cols) through G = W^T W
@@ -621,10 +623,13 @@ pod_status pod_enable_adjoint(pod_ctx *ctx)
     if (ctx->failed) return POD_EHIP;
     if (ctx->merges > 0 || ctx->pending) return POD_ESTATE;
     const pod_params &p = ctx->prm;
-    if (p.r_update != 0 || ctx->pmax > 64) return POD_EINVAL;
+    // row-sampled merges: p <= 64; column draws: p <= 160, p + r <= 208
+    if (p.r_update != 0 || (p.w > 0 && ctx->pmax > SMALL_LDS_P)) return POD_EINVAL;
     if (ctx->ckU) return POD_OK;
-    const int32_t pb = ((ctx->pmax + ctx->r) + 15) & ~15;
-    if (pb > 160) return POD_EINVAL;
+    // widest reverse-step block [U | A(:, I) | Ubar]: r + min(c, n) + r columns
+    const int64_t cmax = (p.c < p.n) ? p.c : p.n;
+    const int32_t pb = (int32_t)(((2 * (int64_t)ctx->r + cmax) + 15) & ~15);
+    if (pb > 208) return POD_EINVAL;
     ctx->pb = pb;
     // checkpoints for about twice the merges a run takes when every draw is
     // distinct (n / c); later merges grow them (ckpt_reserve)
@@ -640,7 +645,7 @@ pod_status pod_enable_adjoint(pod_ctx *ctx)
     al((void **)&ctx->dsb, sizeof(DevState));
     al((void **)&ctx->partb, sizeof(double) * (size_t)ctx->nblk * pb * pb);
     al((void **)&ctx->Gext, sizeof(double) * (size_t)pb * pb);
-    al((void **)&ctx->adj_ws, sizeof(double) * 12 * pm2);
+    al((void **)&ctx->adj_ws, sizeof(double) * ((ctx->pmax > SMALL_LDS_P) ? adj_wide_ws_doubles(ctx->pmax) : 12 * pm2));
     if (p.w > 0) al((void **)&ctx->adj_rows, sizeof(double) * (2 * pm2 + (size_t)ctx->pmax));
     al((void **)&ctx->sbar[0], sizeof(double) * r);
     al((void **)&ctx->sbar[1], sizeof(double) * r);

@@ -293,6 +293,12 @@ constexpr int ITEMS64 = 2;
 constexpr int ITEMS160 = 5;
 constexpr int MAXPW160_8 = 7, ITEMS160_8 = 3;
 constexpr int PMAX_WIDE = 160;
+// The reverse pass's Gram of [U | A(:, I) | Ubar] and its transform from that
+// block reach p + r <= 208 columns (13 tiles: 91 tile pairs, 12 per wave of 8;
+// 4 items per thread of 512 stage 256 columns); its transform stages 7 items
+// per thread of 256 (224 columns) and reads T from device memory.
+constexpr int PMAX_ADJ = 208;
+constexpr int MAXPW208_8 = 12, ITEMS208_8 = 4, ITEMS224 = 7;
 
 template <typename TC, int MAXPW, int ITEMS, int NWV = 4>
 __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const DevState *ds, int which_p, int pmax,
@@ -1066,6 +1072,13 @@ static void gram_launch(const GemmDesc &d, const DevState *ds, int32_t which_p, 
     const SrcT<TC> s = make_src<TC>(d);
     // the stage holds every item's column (ITEMS * 64 NWV / GRP >= pmax)
     const size_t lds = (size_t)(ITEMS * 64 * NWV / GRP) * LDSR * sizeof(TC);
+    if (lds > 64 * 1024) {
+        // (should this fail, the launch below fails and reports the error)
+        static bool attr = false;
+        if (!attr)
+            attr = hipFuncSetAttribute((const void *)k_gram_partial<TC, MAXPW, ITEMS, NWV>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+    }
     hipLaunchKernelGGL((k_gram_partial<TC, MAXPW, ITEMS, NWV>), dim3(nblk), dim3(64 * NWV), lds, st, s, d.m, ds,
                        which_p, pmax, part, nblk, (int)vec_ok(s, d.m));
 }
@@ -1073,10 +1086,14 @@ static void gram_launch(const GemmDesc &d, const DevState *ds, int32_t which_p, 
 hipError_t launch_gram_partial(const GemmDesc &d, const DevState *ds, int32_t which_p, int32_t pmax, double *part,
                                int32_t nblk, hipStream_t st)
 {
-    if (pmax > PMAX_WIDE) return hipErrorInvalidValue;
+    if (pmax > PMAX_ADJ) return hipErrorInvalidValue;
     ProfScope ps(POD_K_GRAM, st);
     const bool wide = pmax > 64;
-    if (d.prec == POD_BF16_REFINE) {
+    if (pmax > PMAX_WIDE) {
+        if (d.prec == POD_F64) gram_launch<double, MAXPW208_8, ITEMS208_8, 8>(d, ds, which_p, pmax, part, nblk, st);
+        else if (d.prec == POD_F32) gram_launch<float, MAXPW208_8, ITEMS208_8, 8>(d, ds, which_p, pmax, part, nblk, st);
+        else return hipErrorInvalidValue;
+    } else if (d.prec == POD_BF16_REFINE) {
         if (d.a_dtype != POD_F32) return hipErrorInvalidValue;
         const SrcT<float> s = make_src<float>(d);
         const int vec = (int)vec_ok(s, d.m);
@@ -1271,18 +1288,38 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
             compute_lds(sg);
             return;
         }
-        for (int tile = wv; tile < ntile; tile += 4) {
-            const int rbk = tile % (RB / 16), jc = tile / (RB / 16);
-            AccT acc = AccT{0, 0, 0, 0};
-            const TC *xb = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
-            // T read from device memory (L2 resident), zero outside pin x pout
-            const int jj = jc * 16 + (lane & 15);
-            const TC *ta = T + (lane >> 4) + (int64_t)jj * ldt;
-            for (int k4 = 0; k4 < PI; k4 += 4) {
-                const TC tv = (jj < pout && k4 + (lane >> 4) < pin) ? ta[k4] : (TC)0;
-                acc = mfma16x16x4(tv, xb[k4 * LDSR], acc);
+        // T read from device memory (L2 resident), zero outside pin x pout
+        // (lanes past pin or pout load an element inside T and drop it: no
+        // branch around the loads); the wave's tiles wv, wv + 4, ... in
+        // groups of four with independent accumulators, each tile summing k in
+        // order
+        for (int t0 = wv; t0 < ntile; t0 += 16) {
+            AccT acc[4];
+            const TC *xb[4], *ta[4];
+            bool ok[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int tile = t0 + 4 * u;
+                const int rbk = tile % (RB / 16), jc = tile / (RB / 16);
+                const int jj = jc * 16 + (lane & 15);
+                ok[u] = tile < ntile && jj < pout;
+                acc[u] = AccT{0, 0, 0, 0};
+                xb[u] = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
+                ta[u] = T + (lane >> 4) + (int64_t)(ok[u] ? jj : 0) * ldt;
             }
-            store_tile(sg, rbk, jc, acc);
+            for (int k4 = 0; k4 < PI; k4 += 4) {
+                const bool kin = k4 + (lane >> 4) < pin;
+                TC tv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) tv[u] = ta[u][kin ? k4 : 0];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] = mfma16x16x4((ok[u] && kin) ? tv[u] : (TC)0, xb[u][k4 * LDSR], acc[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int tile = t0 + 4 * u;
+                if (tile < ntile) store_tile(sg, tile % (RB / 16), tile / (RB / 16), acc[u]);
+            }
         }
     };
     Stage<TC, ITEMS> sa, sb;
@@ -1345,6 +1382,16 @@ __global__ __launch_bounds__(256) void k_gemm_tall_scatter(SrcT<TC> s, int64_t m
                                                            int ldt, TC *__restrict__ Yout, TallScatter sc, int vec)
 {
     gemm_tall_body<TC, ITEMS, false, true>(s, m, ds, sel_in, sel_out, pmax_in, 0, T, ldt, Yout, nullptr, vec,
+                                           blockIdx.x, gridDim.x, 0, sc);
+}
+
+// The same with T read from device memory (inputs up to PMAX_ADJ columns).
+template <typename TC, int ITEMS>
+__global__ __launch_bounds__(256) void k_gemm_tall_scatter_g(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
+                                                           int sel_out, int pmax_in, const TC *__restrict__ T,
+                                                           int ldt, TC *__restrict__ Yout, TallScatter sc, int vec)
+{
+    gemm_tall_body<TC, ITEMS, true, true>(s, m, ds, sel_in, sel_out, pmax_in, 0, T, ldt, Yout, nullptr, vec,
                                            blockIdx.x, gridDim.x, 0, sc);
 }
 
@@ -1920,7 +1967,26 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
 {
     const int PI = (pin_max + 15) & ~15, PO = (pout_max + 15) & ~15;
     const size_t esz = (d.prec == POD_F64) ? 8 : 4;
-    if (PI > PMAX_WIDE || PO > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS) return hipErrorInvalidValue;
+    if (PI > PMAX_ADJ || PO > PMAX_WIDE) return hipErrorInvalidValue;
+    if (PI > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS) {
+        // T too large for LDS: staged X of up to 224 columns, T from device memory
+        const unsigned nb = (unsigned)tall_blocks(d.m);
+        const TallScatter sc{split, cmap, D, ldd};
+        const int CW = ITEMS224 * 256 / GRP;
+        const size_t lds = (size_t)CW * LDSR * esz;
+        if (d.prec == POD_F64) {
+            const SrcT<double> s = make_src<double>(d);
+            hipLaunchKernelGGL((k_gemm_tall_scatter_g<double, ITEMS224>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
+                               which_in, which_out, CW, (const double *)T, ldt, (double *)Yout, sc,
+                               (int)vec_ok(s, d.m));
+        } else {
+            const SrcT<float> s = make_src<float>(d);
+            hipLaunchKernelGGL((k_gemm_tall_scatter_g<float, ITEMS224>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
+                               which_in, which_out, CW, (const float *)T, ldt, (float *)Yout, sc,
+                               (int)vec_ok(s, d.m));
+        }
+        return hipGetLastError();
+    }
     if (PI <= 64 && PO > 64) return hipErrorInvalidValue;   // the narrow class holds 4 column tiles
     const unsigned nb = (unsigned)tall_blocks(d.m);
     const TallScatter sc{split, cmap, D, ldd};

@@ -301,7 +301,7 @@ struct AdjArgs {
     double *sbar_out;      // adjoint of Sigma_{t-1} (rs)
     void *Wt;              // out: ((p + rz) x p, ld pb, compute type)
     int32_t prec;
-    double *ws;            // 10 pm^2 doubles
+    double *ws;            // 12 pm^2 doubles (adj_wide_ws_doubles(pm) for wide merges)
     int32_t rs, g, rz;
     double eta;            // gap guard
     // row-sampled merge (vt set): P = blkdiag(Sigma, V_u), V_u = vt (g x ru, ld pm);
@@ -313,6 +313,15 @@ struct AdjArgs {
     double *gbar = nullptr;
 };
 hipError_t launch_adj_small(const AdjArgs &a, hipStream_t st);
+// The same step for merges wider than SMALL_LDS_P (p <= 160, column draws
+// only): the eigen-decomposition of R R^T and R^-1 in one workgroup, then the
+// small products one launch each over many workgroups.  Workspace (ws):
+// adj_wide_ws_doubles(pm) doubles.
+hipError_t launch_adj_wide(const AdjArgs &a, hipStream_t st);
+__host__ __device__ constexpr size_t adj_wide_ws_doubles(int pm)
+{
+    return (size_t)11 * pm * pm + (size_t)3 * pm + BIG_INVIT_DOUBLES;
+}
 // Reverse pass of a row-sampled merge: G = W^T W (W = diag(s) A(rows, cols)),
 // its full eigen-decomposition (descending) into vfull (g x g, ld pm) and lam,
 // the first ru columns signed like vt; then, after the small adjoint,

@@ -1978,4 +1978,181 @@ hipError_t launch_adj_small_b(const AdjArgs *arr, int32_t count, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The small adjoint of a wide merge (SMALL_LDS_P < pmax, p <= 160; column
+// draws): the steps and arithmetic of adj_small_body with P = diag(Sigma, I),
+// split over launches.  k_adj_wide_eig (one workgroup) recomputes the full
+// eigen-decomposition R R^T = U_R S^2 U_R^T with the forward merge's
+// eigensolver (same start vectors, so the same signs of U_R) and R^-1; then
+// each product of the adjoint is one launch with one output element per
+// thread over as many workgroups as it has elements (the operands are L2
+// resident).  All matrices in the workspace have leading dimension p.
+// ---------------------------------------------------------------------------
+struct AdjWideWs {
+    double *R, *H, *UR, *W, *Ri, *V, *Z, *J, *K, *N, *Wm, *T, *s, *sp;
+};
+
+__device__ __forceinline__ AdjWideWs adj_wide_ws(double *ws, int pm)
+{
+    const size_t q = (size_t)pm * pm;
+    AdjWideWs w;
+    w.R = ws;
+    w.H = ws + q;                  // R R^T, then the reflectors
+    w.UR = ws + 2 * q;             // eigenvectors (all p)
+    w.W = ws + 3 * q + pm;         // inverse-iteration scratch (BIG_INVIT_DOUBLES)
+    double *b = w.W + BIG_INVIT_DOUBLES;
+    w.Ri = b;                      // R^-1
+    w.V = b + q;                   // Vs = R^T U_R
+    w.Z = b + 2 * q;               // R^-T P X0^T Ubar (p x rz)
+    w.J = b + 3 * q;               // U_R^T Z (p x rz)
+    w.K = b + 4 * q;               // F o (J - J^T)
+    w.N = b + 5 * q;
+    w.Wm = b + 6 * q;              // W1
+    w.T = b + 7 * q;               // P R^-1 W1
+    w.s = b + 8 * q;               // singular values of R (p)
+    w.sp = w.s + pm;               // diagonal of P (p)
+    return w;
+}
+
+static_assert(BIG_TRI_SDE <= BIG_PACKED && EIG_NMAX * 64 <= BIG_PACKED, "the wide adjoint's dynamic LDS");
+
+__global__ __launch_bounds__(512) void k_adj_wide_eig(AdjArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double sd[EIG_NMAX], se[EIG_NMAX], stau[EIG_NMAX], sev[EIG_NMAX], stmp[EIG_NMAX];
+    __shared__ __align__(8) int scl[EIG_NMAX + 8];
+    const int p = a.rs + a.g;
+    const AdjWideWs w = adj_wide_ws(a.ws, a.pm);
+    for (int idx = threadIdx.x; idx < p * p; idx += NT) {
+        const int i = idx % p, j = idx / p;
+        w.R[idx] = (i <= j) ? a.R[i + (size_t)j * a.pm] : 0.0;
+    }
+    __syncthreads();
+    // H = R R^T on the matrix cores: tile (I, J) sums k from 16 max(I, J)
+    big_mm(
+        p, false, [&](int i, int k) { return (i < p && k < p) ? w.R[i + k * p] : 0.0; },
+        [&](int k, int j) { return (j < p && k < p) ? w.R[j + k * p] : 0.0; },
+        [&](int i, int j, double v) {
+            if (i < p && j < p) w.H[i + j * p] = v;
+        },
+        [&](int ti, int tj, int &k0, int &k1) {
+            k0 = 16 * ((ti > tj) ? ti : tj);
+            (void)k1;
+        });
+    __syncthreads();
+    big_tridiag(w.H, p, sd, se, stau);
+    const BigTri bt = big_tri(sd, se, p, lds);
+    big_bisect_top(bt, p, p, sev);
+    big_invit(sd, se, p, sev, p, w.UR, w.W, lds, scl);
+    big_backtransform(w.H, stau, p, w.UR, p);
+    for (int i = threadIdx.x; i < p; i += NT) {
+        w.s[i] = sqrt(fmax(sev[i], 0.0));
+        w.sp[i] = (i < a.rs) ? a.sig[i] : 1.0;
+    }
+    trinv_upper<true>(w.R, p, w.Ri, stmp);
+}
+
+template <int STEP> __global__ __launch_bounds__(256) void k_adj_wide_step(AdjArgs a)
+{
+    const int rs = a.rs, p = a.rs + a.g, rz = a.rz, pb = a.pb;
+    const AdjWideWs w = adj_wide_ws(a.ws, a.pm);
+    const int idx = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (STEP == 0) {
+        if (idx < p * p) {   // Vs = R^T U_R
+            const int i = idx % p, j = idx / p;
+            double s = 0.0;
+            for (int l = 0; l <= i; ++l) s += w.R[l + i * p] * w.UR[l + j * p];
+            w.V[idx] = s;
+        } else if (idx < p * p + p * rz) {   // Z = R^-T P X0^T Ubar
+            const int e = idx - p * p, i = e % p, j = e / p;
+            double s = 0.0;
+            for (int l = 0; l <= i; ++l) s += w.Ri[l + i * p] * w.sp[l] * a.Gext[l + (size_t)(p + j) * pb];
+            w.Z[i + j * p] = s;
+        }
+    } else if (STEP == 1) {   // J = U_R^T Z
+        if (idx < p * rz) {
+            const int i = idx % p, j = idx / p;
+            double s = 0.0;
+            for (int l = 0; l < p; ++l) s += w.UR[l + i * p] * w.Z[l + j * p];
+            w.J[i + j * p] = s;
+        }
+    } else if (STEP == 2) {   // K~ = F o (J - J^T), J zero beyond column rz
+        if (idx < p * p) {
+            const int i = idx % p, j = idx / p;
+            const double gl = a.eta * w.s[0] * w.s[0];
+            double v = 0.0;
+            if (i != j) {
+                const double d = w.s[j] * w.s[j] - w.s[i] * w.s[i];
+                const double f = d / (d * d + gl * gl);
+                const double jij = (j < rz) ? w.J[i + j * p] : 0.0;
+                const double jji = (i < rz) ? w.J[j + i * p] : 0.0;
+                v = f * (jij - jji);
+            }
+            w.K[idx] = v;
+        }
+    } else if (STEP == 3) {   // N = K~ Vs^T + diag(sbar) V_r^T
+        if (idx < p * p) {
+            const int i = idx % p, c = idx / p;
+            double s = 0.0;
+            for (int j = 0; j < p; ++j) s += w.K[i + j * p] * w.V[c + j * p];
+            if (i < rz) s += a.sbar_in[i] / w.s[i] * w.V[c + i * p];
+            w.N[idx] = s;
+        }
+    } else if (STEP == 4) {   // W1 = U_R N - Z S_r^-2 Vs_r^T
+        if (idx < p * p) {
+            const int r0 = idx % p, c = idx / p;
+            double s = 0.0;
+            for (int i = 0; i < p; ++i) s += w.UR[r0 + i * p] * w.N[i + c * p];
+            for (int j = 0; j < rz; ++j) s -= w.Z[r0 + j * p] * w.V[c + j * p] / (w.s[j] * w.s[j]);
+            w.Wm[idx] = s;
+        }
+    } else if (STEP == 5) {   // T = P R^-1 W1
+        if (idx < p * p) {
+            const int r0 = idx % p, c = idx / p;
+            double s = 0.0;
+            for (int l = r0; l < p; ++l) s += w.Ri[r0 + l * p] * w.Wm[l + c * p];
+            w.T[idx] = w.sp[r0] * s;
+        }
+    } else {
+        if (idx < (p + rz) * p) {   // Wt = [T P ; W2 P]
+            const int row = idx % (p + rz), c = idx / (p + rz);
+            double v;
+            if (row < p) v = w.T[row + c * p] * w.sp[c];
+            else v = w.V[c + (row - p) * p] / (w.s[row - p] * w.s[row - p]) * w.sp[c];
+            store_c(a.Wt, a.prec, row + (int64_t)c * pb, v);
+        } else if (idx < (p + rz) * p + rs) {   // sbar_{t-1,i} = [X0^T X0 T + X0^T Ubar W2]_{ii}
+            const int i = idx - (p + rz) * p;
+            double s = 0.0;
+            for (int l = 0; l < p; ++l) s += a.Gext[i + (size_t)l * pb] * w.T[l + i * p];
+            for (int j = 0; j < rz; ++j) s += a.Gext[i + (size_t)(p + j) * pb] * w.V[i + j * p] / (w.s[j] * w.s[j]);
+            a.sbar_out[i] = s;
+        }
+    }
+}
+
+hipError_t launch_adj_wide(const AdjArgs &a, hipStream_t st)
+{
+    const int p = a.rs + a.g;
+    if (a.vt || p > EIG_NMAX || p > a.pm || a.rz < 0 || a.rz > p || p + a.rz > a.pb) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_adj_wide_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_limit(true));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (p < 1) return hipSuccess;
+    auto grid = [](int n) { return dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)); };
+    const int pp = p * p, prz = p * a.rz;
+    hipLaunchKernelGGL(k_adj_wide_eig, dim3(1), dim3(NT), (size_t)BIG_PACKED * sizeof(double), st, a);
+    hipLaunchKernelGGL(k_adj_wide_step<0>, grid(pp + prz), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_wide_step<1>, grid(prz), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_wide_step<2>, grid(pp), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_wide_step<3>, grid(pp), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_wide_step<4>, grid(pp), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_wide_step<5>, grid(pp), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_wide_step<6>, grid((p + a.rz) * p + a.rs), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 }  // namespace pod
