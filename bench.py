@@ -59,6 +59,8 @@ def parse():
                          "k=20, c=40; c5: 64-matrix batch, forward + gradient; c4: Alg. 3 over pinned host "
                          "blocks of 2M x 512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the forward-with-checkpoints plus gradient timing of each path")
     ap.add_argument("--paths", default="f64,bf16,f32",
                     help="precision paths run (f64 first; the reduced ones are compared against it)")
     ap.add_argument("--no-class-breakdown", action="store_true",
@@ -347,6 +349,38 @@ def run_single(args):
         if path == "bf16" and not args.no_class_breakdown:
             mixed_classes = classes("bf16", inf.iter)
 
+    # forward with reverse-pass checkpoints, then L = |A - U_k U_k^T A|_F^2 and
+    # dL/dA through every merge, per path (one warm-up, one timed); each
+    # reduced-precision gradient against the FP64 path's
+    adjoint = None
+    if not args.no_adjoint:
+        def fwd_grad(path):
+            with pod.PodContext(A, precision=precs[path], **kw) as ctx:
+                ctx.enable_adjoint()
+                ctx.run(chunk=RUN_CHUNK)
+                L, dA = ctx.loss_grad()
+                inf = ctx.info()
+            return L, dA, inf
+
+        adjoint = {}
+        g64 = None
+        for path in ["f64"] + [q for q in ("bf16", "f32") if q in args.paths.split(",")]:
+            fwd_grad(path)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L, dA, inf = fwd_grad(path)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            e = {"ms": round(sec * 1e3, 3), "merges": inf.iter, "loss": L}
+            if path == "f64":
+                g64 = (sec, dA, float(torch.linalg.norm(dA)))
+            else:
+                d = float(torch.linalg.norm(dA.to(torch.float64) - g64[1])) / g64[2]
+                e.update({"grad_rel_vs_f64": d, "speedup_vs_f64": round(g64[0] / sec, 3)})
+            del dA
+            adjoint[path] = e
+        del g64
+
     out = {
         "metric": METRIC,
         "value": round(sec64 * 1e3, 3),
@@ -370,9 +404,10 @@ def run_single(args):
         "small_stage_us_per_launch": ({q: {"f64": cls64[q]["avg_launch_us"],
                                            "bf16": mixed_classes[q]["avg_launch_us"] if mixed_classes else None}
                                        for q in SMALL} if cls64 else None),
-        "adjoint_included": False,
-        "adjoint_note": ("the reverse pass covers merge widths up to 64; this workload merges "
-                         f"{p} columns. The batched workload (--workload c5) times forward plus gradient"),
+        "adjoint_included": adjoint is not None,
+        "adjoint": adjoint,
+        "adjoint_note": ("per path: forward with checkpoints plus loss and gradient dL/dA through every merge "
+                         "(ms, outside the value's timed region)") if adjoint is not None else None,
         "gen_s": round(t_gen, 2),
     }
     if args.no_cpu_baseline:

@@ -172,6 +172,128 @@ __global__ __launch_bounds__(256) void k_loss_resid(const TA *__restrict__ A, in
     if (threadIdx.x == 0) lossp[blockIdx.x] = ((sw[0] + sw[1]) + sw[2]) + sw[3];
 }
 
+// The same for k > 16 on the FP64 matrix cores: B U_k^T and R B^T are dense
+// contractions (2 m n k flops each).  A workgroup of 8 waves takes 256 rows
+// (the loss partial of k_loss_resid's layout); wave w its two 16-row tiles
+// (two independent product chains), U_k of its rows held in the B-operand
+// layout (lane l: row l % 16, k = 4 s + l / 16).  Per 16-column chunk c:
+//   S = B(:, c)^T U_k(rows, :)^T   (16 x 16, k in steps of 4),
+//   R^T = A(rows, c)^T - S, dA(rows, c) = 2 R, L += |R|^2,
+//   Ubar(rows, :)^T += B(:, c) R(rows, c)^T (k in tiles of 16),
+// where the FP64 accumulator layout of S (lane l: column l / 16 + 4 v of the
+// chunk, row l % 16) is the B-operand layout of the second product; k is
+// padded to 64 with zero operands.  B is
+// staged in LDS 64 columns at a time (column-major, padded); loads of A,
+// clamped into range, carry no branch.
+constexpr int LM_NT = 512, LM_NC = 64, LM_LDB = 65;
+template <typename TC, typename TA>
+__global__ __launch_bounds__(LM_NT) void k_loss_mfma(const TA *__restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                     const TC *__restrict__ U, int32_t k,
+                                                     const double *__restrict__ B, TC *__restrict__ dA,
+                                                     TC *__restrict__ Ubar, double *__restrict__ lossp)
+{
+    __shared__ double Bs[LM_NC * LM_LDB];
+    __shared__ double sw[LM_NT / 64];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = l & 15, lk = l >> 4;
+    int64_t row[2];
+    bool rin[2];
+    double u[2][16];
+    v4d ub[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        row[t] = (int64_t)blockIdx.x * 256 + w * 32 + t * 16 + li;
+        rin[t] = row[t] < m;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int kk = 4 * s + lk;
+            const bool ok = rin[t] && kk < k;
+            const TC v = U[ok ? (int64_t)kk * m + row[t] : 0];
+            u[t][s] = ok ? (double)v : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ub[t][q] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    const int64_t rc[2] = {rin[0] ? row[0] : 0, rin[1] ? row[1] : 0};
+    double L = 0.0;
+    for (int64_t c0 = 0; c0 < n; c0 += LM_NC) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < LM_NC * 64; e += LM_NT) {
+            const int cc = e >> 6, kk = e & 63;
+            const bool ok = c0 + cc < n && kk < k;
+            const double v = B[ok ? (c0 + cc) * k + kk : 0];
+            Bs[cc * LM_LDB + kk] = ok ? v : 0.0;
+        }
+        __syncthreads();
+        const int nch = (int)(((n - c0 < LM_NC) ? n - c0 : LM_NC) + 15) >> 4;
+        for (int ch = 0; ch < nch; ++ch) {
+            const int cb = ch * 16;
+            // A of the four columns l / 16 + 4 v of the chunk, for both row tiles
+            TA av[2][4];
+            bool cin[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t col = c0 + cb + lk + 4 * v;
+                cin[v] = col < n;
+                const int64_t cl = cin[v] ? col : 0;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) av[t][v] = A[cl * lda + rc[t]];
+            }
+            v4d S[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
+            const double *ba = Bs + (cb + li) * LM_LDB + lk;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {   // (zero operands past k)
+                const double a = ba[4 * s];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) S[t] = mfma16x16x4(a, u[t][s], S[t]);
+            }
+            v4d R[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double r = (rin[t] && cin[v]) ? (double)av[t][v] - S[t][v] : 0.0;
+                    R[t][v] = r;
+                    L += r * r;
+                }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (rin[t] && cin[v]) dA[(c0 + cb + lk + 4 * v) * m + row[t]] = (TC)(2.0 * R[t][v]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double *bb = Bs + (cb + lk) * LM_LDB + 16 * q + li;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const double a = bb[4 * s * LM_LDB];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) ub[t][q] = mfma16x16x4(a, R[t][s], ub[t][q]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int kk = 16 * q + lk + 4 * v;
+                if (rin[t] && kk < k) Ubar[(int64_t)kk * m + row[t]] = (TC)(-2.0 * ub[t][q][v]);
+            }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) L += __shfl_xor(L, o, 64);
+    if (l == 0) sw[w] = L;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < LM_NT / 64; ++q) t += sw[q];
+        lossp[blockIdx.x] = t;
+    }
+}
+
 template <typename TC, typename TA>
 hipError_t loss_resid_launch(const void *A, int64_t lda, int64_t m, int64_t n, const void *U, int32_t k,
                              const double *B, void *dA, void *Ubar, double *lossp, hipStream_t st)
@@ -180,9 +302,11 @@ hipError_t loss_resid_launch(const void *A, int64_t lda, int64_t m, int64_t n, c
     if (k <= 16)
         hipLaunchKernelGGL((k_loss_resid<TC, TA, 16>), dim3(nb), dim3(256), 0, st, (const TA *)A, lda, m, n,
                            (const TC *)U, k, B, (TC *)dA, (TC *)Ubar, lossp);
-    else
-        hipLaunchKernelGGL((k_loss_resid<TC, TA, 64>), dim3(nb), dim3(256), 0, st, (const TA *)A, lda, m, n,
+    else if (k <= 64)
+        hipLaunchKernelGGL((k_loss_mfma<TC, TA>), dim3(nb), dim3(LM_NT), 0, st, (const TA *)A, lda, m, n,
                            (const TC *)U, k, B, (TC *)dA, (TC *)Ubar, lossp);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

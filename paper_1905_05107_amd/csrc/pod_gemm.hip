@@ -1385,14 +1385,22 @@ __global__ __launch_bounds__(256) void k_gemm_tall_scatter(SrcT<TC> s, int64_t m
                                            blockIdx.x, gridDim.x, 0, sc);
 }
 
-// The same with T read from device memory (inputs up to PMAX_ADJ columns).
+// The same for inputs up to PMAX_ADJ columns whose T does not fit in LDS
+// whole: workgroup row (blockIdx.y) takes output columns [cgw y, cgw (y + 1))
+// with that slice of T in LDS (each column group reads X once more).  The
+// output count sel_out is literal.
 template <typename TC, int ITEMS>
-__global__ __launch_bounds__(256) void k_gemm_tall_scatter_g(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
-                                                           int sel_out, int pmax_in, const TC *__restrict__ T,
-                                                           int ldt, TC *__restrict__ Yout, TallScatter sc, int vec)
+__global__ __launch_bounds__(256) void k_gemm_tall_scatter_cg(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
+                                                            int sel_out, int pmax_in, const TC *__restrict__ T,
+                                                            int ldt, TC *__restrict__ Yout, TallScatter sc, int vec,
+                                                            int cgw)
 {
-    gemm_tall_body<TC, ITEMS, true, true>(s, m, ds, sel_in, sel_out, pmax_in, 0, T, ldt, Yout, nullptr, vec,
-                                           blockIdx.x, gridDim.x, 0, sc);
+    const int j0 = (int)blockIdx.y * cgw;
+    const int po = (sel_out - j0 < cgw) ? sel_out - j0 : cgw;
+    TallScatter g = sc;
+    g.split = sc.split - j0;   // column j0 + c' goes where column c of the whole output goes
+    gemm_tall_body<TC, ITEMS, false, true>(s, m, ds, sel_in, po, pmax_in, 0, T + (int64_t)j0 * ldt, ldt,
+                                           Yout + (int64_t)j0 * m, nullptr, vec, blockIdx.x, gridDim.x, 0, g);
 }
 
 // Batched scatter (P <= 64): matrix blockIdx.y, its own block count.
@@ -1969,21 +1977,34 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
     const size_t esz = (d.prec == POD_F64) ? 8 : 4;
     if (PI > PMAX_ADJ || PO > PMAX_WIDE) return hipErrorInvalidValue;
     if (PI > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS) {
-        // T too large for LDS: staged X of up to 224 columns, T from device memory
+        // column groups of cgw output columns, each with its slice of T in LDS
+        // beside a stage of up to 224 columns of X
+        if (pout_max < 0 || which_out < 0 || which_out > pout_max) return hipErrorInvalidValue;
+        const int CW = ITEMS224 * 256 / GRP;
+        const int cgw = (int)(((size_t)TALL_DYN_LDS / esz - (size_t)CW * LDSR) / PI) & ~15;
+        if (cgw < 16) return hipErrorInvalidValue;
+        const unsigned ng = (unsigned)((PO + cgw - 1) / cgw);
         const unsigned nb = (unsigned)tall_blocks(d.m);
         const TallScatter sc{split, cmap, D, ldd};
-        const int CW = ITEMS224 * 256 / GRP;
-        const size_t lds = (size_t)CW * LDSR * esz;
+        const size_t lds = (size_t)(CW * LDSR + PI * ((cgw < PO) ? cgw : PO)) * esz;
         if (d.prec == POD_F64) {
+            static bool attr = false;
+            if (!attr)
+                attr = hipFuncSetAttribute((const void *)k_gemm_tall_scatter_cg<double, ITEMS224>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, TALL_DYN_LDS) == hipSuccess;
             const SrcT<double> s = make_src<double>(d);
-            hipLaunchKernelGGL((k_gemm_tall_scatter_g<double, ITEMS224>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
-                               which_in, which_out, CW, (const double *)T, ldt, (double *)Yout, sc,
-                               (int)vec_ok(s, d.m));
+            hipLaunchKernelGGL((k_gemm_tall_scatter_cg<double, ITEMS224>), dim3(nb, ng), dim3(256), lds, st, s, d.m,
+                               ds, which_in, which_out, CW, (const double *)T, ldt, (double *)Yout, sc,
+                               (int)vec_ok(s, d.m), cgw);
         } else {
+            static bool attr = false;
+            if (!attr)
+                attr = hipFuncSetAttribute((const void *)k_gemm_tall_scatter_cg<float, ITEMS224>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, TALL_DYN_LDS) == hipSuccess;
             const SrcT<float> s = make_src<float>(d);
-            hipLaunchKernelGGL((k_gemm_tall_scatter_g<float, ITEMS224>), dim3(nb), dim3(256), lds, st, s, d.m, ds,
-                               which_in, which_out, CW, (const float *)T, ldt, (float *)Yout, sc,
-                               (int)vec_ok(s, d.m));
+            hipLaunchKernelGGL((k_gemm_tall_scatter_cg<float, ITEMS224>), dim3(nb, ng), dim3(256), lds, st, s, d.m,
+                               ds, which_in, which_out, CW, (const float *)T, ldt, (float *)Yout, sc,
+                               (int)vec_ok(s, d.m), cgw);
         }
         return hipGetLastError();
     }
