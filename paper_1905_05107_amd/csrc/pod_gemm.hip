@@ -1155,7 +1155,7 @@ struct TallScatter {
     int64_t ldd;
 };
 
-template <typename TC, int ITEMS, bool TG, bool SCAT = false, bool TP = false>
+template <typename TC, int ITEMS, bool TG, bool SCAT = false, bool TP = false, bool SPLITK = false>
 __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in, int sel_out,
                                                int pmax_in, int pmax_out, const TC *__restrict__ T, int ldt,
                                                TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec, int bid,
@@ -1244,7 +1244,7 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
     // T in LDS: wave wv owns the tiles of row block rbk = wv % 2 and column
     // tiles jc = wv / 2 + 2 i; each X operand read from LDS feeds the MFMAs of
     // all of them, which accumulate independently (no chained MFMAs)
-    constexpr int MAXJ = (ITEMS * 256 / GRP) / 32;
+    constexpr int MAXJ = SPLITK ? 2 : (ITEMS * 256 / GRP) / 32;   // (SPLITK: at most 4 column tiles)
     auto compute_lds = [&](int64_t sg) {
         const int rbk = wv & 1, j0 = wv >> 1;
         const int nj = (PO / 16 > j0) ? (PO / 16 - j0 + 1) / 2 : 0;
@@ -1252,11 +1252,16 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
         const int jlast = j0 + 2 * (nj - 1);
         const int ke = (tri && nj > 0 && 16 * (jlast + 1) < PI) ? 16 * (jlast + 1) : PI;
         if (nj == 0) return;
-        AccT acc[MAXJ];
+        // SPLITK: odd k-chunks into a second accumulator per tile (twice the
+        // independent product chains; the two halves added at the end)
+        AccT acc[MAXJ], acc2[SPLITK ? MAXJ : 1];
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i) acc[i] = AccT{0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < (SPLITK ? MAXJ : 1); ++i) acc2[i] = AccT{0, 0, 0, 0};
         const TC *xb = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
         for (int k4 = 0; k4 < ke; k4 += 16) {
+            const bool odd = SPLITK && ((k4 >> 4) & 1);
             TC xv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) xv[u] = xb[(k4 + 4 * u) * LDSR];
@@ -1274,11 +1279,19 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
 #pragma unroll
                         for (int u = 0; u < 4; ++u) av[u] = ta[4 * u * PO];
                     }
+                    if (SPLITK && odd) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[i] = mfma16x16x4(av[u], xv[u], acc[i]);
+                        for (int u = 0; u < 4; ++u) acc2[i] = mfma16x16x4(av[u], xv[u], acc2[i]);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc[i] = mfma16x16x4(av[u], xv[u], acc[i]);
+                    }
                 }
             }
         }
+        if (SPLITK)
+#pragma unroll
+            for (int i = 0; i < MAXJ; ++i) acc[i] += acc2[i];
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i)
             if (i < nj) store_tile(sg, rbk, j0 + 2 * i, acc[i]);
@@ -1387,8 +1400,9 @@ __global__ __launch_bounds__(256) void k_gemm_tall_scatter(SrcT<TC> s, int64_t m
 
 // The same for inputs up to PMAX_ADJ columns whose T does not fit in LDS
 // whole: workgroup row (blockIdx.y) takes output columns [cgw y, cgw (y + 1))
-// with that slice of T in LDS (each column group reads X once more).  The
-// output count sel_out is literal.
+// (cgw <= 64) with that slice of T in LDS (each column group reads X once
+// more); odd k-chunks accumulate apart (SPLITK).  The output count sel_out
+// is literal.
 template <typename TC, int ITEMS>
 __global__ __launch_bounds__(256) void k_gemm_tall_scatter_cg(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
                                                             int sel_out, int pmax_in, const TC *__restrict__ T,
@@ -1399,7 +1413,7 @@ __global__ __launch_bounds__(256) void k_gemm_tall_scatter_cg(SrcT<TC> s, int64_
     const int po = (sel_out - j0 < cgw) ? sel_out - j0 : cgw;
     TallScatter g = sc;
     g.split = sc.split - j0;   // column j0 + c' goes where column c of the whole output goes
-    gemm_tall_body<TC, ITEMS, false, true>(s, m, ds, sel_in, po, pmax_in, 0, T + (int64_t)j0 * ldt, ldt,
+    gemm_tall_body<TC, ITEMS, false, true, false, true>(s, m, ds, sel_in, po, pmax_in, 0, T + (int64_t)j0 * ldt, ldt,
                                            Yout + (int64_t)j0 * m, nullptr, vec, blockIdx.x, gridDim.x, 0, g);
 }
 
@@ -1448,16 +1462,27 @@ constexpr int T64_WAVES = 8;
 typedef __attribute__((address_space(1))) const double gdouble;
 typedef __attribute__((address_space(1))) const uint32_t gu32;
 
-template <int KT, int NJ, bool TP, bool MIX>
+// SCAT: the reverse pass's transform of [U | A(:, I) | Ubar] (scatter output
+// as TallScatter; D leading dimension m): workgroup row blockIdx.y takes the
+// output columns [16 NJ y, 16 NJ (y + 1)) with that slice of T.
+template <int KT, int NJ, bool TP, bool MIX, bool SCAT = false>
 __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64_t m, const DevState *ds, int sel_in,
                                                            int sel_out, const double *__restrict__ T, int ldt,
-                                                           double *Yout, double *Yout1, int tri)
+                                                           double *Yout, double *Yout1, int tri, TallScatter sc)
 {
     extern __shared__ double tl[];
     __shared__ uint64_t cptr[16 * KT];
     if (s.guard && merge_halted(ds)) return;
     if (Yout1 && (ds->it & 1)) Yout = Yout1;
-    const int pin = sel_count(ds, sel_in), pout = sel_count(ds, sel_out);
+    const int pin = sel_count(ds, sel_in);
+    int pout = sel_count(ds, sel_out);
+    if (SCAT) {
+        const int j0 = (int)blockIdx.y * 16 * NJ;
+        T += (int64_t)j0 * ldt;
+        Yout += (int64_t)j0 * m;
+        sc.split -= j0;
+        pout = (pout - j0 < 16 * NJ) ? pout - j0 : 16 * NJ;
+    }
     s.rs = ds->rs;
     s.g = ds->g;
     if (s.U1 && (ds->it & 1)) s.U = s.U1;
@@ -1489,6 +1514,18 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
     __syncthreads();
     const int64_t ntile = (m + 15) >> 4;
     const int r16 = lane & 15, cg = lane >> 4;
+    // SCAT: the target column of D of every output column of the lane (0 where
+    // the column is not scattered)
+    int ci[SCAT ? NJ : 1][4];
+#pragma unroll
+    for (int jt = 0; jt < (SCAT ? NJ : 1); ++jt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int col = 16 * jt + cg + 4 * v;
+            const bool sct = SCAT && col >= sc.split && col < pout;
+            ci[jt][v] = SCAT ? sc.cmap[sct ? col - sc.split : 0] : 0;
+            if (!sct) ci[jt][v] = 0;
+        }
     // one row tile: its X operands (raw bits, FP32 columns widened by widen),
     // then the products and the stores
     auto load_tile = [&](int64_t rt, double (&x)[KT][4], uint32_t (&xf)[KT][4], uint32_t (&sel)[KT]) {
@@ -1559,7 +1596,27 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
                     acc[jt] = mfma16x16x4(tlr[256 * t + 64 * q + lane], x[kt][q], acc[jt]);
                 }
         }
-        if (rin) {
+        if (SCAT) {
+            // read-modify-write of the scattered columns, four at a time: the
+            // old values are loaded with no branch (row m - 1 past the end,
+            // column 0 of D where the column is not scattered)
+            const int64_t rowc = rin ? row : m - 1;
+            double *D = reinterpret_cast<double *>(sc.D);
+#pragma unroll
+            for (int jt = 0; jt < NJ; ++jt) {
+                double old[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) old[v] = D[(int64_t)ci[jt][v] * sc.ldd + rowc];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int col = 16 * jt + cg + 4 * v;
+                    if (rin && col < pout) {
+                        if (col < sc.split) Yout[(int64_t)col * m + row] = acc[jt][v];
+                        else D[(int64_t)ci[jt][v] * sc.ldd + row] = old[v] + acc[jt][v];
+                    }
+                }
+            }
+        } else if (rin) {
             // (the column stride laundered per row tile: the forty column
             // addresses are not hoisted out of the row loop into registers)
             int64_t ms = m;
@@ -1604,7 +1661,28 @@ static void tall64_launch_t(const GemmDesc &d, const DevState *ds, int32_t which
     const int64_t want = (ntile + 4 * T64_WAVES - 1) / (4 * T64_WAVES);
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * per_cu));
     hipLaunchKernelGGL((k_tall64<KT, NJ, TP, MIX>), dim3(nb), dim3(64 * T64_WAVES), lds, st, s, d.m, ds, which_in,
-                       which_out, (const double *)T, ldt, (double *)Yout, (double *)Yout1, tri);
+                       which_out, (const double *)T, ldt, (double *)Yout, (double *)Yout1, tri, TallScatter{0, nullptr, nullptr, 0});
+}
+
+// The scatter transform of the reverse pass on FP64 (column groups of 16 NJ).
+template <int KT, int NJ, bool MIX>
+static hipError_t tall64_scatter_launch(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
+                                        int32_t pout_max, const double *T, int32_t ldt, double *Yout,
+                                        const TallScatter &sc, hipStream_t st)
+{
+    const SrcT<double> s = make_src<double>(d);
+    const size_t lds = (size_t)KT * NJ * 256 * sizeof(double);
+    static bool attr = false;
+    if (lds > 64 * 1024 && !attr)
+        attr = hipFuncSetAttribute((const void *)k_tall64<KT, NJ, false, MIX, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+    const unsigned ng = (unsigned)((pout_max + 16 * NJ - 1) / (16 * NJ));
+    const int64_t ntile = (d.m + 15) / 16;
+    const int64_t want = (ntile + 4 * T64_WAVES - 1) / (4 * T64_WAVES);
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256));
+    hipLaunchKernelGGL((k_tall64<KT, NJ, false, MIX, true>), dim3(nb, ng), dim3(64 * T64_WAVES), lds, st, s, d.m, ds,
+                       which_in, which_out, T, ldt, Yout, (double *)nullptr, 0, sc);
+    return hipGetLastError();
 }
 
 // MIX: some columns of the source are FP32 (gathered columns of an FP32 A)
@@ -1976,12 +2054,29 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
     const int PI = (pin_max + 15) & ~15, PO = (pout_max + 15) & ~15;
     const size_t esz = (d.prec == POD_F64) ? 8 : 4;
     if (PI > PMAX_ADJ || PO > PMAX_WIDE) return hipErrorInvalidValue;
+    if (d.prec == POD_F64 && PI > 64 && (PI > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS)) {
+        // X straight into the matrix-core registers, column groups of 80
+        // with their slice of T in LDS; the output count is literal
+        if (which_in < 0 || which_out < 0 || which_out > pout_max || which_in > pin_max) return hipErrorInvalidValue;
+        const TallScatter sc{split, cmap, D, ldd};
+        const bool mix = d.gather && d.a_dtype != POD_F64;
+        if (PI > PMAX_WIDE)
+            return mix ? tall64_scatter_launch<13, 4, true>(d, ds, which_in, which_out, pout_max, (const double *)T,
+                                                             ldt, (double *)Yout, sc, st)
+                       : tall64_scatter_launch<13, 4, false>(d, ds, which_in, which_out, pout_max, (const double *)T,
+                                                              ldt, (double *)Yout, sc, st);
+        return mix ? tall64_scatter_launch<10, 4, true>(d, ds, which_in, which_out, pout_max, (const double *)T, ldt,
+                                                         (double *)Yout, sc, st)
+                   : tall64_scatter_launch<10, 4, false>(d, ds, which_in, which_out, pout_max, (const double *)T, ldt,
+                                                          (double *)Yout, sc, st);
+    }
     if (PI > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS) {
         // column groups of cgw output columns, each with its slice of T in LDS
         // beside a stage of up to 224 columns of X
         if (pout_max < 0 || which_out < 0 || which_out > pout_max) return hipErrorInvalidValue;
         const int CW = ITEMS224 * 256 / GRP;
-        const int cgw = (int)(((size_t)TALL_DYN_LDS / esz - (size_t)CW * LDSR) / PI) & ~15;
+        int cgw = (int)(((size_t)TALL_DYN_LDS / esz - (size_t)CW * LDSR) / PI) & ~15;
+        if (cgw > 64) cgw = 64;   // the kernel's waves hold two column tiles each
         if (cgw < 16) return hipErrorInvalidValue;
         const unsigned ng = (unsigned)((PO + cgw - 1) / cgw);
         const unsigned nb = (unsigned)tall_blocks(d.m);
