@@ -104,3 +104,30 @@ def test_wide_rows_rejected():
     with pod.PodContext(_dev(A), precision=pod.POD_F64, k=20, c=60, w=80, seed=3, theta_tol=1e-12) as ctx:
         with pytest.raises(pod.PodError):
             ctx.enable_adjoint()
+
+
+@pytest.mark.parametrize("m,n,k,c,seed", CASES[1:])
+def test_wide_backward_vjp_fp64(m, n, k, c, seed):
+    """pod_backward through torch.autograd for given (dU, dsigma) at merge
+    width 150 against the oracle's vector-Jacobian product (columns of the two
+    bases may differ in sign: dU is mapped accordingly); dsigma exercises the
+    singular-value adjoint carried from merge to merge."""
+    A = _case(m, n, seed)
+    kw = dict(k=k, c=c, seed=seed + 7, theta_tol=1e-12)
+    ref = oracle_isma(A, IsmaParams(**kw), final_step=False)
+    cs = adj.col_sets_of(ref.log)
+    rng = np.random.default_rng(seed + 1)
+    Ad = _dev(A).requires_grad_(True)
+    print(f"vjp wide fp64 m={m} n={n} k={k} c={c}", flush=True)
+    U, s = pod.pod_function(Ad, k, c, precision=pod.POD_F64, seed=kw["seed"], theta_tol=kw["theta_tol"])
+    dU = rng.standard_normal(U.shape)
+    ds = rng.standard_normal(s.shape)
+    (U * torch.from_numpy(dU).cuda()).sum().add((s * torch.from_numpy(ds).cuda()).sum()).backward()
+    got = Ad.grad.cpu().numpy()
+    _, Uo, so = adj.vjp(A, cs, k, k)
+    sg = np.sign(np.sum(Uo * U.detach().cpu().numpy(), axis=0))
+    want, _, _ = adj.vjp(A, cs, k, k, dU=dU * sg[None, :], dsigma=ds)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"  merges={len(cs)} vjp rel={rel:.2e}", flush=True)
+    assert np.max(np.abs(s.detach().cpu().numpy() - so) / so) <= 1e-10
+    assert rel <= 1e-8
