@@ -1244,7 +1244,7 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
     // T in LDS: wave wv owns the tiles of row block rbk = wv % 2 and column
     // tiles jc = wv / 2 + 2 i; each X operand read from LDS feeds the MFMAs of
     // all of them, which accumulate independently (no chained MFMAs)
-    constexpr int MAXJ = SPLITK ? 2 : (ITEMS * 256 / GRP) / 32;   // (SPLITK: at most 4 column tiles)
+    constexpr int MAXJ = SPLITK ? 3 : (ITEMS * 256 / GRP) / 32;   // (SPLITK: at most 6 column tiles)
     auto compute_lds = [&](int64_t sg) {
         const int rbk = wv & 1, j0 = wv >> 1;
         const int nj = (PO / 16 > j0) ? (PO / 16 - j0 + 1) / 2 : 0;
@@ -1400,7 +1400,7 @@ __global__ __launch_bounds__(256) void k_gemm_tall_scatter(SrcT<TC> s, int64_t m
 
 // The same for inputs up to PMAX_ADJ columns whose T does not fit in LDS
 // whole: workgroup row (blockIdx.y) takes output columns [cgw y, cgw (y + 1))
-// (cgw <= 64) with that slice of T in LDS (each column group reads X once
+// (cgw <= 96) with that slice of T in LDS (each column group reads X once
 // more); odd k-chunks accumulate apart (SPLITK).  The output count sel_out
 // is literal.
 template <typename TC, int ITEMS>
@@ -2076,7 +2076,7 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
         if (pout_max < 0 || which_out < 0 || which_out > pout_max) return hipErrorInvalidValue;
         const int CW = ITEMS224 * 256 / GRP;
         int cgw = (int)(((size_t)TALL_DYN_LDS / esz - (size_t)CW * LDSR) / PI) & ~15;
-        if (cgw > 64) cgw = 64;   // the kernel's waves hold two column tiles each
+        if (cgw > 96) cgw = 96;   // the kernel's waves hold three column tiles each
         if (cgw < 16) return hipErrorInvalidValue;
         const unsigned ng = (unsigned)((PO + cgw - 1) / cgw);
         const unsigned nb = (unsigned)tall_blocks(d.m);
