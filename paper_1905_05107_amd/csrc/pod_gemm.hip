@@ -1465,10 +1465,12 @@ typedef __attribute__((address_space(1))) const uint32_t gu32;
 // SCAT: the reverse pass's transform of [U | A(:, I) | Ubar] (scatter output
 // as TallScatter; D leading dimension m): workgroup row blockIdx.y takes the
 // output columns [16 NJ y, 16 NJ (y + 1)) with that slice of T.
-template <int KT, int NJ, bool TP, bool MIX, bool SCAT = false>
-__global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64_t m, const DevState *ds, int sel_in,
-                                                           int sel_out, const double *__restrict__ T, int ldt,
-                                                           double *Yout, double *Yout1, int tri, TallScatter sc)
+// TS: the storage type of the basis columns, T and the outputs (float on the
+// FP32 path: every operand widened to FP64, the products in FP64).
+template <int KT, int NJ, bool TP, bool MIX, bool SCAT = false, typename TS = double>
+__global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<TS> s, int64_t m, const DevState *ds, int sel_in,
+                                                           int sel_out, const TS *__restrict__ T, int ldt,
+                                                           TS *Yout, TS *Yout1, int tri, TallScatter sc)
 {
     extern __shared__ double tl[];
     __shared__ uint64_t cptr[16 * KT];
@@ -1501,12 +1503,12 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
             kt = t % KT;
         }
         const int k = 16 * kt + 4 * (e >> 6) + ((e >> 4) & 3), j = 16 * jt + (e & 15);
-        tl[idx] = (k < pin && j < pout && (!tri || k <= j)) ? T[k + (int64_t)j * ldt] : 0.0;
+        tl[idx] = (k < pin && j < pout && (!tri || k <= j)) ? (double)T[k + (int64_t)j * ldt] : 0.0;
     }
     for (int c = threadIdx.x; c < 16 * KT; c += 64 * T64_WAVES) {
         uint64_t v = 0;
         if (c < pin) {
-            const ColPtr cp = col_ptr<double>(s, m, c);
+            const ColPtr cp = col_ptr<TS>(s, m, c);
             v = (uint64_t)(uintptr_t)cp.p | (cp.f64 ? 0u : 1u);
         }
         cptr[c] = v;
@@ -1601,18 +1603,18 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
             // old values are loaded with no branch (row m - 1 past the end,
             // column 0 of D where the column is not scattered)
             const int64_t rowc = rin ? row : m - 1;
-            double *D = reinterpret_cast<double *>(sc.D);
+            TS *D = reinterpret_cast<TS *>(sc.D);
 #pragma unroll
             for (int jt = 0; jt < NJ; ++jt) {
-                double old[4];
+                TS old[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) old[v] = D[(int64_t)ci[jt][v] * sc.ldd + rowc];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int col = 16 * jt + cg + 4 * v;
                     if (rin && col < pout) {
-                        if (col < sc.split) Yout[(int64_t)col * m + row] = acc[jt][v];
-                        else D[(int64_t)ci[jt][v] * sc.ldd + row] = old[v] + acc[jt][v];
+                        if (col < sc.split) Yout[(int64_t)col * m + row] = (TS)acc[jt][v];
+                        else D[(int64_t)ci[jt][v] * sc.ldd + row] = (TS)((double)old[v] + acc[jt][v]);
                     }
                 }
             }
@@ -1626,7 +1628,7 @@ __global__ __launch_bounds__(64 * T64_WAVES) void k_tall64(SrcT<double> s, int64
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int col = 16 * jt + cg + 4 * v;
-                    if (col < pout) Yout[(int64_t)col * ms + row] = acc[jt][v];
+                    if (col < pout) Yout[(int64_t)col * ms + row] = (TS)acc[jt][v];
                 }
         }
     };
@@ -1665,23 +1667,23 @@ static void tall64_launch_t(const GemmDesc &d, const DevState *ds, int32_t which
 }
 
 // The scatter transform of the reverse pass on FP64 (column groups of 16 NJ).
-template <int KT, int NJ, bool MIX>
+template <int KT, int NJ, bool MIX, typename TS = double>
 static hipError_t tall64_scatter_launch(const GemmDesc &d, const DevState *ds, int32_t which_in, int32_t which_out,
-                                        int32_t pout_max, const double *T, int32_t ldt, double *Yout,
+                                        int32_t pout_max, const TS *T, int32_t ldt, TS *Yout,
                                         const TallScatter &sc, hipStream_t st)
 {
-    const SrcT<double> s = make_src<double>(d);
+    const SrcT<TS> s = make_src<TS>(d);
     const size_t lds = (size_t)KT * NJ * 256 * sizeof(double);
     static bool attr = false;
     if (lds > 64 * 1024 && !attr)
-        attr = hipFuncSetAttribute((const void *)k_tall64<KT, NJ, false, MIX, true>,
+        attr = hipFuncSetAttribute((const void *)k_tall64<KT, NJ, false, MIX, true, TS>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
     const unsigned ng = (unsigned)((pout_max + 16 * NJ - 1) / (16 * NJ));
     const int64_t ntile = (d.m + 15) / 16;
     const int64_t want = (ntile + 4 * T64_WAVES - 1) / (4 * T64_WAVES);
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256));
-    hipLaunchKernelGGL((k_tall64<KT, NJ, false, MIX, true>), dim3(nb, ng), dim3(64 * T64_WAVES), lds, st, s, d.m, ds,
-                       which_in, which_out, T, ldt, Yout, (double *)nullptr, 0, sc);
+    hipLaunchKernelGGL((k_tall64<KT, NJ, false, MIX, true, TS>), dim3(nb, ng), dim3(64 * T64_WAVES), lds, st, s, d.m,
+                       ds, which_in, which_out, T, ldt, Yout, (TS *)nullptr, 0, sc);
     return hipGetLastError();
 }
 
@@ -2054,6 +2056,14 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
     const int PI = (pin_max + 15) & ~15, PO = (pout_max + 15) & ~15;
     const size_t esz = (d.prec == POD_F64) ? 8 : 4;
     if (PI > PMAX_ADJ || PO > PMAX_WIDE) return hipErrorInvalidValue;
+    if (d.prec == POD_F32 && PI > PMAX_WIDE) {
+        // the FP32 path on the same kernel: every column read as FP32 (or
+        // FP64 for an FP64 A) and widened, T widened into LDS, FP64 products
+        if (which_in < 0 || which_out < 0 || which_out > pout_max || which_in > pin_max) return hipErrorInvalidValue;
+        const TallScatter sc{split, cmap, D, ldd};
+        return tall64_scatter_launch<13, 5, true, float>(d, ds, which_in, which_out, pout_max, (const float *)T, ldt,
+                                                         (float *)Yout, sc, st);
+    }
     if (d.prec == POD_F64 && PI > 64 && (PI > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS)) {
         // X straight into the matrix-core registers, column groups of 80
         // with their slice of T in LDS; the output count is literal
@@ -2061,9 +2071,9 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
         const TallScatter sc{split, cmap, D, ldd};
         const bool mix = d.gather && d.a_dtype != POD_F64;
         if (PI > PMAX_WIDE)
-            return mix ? tall64_scatter_launch<13, 4, true>(d, ds, which_in, which_out, pout_max, (const double *)T,
+            return mix ? tall64_scatter_launch<13, 5, true>(d, ds, which_in, which_out, pout_max, (const double *)T,
                                                              ldt, (double *)Yout, sc, st)
-                       : tall64_scatter_launch<13, 4, false>(d, ds, which_in, which_out, pout_max, (const double *)T,
+                       : tall64_scatter_launch<13, 5, false>(d, ds, which_in, which_out, pout_max, (const double *)T,
                                                               ldt, (double *)Yout, sc, st);
         return mix ? tall64_scatter_launch<10, 4, true>(d, ds, which_in, which_out, pout_max, (const double *)T, ldt,
                                                          (double *)Yout, sc, st)
