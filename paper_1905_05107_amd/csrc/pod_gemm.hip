@@ -1841,31 +1841,38 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
     TA ast[2][2][4];
     Stage<TC, UITEMS> stu[2];
     const TA *Ab = A + c0 * lda;
-    auto loadA = [&](int64_t sg, TA (&st)[2][4]) {
+    // a full stage of A (r0 + RB <= m, aligned): vector loads with no branch
+    auto loadA_full = [&](int64_t sg, TA (&st)[2][4]) {
         const int64_t r0 = sg * RB;
-        const bool full = vec && r0 + RB <= m;   // uniform
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
             const int idx = threadIdx.x + 256 * it;
             const int c = idx / GRP, g = idx % GRP;
             const TA *p = Ab + (int64_t)((c < ncol) ? c : 0) * lda + r0 + 4 * g;
-            if (full) {
-                if (sizeof(TA) == 4) {
-                    const f32x4 a = *reinterpret_cast<const f32x4 *>(p);
+            if (sizeof(TA) == 4) {
+                const f32x4 a = *reinterpret_cast<const f32x4 *>(p);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) st[it][q] = (TA)a[q];
-                } else {
-                    const f64x2 a = *reinterpret_cast<const f64x2 *>(p);
-                    const f64x2 b = *reinterpret_cast<const f64x2 *>(p + 2);
-                    st[it][0] = (TA)a[0];
-                    st[it][1] = (TA)a[1];
-                    st[it][2] = (TA)b[0];
-                    st[it][3] = (TA)b[1];
-                }
+                for (int q = 0; q < 4; ++q) st[it][q] = (TA)a[q];
             } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) st[it][q] = (r0 + 4 * g + q < m) ? p[q] : (TA)0;
+                const f64x2 a = *reinterpret_cast<const f64x2 *>(p);
+                const f64x2 b = *reinterpret_cast<const f64x2 *>(p + 2);
+                st[it][0] = (TA)a[0];
+                st[it][1] = (TA)a[1];
+                st[it][2] = (TA)b[0];
+                st[it][3] = (TA)b[1];
             }
+        }
+    };
+    // any stage (the partial last one, or unaligned data): element loads
+    auto loadA = [&](int64_t sg, TA (&st)[2][4]) {
+        const int64_t r0 = sg * RB;
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int idx = threadIdx.x + 256 * it;
+            const int c = idx / GRP, g = idx % GRP;
+            const TA *p = Ab + (int64_t)((c < ncol) ? c : 0) * lda + r0 + 4 * g;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) st[it][q] = (r0 + 4 * g + q < m) ? p[q] : (TA)0;
         }
     };
     auto storeA = [&](const TA (&st)[2][4]) {
@@ -1882,13 +1889,6 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
     stu[1].f32col = stu[0].f32col;
 #pragma unroll
     for (int it = 0; it < UITEMS; ++it) stu[1].base[it] = stu[0].base[it];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        if (s0 + b < s1) {
-            loadA(s0 + b, ast[b]);
-            stu[b].load(su, m, (s0 + b) * RB, rl, vec);
-        }
-    }
     // (k-chunk outer, mode tiles inner: independent chains alternate; each
     // tile still sums its k in order)
     auto compute = [&]() {
@@ -1902,21 +1902,52 @@ __global__ __launch_bounds__(256) void k_project_partial(const TC *__restrict__ 
                     acc[q] = mfma16x16x4(ua[k4], xb[k4], acc[q]);
                 }
     };
-    for (int64_t sg = s0; sg < s1; sg += 2) {
+    // full stages [s0, e) on the fast path: two register stages in flight,
+    // every load issued with no branch around it (the prefetch index clamped
+    // to the last full stage, so every iteration issues the same loads; a
+    // load inside a branch would be waited for where the branch ends)
+    const int64_t full_end = m / RB;
+    const bool fast = vec && stu[0].fast;
+    const int64_t e = fast ? ((s1 < full_end) ? s1 : ((full_end > s0) ? full_end : s0)) : s0;
+    if (e > s0) {
+        const int64_t last = e - 1;
+        loadA_full(s0, ast[0]);
+        stu[0].load_full(s0 * RB);
+        const int64_t s1n = (s0 + 1 < last) ? s0 + 1 : last;
+        loadA_full(s1n, ast[1]);
+        stu[1].load_full(s1n * RB);
+        int64_t sg = s0;
+        for (; sg + 1 < e; sg += 2) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            if (sg + b < s1) {   // uniform
+            for (int b = 0; b < 2; ++b) {
                 __syncthreads();
                 storeA(ast[b]);
                 stu[b].store(Us, RP, rl);
                 __syncthreads();
-                if (sg + b + 2 < s1) {
-                    loadA(sg + b + 2, ast[b]);
-                    stu[b].load(su, m, (sg + b + 2) * RB, rl, vec);
-                }
+                const int64_t nx = (sg + b + 2 < last) ? sg + b + 2 : last;
+                loadA_full(nx, ast[b]);
+                stu[b].load_full(nx * RB);
                 compute();
             }
         }
+        if (sg < e) {
+            __syncthreads();
+            storeA(ast[0]);
+            stu[0].store(Us, RP, rl);
+            __syncthreads();
+            compute();
+        }
+    }
+    // the remaining stages one at a time (a partial last stage, or every
+    // stage off the fast path)
+    for (int64_t sg = e; sg < s1; ++sg) {
+        loadA(sg, ast[0]);
+        stu[0].load(su, m, sg * RB, rl, vec);
+        __syncthreads();
+        storeA(ast[0]);
+        stu[0].store(Us, RP, rl);
+        __syncthreads();
+        compute();
     }
     const int64_t col = c0 + wv * 16 + (lane & 15);
     if (col < n) {
