@@ -529,18 +529,17 @@ __device__ __forceinline__ void gram_direct_body(SrcT<TC> s, int64_t m, const De
         TC vr[GD_NB][4][4];
 #pragma unroll
         for (int b = 0; b < GD_NB - 1; ++b) load_fast((gstart + NW * b < lastg) ? gstart + NW * b : lastg, vr[b]);
+        // (the loads are issued outside the branch that skips the products of
+        // groups past the wave's last: a load inside a branch is waited for
+        // where the branch ends, and the prefetch with it)
         for (int64_t gr = gstart;; gr += NW * GD_NB) {
-            bool more = true;
 #pragma unroll
             for (int b = 0; b < GD_NB; ++b) {
-                if (more) {
-                    const int64_t ld = gr + NW * (b + GD_NB - 1);
-                    load_fast((ld < lastg) ? ld : lastg, vr[(b + GD_NB - 1) % GD_NB]);
-                    mma(vr[b]);
-                    more = gr + NW * (b + 1) <= lastg;
-                }
+                const int64_t ld = gr + NW * (b + GD_NB - 1);
+                load_fast((ld < lastg) ? ld : lastg, vr[(b + GD_NB - 1) % GD_NB]);
+                if (gr + NW * b <= lastg) mma(vr[b]);
             }
-            if (!more) break;
+            if (gr + NW * GD_NB > lastg) break;
         }
         gstart = lastg + NW;   // the wave's groups past the full ones
     }
