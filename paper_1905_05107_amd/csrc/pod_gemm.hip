@@ -295,10 +295,10 @@ constexpr int MAXPW160_8 = 7, ITEMS160_8 = 3;
 constexpr int PMAX_WIDE = 160;
 // The reverse pass's Gram of [U | A(:, I) | Ubar] and its transform from that
 // block reach p + r <= 208 columns (13 tiles: 91 tile pairs, 12 per wave of 8;
-// 4 items per thread of 512 stage 256 columns); its transform stages 7 items
-// per thread of 256 (224 columns) and reads T from device memory.
+// 4 items per thread of 512 stage 256 columns); its transform runs on the
+// register-operand tall kernel (scatter mode, 80-column groups of T in LDS).
 constexpr int PMAX_ADJ = 208;
-constexpr int MAXPW208_8 = 12, ITEMS208_8 = 4, ITEMS224 = 7;
+constexpr int MAXPW208_8 = 12, ITEMS208_8 = 4;
 
 template <typename TC, int MAXPW, int ITEMS, int NWV = 4>
 __device__ __forceinline__ void gram_partial_body(SrcT<TC> s, int64_t m, const DevState *ds, int which_p, int pmax,
@@ -1154,7 +1154,7 @@ struct TallScatter {
     int64_t ldd;
 };
 
-template <typename TC, int ITEMS, bool TG, bool SCAT = false, bool TP = false, bool SPLITK = false>
+template <typename TC, int ITEMS, bool TG, bool SCAT = false, bool TP = false>
 __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in, int sel_out,
                                                int pmax_in, int pmax_out, const TC *__restrict__ T, int ldt,
                                                TC *__restrict__ Yout, TC *__restrict__ Yout1, int vec, int bid,
@@ -1243,7 +1243,7 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
     // T in LDS: wave wv owns the tiles of row block rbk = wv % 2 and column
     // tiles jc = wv / 2 + 2 i; each X operand read from LDS feeds the MFMAs of
     // all of them, which accumulate independently (no chained MFMAs)
-    constexpr int MAXJ = SPLITK ? 3 : (ITEMS * 256 / GRP) / 32;   // (SPLITK: at most 6 column tiles)
+    constexpr int MAXJ = (ITEMS * 256 / GRP) / 32;
     auto compute_lds = [&](int64_t sg) {
         const int rbk = wv & 1, j0 = wv >> 1;
         const int nj = (PO / 16 > j0) ? (PO / 16 - j0 + 1) / 2 : 0;
@@ -1251,16 +1251,11 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
         const int jlast = j0 + 2 * (nj - 1);
         const int ke = (tri && nj > 0 && 16 * (jlast + 1) < PI) ? 16 * (jlast + 1) : PI;
         if (nj == 0) return;
-        // SPLITK: odd k-chunks into a second accumulator per tile (twice the
-        // independent product chains; the two halves added at the end)
-        AccT acc[MAXJ], acc2[SPLITK ? MAXJ : 1];
+        AccT acc[MAXJ];
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i) acc[i] = AccT{0, 0, 0, 0};
-#pragma unroll
-        for (int i = 0; i < (SPLITK ? MAXJ : 1); ++i) acc2[i] = AccT{0, 0, 0, 0};
         const TC *xb = Xs + (lane >> 4) * LDSR + rbk * 16 + (lane & 15);
         for (int k4 = 0; k4 < ke; k4 += 16) {
-            const bool odd = SPLITK && ((k4 >> 4) & 1);
             TC xv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) xv[u] = xb[(k4 + 4 * u) * LDSR];
@@ -1278,19 +1273,11 @@ __device__ __forceinline__ void gemm_tall_body(SrcT<TC> s, int64_t m, const DevS
 #pragma unroll
                         for (int u = 0; u < 4; ++u) av[u] = ta[4 * u * PO];
                     }
-                    if (SPLITK && odd) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) acc2[i] = mfma16x16x4(av[u], xv[u], acc2[i]);
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) acc[i] = mfma16x16x4(av[u], xv[u], acc[i]);
-                    }
+                    for (int u = 0; u < 4; ++u) acc[i] = mfma16x16x4(av[u], xv[u], acc[i]);
                 }
             }
         }
-        if (SPLITK)
-#pragma unroll
-            for (int i = 0; i < MAXJ; ++i) acc[i] += acc2[i];
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i)
             if (i < nj) store_tile(sg, rbk, j0 + 2 * i, acc[i]);
@@ -1395,25 +1382,6 @@ __global__ __launch_bounds__(256) void k_gemm_tall_scatter(SrcT<TC> s, int64_t m
 {
     gemm_tall_body<TC, ITEMS, false, true>(s, m, ds, sel_in, sel_out, pmax_in, 0, T, ldt, Yout, nullptr, vec,
                                            blockIdx.x, gridDim.x, 0, sc);
-}
-
-// The same for inputs up to PMAX_ADJ columns whose T does not fit in LDS
-// whole: workgroup row (blockIdx.y) takes output columns [cgw y, cgw (y + 1))
-// (cgw <= 96) with that slice of T in LDS (each column group reads X once
-// more); odd k-chunks accumulate apart (SPLITK).  The output count sel_out
-// is literal.
-template <typename TC, int ITEMS>
-__global__ __launch_bounds__(256) void k_gemm_tall_scatter_cg(SrcT<TC> s, int64_t m, const DevState *ds, int sel_in,
-                                                            int sel_out, int pmax_in, const TC *__restrict__ T,
-                                                            int ldt, TC *__restrict__ Yout, TallScatter sc, int vec,
-                                                            int cgw)
-{
-    const int j0 = (int)blockIdx.y * cgw;
-    const int po = (sel_out - j0 < cgw) ? sel_out - j0 : cgw;
-    TallScatter g = sc;
-    g.split = sc.split - j0;   // column j0 + c' goes where column c of the whole output goes
-    gemm_tall_body<TC, ITEMS, false, true, false, true>(s, m, ds, sel_in, po, pmax_in, 0, T + (int64_t)j0 * ldt, ldt,
-                                           Yout + (int64_t)j0 * m, nullptr, vec, blockIdx.x, gridDim.x, 0, g);
 }
 
 // Batched scatter (P <= 64): matrix blockIdx.y, its own block count.
@@ -2110,39 +2078,8 @@ hipError_t launch_gemm_tall_scatter(const GemmDesc &d, const DevState *ds, int32
                    : tall64_scatter_launch<10, 4, false>(d, ds, which_in, which_out, pout_max, (const double *)T, ldt,
                                                           (double *)Yout, sc, st);
     }
-    if (PI > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS) {
-        // column groups of cgw output columns, each with its slice of T in LDS
-        // beside a stage of up to 224 columns of X
-        if (pout_max < 0 || which_out < 0 || which_out > pout_max) return hipErrorInvalidValue;
-        const int CW = ITEMS224 * 256 / GRP;
-        int cgw = (int)(((size_t)TALL_DYN_LDS / esz - (size_t)CW * LDSR) / PI) & ~15;
-        if (cgw > 96) cgw = 96;   // the kernel's waves hold three column tiles each
-        if (cgw < 16) return hipErrorInvalidValue;
-        const unsigned ng = (unsigned)((PO + cgw - 1) / cgw);
-        const unsigned nb = (unsigned)tall_blocks(d.m);
-        const TallScatter sc{split, cmap, D, ldd};
-        const size_t lds = (size_t)(CW * LDSR + PI * ((cgw < PO) ? cgw : PO)) * esz;
-        if (d.prec == POD_F64) {
-            static bool attr = false;
-            if (!attr)
-                attr = hipFuncSetAttribute((const void *)k_gemm_tall_scatter_cg<double, ITEMS224>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, TALL_DYN_LDS) == hipSuccess;
-            const SrcT<double> s = make_src<double>(d);
-            hipLaunchKernelGGL((k_gemm_tall_scatter_cg<double, ITEMS224>), dim3(nb, ng), dim3(256), lds, st, s, d.m,
-                               ds, which_in, which_out, CW, (const double *)T, ldt, (double *)Yout, sc,
-                               (int)vec_ok(s, d.m), cgw);
-        } else {
-            static bool attr = false;
-            if (!attr)
-                attr = hipFuncSetAttribute((const void *)k_gemm_tall_scatter_cg<float, ITEMS224>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, TALL_DYN_LDS) == hipSuccess;
-            const SrcT<float> s = make_src<float>(d);
-            hipLaunchKernelGGL((k_gemm_tall_scatter_cg<float, ITEMS224>), dim3(nb, ng), dim3(256), lds, st, s, d.m,
-                               ds, which_in, which_out, CW, (const float *)T, ldt, (float *)Yout, sc,
-                               (int)vec_ok(s, d.m), cgw);
-        }
-        return hipGetLastError();
-    }
+    // (the register-operand kernel above takes every T too large for LDS)
+    if (PI > PMAX_WIDE || (size_t)PI * PO * esz > TALL_T_LDS) return hipErrorInvalidValue;
     if (PI <= 64 && PO > 64) return hipErrorInvalidValue;   // the narrow class holds 4 column tiles
     const unsigned nb = (unsigned)tall_blocks(d.m);
     const TallScatter sc{split, cmap, D, ldd};
