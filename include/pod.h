@@ -271,7 +271,7 @@ pod_status pod_backward(pod_ctx *ctx, const void *dU, const double *dsigma, void
 /* Loss L = |A - U_k U_k^T A|_F^2 of the merged modes and its gradient:
  * dA (device, m x n, ld m, compute type) is overwritten with dL/dA and
  * *loss (host, nullable) gets L.  Two passes over A plus two per merge.
- * Syncs. */
+ * POD_EINVAL when k exceeds 64.  Syncs. */
 pod_status pod_loss_grad(pod_ctx *ctx, void *dA, double *loss);
 
 /* ---------------------------------------------------------------------------
