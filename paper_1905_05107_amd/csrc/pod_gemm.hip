@@ -958,19 +958,24 @@ __global__ __launch_bounds__(256) void k_gemm_tall_bf16_direct(SrcT<float> s, in
     }
     const int64_t ngr = (m + 31) >> 5;
     const int64_t W = (int64_t)blockIdx.x * 4 + wv, NW = (int64_t)gridDim.x * 4;
+    // every load issued with no branch around it (a load inside a branch is
+    // waited for where the branch ends, and every load before it): rows past
+    // m read row m - 1, columns past pin read column 0 (cptr), and both are
+    // replaced by zero afterwards
     auto load = [&](int64_t gr, float (&x)[2][KS][8]) {
-        const bool full = (gr + 1) * 32 <= m;   // uniform
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const int k = 32 * ks + 8 * kq + t;
                 const float *cp = cptr[k];
-                const bool kin = k < pin;
+                const bool kin = ks < NKS && k < pin;
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
                     const int64_t row = gr * 32 + 16 * rb + ci;
-                    x[rb][ks][t] = (ks < NKS && kin && (full || row < m)) ? cp[row] : 0.0f;
+                    const bool rin = row < m;
+                    const float v = cp[rin ? row : m - 1];
+                    x[rb][ks][t] = (kin && rin) ? v : 0.0f;
                 }
             }
         }
@@ -1038,7 +1043,8 @@ __global__ __launch_bounds__(256) void k_gemm_tall_bf16_direct(SrcT<float> s, in
                 for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
                     for (int t = 0; t < 8; ++t) xc[rb][ks][t] = xa[rb][ks][t];
-            if (gr + NW < ngr) load(gr + NW, xa);
+            // (the last group reloads itself: no branch around the prefetch)
+            load((gr + NW < ngr) ? gr + NW : gr, xa);
             process(gr, xc);
         }
     }
