@@ -131,3 +131,27 @@ def test_wide_backward_vjp_fp64(m, n, k, c, seed):
     print(f"  merges={len(cs)} vjp rel={rel:.2e}", flush=True)
     assert np.max(np.abs(s.detach().cpu().numpy() - so) / so) <= 1e-10
     assert rel <= 1e-8
+
+
+@pytest.mark.parametrize("m,n,k,c,seed", CASES)
+def test_wide_merge_gradient_fp64_on_fp32_storage(m, n, k, c, seed):
+    """The FP64 path on an FP32-stored A (the measured workload's storage):
+    FP32 columns widened inside the reverse pass's transform and loss kernels;
+    against the oracle on the same values in FP64, FP64 bars."""
+    A32 = _case(m, n, seed).astype(np.float32)
+    A = A32.astype(np.float64)
+    kw = dict(k=k, c=c, seed=seed + 7, theta_tol=1e-12)
+    print(f"adjoint wide fp64/fp32-storage m={m} n={n} k={k} c={c}", flush=True)
+    with pod.PodContext(_dev(A32), precision=pod.POD_F64, **kw) as ctx:
+        ctx.enable_adjoint()
+        ctx.run()
+        T = ctx.info().iter
+        cs = [ctx.indices(t)[0] for t in range(T)]
+        L, dA = ctx.loss_grad()
+        dA = dA.cpu().numpy()
+    assert dA.dtype == np.float64
+    Lr, Gr = adj.loss_and_grad(A, cs, k, k)
+    rel = np.linalg.norm(dA - Gr) / np.linalg.norm(Gr)
+    print(f"  merges={T} loss rel={abs(L - Lr) / Lr:.2e} grad rel={rel:.2e}", flush=True)
+    assert abs(L - Lr) <= 1e-10 * Lr
+    assert rel <= 1e-8
